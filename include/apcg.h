@@ -1,0 +1,395 @@
+/*
+ * apcg.h -- C ABI of the asynchronous, device-resident PCG library for
+ * AMD Instinct MI355X (gfx950).
+ *
+ * The library implements the programming model of Faibussowitsch, Adams,
+ * Mills, Zampini and Zhang, "Safe, Seamless, And Scalable Integration Of
+ * Asynchronous GPU Streams In PETSc" (arXiv 2306.17801), for the
+ * preconditioned conjugate-gradient hot path:
+ *
+ *   - an execution context owns one HIP stream and is the only way work is
+ *     ordered (Section 3.1); the stream itself is never handed out
+ *     (Section 2.1 explains why exposing it is unsafe);
+ *   - every operation declares which objects it reads and writes, and
+ *     operations on different contexts touching a common object are ordered
+ *     write-write, write-read and read-write by call order, while reads are
+ *     not ordered among themselves (Section 3.1.2, the formal ordering rule);
+ *   - scalars produced by reductions stay on the device as futures and feed
+ *     later operations without a host round trip (Sections 2.3 and 3.2.2);
+ *   - the PCG iteration keeps alpha, beta, the residual norm and the
+ *     convergence flag on the device; kernels queued after convergence
+ *     return immediately, which is the device-side convergence check the
+ *     paper leaves as future work (Section 5).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *   - Every function returns apcg_status.  APCG_SUCCESS (0) means the call
+ *     was accepted (for asynchronous calls: enqueued).  On any other value
+ *     nothing was enqueued and apcg_last_error() returns a message
+ *     (thread-local, valid until the next failing call on the thread).
+ *   - Numerical failures of asynchronous work (breakdown, NaN, iteration
+ *     limit) are not return codes: they are written to device-resident
+ *     solve-info words and read with apcg_info_get().
+ *   - A NULL context argument means the per-device globally blocking
+ *     context: the call waits for all earlier work on every context of the
+ *     device and has finished when it returns (Section 3.1, "globally
+ *     blocking" streams; Section 3.2.2, Eval without a context).
+ *   - Pointers named dev_* are device (HBM) pointers; pointers named host_*
+ *     are ordinary host memory.  Vector and matrix memory is BORROWED: the
+ *     caller allocates it (e.g. as PyTorch tensors) and keeps it alive until
+ *     every operation using it has finished (apcg_ctx_synchronize or an
+ *     accessor).  Library objects (contexts, scalars, wrappers, info
+ *     arrays) are owned by the library; destroying them is always safe,
+ *     their resources are released once the device no longer uses them
+ *     (Section 3.2.2, lifetime of ManagedMemory).
+ *   - Floating point is IEEE binary64 throughout the solver; indices are
+ *     int32 (row pointers and column indices), sizes int64 where a vector
+ *     may exceed 2^31 elements.
+ *   - Thread safety: the object registry is internally locked; a single
+ *     context must not be used by two host threads at the same time.
+ */
+#ifndef APCG_H
+#define APCG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define APCG_ABI_VERSION 1
+
+/* ---------------------------------------------------------------------- */
+/* Status codes returned by every call                                     */
+/* ---------------------------------------------------------------------- */
+typedef int32_t apcg_status;
+#define APCG_SUCCESS 0
+#define APCG_ERR_INVALID_ARG 1   /* NULL handle, size mismatch, bad enum ...   */
+#define APCG_ERR_INVALID_STATE 2 /* e.g. object used after destroy            */
+#define APCG_ERR_HIP 3           /* the HIP runtime reported an error          */
+#define APCG_ERR_OUT_OF_MEMORY 4
+#define APCG_ERR_UNSUPPORTED 5   /* valid request the library does not serve   */
+
+/* ---------------------------------------------------------------------- */
+/* Solve-status bits written by the device (apcg_solve_info.status)        */
+/* ---------------------------------------------------------------------- */
+#define APCG_SOLVE_RUNNING 0         /* no terminal state reached           */
+#define APCG_SOLVE_CONVERGED 1       /* ||r|| <= rtol * reference norm        */
+#define APCG_SOLVE_MAXIT 2           /* iteration limit reached               */
+#define APCG_SOLVE_BREAKDOWN_PAP 4   /* p.Ap <= 0: operator not SPD           */
+#define APCG_SOLVE_BREAKDOWN_RZ 8    /* r.z <= 0: preconditioner not SPD      */
+#define APCG_SOLVE_NAN 16            /* a non-finite norm or inner product    */
+#define APCG_SOLVE_STALL 32          /* no progress within the stall window   */
+#define APCG_SOLVE_FALLBACK 64       /* fell back to Jacobi-PCG               */
+#define APCG_SOLVE_SETUP_ERROR 128   /* missing or non-positive diagonal      */
+
+/* ---------------------------------------------------------------------- */
+/* Opaque handles                                                          */
+/* ---------------------------------------------------------------------- */
+typedef struct apcg_ctx_s *apcg_ctx;       /* device + one managed stream   */
+typedef struct apcg_scalar_s *apcg_scalar; /* one device-resident double    */
+typedef struct apcg_vec_s *apcg_vec;       /* borrowed dense double vector  */
+typedef struct apcg_mat_s *apcg_mat;       /* borrowed CSR matrix           */
+typedef struct apcg_info_s *apcg_info;     /* device-resident solve results */
+typedef struct apcg_timer_s *apcg_timer;   /* pair of stream timestamps     */
+
+/* Stream types (Section 3.1). */
+#define APCG_STREAM_DEFAULT 0         /* asynchronous w.r.t. host and other contexts */
+#define APCG_STREAM_GLOBAL_BLOCKING 1 /* waits for all contexts; done on return      */
+
+/* Join modes for apcg_ctx_join. */
+#define APCG_JOIN_DESTROY 0 /* parent waits for the children, children destroyed    */
+#define APCG_JOIN_SYNC 1    /* parent waits; host also waits for the children        */
+#define APCG_JOIN_NO_SYNC 2 /* parent waits for the children; nothing else          */
+
+/* ---------------------------------------------------------------------- */
+/* Execution contexts (Section 3.1, core stream-control listing; fork and  */
+/* join appear in the paper only as API names, read here as: children start */
+/* after everything the parent has enqueued so far, and joining makes the   */
+/* parent wait for everything the children enqueued).                       */
+/* ---------------------------------------------------------------------- */
+
+/* Creates a context on HIP device `device` with its own non-blocking stream
+ * (default priority).  stream_type: APCG_STREAM_DEFAULT or
+ * APCG_STREAM_GLOBAL_BLOCKING.  *out receives the handle. */
+apcg_status apcg_ctx_create(int32_t device, int32_t stream_type, apcg_ctx *out);
+
+/* Destroys the handle immediately; the stream and scratch memory are
+ * released once the work already enqueued on it has finished. */
+apcg_status apcg_ctx_destroy(apcg_ctx ctx);
+
+/* Makes all later work of `waiter` start after all work enqueued on
+ * `waitee` so far (no host wait). */
+apcg_status apcg_ctx_wait_for(apcg_ctx waiter, apcg_ctx waitee);
+
+/* *idle = 1 if every operation enqueued on ctx has finished, else 0.
+ * Never blocks. */
+apcg_status apcg_ctx_query_idle(apcg_ctx ctx, int32_t *idle);
+
+/* Blocks the host until every operation enqueued on ctx has finished. */
+apcg_status apcg_ctx_synchronize(apcg_ctx ctx);
+
+/* Creates n children of the parent's device and stream type; each child's
+ * first operation starts after everything enqueued on the parent so far.
+ * children: caller-provided array of n handles (output). */
+apcg_status apcg_ctx_fork(apcg_ctx parent, int32_t n, apcg_ctx *children);
+
+/* The parent waits (on the device) for all work enqueued on the n children;
+ * mode APCG_JOIN_DESTROY then destroys them (the handles become invalid),
+ * APCG_JOIN_SYNC additionally blocks the host until the children are idle,
+ * APCG_JOIN_NO_SYNC does nothing more. */
+apcg_status apcg_ctx_join(apcg_ctx parent, int32_t n, int32_t mode, apcg_ctx *children);
+
+/* *stream_type receives the context's stream type. */
+apcg_status apcg_ctx_get_stream_type(apcg_ctx ctx, int32_t *stream_type);
+
+/* ---------------------------------------------------------------------- */
+/* Device scalars: futures of one double (Sections 3.2 and 3.2.2)          */
+/* ---------------------------------------------------------------------- */
+
+/* Allocates a device scalar on ctx's device and enqueues its
+ * initialisation to 0 on ctx. */
+apcg_status apcg_scalar_create(apcg_ctx ctx, apcg_scalar *out);
+
+/* Releases the scalar once every operation that uses it has finished. */
+apcg_status apcg_scalar_destroy(apcg_scalar s);
+
+/* Enqueues s = value on ctx (value captured at call time; no host sync). */
+apcg_status apcg_scalar_set(apcg_scalar s, double value, apcg_ctx ctx);
+
+/* The host accessor ("front()" in the PCG listing of Section 3.3): waits
+ * only for the last operation that wrote s, then copies its value to
+ * *host_value. */
+apcg_status apcg_scalar_get(apcg_scalar s, double *host_value);
+
+/* Scalar arithmetic on the device (the fixed expressions the PCG loop
+ * evaluates with Eval in Section 3.3: beta/betaold, beta/a, -a, 1/alpha).
+ * out = op(a[, b]); b must be NULL for unary opcodes and non-NULL for
+ * binary ones.  out may alias a or b.  Runs as one single-thread kernel on
+ * ctx. */
+#define APCG_SCALAR_COPY 0  /* out = a      */
+#define APCG_SCALAR_NEG 1   /* out = -a     */
+#define APCG_SCALAR_RECIP 2 /* out = 1 / a  */
+#define APCG_SCALAR_SQRT 3  /* out = sqrt a */
+#define APCG_SCALAR_ADD 4   /* out = a + b  */
+#define APCG_SCALAR_SUB 5   /* out = a - b  */
+#define APCG_SCALAR_MUL 6   /* out = a * b  */
+#define APCG_SCALAR_DIV 7   /* out = a / b  */
+apcg_status apcg_scalar_op(int32_t opcode, apcg_scalar out, apcg_scalar a, apcg_scalar b, apcg_ctx ctx);
+
+/* ---------------------------------------------------------------------- */
+/* Vectors (borrowed device memory)                                        */
+/* ---------------------------------------------------------------------- */
+
+/* Wraps n doubles at dev_ptr (device memory on `device`, 8-byte aligned;
+ * n >= 0; dev_ptr may be NULL only when n == 0).  The library never frees
+ * dev_ptr.  Writes made to the memory outside the library must be finished
+ * before the next library call that uses the vector. */
+apcg_status apcg_vec_wrap(int32_t device, double *dev_ptr, int64_t n, apcg_vec *out);
+
+/* Destroys the wrapper (not the memory) once its pending uses finish. */
+apcg_status apcg_vec_destroy(apcg_vec v);
+
+/* out = x . y (Section 3.3, VecDotAsync).  Deterministic: a fixed two-stage
+ * reduction tree, bitwise reproducible for a given n. */
+apcg_status apcg_vec_dot_async(apcg_vec x, apcg_vec y, apcg_scalar out, apcg_ctx ctx);
+
+/* out = ||x||_2 (Section 3.3, VecNormAsync with NORM_2). */
+apcg_status apcg_vec_norm2_async(apcg_vec x, apcg_scalar out, apcg_ctx ctx);
+
+/* y = y + s a x with s = -1 if negate else +1 (Section 3.3, VecAXPYAsync
+ * with a and -a).  x and y must have equal length and must not overlap
+ * unless they are the same vector. */
+apcg_status apcg_vec_axpy_async(apcg_vec y, apcg_scalar a, int32_t negate, apcg_vec x, apcg_ctx ctx);
+
+/* y = x + b y (Section 3.3, VecAYPX: p <- z + b p). */
+apcg_status apcg_vec_aypx_async(apcg_vec y, apcg_scalar b, apcg_vec x, apcg_ctx ctx);
+
+/* x = a x (Section 3.3, VecScaleAsync; Section 3.1.2, the scale-kernel
+ * example). */
+apcg_status apcg_vec_scale_async(apcg_vec x, apcg_scalar a, apcg_ctx ctx);
+
+/* dst = src (VecCopyAsync, named in the paper's API list). */
+apcg_status apcg_vec_copy_async(apcg_vec dst, apcg_vec src, apcg_ctx ctx);
+
+/* x = value for every entry. */
+apcg_status apcg_vec_set_async(apcg_vec x, double value, apcg_ctx ctx);
+
+/* Host accessor (Section 3.3, accessors synchronise implicitly): waits for
+ * the last operation that wrote x, then copies its n entries to host_out. */
+apcg_status apcg_vec_copy_to_host(apcg_vec x, double *host_out);
+
+/* Enqueues a copy of n host doubles into x on ctx; returns after the host
+ * buffer has been consumed. */
+apcg_status apcg_vec_copy_from_host(apcg_vec x, const double *host_in, apcg_ctx ctx);
+
+/* ---------------------------------------------------------------------- */
+/* CSR matrices (borrowed device memory)                                   */
+/* ---------------------------------------------------------------------- */
+
+/* Wraps an n x n CSR matrix: dev_rowptr int32[n+1] (dev_rowptr[0] == 0,
+ * non-decreasing, dev_rowptr[n] == nnz), dev_col int32[nnz] in [0, n),
+ * dev_val double[nnz].  host_rowptr (may be NULL) is a host copy of the row
+ * pointers used to validate and to plan the SpMV schedule; if NULL the
+ * library copies it once (synchronously).  The arrays are never modified
+ * or freed by the library. */
+apcg_status apcg_mat_wrap_csr(int32_t device, int32_t n, int64_t nnz, const int32_t *dev_rowptr,
+                              const int32_t *dev_col, const double *dev_val, const int32_t *host_rowptr,
+                              apcg_mat *out);
+
+/* Destroys the wrapper once its pending uses finish. */
+apcg_status apcg_mat_destroy(apcg_mat A);
+
+/* y = A x (Section 3.3, MatMult / KSP_MatMultAsync). */
+apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx);
+
+/* SpMV schedule: lanes_per_row in {1,2,4,8,16,32,64} lanes of a 64-wide
+ * wavefront cooperate on one row; block_size in {64,128,256,512,1024}
+ * threads; blocks is the number of workgroups (rounded up to a multiple of
+ * the 8 XCDs; 0 = library default).  Each workgroup owns a contiguous range
+ * of rows and workgroups are renumbered so each XCD owns a contiguous
+ * slice of the matrix. */
+typedef struct apcg_spmv_config {
+    int32_t lanes_per_row;
+    int32_t block_size;
+    int32_t blocks;
+    int32_t reserved;
+} apcg_spmv_config;
+
+apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg);
+apcg_status apcg_mat_get_spmv_config(apcg_mat A, apcg_spmv_config *cfg);
+
+/* Autotuner: times every candidate schedule of the fused PCG product
+ * kernel (reps launches each, HIP events on ctx's stream), keeps the
+ * fastest in A and returns it in *best (and its mean time in *best_us).
+ * The vectors are scratch the library allocates and frees itself.
+ * Blocks the host until the sweep finishes. */
+apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best,
+                              double *best_us);
+
+/* ---------------------------------------------------------------------- */
+/* Krylov solve (Section 3.3, the PCG loop; Section 4.1, Jacobi CG)        */
+/* ---------------------------------------------------------------------- */
+
+#define APCG_PC_NONE 0   /* z = r                                           */
+#define APCG_PC_JACOBI 1 /* z = D^{-1} r                                     */
+
+#define APCG_NORM_UNPRECONDITIONED 0 /* stop when ||r_k|| <= rtol ||b||       */
+#define APCG_NORM_PRECONDITIONED 1   /* stop when ||z_k|| <= rtol ||D^-1 b||  */
+
+/* Host orchestration of the iteration loop. */
+#define APCG_MODE_GRAPH 0      /* K iterations per captured hipGraph,        */
+                               /* host polls a pinned flag L graphs behind   */
+#define APCG_MODE_STREAM 1     /* same kernels launched one by one           */
+#define APCG_MODE_HOST_CHECK 2 /* host reads the convergence flag after     */
+                               /* every iteration (the synchronous shape)   */
+
+typedef struct apcg_solve_opts {
+    int32_t pc;              /* APCG_PC_*                                    */
+    int32_t norm_type;       /* APCG_NORM_*                                  */
+    int32_t mode;            /* APCG_MODE_*                                  */
+    int32_t iters_per_graph; /* K (even, >= 2) for GRAPH; poll period STREAM */
+    int32_t lookahead;       /* graphs/periods in flight before a poll (>=1) */
+    int32_t x0_is_zero;      /* 1: skip r0 = b - A x0 and zero x on device   */
+    int32_t kernel_timing;   /* 1: STREAM mode with HIP events around every  */
+                             /*    product and update kernel (see            */
+                             /*    apcg_ctx_kernel_times)                    */
+    int32_t reserved[9];
+} apcg_solve_opts;
+
+/* Fills *opts with the defaults: Jacobi, unpreconditioned norm, GRAPH mode,
+ * K = 16, lookahead 2, x0 read from x, no kernel timing. */
+apcg_status apcg_solve_opts_default(apcg_solve_opts *opts);
+
+/* Host view of one solve's results. */
+typedef struct apcg_solve_info {
+    int32_t iterations;     /* products A p performed (PETSc's count)       */
+    int32_t status;         /* APCG_SOLVE_* bits                             */
+    int32_t fcg_iterations; /* iterations run by the flexible method         */
+    int32_t reserved;
+    double res_norm;        /* final stopping norm                           */
+    double ref_norm;        /* ||b|| (or ||D^-1 b|| for the preconditioned norm) */
+} apcg_solve_info;
+
+/* Device array of `count` solve-info records on ctx's device. */
+apcg_status apcg_info_create(int32_t device, int32_t count, apcg_info *out);
+apcg_status apcg_info_destroy(apcg_info info);
+
+/* Waits for the last operation that wrote the info array, then copies
+ * record `index` to *out. */
+apcg_status apcg_info_get(apcg_info info, int32_t index, apcg_solve_info *out);
+
+/* Solves A x = b with preconditioned CG on ctx.  x holds x0 on entry
+ * (ignored when opts->x0_is_zero) and the solution on exit.  Stops when the
+ * chosen norm is <= rtol times its reference, or after maxit iterations
+ * (maxit >= 0).  The result is written to info[info_index] on the device.
+ * Workspace (5 n doubles plus a few scalars) is owned by ctx and reused.
+ * With APCG_MODE_GRAPH/STREAM no kernel waits on the host: the host thread
+ * returns once it has enqueued enough work to reach convergence or maxit,
+ * having observed the device flag only through events `lookahead` periods
+ * behind the queue.  On a globally blocking context the call returns after
+ * the solve has finished. */
+apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                           const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
+
+/* Mean device time (microseconds) and launch count of the product kernel
+ * (kind 0: fused SpMV + p.Ap) and the update kernel (kind 1: x, r update
+ * with r.z and ||r||^2) measured by the last solve on ctx that ran with
+ * kernel_timing = 1.  Blocks until that solve has finished. */
+apcg_status apcg_ctx_kernel_times(apcg_ctx ctx, int32_t kind, double *mean_us, int32_t *count);
+
+/* ---------------------------------------------------------------------- */
+/* Timers and diagnostics                                                  */
+/* ---------------------------------------------------------------------- */
+
+apcg_status apcg_timer_create(apcg_timer *out);
+apcg_status apcg_timer_destroy(apcg_timer t);
+/* Records the start / stop timestamp on ctx's stream (no host wait). */
+apcg_status apcg_timer_start(apcg_timer t, apcg_ctx ctx);
+apcg_status apcg_timer_stop(apcg_timer t, apcg_ctx ctx);
+/* Waits for the stop timestamp and returns stop - start in milliseconds. */
+apcg_status apcg_timer_elapsed_ms(apcg_timer t, double *ms);
+
+/* Library-wide counters of host-visible events. */
+typedef struct apcg_counters {
+    int64_t kernel_launches; /* kernels enqueued outside graphs              */
+    int64_t graph_launches;  /* hipGraphLaunch calls                         */
+    int64_t host_syncs;      /* host waits on streams/devices                */
+    int64_t host_polls;      /* host waits on events queued >= 1 period back */
+    int64_t d2h_copies;      /* device-to-host copies                        */
+    int64_t h2d_copies;      /* host-to-device copies                        */
+    int64_t stream_waits;    /* cross-context waits inserted by the registry */
+    int64_t reserved[9];
+} apcg_counters;
+
+apcg_status apcg_counters_get(apcg_counters *out);
+apcg_status apcg_counters_reset(void);
+
+/* Device description for reports. */
+typedef struct apcg_device_props {
+    char name[64];
+    char arch[32];           /* e.g. "gfx950"                                */
+    int32_t compute_units;
+    int32_t wavefront_size;
+    int64_t global_mem_bytes;
+    int32_t clock_khz;
+    int32_t l2_bytes;
+    int32_t lds_bytes_per_block;
+    int32_t reserved[7];
+} apcg_device_props;
+
+apcg_status apcg_device_props_get(int32_t device, apcg_device_props *out);
+
+/* Number of HIP devices visible (0 on a machine without GPU). */
+apcg_status apcg_device_count(int32_t *count);
+
+/* Message of the last failing call on this thread ("" if none). */
+const char *apcg_last_error(void);
+
+/* APCG_ABI_VERSION of the built library. */
+int32_t apcg_abi_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* APCG_H */

@@ -1,0 +1,326 @@
+"""apcg -- asynchronous, device-resident preconditioned CG for AMD MI355X.
+
+Python binding of the C ABI declared in include/apcg.h.  Each ``apcg_*``
+function below calls the C entry point of the same name: it marshals
+arguments (handles are ints, vectors and matrices are float64/int32 torch
+tensors on the GPU), returns what the C call writes through its out-pointers
+and raises ApcgError on failure.  All computation happens in the HIP library;
+there is no Python or CPU fallback, and using any function without the built
+library raises.
+
+PyTorch provides device memory only: the library never allocates the caller's
+vectors, and tensors passed in must stay alive until the work using them has
+finished (``apcg_ctx_synchronize`` or an accessor).  Tensors written by torch
+kernels must be complete before the library reads them (for example
+``torch.cuda.synchronize()`` after filling them).
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _capi
+from ._capi import *  # noqa: F401,F403  -- constants and structures
+from ._capi import ApcgError, check, load
+
+__all__ = [n for n in dir(_capi) if n.startswith(("APCG_", "apcg_"))] + ["ApcgError", "load"]
+
+
+def _L():
+    return load()
+
+
+def _h(x):
+    """Handle -> c_void_p value (None for NULL)."""
+    return None if x is None else ctypes.c_void_p(int(x))
+
+
+def _tensor_ptr(t, dtype_name):
+    import torch
+
+    want = {"float64": torch.float64, "int32": torch.int32}[dtype_name]
+    if not isinstance(t, torch.Tensor):
+        raise TypeError("expected a torch.Tensor")
+    if t.dtype != want:
+        raise TypeError(f"expected dtype {dtype_name}, got {t.dtype}")
+    if not t.is_cuda:
+        raise ValueError("tensor must live on the GPU")
+    if not t.is_contiguous():
+        raise ValueError("tensor must be contiguous")
+    return t.data_ptr(), t.device.index or 0
+
+
+# ------------------------------------------------------------------ misc
+
+def apcg_abi_version() -> int:
+    return int(_L().apcg_abi_version())
+
+
+def apcg_last_error() -> str:
+    m = _L().apcg_last_error()
+    return m.decode() if m else ""
+
+
+def apcg_device_count() -> int:
+    c = ctypes.c_int32()
+    check("apcg_device_count", _L().apcg_device_count(ctypes.byref(c)))
+    return c.value
+
+
+def apcg_device_props_get(device: int = 0) -> dict:
+    p = _capi.apcg_device_props()
+    check("apcg_device_props_get", _L().apcg_device_props_get(device, ctypes.byref(p)))
+    return {"name": p.name.decode(), "arch": p.arch.decode(), "compute_units": p.compute_units,
+            "wavefront_size": p.wavefront_size, "global_mem_bytes": p.global_mem_bytes,
+            "clock_khz": p.clock_khz, "l2_bytes": p.l2_bytes, "lds_bytes_per_block": p.lds_bytes_per_block}
+
+
+def apcg_counters_get() -> dict:
+    c = _capi.apcg_counters()
+    check("apcg_counters_get", _L().apcg_counters_get(ctypes.byref(c)))
+    return c.as_dict()
+
+
+def apcg_counters_reset() -> None:
+    check("apcg_counters_reset", _L().apcg_counters_reset())
+
+
+# ------------------------------------------------------------------ contexts
+
+def apcg_ctx_create(device: int = 0, stream_type: int = _capi.APCG_STREAM_DEFAULT) -> int:
+    out = ctypes.c_void_p()
+    check("apcg_ctx_create", _L().apcg_ctx_create(device, stream_type, ctypes.byref(out)))
+    return out.value
+
+
+def apcg_ctx_destroy(ctx) -> None:
+    check("apcg_ctx_destroy", _L().apcg_ctx_destroy(_h(ctx)))
+
+
+def apcg_ctx_wait_for(waiter, waitee) -> None:
+    check("apcg_ctx_wait_for", _L().apcg_ctx_wait_for(_h(waiter), _h(waitee)))
+
+
+def apcg_ctx_query_idle(ctx) -> bool:
+    out = ctypes.c_int32()
+    check("apcg_ctx_query_idle", _L().apcg_ctx_query_idle(_h(ctx), ctypes.byref(out)))
+    return bool(out.value)
+
+
+def apcg_ctx_synchronize(ctx) -> None:
+    check("apcg_ctx_synchronize", _L().apcg_ctx_synchronize(_h(ctx)))
+
+
+def apcg_ctx_fork(parent, n: int) -> list:
+    arr = (ctypes.c_void_p * max(n, 1))()
+    check("apcg_ctx_fork", _L().apcg_ctx_fork(_h(parent), n, arr))
+    return [arr[i] for i in range(n)]
+
+
+def apcg_ctx_join(parent, children, mode: int = _capi.APCG_JOIN_DESTROY) -> list:
+    n = len(children)
+    arr = (ctypes.c_void_p * max(n, 1))(*[int(c) for c in children])
+    check("apcg_ctx_join", _L().apcg_ctx_join(_h(parent), n, mode, arr))
+    return [arr[i] for i in range(n)]
+
+
+def apcg_ctx_get_stream_type(ctx) -> int:
+    out = ctypes.c_int32()
+    check("apcg_ctx_get_stream_type", _L().apcg_ctx_get_stream_type(_h(ctx), ctypes.byref(out)))
+    return out.value
+
+
+def apcg_ctx_kernel_times(ctx, kind: int):
+    mean = ctypes.c_double()
+    cnt = ctypes.c_int32()
+    check("apcg_ctx_kernel_times", _L().apcg_ctx_kernel_times(_h(ctx), kind, ctypes.byref(mean), ctypes.byref(cnt)))
+    return mean.value, cnt.value
+
+
+# ------------------------------------------------------------------ scalars
+
+def apcg_scalar_create(ctx=None) -> int:
+    out = ctypes.c_void_p()
+    check("apcg_scalar_create", _L().apcg_scalar_create(_h(ctx), ctypes.byref(out)))
+    return out.value
+
+
+def apcg_scalar_destroy(s) -> None:
+    check("apcg_scalar_destroy", _L().apcg_scalar_destroy(_h(s)))
+
+
+def apcg_scalar_set(s, value: float, ctx=None) -> None:
+    check("apcg_scalar_set", _L().apcg_scalar_set(_h(s), float(value), _h(ctx)))
+
+
+def apcg_scalar_get(s) -> float:
+    out = ctypes.c_double()
+    check("apcg_scalar_get", _L().apcg_scalar_get(_h(s), ctypes.byref(out)))
+    return out.value
+
+
+def apcg_scalar_op(opcode: int, out, a, b=None, ctx=None) -> None:
+    check("apcg_scalar_op", _L().apcg_scalar_op(opcode, _h(out), _h(a), _h(b), _h(ctx)))
+
+
+# ------------------------------------------------------------------ vectors
+
+def apcg_vec_wrap(tensor) -> int:
+    """Wraps a contiguous float64 GPU tensor (borrowed; keep it alive)."""
+    ptr, dev = _tensor_ptr(tensor, "float64")
+    out = ctypes.c_void_p()
+    check("apcg_vec_wrap", _L().apcg_vec_wrap(dev, ctypes.c_void_p(ptr), tensor.numel(), ctypes.byref(out)))
+    return out.value
+
+
+def apcg_vec_destroy(v) -> None:
+    check("apcg_vec_destroy", _L().apcg_vec_destroy(_h(v)))
+
+
+def apcg_vec_dot_async(x, y, out, ctx=None) -> None:
+    check("apcg_vec_dot_async", _L().apcg_vec_dot_async(_h(x), _h(y), _h(out), _h(ctx)))
+
+
+def apcg_vec_norm2_async(x, out, ctx=None) -> None:
+    check("apcg_vec_norm2_async", _L().apcg_vec_norm2_async(_h(x), _h(out), _h(ctx)))
+
+
+def apcg_vec_axpy_async(y, a, negate: bool, x, ctx=None) -> None:
+    check("apcg_vec_axpy_async", _L().apcg_vec_axpy_async(_h(y), _h(a), int(bool(negate)), _h(x), _h(ctx)))
+
+
+def apcg_vec_aypx_async(y, b, x, ctx=None) -> None:
+    check("apcg_vec_aypx_async", _L().apcg_vec_aypx_async(_h(y), _h(b), _h(x), _h(ctx)))
+
+
+def apcg_vec_scale_async(x, a, ctx=None) -> None:
+    check("apcg_vec_scale_async", _L().apcg_vec_scale_async(_h(x), _h(a), _h(ctx)))
+
+
+def apcg_vec_copy_async(dst, src, ctx=None) -> None:
+    check("apcg_vec_copy_async", _L().apcg_vec_copy_async(_h(dst), _h(src), _h(ctx)))
+
+
+def apcg_vec_set_async(x, value: float, ctx=None) -> None:
+    check("apcg_vec_set_async", _L().apcg_vec_set_async(_h(x), float(value), _h(ctx)))
+
+
+def apcg_vec_copy_to_host(v, n: int):
+    import numpy as np
+
+    out = np.empty(n, dtype=np.float64)
+    check("apcg_vec_copy_to_host", _L().apcg_vec_copy_to_host(_h(v), out.ctypes.data_as(ctypes.c_void_p)))
+    return out
+
+
+def apcg_vec_copy_from_host(v, host, ctx=None) -> None:
+    import numpy as np
+
+    host = np.ascontiguousarray(host, dtype=np.float64)
+    check("apcg_vec_copy_from_host",
+          _L().apcg_vec_copy_from_host(_h(v), host.ctypes.data_as(ctypes.c_void_p), _h(ctx)))
+
+
+# ------------------------------------------------------------------ matrices
+
+def apcg_mat_wrap_csr(rowptr, col, val, host_rowptr=None) -> int:
+    """Wraps device CSR tensors (int32 rowptr/col, float64 val; borrowed).
+    host_rowptr: optional numpy int32 copy of rowptr for validation."""
+    import numpy as np
+
+    rp, dev = _tensor_ptr(rowptr, "int32")
+    n = rowptr.numel() - 1
+    nnz = val.numel()
+    cp = _tensor_ptr(col, "int32")[0] if nnz else 0
+    vp = _tensor_ptr(val, "float64")[0] if nnz else 0
+    hp = None
+    if host_rowptr is not None:
+        host_rowptr = np.ascontiguousarray(host_rowptr, dtype=np.int32)
+        hp = host_rowptr.ctypes.data_as(ctypes.c_void_p)
+    out = ctypes.c_void_p()
+    check("apcg_mat_wrap_csr", _L().apcg_mat_wrap_csr(dev, n, nnz, ctypes.c_void_p(rp), ctypes.c_void_p(cp or None),
+                                                      ctypes.c_void_p(vp or None), hp, ctypes.byref(out)))
+    return out.value
+
+
+def apcg_mat_destroy(A) -> None:
+    check("apcg_mat_destroy", _L().apcg_mat_destroy(_h(A)))
+
+
+def apcg_mat_mult_async(A, x, y, ctx=None) -> None:
+    check("apcg_mat_mult_async", _L().apcg_mat_mult_async(_h(A), _h(x), _h(y), _h(ctx)))
+
+
+def apcg_mat_set_spmv_config(A, lanes_per_row: int, block_size: int = 256, blocks: int = 0) -> None:
+    cfg = _capi.apcg_spmv_config(lanes_per_row, block_size, blocks, 0)
+    check("apcg_mat_set_spmv_config", _L().apcg_mat_set_spmv_config(_h(A), ctypes.byref(cfg)))
+
+
+def apcg_mat_get_spmv_config(A) -> dict:
+    cfg = _capi.apcg_spmv_config()
+    check("apcg_mat_get_spmv_config", _L().apcg_mat_get_spmv_config(_h(A), ctypes.byref(cfg)))
+    return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks}
+
+
+def apcg_mat_autotune(A, ctx, reps: int = 20):
+    cfg = _capi.apcg_spmv_config()
+    us = ctypes.c_double()
+    check("apcg_mat_autotune", _L().apcg_mat_autotune(_h(A), _h(ctx), reps, ctypes.byref(cfg), ctypes.byref(us)))
+    return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks}, us.value
+
+
+# ------------------------------------------------------------------ solve
+
+def apcg_solve_opts_default(**overrides):
+    o = _capi.apcg_solve_opts()
+    check("apcg_solve_opts_default", _L().apcg_solve_opts_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        setattr(o, k, int(v))
+    return o
+
+
+def apcg_info_create(device: int = 0, count: int = 1) -> int:
+    out = ctypes.c_void_p()
+    check("apcg_info_create", _L().apcg_info_create(device, count, ctypes.byref(out)))
+    return out.value
+
+
+def apcg_info_destroy(info) -> None:
+    check("apcg_info_destroy", _L().apcg_info_destroy(_h(info)))
+
+
+def apcg_info_get(info, index: int = 0) -> dict:
+    out = _capi.apcg_solve_info()
+    check("apcg_info_get", _L().apcg_info_get(_h(info), index, ctypes.byref(out)))
+    return out.as_dict()
+
+
+def apcg_ksp_solve(ctx, A, b, x, rtol: float, maxit: int, opts=None, info=None, info_index: int = 0) -> None:
+    po = ctypes.byref(opts) if opts is not None else None
+    check("apcg_ksp_solve", _L().apcg_ksp_solve(_h(ctx), _h(A), _h(b), _h(x), float(rtol), int(maxit), po, _h(info),
+                                                int(info_index)))
+
+
+# ------------------------------------------------------------------ timers
+
+def apcg_timer_create() -> int:
+    out = ctypes.c_void_p()
+    check("apcg_timer_create", _L().apcg_timer_create(ctypes.byref(out)))
+    return out.value
+
+
+def apcg_timer_destroy(t) -> None:
+    check("apcg_timer_destroy", _L().apcg_timer_destroy(_h(t)))
+
+
+def apcg_timer_start(t, ctx) -> None:
+    check("apcg_timer_start", _L().apcg_timer_start(_h(t), _h(ctx)))
+
+
+def apcg_timer_stop(t, ctx) -> None:
+    check("apcg_timer_stop", _L().apcg_timer_stop(_h(t), _h(ctx)))
+
+
+def apcg_timer_elapsed_ms(t) -> float:
+    out = ctypes.c_double()
+    check("apcg_timer_elapsed_ms", _L().apcg_timer_elapsed_ms(_h(t), ctypes.byref(out)))
+    return out.value

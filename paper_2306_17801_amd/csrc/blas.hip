@@ -1,0 +1,220 @@
+// blas.hip -- vector kernels, device-scalar arithmetic and the plain CSR
+// product behind the asynchronous Vec/Mat calls (Section 3.3: VecDotAsync,
+// VecNormAsync, VecAXPYAsync, VecAYPX, VecScaleAsync, MatMult).
+//
+// Memory-bound kernels: each workgroup streams one contiguous chunk, and the
+// XCD-aware renumbering keeps each XCD's chunks contiguous.  Scalars are read
+// from device slots, never passed through the host.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+
+#include "internal.h"
+
+namespace apcg {
+namespace {
+
+constexpr int BS = 256;
+
+using dev::Chunk;
+using dev::block_chunk;
+
+__global__ __launch_bounds__(BS) void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
+                                            int64_t per_block, double *out, int take_sqrt, double *partials,
+                                            unsigned *counter) {
+    const Chunk c = block_chunk(n, per_block);
+    double acc = 0.0;
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) acc = fma(x[i], y[i], acc);
+    double v[1] = {acc};
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    if (dev::reduce_last_block<BS, 1>(v, partials, gridDim.x, lb, counter) && threadIdx.x == 0)
+        *out = take_sqrt ? sqrt(v[0]) : v[0];
+}
+
+__global__ __launch_bounds__(BS) void k_axpy(double *__restrict__ y, const double *a, double sign,
+                                             const double *__restrict__ x, int64_t n, int64_t per_block) {
+    const double s = sign * *a;
+    const Chunk c = block_chunk(n, per_block);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) y[i] = fma(s, x[i], y[i]);
+}
+
+__global__ __launch_bounds__(BS) void k_aypx(double *__restrict__ y, const double *b, const double *__restrict__ x,
+                                             int64_t n, int64_t per_block) {
+    const double s = *b;
+    const Chunk c = block_chunk(n, per_block);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) y[i] = fma(s, y[i], x[i]);
+}
+
+__global__ __launch_bounds__(BS) void k_scale(double *__restrict__ x, const double *a, int64_t n,
+                                              int64_t per_block) {
+    const double s = *a;
+    const Chunk c = block_chunk(n, per_block);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) x[i] = s * x[i];
+}
+
+__global__ __launch_bounds__(BS) void k_copy(double *__restrict__ d, const double *__restrict__ s, int64_t n,
+                                             int64_t per_block) {
+    const Chunk c = block_chunk(n, per_block);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) d[i] = s[i];
+}
+
+__global__ __launch_bounds__(BS) void k_fill(double *__restrict__ x, double v, int64_t n, int64_t per_block) {
+    const Chunk c = block_chunk(n, per_block);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) x[i] = v;
+}
+
+__global__ void k_scalar_op(int op, double *out, const double *a, const double *b) {
+    if (threadIdx.x != 0) return;
+    const double x = *a;
+    const double y = b ? *b : 0.0;
+    double r = 0.0;
+    switch (op) {
+        case APCG_SCALAR_COPY: r = x; break;
+        case APCG_SCALAR_NEG: r = -x; break;
+        case APCG_SCALAR_RECIP: r = 1.0 / x; break;
+        case APCG_SCALAR_SQRT: r = sqrt(x); break;
+        case APCG_SCALAR_ADD: r = x + y; break;
+        case APCG_SCALAR_SUB: r = x - y; break;
+        case APCG_SCALAR_MUL: r = x * y; break;
+        case APCG_SCALAR_DIV: r = x / y; break;
+        default: r = NAN; break;
+    }
+    *out = r;
+}
+
+__global__ void k_scalar_set(double *out, double v) {
+    if (threadIdx.x == 0) *out = v;
+}
+
+// y = A x with LPR lanes per row; rows of a workgroup form one contiguous
+// range; lanes of a row add strided partial sums, then a butterfly.
+template <int LPR, int TB>
+__global__ __launch_bounds__(TB) void k_spmv(int32_t n, const int32_t *__restrict__ rowptr,
+                                             const int32_t *__restrict__ col, const double *__restrict__ val,
+                                             const double *__restrict__ x, double *__restrict__ y,
+                                             int32_t rows_per_block) {
+    constexpr int RPP = TB / LPR;
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int row0 = lb * rows_per_block;
+    const int row1 = min(n, row0 + rows_per_block);
+    const int lane = threadIdx.x % LPR, grp = threadIdx.x / LPR;
+    for (int base = row0; base < row1; base += RPP) {
+        const int row = base + grp;
+        double sum = 0.0;
+        if (row < row1) {
+            const int e = rowptr[row + 1];
+            for (int k = rowptr[row] + lane; k < e; k += LPR) sum = fma(val[k], x[col[k]], sum);
+        }
+#pragma unroll
+        for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LPR);
+        if (row < row1 && lane == 0) y[row] = sum;
+    }
+}
+
+template <int TB>
+apcg_status spmv_tb(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
+    const int lpr = A->cfg.lanes_per_row;
+    const int64_t rpp = TB / lpr;
+    const int G = normalise_blocks(A->cfg.blocks, (A->n + rpp - 1) / rpp);
+    int32_t rpb = (int32_t)((A->n + G - 1) / G);
+    if (rpb < 1) rpb = 1;
+#define APCG_SPMV_CASE(L)                                                                          \
+    case L:                                                                                        \
+        hipLaunchKernelGGL((k_spmv<L, TB>), dim3(G), dim3(TB), 0, s, A->n, A->rowptr, A->col, A->val, x, y, rpb); \
+        break;
+    switch (lpr) {
+        APCG_SPMV_CASE(1)
+        APCG_SPMV_CASE(2)
+        APCG_SPMV_CASE(4)
+        APCG_SPMV_CASE(8)
+        APCG_SPMV_CASE(16)
+        APCG_SPMV_CASE(32)
+        APCG_SPMV_CASE(64)
+        default: return set_error(APCG_ERR_INVALID_ARG, "unsupported lanes_per_row");
+    }
+#undef APCG_SPMV_CASE
+    APCG_CHECK_LAUNCH("k_spmv");
+    return APCG_SUCCESS;
+}
+
+}  // namespace
+
+apcg_status launch_dot(hipStream_t s, const double *x, const double *y, int64_t n, double *out, int take_sqrt,
+                       double *partials, unsigned *counter) {
+    int G;
+    int64_t pb;
+    elementwise_grid(n, &G, &pb);
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(BS), 0, s, x, y, n, pb, out, take_sqrt, partials, counter);
+    APCG_CHECK_LAUNCH("k_dot");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_axpy(hipStream_t s, double *y, const double *a, double sign, const double *x, int64_t n) {
+    if (n == 0) return APCG_SUCCESS;
+    int G;
+    int64_t pb;
+    elementwise_grid(n, &G, &pb);
+    hipLaunchKernelGGL(k_axpy, dim3(G), dim3(BS), 0, s, y, a, sign, x, n, pb);
+    APCG_CHECK_LAUNCH("k_axpy");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_aypx(hipStream_t s, double *y, const double *b, const double *x, int64_t n) {
+    if (n == 0) return APCG_SUCCESS;
+    int G;
+    int64_t pb;
+    elementwise_grid(n, &G, &pb);
+    hipLaunchKernelGGL(k_aypx, dim3(G), dim3(BS), 0, s, y, b, x, n, pb);
+    APCG_CHECK_LAUNCH("k_aypx");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_scale(hipStream_t s, double *x, const double *a, int64_t n) {
+    if (n == 0) return APCG_SUCCESS;
+    int G;
+    int64_t pb;
+    elementwise_grid(n, &G, &pb);
+    hipLaunchKernelGGL(k_scale, dim3(G), dim3(BS), 0, s, x, a, n, pb);
+    APCG_CHECK_LAUNCH("k_scale");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_copy(hipStream_t s, double *dst, const double *src, int64_t n) {
+    if (n == 0) return APCG_SUCCESS;
+    int G;
+    int64_t pb;
+    elementwise_grid(n, &G, &pb);
+    hipLaunchKernelGGL(k_copy, dim3(G), dim3(BS), 0, s, dst, src, n, pb);
+    APCG_CHECK_LAUNCH("k_copy");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_fill(hipStream_t s, double *x, double v, int64_t n) {
+    if (n == 0) return APCG_SUCCESS;
+    int G;
+    int64_t pb;
+    elementwise_grid(n, &G, &pb);
+    hipLaunchKernelGGL(k_fill, dim3(G), dim3(BS), 0, s, x, v, n, pb);
+    APCG_CHECK_LAUNCH("k_fill");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_scalar_op(hipStream_t s, int op, double *out, const double *a, const double *b) {
+    hipLaunchKernelGGL(k_scalar_op, dim3(1), dim3(64), 0, s, op, out, a, b);
+    APCG_CHECK_LAUNCH("k_scalar_op");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_scalar_set(hipStream_t s, double *out, double v) {
+    hipLaunchKernelGGL(k_scalar_set, dim3(1), dim3(64), 0, s, out, v);
+    APCG_CHECK_LAUNCH("k_scalar_set");
+    return APCG_SUCCESS;
+}
+
+apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
+    if (A->n == 0) return APCG_SUCCESS;
+    if (A->cfg.block_size == 512) return spmv_tb<512>(s, A, x, y);
+    return spmv_tb<256>(s, A, x, y);
+}
+
+}  // namespace apcg

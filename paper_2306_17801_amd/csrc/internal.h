@@ -1,0 +1,296 @@
+// internal.h -- shared declarations of the apcg runtime (host side) and the
+// device helpers every kernel file uses.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <atomic>
+#include <cstdint>
+#include <functional>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <utility>
+#include <vector>
+
+#include "../../include/apcg.h"
+
+namespace apcg {
+
+// ---------------------------------------------------------------------------
+// errors and counters
+// ---------------------------------------------------------------------------
+apcg_status set_error(apcg_status code, const std::string &msg);
+apcg_status hip_error(hipError_t e, const char *what);
+
+struct Counters {
+    std::atomic<int64_t> kernel_launches{0}, graph_launches{0}, host_syncs{0}, host_polls{0},
+        d2h_copies{0}, h2d_copies{0}, stream_waits{0};
+};
+extern Counters g_counters;
+
+#define APCG_HIP(call)                                                   \
+    do {                                                                 \
+        hipError_t e__ = (call);                                         \
+        if (e__ != hipSuccess) return ::apcg::hip_error(e__, #call);     \
+    } while (0)
+
+#define APCG_CHECK_LAUNCH(what)                                          \
+    do {                                                                 \
+        ::apcg::g_counters.kernel_launches++;                            \
+        hipError_t e__ = hipGetLastError();                              \
+        if (e__ != hipSuccess) return ::apcg::hip_error(e__, what);      \
+    } while (0)
+
+// ---------------------------------------------------------------------------
+// pooled events and the access registry (ordering rule of Section 3.1.2)
+// ---------------------------------------------------------------------------
+struct Event {
+    hipEvent_t e = nullptr;
+    int device = 0;
+    ~Event();
+};
+using EventRef = std::shared_ptr<Event>;
+EventRef event_get(int device);  // un-recorded event from the device's pool
+
+struct Record {
+    uint64_t writer_ctx = 0;  // 0: never written through the library
+    EventRef write_ev;
+    std::vector<std::pair<uint64_t, EventRef>> readers;  // reads since the last write
+};
+
+enum AccessMode { ACC_R = 1, ACC_W = 2, ACC_RW = 3 };
+struct Acc {
+    Record *rec;
+    int mode;
+};
+
+extern std::recursive_mutex g_mu;  // guards every Record and the deferred list
+
+// Deferred release: fn runs once every event in deps has completed.
+void defer_release(std::vector<EventRef> deps, std::function<void()> fn);
+void reap();                       // runs the releases whose events completed
+std::vector<EventRef> record_deps(const Record &r);
+
+// ---------------------------------------------------------------------------
+// solve workspace and per-context scratch
+// ---------------------------------------------------------------------------
+struct SolveState;  // device struct, defined in pcg.hip
+
+struct GraphKey {
+    const void *A, *x, *ws;
+    int32_t K, lpr, bs, blocks, pc, norm;
+    bool operator==(const GraphKey &o) const {
+        return A == o.A && x == o.x && ws == o.ws && K == o.K && lpr == o.lpr && bs == o.bs &&
+               blocks == o.blocks && pc == o.pc && norm == o.norm;
+    }
+};
+
+struct GraphEntry {
+    GraphKey key;
+    hipGraphExec_t exec = nullptr;
+    hipGraph_t graph = nullptr;
+};
+
+constexpr int kMaxBlocks = 8192;    // reduction partials per kernel
+constexpr int kNumCounters = 64;    // last-block counters per context
+constexpr int kMaxLookahead = 8;
+
+enum CounterSlot {
+    CNT_DOT = 0, CNT_PCG_INIT = 1, CNT_PCG_PRODUCT = 2, CNT_PCG_UPDATE = 3, CNT_TUNE = 4,
+};
+
+struct Workspace {
+    int64_t cap = 0;          // elements per vector
+    double *base = nullptr;   // 5 * cap doubles: r, dinv, p0, p1, w
+    SolveState *state = nullptr;
+    double *r() const { return base; }
+    double *dinv() const { return base + cap; }
+    double *p(int i) const { return base + (2 + i) * cap; }
+    double *w() const { return base + 4 * cap; }
+};
+
+}  // namespace apcg
+
+// ---------------------------------------------------------------------------
+// opaque handle structs
+// ---------------------------------------------------------------------------
+struct apcg_ctx_s {
+    uint64_t id = 0;
+    int32_t device = 0;
+    int32_t type = APCG_STREAM_DEFAULT;
+    hipStream_t stream = nullptr;
+    bool is_default_global = false;
+    double *partials = nullptr;      // 4 * kMaxBlocks
+    unsigned *counters = nullptr;    // kNumCounters, zero between kernels
+    int32_t *pinned_flags = nullptr; // kMaxLookahead host-pinned words
+    apcg::EventRef poll_ev[apcg::kMaxLookahead];
+    apcg::Workspace ws;
+    std::vector<apcg::GraphEntry> graphs;
+    // kernel timing (solve with kernel_timing = 1)
+    std::vector<hipEvent_t> tev;     // pairs per timed launch
+    std::vector<int> tkind;          // kind of each pair
+    int32_t tpairs = 0;
+    apcg::EventRef tdone;
+};
+
+struct apcg_scalar_s {
+    int32_t device = 0;
+    double *d = nullptr;  // slot in the device scalar pool
+    int64_t slot = -1;
+    apcg::Record rec;
+};
+
+struct apcg_vec_s {
+    int32_t device = 0;
+    double *d = nullptr;
+    int64_t n = 0;
+    apcg::Record rec;
+};
+
+struct apcg_mat_s {
+    int32_t device = 0;
+    int32_t n = 0;
+    int64_t nnz = 0;
+    const int32_t *rowptr = nullptr, *col = nullptr;
+    const double *val = nullptr;
+    apcg_spmv_config cfg{};
+    apcg::Record rec;
+};
+
+struct apcg_info_s {
+    int32_t device = 0;
+    int32_t count = 0;
+    apcg_solve_info *d = nullptr;
+    apcg::Record rec;
+};
+
+struct apcg_timer_s {
+    apcg::EventRef start, stop;
+};
+
+namespace apcg {
+
+// context helpers (runtime.hip)
+apcg_status resolve_ctx(apcg_ctx in, int device, apcg_ctx *out);  // NULL -> global default
+apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
+apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
+apcg_status ensure_workspace(apcg_ctx c, int64_t n);
+void spmv_default_config(int32_t n, int64_t nnz, apcg_spmv_config *cfg);
+int32_t normalise_blocks(int32_t blocks, int64_t units);  // multiple of 8, <= kMaxBlocks
+
+// kernel launchers (blas.hip)
+apcg_status launch_dot(hipStream_t s, const double *x, const double *y, int64_t n, double *out, int take_sqrt,
+                       double *partials, unsigned *counter);
+apcg_status launch_axpy(hipStream_t s, double *y, const double *a, double sign, const double *x, int64_t n);
+apcg_status launch_aypx(hipStream_t s, double *y, const double *b, const double *x, int64_t n);
+apcg_status launch_scale(hipStream_t s, double *x, const double *a, int64_t n);
+apcg_status launch_copy(hipStream_t s, double *dst, const double *src, int64_t n);
+apcg_status launch_fill(hipStream_t s, double *x, double v, int64_t n);
+apcg_status launch_scalar_op(hipStream_t s, int op, double *out, const double *a, const double *b);
+apcg_status launch_scalar_set(hipStream_t s, double *out, double v);
+apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y);
+
+// Grid and chunk for an elementwise pass over n entries: 2048 workgroups at
+// most, chunks a multiple of 64 entries (512-byte aligned for doubles).
+inline void elementwise_grid(int64_t n, int *G, int64_t *per_block) {
+    int64_t units = (n + 63) / 64;
+    *G = normalise_blocks(2048, units);
+    int64_t pb = (n + *G - 1) / *G;
+    *per_block = ((pb + 63) / 64) * 64;
+    if (*per_block < 64) *per_block = 64;
+}
+
+}  // namespace apcg
+
+// ---------------------------------------------------------------------------
+// device helpers
+// ---------------------------------------------------------------------------
+namespace apcg {
+namespace dev {
+
+// Workgroups are dealt round-robin to the 8 XCDs (block b runs on XCD b % 8).
+// Renumber them so XCD x owns the contiguous logical range
+// [x * G/8, (x+1) * G/8); G is always a multiple of 8.
+__device__ __forceinline__ int xcd_block(int b, int G) { return (b & 7) * (G >> 3) + (b >> 3); }
+
+struct Chunk {
+    int64_t lo, hi;
+};
+
+// The contiguous range [lo, hi) of the logical workgroup, clipped to n.
+__device__ __forceinline__ Chunk block_chunk(int64_t n, int64_t per_block) {
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    int64_t lo = (int64_t)lb * per_block;
+    int64_t hi = lo + per_block;
+    if (hi > n) hi = n;
+    return {lo, hi};
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum of v over the block; the result is valid in thread 0.
+template <int BS, int NV>
+__device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
+    constexpr int NW = BS / 64;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = wave_sum(v[k]);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * NW + wid] = v[k];
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) {
+            double s = lds[k * NW];
+            for (int w = 1; w < NW; ++w) s += lds[k * NW + w];
+            v[k] = s;
+        }
+    }
+}
+
+// Two-stage deterministic reduction: every block stores its sum in
+// partials[k*G + slot]; the block that arrives last (counted with an
+// agent-scope atomic) adds the G partials in a fixed order and returns true
+// with the totals in thread 0's v.  The counter is left at zero.
+template <int BS, int NV>
+__device__ __forceinline__ bool reduce_last_block(double (&v)[NV], double *partials, int G, int slot,
+                                                  unsigned *counter) {
+    __shared__ double lds[NV * (BS / 64)];
+    __shared__ int s_last;
+    block_sum<BS, NV>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partials[k * G + slot] = v[k];
+        __threadfence();
+        unsigned prev = atomicAdd(counter, 1u);
+        s_last = (prev == (unsigned)(G - 1));
+    }
+    __syncthreads();
+    if (!s_last) return false;
+    __threadfence();
+    double t[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) t[k] = 0.0;
+    for (int i = threadIdx.x; i < G; i += BS) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) t[k] += partials[k * G + i];
+    }
+    __syncthreads();
+    block_sum<BS, NV>(t, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] = t[k];
+        atomicExch(counter, 0u);
+    }
+    return true;
+}
+
+}  // namespace dev
+}  // namespace apcg

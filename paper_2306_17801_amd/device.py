@@ -1,0 +1,74 @@
+"""Upload helpers: place a CSR system in torch-owned GPU memory and wrap it
+for the library.  Marshalling only; the tensors are kept alive by the
+returned objects for as long as the wrappers exist."""
+from __future__ import annotations
+
+import numpy as np
+
+from . import (apcg_mat_destroy, apcg_mat_wrap_csr, apcg_vec_destroy, apcg_vec_wrap)
+
+
+class DeviceVec:
+    """A float64 GPU tensor and its library wrapper."""
+
+    def __init__(self, data, device: int = 0):
+        import torch
+
+        if isinstance(data, torch.Tensor):
+            t = data.to(device=f"cuda:{device}", dtype=torch.float64).contiguous()
+        else:
+            t = torch.from_numpy(np.ascontiguousarray(data, dtype=np.float64)).to(f"cuda:{device}")
+        torch.cuda.synchronize(device)
+        self.t = t
+        self.n = t.numel()
+        self.h = apcg_vec_wrap(t)
+
+    @classmethod
+    def zeros(cls, n: int, device: int = 0):
+        import torch
+
+        return cls(torch.zeros(n, dtype=torch.float64, device=f"cuda:{device}"), device)
+
+    def numpy(self):
+        """Host copy through the library accessor (waits on the last writer)."""
+        from . import apcg_vec_copy_to_host
+
+        return apcg_vec_copy_to_host(self.h, self.n)
+
+    def close(self):
+        if self.h is not None:
+            apcg_vec_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class DeviceCSR:
+    """CSR arrays in GPU tensors and their library wrapper."""
+
+    def __init__(self, A, device: int = 0):
+        import torch
+
+        dev = f"cuda:{device}"
+        self.n = int(A.n)
+        self.nnz = int(A.rowptr[-1])
+        self.rowptr = torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int32)).to(dev)
+        self.col = torch.from_numpy(np.ascontiguousarray(A.col, dtype=np.int32)).to(dev)
+        self.val = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(dev)
+        torch.cuda.synchronize(device)
+        self.h = apcg_mat_wrap_csr(self.rowptr, self.col, self.val, host_rowptr=np.asarray(A.rowptr, np.int32))
+
+    def close(self):
+        if self.h is not None:
+            apcg_mat_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

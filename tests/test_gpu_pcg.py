@@ -1,0 +1,174 @@
+"""GPU parity of the PCG hot path against the CPU oracle, through the C ABI.
+
+Bar: iteration count within +-1 of the oracle and ||x - x_ref|| / ||x_ref||
+<= 1e-9 at rtol 1e-10 (the two differ only in summation order and FMA use);
+at matched iteration counts the iterates agree far more tightly.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_17801_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apcg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_17801_amd as m
+
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(apcg):
+    c = apcg.apcg_ctx_create(0)
+    yield c
+    apcg.apcg_ctx_synchronize(c)
+    apcg.apcg_ctx_destroy(c)
+
+
+def gpu_solve(apcg, ctx, A, b, rtol, maxit, x0=None, **opt):
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    dA = DeviceCSR(A)
+    db = DeviceVec(b)
+    dx = DeviceVec(np.zeros(A.n) if x0 is None else x0)
+    if x0 is None and "x0_is_zero" not in opt:
+        opt["x0_is_zero"] = 1
+    info = apcg.apcg_info_create(0, 1)
+    cfg = opt.pop("spmv", None)
+    if cfg is not None:
+        apcg.apcg_mat_set_spmv_config(dA.h, *cfg)
+    opts = apcg.apcg_solve_opts_default(**opt)
+    apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, rtol, maxit, opts, info, 0)
+    res = apcg.apcg_info_get(info, 0)
+    x = dx.numpy()
+    apcg.apcg_info_destroy(info)
+    return res, x
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+@pytest.mark.parametrize("mode", [0, 1, 2])
+@pytest.mark.parametrize("pc", [0, 1])
+def test_poisson64_parity(apcg, ctx, mode, pc):
+    """2D 5-point Poisson 64 x 64, x* ~ U[-1,1], x0 = 0, rtol 1e-10."""
+    print(f"case poisson64 mode={mode} pc={pc}", flush=True)
+    s = P.poisson2d_manufactured(64, 0)
+    ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=10000, pc=pc)
+    res, x = gpu_solve(apcg, ctx, s.A, s.b, 1e-10, 10000, pc=pc, mode=mode)
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED
+    assert abs(res["iterations"] - ref.its) <= 1
+    assert rel(x, ref.x) <= 1e-9
+    assert rel(x, s.x_exact) <= 1711.7 * 1e-10
+    assert res["ref_norm"] == pytest.approx(ref.ref, rel=1e-13)
+
+
+@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("tb", [256, 512])
+def test_spmv_schedules_same_solve(apcg, ctx, lpr, tb):
+    """Every SpMV schedule gives the oracle's iteration count on a ragged 3D
+    variable-coefficient system (n = 21 * 17 * 13, not a multiple of 64)."""
+    print(f"case schedule lpr={lpr} tb={tb}", flush=True)
+    rng = np.random.default_rng(40)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((13, 17, 21))), aniso=7.0)
+    b = rng.uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
+    res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=(lpr, tb, 0))
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED
+    assert abs(res["iterations"] - ref.its) <= 1
+    assert rel(x, ref.x) <= 1e-9
+
+
+def test_matched_iterations_tight(apcg, ctx):
+    """At a fixed iteration count (rtol = 0) the GPU and oracle iterates agree
+    to rounding: the paper's fixed-20-iteration protocol (Section 4.1)."""
+    rng = np.random.default_rng(41)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((40, 50))))
+    b = rng.uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, rtol=0.0, maxit=20)
+    res, x = gpu_solve(apcg, ctx, A, b, 0.0, 20)
+    assert res["status"] == apcg.APCG_SOLVE_MAXIT and res["iterations"] == 20
+    assert rel(x, ref.x) <= 1e-12
+    assert res["res_norm"] == pytest.approx(ref.res, rel=1e-10)
+
+
+def test_nonzero_initial_guess_and_preconditioned_norm(apcg, ctx):
+    rng = np.random.default_rng(42)
+    A = P.diffusion_csr(np.exp(1.5 * rng.standard_normal((30, 33))), aniso=20.0)
+    b = rng.uniform(-1, 1, A.n)
+    x0 = rng.uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, x0=x0, rtol=1e-10, maxit=5000, norm_type=oracle.NORM_PRECONDITIONED)
+    res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, x0=x0, norm_type=1)
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED
+    assert abs(res["iterations"] - ref.its) <= 1
+    assert rel(x, ref.x) <= 1e-9
+    assert res["ref_norm"] == pytest.approx(ref.ref, rel=1e-13)
+
+
+def test_edge_cases(apcg, ctx):
+    A = P.laplace_2d(7)
+    n = A.n
+    # b = 0 with a nonzero x0: x = 0, converged in 0 iterations
+    res, x = gpu_solve(apcg, ctx, A, np.zeros(n), 1e-8, 100, x0=np.ones(n))
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED and res["iterations"] == 0 and np.all(x == 0)
+    # maxit = 0 and 1
+    res, _ = gpu_solve(apcg, ctx, A, np.ones(n), 1e-8, 0)
+    assert res["status"] == apcg.APCG_SOLVE_MAXIT and res["iterations"] == 0
+    res, x = gpu_solve(apcg, ctx, A, np.ones(n), 1e-14, 1)
+    ref = oracle.pcg(A, np.ones(n), rtol=1e-14, maxit=1)
+    assert res["status"] == apcg.APCG_SOLVE_MAXIT and res["iterations"] == 1 and rel(x, ref.x) <= 1e-14
+    # x0 already the solution
+    s = P.poisson2d_manufactured(7, 3)
+    res, _ = gpu_solve(apcg, ctx, s.A, s.b, 1e-8, 100, x0=s.x_exact)
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED and res["iterations"] == 0
+    # one unknown
+    one = P.CSR(n=1, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32), val=np.array([4.0]))
+    res, x = gpu_solve(apcg, ctx, one, np.array([2.0]), 1e-12, 10)
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED and res["iterations"] == 1 and x[0] == 0.5
+
+
+def test_failure_states(apcg, ctx):
+    A = P.laplace_2d(6)
+    n = A.n
+    # non-positive diagonal: Jacobi setup error
+    B = P.CSR(n=A.n, rowptr=A.rowptr, col=A.col, val=A.val.copy())
+    diag_pos = np.array([k for i in range(n) for k in range(B.rowptr[i], B.rowptr[i + 1]) if B.col[k] == i])
+    B.val[diag_pos[5]] = -4.0
+    res, _ = gpu_solve(apcg, ctx, B, np.ones(n), 1e-8, 100)
+    assert res["status"] == apcg.APCG_SOLVE_SETUP_ERROR
+    # NaN in b
+    b = np.ones(n)
+    b[3] = np.nan
+    res, _ = gpu_solve(apcg, ctx, A, b, 1e-8, 100)
+    assert res["status"] == apcg.APCG_SOLVE_NAN
+    # indefinite operator, no preconditioner: p.Ap = 0 at the first step
+    D = P.CSR(n=2, rowptr=np.array([0, 1, 2], np.int32), col=np.array([0, 1], np.int32), val=np.array([1.0, -1.0]))
+    res, _ = gpu_solve(apcg, ctx, D, np.array([1.0, 1.0]), 1e-10, 10, pc=0)
+    ref = oracle.pcg(D, np.array([1.0, 1.0]), rtol=1e-10, maxit=10, pc=0)
+    assert ref.status == oracle.BREAKDOWN_PAP
+    assert res["status"] == apcg.APCG_SOLVE_BREAKDOWN_PAP and res["iterations"] == 0
+
+
+def test_repeated_solves_bitwise_identical(apcg, ctx):
+    """Fixed-order reductions: repeated solves agree bit for bit (the
+    PostSolve residual check of Section 4.1 made exact)."""
+    rng = np.random.default_rng(43)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((64, 70))))
+    b = rng.uniform(-1, 1, A.n)
+    r1, x1 = gpu_solve(apcg, ctx, A, b, 1e-8, 5000)
+    r2, x2 = gpu_solve(apcg, ctx, A, b, 1e-8, 5000, mode=1)
+    r3, x3 = gpu_solve(apcg, ctx, A, b, 1e-8, 5000, mode=2)
+    assert r1 == r2 == r3
+    assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
