@@ -1,0 +1,236 @@
+#!/usr/bin/env python3
+"""Benchmark: Jacobi-PCG solves/s on the 3D 7-point variable-coefficient
+diffusion system (128^3 cells, 2,097,152 rows, 14,581,760 nonzeros; k = exp of
+a 3^3 box-smoothed N(0,1) field, harmonic faces, b ~ U[-1,1], seed 2),
+rtol 1e-8, x0 = 0, FP64, on one MI355X.
+
+A step is one complete solve (setup kernels and every iteration until the
+device-side convergence test fires) with A, b and x resident in HBM.  Timing
+follows the paper's protocol (Section 4.1): warm-up solves, then K timed
+solves bracketed by device synchronisation; solves/s = K / elapsed.
+
+Also reported on the same JSON line:
+  roofline      -- the fused product kernel (SpMV + direction update + p.Ap):
+                   algorithmic bytes per launch / mean launch duration, the
+                   duration taken with HIP events on the solve's stream by a
+                   kernel-timed solve right after the timed region;
+  cpu_baseline  -- the CPU oracle (serial C, one thread) timed on one full
+                   solve of the same system;
+  variants      -- the same solve with the loop launched kernel by kernel
+                   (stream) and with a host check after every kernel
+                   (the synchronous shape the paper compares against).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "PCG solves/s at rtol 1e-8 (batched+learned vs plain); SpMV+vec HBM GB/s"
+HBM_PEAK_GBS = 8000.0
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pcg_product_diffusion3d_128.json")
+KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_17801_amd", "csrc", "pcg.hip")
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def source_hash(path):
+    with open(path, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def copy_calibration(apcg, torch):
+    """Five copies of 2^27 doubles (1 GiB read + 1 GiB written each) with the
+    library's copy kernel: the reference reading for the HBM byte counters."""
+    n = 1 << 27
+    src = torch.ones(n, dtype=torch.float64, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    ctx = apcg.apcg_ctx_create(0)
+    vs, vd = apcg.apcg_vec_wrap(src), apcg.apcg_vec_wrap(dst)
+    t = apcg.apcg_timer_create()
+    apcg.apcg_vec_copy_async(vd, vs, ctx)
+    apcg.apcg_timer_start(t, ctx)
+    for _ in range(5):
+        apcg.apcg_vec_copy_async(vd, vs, ctx)
+    apcg.apcg_timer_stop(t, ctx)
+    ms = apcg.apcg_timer_elapsed_ms(t) / 5
+    print(json.dumps({"copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n, "ms_per_copy": round(ms, 4),
+                      "gbs": round(16 * n / (ms * 1e-3) / 1e9, 1)}), flush=True)
+    apcg.apcg_ctx_synchronize(ctx)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--n", type=int, default=128, help="cells per axis of the 3D system")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(run with --gpus 1)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2306_17801_amd as apcg
+    from paper_2306_17801_amd import problems
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    apcg.load()
+
+    if args.copy_calibration:
+        copy_calibration(apcg, torch)
+        return
+
+    t0 = time.time()
+    sysm = problems.diffusion3d_smoothed(args.n, seed=2)
+    A_h = sysm.A
+    n, nnz = A_h.n, A_h.nnz
+    log(f"[bench] generated n={n} nnz={nnz} in {time.time() - t0:.1f}s")
+
+    ctx = apcg.apcg_ctx_create(0)
+    A = DeviceCSR(A_h)
+    b = DeviceVec(sysm.b)
+    x = DeviceVec.zeros(n)
+    info = apcg.apcg_info_create(0, 1)
+    rtol, maxit = 1e-8, 50000
+
+    tuned = None
+    if not args.no_autotune:
+        cfg, us = apcg.apcg_mat_autotune(A.h, ctx, 10)
+        tuned = {"config": cfg, "product_us": round(us, 2)}
+        log(f"[bench] autotune: {cfg} {us:.1f} us")
+
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+
+    def solve(o=opts):
+        apcg.apcg_ksp_solve(ctx, A.h, b.h, x.h, rtol, maxit, o, info, 0)
+
+    for _ in range(args.warmup):
+        solve()
+    torch.cuda.synchronize()
+    res = apcg.apcg_info_get(info, 0)
+    log(f"[bench] warm-up solve: {res}")
+
+    apcg.apcg_counters_reset()
+    torch.cuda.synchronize()
+    t_start = time.perf_counter()
+    for _ in range(args.steps):
+        solve()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t_start
+    counters = apcg.apcg_counters_get()
+    res = apcg.apcg_info_get(info, 0)
+    its = res["iterations"]
+    ms_per_step = 1000.0 * elapsed / args.steps
+    value = args.steps / elapsed
+    log(f"[bench] timed {args.steps} solves: {ms_per_step:.3f} ms/solve, its={its}, status={res['status']}")
+
+    # true residual of the last solve (host check of the result, not timed)
+    xs = x.numpy()
+    true_rel = float(np.linalg.norm(sysm.b - A_h.to_scipy() @ xs) / np.linalg.norm(sysm.b))
+
+    # per-kernel durations: a kernel-timed solve (HIP events around every
+    # product / update launch on the context's stream)
+    topts = apcg.apcg_solve_opts_default(x0_is_zero=1, kernel_timing=1)
+    solve(topts)
+    prod_us, prod_cnt = apcg.apcg_ctx_kernel_times(ctx, 0)
+    upd_us, upd_cnt = apcg.apcg_ctx_kernel_times(ctx, 1)
+    prod_bytes = 12 * nnz + 4 * (n + 1) + 40 * n
+    upd_bytes = 56 * n
+    iter_bytes = 12 * nnz + 4 * (n + 1) + 96 * n
+    achieved = prod_bytes / (prod_us * 1e-6) / 1e9
+    traffic = None
+    if os.path.exists(TRAFFIC_FILE):
+        with open(TRAFFIC_FILE) as f:
+            tr = json.load(f)
+        if tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n:
+            traffic = tr.get("bytes_per_launch")
+    roofline = {"bound": "hbm", "kernel": "k_pcg_product", "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes_per_launch": prod_bytes,
+                "mean_launch_us": round(prod_us, 3), "launches_timed": prod_cnt}
+    per_iter_us = 1000.0 * ms_per_step / max(its, 1)
+    extra = {
+        "iterations": its, "status": res["status"], "true_relres": true_rel,
+        "per_iteration_us": round(per_iter_us, 3),
+        "iteration_gbs": round(iter_bytes / (per_iter_us * 1e-6) / 1e9, 1),
+        "update_kernel": {"mean_launch_us": round(upd_us, 3), "algorithmic_bytes_per_launch": upd_bytes,
+                          "achieved_gbs": round(upd_bytes / (upd_us * 1e-6) / 1e9, 1)},
+        "counters_timed_region": counters,
+        "autotune": tuned,
+    }
+    log(f"[bench] product {prod_us:.2f} us ({achieved:.0f} GB/s), update {upd_us:.2f} us")
+
+    if not args.no_variants:
+        var = {}
+        for name, mode in (("stream", apcg.APCG_MODE_STREAM), ("host_check", apcg.APCG_MODE_HOST_CHECK)):
+            o = apcg.apcg_solve_opts_default(x0_is_zero=1, mode=mode)
+            solve(o)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            reps = 2
+            for _ in range(reps):
+                solve(o)
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - t1) / reps
+            var[name] = {"ms_per_solve": round(1000 * dt, 3), "solves_per_s": round(1 / dt, 3),
+                         "iterations": apcg.apcg_info_get(info, 0)["iterations"]}
+            log(f"[bench] variant {name}: {1000 * dt:.2f} ms/solve")
+        var["graph_speedup_vs_host_check"] = round(var["host_check"]["ms_per_solve"] / ms_per_step, 3)
+        extra["variants"] = var
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        log("[bench] timing the CPU oracle on one full solve ...")
+        t1 = time.perf_counter()
+        r = oracle.pcg(A_h, sysm.b, rtol=rtol, maxit=maxit)
+        dt = time.perf_counter() - t1
+        cpu = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
+               "sample": f"one full serial FP64 Jacobi-PCG solve of the same system ({r.its} iterations, "
+                         f"{dt:.1f} s) on the host",
+               "iterations": r.its}
+        log(f"[bench] oracle: {dt:.1f} s, its={r.its}")
+
+    props = apcg.apcg_device_props_get(0)
+    line = {
+        "metric": METRIC, "value": round(value, 4), "unit": "solves/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4), "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+        "config": {"workload": f"diffusion3d_{args.n}^3_box3_jacobi_pcg", "n": n, "nnz": nnz, "rtol": rtol,
+                   "pc": "jacobi", "x0": "zero", "mode": "graph", "iters_per_graph": 16, "lookahead": 2,
+                   "device": props["name"], "arch": props["arch"]},
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "extra": extra,
+    }
+    print(json.dumps(line), flush=True)
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_synchronize(ctx)
+
+
+if __name__ == "__main__":
+    main()

@@ -243,27 +243,36 @@ apcg_status apcg_mat_destroy(apcg_mat A);
 /* y = A x (Section 3.3, MatMult / KSP_MatMultAsync). */
 apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx);
 
-/* SpMV schedule: lanes_per_row in {1,2,4,8,16,32,64} lanes of a 64-wide
- * wavefront cooperate on one row; block_size in {64,128,256,512,1024}
- * threads; blocks is the number of workgroups (rounded up to a multiple of
- * the 8 XCDs; 0 = library default).  Each workgroup owns a contiguous range
- * of rows and workgroups are renumbered so each XCD owns a contiguous
- * slice of the matrix. */
+/* SpMV schedule.
+ *   schedule APCG_SPMV_ROWGROUP: lanes_per_row in {1,2,4,8,16,32,64} lanes
+ *       of a 64-wide wavefront cooperate on one row;
+ *   schedule APCG_SPMV_STREAM: the workgroup stages the nonzeros of
+ *       block_size consecutive rows in LDS with coalesced loads, then each
+ *       thread reduces one row (lanes_per_row is ignored).  Needs every such
+ *       row block to hold at most 5376 nonzeros (about 21 per row at block
+ *       256, 10 at block 512); apcg_mat_set_spmv_config rejects it otherwise.
+ * block_size in {256, 512} threads; blocks is the number of workgroups
+ * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
+ * workgroup owns a contiguous range of rows and workgroups are renumbered so
+ * each XCD owns a contiguous slice of the matrix. */
+#define APCG_SPMV_ROWGROUP 0
+#define APCG_SPMV_STREAM 1
 typedef struct apcg_spmv_config {
     int32_t lanes_per_row;
     int32_t block_size;
     int32_t blocks;
-    int32_t reserved;
+    int32_t schedule;
 } apcg_spmv_config;
 
 apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg);
 apcg_status apcg_mat_get_spmv_config(apcg_mat A, apcg_spmv_config *cfg);
 
-/* Autotuner: times every candidate schedule of the fused PCG product
- * kernel (reps launches each, HIP events on ctx's stream), keeps the
- * fastest in A and returns it in *best (and its mean time in *best_us).
- * The vectors are scratch the library allocates and frees itself.
- * Blocks the host until the sweep finishes. */
+/* Autotuner: times every candidate schedule of one PCG iteration (the
+ * fused product kernel and the update kernel with their reductions; reps
+ * iterations each, HIP events on ctx's stream), keeps the fastest in A and
+ * returns it in *best (and the mean iteration time in *best_us).  Runs on
+ * scratch vectors (ctx's workspace and one vector the library allocates and
+ * frees); A's arrays are only read.  Blocks the host until the sweep ends. */
 apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best,
                               double *best_us);
 

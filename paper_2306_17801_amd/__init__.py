@@ -250,22 +250,25 @@ def apcg_mat_mult_async(A, x, y, ctx=None) -> None:
     check("apcg_mat_mult_async", _L().apcg_mat_mult_async(_h(A), _h(x), _h(y), _h(ctx)))
 
 
-def apcg_mat_set_spmv_config(A, lanes_per_row: int, block_size: int = 256, blocks: int = 0) -> None:
-    cfg = _capi.apcg_spmv_config(lanes_per_row, block_size, blocks, 0)
+def apcg_mat_set_spmv_config(A, lanes_per_row: int, block_size: int = 256, blocks: int = 0,
+                             schedule: int = _capi.APCG_SPMV_ROWGROUP) -> None:
+    cfg = _capi.apcg_spmv_config(lanes_per_row, block_size, blocks, schedule)
     check("apcg_mat_set_spmv_config", _L().apcg_mat_set_spmv_config(_h(A), ctypes.byref(cfg)))
 
 
 def apcg_mat_get_spmv_config(A) -> dict:
     cfg = _capi.apcg_spmv_config()
     check("apcg_mat_get_spmv_config", _L().apcg_mat_get_spmv_config(_h(A), ctypes.byref(cfg)))
-    return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks}
+    return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks,
+            "schedule": cfg.schedule}
 
 
 def apcg_mat_autotune(A, ctx, reps: int = 20):
     cfg = _capi.apcg_spmv_config()
     us = ctypes.c_double()
     check("apcg_mat_autotune", _L().apcg_mat_autotune(_h(A), _h(ctx), reps, ctypes.byref(cfg), ctypes.byref(us)))
-    return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks}, us.value
+    return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks,
+            "schedule": cfg.schedule}, us.value
 
 
 # ------------------------------------------------------------------ solve

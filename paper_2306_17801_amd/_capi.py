@@ -59,10 +59,12 @@ APCG_NORM_PRECONDITIONED = 1
 APCG_MODE_GRAPH = 0
 APCG_MODE_STREAM = 1
 APCG_MODE_HOST_CHECK = 2
+APCG_SPMV_ROWGROUP = 0
+APCG_SPMV_STREAM = 1
 
 
 class apcg_spmv_config(ctypes.Structure):
-    _fields_ = [("lanes_per_row", c_i32), ("block_size", c_i32), ("blocks", c_i32), ("reserved", c_i32)]
+    _fields_ = [("lanes_per_row", c_i32), ("block_size", c_i32), ("blocks", c_i32), ("schedule", c_i32)]
 
 
 class apcg_solve_opts(ctypes.Structure):

@@ -7,6 +7,7 @@
 // from device slots, never passed through the host.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 
 #include "internal.h"
@@ -20,15 +21,20 @@ using dev::Chunk;
 using dev::block_chunk;
 
 __global__ __launch_bounds__(BS) void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
-                                            int64_t per_block, double *out, int take_sqrt, double *partials,
-                                            unsigned *counter) {
+                                            int64_t per_block, double *partials) {
     const Chunk c = block_chunk(n, per_block);
     double acc = 0.0;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) acc = fma(x[i], y[i], acc);
     double v[1] = {acc};
-    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-    if (dev::reduce_last_block<BS, 1>(v, partials, gridDim.x, lb, counter) && threadIdx.x == 0)
-        *out = take_sqrt ? sqrt(v[0]) : v[0];
+    dev::store_partials<BS, 1>(v, partials, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Second stage of the dot product: one workgroup adds the partials and
+// writes the scalar (its square root for the 2-norm).
+__global__ __launch_bounds__(64) void k_dot_final(const double *partials, int G, double *out, int take_sqrt) {
+    double t[1];
+    dev::reduce_partials<64, 1>(partials, G, t);
+    if (threadIdx.x == 0) *out = take_sqrt ? sqrt(t[0]) : t[0];
 }
 
 __global__ __launch_bounds__(BS) void k_axpy(double *__restrict__ y, const double *a, double sign,
@@ -111,6 +117,40 @@ __global__ __launch_bounds__(TB) void k_spmv(int32_t n, const int32_t *__restric
     }
 }
 
+// Staged schedule (see k_pcg_product_stream): nonzeros of TB consecutive
+// rows copied to LDS with coalesced loads, one row per thread.
+template <int TB>
+__global__ __launch_bounds__(TB) void k_spmv_stream(int32_t n, const int32_t *__restrict__ rowptr,
+                                                    const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                    const double *__restrict__ x, double *__restrict__ y,
+                                                    int32_t chunks_per_block, int32_t lds_nnz) {
+    extern __shared__ double stage[];
+    double *sv = stage;
+    int32_t *sc = reinterpret_cast<int32_t *>(stage + lds_nnz);
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int nchunks = (n + TB - 1) / TB;
+    const int c0 = lb * chunks_per_block;
+    const int c1 = min(nchunks, c0 + chunks_per_block);
+    for (int c = c0; c < c1; ++c) {
+        const int row0 = c * TB;
+        const int row1 = min(n, row0 + TB);
+        const int k0 = rowptr[row0], k1 = rowptr[row1];
+        __syncthreads();
+        for (int k = k0 + threadIdx.x; k < k1; k += TB) {
+            sv[k - k0] = __builtin_nontemporal_load(val + k);
+            sc[k - k0] = __builtin_nontemporal_load(col + k);
+        }
+        __syncthreads();
+        const int row = row0 + threadIdx.x;
+        if (row < row1) {
+            const int s = rowptr[row] - k0, e = rowptr[row + 1] - k0;
+            double sum = 0.0;
+            for (int k = s; k < e; ++k) sum = fma(sv[k], x[sc[k]], sum);
+            y[row] = sum;
+        }
+    }
+}
+
 template <int TB>
 apcg_status spmv_tb(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
     const int lpr = A->cfg.lanes_per_row;
@@ -140,12 +180,14 @@ apcg_status spmv_tb(hipStream_t s, const apcg_mat_s *A, const double *x, double 
 }  // namespace
 
 apcg_status launch_dot(hipStream_t s, const double *x, const double *y, int64_t n, double *out, int take_sqrt,
-                       double *partials, unsigned *counter) {
+                       double *partials) {
     int G;
     int64_t pb;
     elementwise_grid(n, &G, &pb);
-    hipLaunchKernelGGL(k_dot, dim3(G), dim3(BS), 0, s, x, y, n, pb, out, take_sqrt, partials, counter);
+    hipLaunchKernelGGL(k_dot, dim3(G), dim3(BS), 0, s, x, y, n, pb, partials);
     APCG_CHECK_LAUNCH("k_dot");
+    hipLaunchKernelGGL(k_dot_final, dim3(1), dim3(64), 0, s, (const double *)partials, G, out, take_sqrt);
+    APCG_CHECK_LAUNCH("k_dot_final");
     return APCG_SUCCESS;
 }
 
@@ -213,6 +255,22 @@ apcg_status launch_scalar_set(hipStream_t s, double *out, double v) {
 
 apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
     if (A->n == 0) return APCG_SUCCESS;
+    if (A->cfg.schedule == APCG_SPMV_STREAM && stream_fits(A, A->cfg.block_size)) {
+        const int tb = A->cfg.block_size;
+        const int64_t nchunks = ((int64_t)A->n + tb - 1) / tb;
+        const int G = normalise_blocks(A->cfg.blocks, nchunks);
+        const int32_t cpb = (int32_t)std::max<int64_t>(1, (nchunks + G - 1) / G);
+        const int32_t lds_nnz = (int32_t)std::max<int64_t>(2, ((A->max_block_nnz[tb == 512 ? 1 : 0] + 1) / 2) * 2);
+        const size_t lds = (size_t)lds_nnz * (sizeof(double) + sizeof(int32_t));
+        if (tb == 512)
+            hipLaunchKernelGGL((k_spmv_stream<512>), dim3(G), dim3(512), lds, s, A->n, A->rowptr, A->col, A->val, x,
+                               y, cpb, lds_nnz);
+        else
+            hipLaunchKernelGGL((k_spmv_stream<256>), dim3(G), dim3(256), lds, s, A->n, A->rowptr, A->col, A->val, x,
+                               y, cpb, lds_nnz);
+        APCG_CHECK_LAUNCH("k_spmv_stream");
+        return APCG_SUCCESS;
+    }
     if (A->cfg.block_size == 512) return spmv_tb<512>(s, A, x, y);
     return spmv_tb<256>(s, A, x, y);
 }

@@ -93,17 +93,18 @@ struct GraphEntry {
 };
 
 constexpr int kMaxBlocks = 8192;    // reduction partials per kernel
-constexpr int kNumCounters = 64;    // last-block counters per context
+constexpr int kPartialSlots = 8;    // kMaxBlocks-sized slices of the partials buffer
 constexpr int kMaxLookahead = 8;
+// Largest staged chunk (nonzeros): 12 bytes each must fit the 64 KiB of LDS
+// one workgroup may take.
+constexpr int kStreamMaxNnz = 5376;
+inline bool stream_fits(const apcg_mat_s *A, int tb);
 
-enum CounterSlot {
-    CNT_DOT = 0, CNT_PCG_INIT = 1, CNT_PCG_PRODUCT = 2, CNT_PCG_UPDATE = 3, CNT_TUNE = 4,
-};
 
 struct Workspace {
     int64_t cap = 0;          // elements per vector
     double *base = nullptr;   // 5 * cap doubles: r, dinv, p0, p1, w
-    SolveState *state = nullptr;
+    SolveState *state = nullptr;  // 256 bytes
     double *r() const { return base; }
     double *dinv() const { return base + cap; }
     double *p(int i) const { return base + (2 + i) * cap; }
@@ -121,8 +122,7 @@ struct apcg_ctx_s {
     int32_t type = APCG_STREAM_DEFAULT;
     hipStream_t stream = nullptr;
     bool is_default_global = false;
-    double *partials = nullptr;      // 4 * kMaxBlocks
-    unsigned *counters = nullptr;    // kNumCounters, zero between kernels
+    double *partials = nullptr;      // kPartialSlots * kMaxBlocks
     int32_t *pinned_flags = nullptr; // kMaxLookahead host-pinned words
     apcg::EventRef poll_ev[apcg::kMaxLookahead];
     apcg::Workspace ws;
@@ -155,6 +155,7 @@ struct apcg_mat_s {
     const int32_t *rowptr = nullptr, *col = nullptr;
     const double *val = nullptr;
     apcg_spmv_config cfg{};
+    int64_t max_block_nnz[2] = {0, 0};  // most nonzeros in any 256- / 512-row block
     apcg::Record rec;
 };
 
@@ -181,7 +182,7 @@ int32_t normalise_blocks(int32_t blocks, int64_t units);  // multiple of 8, <= k
 
 // kernel launchers (blas.hip)
 apcg_status launch_dot(hipStream_t s, const double *x, const double *y, int64_t n, double *out, int take_sqrt,
-                       double *partials, unsigned *counter);
+                       double *partials);
 apcg_status launch_axpy(hipStream_t s, double *y, const double *a, double sign, const double *x, int64_t n);
 apcg_status launch_aypx(hipStream_t s, double *y, const double *b, const double *x, int64_t n);
 apcg_status launch_scale(hipStream_t s, double *x, const double *a, int64_t n);
@@ -190,6 +191,10 @@ apcg_status launch_fill(hipStream_t s, double *x, double v, int64_t n);
 apcg_status launch_scalar_op(hipStream_t s, int op, double *out, const double *a, const double *b);
 apcg_status launch_scalar_set(hipStream_t s, double *out, double v);
 apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y);
+
+inline bool stream_fits(const apcg_mat_s *A, int tb) {
+    return (tb == 256 || tb == 512) && A->max_block_nnz[tb == 512 ? 1 : 0] <= kStreamMaxNnz;
+}
 
 // Grid and chunk for an elementwise pass over n entries: 2048 workgroups at
 // most, chunks a multiple of 64 entries (512-byte aligned for doubles).
@@ -255,26 +260,28 @@ __device__ __forceinline__ void block_sum(double (&v)[NV], double *lds) {
     }
 }
 
-// Two-stage deterministic reduction: every block stores its sum in
-// partials[k*G + slot]; the block that arrives last (counted with an
-// agent-scope atomic) adds the G partials in a fixed order and returns true
-// with the totals in thread 0's v.  The counter is left at zero.
+// First stage of a deterministic reduction: the block's sums go to
+// partials[k*G + slot].  No fence and no atomic: the consumer is a later
+// kernel, and the kernel boundary makes the partials visible to it.
 template <int BS, int NV>
-__device__ __forceinline__ bool reduce_last_block(double (&v)[NV], double *partials, int G, int slot,
-                                                  unsigned *counter) {
+__device__ __forceinline__ void store_partials(double (&v)[NV], double *partials, int G, int slot) {
     __shared__ double lds[NV * (BS / 64)];
-    __shared__ int s_last;
     block_sum<BS, NV>(v, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) partials[k * G + slot] = v[k];
-        __threadfence();
-        unsigned prev = atomicAdd(counter, 1u);
-        s_last = (prev == (unsigned)(G - 1));
     }
-    __syncthreads();
-    if (!s_last) return false;
-    __threadfence();
+}
+
+// Second stage, run redundantly by every workgroup of the consuming kernel:
+// thread t adds partials[k*G + i] for i = t, t + BS, ... in index order, then
+// the fixed block tree.  Every workgroup of one kernel runs the same
+// instruction sequence, so all of them obtain bit-identical totals.  All
+// threads of the block return the totals.
+template <int BS, int NV>
+__device__ __forceinline__ void reduce_partials(const double *partials, int G, double (&out)[NV]) {
+    __shared__ double lds[NV * (BS / 64)];
+    __shared__ double bcast[NV];
     double t[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) t[k] = 0.0;
@@ -282,14 +289,14 @@ __device__ __forceinline__ bool reduce_last_block(double (&v)[NV], double *parti
 #pragma unroll
         for (int k = 0; k < NV; ++k) t[k] += partials[k * G + i];
     }
-    __syncthreads();
     block_sum<BS, NV>(t, lds);
     if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] = t[k];
-        atomicExch(counter, 0u);
+        for (int k = 0; k < NV; ++k) bcast[k] = t[k];
     }
-    return true;
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) out[k] = bcast[k];
 }
 
 }  // namespace dev

@@ -2,23 +2,35 @@
 // scalar on the device (the PCG loop of Section 3.3 with Jacobi
 // preconditioning as in Section 4.1).
 //
-// One iteration is two kernels, each ending in a deterministic two-stage
-// reduction whose last workgroup evaluates the scalar step on the device:
+// One iteration k is two kernels:
 //
-//   product:  p_new = D^-1 r + beta p_old  (formed while gathering, so the
-//             direction update costs no extra pass), w = A p_new,
-//             delta = p_new . w;  epilogue: alpha = rho / delta, or
-//             BREAKDOWN_PAP when delta is not positive.
-//   update:   x += alpha p_new, r -= alpha w, z = D^-1 r (not stored),
-//             rho' = z . r and nu = ||r||^2 (or ||z||^2); epilogue: count
-//             the iteration, convergence / NaN / breakdown / iteration-limit
-//             tests, beta = rho' / rho.
+//   product P_k: every workgroup first reduces the update partials of
+//       iteration k-1 (rho_{k-1} = z.r, ||r||^2) and applies the tests of
+//       iteration k-1 (NaN, convergence, r.z breakdown, iteration limit); if
+//       none fires, beta_k = rho_{k-1} / rho_{k-2}, and the workgroup computes
+//       p_k = D^-1 r + beta_k p_{k-1} while gathering it, w = A p_k and its
+//       share of delta_k = p_k . w.
+//   update U_k:  every workgroup reduces the delta partials of P_k, stops on
+//       delta <= 0, else alpha_k = rho_{k-1} / delta_k; x += alpha p,
+//       r -= alpha w, z = D^-1 r (not stored) and its shares of z.r, ||r||^2.
 //
-// A device word `flag` is raised on any terminal state; every kernel returns
-// immediately when it is set, so work enqueued past convergence is a no-op
-// and x is exactly the iterate at convergence.  This is the device-side
-// convergence check the paper proposes in Section 5.  p is double-buffered:
-// iteration k reads p[(k+1)%2] and writes p[k%2].
+// There is no atomic and no fence in any kernel: a reduction's first stage
+// writes one partial per workgroup, and the consuming kernel (which starts
+// after the producer has finished) re-adds them in a fixed order in every
+// workgroup, so all workgroups reach bit-identical scalars and identical
+// decisions.  On CDNA each agent-scope release of a workgroup writes back its
+// XCD's L2, which made a last-workgroup-finishes reduction cost several times
+// the kernel's own streaming time; the kernel boundary does that once.
+//
+// Scalars live in a device SolveState.  A kernel never writes a field its own
+// workgroups read: product P_k reads record rec[(k-1)&1] and writes rec[k&1];
+// the stop flag is monotonic (0 -> 1) and every workgroup that could observe
+// either value takes the same decision.  Once the flag is set every later
+// kernel returns at once, so work queued after convergence is a no-op and x is
+// exactly the converged iterate (the device-side convergence check the paper
+// leaves for future work in Section 5).  p is double-buffered: iteration k
+// reads p[(k+1)&1] and writes p[k&1], so a K-iteration graph with K even can
+// be replayed.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -29,36 +41,66 @@
 
 namespace apcg {
 
+struct PcgRecord {  // written by P_k into rec[k & 1]
+    double rho;     // rho_{k-1} = z_{k-1} . r_{k-1}
+    double beta;    // beta_k
+    double res;     // stopping norm after iteration k-1
+    int32_t k;
+    int32_t pad;
+};
+
 struct SolveState {
-    double rho, delta, alpha, beta;
-    double res, ref, rtol, unused;
-    int32_t its, maxit, status, flag;
-    int32_t zero_x, pad0, pad1, pad2;
+    PcgRecord rec[2];
+    double ref, rtol;     // reference norm, relative tolerance (set by init)
+    int32_t maxit, zero_x;
+    double out_res;       // terminal results
+    int32_t out_its, out_status;
+    int32_t flag;         // 1 once a terminal state is reached
+    int32_t pad;
 };
 static_assert(sizeof(SolveState) <= 256, "solve state exceeds its allocation");
 
 namespace {
 
 constexpr int VB = 256;  // block size of the vector-shaped kernels
+// partials layout inside the context's buffer (slices of kMaxBlocks doubles)
+constexpr int kSliceResidual = 0;  // 4 slices: z.r, ||.||^2, reference^2, bad rows
+constexpr int kSliceDelta = 4;     // 1 slice: p.Ap
 
-// The direction entry p_j = z_j + beta p_j with z_j = d_j r_j; written once
+// The direction entry p_j = z_j + beta p_j with z_j = d_j r_j; one function
 // so the stored p and the gathered p agree bit for bit.
 __device__ __forceinline__ double pdir(double d, double r, double beta, double pold) {
     return fma(beta, pold, d * r);
 }
 
+// Tests applied after iteration m (oracle order: NaN, convergence, r.z
+// breakdown, iteration limit).  Returns the status bit or 0.
+__device__ __forceinline__ int iteration_status(double rho, double res, const SolveState *st, int m) {
+    if (!isfinite(res) || !isfinite(rho)) return APCG_SOLVE_NAN;
+    if (res <= st->rtol * st->ref) return APCG_SOLVE_CONVERGED;
+    if (!(rho > 0.0)) return APCG_SOLVE_BREAKDOWN_RZ;
+    if (m >= st->maxit) return APCG_SOLVE_MAXIT;
+    return 0;
+}
+
+__device__ __forceinline__ void terminate(SolveState *st, int its, int status, double res) {
+    st->out_its = its;
+    st->out_status = status;
+    st->out_res = res;
+    st->flag = 1;
+}
+
 // ----------------------------------------------------------------- setup
-// dinv = 1/diag(A) (or 1), r0 = b - A x0 (or b), p_old = 0 and the initial
-// reductions rho0 = z0.r0, reference norm^2, residual norm^2, bad rows.
+// dinv = 1/diag(A) (or 1), r0 = b - A x0 (or b), p_old = 0; partials of
+// z0.r0, residual norm^2, reference norm^2 and the count of bad diagonals.
 __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
                                                  const double *__restrict__ b, double *__restrict__ x,
                                                  double *__restrict__ r, double *__restrict__ dinv,
-                                                 double *__restrict__ pold, SolveState *st, double *partials,
-                                                 unsigned *counter, int64_t per_block, int x0_zero, int pc,
-                                                 int norm_pre, double rtol, int32_t maxit) {
+                                                 double *__restrict__ pold, double *partials, int64_t per_block,
+                                                 int x0_zero, int pc, int norm_pre) {
     const dev::Chunk c = dev::block_chunk(n, per_block);
-    double rz = 0.0, nref = 0.0, nres = 0.0, bad = 0.0;
+    double rz = 0.0, nres = 0.0, nref = 0.0, bad = 0.0;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += VB) {
         const int s = rowptr[i], e = rowptr[i + 1];
         double diag = 0.0, ax = 0.0;
@@ -83,6 +125,7 @@ __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__res
         r[i] = ri;
         dinv[i] = di;
         pold[i] = 0.0;
+        if (x0_zero) x[i] = 0.0;  // x is not read when x0 is taken as zero
         const double zi = di * ri;
         rz = fma(zi, ri, rz);
         if (norm_pre) {
@@ -94,35 +137,37 @@ __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__res
             nres = fma(ri, ri, nres);
         }
     }
-    if (x0_zero) {
-        // x0 is taken as zero (never read above) and written as zero here
-        for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += VB) x[i] = 0.0;
-    }
-    double v[4] = {rz, nref, nres, bad};
-    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-    if (dev::reduce_last_block<VB, 4>(v, partials, gridDim.x, lb, counter) && threadIdx.x == 0) {
-        const double rho = v[0], ref = sqrt(v[1]), res = sqrt(v[2]);
-        int status = 0, zero_x = 0;
-        if (v[3] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
-        else if (ref == 0.0) {
-            status = APCG_SOLVE_CONVERGED;  // b = 0: the solution is x = 0
-            zero_x = 1;
-        } else if (!isfinite(res) || !isfinite(ref)) status = APCG_SOLVE_NAN;
-        else if (res <= rtol * ref) status = APCG_SOLVE_CONVERGED;
-        else if (!(rho > 0.0)) status = isfinite(rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
-        st->rho = rho;
-        st->delta = 0.0;
-        st->alpha = 0.0;
-        st->beta = 0.0;
-        st->res = zero_x ? 0.0 : res;
-        st->ref = ref;
-        st->rtol = rtol;
-        st->its = 0;
-        st->maxit = maxit;
-        st->status = status;
-        st->flag = status != 0;
-        st->zero_x = zero_x;
-    }
+    double v[4] = {rz, nres, nref, bad};
+    dev::store_partials<VB, 4>(v, partials, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+// One workgroup: reference norm, initial tests, record 0.
+__global__ __launch_bounds__(64) void k_pcg_init_final(SolveState *st, const double *partials, int G, double rtol,
+                                                       int32_t maxit) {
+    double v[4];
+    dev::reduce_partials<64, 4>(partials, G, v);
+    if (threadIdx.x != 0) return;
+    const double rho = v[0], res = sqrt(v[1]), ref = sqrt(v[2]);
+    st->ref = ref;
+    st->rtol = rtol;
+    st->maxit = maxit;
+    st->zero_x = 0;
+    st->flag = 0;
+    st->out_its = 0;
+    st->out_status = 0;
+    st->out_res = res;
+    st->rec[0] = PcgRecord{rho, 0.0, res, 0, 0};
+    st->rec[1] = PcgRecord{0.0, 0.0, 0.0, -1, 0};
+    int status = 0;
+    if (v[3] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
+    else if (ref == 0.0) {
+        status = APCG_SOLVE_CONVERGED;  // b = 0: the solution is x = 0
+        st->zero_x = 1;
+    } else if (!isfinite(res) || !isfinite(ref)) status = APCG_SOLVE_NAN;
+    else if (res <= rtol * ref) status = APCG_SOLVE_CONVERGED;
+    else if (!(rho > 0.0)) status = isfinite(rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
+    else if (maxit <= 0) status = APCG_SOLVE_MAXIT;
+    if (status) terminate(st, 0, status, st->zero_x ? 0.0 : res);
 }
 
 // x0 was given and b turned out to be zero: x = 0.
@@ -134,15 +179,52 @@ __global__ __launch_bounds__(VB) void k_pcg_zero_x_if(double *__restrict__ x, in
 }
 
 // ----------------------------------------------------------------- product
+// Scalar step at the start of product P_k, identical in every workgroup:
+// tests of iteration k-1 and beta_k.  Returns false when the solve has
+// stopped (the caller returns).  tune != 0: autotuner timing only (the
+// reduction runs, its result is unused, beta = 0.5, no state is written).
+template <int TB>
+__device__ __forceinline__ bool product_prologue(SolveState *st, const double *part_res, int g_res, int parity,
+                                                 int tune, double *beta_out) {
+    if (tune) {
+        double v[2];
+        dev::reduce_partials<TB, 2>(part_res, g_res, v);
+        *beta_out = v[0] == 12345.678 ? 0.25 : 0.5;  // keeps the timed reduction alive
+        return true;
+    }
+    if (st->flag) return false;
+    const PcgRecord prev = st->rec[parity ^ 1];
+    const int k = prev.k + 1;
+    double rho = prev.rho, res = prev.res, beta = 0.0;
+    if (k > 1) {
+        double v[2];
+        dev::reduce_partials<TB, 2>(part_res, g_res, v);
+        rho = v[0];
+        res = sqrt(v[1]);
+        const int status = iteration_status(rho, res, st, k - 1);
+        if (status) {
+            if (blockIdx.x == 0 && threadIdx.x == 0) terminate(st, k - 1, status, res);
+            return false;
+        }
+        beta = rho / prev.rho;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) st->rec[parity] = PcgRecord{rho, beta, res, k, 0};
+    *beta_out = beta;
+    return true;
+}
+
+// parity = k & 1.  tune != 0 (autotuner only): no tests, beta = 0.5, no state
+// written, the kernel always runs.
 template <int LPR, int TB>
 __global__ __launch_bounds__(TB) void k_pcg_product(int32_t n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
                                                     const double *__restrict__ dinv, const double *__restrict__ r,
                                                     const double *__restrict__ pold, double *__restrict__ pnew,
-                                                    double *__restrict__ w, SolveState *st, double *partials,
-                                                    unsigned *counter, int32_t rows_per_block, int respect_flag) {
-    if (respect_flag && st->flag) return;
-    const double beta = st->beta;
+                                                    double *__restrict__ w, SolveState *st, const double *part_res,
+                                                    int g_res, double *part_delta, int32_t rows_per_block,
+                                                    int parity, int tune, int32_t /*lds_nnz: staged only*/) {
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
     constexpr int RPP = TB / LPR;
     const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
     const int row0 = lb * rows_per_block;
@@ -169,26 +251,143 @@ __global__ __launch_bounds__(TB) void k_pcg_product(int32_t n, const int32_t *__
         }
     }
     double v[1] = {acc};
-    if (dev::reduce_last_block<TB, 1>(v, partials, gridDim.x, lb, counter) && threadIdx.x == 0) {
-        const double delta = v[0];
-        st->delta = delta;
-        if (!(delta > 0.0)) {
-            st->status |= isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN;
-            st->flag = 1;
-        } else {
-            st->alpha = st->rho / delta;
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
+}
+
+
+// Row sum of A p for one row whose nonzeros are staged in LDS at [s, e).
+// Rows of at most 8 entries issue all gathers before the first multiply-add
+// (the padded slots gather the row's own entry and are not added); longer
+// rows take the plain loop.  Both paths add in column-storage order, so the
+// result does not depend on which one ran.
+__device__ __forceinline__ double staged_row_product(const double *sv, const int32_t *sc, int s, int e, int row,
+                                                     const double *__restrict__ dinv, const double *__restrict__ r,
+                                                     const double *__restrict__ pold, double beta) {
+    const int len = e - s;
+    double sum = 0.0;
+    if (len <= 8) {
+        int jj[8];
+        double aa[8], pj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool in = q < len;
+            jj[q] = in ? sc[s + q] : row;
+            aa[q] = in ? sv[s + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pj[q] = pdir(dinv[jj[q]], r[jj[q]], beta, pold[jj[q]]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < len) sum = fma(aa[q], pj[q], sum);
+    } else {
+        for (int k = s; k < e; ++k) {
+            const int j = sc[k];
+            sum = fma(sv[k], pdir(dinv[j], r[j], beta, pold[j]), sum);
         }
     }
+    return sum;
+}
+
+// Staged schedule: each workgroup walks its contiguous run of TB-row chunks;
+// per chunk the nonzeros are moved to LDS with coalesced (non-temporal)
+// loads, then thread t reduces row t of the chunk.  With one row per thread,
+// neighbouring lanes gather neighbouring entries of p, dinv and r, which
+// coalesces for banded/stencil matrices.  The chunk loop is software
+// pipelined: the next chunk's nonzeros are loaded into registers (PF per
+// thread) while the current chunk is reduced, so staging does not serialise
+// with the gathers.  lds_nnz (>= the largest chunk) sizes the LDS stage and
+// PF * TB >= lds_nnz.
+template <int TB, int PF>
+__global__ __launch_bounds__(TB) void k_pcg_product_stream(int32_t n, const int32_t *__restrict__ rowptr,
+                                                           const int32_t *__restrict__ col,
+                                                           const double *__restrict__ val,
+                                                           const double *__restrict__ dinv,
+                                                           const double *__restrict__ r,
+                                                           const double *__restrict__ pold, double *__restrict__ pnew,
+                                                           double *__restrict__ w, SolveState *st,
+                                                           const double *part_res, int g_res, double *part_delta,
+                                                           int32_t chunks_per_block, int parity, int tune,
+                                                           int32_t lds_nnz) {
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    extern __shared__ double stage[];
+    double *sv = stage;
+    int32_t *sc = reinterpret_cast<int32_t *>(stage + lds_nnz);
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int nchunks = (n + TB - 1) / TB;
+    const int c0 = lb * chunks_per_block;
+    const int c1 = min(nchunks, c0 + chunks_per_block);
+    double pv[PF];
+    int32_t pc[PF];
+    int pk0 = 0, pcount = 0;
+    auto prefetch = [&](int c) {
+        const int row0 = c * TB;
+        const int row1 = min(n, row0 + TB);
+        pk0 = rowptr[row0];
+        pcount = rowptr[row1] - pk0;
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = q * TB + threadIdx.x;
+            if (k < pcount) {
+                pv[q] = __builtin_nontemporal_load(val + pk0 + k);
+                pc[q] = __builtin_nontemporal_load(col + pk0 + k);
+            }
+        }
+    };
+    if (c0 < c1) prefetch(c0);
+    double acc = 0.0;
+    for (int c = c0; c < c1; ++c) {
+        const int row0 = c * TB;
+        const int row1 = min(n, row0 + TB);
+        const int k0 = pk0;
+        __syncthreads();  // the previous chunk's LDS reads are done
+#pragma unroll
+        for (int q = 0; q < PF; ++q) {
+            const int k = q * TB + threadIdx.x;
+            if (k < pcount) {
+                sv[k] = pv[q];
+                sc[k] = pc[q];
+            }
+        }
+        __syncthreads();
+        if (c + 1 < c1) prefetch(c + 1);  // in flight during the gathers below
+        const int row = row0 + threadIdx.x;
+        if (row < row1) {
+            const double sum =
+                staged_row_product(sv, sc, rowptr[row] - k0, rowptr[row + 1] - k0, row, dinv, r, pold, beta);
+            const double pi = pdir(dinv[row], r[row], beta, pold[row]);
+            pnew[row] = pi;
+            w[row] = sum;
+            acc = fma(pi, sum, acc);
+        }
+    }
+    double v[1] = {acc};
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
 }
 
 // ----------------------------------------------------------------- update
 __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                    const double *__restrict__ p, const double *__restrict__ w,
                                                    const double *__restrict__ dinv, SolveState *st,
-                                                   double *partials, unsigned *counter, int64_t per_block,
-                                                   int norm_pre) {
-    if (st->flag) return;
-    const double alpha = st->alpha;
+                                                   const double *part_delta, int g_delta, double *part_res,
+                                                   int64_t per_block, int parity, int norm_pre, int tune) {
+    double alpha = 0.0;
+    double d[1];
+    if (tune) {
+        dev::reduce_partials<VB, 1>(part_delta, g_delta, d);  // timed like the real kernel
+        if (d[0] == 12345.678) alpha = 1e-300;
+    } else {
+        if (st->flag) return;
+        const PcgRecord rec = st->rec[parity];
+        dev::reduce_partials<VB, 1>(part_delta, g_delta, d);
+        const double delta = d[0];
+        if (!(delta > 0.0)) {
+            if (blockIdx.x == 0 && threadIdx.x == 0)
+                terminate(st, rec.k - 1, isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN, rec.res);
+            return;
+        }
+        alpha = rec.rho / delta;
+    }
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double rz = 0.0, nn = 0.0;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += VB) {
@@ -201,47 +400,32 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
         nn = norm_pre ? fma(zi, zi, nn) : fma(ri, ri, nn);
     }
     double v[2] = {rz, nn};
-    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-    if (dev::reduce_last_block<VB, 2>(v, partials, gridDim.x, lb, counter) && threadIdx.x == 0) {
-        const double rho_new = v[0];
-        const double res = sqrt(v[1]);
-        const int its = st->its + 1;
-        st->its = its;
-        st->res = res;
-        int status = 0;
-        if (!isfinite(res) || !isfinite(rho_new)) status = APCG_SOLVE_NAN;
-        else if (res <= st->rtol * st->ref) status = APCG_SOLVE_CONVERGED;
-        else if (!(rho_new > 0.0)) status = APCG_SOLVE_BREAKDOWN_RZ;
-        else if (its >= st->maxit) status = APCG_SOLVE_MAXIT;
-        if (status) {
-            st->status |= status;
-            st->flag = 1;
-        } else {
-            st->beta = rho_new / st->rho;
-            st->rho = rho_new;
+    dev::store_partials<VB, 2>(v, part_res, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Applies the tests of the last launched iteration when no later product
+// kernel did, then copies the terminal state into the caller's info record.
+__global__ __launch_bounds__(64) void k_pcg_finish(SolveState *st, const double *part_res, int g_res,
+                                                   apcg_solve_info *out) {
+    if (!st->flag) {
+        const int q = st->rec[1].k > st->rec[0].k ? 1 : 0;
+        const PcgRecord last = st->rec[q];
+        double v[2];
+        dev::reduce_partials<64, 2>(part_res, g_res, v);
+        if (threadIdx.x == 0) {
+            const double res = sqrt(v[1]);
+            int status = iteration_status(v[0], res, st, last.k);
+            if (!status) status = APCG_SOLVE_MAXIT;  // the host stopped at maxit
+            terminate(st, last.k, status, res);
         }
     }
-}
-
-// Copies the terminal state into the caller's info record.
-__global__ void k_pcg_finish(SolveState *st, apcg_solve_info *out) {
     if (threadIdx.x != 0) return;
-    int status = st->status;
-    if (status == 0) status = APCG_SOLVE_MAXIT;  // maxit reached before any test fired
-    out->iterations = st->its;
-    out->status = status;
+    out->iterations = st->out_its;
+    out->status = st->out_status;
     out->fcg_iterations = 0;
     out->reserved = 0;
-    out->res_norm = st->res;
+    out->res_norm = st->out_res;
     out->ref_norm = st->ref;
-}
-
-__global__ void k_tune_state(SolveState *st) {
-    if (threadIdx.x != 0) return;
-    st->flag = 0;
-    st->beta = 0.5;
-    st->rho = 1.0;
-    st->status = 0;
 }
 
 __global__ __launch_bounds__(VB) void k_tune_fill(double *r, double *dinv, double *p, int64_t n) {
@@ -253,8 +437,8 @@ __global__ __launch_bounds__(VB) void k_tune_fill(double *r, double *dinv, doubl
 }
 
 using ProductFn = void (*)(int32_t, const int32_t *, const int32_t *, const double *, const double *,
-                           const double *, const double *, double *, double *, SolveState *, double *, unsigned *,
-                           int32_t, int);
+                           const double *, const double *, double *, double *, SolveState *, const double *, int,
+                           double *, int32_t, int, int, int32_t);
 
 template <int TB>
 ProductFn product_fn_tb(int lpr) {
@@ -270,7 +454,25 @@ ProductFn product_fn_tb(int lpr) {
     }
 }
 
-ProductFn product_fn(int lpr, int tb) { return tb == 512 ? product_fn_tb<512>(lpr) : product_fn_tb<256>(lpr); }
+// Staged kernels by the prefetch depth PF (nonzeros per thread): the
+// smallest PF with PF * TB >= lds_nnz keeps the register count low.
+template <int TB>
+ProductFn stream_fn(int32_t lds_nnz) {
+    const int need = (lds_nnz + TB - 1) / TB;
+    if (need <= 4) return k_pcg_product_stream<TB, 4>;
+    if (need <= 8) return k_pcg_product_stream<TB, 8>;
+    if (need <= 12) return k_pcg_product_stream<TB, 12>;
+    if (TB == 512 || need <= 16) return k_pcg_product_stream<TB, (TB == 512 ? 11 : 16)>;
+    return k_pcg_product_stream<TB, 21>;  // 21 * 256 >= kStreamMaxNnz
+}
+
+ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz) {
+    if (cfg.schedule == APCG_SPMV_STREAM) {
+        if (cfg.block_size == 512) return stream_fn<512>(lds_nnz);
+        return stream_fn<256>(lds_nnz);
+    }
+    return cfg.block_size == 512 ? product_fn_tb<512>(cfg.lanes_per_row) : product_fn_tb<256>(cfg.lanes_per_row);
+}
 
 // Launch geometry of one solve.
 struct Plan {
@@ -278,21 +480,46 @@ struct Plan {
     ProductFn prod;
     int tb;
     int g_prod;
-    int32_t rpb;
+    int32_t rpb;  // rows per workgroup (row groups) or chunks per workgroup (staged)
     int g_vec;
     int64_t pb_vec;
+    int32_t lds_nnz;     // staged schedule: LDS entries per workgroup
+    size_t lds_bytes;
 };
+
+// Vector-shaped kernels: at most 1024 workgroups of VB threads, chunks a
+// multiple of 64 entries; few workgroups keep the partials every consumer
+// workgroup re-adds short.
+void vector_grid(int64_t n, int *G, int64_t *per_block) {
+    const int64_t units = (n + 63) / 64;
+    *G = normalise_blocks(1024, units);
+    int64_t pb = (n + *G - 1) / *G;
+    *per_block = std::max<int64_t>(64, ((pb + 63) / 64) * 64);
+}
 
 apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl) {
     pl->n = A->n;
     pl->tb = cfg.block_size == 512 ? 512 : 256;
-    pl->prod = product_fn(cfg.lanes_per_row, pl->tb);
+    if (cfg.schedule == APCG_SPMV_STREAM && !stream_fits(A, pl->tb))
+        return set_error(APCG_ERR_UNSUPPORTED, "rows too long for the staged schedule");
+    pl->lds_nnz = 0;
+    pl->lds_bytes = 0;
+    if (cfg.schedule == APCG_SPMV_STREAM) {
+        const int64_t most = A->max_block_nnz[pl->tb == 512 ? 1 : 0];
+        pl->lds_nnz = (int32_t)std::max<int64_t>(2, ((most + 1) / 2) * 2);  // keeps the int32 stage 8-byte aligned
+        pl->lds_bytes = (size_t)pl->lds_nnz * (sizeof(double) + sizeof(int32_t));
+        const int64_t nchunks = ((int64_t)A->n + pl->tb - 1) / pl->tb;
+        pl->g_prod = normalise_blocks(cfg.blocks, nchunks);
+        pl->rpb = (int32_t)std::max<int64_t>(1, (nchunks + pl->g_prod - 1) / pl->g_prod);
+    } else {
+        const int64_t rpp = pl->tb / cfg.lanes_per_row;
+        pl->g_prod = normalise_blocks(cfg.blocks, (A->n + rpp - 1) / rpp);
+        int64_t rpb = ((int64_t)A->n + pl->g_prod - 1) / pl->g_prod;
+        pl->rpb = (int32_t)std::max<int64_t>(1, rpb);
+    }
+    pl->prod = product_fn(cfg, pl->lds_nnz);
     if (!pl->prod) return set_error(APCG_ERR_INVALID_ARG, "unsupported lanes_per_row");
-    const int64_t rpp = pl->tb / cfg.lanes_per_row;
-    pl->g_prod = normalise_blocks(cfg.blocks, (A->n + rpp - 1) / rpp);
-    int64_t rpb = ((int64_t)A->n + pl->g_prod - 1) / pl->g_prod;
-    pl->rpb = (int32_t)std::max<int64_t>(1, rpb);
-    elementwise_grid(A->n, &pl->g_vec, &pl->pb_vec);
+    vector_grid(A->n, &pl->g_vec, &pl->pb_vec);
     return APCG_SUCCESS;
 }
 
@@ -302,31 +529,35 @@ struct Bufs {
     const double *b;
     Workspace ws;
     double *partials;
-    unsigned *counters;
+    double *part_res() const { return partials + (size_t)kSliceResidual * kMaxBlocks; }
+    double *part_delta() const { return partials + (size_t)kSliceDelta * kMaxBlocks; }
 };
 
-apcg_status launch_product(hipStream_t s, const Plan &pl, const Bufs &bf, int iter, int respect_flag = 1) {
+apcg_status launch_product(hipStream_t s, const Plan &pl, const Bufs &bf, int iter, int tune = 0) {
     const double *pold = bf.ws.p((iter + 1) & 1);
     double *pnew = bf.ws.p(iter & 1);
-    hipLaunchKernelGGL(pl.prod, dim3(pl.g_prod), dim3(pl.tb), 0, s, pl.n, bf.A->rowptr, bf.A->col, bf.A->val,
-                       (const double *)bf.ws.dinv(), (const double *)bf.ws.r(), pold, pnew, bf.ws.w(), bf.ws.state,
-                       bf.partials, bf.counters + CNT_PCG_PRODUCT, pl.rpb, respect_flag);
+    hipLaunchKernelGGL(pl.prod, dim3(pl.g_prod), dim3(pl.tb), pl.lds_bytes, s, pl.n, bf.A->rowptr, bf.A->col,
+                       bf.A->val, (const double *)bf.ws.dinv(), (const double *)bf.ws.r(), pold, pnew, bf.ws.w(),
+                       bf.ws.state, (const double *)bf.part_res(), pl.g_vec, bf.part_delta(), pl.rpb, iter & 1, tune,
+                       pl.lds_nnz);
     APCG_CHECK_LAUNCH("k_pcg_product");
     return APCG_SUCCESS;
 }
 
-apcg_status launch_update(hipStream_t s, const Plan &pl, const Bufs &bf, int iter, int norm_pre) {
+apcg_status launch_update(hipStream_t s, const Plan &pl, const Bufs &bf, int iter, int norm_pre, int tune = 0) {
     const double *p = bf.ws.p(iter & 1);
     hipLaunchKernelGGL(k_pcg_update, dim3(pl.g_vec), dim3(VB), 0, s, (int64_t)pl.n, bf.x, bf.ws.r(), p,
-                       (const double *)bf.ws.w(), (const double *)bf.ws.dinv(), bf.ws.state, bf.partials,
-                       bf.counters + CNT_PCG_UPDATE, pl.pb_vec, norm_pre);
+                       (const double *)bf.ws.w(), (const double *)bf.ws.dinv(), bf.ws.state,
+                       (const double *)bf.part_delta(), pl.g_prod, bf.part_res(), pl.pb_vec, iter & 1, norm_pre,
+                       tune);
     APCG_CHECK_LAUNCH("k_pcg_update");
     return APCG_SUCCESS;
 }
 
 apcg_status get_graph(apcg_ctx c, const Plan &pl, const Bufs &bf, int K, int pc, int norm_pre,
                       hipGraphExec_t *exec) {
-    GraphKey key{bf.A, bf.x, bf.ws.base, K, bf.A->cfg.lanes_per_row, pl.tb, pl.g_prod, pc, norm_pre};
+    GraphKey key{bf.A, bf.x, bf.ws.base, K, bf.A->cfg.lanes_per_row + 1000 * bf.A->cfg.schedule, pl.tb, pl.g_prod,
+                 pc, norm_pre};
     for (auto &g : c->graphs)
         if (g.key == key) {
             *exec = g.exec;
@@ -386,7 +617,6 @@ apcg_status queue_poll(apcg_ctx c, const Bufs &bf, int slot) {
 // Waits for poll point `slot` (queued `lookahead` periods ago) and reports
 // whether the device had already stopped.
 apcg_status check_poll(apcg_ctx c, int slot, bool *done) {
-    g_counters.host_polls++;
     APCG_HIP(hipEventSynchronize(c->poll_ev[slot]->e));
     *done = c->pinned_flags[slot] != 0;
     return APCG_SUCCESS;
@@ -469,15 +699,17 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
         if ((s = ensure_workspace(c, A->n))) return s;
         Plan pl;
         if ((s = make_plan(A, A->cfg, &pl))) return s;
-        Bufs bf{A, x->d, b->d, c->ws, c->partials, c->counters};
+        Bufs bf{A, x->d, b->d, c->ws, c->partials};
         const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
         hipStream_t st = c->stream;
 
         hipLaunchKernelGGL(k_pcg_init, dim3(pl.g_vec), dim3(VB), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d,
-                           c->ws.r(), c->ws.dinv(), c->ws.p(0), c->ws.state, c->partials,
-                           c->counters + CNT_PCG_INIT, pl.pb_vec, opts.x0_is_zero ? 1 : 0, opts.pc, norm_pre, rtol,
-                           maxit);
+                           c->ws.r(), c->ws.dinv(), c->ws.p(0), bf.part_res(), pl.pb_vec, opts.x0_is_zero ? 1 : 0,
+                           opts.pc, norm_pre);
         APCG_CHECK_LAUNCH("k_pcg_init");
+        hipLaunchKernelGGL(k_pcg_init_final, dim3(1), dim3(64), 0, st, c->ws.state, (const double *)bf.part_res(),
+                           pl.g_vec, rtol, maxit);
+        APCG_CHECK_LAUNCH("k_pcg_init_final");
         if (!opts.x0_is_zero) {
             hipLaunchKernelGGL(k_pcg_zero_x_if, dim3(pl.g_vec), dim3(VB), 0, st, x->d, (int64_t)A->n, pl.pb_vec,
                                (const SolveState *)c->ws.state);
@@ -500,6 +732,7 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
                     if ((s = queue_poll(c, bf, (int)(g % L)))) return s;
                     if (g >= L - 1) {
                         bool done = false;
+                        g_counters.host_polls++;
                         if ((s = check_poll(c, (int)((g - (L - 1)) % L), &done))) return s;
                         if (done) break;
                     }
@@ -519,6 +752,7 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
                         if ((s = queue_poll(c, bf, (int)(period % L)))) return s;
                         if (period >= L - 1) {
                             bool done = false;
+                            g_counters.host_polls++;
                             if ((s = check_poll(c, (int)((period - (L - 1)) % L), &done))) return s;
                             if (done) break;
                         }
@@ -532,18 +766,17 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
                     if ((s = queue_poll(c, bf, 0))) return s;
                     g_counters.host_syncs++;
                     if ((s = check_poll(c, 0, &done))) return s;
-                    g_counters.host_polls--;
                     if (done) break;
                     if ((s = launch_update(st, pl, bf, k, norm_pre))) return s;
                     if ((s = queue_poll(c, bf, 0))) return s;
                     g_counters.host_syncs++;
                     if ((s = check_poll(c, 0, &done))) return s;
-                    g_counters.host_polls--;
                     if (done) break;
                 }
             }
         }
-        hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(64), 0, st, c->ws.state, info->d + info_index);
+        hipLaunchKernelGGL(k_pcg_finish, dim3(1), dim3(64), 0, st, c->ws.state, (const double *)bf.part_res(),
+                           pl.g_vec, info->d + info_index);
         APCG_CHECK_LAUNCH("k_pcg_finish");
         if (opts.kernel_timing) {
             c->tdone = event_get(c->device);
@@ -569,7 +802,7 @@ apcg_status apcg_ctx_kernel_times(apcg_ctx ctx, int32_t kind, double *mean_us, i
     double total = 0.0;
     int32_t n = 0;
     for (int i = 0; i < ctx->tpairs; ++i) {
-        if (ctx->tkind[2 * i] != kind || ctx->tkind[2 * i + 1] > hs.its) continue;
+        if (ctx->tkind[2 * i] != kind || ctx->tkind[2 * i + 1] > hs.out_its) continue;
         float ms = 0.f;
         APCG_HIP(hipEventElapsedTime(&ms, ctx->tev[2 * i], ctx->tev[2 * i + 1]));
         total += ms;
@@ -594,28 +827,36 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         const int64_t n = A->n;
         hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(VB), 0, st, ctx->ws.r(), ctx->ws.dinv(), ctx->ws.p(0), n);
         APCG_CHECK_LAUNCH("k_tune_fill");
-        hipLaunchKernelGGL(k_tune_state, dim3(1), dim3(64), 0, st, ctx->ws.state);
-        APCG_CHECK_LAUNCH("k_tune_state");
-        Bufs bf{A, nullptr, nullptr, ctx->ws, ctx->partials, ctx->counters};
+        double *xs = nullptr;  // stand-in for x: the tuned update writes it
+        APCG_HIP(hipMalloc((void **)&xs, sizeof(double) * std::max<int64_t>(n, 1)));
+        APCG_HIP(hipMemsetAsync(xs, 0, sizeof(double) * std::max<int64_t>(n, 1), st));
+        Bufs bf{A, xs, nullptr, ctx->ws, ctx->partials};
         const double per_row = n > 0 ? (double)A->nnz / n : 1.0;
         hipEvent_t e0, e1;
         APCG_HIP(hipEventCreate(&e0));
         APCG_HIP(hipEventCreate(&e1));
         double best_t = 1e300;
         apcg_spmv_config best_cfg = A->cfg;
-        for (int lpr : {1, 2, 4, 8, 16, 32, 64}) {
+        for (int lpr : {0, 1, 2, 4, 8, 16, 32, 64}) {  // 0: the staged schedule
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
             for (int tb : {256, 512}) {
-                for (int blocks : {1024, 2048, 4096, 8192}) {
-                    apcg_spmv_config cfg{lpr, tb, blocks, 0};
+                if (lpr == 0 && !stream_fits(A, tb)) continue;
+                for (int blocks : {256, 512, 1024, 2048, 4096, 8192}) {
+                    apcg_spmv_config cfg = lpr == 0 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_STREAM}
+                                                    : apcg_spmv_config{lpr, tb, blocks, APCG_SPMV_ROWGROUP};
                     Plan pl;
                     if ((s = make_plan(A, cfg, &pl))) return s;
-                    if (pl.g_prod < blocks && blocks > 1024) continue;  // same grid as a smaller candidate
-                    for (int w = 0; w < 2; ++w)
-                        if ((s = launch_product(st, pl, bf, 1, 0))) return s;
+                    if (pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller candidate
+                    // one product + update pair, both with their partial reductions
+                    for (int w = 0; w < 2; ++w) {
+                        if ((s = launch_product(st, pl, bf, 1, 1))) return s;
+                        if ((s = launch_update(st, pl, bf, 1, 0, 1))) return s;
+                    }
                     APCG_HIP(hipEventRecord(e0, st));
-                    for (int r = 0; r < reps; ++r)
-                        if ((s = launch_product(st, pl, bf, 1, 0))) return s;
+                    for (int r = 0; r < reps; ++r) {
+                        if ((s = launch_product(st, pl, bf, 1, 1))) return s;
+                        if ((s = launch_update(st, pl, bf, 1, 0, 1))) return s;
+                    }
                     APCG_HIP(hipEventRecord(e1, st));
                     g_counters.host_syncs++;
                     APCG_HIP(hipEventSynchronize(e1));
@@ -631,6 +872,7 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
+        hipFree(xs);  // the stream is idle here (synchronised on the last timing event)
         A->cfg = best_cfg;
         if (best) *best = best_cfg;
         if (best_us) *best_us = best_t;

@@ -141,9 +141,7 @@ static apcg_status ctx_init(apcg_ctx c, int32_t device, int32_t type) {
     c->type = type;
     APCG_HIP(hipSetDevice(device));
     APCG_HIP(hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking));
-    APCG_HIP(hipMalloc((void **)&c->partials, sizeof(double) * 4 * kMaxBlocks));
-    APCG_HIP(hipMalloc((void **)&c->counters, sizeof(unsigned) * kNumCounters));
-    APCG_HIP(hipMemsetAsync(c->counters, 0, sizeof(unsigned) * kNumCounters, c->stream));
+    APCG_HIP(hipMalloc((void **)&c->partials, sizeof(double) * kPartialSlots * kMaxBlocks));
     APCG_HIP(hipHostMalloc((void **)&c->pinned_flags, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
     for (int i = 0; i < kMaxLookahead; ++i) c->pinned_flags[i] = 0;
     return APCG_SUCCESS;
@@ -159,7 +157,6 @@ static void ctx_release_now(apcg_ctx c) {
     if (c->ws.base) hipFree(c->ws.base);
     if (c->ws.state) hipFree(c->ws.state);
     if (c->partials) hipFree(c->partials);
-    if (c->counters) hipFree(c->counters);
     if (c->pinned_flags) hipHostFree(c->pinned_flags);
     if (c->stream) hipStreamDestroy(c->stream);
     delete c;
@@ -305,13 +302,11 @@ int32_t normalise_blocks(int32_t blocks, int64_t units) {
 void spmv_default_config(int32_t n, int64_t nnz, apcg_spmv_config *cfg) {
     double per_row = n > 0 ? (double)nnz / n : 0.0;
     int lpr = 1;
-    while (lpr < 64 && lpr * 2 <= per_row) lpr *= 2;  // about two entries per lane
-    lpr = std::max(1, lpr / 1);
-    if (per_row >= 5 && per_row < 12) lpr = 8;
+    while (lpr < 64 && lpr * 4 <= per_row) lpr *= 2;  // about four entries per lane
     cfg->lanes_per_row = lpr;
     cfg->block_size = 256;
-    cfg->blocks = 2048;
-    cfg->reserved = 0;
+    cfg->blocks = 1024;
+    cfg->schedule = APCG_SPMV_ROWGROUP;
 }
 
 }  // namespace apcg
@@ -690,7 +685,7 @@ apcg_status apcg_vec_dot_async(apcg_vec x, apcg_vec y, apcg_scalar out, apcg_ctx
     Acc acc[3] = {{&out->rec, ACC_W}, {&x->rec, ACC_R}, {&y->rec, ACC_R}};
     int na = (x == y) ? 2 : 3;
     if ((s = op_begin(c, acc, na))) return s;
-    if ((s = launch_dot(c->stream, x->d, y->d, x->n, out->d, 0, c->partials, c->counters + CNT_DOT))) return s;
+    if ((s = launch_dot(c->stream, x->d, y->d, x->n, out->d, 0, c->partials))) return s;
     return op_end(c, acc, na);
     API_END();
 }
@@ -704,7 +699,7 @@ apcg_status apcg_vec_norm2_async(apcg_vec x, apcg_scalar out, apcg_ctx ctx) {
     if (s) return s;
     Acc acc[2] = {{&out->rec, ACC_W}, {&x->rec, ACC_R}};
     if ((s = op_begin(c, acc, 2))) return s;
-    if ((s = launch_dot(c->stream, x->d, x->d, x->n, out->d, 1, c->partials, c->counters + CNT_DOT))) return s;
+    if ((s = launch_dot(c->stream, x->d, x->d, x->n, out->d, 1, c->partials))) return s;
     return op_end(c, acc, 2);
     API_END();
 }
@@ -848,7 +843,14 @@ apcg_status apcg_mat_wrap_csr(int32_t device, int32_t n, int64_t nnz, const int3
     A->rowptr = dev_rowptr;
     A->col = dev_col;
     A->val = dev_val;
+    for (int t = 0; t < 2; ++t) {
+        const int64_t rows = t == 0 ? 256 : 512;
+        int64_t mx = 0;
+        for (int64_t r0 = 0; r0 < n; r0 += rows) mx = std::max<int64_t>(mx, rp[std::min<int64_t>(n, r0 + rows)] - rp[r0]);
+        A->max_block_nnz[t] = mx;
+    }
     spmv_default_config(n, nnz, &A->cfg);
+    if (stream_fits(A, 256)) A->cfg = apcg_spmv_config{1, 256, 1024, APCG_SPMV_STREAM};
     *out = A;
     return APCG_SUCCESS;
     API_END();
@@ -872,15 +874,17 @@ apcg_status apcg_mat_destroy(apcg_mat A) {
 static bool valid_spmv_config(const apcg_spmv_config *cfg) {
     int l = cfg->lanes_per_row, b = cfg->block_size;
     bool lok = l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64;
-    bool bok = b == 64 || b == 128 || b == 256 || b == 512 || b == 1024;
-    return lok && bok && cfg->blocks >= 0;
+    bool bok = b == 256 || b == 512;
+    bool sok = cfg->schedule == APCG_SPMV_ROWGROUP || cfg->schedule == APCG_SPMV_STREAM;
+    return lok && bok && sok && cfg->blocks >= 0;
 }
 
 apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg) {
     if (!A || !cfg) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
-    if (!valid_spmv_config(cfg)) return set_error(APCG_ERR_INVALID_ARG, "invalid SpMV configuration");
-    if (cfg->block_size != 256 && cfg->block_size != 512)
-        return set_error(APCG_ERR_UNSUPPORTED, "block_size must be 256 or 512");
+    if (!valid_spmv_config(cfg))
+        return set_error(APCG_ERR_INVALID_ARG, "invalid SpMV configuration (block_size must be 256 or 512)");
+    if (cfg->schedule == APCG_SPMV_STREAM && !stream_fits(A, cfg->block_size))
+        return set_error(APCG_ERR_UNSUPPORTED, "rows too long for the staged schedule at this block size");
     A->cfg = *cfg;
     return APCG_SUCCESS;
 }

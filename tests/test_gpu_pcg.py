@@ -75,17 +75,19 @@ def test_poisson64_parity(apcg, ctx, mode, pc):
     assert res["ref_norm"] == pytest.approx(ref.ref, rel=1e-13)
 
 
-@pytest.mark.parametrize("lpr", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lpr", [0, 1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("tb", [256, 512])
 def test_spmv_schedules_same_solve(apcg, ctx, lpr, tb):
-    """Every SpMV schedule gives the oracle's iteration count on a ragged 3D
-    variable-coefficient system (n = 21 * 17 * 13, not a multiple of 64)."""
+    """Every SpMV schedule (lpr 0: the LDS-staged one) gives the oracle's
+    iteration count on a ragged 3D variable-coefficient system
+    (n = 21 * 17 * 13, not a multiple of 64)."""
     print(f"case schedule lpr={lpr} tb={tb}", flush=True)
     rng = np.random.default_rng(40)
     A = P.diffusion_csr(np.exp(rng.standard_normal((13, 17, 21))), aniso=7.0)
     b = rng.uniform(-1, 1, A.n)
     ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
-    res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=(lpr, tb, 0))
+    spmv = (1, tb, 0, 1) if lpr == 0 else (lpr, tb, 0, 0)
+    res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=spmv)
     assert res["status"] == apcg.APCG_SOLVE_CONVERGED
     assert abs(res["iterations"] - ref.its) <= 1
     assert rel(x, ref.x) <= 1e-9
