@@ -167,7 +167,10 @@ def main():
             tr = json.load(f)
         if tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n:
             traffic = tr.get("bytes_per_launch")
-    roofline = {"bound": "hbm", "kernel": "k_pcg_product", "achieved": round(achieved, 1),
+    cfg_now = apcg.apcg_mat_get_spmv_config(A.h)
+    kname = ("k_pcg_product_stream" if cfg_now["schedule"] == apcg.APCG_SPMV_STREAM else "k_pcg_product") + \
+        f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)"
+    roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": prod_bytes,
                 "mean_launch_us": round(prod_us, 3), "launches_timed": prod_cnt}

@@ -211,7 +211,12 @@ apcg_status op_begin(apcg_ctx c, const Acc *acc, int n) {
     for (int i = 0; i < n; ++i) {
         Record *r = acc[i].rec;
         if (!r) continue;
-        if (r->writer_ctx && r->writer_ctx != c->id) {
+        // a context that already read the object since its last write has
+        // already waited for that write
+        bool synced = false;
+        for (auto &rd : r->readers)
+            if (rd.first == c->id) synced = true;
+        if (r->writer_ctx && r->writer_ctx != c->id && !synced) {
             apcg_status s = wait(r->write_ev);
             if (s) return s;
         }

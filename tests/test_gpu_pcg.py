@@ -174,3 +174,32 @@ def test_repeated_solves_bitwise_identical(apcg, ctx):
     r3, x3 = gpu_solve(apcg, ctx, A, b, 1e-8, 5000, mode=2)
     assert r1 == r2 == r3
     assert np.array_equal(x1, x2) and np.array_equal(x1, x3)
+
+
+@pytest.fixture(scope="module")
+def diffusion128():
+    return P.diffusion3d_smoothed(128, 2)
+
+
+def test_full_size_diffusion128_parity(apcg, ctx, diffusion128):
+    """The 128^3 variable-coefficient system at its full size, in the launch
+    configuration the benchmark times (graph mode, autotuned schedule):
+    iterations +-1 and ||x - x_ref|| / ||x_ref|| <= 1e-9 at rtol 1e-10."""
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    s = diffusion128
+    print("case diffusion128 full size", flush=True)
+    dA, db, dx = DeviceCSR(s.A), DeviceVec(s.b), DeviceVec.zeros(s.A.n)
+    apcg.apcg_mat_autotune(dA.h, ctx, 3)
+    info = apcg.apcg_info_create(0, 1)
+    apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, 1e-10, 50000, apcg.apcg_solve_opts_default(x0_is_zero=1), info, 0)
+    res = apcg.apcg_info_get(info, 0)
+    x = dx.numpy()
+    ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=50000)
+    print(f"gpu its={res['iterations']} oracle its={ref.its}", flush=True)
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED
+    assert abs(res["iterations"] - ref.its) <= 1
+    assert rel(x, ref.x) <= 1e-9
+    true = np.linalg.norm(s.b - s.A.to_scipy() @ x) / np.linalg.norm(s.b)
+    assert true <= 1.5e-10
+    apcg.apcg_info_destroy(info)
