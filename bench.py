@@ -68,6 +68,68 @@ def copy_calibration(apcg, torch):
     apcg.apcg_ctx_synchronize(ctx)
 
 
+def bench_batch(apcg, torch, reps):
+    """256 independent 2D 5-point systems (side ~ U{32..256}, k = exp(N(0,1)),
+    b ~ U[-1,1], seed 3), Jacobi-PCG rtol 1e-8: one batched persistent launch
+    (graph) against the plain path, one apcg_ksp_solve per system spread over
+    8 forked contexts."""
+    from paper_2306_17801_amd import problems
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    systems = problems.batch2d_lognormal(256, seed=3)
+    As = [DeviceCSR(s.A) for s in systems]
+    bs = [DeviceVec(s.b) for s in systems]
+    xs = [DeviceVec.zeros(s.A.n) for s in systems]
+    nsys = len(systems)
+    info = apcg.apcg_info_create(0, nsys)
+    ctx = apcg.apcg_ctx_create(0)
+    out = {"systems": nsys, "rows": int(sum(s.A.n for s in systems)), "nnz": int(sum(s.A.nnz for s in systems))}
+    best = None
+    for tb in (256, 512, 1024):
+        o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_block_size=tb)
+        apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o, info)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o,
+                                        info)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out[f"batched_block{tb}_ms"] = round(1000 * dt, 3)
+        if best is None or dt < best[0]:
+            best = (dt, tb)
+    res = [apcg.apcg_info_get(info, i) for i in range(nsys)]
+    out["batched_block"] = best[1]
+    out["batched_ms"] = round(1000 * best[0], 3)
+    out["batched_solves_per_s"] = round(nsys / best[0], 2)
+    out["converged"] = sum(1 for r in res if r["status"] == apcg.APCG_SOLVE_CONVERGED)
+    out["iterations_min_max"] = [min(r["iterations"] for r in res), max(r["iterations"] for r in res)]
+    log(f"[bench] batch: {out['batched_ms']} ms for {nsys} systems (block {best[1]})")
+
+    # plain path: one graph-mode solve per system, 8 contexts round robin
+    kids = apcg.apcg_ctx_fork(ctx, 8)
+    plain = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    infos = apcg.apcg_info_create(0, nsys)
+    for i in range(nsys):  # warm-up (graph capture per system)
+        apcg.apcg_ksp_solve(kids[i % 8], As[i].h, bs[i].h, xs[i].h, 1e-8, 50000, plain, infos, i)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(nsys):
+        apcg.apcg_ksp_solve(kids[i % 8], As[i].h, bs[i].h, xs[i].h, 1e-8, 50000, plain, infos, i)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    out["per_solve_loop_ms"] = round(1000 * dt, 3)
+    out["per_solve_loop_solves_per_s"] = round(nsys / dt, 2)
+    out["batched_speedup_vs_per_solve_loop"] = round(dt / best[0], 3)
+    log(f"[bench] per-solve loop: {1000 * dt:.1f} ms")
+    apcg.apcg_ctx_join(ctx, kids, apcg.APCG_JOIN_DESTROY)
+    apcg.apcg_info_destroy(infos)
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_synchronize(ctx)
+    apcg.apcg_ctx_destroy(ctx)
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -77,6 +139,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched measurement")
+    ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -203,6 +267,9 @@ def main():
             log(f"[bench] variant {name}: {1000 * dt:.2f} ms/solve")
         var["graph_speedup_vs_host_check"] = round(var["host_check"]["ms_per_solve"] / ms_per_step, 3)
         extra["variants"] = var
+
+    if not args.no_batch:
+        extra["batch2d_256"] = bench_batch(apcg, torch, args.batch_reps)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -303,7 +303,9 @@ typedef struct apcg_solve_opts {
     int32_t kernel_timing;   /* 1: STREAM mode with HIP events around every  */
                              /*    product and update kernel (see            */
                              /*    apcg_ctx_kernel_times)                    */
-    int32_t reserved[9];
+    int32_t batch_block_size;/* apcg_ksp_solve_batched: threads per system   */
+                             /*    (256, 512 or 1024; 0 = 512)               */
+    int32_t reserved[8];
 } apcg_solve_opts;
 
 /* Fills *opts with the defaults: Jacobi, unpreconditioned norm, GRAPH mode,
@@ -340,6 +342,25 @@ apcg_status apcg_info_get(apcg_info info, int32_t index, apcg_solve_info *out);
  * the solve has finished. */
 apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                            const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
+
+/* Solves the nsys independent systems A[i] x[i] = b[i] with Jacobi-PCG (or
+ * CG) in ONE persistent launch: each workgroup takes the next system from a
+ * device work queue ordered by decreasing estimated cost (nnz * sqrt(n)) and
+ * runs that system's whole iteration with workgroup-level reductions; no
+ * iteration involves the host or other workgroups.  Same stopping rule,
+ * tests and order as apcg_ksp_solve (Section 3.3 loop, Section 4.1 Jacobi).
+ * A, b, x: arrays of nsys handles on ctx's device (the x[i] distinct and not
+ * aliasing any b[i]); x[i] holds x0 (ignored with x0_is_zero) and receives
+ * the solution; info must hold >= nsys records, record i for system i.
+ * opts->mode APCG_MODE_GRAPH (default) replays a captured graph of the
+ * queue reset and the launch (cached while the batch is unchanged); other
+ * modes launch directly.  opts->batch_block_size picks the workgroup size.
+ * The context keeps 5 sum(n_i) doubles of workspace and the batch
+ * descriptors.  Returns once the work is enqueued (after a one-time upload
+ * of the descriptors when the batch changed). */
+apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                   const apcg_vec *x, double rtol, int32_t maxit, const apcg_solve_opts *opts,
+                                   apcg_info info);
 
 /* Mean device time (microseconds) and launch count of the product kernel
  * (kind 0: fused SpMV + p.Ap) and the update kernel (kind 1: x, r update

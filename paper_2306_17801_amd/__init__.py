@@ -303,6 +303,17 @@ def apcg_ksp_solve(ctx, A, b, x, rtol: float, maxit: int, opts=None, info=None, 
                                                 int(info_index)))
 
 
+def apcg_ksp_solve_batched(ctx, A_list, b_list, x_list, rtol: float, maxit: int, opts=None, info=None) -> None:
+    """A_list, b_list, x_list: equal-length sequences of handles."""
+    n = len(A_list)
+    if len(b_list) != n or len(x_list) != n:
+        raise ValueError("A_list, b_list and x_list must have the same length")
+    arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[int(h) for h in hs])  # noqa: E731
+    po = ctypes.byref(opts) if opts is not None else None
+    check("apcg_ksp_solve_batched", _L().apcg_ksp_solve_batched(_h(ctx), n, arr(A_list), arr(b_list), arr(x_list),
+                                                                float(rtol), int(maxit), po, _h(info)))
+
+
 # ------------------------------------------------------------------ timers
 
 def apcg_timer_create() -> int:

@@ -70,7 +70,7 @@ class apcg_spmv_config(ctypes.Structure):
 class apcg_solve_opts(ctypes.Structure):
     _fields_ = [("pc", c_i32), ("norm_type", c_i32), ("mode", c_i32), ("iters_per_graph", c_i32),
                 ("lookahead", c_i32), ("x0_is_zero", c_i32), ("kernel_timing", c_i32),
-                ("reserved", c_i32 * 9)]
+                ("batch_block_size", c_i32), ("reserved", c_i32 * 8)]
 
 
 class apcg_solve_info(ctypes.Structure):
@@ -139,6 +139,7 @@ SIGNATURES = {
     "apcg_info_destroy": [c_vp],
     "apcg_info_get": [c_vp, c_i32, P(apcg_solve_info)],
     "apcg_ksp_solve": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts), c_vp, c_i32],
+    "apcg_ksp_solve_batched": [c_vp, c_i32, P(c_vp), P(c_vp), P(c_vp), c_f64, c_i32, P(apcg_solve_opts), c_vp],
     "apcg_ctx_kernel_times": [c_vp, c_i32, P(c_f64), P(c_i32)],
     "apcg_timer_create": [P(c_vp)],
     "apcg_timer_destroy": [c_vp],

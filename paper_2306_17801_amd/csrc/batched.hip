@@ -1,0 +1,472 @@
+// batched.hip -- many independent Jacobi-PCG solves in one persistent launch.
+//
+// Each workgroup takes the next system from a device work queue (ordered by
+// decreasing estimated cost, so the longest solves start first) and runs the
+// whole PCG iteration for it: the same steps, tests and order as the
+// single-system path (the PCG loop of Section 3.3), with the two grid-wide
+// reductions per iteration replaced by workgroup reductions.  Nothing in a
+// solve crosses a workgroup, so there is no inter-workgroup synchronisation at
+// all; the queue index is the only atomic.  Launched once per batch (captured
+// in a hipGraph together with the queue reset), every scalar stays in
+// registers/LDS and no iteration involves the host.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <numeric>
+#include <vector>
+
+#include "internal.h"
+
+namespace apcg {
+
+struct BatchSys {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *b;
+    double *x;
+    double *ws;  // 5 n doubles: r, dinv, p0, p1, w
+    int32_t n;
+    int32_t pad;
+};
+
+namespace {
+
+__device__ __forceinline__ double pdir_b(double d, double r, double beta, double pold) {
+    return fma(beta, pold, d * r);
+}
+
+// Sum of v over the workgroup, returned to every thread; the same fixed tree
+// in every thread, so all threads hold identical totals.
+template <int TB, int NV>
+__device__ __forceinline__ void block_allreduce(double (&v)[NV], double *lds) {
+    constexpr int NW = TB / 64;
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = dev::wave_sum(v[k]);
+    const int wid = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) lds[k * NW + wid] = v[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+        double s = lds[k * NW];
+        for (int w = 1; w < NW; ++w) s += lds[k * NW + w];
+        v[k] = s;
+    }
+    __syncthreads();  // lds may be reused right after
+}
+
+// Row i of A p with p_j = d_j r_j + beta pold_j formed while gathering; rows
+// of up to 8 entries issue every gather before the first multiply-add.  Both
+// branches add in column-storage order.
+__device__ __forceinline__ double row_product(const int32_t *__restrict__ col, const double *__restrict__ val, int s,
+                                              int e, int row, const double *__restrict__ dinv,
+                                              const double *__restrict__ r, const double *__restrict__ pold,
+                                              double beta) {
+    const int len = e - s;
+    double sum = 0.0;
+    if (len <= 8) {
+        int jj[8];
+        double aa[8], pj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool in = q < len;
+            jj[q] = in ? col[s + q] : row;
+            aa[q] = in ? val[s + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pj[q] = pdir_b(dinv[jj[q]], r[jj[q]], beta, pold[jj[q]]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < len) sum = fma(aa[q], pj[q], sum);
+    } else {
+        for (int k = s; k < e; ++k) {
+            const int j = col[k];
+            sum = fma(val[k], pdir_b(dinv[j], r[j], beta, pold[j]), sum);
+        }
+    }
+    return sum;
+}
+
+template <int TB>
+__device__ void solve_one(const BatchSys &S, double rtol, int32_t maxit, int x0_zero, int pc, int norm_pre,
+                          apcg_solve_info *out, double *lds) {
+    const int n = S.n;
+    double *r = S.ws, *dinv = S.ws + n, *pbuf0 = S.ws + 2 * (int64_t)n, *pbuf1 = S.ws + 3 * (int64_t)n;
+    double *w = S.ws + 4 * (int64_t)n;
+    double *x = S.x;
+    const double *b = S.b;
+
+    // setup: dinv, r0, p_old = 0, rho0, reference and residual norms
+    double v4[4] = {0.0, 0.0, 0.0, 0.0};  // z.r, residual^2, reference^2, bad diagonals
+    for (int i = threadIdx.x; i < n; i += TB) {
+        const int s = S.rowptr[i], e = S.rowptr[i + 1];
+        double diag = 0.0, ax = 0.0;
+        bool found = false;
+        for (int k = s; k < e; ++k) {
+            const int j = S.col[k];
+            const double a = S.val[k];
+            if (j == i) {
+                diag = a;
+                found = true;
+            }
+            if (!x0_zero) ax = fma(a, x[j], ax);
+        }
+        double di = 1.0;
+        if (pc == APCG_PC_JACOBI) {
+            const bool ok = found && diag > 0.0;
+            v4[3] += ok ? 0.0 : 1.0;
+            di = ok ? 1.0 / diag : 0.0;
+        }
+        const double bi = b[i];
+        const double ri = x0_zero ? bi : bi - ax;
+        r[i] = ri;
+        dinv[i] = di;
+        pbuf0[i] = 0.0;
+        const double zi = di * ri;
+        v4[0] = fma(zi, ri, v4[0]);
+        if (norm_pre) {
+            const double zb = di * bi;
+            v4[2] = fma(zb, zb, v4[2]);
+            v4[1] = fma(zi, zi, v4[1]);
+        } else {
+            v4[2] = fma(bi, bi, v4[2]);
+            v4[1] = fma(ri, ri, v4[1]);
+        }
+    }
+    // x is written only after every workgroup thread has read x0
+    block_allreduce<TB, 4>(v4, lds);
+    if (x0_zero)
+        for (int i = threadIdx.x; i < n; i += TB) x[i] = 0.0;
+    double rho = v4[0];
+    double res = sqrt(v4[1]);
+    const double ref = sqrt(v4[2]);
+    int status = 0, its = 0;
+    if (v4[3] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
+    else if (ref == 0.0) {
+        status = APCG_SOLVE_CONVERGED;
+        res = 0.0;
+        for (int i = threadIdx.x; i < n; i += TB) x[i] = 0.0;
+    } else if (!isfinite(res) || !isfinite(ref)) status = APCG_SOLVE_NAN;
+    else if (res <= rtol * ref) status = APCG_SOLVE_CONVERGED;
+    else if (!(rho > 0.0)) status = isfinite(rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
+    else if (maxit <= 0) status = APCG_SOLVE_MAXIT;
+
+    double beta = 0.0;
+    for (int k = 1; !status; ++k) {
+        const double *pold = (k & 1) ? pbuf0 : pbuf1;
+        double *pnew = (k & 1) ? pbuf1 : pbuf0;
+        double d1[1] = {0.0};
+        for (int i = threadIdx.x; i < n; i += TB) {
+            const double sum = row_product(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, dinv, r, pold, beta);
+            const double pi = pdir_b(dinv[i], r[i], beta, pold[i]);
+            pnew[i] = pi;
+            w[i] = sum;
+            d1[0] = fma(pi, sum, d1[0]);
+        }
+        block_allreduce<TB, 1>(d1, lds);
+        const double delta = d1[0];
+        if (!(delta > 0.0)) {
+            status = isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN;
+            its = k - 1;
+            break;
+        }
+        const double alpha = rho / delta;
+        double v2[2] = {0.0, 0.0};
+        for (int i = threadIdx.x; i < n; i += TB) {
+            const double xi = fma(alpha, pnew[i], x[i]);
+            const double ri = fma(-alpha, w[i], r[i]);
+            x[i] = xi;
+            r[i] = ri;
+            const double zi = dinv[i] * ri;
+            v2[0] = fma(zi, ri, v2[0]);
+            v2[1] = norm_pre ? fma(zi, zi, v2[1]) : fma(ri, ri, v2[1]);
+        }
+        block_allreduce<TB, 2>(v2, lds);
+        const double rho_new = v2[0];
+        res = sqrt(v2[1]);
+        its = k;
+        if (!isfinite(res) || !isfinite(rho_new)) status = APCG_SOLVE_NAN;
+        else if (res <= rtol * ref) status = APCG_SOLVE_CONVERGED;
+        else if (!(rho_new > 0.0)) status = APCG_SOLVE_BREAKDOWN_RZ;
+        else if (k >= maxit) status = APCG_SOLVE_MAXIT;
+        if (!status) {
+            beta = rho_new / rho;
+            rho = rho_new;
+        }
+    }
+    if (threadIdx.x == 0) {
+        out->iterations = its;
+        out->status = status;
+        out->fcg_iterations = 0;
+        out->reserved = 0;
+        out->res_norm = res;
+        out->ref_norm = ref;
+    }
+}
+
+template <int TB>
+__global__ __launch_bounds__(TB) void k_pcg_batched(const BatchSys *sys, const int32_t *order, int32_t nsys,
+                                                    unsigned *queue, double rtol, int32_t maxit, int x0_zero, int pc,
+                                                    int norm_pre, apcg_solve_info *info) {
+    __shared__ double lds[4 * (TB / 64)];
+    __shared__ int s_next;
+    for (;;) {
+        if (threadIdx.x == 0) s_next = (int)atomicAdd(queue, 1u);
+        __syncthreads();
+        const int q = s_next;
+        __syncthreads();  // every thread has read s_next before it changes
+        if (q >= nsys) return;
+        const int id = order[q];
+        solve_one<TB>(sys[id], rtol, maxit, x0_zero, pc, norm_pre, info + id, lds);
+        __syncthreads();
+    }
+}
+
+__global__ void k_queue_reset(unsigned *queue) {
+    if (threadIdx.x == 0) *queue = 0u;
+}
+
+using BatchedFn = void (*)(const BatchSys *, const int32_t *, int32_t, unsigned *, double, int32_t, int, int, int,
+                           apcg_solve_info *);
+
+BatchedFn batched_fn(int tb) {
+    switch (tb) {
+        case 256: return k_pcg_batched<256>;
+        case 512: return k_pcg_batched<512>;
+        case 1024: return k_pcg_batched<1024>;
+        default: return nullptr;
+    }
+}
+
+uint64_t fnv1a(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = (const unsigned char *)p;
+    for (size_t i = 0; i < n; ++i) {
+        h ^= c[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+}  // namespace
+
+// Per-context batch resources (kept in a side table keyed by context id).
+struct BatchCache {
+    int device = 0;
+    BatchSys *d_sys = nullptr;
+    int32_t *d_order = nullptr;
+    unsigned *d_queue = nullptr;
+    double *d_ws = nullptr;
+    int64_t sys_cap = 0, ws_cap = 0;
+    uint64_t desc_hash = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_hash = 0;
+};
+
+static std::mutex g_batch_mu;
+static std::vector<std::pair<uint64_t, BatchCache *>> g_batch;
+
+static BatchCache *batch_cache(apcg_ctx c) {
+    std::lock_guard<std::mutex> lk(g_batch_mu);
+    for (auto &p : g_batch)
+        if (p.first == c->id) return p.second;
+    BatchCache *bc = new BatchCache();
+    bc->device = c->device;
+    g_batch.emplace_back(c->id, bc);
+    return bc;
+}
+
+void batch_cache_release(uint64_t ctx_id, int device) {
+    BatchCache *bc = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_batch_mu);
+        for (auto it = g_batch.begin(); it != g_batch.end(); ++it)
+            if (it->first == ctx_id) {
+                bc = it->second;
+                g_batch.erase(it);
+                break;
+            }
+    }
+    if (!bc) return;
+    hipSetDevice(device);
+    if (bc->exec) hipGraphExecDestroy(bc->exec);
+    if (bc->graph) hipGraphDestroy(bc->graph);
+    if (bc->d_sys) hipFree(bc->d_sys);
+    if (bc->d_order) hipFree(bc->d_order);
+    if (bc->d_queue) hipFree(bc->d_queue);
+    if (bc->d_ws) hipFree(bc->d_ws);
+    delete bc;
+}
+
+}  // namespace apcg
+
+using namespace apcg;
+
+extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                              const apcg_vec *x, double rtol, int32_t maxit,
+                                              const apcg_solve_opts *opts_in, apcg_info info) {
+    try {
+        if (!ctx || nsys < 1 || !A || !b || !x || !info) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (info->count < nsys) return set_error(APCG_ERR_INVALID_ARG, "info has fewer records than systems");
+        if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(APCG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
+        if (maxit < 0) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0");
+        if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING && ctx->is_default_global)
+            return set_error(APCG_ERR_INVALID_ARG, "pass a context created with apcg_ctx_create");
+        apcg_solve_opts opts;
+        if (opts_in) opts = *opts_in;
+        else apcg_solve_opts_default(&opts);
+        if (opts.pc != APCG_PC_NONE && opts.pc != APCG_PC_JACOBI)
+            return set_error(APCG_ERR_UNSUPPORTED, "unsupported preconditioner for the batched solve");
+        if (opts.norm_type != APCG_NORM_UNPRECONDITIONED && opts.norm_type != APCG_NORM_PRECONDITIONED)
+            return set_error(APCG_ERR_INVALID_ARG, "unknown norm type");
+        const int tb = opts.batch_block_size ? opts.batch_block_size : 512;
+        const BatchedFn fn = batched_fn(tb);
+        if (!fn) return set_error(APCG_ERR_INVALID_ARG, "batch block size must be 256, 512 or 1024");
+        const int dev = ctx->device;
+        std::vector<BatchSys> hs(nsys);
+        std::vector<double> cost(nsys);
+        int64_t ws_total = 0;
+        for (int32_t i = 0; i < nsys; ++i) {
+            if (!A[i] || !b[i] || !x[i]) return set_error(APCG_ERR_INVALID_ARG, "NULL system handle");
+            if (A[i]->device != dev || b[i]->device != dev || x[i]->device != dev || info->device != dev)
+                return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+            if (b[i]->n != A[i]->n || x[i]->n != A[i]->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
+            if (b[i] == x[i] || (b[i]->d == x[i]->d && A[i]->n > 0))
+                return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
+            const int64_t n = A[i]->n;
+            hs[i] = BatchSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x[i]->d, nullptr, (int32_t)n, 0};
+            hs[i].ws = reinterpret_cast<double *>(ws_total);  // offset for now
+            ws_total += ((5 * n + 63) / 64) * 64;
+            // CG iterations grow like sqrt(condition) ~ n^(1/2) in 2D (n^(1/3) in 3D):
+            // estimated cost = nnz * sqrt(n)
+            cost[i] = (double)(A[i]->nnz + n) * std::sqrt((double)std::max<int64_t>(n, 1));
+        }
+        for (int32_t i = 0; i < nsys; ++i)
+            for (int32_t j = i + 1; j < nsys; ++j)
+                if (x[i] == x[j] || (x[i]->d == x[j]->d && x[i]->n > 0))
+                    return set_error(APCG_ERR_INVALID_ARG, "two systems share one solution vector");
+        std::vector<int32_t> order(nsys);
+        std::iota(order.begin(), order.end(), 0);
+        std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return cost[a] > cost[c]; });
+
+        BatchCache *bc = batch_cache(ctx);
+        // Ordering: x read-write, info written, A and b read
+        std::vector<Acc> acc;
+        acc.reserve(3 * nsys + 1);
+        for (int32_t i = 0; i < nsys; ++i) {
+            acc.push_back({&x[i]->rec, ACC_RW});
+            acc.push_back({&A[i]->rec, ACC_R});
+            acc.push_back({&b[i]->rec, ACC_R});
+        }
+        acc.push_back({&info->rec, ACC_W});
+        apcg_status s;
+        if ((s = op_begin(ctx, acc.data(), (int)acc.size()))) return s;
+        hipStream_t st = ctx->stream;
+
+        // (re)allocate device descriptors and workspace; the old buffers may
+        // still be used by queued work, so their release is deferred
+        if (bc->sys_cap < nsys || bc->ws_cap < ws_total) {
+            EventRef ev = event_get(dev);
+            if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+            APCG_HIP(hipEventRecord(ev->e, st));
+            BatchCache old = *bc;
+            defer_release({ev}, [old]() {
+                hipSetDevice(old.device);
+                if (old.exec) hipGraphExecDestroy(old.exec);
+                if (old.graph) hipGraphDestroy(old.graph);
+                hipFree(old.d_sys);
+                hipFree(old.d_order);
+                hipFree(old.d_queue);
+                hipFree(old.d_ws);
+            });
+            bc->exec = nullptr;
+            bc->graph = nullptr;
+            bc->graph_hash = 0;
+            bc->desc_hash = 0;
+            const int64_t cap = std::max<int64_t>(nsys, bc->sys_cap);
+            APCG_HIP(hipMalloc((void **)&bc->d_sys, sizeof(BatchSys) * cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_order, sizeof(int32_t) * cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_queue, 256));
+            APCG_HIP(hipMalloc((void **)&bc->d_ws, sizeof(double) * std::max<int64_t>(ws_total, 64)));
+            bc->sys_cap = cap;
+            bc->ws_cap = std::max<int64_t>(ws_total, 64);
+        }
+        for (int32_t i = 0; i < nsys; ++i) hs[i].ws = bc->d_ws + reinterpret_cast<int64_t>(hs[i].ws);
+        uint64_t h = fnv1a(hs.data(), sizeof(BatchSys) * nsys);
+        h = fnv1a(order.data(), sizeof(int32_t) * nsys, h);
+        if (h != bc->desc_hash) {
+            g_counters.h2d_copies += 2;
+            APCG_HIP(hipMemcpyAsync(bc->d_sys, hs.data(), sizeof(BatchSys) * nsys, hipMemcpyHostToDevice, st));
+            APCG_HIP(hipMemcpyAsync(bc->d_order, order.data(), sizeof(int32_t) * nsys, hipMemcpyHostToDevice, st));
+            // the host arrays are local: wait until the copies have consumed them
+            g_counters.host_syncs++;
+            APCG_HIP(hipStreamSynchronize(st));
+            bc->desc_hash = h;
+        }
+
+        int per_cu = 0;
+        APCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), tb, 0));
+        hipDeviceProp_t prop;
+        APCG_HIP(hipGetDeviceProperties(&prop, dev));
+        const int grid = std::max(1, std::min<int>(nsys, std::max(1, per_cu) * prop.multiProcessorCount));
+        const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
+        const int x0z = opts.x0_is_zero ? 1 : 0;
+
+        uint64_t gh = fnv1a(&h, sizeof h);
+        double params[2] = {rtol, (double)maxit};
+        int iparams[6] = {grid, tb, x0z, opts.pc, norm_pre, nsys};
+        gh = fnv1a(params, sizeof params, gh);
+        gh = fnv1a(iparams, sizeof iparams, gh);
+        const void *ip = info->d;
+        gh = fnv1a(&ip, sizeof ip, gh);
+        if (opts.mode == APCG_MODE_GRAPH) {
+            if (!bc->exec || bc->graph_hash != gh) {
+                if (bc->exec) {
+                    EventRef ev = event_get(dev);
+                    if (ev) hipEventRecord(ev->e, st);
+                    hipGraphExec_t oe = bc->exec;
+                    hipGraph_t og = bc->graph;
+                    defer_release({ev}, [oe, og, dev]() {
+                        hipSetDevice(dev);
+                        hipGraphExecDestroy(oe);
+                        hipGraphDestroy(og);
+                    });
+                    bc->exec = nullptr;
+                    bc->graph = nullptr;
+                }
+                APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, bc->d_queue);
+                hipLaunchKernelGGL(fn, dim3(grid), dim3(tb), 0, st, (const BatchSys *)bc->d_sys,
+                                   (const int32_t *)bc->d_order, nsys, bc->d_queue, rtol, maxit, x0z, opts.pc,
+                                   norm_pre, info->d);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &g);
+                if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(batched)");
+                e = hipGraphInstantiate(&bc->exec, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    hipGraphDestroy(g);
+                    return hip_error(e, "hipGraphInstantiate(batched)");
+                }
+                bc->graph = g;
+                bc->graph_hash = gh;
+            }
+            g_counters.graph_launches++;
+            APCG_HIP(hipGraphLaunch(bc->exec, st));
+        } else {
+            hipLaunchKernelGGL(k_queue_reset, dim3(1), dim3(64), 0, st, bc->d_queue);
+            APCG_CHECK_LAUNCH("k_queue_reset");
+            hipLaunchKernelGGL(fn, dim3(grid), dim3(tb), 0, st, (const BatchSys *)bc->d_sys,
+                               (const int32_t *)bc->d_order, nsys, bc->d_queue, rtol, maxit, x0z, opts.pc, norm_pre,
+                               info->d);
+            APCG_CHECK_LAUNCH("k_pcg_batched");
+        }
+        return op_end(ctx, acc.data(), (int)acc.size());
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}

@@ -1,0 +1,137 @@
+"""GPU parity of the batched persistent PCG (one launch, one system per
+workgroup) against the CPU oracle, system by system, through the C ABI."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_17801_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apcg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_17801_amd as m
+
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(apcg):
+    c = apcg.apcg_ctx_create(0)
+    yield c
+    apcg.apcg_ctx_synchronize(c)
+    apcg.apcg_ctx_destroy(c)
+
+
+def run_batch(apcg, ctx, systems, rtol, maxit, x0s=None, **opt):
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    As = [DeviceCSR(s.A) for s in systems]
+    bs = [DeviceVec(s.b) for s in systems]
+    xs = [DeviceVec(np.zeros(s.A.n) if x0s is None else x0s[i]) for i, s in enumerate(systems)]
+    if x0s is None:
+        opt.setdefault("x0_is_zero", 1)
+    info = apcg.apcg_info_create(0, len(systems))
+    opts = apcg.apcg_solve_opts_default(**opt)
+    apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], rtol, maxit, opts, info)
+    res = [apcg.apcg_info_get(info, i) for i in range(len(systems))]
+    out = [x.numpy() for x in xs]
+    apcg.apcg_info_destroy(info)
+    return res, out
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def mixed_small_batch():
+    rng = np.random.default_rng(60)
+    out = []
+    for i in range(24):
+        dim = 2 + (i % 2)
+        side = int(rng.integers(2, 40 if dim == 2 else 14))
+        out.append(P._lognormal_system(rng, dim, side, float(rng.uniform(0.5, 2.0)),
+                                       float(np.exp(rng.uniform(0, np.log(50))))))
+    # edge cases: one unknown, b = 0, a non-positive diagonal
+    one = P.CSR(n=1, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32), val=np.array([4.0]))
+    out.append(P.System(A=one, b=np.array([2.0])))
+    z = P.laplace_2d(5)
+    out.append(P.System(A=z, b=np.zeros(z.n)))
+    bad = P.laplace_2d(4)
+    bad.val = bad.val.copy()
+    bad.val[0] = -1.0  # row 0's diagonal is its first entry
+    out.append(P.System(A=bad, b=np.ones(bad.n)))
+    return out
+
+
+@pytest.mark.parametrize("tb", [256, 512, 1024])
+@pytest.mark.parametrize("mode", [0, 1])
+def test_mixed_batch_matches_oracle(apcg, ctx, tb, mode):
+    print(f"case batched mixed tb={tb} mode={mode}", flush=True)
+    systems = mixed_small_batch()
+    res, xs = run_batch(apcg, ctx, systems, 1e-10, 5000, batch_block_size=tb, mode=mode)
+    for i, (s, r, x) in enumerate(zip(systems, res, xs)):
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=5000)
+        assert r["status"] == ref.status, (i, r, ref)
+        if ref.status == oracle.CONVERGED:
+            assert abs(r["iterations"] - ref.its) <= 1, (i, r, ref)
+            assert rel(x, ref.x) <= 1e-9, i
+    assert np.all(xs[-2] == 0)  # b = 0 -> x = 0
+
+
+def test_batched_initial_guess_and_maxit(apcg, ctx):
+    rng = np.random.default_rng(61)
+    systems = [P._lognormal_system(rng, 2, int(rng.integers(8, 30)), 1.0, 1.0) for _ in range(6)]
+    x0s = [rng.uniform(-1, 1, s.A.n) for s in systems]
+    res, xs = run_batch(apcg, ctx, systems, 0.0, 7, x0s=x0s)
+    for s, r, x, x0 in zip(systems, res, xs, x0s):
+        ref = oracle.pcg(s.A, s.b, x0=x0, rtol=0.0, maxit=7)
+        assert r["status"] == oracle.MAXIT and r["iterations"] == 7
+        assert rel(x, ref.x) <= 1e-12
+
+
+def test_batched_deterministic_and_graph_equals_direct(apcg, ctx):
+    systems = mixed_small_batch()[:20]
+    r1, x1 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=0)
+    r2, x2 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=1)
+    r3, x3 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=0)
+    assert r1 == r2 == r3
+    assert all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(x1, x2, x3))
+
+
+@pytest.fixture(scope="module")
+def batch256():
+    return P.batch2d_lognormal(256, seed=3)
+
+
+def test_batch2d_first_sixteen_full_size(apcg, ctx, batch256):
+    """The first 16 systems of the 256-system 2D batch, at full size,
+    rtol 1e-10: iterations +-1 and rel <= 1e-9 per system."""
+    systems = batch256[:16]
+    res, xs = run_batch(apcg, ctx, systems, 1e-10, 20000)
+    for s, r, x in zip(systems, res, xs):
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=20000)
+        assert r["status"] == apcg.APCG_SOLVE_CONVERGED
+        assert abs(r["iterations"] - ref.its) <= 1
+        assert rel(x, ref.x) <= 1e-9
+
+
+def test_batch2d_all_256_in_bench_configuration(apcg, ctx, batch256):
+    """All 256 systems at rtol 1e-8 in the launch configuration the benchmark
+    times: every system converges with a true residual within 1.5 rtol; eight
+    sampled systems match the oracle's iteration count +-1."""
+    res, xs = run_batch(apcg, ctx, batch256, 1e-8, 20000)
+    for s, r, x in zip(batch256, res, xs):
+        assert r["status"] == apcg.APCG_SOLVE_CONVERGED
+        tr = np.linalg.norm(s.b - oracle.spmv(s.A, x)) / np.linalg.norm(s.b)
+        assert tr <= 1.5e-8
+    for i in (0, 37, 64, 101, 150, 199, 230, 255):
+        ref = oracle.pcg(batch256[i].A, batch256[i].b, rtol=1e-8, maxit=20000)
+        assert abs(res[i]["iterations"] - ref.its) <= 1
