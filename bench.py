@@ -85,8 +85,9 @@ def bench_batch(apcg, torch, reps):
     ctx = apcg.apcg_ctx_create(0)
     out = {"systems": nsys, "rows": int(sum(s.A.n for s in systems)), "nnz": int(sum(s.A.nnz for s in systems))}
     best = None
-    for tb in (256, 512, 1024):
-        o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_block_size=tb)
+    for name, sched, tb in (("persistent256", 1, 256), ("persistent512", 1, 512), ("persistent1024", 1, 1024),
+                            ("segmented", 2, 0)):
+        o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_block_size=tb, batch_schedule=sched)
         apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o, info)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -95,16 +96,16 @@ def bench_batch(apcg, torch, reps):
                                         info)
         torch.cuda.synchronize()
         dt = (time.perf_counter() - t0) / reps
-        out[f"batched_block{tb}_ms"] = round(1000 * dt, 3)
+        out[f"batched_{name}_ms"] = round(1000 * dt, 3)
         if best is None or dt < best[0]:
-            best = (dt, tb)
+            best = (dt, name)
     res = [apcg.apcg_info_get(info, i) for i in range(nsys)]
-    out["batched_block"] = best[1]
+    out["batched_schedule"] = best[1]
     out["batched_ms"] = round(1000 * best[0], 3)
     out["batched_solves_per_s"] = round(nsys / best[0], 2)
     out["converged"] = sum(1 for r in res if r["status"] == apcg.APCG_SOLVE_CONVERGED)
     out["iterations_min_max"] = [min(r["iterations"] for r in res), max(r["iterations"] for r in res)]
-    log(f"[bench] batch: {out['batched_ms']} ms for {nsys} systems (block {best[1]})")
+    log(f"[bench] batch: {out} ")
 
     # plain path: one graph-mode solve per system, 8 contexts round robin
     kids = apcg.apcg_ctx_fork(ctx, 8)

@@ -305,8 +305,14 @@ typedef struct apcg_solve_opts {
                              /*    apcg_ctx_kernel_times)                    */
     int32_t batch_block_size;/* apcg_ksp_solve_batched: threads per system   */
                              /*    (256, 512 or 1024; 0 = 512)               */
-    int32_t reserved[8];
+    int32_t batch_schedule;  /* APCG_BATCH_*                                 */
+    int32_t reserved[7];
 } apcg_solve_opts;
+
+/* Schedules of apcg_ksp_solve_batched. */
+#define APCG_BATCH_AUTO 0       /* persistent when the batch is balanced enough */
+#define APCG_BATCH_PERSISTENT 1 /* one launch; one workgroup per system        */
+#define APCG_BATCH_SEGMENTED 2  /* the batch as one block-diagonal system      */
 
 /* Fills *opts with the defaults: Jacobi, unpreconditioned norm, GRAPH mode,
  * K = 16, lookahead 2, x0 read from x, no kernel timing. */
@@ -344,20 +350,29 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
                            const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
 
 /* Solves the nsys independent systems A[i] x[i] = b[i] with Jacobi-PCG (or
- * CG) in ONE persistent launch: each workgroup takes the next system from a
- * device work queue ordered by decreasing estimated cost (nnz * sqrt(n)) and
- * runs that system's whole iteration with workgroup-level reductions; no
- * iteration involves the host or other workgroups.  Same stopping rule,
- * tests and order as apcg_ksp_solve (Section 3.3 loop, Section 4.1 Jacobi).
+ * CG): same stopping rule, tests and order as apcg_ksp_solve (Section 3.3
+ * loop, Section 4.1 Jacobi), every system with its own scalars and status.
+ *   APCG_BATCH_PERSISTENT: ONE launch; each workgroup takes the next system
+ *     from a device work queue ordered by decreasing estimated cost
+ *     (nnz * sqrt(n)) and runs that system's whole iteration with
+ *     workgroup-level reductions (opts->batch_block_size threads).  Best for
+ *     many similar small systems.
+ *   APCG_BATCH_SEGMENTED: the batch as one block-diagonal system cut into
+ *     256-row tiles; per iteration a tile product, a per-system alpha, a
+ *     tile update and a per-system test, K iterations per captured graph;
+ *     stopped systems' tiles return at once.  Best when a few large systems
+ *     dominate.
+ *   APCG_BATCH_AUTO: persistent when no system costs more than 1/CUs of the
+ *     batch, else segmented.
  * A, b, x: arrays of nsys handles on ctx's device (the x[i] distinct and not
  * aliasing any b[i]); x[i] holds x0 (ignored with x0_is_zero) and receives
  * the solution; info must hold >= nsys records, record i for system i.
- * opts->mode APCG_MODE_GRAPH (default) replays a captured graph of the
- * queue reset and the launch (cached while the batch is unchanged); other
- * modes launch directly.  opts->batch_block_size picks the workgroup size.
- * The context keeps 5 sum(n_i) doubles of workspace and the batch
- * descriptors.  Returns once the work is enqueued (after a one-time upload
- * of the descriptors when the batch changed). */
+ * opts->mode APCG_MODE_GRAPH (default) replays captured graphs (cached while
+ * the batch is unchanged).  The context keeps 5 sum(n_i) doubles of
+ * workspace and the batch descriptors.  Returns once the work is enqueued
+ * (after a one-time upload of the descriptors when the batch changed; the
+ * segmented schedule polls the device's count of running systems one graph
+ * behind, as apcg_ksp_solve does). */
 apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
                                    const apcg_vec *x, double rtol, int32_t maxit, const apcg_solve_opts *opts,
                                    apcg_info info);

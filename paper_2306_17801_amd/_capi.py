@@ -61,6 +61,9 @@ APCG_MODE_STREAM = 1
 APCG_MODE_HOST_CHECK = 2
 APCG_SPMV_ROWGROUP = 0
 APCG_SPMV_STREAM = 1
+APCG_BATCH_AUTO = 0
+APCG_BATCH_PERSISTENT = 1
+APCG_BATCH_SEGMENTED = 2
 
 
 class apcg_spmv_config(ctypes.Structure):
@@ -70,7 +73,7 @@ class apcg_spmv_config(ctypes.Structure):
 class apcg_solve_opts(ctypes.Structure):
     _fields_ = [("pc", c_i32), ("norm_type", c_i32), ("mode", c_i32), ("iters_per_graph", c_i32),
                 ("lookahead", c_i32), ("x0_is_zero", c_i32), ("kernel_timing", c_i32),
-                ("batch_block_size", c_i32), ("reserved", c_i32 * 8)]
+                ("batch_block_size", c_i32), ("batch_schedule", c_i32), ("reserved", c_i32 * 7)]
 
 
 class apcg_solve_info(ctypes.Structure):

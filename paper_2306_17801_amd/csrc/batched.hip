@@ -32,6 +32,10 @@ struct BatchSys {
     int32_t pad;
 };
 
+// segmented schedule (below)
+apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const BatchSys *d_sys, double rtol,
+                      int32_t maxit, const apcg_solve_opts &opts, apcg_solve_info *d_info);
+
 namespace {
 
 __device__ __forceinline__ double pdir_b(double d, double r, double beta, double pold) {
@@ -409,10 +413,24 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
             bc->desc_hash = h;
         }
 
-        int per_cu = 0;
-        APCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), tb, 0));
         hipDeviceProp_t prop;
         APCG_HIP(hipGetDeviceProperties(&prop, dev));
+        int sched = opts.batch_schedule;
+        if (sched == APCG_BATCH_AUTO) {
+            // one workgroup per system finishes no earlier than its costliest
+            // system on one CU; the segmented schedule spreads every system
+            // over the whole chip
+            const double total = std::accumulate(cost.begin(), cost.end(), 0.0);
+            const double worst = *std::max_element(cost.begin(), cost.end());
+            sched = worst * prop.multiProcessorCount <= total ? APCG_BATCH_PERSISTENT : APCG_BATCH_SEGMENTED;
+        }
+        if (sched == APCG_BATCH_SEGMENTED) {
+            if ((s = seg_solve(ctx, nsys, hs.data(), bc->d_sys, rtol, maxit, opts, info->d))) return s;
+            return op_end(ctx, acc.data(), (int)acc.size());
+        }
+        if (sched != APCG_BATCH_PERSISTENT) return set_error(APCG_ERR_INVALID_ARG, "unknown batch schedule");
+        int per_cu = 0;
+        APCG_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, reinterpret_cast<const void *>(fn), tb, 0));
         const int grid = std::max(1, std::min<int>(nsys, std::max(1, per_cu) * prop.multiProcessorCount));
         const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
         const int x0z = opts.x0_is_zero ? 1 : 0;
@@ -470,3 +488,520 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
 }
+
+// ===========================================================================
+// Segmented schedule: the batch as one block-diagonal system.
+//
+// Rows of every system are cut into tiles of ST rows (a tile never crosses
+// two systems).  Each iteration is four kernels, queued K iterations at a
+// time in a captured graph:
+//   seg_product (tiles):   p_new = D^-1 r + beta_s p_old, w = A p_new, and a
+//                          partial of p.w per tile;
+//   seg_alpha   (systems): one workgroup per system adds its tiles' partials
+//                          in order, tests p.Ap, alpha_s = rho_s / delta_s;
+//   seg_update  (tiles):   x += alpha_s p, r -= alpha_s w, partials of z.r
+//                          and ||r||^2 per tile;
+//   seg_beta    (systems): the tests of the iteration and beta_s.
+// Every system keeps its own scalars and stop flag; tiles of stopped systems
+// return at once, and a device count of running systems lets the host stop
+// queueing graphs.  All CUs stream all systems' rows, so the batch runs at
+// HBM speed instead of one CU per system.
+// ===========================================================================
+
+namespace apcg {
+
+struct SegSys {  // per-system scalars, owned by the per-system kernels
+    double rho, beta, alpha, delta;
+    double res, ref;
+    int32_t its, status, flag, zero_x;
+};
+
+struct SegPlan {
+    const BatchSys *sys;   // [nsys]
+    const int32_t *tile_sys, *tile_row0;  // [ntiles]
+    const int32_t *sys_tile0;  // [nsys + 1]
+    SegSys *st;            // [nsys]
+    double *part_res;      // 4 * ntiles
+    double *part_delta;    // ntiles
+    unsigned *running;     // systems still iterating
+    int32_t nsys, ntiles, tiles_per_block;
+};
+
+namespace {
+
+constexpr int ST = 256;  // rows per tile = threads per tile workgroup
+
+__device__ __forceinline__ void tile_range(const SegPlan &P, int *t0, int *t1) {
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    *t0 = lb * P.tiles_per_block;
+    *t1 = min(P.ntiles, *t0 + P.tiles_per_block);
+}
+
+__global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc, int norm_pre) {
+    int t0, t1;
+    tile_range(P, &t0, &t1);
+    __shared__ double lds[4 * (ST / 64)];
+    for (int t = t0; t < t1; ++t) {
+        const BatchSys S = P.sys[P.tile_sys[t]];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[4] = {0.0, 0.0, 0.0, 0.0};
+        if (i < S.n) {
+            const int s = S.rowptr[i], e = S.rowptr[i + 1];
+            double diag = 0.0, ax = 0.0;
+            bool found = false;
+            for (int k = s; k < e; ++k) {
+                const int j = S.col[k];
+                const double a = S.val[k];
+                if (j == i) {
+                    diag = a;
+                    found = true;
+                }
+                if (!x0_zero) ax = fma(a, S.x[j], ax);
+            }
+            double di = 1.0;
+            if (pc == APCG_PC_JACOBI) {
+                const bool ok = found && diag > 0.0;
+                v[3] = ok ? 0.0 : 1.0;
+                di = ok ? 1.0 / diag : 0.0;
+            }
+            const double bi = S.b[i];
+            const double ri = x0_zero ? bi : bi - ax;
+            const int64_t n = S.n;
+            S.ws[i] = ri;             // r
+            S.ws[n + i] = di;         // dinv
+            S.ws[2 * n + i] = 0.0;    // p[0]
+            if (x0_zero) S.x[i] = 0.0;
+            const double zi = di * ri;
+            v[0] = zi * ri;
+            if (norm_pre) {
+                const double zb = di * bi;
+                v[1] = zi * zi;
+                v[2] = zb * zb;
+            } else {
+                v[1] = ri * ri;
+                v[2] = bi * bi;
+            }
+        }
+        dev::block_sum<ST, 4>(v, lds);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 4; ++k) P.part_res[k * P.ntiles + t] = v[k];
+        __syncthreads();
+    }
+}
+
+// Adds the partials part[k*ntiles + t] of system s's tiles (index order),
+// result in thread 0.
+template <int NV>
+__device__ __forceinline__ void sys_sum(const double *part, int ntiles, int ta, int tb, double (&v)[NV], double *lds) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int t = ta + (int)threadIdx.x; t < tb; t += 64) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += part[k * ntiles + t];
+    }
+    dev::block_sum<64, NV>(v, lds);
+}
+
+__global__ __launch_bounds__(64) void k_seg_init_final(SegPlan P, double rtol, int32_t maxit) {
+    const int s = blockIdx.x;
+    __shared__ double lds[4];
+    double v[4];
+    sys_sum<4>(P.part_res, P.ntiles, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    if (threadIdx.x != 0) return;
+    SegSys q;
+    q.rho = v[0];
+    q.res = sqrt(v[1]);
+    q.ref = sqrt(v[2]);
+    q.beta = 0.0;
+    q.alpha = 0.0;
+    q.delta = 0.0;
+    q.its = 0;
+    q.zero_x = 0;
+    int status = 0;
+    if (v[3] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
+    else if (q.ref == 0.0) {
+        status = APCG_SOLVE_CONVERGED;
+        q.zero_x = 1;
+        q.res = 0.0;
+    } else if (!isfinite(q.res) || !isfinite(q.ref)) status = APCG_SOLVE_NAN;
+    else if (q.res <= rtol * q.ref) status = APCG_SOLVE_CONVERGED;
+    else if (!(q.rho > 0.0)) status = isfinite(q.rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
+    else if (maxit <= 0) status = APCG_SOLVE_MAXIT;
+    q.status = status;
+    q.flag = status != 0;
+    P.st[s] = q;
+    if (!q.flag) atomicAdd(P.running, 1u);
+}
+
+__global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
+    int t0, t1;
+    tile_range(P, &t0, &t1);
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        if (!P.st[s].zero_x) continue;
+        const BatchSys S = P.sys[s];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        if (i < S.n) S.x[i] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
+    int t0, t1;
+    tile_range(P, &t0, &t1);
+    __shared__ double lds[ST / 64];
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        if (P.st[s].flag) continue;  // uniform across the workgroup
+        const double beta = P.st[s].beta;
+        const BatchSys S = P.sys[s];
+        const int64_t n = S.n;
+        const double *r = S.ws, *dinv = S.ws + n;
+        const double *pold = S.ws + (2 + ((parity + 1) & 1)) * n;
+        double *pnew = S.ws + (2 + (parity & 1)) * n;
+        double *w = S.ws + 4 * n;
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[1] = {0.0};
+        if (i < S.n) {
+            const double sum = row_product(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, dinv, r, pold, beta);
+            const double pi = pdir_b(dinv[i], r[i], beta, pold[i]);
+            pnew[i] = pi;
+            w[i] = sum;
+            v[0] = pi * sum;
+        }
+        dev::block_sum<ST, 1>(v, lds);
+        if (threadIdx.x == 0) P.part_delta[t] = v[0];
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
+    const int s = blockIdx.x;
+    if (P.st[s].flag) return;
+    __shared__ double lds[1];
+    double v[1];
+    sys_sum<1>(P.part_delta, P.ntiles, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    if (threadIdx.x != 0) return;
+    SegSys *q = P.st + s;
+    const double delta = v[0];
+    q->delta = delta;
+    if (!(delta > 0.0)) {
+        q->status = isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN;
+        q->flag = 1;
+        atomicSub(P.running, 1u);
+    } else {
+        q->alpha = q->rho / delta;
+    }
+}
+
+__global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int norm_pre) {
+    int t0, t1;
+    tile_range(P, &t0, &t1);
+    __shared__ double lds[2 * (ST / 64)];
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        if (P.st[s].flag) continue;
+        const double alpha = P.st[s].alpha;
+        const BatchSys S = P.sys[s];
+        const int64_t n = S.n;
+        double *r = S.ws;
+        const double *dinv = S.ws + n;
+        const double *p = S.ws + (2 + (parity & 1)) * n;
+        const double *w = S.ws + 4 * n;
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[2] = {0.0, 0.0};
+        if (i < S.n) {
+            const double xi = fma(alpha, p[i], S.x[i]);
+            const double ri = fma(-alpha, w[i], r[i]);
+            S.x[i] = xi;
+            r[i] = ri;
+            const double zi = dinv[i] * ri;
+            v[0] = zi * ri;
+            v[1] = norm_pre ? zi * zi : ri * ri;
+        }
+        dev::block_sum<ST, 2>(v, lds);
+        if (threadIdx.x == 0) {
+            P.part_res[t] = v[0];
+            P.part_res[P.ntiles + t] = v[1];
+        }
+        __syncthreads();
+    }
+}
+
+__global__ __launch_bounds__(64) void k_seg_beta(SegPlan P, double rtol, int32_t maxit) {
+    const int s = blockIdx.x;
+    if (P.st[s].flag) return;
+    __shared__ double lds[2];
+    double v[2];
+    sys_sum<2>(P.part_res, P.ntiles, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    if (threadIdx.x != 0) return;
+    SegSys *q = P.st + s;
+    const double rho_new = v[0], res = sqrt(v[1]);
+    const int its = q->its + 1;
+    q->its = its;
+    q->res = res;
+    int status = 0;
+    if (!isfinite(res) || !isfinite(rho_new)) status = APCG_SOLVE_NAN;
+    else if (res <= rtol * q->ref) status = APCG_SOLVE_CONVERGED;
+    else if (!(rho_new > 0.0)) status = APCG_SOLVE_BREAKDOWN_RZ;
+    else if (its >= maxit) status = APCG_SOLVE_MAXIT;
+    if (status) {
+        q->status = status;
+        q->flag = 1;
+        atomicSub(P.running, 1u);
+    } else {
+        q->beta = rho_new / q->rho;
+        q->rho = rho_new;
+    }
+}
+
+__global__ void k_seg_finish(SegPlan P, apcg_solve_info *info) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.nsys) return;
+    const SegSys q = P.st[s];
+    info[s].iterations = q.its;
+    info[s].status = q.status ? q.status : APCG_SOLVE_MAXIT;
+    info[s].fcg_iterations = 0;
+    info[s].reserved = 0;
+    info[s].res_norm = q.res;
+    info[s].ref_norm = q.ref;
+}
+
+__global__ void k_seg_reset(unsigned *running) {
+    if (threadIdx.x == 0) *running = 0u;
+}
+
+}  // namespace
+
+// Segment resources of one context (tile tables, per-system scalars, graph).
+struct SegCache {
+    int device = 0;
+    int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr;
+    SegSys *d_st = nullptr;
+    double *d_part = nullptr;  // 5 * ntiles
+    unsigned *d_running = nullptr;
+    int64_t tiles_cap = 0, sys_cap = 0;
+    uint64_t hash = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_hash = 0;
+    int32_t *pinned = nullptr;  // lookahead flags
+    EventRef poll_ev[kMaxLookahead];
+};
+
+static std::mutex g_seg_mu;
+static std::vector<std::pair<uint64_t, SegCache *>> g_seg;
+
+static SegCache *seg_cache(apcg_ctx c) {
+    std::lock_guard<std::mutex> lk(g_seg_mu);
+    for (auto &p : g_seg)
+        if (p.first == c->id) return p.second;
+    SegCache *sc = new SegCache();
+    sc->device = c->device;
+    g_seg.emplace_back(c->id, sc);
+    return sc;
+}
+
+static void seg_free_buffers(SegCache &s) {
+    if (s.exec) hipGraphExecDestroy(s.exec);
+    if (s.graph) hipGraphDestroy(s.graph);
+    hipFree(s.d_tile_sys);
+    hipFree(s.d_tile_row0);
+    hipFree(s.d_sys_tile0);
+    hipFree(s.d_st);
+    hipFree(s.d_part);
+    hipFree(s.d_running);
+}
+
+void seg_cache_release(uint64_t ctx_id, int device) {
+    SegCache *sc = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_seg_mu);
+        for (auto it = g_seg.begin(); it != g_seg.end(); ++it)
+            if (it->first == ctx_id) {
+                sc = it->second;
+                g_seg.erase(it);
+                break;
+            }
+    }
+    if (!sc) return;
+    hipSetDevice(device);
+    seg_free_buffers(*sc);
+    if (sc->pinned) hipHostFree(sc->pinned);
+    delete sc;
+}
+
+// Enqueues the segmented solve of the batch whose descriptors are already on
+// the device (d_sys).  Called from apcg_ksp_solve_batched.
+apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const BatchSys *d_sys, double rtol,
+                      int32_t maxit, const apcg_solve_opts &opts, apcg_solve_info *d_info) {
+    SegCache *sc = seg_cache(ctx);
+    const int dev = ctx->device;
+    hipStream_t st = ctx->stream;
+    std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
+    for (int32_t s = 0; s < nsys; ++s) {
+        sys_tile0[s] = (int32_t)tile_sys.size();
+        const int32_t n = hsys[s].n;
+        for (int32_t r0 = 0; r0 < n; r0 += ST) {
+            tile_sys.push_back(s);
+            tile_row0.push_back(r0);
+        }
+    }
+    sys_tile0[nsys] = (int32_t)tile_sys.size();
+    const int32_t ntiles = (int32_t)tile_sys.size();
+    if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well-formed
+        tile_sys.push_back(0);
+        tile_row0.push_back(0);
+    }
+    const int32_t nt_alloc = std::max<int32_t>(ntiles, 1);
+    if (sc->tiles_cap < nt_alloc || sc->sys_cap < nsys) {
+        EventRef ev = event_get(dev);
+        if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+        APCG_HIP(hipEventRecord(ev->e, st));
+        SegCache old = *sc;
+        defer_release({ev}, [old, dev]() mutable {
+            hipSetDevice(dev);
+            seg_free_buffers(old);
+        });
+        sc->exec = nullptr;
+        sc->graph = nullptr;
+        sc->graph_hash = 0;
+        sc->hash = 0;
+        sc->tiles_cap = std::max<int64_t>(nt_alloc, sc->tiles_cap);
+        sc->sys_cap = std::max<int64_t>(nsys, sc->sys_cap);
+        APCG_HIP(hipMalloc((void **)&sc->d_tile_sys, sizeof(int32_t) * sc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&sc->d_tile_row0, sizeof(int32_t) * sc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&sc->d_sys_tile0, sizeof(int32_t) * (sc->sys_cap + 1)));
+        APCG_HIP(hipMalloc((void **)&sc->d_st, sizeof(SegSys) * sc->sys_cap));
+        APCG_HIP(hipMalloc((void **)&sc->d_part, sizeof(double) * 5 * sc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&sc->d_running, 256));
+    }
+    if (!sc->pinned) APCG_HIP(hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
+    uint64_t h = fnv1a(tile_sys.data(), sizeof(int32_t) * tile_sys.size());
+    h = fnv1a(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
+    h = fnv1a(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
+    if (h != sc->hash) {
+        g_counters.h2d_copies += 3;
+        APCG_HIP(hipMemcpyAsync(sc->d_tile_sys, tile_sys.data(), sizeof(int32_t) * tile_sys.size(),
+                                hipMemcpyHostToDevice, st));
+        APCG_HIP(hipMemcpyAsync(sc->d_tile_row0, tile_row0.data(), sizeof(int32_t) * tile_row0.size(),
+                                hipMemcpyHostToDevice, st));
+        APCG_HIP(hipMemcpyAsync(sc->d_sys_tile0, sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(),
+                                hipMemcpyHostToDevice, st));
+        g_counters.host_syncs++;
+        APCG_HIP(hipStreamSynchronize(st));  // host tables are local
+        sc->hash = h;
+    }
+    SegPlan P;
+    P.sys = d_sys;
+    P.tile_sys = sc->d_tile_sys;
+    P.tile_row0 = sc->d_tile_row0;
+    P.sys_tile0 = sc->d_sys_tile0;
+    P.st = sc->d_st;
+    P.part_res = sc->d_part;
+    P.part_delta = sc->d_part + 4 * (int64_t)sc->tiles_cap;
+    P.running = sc->d_running;
+    P.nsys = nsys;
+    P.ntiles = ntiles;
+    const int G = normalise_blocks(2048, std::max<int32_t>(ntiles, 1));
+    P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
+    const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
+    const int x0z = opts.x0_is_zero ? 1 : 0;
+
+    hipLaunchKernelGGL(k_seg_reset, dim3(1), dim3(64), 0, st, sc->d_running);
+    APCG_CHECK_LAUNCH("k_seg_reset");
+    hipLaunchKernelGGL(k_seg_init, dim3(G), dim3(ST), 0, st, P, x0z, opts.pc, norm_pre);
+    APCG_CHECK_LAUNCH("k_seg_init");
+    hipLaunchKernelGGL(k_seg_init_final, dim3(nsys), dim3(64), 0, st, P, rtol, maxit);
+    APCG_CHECK_LAUNCH("k_seg_init_final");
+    hipLaunchKernelGGL(k_seg_zero_x, dim3(G), dim3(ST), 0, st, P);
+    APCG_CHECK_LAUNCH("k_seg_zero_x");
+
+    int K = std::max(2, opts.iters_per_graph);
+    if (K & 1) ++K;
+    const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
+    auto launch_iter = [&](int j) -> apcg_status {
+        hipLaunchKernelGGL(k_seg_product, dim3(G), dim3(ST), 0, st, P, j & 1);
+        APCG_CHECK_LAUNCH("k_seg_product");
+        hipLaunchKernelGGL(k_seg_alpha, dim3(nsys), dim3(64), 0, st, P);
+        APCG_CHECK_LAUNCH("k_seg_alpha");
+        hipLaunchKernelGGL(k_seg_update, dim3(G), dim3(ST), 0, st, P, j & 1, norm_pre);
+        APCG_CHECK_LAUNCH("k_seg_update");
+        hipLaunchKernelGGL(k_seg_beta, dim3(nsys), dim3(64), 0, st, P, rtol, maxit);
+        APCG_CHECK_LAUNCH("k_seg_beta");
+        return APCG_SUCCESS;
+    };
+    uint64_t gh = fnv1a(&h, sizeof h);
+    const void *dsp = d_sys;
+    gh = fnv1a(&dsp, sizeof dsp, gh);
+    double prm[1] = {rtol};
+    int iprm[5] = {K, maxit, norm_pre, G, nsys};
+    gh = fnv1a(prm, sizeof prm, gh);
+    gh = fnv1a(iprm, sizeof iprm, gh);
+    apcg_status s;
+    if (maxit > 0) {
+        if (opts.mode == APCG_MODE_GRAPH) {
+            if (!sc->exec || sc->graph_hash != gh) {
+                if (sc->exec) {
+                    EventRef ev = event_get(dev);
+                    if (ev) hipEventRecord(ev->e, st);
+                    hipGraphExec_t oe = sc->exec;
+                    hipGraph_t og = sc->graph;
+                    defer_release({ev}, [oe, og, dev]() {
+                        hipSetDevice(dev);
+                        hipGraphExecDestroy(oe);
+                        hipGraphDestroy(og);
+                    });
+                    sc->exec = nullptr;
+                    sc->graph = nullptr;
+                }
+                APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                apcg_status cs = APCG_SUCCESS;
+                for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &g);
+                if (cs) {
+                    if (g) hipGraphDestroy(g);
+                    return cs;
+                }
+                if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(segmented)");
+                g_counters.kernel_launches -= 4 * K;
+                e = hipGraphInstantiate(&sc->exec, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    hipGraphDestroy(g);
+                    return hip_error(e, "hipGraphInstantiate(segmented)");
+                }
+                sc->graph = g;
+                sc->graph_hash = gh;
+            }
+        }
+        const int64_t periods = ((int64_t)maxit + K - 1) / K;
+        for (int64_t g = 0; g < periods; ++g) {
+            if (opts.mode == APCG_MODE_GRAPH) {
+                g_counters.graph_launches++;
+                APCG_HIP(hipGraphLaunch(sc->exec, st));
+            } else {
+                for (int j = 1; j <= K; ++j)
+                    if ((s = launch_iter(j))) return s;
+            }
+            const int slot = (int)(g % L);
+            if (!sc->poll_ev[slot]) {
+                sc->poll_ev[slot] = event_get(dev);
+                if (!sc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
+            }
+            g_counters.d2h_copies++;
+            APCG_HIP(hipMemcpyAsync(&sc->pinned[slot], sc->d_running, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            APCG_HIP(hipEventRecord(sc->poll_ev[slot]->e, st));
+            if (g >= L - 1) {
+                const int ps = (int)((g - (L - 1)) % L);
+                g_counters.host_polls++;
+                APCG_HIP(hipEventSynchronize(sc->poll_ev[ps]->e));
+                if (sc->pinned[ps] == 0) break;  // every system has stopped
+            }
+        }
+    }
+    hipLaunchKernelGGL(k_seg_finish, dim3((nsys + 63) / 64), dim3(64), 0, st, P, d_info);
+    APCG_CHECK_LAUNCH("k_seg_finish");
+    return APCG_SUCCESS;
+}
+
+}  // namespace apcg

@@ -178,6 +178,7 @@ apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
 void batch_cache_release(uint64_t ctx_id, int device);  // batched.hip
+void seg_cache_release(uint64_t ctx_id, int device);    // batched.hip
 void spmv_default_config(int32_t n, int64_t nnz, apcg_spmv_config *cfg);
 int32_t normalise_blocks(int32_t blocks, int64_t units);  // multiple of 8, <= kMaxBlocks
 

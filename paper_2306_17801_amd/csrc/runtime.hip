@@ -150,6 +150,7 @@ static apcg_status ctx_init(apcg_ctx c, int32_t device, int32_t type) {
 static void ctx_release_now(apcg_ctx c) {
     hipSetDevice(c->device);
     batch_cache_release(c->id, c->device);
+    seg_cache_release(c->id, c->device);
     for (auto &g : c->graphs) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         if (g.graph) hipGraphDestroy(g.graph);

@@ -71,12 +71,14 @@ def mixed_small_batch():
     return out
 
 
-@pytest.mark.parametrize("tb", [256, 512, 1024])
+@pytest.mark.parametrize("sched,tb", [(1, 256), (1, 512), (1, 1024), (2, 0)])
 @pytest.mark.parametrize("mode", [0, 1])
-def test_mixed_batch_matches_oracle(apcg, ctx, tb, mode):
-    print(f"case batched mixed tb={tb} mode={mode}", flush=True)
+def test_mixed_batch_matches_oracle(apcg, ctx, sched, tb, mode):
+    """Persistent (one workgroup per system, three block sizes) and segmented
+    schedules, graph and direct launches."""
+    print(f"case batched mixed sched={sched} tb={tb} mode={mode}", flush=True)
     systems = mixed_small_batch()
-    res, xs = run_batch(apcg, ctx, systems, 1e-10, 5000, batch_block_size=tb, mode=mode)
+    res, xs = run_batch(apcg, ctx, systems, 1e-10, 5000, batch_block_size=tb, mode=mode, batch_schedule=sched)
     for i, (s, r, x) in enumerate(zip(systems, res, xs)):
         ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=5000)
         assert r["status"] == ref.status, (i, r, ref)
@@ -86,22 +88,24 @@ def test_mixed_batch_matches_oracle(apcg, ctx, tb, mode):
     assert np.all(xs[-2] == 0)  # b = 0 -> x = 0
 
 
-def test_batched_initial_guess_and_maxit(apcg, ctx):
+@pytest.mark.parametrize("sched", [1, 2])
+def test_batched_initial_guess_and_maxit(apcg, ctx, sched):
     rng = np.random.default_rng(61)
     systems = [P._lognormal_system(rng, 2, int(rng.integers(8, 30)), 1.0, 1.0) for _ in range(6)]
     x0s = [rng.uniform(-1, 1, s.A.n) for s in systems]
-    res, xs = run_batch(apcg, ctx, systems, 0.0, 7, x0s=x0s)
+    res, xs = run_batch(apcg, ctx, systems, 0.0, 7, x0s=x0s, batch_schedule=sched)
     for s, r, x, x0 in zip(systems, res, xs, x0s):
         ref = oracle.pcg(s.A, s.b, x0=x0, rtol=0.0, maxit=7)
         assert r["status"] == oracle.MAXIT and r["iterations"] == 7
         assert rel(x, ref.x) <= 1e-12
 
 
-def test_batched_deterministic_and_graph_equals_direct(apcg, ctx):
+@pytest.mark.parametrize("sched", [1, 2])
+def test_batched_deterministic_and_graph_equals_direct(apcg, ctx, sched):
     systems = mixed_small_batch()[:20]
-    r1, x1 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=0)
-    r2, x2 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=1)
-    r3, x3 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=0)
+    r1, x1 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=0, batch_schedule=sched)
+    r2, x2 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=1, batch_schedule=sched)
+    r3, x3 = run_batch(apcg, ctx, systems, 1e-8, 5000, mode=0, batch_schedule=sched)
     assert r1 == r2 == r3
     assert all(np.array_equal(a, b) and np.array_equal(a, c) for a, b, c in zip(x1, x2, x3))
 
@@ -111,11 +115,12 @@ def batch256():
     return P.batch2d_lognormal(256, seed=3)
 
 
-def test_batch2d_first_sixteen_full_size(apcg, ctx, batch256):
+@pytest.mark.parametrize("sched", [1, 2])
+def test_batch2d_first_sixteen_full_size(apcg, ctx, batch256, sched):
     """The first 16 systems of the 256-system 2D batch, at full size,
     rtol 1e-10: iterations +-1 and rel <= 1e-9 per system."""
     systems = batch256[:16]
-    res, xs = run_batch(apcg, ctx, systems, 1e-10, 20000)
+    res, xs = run_batch(apcg, ctx, systems, 1e-10, 20000, batch_schedule=sched)
     for s, r, x in zip(systems, res, xs):
         ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=20000)
         assert r["status"] == apcg.APCG_SOLVE_CONVERGED
@@ -123,11 +128,12 @@ def test_batch2d_first_sixteen_full_size(apcg, ctx, batch256):
         assert rel(x, ref.x) <= 1e-9
 
 
-def test_batch2d_all_256_in_bench_configuration(apcg, ctx, batch256):
-    """All 256 systems at rtol 1e-8 in the launch configuration the benchmark
-    times: every system converges with a true residual within 1.5 rtol; eight
-    sampled systems match the oracle's iteration count +-1."""
-    res, xs = run_batch(apcg, ctx, batch256, 1e-8, 20000)
+@pytest.mark.parametrize("sched", [0, 1, 2])
+def test_batch2d_all_256_in_bench_configuration(apcg, ctx, batch256, sched):
+    """All 256 systems at rtol 1e-8 in the launch configurations the
+    benchmark times: every system converges with a true residual within
+    1.5 rtol; eight sampled systems match the oracle's iteration count +-1."""
+    res, xs = run_batch(apcg, ctx, batch256, 1e-8, 20000, batch_schedule=sched)
     for s, r, x in zip(batch256, res, xs):
         assert r["status"] == apcg.APCG_SOLVE_CONVERGED
         tr = np.linalg.norm(s.b - oracle.spmv(s.A, x)) / np.linalg.norm(s.b)
