@@ -1,0 +1,165 @@
+"""Oracle for the learned polynomial preconditioner -- TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 numpy: matrix features, the Gauss-quadrature data of the
+preconditioner loss, the loss itself, a 16 -> 64 -> 64 -> 9 tanh MLP with
+its analytic backward pass, and Adam (Kingma & Ba, 2015).  The HIP kernels
+are checked against these functions; nothing here is imported by the product
+path.
+
+Preconditioner: z = p(M) D^-1 r with M = D^-1 A and
+p(t) = sum_{j=0..8} c_j T_j(2 t / lmax - 1), lmax = the Gershgorin upper
+bound of M (the operator of or_poly_apply).
+
+Loss of one system, from m steps of Jacobi-PCG started at x0 = 0 (the
+CG-Lanczos relation gives nodes theta_i and weights w_i of the Gauss rule of
+the spectral measure of r0_hat = D^-1/2 b, Saad, Iterative Methods for Sparse
+Linear Systems, 2nd ed., Sec. 6.7.3):
+    L(c) = sum_i w_i (1 - theta_i p(theta_i))^2
+         + mu / Q sum_q max(0, eps - p(t_q))^2
+The first term is ||(I - p(M) M) r0_hat||^2 / ||r0_hat||^2, exact for m >= 10
+because the integrand has degree 18 <= 2m - 1; the second keeps p positive
+on Q points t_q spread over [0, lmax] (p > 0 on the spectrum makes the
+preconditioner SPD).  With G_jk = sum_i w_i theta_i^2 T_j(y_i) T_k(y_i),
+h_j = sum_i w_i theta_i T_j(y_i), y_i = 2 theta_i / lmax - 1 and
+sum_i w_i = 1: first term = c'G c - 2 h'c + 1.
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+
+from . import gershgorin, jacobi_inverse, pcg, gauss_nodes_weights, cheb_T
+
+DEG = 8
+NCOEF = DEG + 1
+NFEAT = 16
+M_STEPS = 12
+Q_GRID = 64
+
+
+def positivity_grid(q: int = Q_GRID) -> np.ndarray:
+    """Phi[q, j] = T_j(y_q), y_q = -1 + 2 q / (Q - 1): p at Q points spread
+    uniformly over [0, lmax]."""
+    y = -1.0 + 2.0 * np.arange(q) / (q - 1)
+    return cheb_T(DEG, y)
+
+
+def matrix_stats(A):
+    """Diagonal and off-diagonal statistics of a CSR matrix (row loops)."""
+    n = A.n
+    ld = np.empty(n)
+    aniso = []
+    for i in range(n):
+        a, b = A.rowptr[i], A.rowptr[i + 1]
+        cols, vals = A.col[a:b], A.val[a:b]
+        d = vals[cols == i][0]
+        ld[i] = math.log(d)
+        off = np.abs(vals[cols != i])
+        if off.size:
+            aniso.append(math.log(off.max() / off.min()))
+    return {
+        "log10_diag_contrast": (ld.max() - ld.min()) / math.log(10.0),
+        "std_log_diag": math.sqrt(float(np.mean((ld - np.mean(ld)) ** 2))),
+        "mean_log_offdiag_ratio": float(np.mean(aniso)) if aniso else 0.0,
+    }
+
+
+def lanczos_data(A, b, m: int = M_STEPS):
+    """m steps of Jacobi-PCG from x0 = 0 (rtol = 0): alpha, beta, and the
+    relative residual after the last step."""
+    r = pcg(A, b, rtol=0.0, maxit=m, history=True)
+    k = r.its
+    return r.alpha[:k], r.beta[: max(k - 1, 0)], r.res / r.ref
+
+
+def features(A, b):
+    """The 16 features, in order:
+      0 log10 n, 1 nnz/n, 2 Gershgorin lower, 3 Gershgorin upper (of D^-1 A),
+      4 log10(max diag / min diag), 5 std of ln diag, 6 mean over rows of
+      ln(max |offdiag| / min |offdiag|), 7-9 the three smallest and 10-12 the
+      three largest Ritz values / Gershgorin upper, 13 log10(theta_max /
+      theta_min), 14 log10 of the relative residual after the steps,
+      15 log10(theta_min / Gershgorin upper)."""
+    lo, hi = gershgorin(A)
+    st = matrix_stats(A)
+    al, be, relres = lanczos_data(A, b)
+    th, _ = gauss_nodes_weights(al, np.append(be, 0.0)[: al.size])
+    th = np.sort(th)
+    f = np.array([
+        math.log10(A.n), A.nnz / A.n, lo, hi,
+        st["log10_diag_contrast"], st["std_log_diag"], st["mean_log_offdiag_ratio"],
+        th[0] / hi, th[1] / hi, th[2] / hi, th[-3] / hi, th[-2] / hi, th[-1] / hi,
+        math.log10(th[-1] / th[0]), math.log10(relres), math.log10(th[0] / hi),
+    ])
+    return f
+
+
+def quadrature_gram(alpha, beta, lmax):
+    """G (9 x 9), h (9): the quadratic form of the loss's first term."""
+    th, w = gauss_nodes_weights(alpha, np.append(beta, 0.0)[: len(alpha)])
+    Ty = cheb_T(DEG, 2.0 * th / lmax - 1.0)          # [m, 9]
+    G = (Ty * (w * th * th)[:, None]).T @ Ty
+    h = Ty.T @ (w * th)
+    return G, h
+
+
+def loss_terms(c, G, h, Phi, mu=1.0, eps=0.05):
+    """Loss of one system and dL/dc."""
+    c = np.asarray(c, dtype=np.float64)
+    q = Phi @ c
+    viol = np.maximum(0.0, eps - q)
+    Q = Phi.shape[0]
+    L = c @ G @ c - 2.0 * h @ c + 1.0 + mu / Q * np.sum(viol * viol)
+    dc = 2.0 * G @ c - 2.0 * h - 2.0 * mu / Q * (Phi.T @ viol)
+    return L, dc
+
+
+# ---------------------------------------------------------------------------
+# MLP 16 -> 64 -> 64 -> 9, tanh, FP64
+# ---------------------------------------------------------------------------
+SHAPES = [("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (9, 64)), ("b3", (9,))]
+
+
+def mlp_forward(params, X):
+    """X [B, 16] -> C [B, 9] and the activations for the backward pass."""
+    H1 = np.tanh(X @ params["W1"].T + params["b1"])
+    H2 = np.tanh(H1 @ params["W2"].T + params["b2"])
+    C = H2 @ params["W3"].T + params["b3"]
+    return C, (X, H1, H2)
+
+
+def mlp_backward(params, cache, dC):
+    """Gradients of sum_b L_b with respect to every parameter, given dL/dC."""
+    X, H1, H2 = cache
+    g = {"W3": dC.T @ H2, "b3": dC.sum(0)}
+    dA2 = (dC @ params["W3"]) * (1.0 - H2 * H2)
+    g["W2"] = dA2.T @ H1
+    g["b2"] = dA2.sum(0)
+    dA1 = (dA2 @ params["W2"]) * (1.0 - H1 * H1)
+    g["W1"] = dA1.T @ X
+    g["b1"] = dA1.sum(0)
+    return g
+
+
+def batch_loss(params, X, Gs, hs, Phi, mu=1.0, eps=0.05):
+    """Mean loss over the batch and its parameter gradients."""
+    C, cache = mlp_forward(params, X)
+    B = X.shape[0]
+    dC = np.zeros_like(C)
+    tot = 0.0
+    for b in range(B):
+        L, d = loss_terms(C[b], Gs[b], hs[b], Phi, mu, eps)
+        tot += L
+        dC[b] = d / B
+    return tot / B, mlp_backward(params, cache, dC)
+
+
+def adam_step(params, grads, m, v, t, lr=1e-3, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (t is the 1-based step count); in place."""
+    for k in params:
+        m[k] = b1 * m[k] + (1 - b1) * grads[k]
+        v[k] = b2 * v[k] + (1 - b2) * grads[k] * grads[k]
+        mh = m[k] / (1 - b1 ** t)
+        vh = v[k] / (1 - b2 ** t)
+        params[k] = params[k] - lr * mh / (np.sqrt(vh) + eps)

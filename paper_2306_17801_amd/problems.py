@@ -287,3 +287,23 @@ def random_csr(n: int, max_per_row: int, seed: int, empty_rows: bool = True) -> 
         cols[rowptr[i]:rowptr[i + 1]] = c
     vals = rng.uniform(-1.0, 1.0, int(rowptr[-1]))
     return CSR(n=n, rowptr=rowptr.astype(np.int32), col=cols, val=vals)
+
+
+# --------------------------------------------------------------------------
+# Seeded initial parameters of the 16 -> 64 -> 64 -> 9 MLP
+# --------------------------------------------------------------------------
+MLP_SHAPES = [("W1", (64, 16)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("W3", (9, 64)), ("b3", (9,))]
+
+
+def mlp_initial_params(seed: int = 7) -> dict:
+    """Glorot-uniform weights, zero biases, drawn in the order of MLP_SHAPES
+    (float64; the GPU side takes float32 copies of the same numbers)."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for name, shape in MLP_SHAPES:
+        if name.startswith("W"):
+            lim = math.sqrt(6.0 / (shape[0] + shape[1]))
+            out[name] = rng.uniform(-lim, lim, shape)
+        else:
+            out[name] = np.zeros(shape)
+    return out

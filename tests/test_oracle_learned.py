@@ -1,0 +1,132 @@
+"""Pins for the learned-preconditioner oracle (CPU only)."""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from oracle import learned as LO
+from paper_2306_17801_amd import problems as P
+
+
+def small_system(seed=0, side=7, sigma=1.0, aniso=5.0):
+    return P._lognormal_system(np.random.default_rng(seed), 3, side, sigma, aniso)
+
+
+def dense_hat(A, b):
+    D = A.to_scipy().toarray()
+    d = np.diag(D)
+    Ah = D / np.sqrt(np.outer(d, d))
+    r0 = b / np.sqrt(d)
+    return Ah, r0 / np.linalg.norm(r0)
+
+
+def test_quadrature_loss_is_exact_against_dense():
+    """With 12 Lanczos steps the Gauss rule integrates the degree-18 loss
+    integrand exactly: c'Gc - 2h'c + 1 = ||(I - p(M) M) r0_hat||^2."""
+    s = small_system()
+    lo, hi = oracle.gershgorin(s.A)
+    al, be, _ = LO.lanczos_data(s.A, s.b)
+    assert al.size == 12
+    G, h = LO.quadrature_gram(al, be, hi)
+    Ah, r0 = dense_hat(s.A, s.b)
+    lam, U = np.linalg.eigh(Ah)
+    rng = np.random.default_rng(1)
+    for _ in range(3):
+        c = rng.standard_normal(9)
+        p = np.polynomial.chebyshev.chebval(2 * lam / hi - 1, c)
+        resid = U @ ((1 - lam * p) * (U.T @ r0))
+        assert c @ G @ c - 2 * h @ c + 1 == pytest.approx(resid @ resid, rel=1e-9)
+
+
+def test_quadratic_minimiser_equals_krylov_least_squares():
+    s = small_system(seed=3)
+    lo, hi = oracle.gershgorin(s.A)
+    al, be, _ = LO.lanczos_data(s.A, s.b)
+    G, h = LO.quadrature_gram(al, be, hi)
+    c_star = np.linalg.solve(G, h)
+    Ah, r0 = dense_hat(s.A, s.b)
+    lam, U = np.linalg.eigh(Ah)
+    cols = []
+    for j in range(9):
+        e = np.zeros(9)
+        e[j] = 1
+        pj = np.polynomial.chebyshev.chebval(2 * lam / hi - 1, e)
+        cols.append(U @ (lam * pj * (U.T @ r0)))
+    K = np.array(cols).T
+    c_ls, *_ = np.linalg.lstsq(K, r0, rcond=None)
+    best = np.sum((r0 - K @ c_ls) ** 2)
+    assert c_star @ G @ c_star - 2 * h @ c_star + 1 == pytest.approx(best, rel=1e-6, abs=1e-13)
+
+
+def test_loss_gradient_central_differences():
+    s = small_system(seed=4)
+    lo, hi = oracle.gershgorin(s.A)
+    al, be, _ = LO.lanczos_data(s.A, s.b)
+    G, h = LO.quadrature_gram(al, be, hi)
+    Phi = LO.positivity_grid()
+    c = np.random.default_rng(2).standard_normal(9) * 0.3  # some grid points violate positivity
+    L, dc = LO.loss_terms(c, G, h, Phi)
+    assert np.any(Phi @ c < 0.05)
+    for j in range(9):
+        e = np.zeros(9)
+        e[j] = 1e-6
+        num = (LO.loss_terms(c + e, G, h, Phi)[0] - LO.loss_terms(c - e, G, h, Phi)[0]) / 2e-6
+        assert dc[j] == pytest.approx(num, rel=1e-6, abs=1e-8)
+
+
+def test_mlp_gradients_central_differences():
+    rng = np.random.default_rng(5)
+    params = P.mlp_initial_params(11)
+    for k in params:
+        params[k] = params[k] + 0.1 * rng.standard_normal(params[k].shape)
+    B = 5
+    X = rng.standard_normal((B, 16))
+    Gs, hs = [], []
+    for b in range(B):
+        M = rng.standard_normal((9, 9))
+        Gs.append(M @ M.T + np.eye(9))
+        hs.append(rng.standard_normal(9))
+    Phi = LO.positivity_grid()
+    L, g = LO.batch_loss(params, X, Gs, hs, Phi)
+    for k, shape in LO.SHAPES:
+        for idx in [tuple(rng.integers(0, s) for s in shape) for _ in range(4)]:
+            p2 = {kk: vv.copy() for kk, vv in params.items()}
+            hstep = 1e-6 * max(1.0, abs(params[k][idx]))
+            p2[k][idx] += hstep
+            Lp = LO.batch_loss(p2, X, Gs, hs, Phi)[0]
+            p2[k][idx] -= 2 * hstep
+            Lm = LO.batch_loss(p2, X, Gs, hs, Phi)[0]
+            num = (Lp - Lm) / (2 * hstep)
+            assert g[k][idx] == pytest.approx(num, rel=1e-6, abs=1e-9), (k, idx)
+
+
+def test_adam_first_step_is_signed_learning_rate():
+    params = {"w": np.array([1.0, -2.0, 3.0])}
+    grads = {"w": np.array([0.5, -4.0, 1e-3])}
+    m = {"w": np.zeros(3)}
+    v = {"w": np.zeros(3)}
+    LO.adam_step(params, grads, m, v, 1, lr=0.01)
+    assert np.allclose(params["w"], [1.0 - 0.01, -2.0 + 0.01, 3.0 - 0.01], atol=1e-7)
+
+
+def test_features_on_constant_coefficient_laplacian():
+    n = 10
+    A = P.laplace_3d(n)
+    b = np.random.default_rng(6).uniform(-1, 1, A.n)
+    f = LO.features(A, b)
+    assert f[0] == pytest.approx(3.0)
+    assert f[1] == pytest.approx(7 - 6 / n)
+    assert (f[2], f[3]) == (0.0, 2.0)
+    assert f[4] == 0.0 and abs(f[5]) <= 1e-12 and f[6] == 0.0
+    lam_min = (6 - 6 * math.cos(math.pi / (n + 1))) / 6
+    lam_max = (6 + 6 * math.cos(math.pi / (n + 1))) / 6
+    # Ritz values interlace: inside the exact spectrum of D^-1 A, ascending
+    assert lam_min / 2 - 1e-12 <= f[7] <= f[8] <= f[9] <= f[10] <= f[11] <= f[12] <= lam_max / 2 + 1e-12
+    assert f[14] < 0 and f[15] == pytest.approx(math.log10(f[7]))
+
+
+def test_initial_params_shapes_and_scale():
+    p = P.mlp_initial_params(7)
+    assert sum(v.size for v in p.values()) == 5833
+    assert np.all(p["b1"] == 0) and abs(p["W2"]).max() <= math.sqrt(6 / 128)
