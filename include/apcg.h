@@ -377,6 +377,86 @@ apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A
                                    const apcg_vec *x, double rtol, int32_t maxit, const apcg_solve_opts *opts,
                                    apcg_info info);
 
+/* ---------------------------------------------------------------------- */
+/* Learned polynomial preconditioner                                       */
+/*                                                                         */
+/* Preconditioner z = p(D^-1 A) D^-1 r with                                */
+/*   p(t) = sum_{j=0..8} c_j T_j(2 t / lmax - 1),                          */
+/* lmax = the Gershgorin upper bound of D^-1 A, inside flexible CG         */
+/* (FCG(1)) -- the PCG loop of Section 3.3 with a variable preconditioner.  */
+/* A 16 -> 64 -> 64 -> 9 tanh MLP (FP32) maps cheap matrix features to the */
+/* nine coefficients.  Parameters are one float array of 5833 entries:     */
+/* W1[64][16], b1[64], W2[64][64], b2[64], W3[9][64], b3[9] (row-major).   */
+/* These calls take raw device pointers and are ordered on ctx only.       */
+/* ---------------------------------------------------------------------- */
+
+/* Features and loss data of one system (n >= 1, Jacobi diagonal > 0):
+ * dev_feat[16] (float): log10 n, nnz/n, Gershgorin lower and upper bounds of
+ *   D^-1 A, log10(max diag / min diag), std of ln diag, mean over rows of
+ *   ln(max |offdiag| / min |offdiag|), the three smallest and three largest
+ *   Ritz values / upper bound, log10(largest / smallest Ritz value), log10
+ *   of the relative residual after the steps, log10(smallest Ritz / upper);
+ * dev_G[81], dev_h[9] (float): the quadratic form of the loss
+ *   sum_i w_i (1 - th_i p(th_i))^2 = c'G c - 2 h'c + 1 over the Gauss rule
+ *   (nodes th_i, weights w_i) of the spectral measure of D^-1/2 b, exact for
+ *   the degree-18 integrand;
+ * dev_lmax (double): the Gershgorin upper bound.
+ * Runs 12 Jacobi-PCG iterations from x0 = 0 on ctx's workspace (the
+ * CG-Lanczos relation turns their alpha, beta into the Ritz values and Gauss
+ * weights) plus two passes over the rows. */
+apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, float *dev_G, float *dev_h,
+                             double *dev_lmax);
+
+/* Standardises the rows of dev_X[B][16] in place with the column means and
+ * standard deviations dev_mean[16], dev_std[16]; compute_stats != 0 first
+ * computes them from X (two passes; a zero deviation is replaced by 1). */
+apcg_status apcg_mlp_standardize(apcg_ctx ctx, float *dev_X, int32_t B, float *dev_mean, float *dev_std,
+                                 int32_t compute_stats);
+
+/* dev_C[B][9] = MLP(dev_X[B][16]). */
+apcg_status apcg_mlp_forward(apcg_ctx ctx, const float *dev_params, const float *dev_X, int32_t B, float *dev_C);
+
+/* Mean loss over B systems (dev_loss[1]) and its gradient with respect to
+ * the 5833 parameters (dev_grad), given each system's dev_G[B][81] and
+ * dev_h[B][9]; penalty weight mu and floor eps of the positivity term
+ * mu / 64 sum_q max(0, eps - p(t_q))^2 over 64 points of [0, lmax]. */
+apcg_status apcg_mlp_loss_grad(apcg_ctx ctx, const float *dev_params, const float *dev_X, const float *dev_G,
+                               const float *dev_h, int32_t B, float mu, float eps, float *dev_loss, float *dev_grad);
+
+/* One Adam step (Kingma & Ba; beta1 0.9, beta2 0.999, eps 1e-8) on the
+ * parameters with the loss gradient above; t >= 1 is the step number;
+ * dev_adam_m, dev_adam_v (5833 each) hold the moment estimates. */
+apcg_status apcg_mlp_train_step(apcg_ctx ctx, float *dev_params, float *dev_adam_m, float *dev_adam_v, int32_t t,
+                                float lr, const float *dev_X, const float *dev_G, const float *dev_h, int32_t B,
+                                float mu, float eps, float *dev_loss);
+
+typedef struct apcg_fcg_opts {
+    int32_t stall_min;  /* stall window floor (iterations)                    */
+    int32_t fallback;   /* 1: continue with Jacobi-PCG after a breakdown,     */
+                        /*    a stall or a non-positive polynomial            */
+    double stall_frac;  /* window = max(stall_min, stall_frac * k)            */
+    int32_t reserved[4];
+} apcg_fcg_opts;
+
+/* stall_min 50, stall_frac 0.1, fallback 1. */
+apcg_status apcg_fcg_opts_default(apcg_fcg_opts *opts);
+
+/* Solves A x = b with FCG(1) and the polynomial preconditioner above
+ * (coefficients dev_coeffs[9], float, and dev_lmax, double, in device
+ * memory, e.g. from apcg_mlp_forward and apcg_pc_features).  p is first
+ * checked on 1024 points of [0, lmax]; if it is not positive there, or if
+ * the iteration breaks down (p.Ap <= 0, r.z <= 0) or stalls (no new minimum
+ * of ||r|| within the window), Jacobi-PCG continues from the current x for
+ * the remaining iterations when fopts->fallback is set (status then carries
+ * APCG_SOLVE_FALLBACK and the reason; iterations count both phases;
+ * fcg_iterations the flexible ones).  Stopping: ||r|| <= rtol ||b||.
+ * opts: mode (graph/stream), iters_per_graph, lookahead and x0_is_zero as
+ * for apcg_ksp_solve.  The host waits once, at the end of the flexible
+ * phase, to decide on the fallback. */
+apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                                    const float *dev_coeffs, const double *dev_lmax, const apcg_solve_opts *opts,
+                                    const apcg_fcg_opts *fopts, apcg_info info, int32_t info_index);
+
 /* Mean device time (microseconds) and launch count of the product kernel
  * (kind 0: fused SpMV + p.Ap) and the update kernel (kind 1: x, r update
  * with r.z and ||r||^2) measured by the last solve on ctx that ran with

@@ -75,7 +75,7 @@ def lib():
         L.or_pcg.restype = i32
         L.or_poly_apply.argtypes = [i32, P, P, P, P, f64, i32, P, P, P]
         L.or_poly_apply.restype = i32
-        L.or_fcg_poly.argtypes = [i32, P, P, P, P, P, f64, i32, i32, P, f64, i32, f64, i32, P, P, P, P]
+        L.or_fcg_poly.argtypes = [i32, P, P, P, P, P, f64, i32, i32, P, f64, i32, f64, i32, i32, P, P, P, P]
         L.or_fcg_poly.restype = i32
         _lib = L
     return _lib
@@ -178,9 +178,9 @@ def poly_apply(A, dinv, lmax, coeffs, r):
 
 
 def fcg_poly(A, b, coeffs, lmax, x0=None, rtol=1e-8, maxit=None, stall_min=50, stall_frac=0.1,
-             fallback=True):
-    """FCG(1) with the Chebyshev polynomial preconditioner and Jacobi-PCG
-    fallback (see or_fcg_poly)."""
+             fallback=True, precheck=True):
+    """FCG(1) with the Chebyshev polynomial preconditioner, the positivity
+    pre-check and the Jacobi-PCG fallback (see or_fcg_poly)."""
     rp, c, v = _csr(A)
     n = A.n
     maxit = n if maxit is None else int(maxit)
@@ -191,7 +191,8 @@ def fcg_poly(A, b, coeffs, lmax, x0=None, rtol=1e-8, maxit=None, stall_min=50, s
     res, ref = ctypes.c_double(), ctypes.c_double()
     st = lib().or_fcg_poly(n, _p(rp), _p(c), _p(v), _p(b), _p(x), float(rtol), maxit, coeffs.size - 1,
                            _p(coeffs), float(lmax), int(stall_min), float(stall_frac), int(bool(fallback)),
-                           ctypes.byref(its), ctypes.byref(res), ctypes.byref(ref), ctypes.byref(fits))
+                           int(bool(precheck)), ctypes.byref(its), ctypes.byref(res), ctypes.byref(ref),
+                           ctypes.byref(fits))
     return PCGResult(x=x, its=its.value, fcg_its=fits.value, status=st, res=res.value, ref=ref.value)
 
 

@@ -271,11 +271,33 @@ int32_t or_poly_apply(int32_t n, const int32_t *rowptr, const int32_t *col, cons
  * With fallback != 0 a breakdown or stall restarts plain Jacobi-PCG from the
  * current x for the remaining iteration budget (FALLBACK is then set and the
  * iteration counts add up).  The stopping norm is the unpreconditioned one.
+ * With precheck != 0, p(t) = sum_j c_j T_j(2t/lmax - 1) is evaluated first at
+ * t = lmax q / 1023, q = 0..1023; a value <= 0 means the preconditioner is
+ * not SPD on the spectrum's enclosure [0, lmax], which counts as a
+ * BREAKDOWN_RZ before the first iteration.
  */
+static int poly_positive(int32_t deg, const double *c, double lmax)
+{
+    for (int q = 0; q < 1024; ++q) {
+        double y = 2.0 * (lmax * q / 1023.0) / lmax - 1.0;
+        double t0 = 1.0, t1 = y, p = c[0];
+        if (deg >= 1) p += c[1] * t1;
+        for (int32_t j = 2; j <= deg; ++j) {
+            double t2 = 2.0 * y * t1 - t0;
+            p += c[j] * t2;
+            t0 = t1;
+            t1 = t2;
+        }
+        if (!(p > 0.0)) return 0;
+    }
+    return 1;
+}
+
 int32_t or_fcg_poly(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
                     const double *b, double *x, double rtol, int32_t maxit, int32_t deg,
                     const double *c, double lmax, int32_t stall_min, double stall_frac,
-                    int32_t fallback, int32_t *its, double *res, double *ref, int32_t *fcg_its)
+                    int32_t fallback, int32_t precheck, int32_t *its, double *res, double *ref,
+                    int32_t *fcg_its)
 {
     size_t nb = (size_t)(n > 0 ? n : 1) * sizeof(double);
     double *dinv = malloc(nb), *r = malloc(nb), *z = malloc(nb), *p = malloc(nb), *w = malloc(nb);
@@ -299,11 +321,16 @@ int32_t or_fcg_poly(int32_t n, const int32_t *rowptr, const int32_t *col, const 
     }
     if (!isfinite(*res) || !isfinite(*ref)) { status = OR_NAN; goto done; }
     if (*res <= rtol * *ref) { status = OR_CONVERGED; goto done; }
-    if (or_poly_apply(n, rowptr, col, val, dinv, lmax, deg, c, r, z) != 0) { status = OR_SETUP_ERROR; goto done; }
-    double rho = or_dot(n, r, z);
-    if (!(rho > 0.0)) {
-        if (!isfinite(rho)) { status = OR_NAN; goto done; }
+    double rho = 0.0;
+    if (precheck && !poly_positive(deg, c, lmax)) {
         failed = OR_BREAKDOWN_RZ;
+    } else {
+        if (or_poly_apply(n, rowptr, col, val, dinv, lmax, deg, c, r, z) != 0) { status = OR_SETUP_ERROR; goto done; }
+        rho = or_dot(n, r, z);
+        if (!(rho > 0.0)) {
+            if (!isfinite(rho)) { status = OR_NAN; goto done; }
+            failed = OR_BREAKDOWN_RZ;
+        }
     }
     for (int32_t i = 0; i < n; ++i) p[i] = z[i];
     double best = *res;

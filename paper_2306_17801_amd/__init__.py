@@ -314,6 +314,69 @@ def apcg_ksp_solve_batched(ctx, A_list, b_list, x_list, rtol: float, maxit: int,
                                                                 float(rtol), int(maxit), po, _h(info)))
 
 
+# ------------------------------------------------------------------ learned preconditioner
+
+def _dptr(t, dtype):
+    import torch
+
+    want = {"float32": torch.float32, "float64": torch.float64}[dtype]
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.dtype == want and t.is_contiguous()):
+        raise TypeError(f"expected a contiguous {dtype} GPU tensor")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def apcg_pc_features(ctx, A, b, feat, G, h, lmax) -> None:
+    """feat: float32[16], G: float32[81], h: float32[9], lmax: float64[1] (GPU tensors)."""
+    check("apcg_pc_features", _L().apcg_pc_features(_h(ctx), _h(A), _h(b), _dptr(feat, "float32"),
+                                                    _dptr(G, "float32"), _dptr(h, "float32"),
+                                                    _dptr(lmax, "float64")))
+
+
+def apcg_mlp_standardize(ctx, X, mean, std, compute_stats: bool) -> None:
+    check("apcg_mlp_standardize", _L().apcg_mlp_standardize(_h(ctx), _dptr(X, "float32"), X.shape[0],
+                                                            _dptr(mean, "float32"), _dptr(std, "float32"),
+                                                            int(bool(compute_stats))))
+
+
+def apcg_mlp_forward(ctx, params, X, C) -> None:
+    check("apcg_mlp_forward", _L().apcg_mlp_forward(_h(ctx), _dptr(params, "float32"), _dptr(X, "float32"),
+                                                    X.shape[0], _dptr(C, "float32")))
+
+
+def apcg_mlp_loss_grad(ctx, params, X, G, h, loss, grad, mu=1.0, eps=0.05) -> None:
+    check("apcg_mlp_loss_grad", _L().apcg_mlp_loss_grad(_h(ctx), _dptr(params, "float32"), _dptr(X, "float32"),
+                                                        _dptr(G, "float32"), _dptr(h, "float32"), X.shape[0],
+                                                        float(mu), float(eps), _dptr(loss, "float32"),
+                                                        _dptr(grad, "float32")))
+
+
+def apcg_mlp_train_step(ctx, params, m, v, t: int, lr: float, X, G, h, loss, mu=1.0, eps=0.05) -> None:
+    check("apcg_mlp_train_step", _L().apcg_mlp_train_step(_h(ctx), _dptr(params, "float32"), _dptr(m, "float32"),
+                                                          _dptr(v, "float32"), int(t), float(lr),
+                                                          _dptr(X, "float32"), _dptr(G, "float32"),
+                                                          _dptr(h, "float32"), X.shape[0], float(mu), float(eps),
+                                                          _dptr(loss, "float32")))
+
+
+def apcg_fcg_opts_default(**overrides):
+    o = _capi.apcg_fcg_opts()
+    check("apcg_fcg_opts_default", _L().apcg_fcg_opts_default(ctypes.byref(o)))
+    for k, v in overrides.items():
+        setattr(o, k, v)
+    return o
+
+
+def apcg_ksp_solve_fcg_poly(ctx, A, b, x, rtol: float, maxit: int, coeffs, lmax, opts=None, fopts=None,
+                            info=None, info_index: int = 0) -> None:
+    """coeffs: float32[9] GPU tensor, lmax: float64[1] GPU tensor."""
+    po = ctypes.byref(opts) if opts is not None else None
+    pf = ctypes.byref(fopts) if fopts is not None else None
+    check("apcg_ksp_solve_fcg_poly", _L().apcg_ksp_solve_fcg_poly(_h(ctx), _h(A), _h(b), _h(x), float(rtol),
+                                                                  int(maxit), _dptr(coeffs, "float32"),
+                                                                  _dptr(lmax, "float64"), po, pf, _h(info),
+                                                                  int(info_index)))
+
+
 # ------------------------------------------------------------------ timers
 
 def apcg_timer_create() -> int:

@@ -85,6 +85,10 @@ class apcg_solve_info(ctypes.Structure):
                 "res_norm": self.res_norm, "ref_norm": self.ref_norm}
 
 
+class apcg_fcg_opts(ctypes.Structure):
+    _fields_ = [("stall_min", c_i32), ("fallback", c_i32), ("stall_frac", c_f64), ("reserved", c_i32 * 4)]
+
+
 class apcg_counters(ctypes.Structure):
     _fields_ = [("kernel_launches", c_i64), ("graph_launches", c_i64), ("host_syncs", c_i64),
                 ("host_polls", c_i64), ("d2h_copies", c_i64), ("h2d_copies", c_i64), ("stream_waits", c_i64),
@@ -144,6 +148,15 @@ SIGNATURES = {
     "apcg_ksp_solve": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts), c_vp, c_i32],
     "apcg_ksp_solve_batched": [c_vp, c_i32, P(c_vp), P(c_vp), P(c_vp), c_f64, c_i32, P(apcg_solve_opts), c_vp],
     "apcg_ctx_kernel_times": [c_vp, c_i32, P(c_f64), P(c_i32)],
+    "apcg_pc_features": [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp],
+    "apcg_mlp_standardize": [c_vp, c_vp, c_i32, c_vp, c_vp, c_i32],
+    "apcg_mlp_forward": [c_vp, c_vp, c_vp, c_i32, c_vp],
+    "apcg_mlp_loss_grad": [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, ctypes.c_float, ctypes.c_float, c_vp, c_vp],
+    "apcg_mlp_train_step": [c_vp, c_vp, c_vp, c_vp, c_i32, ctypes.c_float, c_vp, c_vp, c_vp, c_i32, ctypes.c_float,
+                            ctypes.c_float, c_vp],
+    "apcg_fcg_opts_default": [P(apcg_fcg_opts)],
+    "apcg_ksp_solve_fcg_poly": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, P(apcg_solve_opts),
+                                P(apcg_fcg_opts), c_vp, c_i32],
     "apcg_timer_create": [P(c_vp)],
     "apcg_timer_destroy": [c_vp],
     "apcg_timer_start": [c_vp, c_vp],

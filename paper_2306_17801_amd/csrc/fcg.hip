@@ -1,0 +1,623 @@
+// fcg.hip -- flexible CG, FCG(1), with a degree-8 Chebyshev polynomial
+// preconditioner, and its fallback to Jacobi-PCG.
+//
+// Preconditioner: z = P r = sum_{j=0..8} c_j T_j(Y) v with v = D^-1 r and
+// Y = (2/lmax) D^-1 A - I (lmax = the Gershgorin upper bound of D^-1 A),
+// evaluated by Clenshaw's recurrence b_j = c_j v + 2 Y b_{j+1} - b_{j+2}
+// (b_9 = b_10 = 0), z = c_0 v + Y b_1 - b_2: eight products with A.  FCG(1)
+// (Notay 2000; Golub & Ye 1999): the PCG loop of Section 3.3 with
+// beta = -(z_{k+1} . w_k) / (p_k . w_k), which keeps the search directions
+// A-orthogonal when P is applied inexactly (FP32-derived coefficients).
+//
+// One iteration is 13 kernels: product, alpha, update, check, eight
+// Clenshaw steps (the last forms z and the partials of r.z and z.w), beta.
+// The scalar steps run in one-workgroup kernels that add the producer's
+// partials in a fixed order; the stop flag makes every later kernel a no-op.
+// Before the first iteration p is evaluated on 1024 points of [0, lmax]; a
+// value <= 0 (the preconditioner would not be SPD) stops the flexible phase
+// at once.  A breakdown, that rejection, or a stall (no new minimum of ||r||
+// in the last max(stall_min, stall_frac * k) iterations) hands over to
+// Jacobi-PCG from the current x when the fallback is enabled.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace apcg {
+namespace {
+
+constexpr int TBF = 256;
+constexpr int DEG = 8;
+
+struct FcgState {
+    double c[DEG + 1];
+    double lmax;
+    double rho, delta, alpha, beta;
+    double res, ref, best_res, rtol;
+    double stall_frac;
+    int32_t its, best_its, maxit, stall_min;
+    int32_t status, flag, zero_x, reject;
+};
+static_assert(sizeof(FcgState) <= 512, "FCG state exceeds its allocation");
+
+__device__ __forceinline__ double pdir_f(double z, double beta, double pold) { return fma(beta, pold, z); }
+
+// sum_j a_ij u_j for row i; rows of up to 8 entries gather before adding.
+template <typename F>
+__device__ __forceinline__ double row_dot(const int32_t *__restrict__ col, const double *__restrict__ val, int s,
+                                          int e, int row, F u) {
+    const int len = e - s;
+    double sum = 0.0;
+    if (len <= 8) {
+        int jj[8];
+        double aa[8], uj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool in = q < len;
+            jj[q] = in ? col[s + q] : row;
+            aa[q] = in ? val[s + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) uj[q] = u(jj[q]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < len) sum = fma(aa[q], uj[q], sum);
+    } else {
+        for (int k = s; k < e; ++k) sum = fma(val[k], u(col[k]), sum);
+    }
+    return sum;
+}
+
+__global__ __launch_bounds__(TBF) void k_fcg_init(int32_t n, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  const double *__restrict__ b, double *__restrict__ x,
+                                                  double *__restrict__ r, double *__restrict__ dinv,
+                                                  double *__restrict__ pold, double *part, int64_t per_block,
+                                                  int x0_zero) {
+    const dev::Chunk c = dev::block_chunk(n, per_block);
+    double v[3] = {0.0, 0.0, 0.0};  // ||b||^2, ||r||^2, bad diagonals
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBF) {
+        double d = 0.0, ax = 0.0;
+        bool found = false;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const int j = col[k];
+            if (j == (int)i) {
+                d = val[k];
+                found = true;
+            }
+            if (!x0_zero) ax = fma(val[k], x[j], ax);
+        }
+        const bool ok = found && d > 0.0;
+        v[2] += ok ? 0.0 : 1.0;
+        const double bi = b[i];
+        const double ri = x0_zero ? bi : bi - ax;
+        r[i] = ri;
+        dinv[i] = ok ? 1.0 / d : 0.0;
+        pold[i] = 0.0;
+        if (x0_zero) x[i] = 0.0;
+        v[0] = fma(bi, bi, v[0]);
+        v[1] = fma(ri, ri, v[1]);
+    }
+    dev::store_partials<TBF, 3>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Clenshaw evaluation of p at one point t (scalar).
+__device__ double poly_at(const double *c, double t, double lmax) {
+    const double y = 2.0 * t / lmax - 1.0;
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = DEG; j >= 1; --j) {
+        const double b0 = c[j] + 2.0 * y * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return c[0] + y * b1 - b2;
+}
+
+__global__ __launch_bounds__(64) void k_fcg_init_final(FcgState *st, const double *part, int G, const float *coef,
+                                                       const double *lmax, double rtol, int32_t maxit,
+                                                       int32_t stall_min, double stall_frac) {
+    double v[3];
+    dev::reduce_partials<64, 3>(part, G, v);
+    __shared__ double cc[DEG + 1];
+    __shared__ int bad_point;
+    if (threadIdx.x <= DEG) cc[threadIdx.x] = (double)coef[threadIdx.x];
+    if (threadIdx.x == 0) bad_point = 0;
+    __syncthreads();
+    const double lm = *lmax;
+    // positivity of p on [0, lmax]: 1024 points
+    for (int q = threadIdx.x; q < 1024; q += 64)
+        if (!(poly_at(cc, lm * q / 1023.0, lm) > 0.0)) atomicOr(&bad_point, 1);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    FcgState s;
+    for (int j = 0; j <= DEG; ++j) s.c[j] = cc[j];
+    s.lmax = lm;
+    s.ref = sqrt(v[0]);
+    s.res = sqrt(v[1]);
+    s.best_res = s.res;
+    s.rtol = rtol;
+    s.stall_frac = stall_frac;
+    s.its = 0;
+    s.best_its = 0;
+    s.maxit = maxit;
+    s.stall_min = stall_min;
+    s.rho = s.delta = s.alpha = s.beta = 0.0;
+    s.zero_x = 0;
+    s.reject = 0;
+    int status = 0;
+    if (v[2] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
+    else if (s.ref == 0.0) {
+        status = APCG_SOLVE_CONVERGED;
+        s.zero_x = 1;
+        s.res = 0.0;
+    } else if (!isfinite(s.res) || !isfinite(s.ref)) status = APCG_SOLVE_NAN;
+    else if (s.res <= rtol * s.ref) status = APCG_SOLVE_CONVERGED;
+    else if (bad_point || !(lm > 0.0) || !isfinite(lm)) {
+        status = APCG_SOLVE_BREAKDOWN_RZ;  // the preconditioner is not positive on [0, lmax]
+        s.reject = 1;
+    } else if (maxit <= 0) status = APCG_SOLVE_MAXIT;
+    s.status = status;
+    s.flag = status != 0;
+    *st = s;
+}
+
+__global__ __launch_bounds__(TBF) void k_fcg_zero_x_if(double *__restrict__ x, int64_t n, int64_t per_block,
+                                                       const FcgState *st) {
+    if (!st->zero_x) return;
+    const dev::Chunk c = dev::block_chunk(n, per_block);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBF) x[i] = 0.0;
+}
+
+// One Clenshaw step.  stage: 0 = first (j = DEG-1), 1 = middle, 2 = last
+// (forms z and the partials of r.z and z.w).
+__global__ __launch_bounds__(TBF) void k_cheb(int32_t n, const int32_t *__restrict__ rowptr,
+                                              const int32_t *__restrict__ col, const double *__restrict__ val,
+                                              const double *__restrict__ r, const double *__restrict__ dinv,
+                                              const double *__restrict__ bj1, const double *__restrict__ bj2,
+                                              double *__restrict__ out, const double *__restrict__ w,
+                                              const FcgState *st, int j, int stage, double *part, int64_t per_block) {
+    if (st->flag) return;
+    const double s2 = 2.0 / st->lmax;
+    const double cj = st->c[j], cd = st->c[DEG];
+    const dev::Chunk ch = dev::block_chunk(n, per_block);
+    double v[2] = {0.0, 0.0};
+    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
+        const int s = rowptr[i], e = rowptr[i + 1];
+        const double vi = dinv[i] * r[i];
+        double res;
+        if (stage == 0) {  // b_{d-1} = c_{d-1} v + 2 c_d Y v
+            const double av = row_dot(col, val, s, e, (int)i, [&](int q) { return dinv[q] * r[q]; });
+            const double yv = s2 * dinv[i] * av - vi;
+            res = fma(2.0 * cd, yv, cj * vi);
+        } else {
+            const double au = row_dot(col, val, s, e, (int)i, [&](int q) { return bj1[q]; });
+            const double yu = s2 * dinv[i] * au - bj1[i];
+            const double b2v = bj2 ? bj2[i] : cd * vi;  // b_{d} = c_d v is not stored
+            if (stage == 1) res = fma(2.0, yu, cj * vi) - b2v;
+            else {
+                res = cj * vi + yu - b2v;
+                v[0] = fma(r[i], res, v[0]);
+                v[1] = fma(res, w[i], v[1]);
+            }
+        }
+        out[i] = res;
+    }
+    if (stage == 2) dev::store_partials<TBF, 2>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+// rho0 = r.z after the first preconditioner application.
+__global__ __launch_bounds__(64) void k_fcg_rho0(FcgState *st, const double *part, int G) {
+    if (st->flag) return;
+    double v[2];
+    dev::reduce_partials<64, 2>(part, G, v);
+    if (threadIdx.x != 0) return;
+    const double rho = v[0];
+    if (!(rho > 0.0)) {
+        st->status = isfinite(rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
+        st->flag = 1;
+        return;
+    }
+    st->rho = rho;
+    st->beta = 0.0;
+}
+
+__global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, const int32_t *__restrict__ rowptr,
+                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                     const double *__restrict__ z, const double *__restrict__ pold,
+                                                     double *__restrict__ pnew, double *__restrict__ w,
+                                                     const FcgState *st, double *part, int64_t per_block) {
+    if (st->flag) return;
+    const double beta = st->beta;
+    const dev::Chunk ch = dev::block_chunk(n, per_block);
+    double v[1] = {0.0};
+    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
+        const double sum = row_dot(col, val, rowptr[i], rowptr[i + 1], (int)i,
+                                   [&](int q) { return pdir_f(z[q], beta, pold[q]); });
+        const double pi = pdir_f(z[i], beta, pold[i]);
+        pnew[i] = pi;
+        w[i] = sum;
+        v[0] = fma(pi, sum, v[0]);
+    }
+    dev::store_partials<TBF, 1>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+__global__ __launch_bounds__(64) void k_fcg_alpha(FcgState *st, const double *part, int G) {
+    if (st->flag) return;
+    double v[1];
+    dev::reduce_partials<64, 1>(part, G, v);
+    if (threadIdx.x != 0) return;
+    const double delta = v[0];
+    st->delta = delta;
+    if (!(delta > 0.0)) {
+        st->status = isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN;
+        st->flag = 1;
+    } else {
+        st->alpha = st->rho / delta;
+    }
+}
+
+__global__ __launch_bounds__(TBF) void k_fcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
+                                                    const double *__restrict__ p, const double *__restrict__ w,
+                                                    const FcgState *st, double *part, int64_t per_block) {
+    if (st->flag) return;
+    const double alpha = st->alpha;
+    const dev::Chunk ch = dev::block_chunk(n, per_block);
+    double v[1] = {0.0};
+    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
+        x[i] = fma(alpha, p[i], x[i]);
+        const double ri = fma(-alpha, w[i], r[i]);
+        r[i] = ri;
+        v[0] = fma(ri, ri, v[0]);
+    }
+    dev::store_partials<TBF, 1>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+__global__ __launch_bounds__(64) void k_fcg_check(FcgState *st, const double *part, int G) {
+    if (st->flag) return;
+    double v[1];
+    dev::reduce_partials<64, 1>(part, G, v);
+    if (threadIdx.x != 0) return;
+    const double res = sqrt(v[0]);
+    const int its = st->its + 1;
+    st->its = its;
+    st->res = res;
+    int status = 0;
+    if (!isfinite(res)) status = APCG_SOLVE_NAN;
+    else if (res <= st->rtol * st->ref) status = APCG_SOLVE_CONVERGED;
+    else {
+        if (res < st->best_res) {
+            st->best_res = res;
+            st->best_its = its;
+        } else {
+            double win = st->stall_frac * (double)its;
+            if (win < (double)st->stall_min) win = (double)st->stall_min;
+            if ((double)(its - st->best_its) >= win) status = APCG_SOLVE_STALL;
+        }
+        if (!status && its >= st->maxit) status = APCG_SOLVE_MAXIT;
+    }
+    if (status) {
+        st->status = status;
+        st->flag = 1;
+    }
+}
+
+__global__ __launch_bounds__(64) void k_fcg_beta(FcgState *st, const double *part, int G) {
+    if (st->flag) return;
+    double v[2];
+    dev::reduce_partials<64, 2>(part, G, v);
+    if (threadIdx.x != 0) return;
+    const double rho_new = v[0], zeta = v[1];
+    if (!isfinite(rho_new) || !isfinite(zeta)) {
+        st->status = APCG_SOLVE_NAN;
+        st->flag = 1;
+    } else if (!(rho_new > 0.0)) {
+        st->status = APCG_SOLVE_BREAKDOWN_RZ;
+        st->flag = 1;
+    } else {
+        st->beta = -zeta / st->delta;
+        st->rho = rho_new;
+    }
+}
+
+// Writes the result record; with a fallback solve, adds its iterations.
+__global__ void k_fcg_finish(const FcgState *st, const apcg_solve_info *fallback, apcg_solve_info *out) {
+    if (threadIdx.x != 0) return;
+    int status = st->status ? st->status : APCG_SOLVE_MAXIT;
+    apcg_solve_info o;
+    o.fcg_iterations = st->its;
+    o.reserved = 0;
+    o.ref_norm = st->ref;
+    if (fallback) {
+        o.iterations = st->its + fallback->iterations;
+        o.status = fallback->status | APCG_SOLVE_FALLBACK | status;
+        o.res_norm = fallback->res_norm;
+    } else {
+        o.iterations = st->its;
+        o.status = status;
+        o.res_norm = st->res;
+    }
+    *out = o;
+}
+
+struct FcgCache {
+    int device = 0;
+    int64_t cap = 0;
+    double *ws = nullptr;       // 9 * cap: r, dinv, z, p0, p1, w, t0, t1, t2
+    FcgState *st = nullptr;
+    apcg_info fb_info = nullptr;  // fallback solve record
+    int32_t *pinned = nullptr;    // flag, status pairs
+    EventRef poll_ev[kMaxLookahead];
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    const void *gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+    int32_t gK = 0;
+};
+
+}  // namespace
+
+static std::mutex g_fcg_mu;
+static std::vector<std::pair<uint64_t, FcgCache *>> g_fcg;
+
+static FcgCache *fcg_cache(apcg_ctx c) {
+    std::lock_guard<std::mutex> lk(g_fcg_mu);
+    for (auto &p : g_fcg)
+        if (p.first == c->id) return p.second;
+    FcgCache *s = new FcgCache();
+    s->device = c->device;
+    g_fcg.emplace_back(c->id, s);
+    return s;
+}
+
+void fcg_cache_release(uint64_t ctx_id, int device) {
+    FcgCache *s = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_fcg_mu);
+        for (auto it = g_fcg.begin(); it != g_fcg.end(); ++it)
+            if (it->first == ctx_id) {
+                s = it->second;
+                g_fcg.erase(it);
+                break;
+            }
+    }
+    if (!s) return;
+    hipSetDevice(device);
+    if (s->exec) hipGraphExecDestroy(s->exec);
+    if (s->graph) hipGraphDestroy(s->graph);
+    hipFree(s->ws);
+    hipFree(s->st);
+    if (s->pinned) hipHostFree(s->pinned);
+    if (s->fb_info) apcg_info_destroy(s->fb_info);
+    delete s;
+}
+
+}  // namespace apcg
+
+using namespace apcg;
+
+extern "C" apcg_status apcg_fcg_opts_default(apcg_fcg_opts *o) {
+    if (!o) return set_error(APCG_ERR_INVALID_ARG, "opts is NULL");
+    memset(o, 0, sizeof *o);
+    o->stall_min = 50;
+    o->stall_frac = 0.1;
+    o->fallback = 1;
+    return APCG_SUCCESS;
+}
+
+extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol,
+                                               int32_t maxit, const float *dev_coeffs, const double *dev_lmax,
+                                               const apcg_solve_opts *opts_in, const apcg_fcg_opts *fopts_in,
+                                               apcg_info info, int32_t info_index) {
+    try {
+        if (!ctx || !A || !b || !x || !info || !dev_coeffs || !dev_lmax)
+            return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (b->n != A->n || x->n != A->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
+        if (b == x || (b->d == x->d && A->n > 0)) return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
+        if (ctx->device != A->device || b->device != A->device || x->device != A->device ||
+            info->device != A->device)
+            return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+        if (info_index < 0 || info_index >= info->count)
+            return set_error(APCG_ERR_INVALID_ARG, "info index out of range");
+        if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(APCG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
+        if (maxit < 0) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0");
+        if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING && ctx->is_default_global)
+            return set_error(APCG_ERR_INVALID_ARG, "pass a context created with apcg_ctx_create");
+        apcg_solve_opts opts;
+        if (opts_in) opts = *opts_in;
+        else apcg_solve_opts_default(&opts);
+        apcg_fcg_opts fo;
+        if (fopts_in) fo = *fopts_in;
+        else apcg_fcg_opts_default(&fo);
+        if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        int K = std::max(2, opts.iters_per_graph);
+        if (K & 1) ++K;
+        const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
+
+        FcgCache *fc = fcg_cache(ctx);
+        const int dev = ctx->device;
+        hipStream_t st = ctx->stream;
+        Acc acc[4] = {{&x->rec, ACC_RW}, {&info->rec, ACC_W}, {&A->rec, ACC_R}, {&b->rec, ACC_R}};
+        apcg_status s;
+        if ((s = op_begin(ctx, acc, 4))) return s;
+        const int64_t n = A->n;
+        if (fc->cap < n || !fc->ws) {
+            if (fc->ws) {
+                EventRef ev = event_get(dev);
+                if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+                APCG_HIP(hipEventRecord(ev->e, st));
+                double *old = fc->ws;
+                hipGraphExec_t oe = fc->exec;
+                hipGraph_t og = fc->graph;
+                defer_release({ev}, [old, oe, og, dev]() {
+                    hipSetDevice(dev);
+                    if (oe) hipGraphExecDestroy(oe);
+                    if (og) hipGraphDestroy(og);
+                    hipFree(old);
+                });
+                fc->exec = nullptr;
+                fc->graph = nullptr;
+            }
+            const int64_t cap = std::max<int64_t>(64, ((n + 63) / 64) * 64);
+            APCG_HIP(hipMalloc((void **)&fc->ws, sizeof(double) * 9 * cap));
+            fc->cap = cap;
+        }
+        if (!fc->st) {
+            APCG_HIP(hipMalloc((void **)&fc->st, 512));
+            APCG_HIP(hipHostMalloc((void **)&fc->pinned, sizeof(int32_t) * 2 * kMaxLookahead, hipHostMallocDefault));
+            if ((s = apcg_info_create(dev, 1, &fc->fb_info))) return s;
+        }
+        const int64_t cap = fc->cap;
+        double *r = fc->ws, *dinv = fc->ws + cap, *z = fc->ws + 2 * cap, *pb[2] = {fc->ws + 3 * cap, fc->ws + 4 * cap};
+        double *w = fc->ws + 5 * cap, *t[3] = {fc->ws + 6 * cap, fc->ws + 7 * cap, fc->ws + 8 * cap};
+        double *part = ctx->partials;
+        int G;
+        int64_t pbk;
+        elementwise_grid(n, &G, &pbk);
+        const int x0z = opts.x0_is_zero ? 1 : 0;
+
+        hipLaunchKernelGGL(k_fcg_init, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d, r, dinv,
+                           pb[0], part, pbk, x0z);
+        APCG_CHECK_LAUNCH("k_fcg_init");
+        hipLaunchKernelGGL(k_fcg_init_final, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G, dev_coeffs,
+                           dev_lmax, rtol, maxit, fo.stall_min, fo.stall_frac);
+        APCG_CHECK_LAUNCH("k_fcg_init_final");
+        if (!x0z) {
+            hipLaunchKernelGGL(k_fcg_zero_x_if, dim3(G), dim3(TBF), 0, st, x->d, n, pbk, (const FcgState *)fc->st);
+            APCG_CHECK_LAUNCH("k_fcg_zero_x_if");
+        }
+        // z = P r: b_7 -> t[7%3], ..., b_1 -> t[1%3], z
+        auto precondition = [&]() -> apcg_status {
+            for (int j = DEG - 1; j >= 0; --j) {
+                const int stage = j == DEG - 1 ? 0 : (j == 0 ? 2 : 1);
+                const double *bj1 = stage == 0 ? nullptr : t[(j + 1) % 3];
+                const double *bj2 = (stage == 0 || j + 2 == DEG) ? nullptr : t[(j + 2) % 3];
+                double *outp = stage == 2 ? z : t[j % 3];
+                hipLaunchKernelGGL(k_cheb, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val,
+                                   (const double *)r, (const double *)dinv, bj1, bj2, outp, (const double *)w,
+                                   (const FcgState *)fc->st, j, stage, part, pbk);
+                APCG_CHECK_LAUNCH("k_cheb");
+            }
+            return APCG_SUCCESS;
+        };
+        // the first application (z0; w is not read in the zeta partials used)
+        if ((s = precondition())) return s;
+        hipLaunchKernelGGL(k_fcg_rho0, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
+        APCG_CHECK_LAUNCH("k_fcg_rho0");
+
+        auto iteration = [&](int k) -> apcg_status {
+            const double *pold = pb[(k + 1) & 1];
+            double *pnew = pb[k & 1];
+            hipLaunchKernelGGL(k_fcg_product, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val,
+                               (const double *)z, pold, pnew, w, (const FcgState *)fc->st, part, pbk);
+            APCG_CHECK_LAUNCH("k_fcg_product");
+            hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
+            APCG_CHECK_LAUNCH("k_fcg_alpha");
+            hipLaunchKernelGGL(k_fcg_update, dim3(G), dim3(TBF), 0, st, n, x->d, r, (const double *)pnew,
+                               (const double *)w, (const FcgState *)fc->st, part, pbk);
+            APCG_CHECK_LAUNCH("k_fcg_update");
+            hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
+            APCG_CHECK_LAUNCH("k_fcg_check");
+            apcg_status ps = precondition();
+            if (ps) return ps;
+            hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
+            APCG_CHECK_LAUNCH("k_fcg_beta");
+            return APCG_SUCCESS;
+        };
+
+        if (maxit > 0) {
+            if (opts.mode == APCG_MODE_GRAPH) {
+                const void *key[4] = {A, x->d, fc->ws, (const void *)ctx->partials};
+                if (!fc->exec || fc->gK != K || memcmp(key, fc->gkey, sizeof key) != 0) {
+                    if (fc->exec) {
+                        EventRef ev = event_get(dev);
+                        if (ev) hipEventRecord(ev->e, st);
+                        hipGraphExec_t oe = fc->exec;
+                        hipGraph_t og = fc->graph;
+                        defer_release({ev}, [oe, og, dev]() {
+                            hipSetDevice(dev);
+                            hipGraphExecDestroy(oe);
+                            hipGraphDestroy(og);
+                        });
+                        fc->exec = nullptr;
+                        fc->graph = nullptr;
+                    }
+                    APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                    apcg_status cs = APCG_SUCCESS;
+                    for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = iteration(j);
+                    hipGraph_t g = nullptr;
+                    hipError_t e = hipStreamEndCapture(st, &g);
+                    if (cs) {
+                        if (g) hipGraphDestroy(g);
+                        return cs;
+                    }
+                    if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(fcg)");
+                    g_counters.kernel_launches -= (int64_t)(4 + DEG + 1) * K;
+                    e = hipGraphInstantiate(&fc->exec, g, nullptr, nullptr, 0);
+                    if (e != hipSuccess) {
+                        hipGraphDestroy(g);
+                        return hip_error(e, "hipGraphInstantiate(fcg)");
+                    }
+                    fc->graph = g;
+                    memcpy(fc->gkey, key, sizeof key);
+                    fc->gK = K;
+                }
+            }
+            const int64_t periods = ((int64_t)maxit + K - 1) / K;
+            for (int64_t g = 0; g < periods; ++g) {
+                if (opts.mode == APCG_MODE_GRAPH) {
+                    g_counters.graph_launches++;
+                    APCG_HIP(hipGraphLaunch(fc->exec, st));
+                } else {
+                    for (int j = 1; j <= K; ++j)
+                        if ((s = iteration(j))) return s;
+                }
+                const int slot = (int)(g % L);
+                if (!fc->poll_ev[slot]) {
+                    fc->poll_ev[slot] = event_get(dev);
+                    if (!fc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
+                }
+                g_counters.d2h_copies++;
+                APCG_HIP(hipMemcpyAsync(&fc->pinned[2 * slot], &fc->st->status, 2 * sizeof(int32_t),
+                                        hipMemcpyDeviceToHost, st));
+                APCG_HIP(hipEventRecord(fc->poll_ev[slot]->e, st));
+                if (g >= L - 1) {
+                    const int ps = (int)((g - (L - 1)) % L);
+                    g_counters.host_polls++;
+                    APCG_HIP(hipEventSynchronize(fc->poll_ev[ps]->e));
+                    if (fc->pinned[2 * ps + 1]) break;  // flag
+                }
+            }
+        }
+        // Fallback: the flexible phase ended in a breakdown, a rejected
+        // polynomial or a stall.  Reading its status is the one host wait of
+        // the solve outside the pacing polls.
+        const apcg_solve_info *fb = nullptr;
+        if (fo.fallback) {
+            FcgState hs;
+            g_counters.host_syncs++;
+            g_counters.d2h_copies++;
+            APCG_HIP(hipMemcpyAsync(&hs, fc->st, sizeof hs, hipMemcpyDeviceToHost, st));
+            APCG_HIP(hipStreamSynchronize(st));
+            const int bad = APCG_SOLVE_BREAKDOWN_PAP | APCG_SOLVE_BREAKDOWN_RZ | APCG_SOLVE_STALL;
+            if ((hs.status & bad) && !(hs.status & APCG_SOLVE_SETUP_ERROR)) {
+                apcg_solve_opts po;
+                apcg_solve_opts_default(&po);
+                po.mode = opts.mode;
+                po.iters_per_graph = opts.iters_per_graph;
+                po.lookahead = opts.lookahead;
+                po.x0_is_zero = 0;
+                const int32_t left = std::max(0, maxit - hs.its);
+                if ((s = pcg_solve_marked(ctx, A, b, x, rtol, left, &po, fc->fb_info, 0, nullptr, 0))) return s;
+                fb = fc->fb_info->d;
+            }
+        }
+        hipLaunchKernelGGL(k_fcg_finish, dim3(1), dim3(64), 0, st, (const FcgState *)fc->st, fb,
+                           info->d + info_index);
+        APCG_CHECK_LAUNCH("k_fcg_finish");
+        return op_end(ctx, acc, 4);
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}

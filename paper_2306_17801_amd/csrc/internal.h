@@ -178,7 +178,14 @@ apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
 void batch_cache_release(uint64_t ctx_id, int device);  // batched.hip
+// Jacobi-PCG solve with registry marking (pcg.hip); hist (2 hist_cap doubles,
+// device) receives alpha_k and beta_k of the first hist_cap iterations.
+apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                             const apcg_solve_opts *opts, apcg_info info, int32_t info_index, double *hist,
+                             int32_t hist_cap);
 void seg_cache_release(uint64_t ctx_id, int device);    // batched.hip
+void learn_cache_release(uint64_t ctx_id, int device);  // learn.hip
+void fcg_cache_release(uint64_t ctx_id, int device);    // fcg.hip
 void spmv_default_config(int32_t n, int64_t nnz, apcg_spmv_config *cfg);
 int32_t normalise_blocks(int32_t blocks, int64_t units);  // multiple of 8, <= kMaxBlocks
 

@@ -1,0 +1,654 @@
+// learn.hip -- the learned part of the polynomial preconditioner.
+//
+//   * features of one system: row statistics of A, Gershgorin bounds of
+//     D^-1 A, and the Ritz values / Gauss weights of the Lanczos tridiagonal
+//     that 12 Jacobi-PCG iterations build (the CG-Lanczos relation; the
+//     iterations run on the solve kernels, the tridiagonal's eigenproblem on
+//     one device thread with cyclic Jacobi rotations);
+//   * the quadrature data (G, h) of the preconditioner loss;
+//   * a 16 -> 64 -> 64 -> 9 tanh MLP in FP32: forward, loss, backward,
+//     Adam, all with fixed reduction orders (deterministic).
+//
+// The polynomial is p(t) = sum_j c_j T_j(2 t / lmax - 1) on [0, lmax],
+// lmax = the Gershgorin upper bound of D^-1 A.  Loss of one system:
+//   L(c) = c'G c - 2 h'c + 1 + mu/Q sum_q max(0, eps - p(t_q))^2
+// with G_jk = sum_i w_i th_i^2 T_j(y_i) T_k(y_i), h_j = sum_i w_i th_i T_j(y_i)
+// (Gauss nodes th_i, weights w_i, y_i = 2 th_i / lmax - 1): the squared
+// D^-1-norm of the residual after one preconditioned step from x0 = 0,
+// relative to b, plus a positivity penalty on Q = 64 points of [0, lmax].
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+
+#include "internal.h"
+
+namespace apcg {
+namespace {
+
+constexpr int FB = 256;   // block size of the row-statistics kernels
+constexpr int MSTEPS = 12;
+constexpr int NF = 16, NH = 64, NC = 9, NPARAM = 5833, QGRID = 64;
+constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5824;
+
+// Row statistics, pass 1 -> partials [7][G]:
+// min(1 - R_i), max(1 + R_i), min ln d_i, max ln d_i, sum ln d_i,
+// sum ln(max|off| / min|off|), rows with off-diagonals; R_i = sum|off| / |d_i|.
+__global__ __launch_bounds__(FB) void k_feat_rows(int32_t n, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  double *part, int64_t per_block) {
+    const dev::Chunk c = dev::block_chunk(n, per_block);
+    double lo = INFINITY, hi = -INFINITY, ldmin = INFINITY, ldmax = -INFINITY, ldsum = 0.0, an = 0.0, cnt = 0.0;
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += FB) {
+        double d = 0.0, off = 0.0, omax = 0.0, omin = INFINITY;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+            const double a = val[k];
+            if (col[k] == (int)i) d = a;
+            else {
+                const double aa = fabs(a);
+                off += aa;
+                omax = fmax(omax, aa);
+                omin = fmin(omin, aa);
+            }
+        }
+        const double R = off / fabs(d);
+        lo = fmin(lo, 1.0 - R);
+        hi = fmax(hi, 1.0 + R);
+        const double ld = log(d);
+        ldmin = fmin(ldmin, ld);
+        ldmax = fmax(ldmax, ld);
+        ldsum += ld;
+        if (omax > 0.0) {
+            an += log(omax / omin);
+            cnt += 1.0;
+        }
+    }
+    __shared__ double s[7][FB];
+    s[0][threadIdx.x] = lo;
+    s[1][threadIdx.x] = hi;
+    s[2][threadIdx.x] = ldmin;
+    s[3][threadIdx.x] = ldmax;
+    s[4][threadIdx.x] = ldsum;
+    s[5][threadIdx.x] = an;
+    s[6][threadIdx.x] = cnt;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double v[7] = {s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], s[5][0], s[6][0]};
+        for (int t = 1; t < FB; ++t) {
+            v[0] = fmin(v[0], s[0][t]);
+            v[1] = fmax(v[1], s[1][t]);
+            v[2] = fmin(v[2], s[2][t]);
+            v[3] = fmax(v[3], s[3][t]);
+            v[4] += s[4][t];
+            v[5] += s[5][t];
+            v[6] += s[6][t];
+        }
+        const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+        for (int k = 0; k < 7; ++k) part[k * gridDim.x + lb] = v[k];
+    }
+}
+
+// One thread: pass-1 totals -> stats[0..6] (stats[7] = mean ln d).
+__global__ void k_feat_rows_final(const double *part, int G, int32_t n, double *stats) {
+    if (threadIdx.x != 0) return;
+    double v[7] = {part[0], part[G], part[2 * G], part[3 * G], part[4 * G], part[5 * G], part[6 * G]};
+    for (int t = 1; t < G; ++t) {
+        v[0] = fmin(v[0], part[t]);
+        v[1] = fmax(v[1], part[G + t]);
+        v[2] = fmin(v[2], part[2 * G + t]);
+        v[3] = fmax(v[3], part[3 * G + t]);
+        v[4] += part[4 * G + t];
+        v[5] += part[5 * G + t];
+        v[6] += part[6 * G + t];
+    }
+    for (int k = 0; k < 7; ++k) stats[k] = v[k];
+    stats[7] = v[4] / (double)n;
+}
+
+// Pass 2: partials of sum (ln d_i - mean)^2 (two-pass variance).
+__global__ __launch_bounds__(FB) void k_feat_rows2(int32_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const double *stats, double *part, int64_t per_block) {
+    const dev::Chunk c = dev::block_chunk(n, per_block);
+    const double mean = stats[7];
+    double acc = 0.0;
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += FB) {
+        double d = 0.0;
+        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+            if (col[k] == (int)i) d = val[k];
+        const double e = log(d) - mean;
+        acc = fma(e, e, acc);
+    }
+    double v[1] = {acc};
+    dev::store_partials<FB, 1>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+}
+
+__device__ double cheb(int j, double y) {
+    double t0 = 1.0, t1 = y;
+    if (j == 0) return t0;
+    for (int k = 2; k <= j; ++k) {
+        const double t2 = 2.0 * y * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+    }
+    return t1;
+}
+
+// Cyclic Jacobi eigen-decomposition of a symmetric m x m matrix (m <= 16) in
+// place: on return the diagonal holds the eigenvalues and V's columns the
+// eigenvectors (Golub & Van Loan, Matrix Computations, the cyclic Jacobi
+// method with the symmetric Schur 2x2 rotation).
+__device__ void jacobi_eigen(double (&A)[16][16], double (&V)[16][16], int m) {
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                tot += A[i][j] * A[i][j];
+                if (i != j) off += A[i][j] * A[i][j];
+            }
+        if (off <= 1e-30 * tot) break;
+        for (int p = 0; p < m - 1; ++p)
+            for (int q = p + 1; q < m; ++q) {
+                if (A[p][q] == 0.0) continue;
+                const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
+                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
+                for (int k = 0; k < m; ++k) {  // A <- A J (columns p, q)
+                    const double akp = A[k][p], akq = A[k][q];
+                    A[k][p] = cs * akp - sn * akq;
+                    A[k][q] = sn * akp + cs * akq;
+                }
+                for (int k = 0; k < m; ++k) {  // A <- J' A (rows p, q)
+                    const double apk = A[p][k], aqk = A[q][k];
+                    A[p][k] = cs * apk - sn * aqk;
+                    A[q][k] = sn * apk + cs * aqk;
+                }
+                for (int k = 0; k < m; ++k) {  // V <- V J
+                    const double vkp = V[k][p], vkq = V[k][q];
+                    V[k][p] = cs * vkp - sn * vkq;
+                    V[k][q] = sn * vkp + cs * vkq;
+                }
+            }
+    }
+}
+
+// One thread: Lanczos tridiagonal from alpha/beta, its eigenpairs, the 16
+// features (FP32), G and h (FP32) and lmax (FP64).
+__global__ void k_feat_final(const double *stats, const double *var_part, int Gv, const double *hist, int hist_cap,
+                             const apcg_solve_info *info, int32_t n, int64_t nnz, float *feat, float *Gout,
+                             float *hout, double *lmax_out) {
+    if (threadIdx.x != 0 || blockIdx.x != 0) return;
+    double var = 0.0;
+    for (int t = 0; t < Gv; ++t) var += var_part[t];
+    const double lo = stats[0], hi = stats[1];
+    int m = info->iterations;
+    if (m > hist_cap) m = hist_cap;
+    if (m > 16) m = 16;
+    double T[16][16], V[16][16];
+    for (int i = 0; i < 16; ++i)
+        for (int j = 0; j < 16; ++j) T[i][j] = 0.0;
+    const double *al = hist, *be = hist + hist_cap;
+    for (int j = 0; j < m; ++j) {
+        T[j][j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+        if (j + 1 < m) T[j][j + 1] = T[j + 1][j] = sqrt(be[j]) / al[j];
+    }
+    jacobi_eigen(T, V, m);
+    double th[16], w[16];
+    for (int i = 0; i < m; ++i) {
+        th[i] = T[i][i];
+        w[i] = V[0][i] * V[0][i];
+    }
+    for (int i = 1; i < m; ++i)  // insertion sort by eigenvalue (weights follow)
+        for (int j = i; j > 0 && th[j] < th[j - 1]; --j) {
+            double a = th[j]; th[j] = th[j - 1]; th[j - 1] = a;
+            a = w[j]; w[j] = w[j - 1]; w[j - 1] = a;
+        }
+    const double relres = info->ref_norm > 0.0 ? info->res_norm / info->ref_norm : 1.0;
+    const int top = m - 1;
+    double f[NF];
+    f[0] = log10((double)n);
+    f[1] = (double)nnz / (double)n;
+    f[2] = lo;
+    f[3] = hi;
+    f[4] = (stats[3] - stats[2]) / log(10.0);
+    f[5] = sqrt(var / (double)n);
+    f[6] = stats[6] > 0.0 ? stats[5] / stats[6] : 0.0;
+    f[7] = th[0] / hi;
+    f[8] = th[m > 1 ? 1 : 0] / hi;
+    f[9] = th[m > 2 ? 2 : 0] / hi;
+    f[10] = th[top >= 2 ? top - 2 : 0] / hi;
+    f[11] = th[top >= 1 ? top - 1 : 0] / hi;
+    f[12] = th[top] / hi;
+    f[13] = log10(th[top] / th[0]);
+    f[14] = log10(relres);
+    f[15] = log10(th[0] / hi);
+    for (int k = 0; k < NF; ++k) feat[k] = (float)f[k];
+    double Ty[16][NC];
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < NC; ++j) Ty[i][j] = cheb(j, 2.0 * th[i] / hi - 1.0);
+    for (int j = 0; j < NC; ++j) {
+        double hj = 0.0;
+        for (int i = 0; i < m; ++i) hj += w[i] * th[i] * Ty[i][j];
+        hout[j] = (float)hj;
+        for (int k = 0; k < NC; ++k) {
+            double g = 0.0;
+            for (int i = 0; i < m; ++i) g += w[i] * th[i] * th[i] * Ty[i][j] * Ty[i][k];
+            Gout[j * NC + k] = (float)g;
+        }
+    }
+    *lmax_out = hi;
+}
+
+// ----------------------------------------------------------------- MLP
+__global__ void k_phi_grid(float *phi) {
+    const int q = threadIdx.x;  // Q = 64 threads
+    if (q >= QGRID) return;
+    const double y = -1.0 + 2.0 * q / (QGRID - 1);
+    for (int j = 0; j < NC; ++j) phi[q * NC + j] = (float)cheb(j, y);
+}
+
+// One workgroup of 64 threads per sample.
+__global__ __launch_bounds__(64) void k_mlp_fwd(const float *__restrict__ P, const float *__restrict__ X, int B,
+                                                float *__restrict__ H1, float *__restrict__ H2,
+                                                float *__restrict__ C) {
+    const int b = blockIdx.x, j = threadIdx.x;
+    if (b >= B) return;
+    __shared__ float x[NF], h1[NH], h2[NH];
+    if (j < NF) x[j] = X[b * NF + j];
+    __syncthreads();
+    float a = P[OFF_B1 + j];
+    for (int k = 0; k < NF; ++k) a = fmaf(P[OFF_W1 + j * NF + k], x[k], a);
+    const float t1 = tanhf(a);
+    h1[j] = t1;
+    if (H1) H1[b * NH + j] = t1;
+    __syncthreads();
+    a = P[OFF_B2 + j];
+    for (int k = 0; k < NH; ++k) a = fmaf(P[OFF_W2 + j * NH + k], h1[k], a);
+    const float t2 = tanhf(a);
+    h2[j] = t2;
+    if (H2) H2[b * NH + j] = t2;
+    __syncthreads();
+    if (j < NC) {
+        a = P[OFF_B3 + j];
+        for (int k = 0; k < NH; ++k) a = fmaf(P[OFF_W3 + j * NH + k], h2[k], a);
+        C[b * NC + j] = a;
+    }
+}
+
+// Per-sample loss and dL/dc (already divided by B for the mean loss).
+__global__ __launch_bounds__(64) void k_mlp_loss(const float *__restrict__ C, const float *__restrict__ G,
+                                                 const float *__restrict__ h, const float *__restrict__ phi, int B,
+                                                 float mu, float eps, float *__restrict__ dC,
+                                                 float *__restrict__ loss_b) {
+    const int b = blockIdx.x, t = threadIdx.x;
+    if (b >= B) return;
+    __shared__ float c[NC], viol[QGRID];
+    if (t < NC) c[t] = C[b * NC + t];
+    __syncthreads();
+    float q = 0.f;
+    for (int j = 0; j < NC; ++j) q = fmaf(phi[t * NC + j], c[j], q);
+    viol[t] = fmaxf(0.f, eps - q);
+    __syncthreads();
+    const float scale = mu / (float)QGRID;
+    if (t < NC) {
+        float g = -2.f * h[b * NC + t];
+        for (int k = 0; k < NC; ++k) g = fmaf(2.f * G[b * NC * NC + t * NC + k], c[k], g);
+        float pen = 0.f;
+        for (int qq = 0; qq < QGRID; ++qq) pen = fmaf(viol[qq], phi[qq * NC + t], pen);
+        g = fmaf(-2.f * scale, pen, g);
+        dC[b * NC + t] = g / (float)B;
+    }
+    if (t == 0) {
+        float L = 1.f;
+        for (int j = 0; j < NC; ++j) {
+            float gc = 0.f;
+            for (int k = 0; k < NC; ++k) gc = fmaf(G[b * NC * NC + j * NC + k], c[k], gc);
+            L = fmaf(c[j], gc - 2.f * h[b * NC + j], L);
+        }
+        float pen = 0.f;
+        for (int qq = 0; qq < QGRID; ++qq) pen = fmaf(viol[qq], viol[qq], pen);
+        loss_b[b] = fmaf(scale, pen, L);
+    }
+}
+
+// Per-sample back-propagated activation gradients dA2 = (dC W3) (1 - h2^2),
+// dA1 = (dA2 W2) (1 - h1^2).
+__global__ __launch_bounds__(64) void k_mlp_bwd_act(const float *__restrict__ P, const float *__restrict__ dC,
+                                                    const float *__restrict__ H1, const float *__restrict__ H2, int B,
+                                                    float *__restrict__ dA1, float *__restrict__ dA2) {
+    const int b = blockIdx.x, j = threadIdx.x;
+    if (b >= B) return;
+    __shared__ float dc[NC], da2[NH];
+    if (j < NC) dc[j] = dC[b * NC + j];
+    __syncthreads();
+    float a = 0.f;
+    for (int o = 0; o < NC; ++o) a = fmaf(dc[o], P[OFF_W3 + o * NH + j], a);
+    const float h2 = H2[b * NH + j];
+    const float d2 = a * (1.f - h2 * h2);
+    da2[j] = d2;
+    dA2[b * NH + j] = d2;
+    __syncthreads();
+    a = 0.f;
+    for (int k = 0; k < NH; ++k) a = fmaf(da2[k], P[OFF_W2 + k * NH + j], a);
+    const float h1 = H1[b * NH + j];
+    dA1[b * NH + j] = a * (1.f - h1 * h1);
+}
+
+// Parameter gradients: one thread per parameter, sum over samples in order.
+__global__ __launch_bounds__(256) void k_mlp_grad(const float *__restrict__ X, const float *__restrict__ H1,
+                                                  const float *__restrict__ H2, const float *__restrict__ dC,
+                                                  const float *__restrict__ dA1, const float *__restrict__ dA2, int B,
+                                                  float *__restrict__ grad) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NPARAM) return;
+    float g = 0.f;
+    if (p < OFF_B1) {
+        const int j = p / NF, k = p % NF;
+        for (int b = 0; b < B; ++b) g = fmaf(dA1[b * NH + j], X[b * NF + k], g);
+    } else if (p < OFF_W2) {
+        const int j = p - OFF_B1;
+        for (int b = 0; b < B; ++b) g += dA1[b * NH + j];
+    } else if (p < OFF_B2) {
+        const int j = (p - OFF_W2) / NH, k = (p - OFF_W2) % NH;
+        for (int b = 0; b < B; ++b) g = fmaf(dA2[b * NH + j], H1[b * NH + k], g);
+    } else if (p < OFF_W3) {
+        const int j = p - OFF_B2;
+        for (int b = 0; b < B; ++b) g += dA2[b * NH + j];
+    } else if (p < OFF_B3) {
+        const int o = (p - OFF_W3) / NH, k = (p - OFF_W3) % NH;
+        for (int b = 0; b < B; ++b) g = fmaf(dC[b * NC + o], H2[b * NH + k], g);
+    } else {
+        const int o = p - OFF_B3;
+        for (int b = 0; b < B; ++b) g += dC[b * NC + o];
+    }
+    grad[p] = g;
+}
+
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ P, const float *__restrict__ g,
+                                              float *__restrict__ m, float *__restrict__ v, int t, float lr, float b1,
+                                              float b2, float eps) {
+    const int p = blockIdx.x * blockDim.x + threadIdx.x;
+    if (p >= NPARAM) return;
+    const float gi = g[p];
+    const float mi = b1 * m[p] + (1.f - b1) * gi;
+    const float vi = b2 * v[p] + (1.f - b2) * gi * gi;
+    m[p] = mi;
+    v[p] = vi;
+    const float mh = mi / (1.f - powf(b1, (float)t));
+    const float vh = vi / (1.f - powf(b2, (float)t));
+    P[p] -= lr * mh / (sqrtf(vh) + eps);
+}
+
+__global__ void k_loss_mean(const float *loss_b, int B, float *out) {
+    if (threadIdx.x != 0) return;
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += loss_b[b];
+    *out = (float)(s / B);
+}
+
+// Column statistics (two-pass) and in-place standardisation of X [B, 16].
+__global__ void k_standardize(float *X, int B, float *mean, float *stdv, int compute) {
+    const int f = threadIdx.x;
+    if (f >= NF) return;
+    if (compute) {
+        double s = 0.0;
+        for (int b = 0; b < B; ++b) s += X[b * NF + f];
+        const double mu = s / B;
+        double q = 0.0;
+        for (int b = 0; b < B; ++b) {
+            const double e = X[b * NF + f] - mu;
+            q += e * e;
+        }
+        const double sd = sqrt(q / B);
+        mean[f] = (float)mu;
+        stdv[f] = (float)(sd > 1e-12 ? sd : 1.0);
+    }
+    const float mu = mean[f], sd = stdv[f];
+    for (int b = 0; b < B; ++b) X[b * NF + f] = (X[b * NF + f] - mu) / sd;
+}
+
+// Per-context MLP scratch (activations and gradients for up to cap samples).
+struct MlpScratch {
+    int device = 0;
+    int64_t cap = 0;
+    float *buf = nullptr;  // H1, H2, C, dC, dA1, dA2, loss_b, grad, phi
+    float *H1() const { return buf; }
+    float *H2() const { return buf + cap * NH; }
+    float *C() const { return buf + 2 * cap * NH; }
+    float *dC() const { return buf + 2 * cap * NH + cap * NC; }
+    float *dA1() const { return buf + 2 * cap * NH + 2 * cap * NC; }
+    float *dA2() const { return buf + 3 * cap * NH + 2 * cap * NC; }
+    float *loss_b() const { return buf + 4 * cap * NH + 2 * cap * NC; }
+    float *grad() const { return buf + 4 * cap * NH + 2 * cap * NC + cap; }
+    float *phi() const { return grad() + NPARAM; }
+    static size_t floats(int64_t cap) { return (size_t)(4 * cap * NH + 2 * cap * NC + cap + NPARAM + QGRID * NC); }
+};
+
+struct FeatScratch {
+    int device = 0;
+    int64_t cap = 0;
+    double *x = nullptr;      // n doubles
+    double *stats = nullptr;  // 8 + partials
+    double *hist = nullptr;   // 2 * MSTEPS
+    apcg_info info = nullptr;
+};
+
+}  // namespace
+
+static std::mutex g_learn_mu;
+static std::vector<std::pair<uint64_t, MlpScratch *>> g_mlp;
+static std::vector<std::pair<uint64_t, FeatScratch *>> g_feat;
+
+static MlpScratch *mlp_scratch(apcg_ctx c) {
+    std::lock_guard<std::mutex> lk(g_learn_mu);
+    for (auto &p : g_mlp)
+        if (p.first == c->id) return p.second;
+    MlpScratch *s = new MlpScratch();
+    s->device = c->device;
+    g_mlp.emplace_back(c->id, s);
+    return s;
+}
+
+static FeatScratch *feat_scratch(apcg_ctx c) {
+    std::lock_guard<std::mutex> lk(g_learn_mu);
+    for (auto &p : g_feat)
+        if (p.first == c->id) return p.second;
+    FeatScratch *s = new FeatScratch();
+    s->device = c->device;
+    g_feat.emplace_back(c->id, s);
+    return s;
+}
+
+void learn_cache_release(uint64_t ctx_id, int device) {
+    MlpScratch *m = nullptr;
+    FeatScratch *f = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_learn_mu);
+        for (auto it = g_mlp.begin(); it != g_mlp.end(); ++it)
+            if (it->first == ctx_id) {
+                m = it->second;
+                g_mlp.erase(it);
+                break;
+            }
+        for (auto it = g_feat.begin(); it != g_feat.end(); ++it)
+            if (it->first == ctx_id) {
+                f = it->second;
+                g_feat.erase(it);
+                break;
+            }
+    }
+    hipSetDevice(device);
+    if (m) {
+        hipFree(m->buf);
+        delete m;
+    }
+    if (f) {
+        hipFree(f->x);
+        hipFree(f->stats);
+        hipFree(f->hist);
+        if (f->info) apcg_info_destroy(f->info);
+        delete f;
+    }
+}
+
+static apcg_status ensure_mlp(apcg_ctx c, MlpScratch *s, int64_t B) {
+    if (s->buf && s->cap >= B) return APCG_SUCCESS;
+    if (s->buf) {
+        EventRef ev = event_get(c->device);
+        if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+        APCG_HIP(hipEventRecord(ev->e, c->stream));
+        float *old = s->buf;
+        const int dev = c->device;
+        defer_release({ev}, [old, dev]() {
+            hipSetDevice(dev);
+            hipFree(old);
+        });
+        s->buf = nullptr;
+    }
+    const int64_t cap = std::max<int64_t>(B, 256);
+    APCG_HIP(hipMalloc((void **)&s->buf, sizeof(float) * MlpScratch::floats(cap)));
+    s->cap = cap;
+    hipLaunchKernelGGL(k_phi_grid, dim3(1), dim3(64), 0, c->stream, s->phi());
+    APCG_CHECK_LAUNCH("k_phi_grid");
+    return APCG_SUCCESS;
+}
+
+}  // namespace apcg
+
+using namespace apcg;
+
+extern "C" {
+
+apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, float *dev_G, float *dev_h,
+                             double *dev_lmax) {
+    try {
+        if (!ctx || !A || !b || !dev_feat || !dev_G || !dev_h || !dev_lmax)
+            return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (b->n != A->n || A->n < 1) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch or empty system");
+        if (ctx->device != A->device || b->device != A->device)
+            return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+        FeatScratch *fs = feat_scratch(ctx);
+        apcg_status s;
+        APCG_HIP(hipSetDevice(ctx->device));
+        if (!fs->stats) {
+            APCG_HIP(hipMalloc((void **)&fs->stats, sizeof(double) * (8 + 8 * (int64_t)kMaxBlocks)));
+            APCG_HIP(hipMalloc((void **)&fs->hist, sizeof(double) * 2 * MSTEPS));
+            if ((s = apcg_info_create(ctx->device, 1, &fs->info))) return s;
+        }
+        if (fs->cap < A->n) {
+            if (fs->x) {
+                EventRef ev = event_get(ctx->device);
+                if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+                APCG_HIP(hipEventRecord(ev->e, ctx->stream));
+                double *old = fs->x;
+                const int dev = ctx->device;
+                defer_release({ev}, [old, dev]() {
+                    hipSetDevice(dev);
+                    hipFree(old);
+                });
+            }
+            APCG_HIP(hipMalloc((void **)&fs->x, sizeof(double) * A->n));
+            fs->cap = A->n;
+        }
+        // 12 Jacobi-PCG steps from x0 = 0 with rtol = 0 record alpha and beta
+        apcg_vec_s xv;
+        xv.device = ctx->device;
+        xv.d = fs->x;
+        xv.n = A->n;
+        apcg_solve_opts o;
+        apcg_solve_opts_default(&o);
+        o.x0_is_zero = 1;
+        o.iters_per_graph = 2 * ((MSTEPS + 2) / 2);
+        if ((s = pcg_solve_marked(ctx, A, b, &xv, 0.0, MSTEPS, &o, fs->info, 0, fs->hist, MSTEPS))) return s;
+        Acc acc[2] = {{&A->rec, ACC_R}, {&b->rec, ACC_R}};
+        if ((s = op_begin(ctx, acc, 2))) return s;
+        hipStream_t st = ctx->stream;
+        int G;
+        int64_t pb;
+        elementwise_grid(A->n, &G, &pb);
+        double *part = fs->stats + 8;
+        hipLaunchKernelGGL(k_feat_rows, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val, part, pb);
+        APCG_CHECK_LAUNCH("k_feat_rows");
+        hipLaunchKernelGGL(k_feat_rows_final, dim3(1), dim3(64), 0, st, (const double *)part, G, A->n, fs->stats);
+        APCG_CHECK_LAUNCH("k_feat_rows_final");
+        hipLaunchKernelGGL(k_feat_rows2, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val,
+                           (const double *)fs->stats, part, pb);
+        APCG_CHECK_LAUNCH("k_feat_rows2");
+        hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(64), 0, st, (const double *)fs->stats, (const double *)part, G,
+                           (const double *)fs->hist, MSTEPS, (const apcg_solve_info *)fs->info->d, A->n, A->nnz,
+                           dev_feat, dev_G, dev_h, dev_lmax);
+        APCG_CHECK_LAUNCH("k_feat_final");
+        return op_end(ctx, acc, 2);
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+apcg_status apcg_mlp_standardize(apcg_ctx ctx, float *dev_X, int32_t B, float *dev_mean, float *dev_std,
+                                 int32_t compute_stats) {
+    if (!ctx || !dev_X || !dev_mean || !dev_std || B < 1) return set_error(APCG_ERR_INVALID_ARG, "bad arguments");
+    APCG_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_standardize, dim3(1), dim3(64), 0, ctx->stream, dev_X, B, dev_mean, dev_std,
+                       compute_stats ? 1 : 0);
+    APCG_CHECK_LAUNCH("k_standardize");
+    if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING) APCG_HIP(hipStreamSynchronize(ctx->stream));
+    return APCG_SUCCESS;
+}
+
+apcg_status apcg_mlp_forward(apcg_ctx ctx, const float *dev_params, const float *dev_X, int32_t B, float *dev_C) {
+    if (!ctx || !dev_params || !dev_X || !dev_C || B < 1) return set_error(APCG_ERR_INVALID_ARG, "bad arguments");
+    APCG_HIP(hipSetDevice(ctx->device));
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(B), dim3(64), 0, ctx->stream, dev_params, dev_X, B, (float *)nullptr,
+                       (float *)nullptr, dev_C);
+    APCG_CHECK_LAUNCH("k_mlp_fwd");
+    if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING) APCG_HIP(hipStreamSynchronize(ctx->stream));
+    return APCG_SUCCESS;
+}
+
+apcg_status apcg_mlp_loss_grad(apcg_ctx ctx, const float *dev_params, const float *dev_X, const float *dev_G,
+                               const float *dev_h, int32_t B, float mu, float eps, float *dev_loss,
+                               float *dev_grad) {
+    if (!ctx || !dev_params || !dev_X || !dev_G || !dev_h || !dev_loss || !dev_grad || B < 1)
+        return set_error(APCG_ERR_INVALID_ARG, "bad arguments");
+    APCG_HIP(hipSetDevice(ctx->device));
+    MlpScratch *ms = mlp_scratch(ctx);
+    apcg_status s;
+    if ((s = ensure_mlp(ctx, ms, B))) return s;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(B), dim3(64), 0, st, dev_params, dev_X, B, ms->H1(), ms->H2(), ms->C());
+    APCG_CHECK_LAUNCH("k_mlp_fwd");
+    hipLaunchKernelGGL(k_mlp_loss, dim3(B), dim3(64), 0, st, (const float *)ms->C(), dev_G, dev_h,
+                       (const float *)ms->phi(), B, mu, eps, ms->dC(), ms->loss_b());
+    APCG_CHECK_LAUNCH("k_mlp_loss");
+    hipLaunchKernelGGL(k_mlp_bwd_act, dim3(B), dim3(64), 0, st, dev_params, (const float *)ms->dC(),
+                       (const float *)ms->H1(), (const float *)ms->H2(), B, ms->dA1(), ms->dA2());
+    APCG_CHECK_LAUNCH("k_mlp_bwd_act");
+    hipLaunchKernelGGL(k_mlp_grad, dim3((NPARAM + 255) / 256), dim3(256), 0, st, dev_X, (const float *)ms->H1(),
+                       (const float *)ms->H2(), (const float *)ms->dC(), (const float *)ms->dA1(),
+                       (const float *)ms->dA2(), B, dev_grad);
+    APCG_CHECK_LAUNCH("k_mlp_grad");
+    hipLaunchKernelGGL(k_loss_mean, dim3(1), dim3(64), 0, st, (const float *)ms->loss_b(), B, dev_loss);
+    APCG_CHECK_LAUNCH("k_loss_mean");
+    if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING) APCG_HIP(hipStreamSynchronize(ctx->stream));
+    return APCG_SUCCESS;
+}
+
+apcg_status apcg_mlp_train_step(apcg_ctx ctx, float *dev_params, float *dev_adam_m, float *dev_adam_v, int32_t t,
+                                float lr, const float *dev_X, const float *dev_G, const float *dev_h, int32_t B,
+                                float mu, float eps, float *dev_loss) {
+    if (!dev_adam_m || !dev_adam_v || t < 1) return set_error(APCG_ERR_INVALID_ARG, "bad Adam state");
+    MlpScratch *ms = mlp_scratch(ctx);
+    apcg_status s;
+    if ((s = ensure_mlp(ctx, ms, B))) return s;
+    if ((s = apcg_mlp_loss_grad(ctx, dev_params, dev_X, dev_G, dev_h, B, mu, eps, dev_loss, ms->grad()))) return s;
+    hipLaunchKernelGGL(k_adam, dim3((NPARAM + 255) / 256), dim3(256), 0, ctx->stream, dev_params,
+                       (const float *)ms->grad(), dev_adam_m, dev_adam_v, t, lr, 0.9f, 0.999f, 1e-8f);
+    APCG_CHECK_LAUNCH("k_adam");
+    if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING) APCG_HIP(hipStreamSynchronize(ctx->stream));
+    return APCG_SUCCESS;
+}
+
+}  // extern "C"

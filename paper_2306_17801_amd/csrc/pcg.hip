@@ -56,7 +56,8 @@ struct SolveState {
     double out_res;       // terminal results
     int32_t out_its, out_status;
     int32_t flag;         // 1 once a terminal state is reached
-    int32_t pad;
+    int32_t hist_cap;     // > 0: record alpha_k / beta_k (Lanczos data)
+    double *hist;         // [0, cap): alpha_k; [cap, 2 cap): beta_k
 };
 static_assert(sizeof(SolveState) <= 256, "solve state exceeds its allocation");
 
@@ -143,7 +144,7 @@ __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__res
 
 // One workgroup: reference norm, initial tests, record 0.
 __global__ __launch_bounds__(64) void k_pcg_init_final(SolveState *st, const double *partials, int G, double rtol,
-                                                       int32_t maxit) {
+                                                       int32_t maxit, double *hist, int32_t hist_cap) {
     double v[4];
     dev::reduce_partials<64, 4>(partials, G, v);
     if (threadIdx.x != 0) return;
@@ -158,6 +159,8 @@ __global__ __launch_bounds__(64) void k_pcg_init_final(SolveState *st, const dou
     st->out_res = res;
     st->rec[0] = PcgRecord{rho, 0.0, res, 0, 0};
     st->rec[1] = PcgRecord{0.0, 0.0, 0.0, -1, 0};
+    st->hist = hist;
+    st->hist_cap = hist ? hist_cap : 0;
     int status = 0;
     if (v[3] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
     else if (ref == 0.0) {
@@ -208,7 +211,10 @@ __device__ __forceinline__ bool product_prologue(SolveState *st, const double *p
         }
         beta = rho / prev.rho;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) st->rec[parity] = PcgRecord{rho, beta, res, k, 0};
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rec[parity] = PcgRecord{rho, beta, res, k, 0};
+        if (k > 1 && k - 1 <= st->hist_cap) st->hist[st->hist_cap + k - 2] = beta;  // beta after iteration k-1
+    }
     *beta_out = beta;
     return true;
 }
@@ -387,6 +393,7 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
             return;
         }
         alpha = rec.rho / delta;
+        if (blockIdx.x == 0 && threadIdx.x == 0 && rec.k <= st->hist_cap) st->hist[rec.k - 1] = alpha;
     }
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double rz = 0.0, nn = 0.0;
@@ -665,6 +672,16 @@ apcg_status apcg_solve_opts_default(apcg_solve_opts *opts) {
 
 apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                            const apcg_solve_opts *opts_in, apcg_info info, int32_t info_index) {
+    return apcg::pcg_solve_marked(ctx, A, b, x, rtol, maxit, opts_in, info, info_index, nullptr, 0);
+}
+
+}  // extern "C"
+
+namespace apcg {
+
+apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                             const apcg_solve_opts *opts_in, apcg_info info, int32_t info_index, double *hist,
+                             int32_t hist_cap) {
     try {
         if (!A || !b || !x || !info) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
         if (b->n != A->n || x->n != A->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
@@ -708,7 +725,7 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
                            opts.pc, norm_pre);
         APCG_CHECK_LAUNCH("k_pcg_init");
         hipLaunchKernelGGL(k_pcg_init_final, dim3(1), dim3(64), 0, st, c->ws.state, (const double *)bf.part_res(),
-                           pl.g_vec, rtol, maxit);
+                           pl.g_vec, rtol, maxit, hist, hist_cap);
         APCG_CHECK_LAUNCH("k_pcg_init_final");
         if (!opts.x0_is_zero) {
             hipLaunchKernelGGL(k_pcg_zero_x_if, dim3(pl.g_vec), dim3(VB), 0, st, x->d, (int64_t)A->n, pl.pb_vec,
@@ -787,6 +804,10 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
     }
 }
+
+}  // namespace apcg
+
+extern "C" {
 
 apcg_status apcg_ctx_kernel_times(apcg_ctx ctx, int32_t kind, double *mean_us, int32_t *count) {
     if (!ctx || !mean_us || !count) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");

@@ -453,3 +453,22 @@ def test_fcg_stall_detector_triggers_fallback():
     assert f.status & oracle.STALL and f.status & oracle.FALLBACK and f.status & oracle.CONVERGED
     assert 0 < f.fcg_its < f.its
     assert np.linalg.norm(b - A.to_scipy() @ f.x) <= 1.0001e-8 * np.linalg.norm(b)
+
+
+def test_fcg_precheck_rejects_polynomial_negative_on_the_enclosure():
+    """p > 0 on [0, lmax] is required for an SPD preconditioner: a
+    polynomial that dips below zero near lmax (T_1 with c = (0.2, -0.5):
+    p(lmax) = -0.3) is rejected before the first iteration and Jacobi-PCG
+    solves from x0; a shifted copy that stays positive is used."""
+    rng = np.random.default_rng(35)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((16, 16))))
+    b = rng.uniform(-1, 1, A.n)
+    c = np.zeros(9)
+    c[0], c[1] = 0.2, -0.5
+    f = oracle.fcg_poly(A, b, c, 2.0, rtol=1e-8, maxit=5000)
+    j = oracle.pcg(A, b, rtol=1e-8, maxit=5000)
+    assert f.fcg_its == 0 and f.status & oracle.FALLBACK and f.status & oracle.BREAKDOWN_RZ
+    assert f.its == j.its and np.array_equal(f.x, j.x)
+    c[0] = 0.8  # p = 0.8 - 0.5 y > 0 on y in [-1, 1]
+    g = oracle.fcg_poly(A, b, c, 2.0, rtol=1e-8, maxit=5000)
+    assert g.status == oracle.CONVERGED and g.fcg_its == g.its > 0
