@@ -395,7 +395,8 @@ apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A
  *   D^-1 A, log10(max diag / min diag), std of ln diag, mean over rows of
  *   ln(max |offdiag| / min |offdiag|), the three smallest and three largest
  *   Ritz values / upper bound, log10(largest / smallest Ritz value), log10
- *   of the relative residual after the steps, log10(smallest Ritz / upper);
+ *   of the relative residual after the steps (floored at 1e-30), log10(smallest
+ *   Ritz / upper);
  * dev_G[81], dev_h[9] (float): the quadratic form of the loss
  *   sum_i w_i (1 - th_i p(th_i))^2 = c'G c - 2 h'c + 1 over the Gauss rule
  *   (nodes th_i, weights w_i) of the spectral measure of D^-1/2 b, exact for

@@ -79,18 +79,22 @@ def features(A, b):
       4 log10(max diag / min diag), 5 std of ln diag, 6 mean over rows of
       ln(max |offdiag| / min |offdiag|), 7-9 the three smallest and 10-12 the
       three largest Ritz values / Gershgorin upper, 13 log10(theta_max /
-      theta_min), 14 log10 of the relative residual after the steps,
-      15 log10(theta_min / Gershgorin upper)."""
+      theta_min), 14 log10 of the relative residual after the steps (floored
+      at 1e-30, so a system that CG solves exactly in fewer steps still has
+      a finite feature), 15 log10(theta_min / Gershgorin upper)."""
     lo, hi = gershgorin(A)
     st = matrix_stats(A)
     al, be, relres = lanczos_data(A, b)
     th, _ = gauss_nodes_weights(al, np.append(be, 0.0)[: al.size])
     th = np.sort(th)
+    m = th.size  # fewer than three Ritz values (m < 3): the k-th smallest and
+    lo3 = [th[min(k, m - 1)] for k in range(3)]          # k-th largest clamp to
+    hi3 = [th[max(m - 3 + k, 0)] for k in range(3)]      # the ones that exist
     f = np.array([
         math.log10(A.n), A.nnz / A.n, lo, hi,
         st["log10_diag_contrast"], st["std_log_diag"], st["mean_log_offdiag_ratio"],
-        th[0] / hi, th[1] / hi, th[2] / hi, th[-3] / hi, th[-2] / hi, th[-1] / hi,
-        math.log10(th[-1] / th[0]), math.log10(relres), math.log10(th[0] / hi),
+        lo3[0] / hi, lo3[1] / hi, lo3[2] / hi, hi3[0] / hi, hi3[1] / hi, hi3[2] / hi,
+        math.log10(th[-1] / th[0]), math.log10(max(relres, 1e-30)), math.log10(th[0] / hi),
     ])
     return f
 

@@ -352,7 +352,7 @@ struct FcgCache {
     EventRef poll_ev[kMaxLookahead];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void *gkey[4] = {nullptr, nullptr, nullptr, nullptr};
+    const void *gkey[8] = {};
     int32_t gK = 0;
 };
 
@@ -528,7 +528,8 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
 
         if (maxit > 0) {
             if (opts.mode == APCG_MODE_GRAPH) {
-                const void *key[4] = {A, x->d, fc->ws, (const void *)ctx->partials};
+                const void *key[8] = {A, A->rowptr, A->col, A->val, x->d, fc->ws, (const void *)ctx->partials,
+                                      (const void *)(intptr_t)n};
                 if (!fc->exec || fc->gK != K || memcmp(key, fc->gkey, sizeof key) != 0) {
                     if (fc->exec) {
                         EventRef ev = event_get(dev);

@@ -216,14 +216,14 @@ __global__ void k_feat_final(const double *stats, const double *var_part, int Gv
     f[4] = (stats[3] - stats[2]) / log(10.0);
     f[5] = sqrt(var / (double)n);
     f[6] = stats[6] > 0.0 ? stats[5] / stats[6] : 0.0;
-    f[7] = th[0] / hi;
-    f[8] = th[m > 1 ? 1 : 0] / hi;
-    f[9] = th[m > 2 ? 2 : 0] / hi;
-    f[10] = th[top >= 2 ? top - 2 : 0] / hi;
-    f[11] = th[top >= 1 ? top - 1 : 0] / hi;
-    f[12] = th[top] / hi;
+    // k-th smallest / largest Ritz values; with fewer than three, the index
+    // clamps to the values that exist
+    for (int k = 0; k < 3; ++k) {
+        f[7 + k] = th[k < top ? k : top] / hi;
+        f[10 + k] = th[top - 2 + k > 0 ? top - 2 + k : 0] / hi;
+    }
     f[13] = log10(th[top] / th[0]);
-    f[14] = log10(relres);
+    f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
     f[15] = log10(th[0] / hi);
     for (int k = 0; k < NF; ++k) feat[k] = (float)f[k];
     double Ty[16][NC];
@@ -561,7 +561,8 @@ apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_fe
         apcg_solve_opts o;
         apcg_solve_opts_default(&o);
         o.x0_is_zero = 1;
-        o.iters_per_graph = 2 * ((MSTEPS + 2) / 2);
+        o.mode = APCG_MODE_STREAM;  // a one-off 12-step run: no graph to capture
+        o.iters_per_graph = MSTEPS;
         if ((s = pcg_solve_marked(ctx, A, b, &xv, 0.0, MSTEPS, &o, fs->info, 0, fs->hist, MSTEPS))) return s;
         Acc acc[2] = {{&A->rec, ACC_R}, {&b->rec, ACC_R}};
         if ((s = op_begin(ctx, acc, 2))) return s;

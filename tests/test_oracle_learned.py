@@ -130,3 +130,14 @@ def test_initial_params_shapes_and_scale():
     p = P.mlp_initial_params(7)
     assert sum(v.size for v in p.values()) == 5833
     assert np.all(p["b1"] == 0) and abs(p["W2"]).max() <= math.sqrt(6 / 128)
+
+
+def test_features_with_fewer_than_three_ritz_values():
+    """A 1 x 1 system: CG is exact after one step, so there is one Ritz value
+    (the eigenvalue 1 of D^-1 A); the k-th smallest and largest clamp to it
+    and the relative-residual feature takes its floor."""
+    A = P.CSR(n=1, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32), val=np.array([2.0]))
+    f = LO.features(A, np.array([3.0]))
+    assert np.all(np.isfinite(f))
+    assert np.allclose(f[7:13], 1.0, rtol=0, atol=1e-15)
+    assert f[13] == 0.0 and f[14] == -30.0 and f[15] == 0.0
