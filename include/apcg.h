@@ -390,23 +390,30 @@ apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A
 /* These calls take raw device pointers and are ordered on ctx only.       */
 /* ---------------------------------------------------------------------- */
 
-/* Features and loss data of one system (n >= 1, Jacobi diagonal > 0):
+/* Features of one system (n >= 1, Jacobi diagonal > 0):
  * dev_feat[16] (float): log10 n, nnz/n, Gershgorin lower and upper bounds of
  *   D^-1 A, log10(max diag / min diag), std of ln diag, mean over rows of
  *   ln(max |offdiag| / min |offdiag|), the three smallest and three largest
- *   Ritz values / upper bound, log10(largest / smallest Ritz value), log10
- *   of the relative residual after the steps (floored at 1e-30), log10(smallest
+ *   Ritz values / upper bound (with fewer than three, indices clamp to the
+ *   ones that exist), log10(largest / smallest Ritz value), log10 of the
+ *   relative residual after the steps (floored at 1e-30), log10(smallest
  *   Ritz / upper);
- * dev_G[81], dev_h[9] (float): the quadratic form of the loss
- *   sum_i w_i (1 - th_i p(th_i))^2 = c'G c - 2 h'c + 1 over the Gauss rule
- *   (nodes th_i, weights w_i) of the spectral measure of D^-1/2 b, exact for
- *   the degree-18 integrand;
- * dev_lmax (double): the Gershgorin upper bound.
+ * dev_lmax[1] (double): the Gershgorin upper bound.
  * Runs 12 Jacobi-PCG iterations from x0 = 0 on ctx's workspace (the
- * CG-Lanczos relation turns their alpha, beta into the Ritz values and Gauss
- * weights) plus two passes over the rows. */
-apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, float *dev_G, float *dev_h,
-                             double *dev_lmax);
+ * CG-Lanczos relation turns their alpha, beta into the Ritz values) plus two
+ * passes over the rows. */
+apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, double *dev_lmax);
+
+/* Training label of one system, from its own Jacobi-PCG solve (x0 = 0, rtol,
+ * maxit >= 1; the tridiagonal of all its iterations):
+ * dev_label[3] (double): lmin = the smallest Ritz value of the solve (0 when
+ *   it takes no iteration), a = 4 lmin clamped to [1e-6 lmax, lmax / 2]
+ *   (lmax / 2 without iterations), lmax;
+ * dev_G[81], dev_h[9] (float): the loss's quadratic form
+ *   sum_q w_q (1 - t_q p(t_q))^2 = c'G c - 2 h'c + 1 over the 16-point
+ *   Gauss-Chebyshev rule (t_q, w_q = 1/16) on [a, lmax]. */
+apcg_status apcg_pc_label(apcg_ctx ctx, apcg_mat A, apcg_vec b, double rtol, int32_t maxit, float *dev_G,
+                          float *dev_h, double *dev_label);
 
 /* Standardises the rows of dev_X[B][16] in place with the column means and
  * standard deviations dev_mean[16], dev_std[16]; compute_stats != 0 first
@@ -419,7 +426,7 @@ apcg_status apcg_mlp_forward(apcg_ctx ctx, const float *dev_params, const float 
 
 /* Mean loss over B systems (dev_loss[1]) and its gradient with respect to
  * the 5833 parameters (dev_grad), given each system's dev_G[B][81] and
- * dev_h[B][9]; penalty weight mu and floor eps of the positivity term
+ * dev_h[B][9] (from apcg_pc_label); penalty weight mu and floor eps of the positivity term
  * mu / 64 sum_q max(0, eps - p(t_q))^2 over 64 points of [0, lmax]. */
 apcg_status apcg_mlp_loss_grad(apcg_ctx ctx, const float *dev_params, const float *dev_X, const float *dev_G,
                                const float *dev_h, int32_t B, float mu, float eps, float *dev_loss, float *dev_grad);
@@ -457,6 +464,15 @@ apcg_status apcg_fcg_opts_default(apcg_fcg_opts *opts);
 apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                                     const float *dev_coeffs, const double *dev_lmax, const apcg_solve_opts *opts,
                                     const apcg_fcg_opts *fopts, apcg_info info, int32_t info_index);
+
+/* The learned solve in one call: features of (A, b), standardised with
+ * dev_mean[16] / dev_std[16], the network dev_params[5833] -> coefficients,
+ * then apcg_ksp_solve_fcg_poly with them (same options, result record and
+ * fallback).  Network arrays are device pointers ordered on ctx only. */
+apcg_status apcg_ksp_solve_learned(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                                   const float *dev_params, const float *dev_mean, const float *dev_std,
+                                   const apcg_solve_opts *opts, const apcg_fcg_opts *fopts, apcg_info info,
+                                   int32_t info_index);
 
 /* Mean device time (microseconds) and launch count of the product kernel
  * (kind 0: fused SpMV + p.Ap) and the update kernel (kind 1: x, r update

@@ -1,27 +1,33 @@
 """Oracle for the learned polynomial preconditioner -- TEST INFRASTRUCTURE ONLY.
 
-Plain FP64 numpy: matrix features, the Gauss-quadrature data of the
-preconditioner loss, the loss itself, a 16 -> 64 -> 64 -> 9 tanh MLP with
-its analytic backward pass, and Adam (Kingma & Ba, 2015).  The HIP kernels
-are checked against these functions; nothing here is imported by the product
+Plain FP64 numpy: matrix features, the training label and the quadratic
+form of the loss, the loss itself, a 16 -> 64 -> 64 -> 9 tanh MLP with its
+analytic backward pass, and Adam (Kingma & Ba, 2015).  The HIP kernels are
+checked against these functions; nothing here is imported by the product
 path.
 
 Preconditioner: z = p(M) D^-1 r with M = D^-1 A and
 p(t) = sum_{j=0..8} c_j T_j(2 t / lmax - 1), lmax = the Gershgorin upper
 bound of M (the operator of or_poly_apply).
 
-Loss of one system, from m steps of Jacobi-PCG started at x0 = 0 (the
-CG-Lanczos relation gives nodes theta_i and weights w_i of the Gauss rule of
-the spectral measure of r0_hat = D^-1/2 b, Saad, Iterative Methods for Sparse
-Linear Systems, 2nd ed., Sec. 6.7.3):
-    L(c) = sum_i w_i (1 - theta_i p(theta_i))^2
-         + mu / Q sum_q max(0, eps - p(t_q))^2
-The first term is ||(I - p(M) M) r0_hat||^2 / ||r0_hat||^2, exact for m >= 10
-because the integrand has degree 18 <= 2m - 1; the second keeps p positive
-on Q points t_q spread over [0, lmax] (p > 0 on the spectrum makes the
-preconditioner SPD).  With G_jk = sum_i w_i theta_i^2 T_j(y_i) T_k(y_i),
-h_j = sum_i w_i theta_i T_j(y_i), y_i = 2 theta_i / lmax - 1 and
-sum_i w_i = 1: first term = c'G c - 2 h'c + 1.
+Features come from 12 steps of Jacobi-PCG started at x0 = 0: the CG-Lanczos
+relation turns their alpha, beta into a tridiagonal whose eigenvalues are
+Ritz values of M (Saad, Iterative Methods for Sparse Linear Systems, 2nd
+ed., Sec. 6.7.3).
+
+Label of one training system: lmin = the smallest Ritz value of the full
+Jacobi-PCG solve of that system (CG finds the extreme eigenvalues first, so
+after convergence it matches lambda_min(M) closely), and the interval
+[a, lmax] with a = 4 lmin clamped to [1e-6 lmax, lmax / 2].  Loss:
+    L(c) = sum_q w_q (1 - t_q p(t_q))^2 + mu / Q sum_q' max(0, eps - p(s_q'))^2
+over the Q = 16 point Gauss-Chebyshev rule (t_q, w_q = 1/Q) on [a, lmax],
+which integrates the degree-18 residual polynomial exactly against the
+Chebyshev weight; its minimiser is close to the minimax (Chebyshev)
+residual polynomial on [a, lmax].  The second term keeps p positive on 64
+points s_q' spread over [0, lmax] (p > 0 on the spectrum makes the
+preconditioner SPD).  With G_jk = sum_q w_q t_q^2 T_j(y_q) T_k(y_q),
+h_j = sum_q w_q t_q T_j(y_q), y_q = 2 t_q / lmax - 1 and sum_q w_q = 1, the
+first term is c'G c - 2 h'c + 1.
 """
 from __future__ import annotations
 
@@ -29,13 +35,15 @@ import math
 
 import numpy as np
 
-from . import gershgorin, jacobi_inverse, pcg, gauss_nodes_weights, cheb_T
+from . import gershgorin, pcg, gauss_nodes_weights, cheb_T, lanczos_tridiagonal
 
 DEG = 8
 NCOEF = DEG + 1
 NFEAT = 16
 M_STEPS = 12
 Q_GRID = 64
+LABEL_Q = 16
+LABEL_SHIFT = 4.0
 
 
 def positivity_grid(q: int = Q_GRID) -> np.ndarray:
@@ -99,13 +107,62 @@ def features(A, b):
     return f
 
 
-def quadrature_gram(alpha, beta, lmax):
-    """G (9 x 9), h (9): the quadratic form of the loss's first term."""
-    th, w = gauss_nodes_weights(alpha, np.append(beta, 0.0)[: len(alpha)])
-    Ty = cheb_T(DEG, 2.0 * th / lmax - 1.0)          # [m, 9]
-    G = (Ty * (w * th * th)[:, None]).T @ Ty
-    h = Ty.T @ (w * th)
+def gram(nodes, weights, lmax):
+    """G (9 x 9), h (9) of sum_i w_i (1 - t_i p(t_i))^2 = c'G c - 2 h'c + sum w."""
+    nodes = np.asarray(nodes, dtype=np.float64)
+    weights = np.asarray(weights, dtype=np.float64)
+    Ty = cheb_T(DEG, 2.0 * nodes / lmax - 1.0)          # [m, 9]
+    G = (Ty * (weights * nodes * nodes)[:, None]).T @ Ty
+    h = Ty.T @ (weights * nodes)
     return G, h
+
+
+def quadrature_gram(alpha, beta, lmax):
+    """The same form over the Gauss rule of the spectral measure of
+    D^-1/2 b from m Lanczos steps (exact for m >= 10)."""
+    th, w = gauss_nodes_weights(alpha, np.append(beta, 0.0)[: len(alpha)])
+    return gram(th, w, lmax)
+
+
+def smallest_ritz(A, b, rtol=1e-8, maxit=None):
+    """Smallest eigenvalue of the CG-Lanczos tridiagonal of a full
+    Jacobi-PCG solve from x0 = 0, and the solve's iteration count."""
+    r = pcg(A, b, rtol=rtol, maxit=maxit, history=True)
+    k = r.its
+    if k == 0:
+        return None, 0
+    T = lanczos_tridiagonal(r.alpha[:k], r.beta[: k - 1])
+    return float(np.linalg.eigvalsh(T)[0]), k
+
+
+def chebyshev_rule(a, b, q=LABEL_Q):
+    """Gauss-Chebyshev nodes on [a, b] and equal weights 1/q."""
+    j = np.arange(q)
+    t = 0.5 * (a + b) + 0.5 * (b - a) * np.cos((2 * j + 1) * math.pi / (2 * q))
+    return t, np.full(q, 1.0 / q)
+
+
+def label_interval(lmin, lmax):
+    """a = 4 lmin clamped to [1e-6 lmax, lmax / 2]; a system the solve does
+    not iterate on (lmin None) takes a = lmax / 2."""
+    if lmin is None:
+        return 0.5 * lmax
+    return min(max(LABEL_SHIFT * lmin, 1e-6 * lmax), 0.5 * lmax)
+
+
+def label_gram(lmin, lmax):
+    a = label_interval(lmin, lmax)
+    t, w = chebyshev_rule(a, lmax)
+    G, h = gram(t, w, lmax)
+    return G, h, a
+
+
+def label_data(A, b, rtol=1e-8, maxit=None):
+    """(G, h, lmin, a, lmax) of one training system."""
+    lo, hi = gershgorin(A)
+    lmin, _ = smallest_ritz(A, b, rtol, maxit)
+    G, h, a = label_gram(lmin, hi)
+    return G, h, lmin, a, hi
 
 
 def loss_terms(c, G, h, Phi, mu=1.0, eps=0.05):

@@ -325,11 +325,16 @@ def _dptr(t, dtype):
     return ctypes.c_void_p(t.data_ptr())
 
 
-def apcg_pc_features(ctx, A, b, feat, G, h, lmax) -> None:
-    """feat: float32[16], G: float32[81], h: float32[9], lmax: float64[1] (GPU tensors)."""
+def apcg_pc_features(ctx, A, b, feat, lmax) -> None:
+    """feat: float32[16], lmax: float64[1] (GPU tensors, written on ctx)."""
     check("apcg_pc_features", _L().apcg_pc_features(_h(ctx), _h(A), _h(b), _dptr(feat, "float32"),
-                                                    _dptr(G, "float32"), _dptr(h, "float32"),
                                                     _dptr(lmax, "float64")))
+
+
+def apcg_pc_label(ctx, A, b, rtol: float, maxit: int, G, h, label) -> None:
+    """G: float32[81], h: float32[9], label: float64[3] = (lmin, a, lmax)."""
+    check("apcg_pc_label", _L().apcg_pc_label(_h(ctx), _h(A), _h(b), float(rtol), int(maxit), _dptr(G, "float32"),
+                                              _dptr(h, "float32"), _dptr(label, "float64")))
 
 
 def apcg_mlp_standardize(ctx, X, mean, std, compute_stats: bool) -> None:
@@ -375,6 +380,17 @@ def apcg_ksp_solve_fcg_poly(ctx, A, b, x, rtol: float, maxit: int, coeffs, lmax,
                                                                   int(maxit), _dptr(coeffs, "float32"),
                                                                   _dptr(lmax, "float64"), po, pf, _h(info),
                                                                   int(info_index)))
+
+
+def apcg_ksp_solve_learned(ctx, A, b, x, rtol: float, maxit: int, params, mean, std, opts=None, fopts=None,
+                           info=None, info_index: int = 0) -> None:
+    """params: float32[5833], mean / std: float32[16] GPU tensors."""
+    po = ctypes.byref(opts) if opts is not None else None
+    pf = ctypes.byref(fopts) if fopts is not None else None
+    check("apcg_ksp_solve_learned", _L().apcg_ksp_solve_learned(_h(ctx), _h(A), _h(b), _h(x), float(rtol),
+                                                                int(maxit), _dptr(params, "float32"),
+                                                                _dptr(mean, "float32"), _dptr(std, "float32"),
+                                                                po, pf, _h(info), int(info_index)))
 
 
 # ------------------------------------------------------------------ timers

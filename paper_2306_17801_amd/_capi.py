@@ -148,7 +148,8 @@ SIGNATURES = {
     "apcg_ksp_solve": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts), c_vp, c_i32],
     "apcg_ksp_solve_batched": [c_vp, c_i32, P(c_vp), P(c_vp), P(c_vp), c_f64, c_i32, P(apcg_solve_opts), c_vp],
     "apcg_ctx_kernel_times": [c_vp, c_i32, P(c_f64), P(c_i32)],
-    "apcg_pc_features": [c_vp, c_vp, c_vp, c_vp, c_vp, c_vp, c_vp],
+    "apcg_pc_features": [c_vp, c_vp, c_vp, c_vp, c_vp],
+    "apcg_pc_label": [c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, c_vp],
     "apcg_mlp_standardize": [c_vp, c_vp, c_i32, c_vp, c_vp, c_i32],
     "apcg_mlp_forward": [c_vp, c_vp, c_vp, c_i32, c_vp],
     "apcg_mlp_loss_grad": [c_vp, c_vp, c_vp, c_vp, c_vp, c_i32, ctypes.c_float, ctypes.c_float, c_vp, c_vp],
@@ -157,6 +158,8 @@ SIGNATURES = {
     "apcg_fcg_opts_default": [P(apcg_fcg_opts)],
     "apcg_ksp_solve_fcg_poly": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, P(apcg_solve_opts),
                                 P(apcg_fcg_opts), c_vp, c_i32],
+    "apcg_ksp_solve_learned": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, c_vp, P(apcg_solve_opts),
+                               P(apcg_fcg_opts), c_vp, c_i32],
     "apcg_timer_create": [P(c_vp)],
     "apcg_timer_destroy": [c_vp],
     "apcg_timer_start": [c_vp, c_vp],

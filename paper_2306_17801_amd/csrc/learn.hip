@@ -1,21 +1,27 @@
 // learn.hip -- the learned part of the polynomial preconditioner.
 //
 //   * features of one system: row statistics of A, Gershgorin bounds of
-//     D^-1 A, and the Ritz values / Gauss weights of the Lanczos tridiagonal
-//     that 12 Jacobi-PCG iterations build (the CG-Lanczos relation; the
-//     iterations run on the solve kernels, the tridiagonal's eigenproblem on
-//     one device thread with cyclic Jacobi rotations);
-//   * the quadrature data (G, h) of the preconditioner loss;
+//     D^-1 A, and the Ritz values of the Lanczos tridiagonal that 12
+//     Jacobi-PCG iterations build (the CG-Lanczos relation; the iterations
+//     run on the solve kernels, the tridiagonal's eigenproblem on one device
+//     thread with cyclic Jacobi rotations);
+//   * the training label of one system: the smallest Ritz value lmin of its
+//     full Jacobi-PCG solve (Sturm-sequence multisection on the tridiagonal
+//     of all iterations), and the quadratic form (G, h) of the loss over the
+//     Gauss-Chebyshev rule on [a, lmax], a = 4 lmin clamped to
+//     [1e-6 lmax, lmax / 2];
 //   * a 16 -> 64 -> 64 -> 9 tanh MLP in FP32: forward, loss, backward,
 //     Adam, all with fixed reduction orders (deterministic).
 //
 // The polynomial is p(t) = sum_j c_j T_j(2 t / lmax - 1) on [0, lmax],
 // lmax = the Gershgorin upper bound of D^-1 A.  Loss of one system:
-//   L(c) = c'G c - 2 h'c + 1 + mu/Q sum_q max(0, eps - p(t_q))^2
-// with G_jk = sum_i w_i th_i^2 T_j(y_i) T_k(y_i), h_j = sum_i w_i th_i T_j(y_i)
-// (Gauss nodes th_i, weights w_i, y_i = 2 th_i / lmax - 1): the squared
-// D^-1-norm of the residual after one preconditioned step from x0 = 0,
-// relative to b, plus a positivity penalty on Q = 64 points of [0, lmax].
+//   L(c) = c'G c - 2 h'c + 1 + mu/Q sum_q max(0, eps - p(s_q))^2
+// with G_jk = sum_q w_q t_q^2 T_j(y_q) T_k(y_q), h_j = sum_q w_q t_q T_j(y_q)
+// (Chebyshev nodes t_q on [a, lmax], w_q = 1/16, y_q = 2 t_q / lmax - 1):
+// the mean square of the residual polynomial 1 - t p(t) against the
+// Chebyshev weight on [a, lmax], whose minimiser is close to the minimax
+// residual polynomial there, plus a positivity penalty on Q = 64 points s_q
+// of [0, lmax].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -30,6 +36,8 @@ namespace {
 constexpr int FB = 256;   // block size of the row-statistics kernels
 constexpr int MSTEPS = 12;
 constexpr int NF = 16, NH = 64, NC = 9, NPARAM = 5833, QGRID = 64;
+constexpr int LABEL_Q = 16;
+constexpr double LABEL_SHIFT = 4.0;
 constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5824;
 
 // Row statistics, pass 1 -> partials [7][G]:
@@ -139,7 +147,7 @@ __device__ double cheb(int j, double y) {
 // place: on return the diagonal holds the eigenvalues and V's columns the
 // eigenvectors (Golub & Van Loan, Matrix Computations, the cyclic Jacobi
 // method with the symmetric Schur 2x2 rotation).
-__device__ void jacobi_eigen(double (&A)[16][16], double (&V)[16][16], int m) {
+__device__ void jacobi_eigen(double (&A)[16][16], double (&V)[16][16], int m) {  // V: eigenvectors
     for (int i = 0; i < m; ++i)
         for (int j = 0; j < m; ++j) V[i][j] = i == j ? 1.0 : 0.0;
     for (int sweep = 0; sweep < 60; ++sweep) {
@@ -175,11 +183,11 @@ __device__ void jacobi_eigen(double (&A)[16][16], double (&V)[16][16], int m) {
     }
 }
 
-// One thread: Lanczos tridiagonal from alpha/beta, its eigenpairs, the 16
-// features (FP32), G and h (FP32) and lmax (FP64).
+// One thread: Lanczos tridiagonal from alpha/beta, its eigenvalues, the 16
+// features (FP32) and lmax (FP64).
 __global__ void k_feat_final(const double *stats, const double *var_part, int Gv, const double *hist, int hist_cap,
-                             const apcg_solve_info *info, int32_t n, int64_t nnz, float *feat, float *Gout,
-                             float *hout, double *lmax_out) {
+                             const apcg_solve_info *info, int32_t n, int64_t nnz, float *feat,
+                             double *lmax_out) {
     if (threadIdx.x != 0 || blockIdx.x != 0) return;
     double var = 0.0;
     for (int t = 0; t < Gv; ++t) var += var_part[t];
@@ -196,15 +204,13 @@ __global__ void k_feat_final(const double *stats, const double *var_part, int Gv
         if (j + 1 < m) T[j][j + 1] = T[j + 1][j] = sqrt(be[j]) / al[j];
     }
     jacobi_eigen(T, V, m);
-    double th[16], w[16];
-    for (int i = 0; i < m; ++i) {
-        th[i] = T[i][i];
-        w[i] = V[0][i] * V[0][i];
-    }
-    for (int i = 1; i < m; ++i)  // insertion sort by eigenvalue (weights follow)
+    double th[16];
+    for (int i = 0; i < m; ++i) th[i] = T[i][i];
+    for (int i = 1; i < m; ++i)  // insertion sort
         for (int j = i; j > 0 && th[j] < th[j - 1]; --j) {
-            double a = th[j]; th[j] = th[j - 1]; th[j - 1] = a;
-            a = w[j]; w[j] = w[j - 1]; w[j - 1] = a;
+            const double a = th[j];
+            th[j] = th[j - 1];
+            th[j - 1] = a;
         }
     const double relres = info->ref_norm > 0.0 ? info->res_norm / info->ref_norm : 1.0;
     const int top = m - 1;
@@ -226,20 +232,89 @@ __global__ void k_feat_final(const double *stats, const double *var_part, int Gv
     f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
     f[15] = log10(th[0] / hi);
     for (int k = 0; k < NF; ++k) feat[k] = (float)f[k];
-    double Ty[16][NC];
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < NC; ++j) Ty[i][j] = cheb(j, 2.0 * th[i] / hi - 1.0);
-    for (int j = 0; j < NC; ++j) {
-        double hj = 0.0;
-        for (int i = 0; i < m; ++i) hj += w[i] * th[i] * Ty[i][j];
-        hout[j] = (float)hj;
-        for (int k = 0; k < NC; ++k) {
-            double g = 0.0;
-            for (int i = 0; i < m; ++i) g += w[i] * th[i] * th[i] * Ty[i][j] * Ty[i][k];
-            Gout[j * NC + k] = (float)g;
+    *lmax_out = hi;
+}
+
+// Number of eigenvalues below x of the symmetric tridiagonal with diagonal
+// 1/al_j + be_{j-1}/al_{j-1} and squared off-diagonal be_j / al_j^2 (the
+// CG-Lanczos tridiagonal): negative pivots of the LDL' factorisation of
+// T - x I (Sturm sequence; Golub & Van Loan, Sec. 8.4.1), with a zero
+// pivot replaced by a tiny negative one.
+__device__ int sturm_below(const double *al, const double *be, int m, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int j = 0; j < m; ++j) {
+        double d = 1.0 / al[j] - x;
+        if (j > 0) d += be[j - 1] / al[j - 1] - (be[j - 1] / (al[j - 1] * al[j - 1])) / q;
+        q = d;
+        if (fabs(q) < 1e-300) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// One workgroup of 64: the smallest eigenvalue by multisection (each round
+// splits the bracket into 65 parts and keeps the one where the count first
+// reaches 1), then the interval and the quadratic form of the loss.
+__global__ __launch_bounds__(64) void k_label(const double *stats, const double *hist, int cap,
+                                              const apcg_solve_info *info, float *Gout, float *hout,
+                                              double *lab) {
+    const double hi = stats[1];
+    int m = info->iterations;
+    if (m > cap) m = cap;
+    const double *al = hist, *be = hist + cap;
+    __shared__ double s_lo, s_hi;
+    __shared__ int first;
+    if (threadIdx.x == 0) {
+        s_lo = -0.5 * hi;
+        s_hi = 1.5 * hi;
+    }
+    __syncthreads();
+    if (m > 0) {
+        for (int round = 0; round < 10; ++round) {
+            const double lo = s_lo, w = (s_hi - lo) / 65.0;
+            const double x = lo + w * (threadIdx.x + 1);
+            const bool hit = sturm_below(al, be, m, x) >= 1;
+            if (threadIdx.x == 0) first = 64;
+            __syncthreads();
+            if (hit) atomicMin(&first, (int)threadIdx.x);
+            __syncthreads();
+            if (threadIdx.x == 0) {
+                const int f = first;
+                s_lo = lo + w * f;  // count(lo + w f) == 0 (f = 0: the old lower end)
+                if (f < 64) s_hi = lo + w * (f + 1);
+            }
+            __syncthreads();
         }
     }
-    *lmax_out = hi;
+    if (threadIdx.x != 0) return;
+    const double lmin = m > 0 ? 0.5 * (s_lo + s_hi) : 0.0;
+    double a = 0.5 * hi;
+    if (m > 0) a = fmin(fmax(LABEL_SHIFT * lmin, 1e-6 * hi), 0.5 * hi);
+    double G[NC][NC], h[NC];
+    for (int j = 0; j < NC; ++j) {
+        h[j] = 0.0;
+        for (int k = 0; k < NC; ++k) G[j][k] = 0.0;
+    }
+    for (int q = 0; q < LABEL_Q; ++q) {
+        const double t = 0.5 * (a + hi) + 0.5 * (hi - a) * cos((2 * q + 1) * M_PI / (2 * LABEL_Q));
+        const double y = 2.0 * t / hi - 1.0, w = 1.0 / LABEL_Q;
+        double T[NC];
+        T[0] = 1.0;
+        T[1] = y;
+        for (int j = 2; j < NC; ++j) T[j] = 2.0 * y * T[j - 1] - T[j - 2];
+        for (int j = 0; j < NC; ++j) {
+            h[j] += w * t * T[j];
+            for (int k = 0; k < NC; ++k) G[j][k] += w * t * t * T[j] * T[k];
+        }
+    }
+    for (int j = 0; j < NC; ++j) {
+        hout[j] = (float)h[j];
+        for (int k = 0; k < NC; ++k) Gout[j * NC + k] = (float)G[j][k];
+    }
+    lab[0] = lmin;
+    lab[1] = a;
+    lab[2] = hi;
 }
 
 // ----------------------------------------------------------------- MLP
@@ -433,6 +508,10 @@ struct FeatScratch {
     double *x = nullptr;      // n doubles
     double *stats = nullptr;  // 8 + partials
     double *hist = nullptr;   // 2 * MSTEPS
+    double *lhist = nullptr;  // 2 * lhist_cap: alpha, beta of a full solve
+    int64_t lhist_cap = 0;
+    float *fbuf = nullptr;    // learned solve: features [16], coefficients [9]
+    double *dbuf = nullptr;   // learned solve: lmax
     apcg_info info = nullptr;
 };
 
@@ -489,6 +568,9 @@ void learn_cache_release(uint64_t ctx_id, int device) {
         hipFree(f->x);
         hipFree(f->stats);
         hipFree(f->hist);
+        hipFree(f->lhist);
+        hipFree(f->fbuf);
+        hipFree(f->dbuf);
         if (f->info) apcg_info_destroy(f->info);
         delete f;
     }
@@ -516,44 +598,134 @@ static apcg_status ensure_mlp(apcg_ctx c, MlpScratch *s, int64_t B) {
     return APCG_SUCCESS;
 }
 
+// Allocates the per-context feature scratch for n rows (ordered after the
+// context's pending work when it grows).
+static apcg_status feat_prepare(apcg_ctx ctx, FeatScratch *fs, int64_t n) {
+    apcg_status s;
+    if (!fs->stats) {
+        APCG_HIP(hipMalloc((void **)&fs->stats, sizeof(double) * (8 + 8 * (int64_t)kMaxBlocks)));
+        APCG_HIP(hipMalloc((void **)&fs->hist, sizeof(double) * 2 * MSTEPS));
+        APCG_HIP(hipMalloc((void **)&fs->fbuf, sizeof(float) * 32));
+        APCG_HIP(hipMalloc((void **)&fs->dbuf, sizeof(double) * 4));
+        if ((s = apcg_info_create(ctx->device, 1, &fs->info))) return s;
+    }
+    if (fs->cap < n) {
+        if (fs->x) {
+            EventRef ev = event_get(ctx->device);
+            if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+            APCG_HIP(hipEventRecord(ev->e, ctx->stream));
+            double *old = fs->x;
+            const int dev = ctx->device;
+            defer_release({ev}, [old, dev]() {
+                hipSetDevice(dev);
+                hipFree(old);
+            });
+            fs->x = nullptr;
+        }
+        APCG_HIP(hipMalloc((void **)&fs->x, sizeof(double) * n));
+        fs->cap = n;
+    }
+    return APCG_SUCCESS;
+}
+
+// Row statistics (both passes) into fs->stats; partials after the first 8.
+static apcg_status feat_rows(apcg_ctx ctx, apcg_mat A, FeatScratch *fs, int *G_out) {
+    hipStream_t st = ctx->stream;
+    int G;
+    int64_t pb;
+    elementwise_grid(A->n, &G, &pb);
+    double *part = fs->stats + 8;
+    hipLaunchKernelGGL(k_feat_rows, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val, part, pb);
+    APCG_CHECK_LAUNCH("k_feat_rows");
+    hipLaunchKernelGGL(k_feat_rows_final, dim3(1), dim3(64), 0, st, (const double *)part, G, A->n, fs->stats);
+    APCG_CHECK_LAUNCH("k_feat_rows_final");
+    hipLaunchKernelGGL(k_feat_rows2, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val,
+                       (const double *)fs->stats, part, pb);
+    APCG_CHECK_LAUNCH("k_feat_rows2");
+    *G_out = G;
+    return APCG_SUCCESS;
+}
+
+static apcg_status check_system(apcg_ctx ctx, apcg_mat A, apcg_vec b) {
+    if (!ctx || !A || !b) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+    if (b->n != A->n || A->n < 1) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch or empty system");
+    if (ctx->device != A->device || b->device != A->device)
+        return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+    return APCG_SUCCESS;
+}
+
+// Features into dev_feat[16] / dev_lmax[1] (device pointers), on ctx.
+static apcg_status features_into(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, double *dev_lmax) {
+    FeatScratch *fs = feat_scratch(ctx);
+    apcg_status s;
+    APCG_HIP(hipSetDevice(ctx->device));
+    if ((s = feat_prepare(ctx, fs, A->n))) return s;
+    // 12 Jacobi-PCG steps from x0 = 0 with rtol = 0 record alpha and beta
+    apcg_vec_s xv;
+    xv.device = ctx->device;
+    xv.d = fs->x;
+    xv.n = A->n;
+    apcg_solve_opts o;
+    apcg_solve_opts_default(&o);
+    o.x0_is_zero = 1;
+    o.mode = APCG_MODE_STREAM;  // a one-off 12-step run: no graph to capture
+    o.iters_per_graph = MSTEPS;
+    if ((s = pcg_solve_marked(ctx, A, b, &xv, 0.0, MSTEPS, &o, fs->info, 0, fs->hist, MSTEPS))) return s;
+    Acc acc[2] = {{&A->rec, ACC_R}, {&b->rec, ACC_R}};
+    if ((s = op_begin(ctx, acc, 2))) return s;
+    int G;
+    if ((s = feat_rows(ctx, A, fs, &G))) return s;
+    hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(64), 0, ctx->stream, (const double *)fs->stats,
+                       (const double *)(fs->stats + 8), G, (const double *)fs->hist, MSTEPS,
+                       (const apcg_solve_info *)fs->info->d, A->n, A->nnz, dev_feat, dev_lmax);
+    APCG_CHECK_LAUNCH("k_feat_final");
+    return op_end(ctx, acc, 2);
+}
+
 }  // namespace apcg
 
 using namespace apcg;
 
 extern "C" {
 
-apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, float *dev_G, float *dev_h,
-                             double *dev_lmax) {
+apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_feat, double *dev_lmax) {
     try {
-        if (!ctx || !A || !b || !dev_feat || !dev_G || !dev_h || !dev_lmax)
-            return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
-        if (b->n != A->n || A->n < 1) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch or empty system");
-        if (ctx->device != A->device || b->device != A->device)
-            return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
-        FeatScratch *fs = feat_scratch(ctx);
         apcg_status s;
+        if ((s = check_system(ctx, A, b))) return s;
+        if (!dev_feat || !dev_lmax) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        return features_into(ctx, A, b, dev_feat, dev_lmax);
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+apcg_status apcg_pc_label(apcg_ctx ctx, apcg_mat A, apcg_vec b, double rtol, int32_t maxit, float *dev_G,
+                          float *dev_h, double *dev_label) {
+    try {
+        apcg_status s;
+        if ((s = check_system(ctx, A, b))) return s;
+        if (!dev_G || !dev_h || !dev_label) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (maxit < 1) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 1");
+        FeatScratch *fs = feat_scratch(ctx);
         APCG_HIP(hipSetDevice(ctx->device));
-        if (!fs->stats) {
-            APCG_HIP(hipMalloc((void **)&fs->stats, sizeof(double) * (8 + 8 * (int64_t)kMaxBlocks)));
-            APCG_HIP(hipMalloc((void **)&fs->hist, sizeof(double) * 2 * MSTEPS));
-            if ((s = apcg_info_create(ctx->device, 1, &fs->info))) return s;
-        }
-        if (fs->cap < A->n) {
-            if (fs->x) {
+        if ((s = feat_prepare(ctx, fs, A->n))) return s;
+        if (fs->lhist_cap < maxit) {
+            if (fs->lhist) {
                 EventRef ev = event_get(ctx->device);
                 if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
                 APCG_HIP(hipEventRecord(ev->e, ctx->stream));
-                double *old = fs->x;
+                double *old = fs->lhist;
                 const int dev = ctx->device;
                 defer_release({ev}, [old, dev]() {
                     hipSetDevice(dev);
                     hipFree(old);
                 });
+                fs->lhist = nullptr;
             }
-            APCG_HIP(hipMalloc((void **)&fs->x, sizeof(double) * A->n));
-            fs->cap = A->n;
+            APCG_HIP(hipMalloc((void **)&fs->lhist, sizeof(double) * 2 * (int64_t)maxit));
+            fs->lhist_cap = maxit;
         }
-        // 12 Jacobi-PCG steps from x0 = 0 with rtol = 0 record alpha and beta
+        const int cap = (int)fs->lhist_cap;
         apcg_vec_s xv;
         xv.device = ctx->device;
         xv.d = fs->x;
@@ -561,28 +733,41 @@ apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_fe
         apcg_solve_opts o;
         apcg_solve_opts_default(&o);
         o.x0_is_zero = 1;
-        o.mode = APCG_MODE_STREAM;  // a one-off 12-step run: no graph to capture
-        o.iters_per_graph = MSTEPS;
-        if ((s = pcg_solve_marked(ctx, A, b, &xv, 0.0, MSTEPS, &o, fs->info, 0, fs->hist, MSTEPS))) return s;
+        if ((s = pcg_solve_marked(ctx, A, b, &xv, rtol, maxit, &o, fs->info, 0, fs->lhist, cap))) return s;
         Acc acc[2] = {{&A->rec, ACC_R}, {&b->rec, ACC_R}};
         if ((s = op_begin(ctx, acc, 2))) return s;
-        hipStream_t st = ctx->stream;
         int G;
-        int64_t pb;
-        elementwise_grid(A->n, &G, &pb);
-        double *part = fs->stats + 8;
-        hipLaunchKernelGGL(k_feat_rows, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val, part, pb);
-        APCG_CHECK_LAUNCH("k_feat_rows");
-        hipLaunchKernelGGL(k_feat_rows_final, dim3(1), dim3(64), 0, st, (const double *)part, G, A->n, fs->stats);
-        APCG_CHECK_LAUNCH("k_feat_rows_final");
-        hipLaunchKernelGGL(k_feat_rows2, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val,
-                           (const double *)fs->stats, part, pb);
-        APCG_CHECK_LAUNCH("k_feat_rows2");
-        hipLaunchKernelGGL(k_feat_final, dim3(1), dim3(64), 0, st, (const double *)fs->stats, (const double *)part, G,
-                           (const double *)fs->hist, MSTEPS, (const apcg_solve_info *)fs->info->d, A->n, A->nnz,
-                           dev_feat, dev_G, dev_h, dev_lmax);
-        APCG_CHECK_LAUNCH("k_feat_final");
+        if ((s = feat_rows(ctx, A, fs, &G))) return s;
+        hipLaunchKernelGGL(k_label, dim3(1), dim3(64), 0, ctx->stream, (const double *)fs->stats,
+                           (const double *)fs->lhist, cap, (const apcg_solve_info *)fs->info->d, dev_G, dev_h,
+                           dev_label);
+        APCG_CHECK_LAUNCH("k_label");
         return op_end(ctx, acc, 2);
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+apcg_status apcg_ksp_solve_learned(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                                   const float *dev_params, const float *dev_mean, const float *dev_std,
+                                   const apcg_solve_opts *opts, const apcg_fcg_opts *fopts, apcg_info info,
+                                   int32_t info_index) {
+    try {
+        apcg_status s;
+        if ((s = check_system(ctx, A, b))) return s;
+        if (!dev_params || !dev_mean || !dev_std) return set_error(APCG_ERR_INVALID_ARG, "NULL network argument");
+        FeatScratch *fs = feat_scratch(ctx);
+        APCG_HIP(hipSetDevice(ctx->device));
+        if ((s = feat_prepare(ctx, fs, A->n))) return s;
+        float *feat = fs->fbuf, *coef = fs->fbuf + NF;
+        if ((s = features_into(ctx, A, b, feat, fs->dbuf))) return s;
+        hipLaunchKernelGGL(k_standardize, dim3(1), dim3(64), 0, ctx->stream, feat, 1, (float *)dev_mean,
+                           (float *)dev_std, 0);
+        APCG_CHECK_LAUNCH("k_standardize");
+        hipLaunchKernelGGL(k_mlp_fwd, dim3(1), dim3(64), 0, ctx->stream, dev_params, (const float *)feat, 1,
+                           (float *)nullptr, (float *)nullptr, coef);
+        APCG_CHECK_LAUNCH("k_mlp_fwd");
+        return apcg_ksp_solve_fcg_poly(ctx, A, b, x, rtol, maxit, coef, fs->dbuf, opts, fopts, info, info_index);
     } catch (const std::bad_alloc &) {
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
     }

@@ -1,7 +1,8 @@
 """GPU parity of the learned polynomial preconditioner against the oracle,
-through the C ABI: features and quadrature data, the FP32 MLP (forward,
-loss, gradients, Adam), and FCG(1) with the Chebyshev-basis polynomial and
-its Jacobi-PCG fallback.
+through the C ABI: features, training labels and the loss's quadratic form,
+the FP32 MLP (forward, loss, gradients, Adam), FCG(1) with the
+Chebyshev-basis polynomial and its Jacobi-PCG fallback, and the one-call
+learned solve.
 
 Tolerances.  Features, G and h are computed in FP64 on both sides and
 rounded to FP32 by the kernel: 2e-6 relative (FP32 rounding 6e-8, plus the
@@ -89,54 +90,79 @@ def _feature_systems():
             ("laplace2d_20", lap, rng.uniform(-1, 1, lap.n))]
 
 
-@pytest.mark.parametrize("case", range(3))
-def test_features_and_quadrature_parity(apcg, ctx, case):
+def _zeros(n, dtype):
     import torch
+
+    t = torch.zeros(n, dtype=getattr(torch, dtype), device="cuda:0")
+    torch.cuda.synchronize()
+    return t
+
+
+def gpu_features(apcg, ctx, A, b):
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
+    dA, db = DeviceCSR(A), DeviceVec(b)
+    feat, lm = _zeros(16, "float32"), _zeros(1, "float64")
+    apcg.apcg_pc_features(ctx, dA.h, db.h, feat, lm)
+    return host(apcg, ctx, feat), host(apcg, ctx, lm)[0]
+
+
+def gpu_label(apcg, ctx, A, b, rtol=1e-8, maxit=20000):
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    dA, db = DeviceCSR(A), DeviceVec(b)
+    G, h, lab = _zeros(81, "float32"), _zeros(9, "float32"), _zeros(3, "float64")
+    apcg.apcg_pc_label(ctx, dA.h, db.h, rtol, maxit, G, h, lab)
+    return host(apcg, ctx, G).reshape(9, 9), host(apcg, ctx, h), host(apcg, ctx, lab)
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_features_parity(apcg, ctx, case):
     name, A, b = _feature_systems()[case]
     print(f"case features {name}", flush=True)
-    dA, db = DeviceCSR(A), DeviceVec(b)
-    feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
-    G = torch.zeros(81, dtype=torch.float32, device="cuda:0")
-    h = torch.zeros(9, dtype=torch.float32, device="cuda:0")
-    lm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-    torch.cuda.synchronize()
-    apcg.apcg_pc_features(ctx, dA.h, db.h, feat, G, h, lm)
-    f_gpu, G_gpu, h_gpu, lm_gpu = (host(apcg, ctx, t) for t in (feat, G, h, lm))
-
+    f_gpu, lm_gpu = gpu_features(apcg, ctx, A, b)
     f_ref = OL.features(A, b)
     assert np.all(np.abs(f_gpu - f_ref) <= 2e-6 * np.maximum(1.0, np.abs(f_ref))), (f_gpu, f_ref)
     lo, hi = oracle.gershgorin(A)
-    assert lm_gpu[0] == pytest.approx(hi, rel=1e-15)
-    al, be, _ = OL.lanczos_data(A, b)
-    G_ref, h_ref = OL.quadrature_gram(al, be, hi)
-    assert np.max(np.abs(G_gpu.reshape(9, 9) - G_ref)) <= 2e-6 * np.max(np.abs(G_ref))
-    assert np.max(np.abs(h_gpu - h_ref)) <= 2e-6 * np.max(np.abs(h_ref))
-    # the quadratic form reproduces the loss at c = e0 (p = 1): the relative
-    # squared D^-1-weighted residual after one Jacobi step, below 1
-    assert 0.0 < G_gpu[0] - 2 * h_gpu[0] + 1.0 < 1.0
+    assert lm_gpu == pytest.approx(hi, rel=1e-15)
 
 
 def test_features_one_row_system(apcg, ctx):
-    """n = 1: CG solves it in one step (r = 0 exactly); the relative-residual
-    feature takes its floor and every feature stays finite."""
-    import torch
-    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
-
+    """n = 1: CG solves it in one step (r = 0 exactly); the Ritz-value
+    features clamp to the one value and the relative-residual feature takes
+    its floor."""
     A = P.CSR(n=1, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32), val=np.array([2.0]))
     b = np.array([3.0])
-    dA, db = DeviceCSR(A), DeviceVec(b)
-    feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
-    G = torch.zeros(81, dtype=torch.float32, device="cuda:0")
-    h = torch.zeros(9, dtype=torch.float32, device="cuda:0")
-    lm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
-    torch.cuda.synchronize()
-    apcg.apcg_pc_features(ctx, dA.h, db.h, feat, G, h, lm)
-    f_gpu = host(apcg, ctx, feat)
+    f_gpu, _ = gpu_features(apcg, ctx, A, b)
     f_ref = OL.features(A, b)
     assert np.all(np.isfinite(f_gpu)) and f_ref[14] == -30.0
     assert np.all(np.abs(f_gpu - f_ref) <= 2e-6 * np.maximum(1.0, np.abs(f_ref)))
+
+
+@pytest.mark.parametrize("case", range(3))
+def test_label_parity(apcg, ctx, case):
+    """lmin from the GPU solve's tridiagonal (Sturm multisection) against the
+    oracle solve's (dense eigensolver): the two solves differ only in
+    rounding, and the smallest Ritz value has converged long before the end."""
+    name, A, b = _feature_systems()[case]
+    print(f"case label {name}", flush=True)
+    G, h, lab = gpu_label(apcg, ctx, A, b)
+    G_ref, h_ref, lmin_ref, a_ref, hi = OL.label_data(A, b, rtol=1e-8, maxit=20000)
+    assert lab[0] == pytest.approx(lmin_ref, rel=1e-6)
+    assert lab[1] == pytest.approx(a_ref, rel=1e-6)
+    assert lab[2] == pytest.approx(hi, rel=1e-15)
+    assert np.max(np.abs(G - G_ref)) <= 2e-6 * np.max(np.abs(G_ref))
+    assert np.max(np.abs(h - h_ref)) <= 2e-6 * np.max(np.abs(h_ref))
+    if name == "laplace2d_20":  # closed form: lambda_min(D^-1 A) = 1 - cos(pi / 21)
+        assert lab[0] == pytest.approx(1 - math.cos(math.pi / 21), rel=1e-6)
+
+
+def test_label_without_iterations(apcg, ctx):
+    A = P.laplace_2d(6)
+    G, h, lab = gpu_label(apcg, ctx, A, np.zeros(A.n))
+    G_ref, h_ref, lmin_ref, a_ref, hi = OL.label_data(A, np.zeros(A.n))
+    assert lmin_ref is None and lab[0] == 0.0 and lab[1] == a_ref == hi / 2
+    assert np.max(np.abs(G - G_ref)) <= 2e-6 * np.max(np.abs(G_ref))
 
 
 # ---------------------------------------------------------------------------
@@ -144,8 +170,9 @@ def test_features_one_row_system(apcg, ctx):
 # ---------------------------------------------------------------------------
 
 def _mlp_inputs(B, seed):
-    """Standardised-looking features and the quadrature data of random
-    Gauss rules (nodes in (0, lmax], weights on the simplex), rounded to FP32."""
+    """Standardised-looking features and the quadratic forms of random
+    discrete measures (nodes in (0, lmax], weights on the simplex), rounded
+    to FP32."""
     rng = np.random.default_rng(seed)
     X = rng.standard_normal((B, 16)).astype(np.float32)
     Gs = np.zeros((B, 9, 9))
@@ -451,3 +478,41 @@ def test_fcg_bitwise_repeatable_and_mode_independent(apcg, ctx):
     for r, x in outs[1:]:
         assert r["iterations"] == outs[0][0]["iterations"]
         assert np.array_equal(x, outs[0][1])
+
+
+def test_learned_solve_equals_its_steps(apcg, ctx):
+    """apcg_ksp_solve_learned = features -> standardise -> forward ->
+    apcg_ksp_solve_fcg_poly, bit for bit; the network's coefficients match
+    the oracle's FP64 forward pass on the oracle's features."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    rng = np.random.default_rng(50)
+    s = P._lognormal_system(rng, 3, 18, 1.2, 8.0)
+    params = _params(3)
+    params["b3"] = np.array([1.2, -0.5, 0.2, -0.05, 0, 0, 0, 0, 0])
+    pv = pack(params)
+    f_ref = OL.features(s.A, s.b)
+    mean = np.linspace(-1, 1, 16).astype(np.float32)
+    std = np.linspace(0.5, 3, 16).astype(np.float32)
+    dP, dM, dS = dev(pv), dev(mean), dev(std)
+    dA, db = DeviceCSR(s.A), DeviceVec(s.b)
+    # the steps one by one
+    feat, lm = _zeros(16, "float32"), _zeros(1, "float64")
+    apcg.apcg_pc_features(ctx, dA.h, db.h, feat, lm)
+    X = feat.view(1, 16)
+    apcg.apcg_mlp_standardize(ctx, X, dM, dS, False)
+    C = torch.zeros((1, 9), dtype=torch.float32, device="cuda:0")
+    apcg.apcg_mlp_forward(ctx, dP, X, C)
+    c_gpu = host(apcg, ctx, C)[0]
+    c_ref, _ = OL.mlp_forward(unpack(pv), ((f_ref.astype(np.float32) - mean) / std).astype(np.float64)[None, :])
+    assert np.max(np.abs(c_gpu - c_ref[0])) <= 2e-5 * max(1.0, np.max(np.abs(c_ref)))
+    info = apcg.apcg_info_create(0, 2)
+    x1, x2 = DeviceVec.zeros(s.A.n), DeviceVec.zeros(s.A.n)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, x1.h, 1e-9, 5000, C.view(9), lm, opts, None, info, 0)
+    apcg.apcg_ksp_solve_learned(ctx, dA.h, db.h, x2.h, 1e-9, 5000, dP, dM, dS, opts, None, info, 1)
+    r1, r2 = apcg.apcg_info_get(info, 0), apcg.apcg_info_get(info, 1)
+    assert r1 == r2 and r1["status"] & apcg.APCG_SOLVE_CONVERGED
+    assert np.array_equal(x1.numpy(), x2.numpy())
+    apcg.apcg_info_destroy(info)

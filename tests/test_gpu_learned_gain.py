@@ -1,0 +1,122 @@
+"""What the trained network gains: train on the GPU (the library's own
+forward, backward and Adam kernels, labels from each training system's own
+Jacobi-PCG solve), then solve held-out systems with FCG(1) and the network's
+polynomial, against
+
+  * Jacobi-PCG (the method without the learned part),
+  * FCG(1) with the untrained network (what training adds),
+  * FCG(1) with a fixed Chebyshev polynomial on [lmax/100, lmax] (a
+    hand-set control).
+
+Systems follow the learned-preconditioner workload (3D 7-point, log-normal
+coefficients with sigma ~ U[0.5, 2], anisotropy ~ log-U[1, 100]) at sides
+12..28 so that the test runs in seconds.  The gain has no closed form
+(parity unpinned); the thresholds below are the measured behaviour with a
+margin.
+"""
+import numpy as np
+import pytest
+
+from paper_2306_17801_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apcg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_17801_amd as m
+
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(apcg):
+    c = apcg.apcg_ctx_create(0)
+    yield c
+    apcg.apcg_ctx_synchronize(c)
+    apcg.apcg_ctx_destroy(c)
+
+
+def chebyshev_control(lmax, a):
+    """Chebyshev-basis coefficients of the Chebyshev semi-iterative
+    polynomial on [a, lmax] (exact interpolation at 9 points)."""
+    from numpy.polynomial import chebyshev as Ch
+
+    T9 = [0] * 9 + [1]
+    s0 = (lmax + a) / (lmax - a)
+
+    def f(y):
+        t = (y + 1) * lmax / 2
+        return (1 - Ch.chebval((lmax + a - 2 * t) / (lmax - a), T9) / Ch.chebval(s0, T9)) / t
+
+    return Ch.chebinterpolate(f, 8)
+
+
+def test_trained_network_gains_over_jacobi_and_untrained(apcg, ctx):
+    import torch
+    from paper_2306_17801_amd import learned as L
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    train_set = P.learned_pc_set(160, 4, 12, 28)
+    eval_set = P.learned_pc_set(24, 40, 12, 28)
+    print("case learned-gain: collect", flush=True)
+    dtrain = L.collect(ctx, train_set)
+    deval = L.collect(ctx, eval_set)
+    print("case learned-gain: train", flush=True)
+    pc, losses = L.train(ctx, dtrain, epochs=300, batch=32, lr=3e-3)
+    untrained, _ = L.train(ctx, dtrain, epochs=0)
+    l_tr, l_un = L.mean_loss(ctx, pc, deval), L.mean_loss(ctx, untrained, deval)
+    print(f"held-out loss: trained {l_tr:.4e}  untrained {l_un:.4e}  first/last train step "
+          f"{losses[0]:.4e}/{losses[-1]:.4e}", flush=True)
+    assert np.all(np.isfinite(losses)) and l_tr < 0.2 * l_un
+
+    rtol, maxit = 1e-8, 20000
+    info = apcg.apcg_info_create(0, 1)
+    rows = []
+    for s in eval_set:
+        dA, db = DeviceCSR(s.A), DeviceVec(s.b)
+        x = DeviceVec.zeros(s.A.n)
+        opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+        apcg.apcg_ksp_solve(ctx, dA.h, db.h, x.h, rtol, maxit, opts, info, 0)
+        jac = apcg.apcg_info_get(info, 0)
+        out = {"jacobi": jac}
+        for name, net in (("learned", pc), ("untrained", untrained)):
+            L.solve(ctx, net, dA.h, db.h, x.h, rtol, maxit, opts, None, info, 0)
+            out[name] = apcg.apcg_info_get(info, 0)
+        lm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
+        torch.cuda.synchronize()
+        apcg.apcg_pc_features(ctx, dA.h, db.h, feat, lm)
+        apcg.apcg_ctx_synchronize(ctx)
+        lmax = float(lm.cpu()[0])
+        cc = torch.from_numpy(chebyshev_control(lmax, lmax / 100).astype(np.float32)).to("cuda:0")
+        torch.cuda.synchronize()
+        apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, x.h, rtol, maxit, cc, lm, opts, None, info, 0)
+        out["control"] = apcg.apcg_info_get(info, 0)
+        # the learned solve's answer is a solution
+        L.solve(ctx, pc, dA.h, db.h, x.h, rtol, maxit, opts, None, info, 0)
+        xs = x.numpy()
+        r = s.b - s.A.to_scipy() @ xs
+        assert np.linalg.norm(r) <= 1.01 * rtol * np.linalg.norm(s.b)
+        rows.append(out)
+        m = s.meta
+        print(f"side {m['side']:3d} sigma {m['sigma']:.2f} aniso {m['aniso']:6.1f}  jacobi {jac['iterations']:4d}  "
+              + "  ".join(f"{k} {out[k]['iterations']:4d} (st {out[k]['status']})"
+                          for k in ("learned", "untrained", "control")), flush=True)
+    apcg.apcg_info_destroy(info)
+    for o in rows:
+        for k in o:
+            assert o[k]["status"] & apcg.APCG_SOLVE_CONVERGED, (k, o[k])
+    its = {k: np.array([o[k]["iterations"] for o in rows], float) for k in rows[0]}
+    fb = sum(1 for o in rows if o["learned"]["status"] & apcg.APCG_SOLVE_FALLBACK)
+    print("mean iterations " + " ".join(f"{k} {v.mean():.1f}" for k, v in its.items()) + f"  learned fallbacks {fb}",
+          flush=True)
+    # outer iterations: each flexible iteration applies 8 extra products
+    assert its["learned"].mean() <= 0.25 * its["jacobi"].mean()
+    assert its["learned"].mean() < its["untrained"].mean()
+    assert fb == 0

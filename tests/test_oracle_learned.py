@@ -141,3 +141,67 @@ def test_features_with_fewer_than_three_ritz_values():
     assert np.all(np.isfinite(f))
     assert np.allclose(f[7:13], 1.0, rtol=0, atol=1e-15)
     assert f[13] == 0.0 and f[14] == -30.0 and f[15] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# training label: smallest Ritz value of the full solve, Chebyshev-measure form
+# ---------------------------------------------------------------------------
+
+def test_chebyshev_rule_integrates_degree_31_exactly():
+    """sum_q f(t_q) / Q = (1/pi) int_0^pi f(a + (b-a)(1 + cos s)/2) ds for
+    polynomials of degree <= 2Q - 1 (checked by adaptive quadrature)."""
+    from scipy.integrate import quad
+
+    a, b = 0.03, 1.9
+    t, w = LO.chebyshev_rule(a, b)
+    assert t.size == 16 and w.sum() == pytest.approx(1.0, rel=1e-15)
+    coef = np.random.default_rng(9).standard_normal(32)
+    f = lambda x: np.polynomial.polynomial.polyval((2 * x - a - b) / (b - a), coef)
+    exact = quad(lambda s: f(a + (b - a) * (1 + math.cos(s)) / 2), 0, math.pi, epsabs=1e-12, epsrel=1e-12,
+                 limit=200)[0] / math.pi
+    assert w @ f(t) == pytest.approx(exact, rel=1e-10)
+
+
+def test_label_minimiser_is_the_kernel_polynomial():
+    """The minimiser of sum_q w_q q(t_q)^2 over residual polynomials
+    q(t) = 1 - t p(t) (degree 9, q(0) = 1) for the Chebyshev measure on [a, b]
+    is the kernel polynomial q*(t) = sum_k g_k T_k(s(t)) T_k(s0) /
+    sum_k g_k T_k(s0)^2, s(t) = (b + a - 2t)/(b - a), s0 = s(0), g_0 = 1,
+    g_k = 2 (Szego; the T_k are orthogonal for this measure, norms 1 and 1/2).
+    Its maximum on [a, b] is at least the minimax value 1/T_9(s0) (Chebyshev)."""
+    for a, b in [(0.02, 2.0), (1e-3, 1.7), (0.4, 2.0)]:
+        G, h = LO.gram(*LO.chebyshev_rule(a, b), b)
+        c = np.linalg.solve(G, h)
+        s0 = (b + a) / (b - a)
+        g = np.array([1.0] + [2.0] * 9)
+        Ts0 = LO.cheb_T(9, np.array(s0))
+        t = np.concatenate([np.linspace(0, a, 50, endpoint=False), np.linspace(a, b, 2001)])
+        qstar = (LO.cheb_T(9, (b + a - 2 * t) / (b - a)) * (g * Ts0)).sum(-1) / np.sum(g * Ts0 * Ts0)
+        q = 1 - t * oracle.poly_eval(c, t, b)
+        assert np.max(np.abs(q - qstar)) <= 1e-8
+        inside = (t >= a)
+        T9s0 = np.cosh(9 * np.arccosh(s0))
+        assert np.max(np.abs(q[inside])) >= 1 / T9s0 * (1 - 1e-9)
+        # and the value of the form at c is the minimum sum_q w_q q*(t_q)^2
+        tq, wq = LO.chebyshev_rule(a, b)
+        qq = (LO.cheb_T(9, (b + a - 2 * tq) / (b - a)) * (g * Ts0)).sum(-1) / np.sum(g * Ts0 * Ts0)
+        assert c @ G @ c - 2 * h @ c + 1 == pytest.approx(wq @ qq ** 2, rel=1e-8)
+
+
+def test_smallest_ritz_value_matches_laplacian_eigenvalue():
+    """lambda_min(D^-1 A) of the n x n 5-point Laplacian is 1 - cos(pi/(n+1));
+    a full solve's Lanczos tridiagonal resolves it."""
+    n = 24
+    A = P.laplace_2d(n)
+    b = np.random.default_rng(4).uniform(-1, 1, A.n)
+    lmin, its = LO.smallest_ritz(A, b, rtol=1e-10)
+    assert its > 20
+    assert lmin == pytest.approx(1 - math.cos(math.pi / (n + 1)), rel=1e-8)
+    G, h, lm, a, hi = LO.label_data(A, b, rtol=1e-10)
+    assert a == pytest.approx(4 * lmin, rel=1e-15) and hi == 2.0
+
+
+def test_label_of_a_system_without_iterations():
+    A = P.laplace_2d(4)
+    G, h, lmin, a, hi = LO.label_data(A, np.zeros(A.n))
+    assert lmin is None and a == hi / 2
