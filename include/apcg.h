@@ -407,11 +407,13 @@ apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_fe
 /* Training label of one system, from its own Jacobi-PCG solve (x0 = 0, rtol,
  * maxit >= 1; the tridiagonal of all its iterations):
  * dev_label[3] (double): lmin = the smallest Ritz value of the solve (0 when
- *   it takes no iteration), a = 4 lmin clamped to [1e-6 lmax, lmax / 2]
+ *   it takes no iteration), a = 3 lmin clamped to [1e-6 lmax, lmax / 2]
  *   (lmax / 2 without iterations), lmax;
- * dev_G[81], dev_h[9] (float): the loss's quadratic form
- *   sum_q w_q (1 - t_q p(t_q))^2 = c'G c - 2 h'c + 1 over the 16-point
- *   Gauss-Chebyshev rule (t_q, w_q = 1/16) on [a, lmax]. */
+ * dev_G[81], dev_h[9] (float): the loss's quadratic form c'G c - 2 h'c + 1 =
+ *   sum_q w_q t_q^2 (p(t_q) - p*(t_q))^2 / sum_q w_q t_q^2 p*(t_q)^2 over the
+ *   16-point Gauss-Chebyshev rule (t_q, w_q = 1/16) on [a, lmax], where p*
+ *   is the Chebyshev semi-iterative polynomial on [a, lmax] (its residual
+ *   polynomial 1 - t p*(t) is the minimax one there). */
 apcg_status apcg_pc_label(apcg_ctx ctx, apcg_mat A, apcg_vec b, double rtol, int32_t maxit, float *dev_G,
                           float *dev_h, double *dev_label);
 

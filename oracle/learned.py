@@ -17,17 +17,21 @@ ed., Sec. 6.7.3).
 
 Label of one training system: lmin = the smallest Ritz value of the full
 Jacobi-PCG solve of that system (CG finds the extreme eigenvalues first, so
-after convergence it matches lambda_min(M) closely), and the interval
-[a, lmax] with a = 4 lmin clamped to [1e-6 lmax, lmax / 2].  Loss:
-    L(c) = sum_q w_q (1 - t_q p(t_q))^2 + mu / Q sum_q' max(0, eps - p(s_q'))^2
-over the Q = 16 point Gauss-Chebyshev rule (t_q, w_q = 1/Q) on [a, lmax],
-which integrates the degree-18 residual polynomial exactly against the
-Chebyshev weight; its minimiser is close to the minimax (Chebyshev)
-residual polynomial on [a, lmax].  The second term keeps p positive on 64
-points s_q' spread over [0, lmax] (p > 0 on the spectrum makes the
-preconditioner SPD).  With G_jk = sum_q w_q t_q^2 T_j(y_q) T_k(y_q),
-h_j = sum_q w_q t_q T_j(y_q), y_q = 2 t_q / lmax - 1 and sum_q w_q = 1, the
-first term is c'G c - 2 h'c + 1.
+after convergence it matches lambda_min(M) closely), the interval [a, lmax]
+with a = 3 lmin clamped to [1e-6 lmax, lmax / 2], and the target p* = the
+Chebyshev semi-iterative polynomial of degree 8 on [a, lmax], whose residual
+polynomial 1 - t p*(t) = T_9(s(t)) / T_9(s(0)), s(t) = (lmax + a - 2t) /
+(lmax - a), is the minimax one there.  Loss:
+    L(c) = sum_q w_q t_q^2 (p(t_q) - p*(t_q))^2 / sum_q w_q t_q^2 p*(t_q)^2
+         + mu / Q sum_q' max(0, eps - p(s_q'))^2
+over the Q = 16 point Gauss-Chebyshev rule (t_q, w_q = 1/Q) on [a, lmax]:
+the relative mean-square distance of the residual polynomial from the
+minimax one (exact for these degree-16 integrands against the Chebyshev
+weight), plus a term that keeps p positive on 64 points s_q' spread over
+[0, lmax] (p > 0 on the spectrum makes the preconditioner SPD).  With
+G0_jk = sum_q w_q t_q^2 T_j(y_q) T_k(y_q), y_q = 2 t_q / lmax - 1,
+kappa = c*' G0 c*, G = G0 / kappa and h = G0 c* / kappa, the first term is
+c'G c - 2 h'c + 1.
 """
 from __future__ import annotations
 
@@ -43,7 +47,7 @@ NFEAT = 16
 M_STEPS = 12
 Q_GRID = 64
 LABEL_Q = 16
-LABEL_SHIFT = 4.0
+LABEL_SHIFT = 3.0
 
 
 def positivity_grid(q: int = Q_GRID) -> np.ndarray:
@@ -143,26 +147,44 @@ def chebyshev_rule(a, b, q=LABEL_Q):
 
 
 def label_interval(lmin, lmax):
-    """a = 4 lmin clamped to [1e-6 lmax, lmax / 2]; a system the solve does
+    """a = 3 lmin clamped to [1e-6 lmax, lmax / 2]; a system the solve does
     not iterate on (lmin None) takes a = lmax / 2."""
     if lmin is None:
         return 0.5 * lmax
     return min(max(LABEL_SHIFT * lmin, 1e-6 * lmax), 0.5 * lmax)
 
 
+def chebyshev_iteration_coeffs(a, lmax):
+    """Coefficients in T_j(2 t / lmax - 1) of p*(t) = (1 - T_9(s(t)) /
+    T_9(s(0))) / t, s(t) = (lmax + a - 2t) / (lmax - a): the degree-8
+    polynomial is interpolated exactly at 9 Chebyshev points."""
+    from numpy.polynomial import chebyshev as Ch
+
+    T9 = Ch.Chebyshev.basis(DEG + 1)
+    s0 = (lmax + a) / (lmax - a)
+
+    def f(y):
+        t = 0.5 * (y + 1.0) * lmax
+        return (1.0 - T9((lmax + a - 2.0 * t) / (lmax - a)) / T9(s0)) / t
+
+    return Ch.chebinterpolate(f, DEG)
+
+
 def label_gram(lmin, lmax):
+    """(G, h, a, c*) of one system's loss."""
     a = label_interval(lmin, lmax)
-    t, w = chebyshev_rule(a, lmax)
-    G, h = gram(t, w, lmax)
-    return G, h, a
+    cstar = chebyshev_iteration_coeffs(a, lmax)
+    G0, _ = gram(*chebyshev_rule(a, lmax), lmax)
+    kappa = cstar @ G0 @ cstar
+    return G0 / kappa, G0 @ cstar / kappa, a, cstar
 
 
 def label_data(A, b, rtol=1e-8, maxit=None):
-    """(G, h, lmin, a, lmax) of one training system."""
+    """(G, h, lmin, a, lmax, c*) of one training system."""
     lo, hi = gershgorin(A)
     lmin, _ = smallest_ritz(A, b, rtol, maxit)
-    G, h, a = label_gram(lmin, hi)
-    return G, h, lmin, a, hi
+    G, h, a, cstar = label_gram(lmin, hi)
+    return G, h, lmin, a, hi, cstar
 
 
 def loss_terms(c, G, h, Phi, mu=1.0, eps=0.05):

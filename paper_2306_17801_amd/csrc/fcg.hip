@@ -528,8 +528,8 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
 
         if (maxit > 0) {
             if (opts.mode == APCG_MODE_GRAPH) {
-                const void *key[8] = {A, A->rowptr, A->col, A->val, x->d, fc->ws, (const void *)ctx->partials,
-                                      (const void *)(intptr_t)n};
+                const void *key[8] = {(const void *)(uintptr_t)A->uid, A->rowptr, A->col, A->val, x->d, fc->ws,
+                                      (const void *)ctx->partials, (const void *)(intptr_t)n};
                 if (!fc->exec || fc->gK != K || memcmp(key, fc->gkey, sizeof key) != 0) {
                     if (fc->exec) {
                         EventRef ev = event_get(dev);

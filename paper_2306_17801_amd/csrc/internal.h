@@ -77,12 +77,19 @@ std::vector<EventRef> record_deps(const Record &r);
 // ---------------------------------------------------------------------------
 struct SolveState;  // device struct, defined in pcg.hip
 
+// Everything a captured PCG graph bakes into its kernel arguments: a cached
+// graph is replayed only for an identical key.
 struct GraphKey {
-    const void *A, *x, *ws;
-    int32_t K, lpr, bs, blocks, pc, norm;
+    uint64_t mat_uid;
+    const void *rowptr, *col, *val, *x, *ws, *state, *partials, *prod;
+    int64_t ws_cap, pb_vec, lds_bytes;
+    int32_t n, K, tb, g_prod, rpb, g_vec, lds_nnz, pc, norm;
     bool operator==(const GraphKey &o) const {
-        return A == o.A && x == o.x && ws == o.ws && K == o.K && lpr == o.lpr && bs == o.bs &&
-               blocks == o.blocks && pc == o.pc && norm == o.norm;
+        return mat_uid == o.mat_uid && rowptr == o.rowptr && col == o.col && val == o.val && x == o.x &&
+               ws == o.ws && state == o.state && partials == o.partials && prod == o.prod && ws_cap == o.ws_cap &&
+               pb_vec == o.pb_vec && lds_bytes == o.lds_bytes && n == o.n && K == o.K && tb == o.tb &&
+               g_prod == o.g_prod && rpb == o.rpb && g_vec == o.g_vec && lds_nnz == o.lds_nnz && pc == o.pc &&
+               norm == o.norm;
     }
 };
 
@@ -149,6 +156,7 @@ struct apcg_vec_s {
 };
 
 struct apcg_mat_s {
+    uint64_t uid = 0;  // never reused: cached graphs are keyed on it, not on the handle's address
     int32_t device = 0;
     int32_t n = 0;
     int64_t nnz = 0;

@@ -7,21 +7,21 @@
 //     thread with cyclic Jacobi rotations);
 //   * the training label of one system: the smallest Ritz value lmin of its
 //     full Jacobi-PCG solve (Sturm-sequence multisection on the tridiagonal
-//     of all iterations), and the quadratic form (G, h) of the loss over the
-//     Gauss-Chebyshev rule on [a, lmax], a = 4 lmin clamped to
-//     [1e-6 lmax, lmax / 2];
+//     of all iterations), a = 3 lmin clamped to [1e-6 lmax, lmax / 2], and
+//     the target p* = the Chebyshev semi-iterative polynomial on [a, lmax]
+//     (its residual polynomial is the minimax one there), as the quadratic
+//     form (G, h) of the loss;
 //   * a 16 -> 64 -> 64 -> 9 tanh MLP in FP32: forward, loss, backward,
 //     Adam, all with fixed reduction orders (deterministic).
 //
 // The polynomial is p(t) = sum_j c_j T_j(2 t / lmax - 1) on [0, lmax],
 // lmax = the Gershgorin upper bound of D^-1 A.  Loss of one system:
 //   L(c) = c'G c - 2 h'c + 1 + mu/Q sum_q max(0, eps - p(s_q))^2
-// with G_jk = sum_q w_q t_q^2 T_j(y_q) T_k(y_q), h_j = sum_q w_q t_q T_j(y_q)
-// (Chebyshev nodes t_q on [a, lmax], w_q = 1/16, y_q = 2 t_q / lmax - 1):
-// the mean square of the residual polynomial 1 - t p(t) against the
-// Chebyshev weight on [a, lmax], whose minimiser is close to the minimax
-// residual polynomial there, plus a positivity penalty on Q = 64 points s_q
-// of [0, lmax].
+// with G = G0 / kappa, h = G0 c* / kappa, kappa = c*' G0 c*,
+// G0_jk = sum_q w_q t_q^2 T_j(y_q) T_k(y_q) over the 16-point Gauss-Chebyshev
+// rule (t_q on [a, lmax], w_q = 1/16, y_q = 2 t_q / lmax - 1): the relative
+// mean-square distance of the residual polynomial 1 - t p(t) from the
+// minimax one, plus a positivity penalty on Q = 64 points s_q of [0, lmax].
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -37,7 +37,7 @@ constexpr int FB = 256;   // block size of the row-statistics kernels
 constexpr int MSTEPS = 12;
 constexpr int NF = 16, NH = 64, NC = 9, NPARAM = 5833, QGRID = 64;
 constexpr int LABEL_Q = 16;
-constexpr double LABEL_SHIFT = 4.0;
+constexpr double LABEL_SHIFT = 3.0;
 constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5824;
 
 // Row statistics, pass 1 -> partials [7][G]:
@@ -253,9 +253,23 @@ __device__ int sturm_below(const double *al, const double *be, int m, double x) 
     return cnt;
 }
 
+__device__ double cheb_T_at(int j, double s) {  // T_j(s) by the recurrence, any real s
+    double t0 = 1.0, t1 = s;
+    if (j == 0) return t0;
+    for (int k = 2; k <= j; ++k) {
+        const double t2 = 2.0 * s * t1 - t0;
+        t0 = t1;
+        t1 = t2;
+    }
+    return t1;
+}
+
 // One workgroup of 64: the smallest eigenvalue by multisection (each round
 // splits the bracket into 65 parts and keeps the one where the count first
-// reaches 1), then the interval and the quadratic form of the loss.
+// reaches 1), then the interval, the target's coefficients (interpolation at
+// the 9 Chebyshev points, exact for a degree-8 polynomial:
+// c_j = (2 - [j = 0]) / 9 sum_k p*(t(y_k)) T_j(y_k), y_k = cos(pi (k + 1/2) / 9))
+// and the loss's normalised quadratic form.
 __global__ __launch_bounds__(64) void k_label(const double *stats, const double *hist, int cap,
                                               const apcg_solve_info *info, float *Gout, float *hout,
                                               double *lab) {
@@ -291,11 +305,21 @@ __global__ __launch_bounds__(64) void k_label(const double *stats, const double 
     const double lmin = m > 0 ? 0.5 * (s_lo + s_hi) : 0.0;
     double a = 0.5 * hi;
     if (m > 0) a = fmin(fmax(LABEL_SHIFT * lmin, 1e-6 * hi), 0.5 * hi);
-    double G[NC][NC], h[NC];
-    for (int j = 0; j < NC; ++j) {
-        h[j] = 0.0;
-        for (int k = 0; k < NC; ++k) G[j][k] = 0.0;
+    // target coefficients
+    const double s0 = (hi + a) / (hi - a), T9s0 = cheb_T_at(9, s0);
+    double cs[NC];
+    for (int j = 0; j < NC; ++j) cs[j] = 0.0;
+    for (int k = 0; k < NC; ++k) {
+        const double y = cos(M_PI * (k + 0.5) / NC);
+        const double t = 0.5 * (y + 1.0) * hi;
+        const double pv = (1.0 - cheb_T_at(9, (hi + a - 2.0 * t) / (hi - a)) / T9s0) / t;
+        for (int j = 0; j < NC; ++j) cs[j] += pv * cheb_T_at(j, y);
     }
+    for (int j = 0; j < NC; ++j) cs[j] *= (j == 0 ? 1.0 : 2.0) / NC;
+    // G0 over the Gauss-Chebyshev rule on [a, hi]
+    double G[NC][NC];
+    for (int j = 0; j < NC; ++j)
+        for (int k = 0; k < NC; ++k) G[j][k] = 0.0;
     for (int q = 0; q < LABEL_Q; ++q) {
         const double t = 0.5 * (a + hi) + 0.5 * (hi - a) * cos((2 * q + 1) * M_PI / (2 * LABEL_Q));
         const double y = 2.0 * t / hi - 1.0, w = 1.0 / LABEL_Q;
@@ -303,14 +327,18 @@ __global__ __launch_bounds__(64) void k_label(const double *stats, const double 
         T[0] = 1.0;
         T[1] = y;
         for (int j = 2; j < NC; ++j) T[j] = 2.0 * y * T[j - 1] - T[j - 2];
-        for (int j = 0; j < NC; ++j) {
-            h[j] += w * t * T[j];
+        for (int j = 0; j < NC; ++j)
             for (int k = 0; k < NC; ++k) G[j][k] += w * t * t * T[j] * T[k];
-        }
+    }
+    double Gc[NC], kappa = 0.0;
+    for (int j = 0; j < NC; ++j) {
+        Gc[j] = 0.0;
+        for (int k = 0; k < NC; ++k) Gc[j] += G[j][k] * cs[k];
+        kappa += cs[j] * Gc[j];
     }
     for (int j = 0; j < NC; ++j) {
-        hout[j] = (float)h[j];
-        for (int k = 0; k < NC; ++k) Gout[j * NC + k] = (float)G[j][k];
+        hout[j] = (float)(Gc[j] / kappa);
+        for (int k = 0; k < NC; ++k) Gout[j * NC + k] = (float)(G[j][k] / kappa);
     }
     lab[0] = lmin;
     lab[1] = a;

@@ -563,8 +563,28 @@ apcg_status launch_update(hipStream_t s, const Plan &pl, const Bufs &bf, int ite
 
 apcg_status get_graph(apcg_ctx c, const Plan &pl, const Bufs &bf, int K, int pc, int norm_pre,
                       hipGraphExec_t *exec) {
-    GraphKey key{bf.A, bf.x, bf.ws.base, K, bf.A->cfg.lanes_per_row + 1000 * bf.A->cfg.schedule, pl.tb, pl.g_prod,
-                 pc, norm_pre};
+    GraphKey key;
+    key.mat_uid = bf.A->uid;
+    key.rowptr = bf.A->rowptr;
+    key.col = bf.A->col;
+    key.val = bf.A->val;
+    key.x = bf.x;
+    key.ws = bf.ws.base;
+    key.state = bf.ws.state;
+    key.partials = bf.partials;
+    key.prod = reinterpret_cast<const void *>(pl.prod);
+    key.ws_cap = bf.ws.cap;
+    key.pb_vec = pl.pb_vec;
+    key.lds_bytes = (int64_t)pl.lds_bytes;
+    key.n = pl.n;
+    key.K = K;
+    key.tb = pl.tb;
+    key.g_prod = pl.g_prod;
+    key.rpb = pl.rpb;
+    key.g_vec = pl.g_vec;
+    key.lds_nnz = pl.lds_nnz;
+    key.pc = pc;
+    key.norm = norm_pre;
     for (auto &g : c->graphs)
         if (g.key == key) {
             *exec = g.exec;

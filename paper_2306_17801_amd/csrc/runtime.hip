@@ -846,6 +846,7 @@ apcg_status apcg_mat_wrap_csr(int32_t device, int32_t n, int64_t nnz, const int3
     for (int32_t i = 0; i < n; ++i)
         if (rp[i + 1] < rp[i]) return set_error(APCG_ERR_INVALID_ARG, "rowptr is decreasing");
     apcg_mat A = new apcg_mat_s();
+    A->uid = g_next_id++;
     A->device = device;
     A->n = n;
     A->nnz = nnz;

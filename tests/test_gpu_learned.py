@@ -147,7 +147,7 @@ def test_label_parity(apcg, ctx, case):
     name, A, b = _feature_systems()[case]
     print(f"case label {name}", flush=True)
     G, h, lab = gpu_label(apcg, ctx, A, b)
-    G_ref, h_ref, lmin_ref, a_ref, hi = OL.label_data(A, b, rtol=1e-8, maxit=20000)
+    G_ref, h_ref, lmin_ref, a_ref, hi, _ = OL.label_data(A, b, rtol=1e-8, maxit=20000)
     assert lab[0] == pytest.approx(lmin_ref, rel=1e-6)
     assert lab[1] == pytest.approx(a_ref, rel=1e-6)
     assert lab[2] == pytest.approx(hi, rel=1e-15)
@@ -160,7 +160,7 @@ def test_label_parity(apcg, ctx, case):
 def test_label_without_iterations(apcg, ctx):
     A = P.laplace_2d(6)
     G, h, lab = gpu_label(apcg, ctx, A, np.zeros(A.n))
-    G_ref, h_ref, lmin_ref, a_ref, hi = OL.label_data(A, np.zeros(A.n))
+    G_ref, h_ref, lmin_ref, a_ref, hi, _ = OL.label_data(A, np.zeros(A.n))
     assert lmin_ref is None and lab[0] == 0.0 and lab[1] == a_ref == hi / 2
     assert np.max(np.abs(G - G_ref)) <= 2e-6 * np.max(np.abs(G_ref))
 

@@ -119,4 +119,5 @@ def test_trained_network_gains_over_jacobi_and_untrained(apcg, ctx):
     # outer iterations: each flexible iteration applies 8 extra products
     assert its["learned"].mean() <= 0.25 * its["jacobi"].mean()
     assert its["learned"].mean() < its["untrained"].mean()
+    assert its["learned"].mean() <= 1.05 * its["control"].mean()
     assert fb == 0

@@ -203,3 +203,33 @@ def test_full_size_diffusion128_parity(apcg, ctx, diffusion128):
     true = np.linalg.norm(s.b - s.A.to_scipy() @ x) / np.linalg.norm(s.b)
     assert true <= 1.5e-10
     apcg.apcg_info_destroy(info)
+
+
+def test_graph_cache_after_matrix_destroy(apcg, ctx):
+    """Matrices of different sizes, each destroyed before the next is
+    wrapped, solved into the same x memory in graph mode: a new handle may
+    land at a destroyed one's address, and the cached graph must not be
+    replayed for it (its row count and arrays are baked into the capture)."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    xbig = torch.zeros(2000, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    info = apcg.apcg_info_create(0, 1)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    for side in (40, 20, 40, 36, 8, 20):
+        A = P.laplace_2d(side)
+        b = np.random.default_rng(side).uniform(-1, 1, A.n)
+        print(f"case graph-cache side={side}", flush=True)
+        dA, db = DeviceCSR(A), DeviceVec(b)
+        dx = DeviceVec(xbig[: A.n])
+        assert dx.t.data_ptr() == xbig.data_ptr()
+        apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, 1e-10, 10000, opts, info, 0)
+        res = apcg.apcg_info_get(info, 0)
+        ref = oracle.pcg(A, b, rtol=1e-10, maxit=10000)
+        assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
+        assert rel(dx.numpy(), ref.x) <= 1e-9
+        dx.close()
+        db.close()
+        dA.close()
+    apcg.apcg_info_destroy(info)

@@ -197,11 +197,32 @@ def test_smallest_ritz_value_matches_laplacian_eigenvalue():
     lmin, its = LO.smallest_ritz(A, b, rtol=1e-10)
     assert its > 20
     assert lmin == pytest.approx(1 - math.cos(math.pi / (n + 1)), rel=1e-8)
-    G, h, lm, a, hi = LO.label_data(A, b, rtol=1e-10)
-    assert a == pytest.approx(4 * lmin, rel=1e-15) and hi == 2.0
+    G, h, lm, a, hi, cstar = LO.label_data(A, b, rtol=1e-10)
+    assert a == pytest.approx(3 * lmin, rel=1e-15) and hi == 2.0
 
 
 def test_label_of_a_system_without_iterations():
     A = P.laplace_2d(4)
-    G, h, lmin, a, hi = LO.label_data(A, np.zeros(A.n))
+    G, h, lmin, a, hi, cstar = LO.label_data(A, np.zeros(A.n))
     assert lmin is None and a == hi / 2
+
+
+@pytest.mark.parametrize("a,b", [(0.02, 2.0), (1e-3, 1.7), (0.5, 2.0)])
+def test_label_target_is_the_minimax_residual_polynomial(a, b):
+    """1 - t p*(t) equioscillates on [a, b] with amplitude 1/T_9(s0)
+    (Chebyshev's minimax theorem), p* > 0 on [0, b], and the loss's form is
+    0 at c* and 1 at c = 0."""
+    G, h, aa, cstar = LO.label_gram(a / 3.0, b)
+    assert aa == pytest.approx(a, rel=1e-15)
+    s0 = (b + a) / (b - a)
+    amp = 1.0 / math.cosh(9 * math.acosh(s0))
+    t = np.linspace(a, b, 4001)
+    q = 1 - t * oracle.poly_eval(cstar, t, b)
+    assert np.max(np.abs(q)) == pytest.approx(amp, rel=1e-8)
+    # ten alternation points: the extrema of T_9 on [a, b]
+    ext = 0.5 * (b + a) - 0.5 * (b - a) * np.cos(np.arange(10) * math.pi / 9)
+    qe = 1 - ext * oracle.poly_eval(cstar, ext, b)
+    assert np.allclose(np.abs(qe), amp, rtol=1e-8) and np.all(qe[1:] * qe[:-1] < 0)
+    assert np.all(oracle.poly_eval(cstar, np.linspace(0, b, 2001), b) > 0)
+    assert cstar @ G @ cstar - 2 * h @ cstar + 1 == pytest.approx(0.0, abs=1e-12)
+    assert np.linalg.eigvalsh(G).min() > 0
