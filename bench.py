@@ -9,7 +9,10 @@ device-side convergence test fires) with A, b and x resident in HBM.  Timing
 follows the paper's protocol (Section 4.1): warm-up solves, then K timed
 solves bracketed by device synchronisation; solves/s = K / elapsed.
 
-Also reported on the same JSON line:
+Also reported on the same JSON line (under "extra"): the 256-system batch
+(one batched launch against a per-solve loop), the learned polynomial
+preconditioner (FCG(1) with the network's polynomial against Jacobi-PCG on
+held-out systems), and:
   roofline      -- the fused product kernel (SpMV + direction update + p.Ap):
                    algorithmic bytes per launch / mean launch duration, the
                    duration taken with HIP events on the solve's stream by a
@@ -131,6 +134,118 @@ def bench_batch(apcg, torch, reps):
     return out
 
 
+def learned_systems(count, seed, lo, hi, workers):
+    """The learned-PC workload's systems, generated on the host (in worker
+    processes when there are many: generation is numpy-bound)."""
+    from paper_2306_17801_amd import problems
+
+    if workers <= 1 or count < 64:
+        return problems.learned_pc_set(count, seed, lo, hi)
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    # the same per-system seeds as one call: SeedSequence(seed).spawn(count)
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(problems.learned_pc_system, [(seed, i, count, lo, hi) for i in range(count)],
+                           chunksize=8))
+
+
+def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, workers):
+    """Learned polynomial preconditioner: 3D 7-point systems, side ~
+    U{side_lo..side_hi}, sigma ~ U[0.5, 2], anisotropy ~ log-U[1, 100]
+    (training seed 4, held-out seed 40).  Features and labels on the GPU,
+    training with the library's MLP kernels, then each held-out system solved
+    at rtol 1e-8 by Jacobi-PCG (the plain path), FCG(1) with the network's
+    polynomial (features + network + solve, one call) and FCG(1) with a fixed
+    Chebyshev polynomial on [lmax/100, lmax]."""
+    import numpy as np
+    from numpy.polynomial import chebyshev as Ch
+
+    from paper_2306_17801_amd import learned as L
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    t0 = time.perf_counter()
+    train_set = learned_systems(n_train, 4, side_lo, side_hi, workers)
+    eval_set = learned_systems(n_eval, 40, side_lo, side_hi, workers)
+    t_gen = time.perf_counter() - t0
+    ctx = apcg.apcg_ctx_create(0)
+    t0 = time.perf_counter()
+    dtrain = L.collect(ctx, train_set)
+    t_collect = time.perf_counter() - t0
+    del train_set
+    deval = L.collect(ctx, eval_set)
+    t0 = time.perf_counter()
+    pc, losses = L.train(ctx, dtrain, epochs=epochs, batch=32, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    untrained, _ = L.train(ctx, dtrain, epochs=0)
+    out = {"train_systems": n_train, "eval_systems": n_eval, "sides": [side_lo, side_hi], "epochs": epochs,
+           "generate_s": round(t_gen, 1), "collect_s": round(t_collect, 2), "train_s": round(t_train, 3),
+           "train_steps": int(losses.size),
+           "heldout_loss_trained": L.mean_loss(ctx, pc, deval), "heldout_loss_untrained": L.mean_loss(ctx, untrained, deval)}
+    log(f"[bench] learned: generated {t_gen:.1f}s, collected {t_collect:.1f}s, trained {t_train:.2f}s")
+
+    T9 = [0] * 9 + [1]
+
+    def control(lmax):
+        a = lmax / 100
+        s0 = (lmax + a) / (lmax - a)
+        f = lambda y: (1 - Ch.chebval((lmax + a - 2 * (y + 1) * lmax / 2) / (lmax - a), T9) /
+                       Ch.chebval(s0, T9)) / ((y + 1) * lmax / 2)
+        return Ch.chebinterpolate(f, 8).astype(np.float32)
+
+    info = apcg.apcg_info_create(0, 1)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    tot = {"jacobi": 0.0, "learned": 0.0, "control": 0.0}
+    its = {k: [] for k in tot}
+    fallbacks = 0
+    unconverged = 0
+    for s in eval_set:
+        dA, db, dx = DeviceCSR(s.A), DeviceVec(s.b), DeviceVec.zeros(s.A.n)
+        feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
+        lm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
+        torch.cuda.synchronize()
+        apcg.apcg_pc_features(ctx, dA.h, db.h, feat, lm)
+        apcg.apcg_ctx_synchronize(ctx)
+        cc = torch.from_numpy(control(float(lm.cpu()[0]))).to("cuda:0")
+        torch.cuda.synchronize()
+        runs = {
+            "jacobi": lambda: apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, 1e-8, 50000, opts, info, 0),
+            "learned": lambda: L.solve(ctx, pc, dA.h, db.h, dx.h, 1e-8, 50000, opts, None, info, 0),
+            "control": lambda: apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, dx.h, 1e-8, 50000, cc, lm, opts,
+                                                             None, info, 0),
+        }
+        for k, run in runs.items():
+            run()  # warm-up (graph capture)
+            apcg.apcg_ctx_synchronize(ctx)
+            t1 = time.perf_counter()
+            for _ in range(reps):
+                run()
+            apcg.apcg_ctx_synchronize(ctx)
+            tot[k] += (time.perf_counter() - t1) / reps
+            r = apcg.apcg_info_get(info, 0)
+            its[k].append(r["iterations"])
+            if not r["status"] & apcg.APCG_SOLVE_CONVERGED:
+                unconverged += 1
+            if k == "learned" and r["status"] & apcg.APCG_SOLVE_FALLBACK:
+                fallbacks += 1
+        dA.close()
+        db.close()
+        dx.close()
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_synchronize(ctx)
+    apcg.apcg_ctx_destroy(ctx)
+    for k in tot:
+        out[f"{k}_mean_iterations"] = round(float(np.mean(its[k])), 2)
+        out[f"{k}_ms_per_solve"] = round(1000 * tot[k] / n_eval, 4)
+        out[f"{k}_solves_per_s"] = round(n_eval / tot[k], 3)
+    out["learned_speedup_vs_jacobi"] = round(tot["jacobi"] / tot["learned"], 3)
+    out["learned_speedup_vs_control"] = round(tot["control"] / tot["learned"], 3)
+    out["learned_fallbacks"] = fallbacks
+    out["unconverged"] = unconverged
+    log(f"[bench] learned: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -142,6 +257,14 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched measurement")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
+    ap.add_argument("--learned-train", type=int, default=128, help="training systems (the full workload: 2000)")
+    ap.add_argument("--learned-eval", type=int, default=16, help="held-out systems (the full workload: 200)")
+    ap.add_argument("--learned-sides", type=int, nargs=2, default=[32, 64],
+                    help="side range of the learned workload (the full workload: 32 96)")
+    ap.add_argument("--learned-epochs", type=int, default=300)
+    ap.add_argument("--learned-reps", type=int, default=3)
+    ap.add_argument("--workers", type=int, default=8, help="host processes generating the learned systems")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -271,6 +394,11 @@ def main():
 
     if not args.no_batch:
         extra["batch2d_256"] = bench_batch(apcg, torch, args.batch_reps)
+
+    if not args.no_learned:
+        extra["learned_pc"] = bench_learned(apcg, torch, args.learned_train, args.learned_eval,
+                                            args.learned_sides[0], args.learned_sides[1], args.learned_epochs,
+                                            args.learned_reps, args.workers)
 
     cpu = None
     if not args.no_cpu_baseline:

@@ -231,19 +231,31 @@ def batch2d_lognormal(count: int = 256, seed: int = 3, side_lo: int = 32, side_h
     return out
 
 
+def _learned_pc_from(child, index: int, side_lo: int, side_hi: int) -> System:
+    rng = np.random.default_rng(child)
+    side = int(rng.integers(side_lo, side_hi + 1))
+    sigma = float(rng.uniform(0.5, 2.0))
+    aniso = float(math.exp(rng.uniform(0.0, math.log(100.0))))
+    s = _lognormal_system(rng, 3, side, sigma, aniso)
+    s.meta["index"] = index
+    return s
+
+
 def learned_pc_set(count: int, seed: int, side_lo: int = 32, side_hi: int = 96) -> list[System]:
     """3D 7-point systems for the learned preconditioner: side ~ U{32..96},
-    sigma ~ U[0.5, 2], anisotropy ~ log-U[1, 100]."""
-    out = []
-    for i, child in enumerate(np.random.SeedSequence(seed).spawn(count)):
-        rng = np.random.default_rng(child)
-        side = int(rng.integers(side_lo, side_hi + 1))
-        sigma = float(rng.uniform(0.5, 2.0))
-        aniso = float(math.exp(rng.uniform(0.0, math.log(100.0))))
-        s = _lognormal_system(rng, 3, side, sigma, aniso)
-        s.meta["index"] = i
-        out.append(s)
-    return out
+    sigma ~ U[0.5, 2], anisotropy ~ log-U[1, 100]; system i draws from child
+    i of SeedSequence(seed)."""
+    return [_learned_pc_from(child, i, side_lo, side_hi)
+            for i, child in enumerate(np.random.SeedSequence(seed).spawn(count))]
+
+
+def learned_pc_system(args) -> System:
+    """System ``index`` of ``learned_pc_set(count, seed, side_lo, side_hi)``
+    alone (args = (seed, index, count, side_lo, side_hi)), for generating a
+    set in several processes."""
+    seed, index, count, side_lo, side_hi = args
+    # child i of SeedSequence(seed).spawn(...) is SeedSequence(seed, spawn_key=(i,))
+    return _learned_pc_from(np.random.SeedSequence(seed, spawn_key=(index,)), index, side_lo, side_hi)
 
 
 def mixed_batch_params(count: int = 1024, seed: int = 5, n_lo: float = 1e3, n_hi: float = 1e6):

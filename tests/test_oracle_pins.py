@@ -472,3 +472,12 @@ def test_fcg_precheck_rejects_polynomial_negative_on_the_enclosure():
     c[0] = 0.8  # p = 0.8 - 0.5 y > 0 on y in [-1, 1]
     g = oracle.fcg_poly(A, b, c, 2.0, rtol=1e-8, maxit=5000)
     assert g.status == oracle.CONVERGED and g.fcg_its == g.its > 0
+
+
+def test_learned_pc_system_is_the_sets_member():
+    """One system drawn alone equals the same index of the whole set."""
+    full = P.learned_pc_set(6, 4, 8, 12)
+    for i in (0, 3, 5):
+        s = P.learned_pc_system((4, i, 6, 8, 12))
+        assert np.array_equal(s.A.val, full[i].A.val) and np.array_equal(s.b, full[i].b)
+        assert s.meta == full[i].meta
