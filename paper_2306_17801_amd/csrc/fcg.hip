@@ -9,10 +9,14 @@
 // beta = -(z_{k+1} . w_k) / (p_k . w_k), which keeps the search directions
 // A-orthogonal when P is applied inexactly (FP32-derived coefficients).
 //
-// One iteration is 13 kernels: product, alpha, update, check, eight
-// Clenshaw steps (the last forms z and the partials of r.z and z.w), beta.
-// The scalar steps run in one-workgroup kernels that add the producer's
-// partials in a fixed order; the stop flag makes every later kernel a no-op.
+// One iteration is 10 kernels: product (p = z + beta p_old, w = A p, p.w),
+// update (x, r, ||r||^2), and eight Clenshaw steps (the last forms z and
+// r.z, z.w).  No scalar kernels: each kernel's workgroups re-add the
+// previous kernel's per-workgroup partials in a fixed order and all obtain
+// the same scalars (beta and the r.z breakdown test in the product, alpha
+// and the p.w breakdown test in the update, the convergence / stall / maxit
+// test in the first Clenshaw step); workgroup 0 records them in the state,
+// and the stop flag makes every later kernel a no-op.
 // Before the first iteration p is evaluated on 1024 points of [0, lmax]; a
 // value <= 0 (the preconditioner would not be SPD) stops the flexible phase
 // at once.  A breakdown, that rejection, or a stall (no new minimum of ||r||
@@ -31,14 +35,34 @@ namespace {
 
 constexpr int TBF = 256;
 constexpr int DEG = 8;
+// slices of the context's partials buffer (kMaxBlocks doubles each)
+constexpr int S_INIT = 0, S_DELTA = 1, S_RES = 2, S_RZ = 3;
+
+// Workgroups and rows per workgroup of the FCG kernels: at most 1024
+// workgroups, so that re-adding a kernel's partials stays short.
+void fcg_grid(int64_t n, int *G, int64_t *per_block) {
+    *G = normalise_blocks(1024, (n + 63) / 64);
+    const int64_t pb = (n + *G - 1) / *G;
+    *per_block = std::max<int64_t>(64, ((pb + 63) / 64) * 64);
+}
+
+// Per-iteration test state, double-buffered by iteration parity: the
+// kernel that runs the test for iteration k reads record (k - 1) & 1 and
+// writes record k & 1, so no workgroup reads what another workgroup of the
+// same kernel writes.
+struct FcgRec {
+    double res, best_res;
+    int32_t its, best_its;
+};
 
 struct FcgState {
     double c[DEG + 1];
     double lmax;
     double rho, delta, alpha, beta;
-    double res, ref, best_res, rtol;
+    double ref, rtol;
     double stall_frac;
-    int32_t its, best_its, maxit, stall_min;
+    FcgRec rec[2];
+    int32_t maxit, stall_min;
     int32_t status, flag, zero_x, reject;
 };
 static_assert(sizeof(FcgState) <= 512, "FCG state exceeds its allocation");
@@ -136,12 +160,10 @@ __global__ __launch_bounds__(64) void k_fcg_init_final(FcgState *st, const doubl
     for (int j = 0; j <= DEG; ++j) s.c[j] = cc[j];
     s.lmax = lm;
     s.ref = sqrt(v[0]);
-    s.res = sqrt(v[1]);
-    s.best_res = s.res;
+    const double res0 = sqrt(v[1]);
     s.rtol = rtol;
     s.stall_frac = stall_frac;
-    s.its = 0;
-    s.best_its = 0;
+    for (int k = 0; k < 2; ++k) s.rec[k] = FcgRec{res0, res0, 0, 0};
     s.maxit = maxit;
     s.stall_min = stall_min;
     s.rho = s.delta = s.alpha = s.beta = 0.0;
@@ -152,9 +174,9 @@ __global__ __launch_bounds__(64) void k_fcg_init_final(FcgState *st, const doubl
     else if (s.ref == 0.0) {
         status = APCG_SOLVE_CONVERGED;
         s.zero_x = 1;
-        s.res = 0.0;
-    } else if (!isfinite(s.res) || !isfinite(s.ref)) status = APCG_SOLVE_NAN;
-    else if (s.res <= rtol * s.ref) status = APCG_SOLVE_CONVERGED;
+        s.rec[0].res = s.rec[1].res = 0.0;
+    } else if (!isfinite(res0) || !isfinite(s.ref)) status = APCG_SOLVE_NAN;
+    else if (res0 <= rtol * s.ref) status = APCG_SOLVE_CONVERGED;
     else if (bad_point || !(lm > 0.0) || !isfinite(lm)) {
         status = APCG_SOLVE_BREAKDOWN_RZ;  // the preconditioner is not positive on [0, lmax]
         s.reject = 1;
@@ -171,15 +193,52 @@ __global__ __launch_bounds__(TBF) void k_fcg_zero_x_if(double *__restrict__ x, i
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBF) x[i] = 0.0;
 }
 
+// Convergence, stall and iteration-cap test after an update, from the
+// update's ||r||^2 partials (every workgroup decides alike; workgroup 0
+// records).  Returns true when the solve stops.
+__device__ bool fcg_check(FcgState *st, const double *part_res, int G, int parity) {
+    double v[1];
+    dev::reduce_partials<TBF, 1>(part_res, G, v);
+    const double res = sqrt(v[0]);
+    const FcgRec prev = st->rec[parity ^ 1];
+    FcgRec cur{res, prev.best_res, prev.its + 1, prev.best_its};
+    int status = 0;
+    if (!isfinite(res)) status = APCG_SOLVE_NAN;
+    else if (res <= st->rtol * st->ref) status = APCG_SOLVE_CONVERGED;
+    else {
+        if (res < cur.best_res) {
+            cur.best_res = res;
+            cur.best_its = cur.its;
+        } else {
+            double win = st->stall_frac * (double)cur.its;
+            if (win < (double)st->stall_min) win = (double)st->stall_min;
+            if ((double)(cur.its - cur.best_its) >= win) status = APCG_SOLVE_STALL;
+        }
+        if (!status && cur.its >= st->maxit) status = APCG_SOLVE_MAXIT;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->rec[parity] = cur;
+        if (status) {
+            st->status = status;
+            st->flag = 1;
+        }
+    }
+    return status != 0;
+}
+
 // One Clenshaw step.  stage: 0 = first (j = DEG-1), 1 = middle, 2 = last
-// (forms z and the partials of r.z and z.w).
+// (forms z and the partials of r.z and z.w).  check != 0 (inside the
+// iteration): the first step first runs the test above for the iteration of
+// the given parity.
 __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, const int32_t *__restrict__ rowptr,
                                               const int32_t *__restrict__ col, const double *__restrict__ val,
                                               const double *__restrict__ r, const double *__restrict__ dinv,
                                               const double *__restrict__ bj1, const double *__restrict__ bj2,
                                               double *__restrict__ out, const double *__restrict__ w,
-                                              const FcgState *st, int j, int stage, double *part, int64_t per_block) {
+                                              FcgState *st, int j, int stage, int check, int parity,
+                                              double *partials, int64_t per_block) {
     if (st->flag) return;
+    if (check && fcg_check(st, partials + (size_t)S_RES * kMaxBlocks, gridDim.x, parity)) return;
     const double s2 = 2.0 / st->lmax;
     const double cj = st->c[j], cd = st->c[DEG];
     const dev::Chunk ch = dev::block_chunk(n, per_block);
@@ -205,32 +264,40 @@ __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, const int32_t *__restri
         }
         out[i] = res;
     }
-    if (stage == 2) dev::store_partials<TBF, 2>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+    if (stage == 2)
+        dev::store_partials<TBF, 2>(v, partials + (size_t)S_RZ * kMaxBlocks, gridDim.x,
+                                    dev::xcd_block(blockIdx.x, gridDim.x));
 }
 
-// rho0 = r.z after the first preconditioner application.
-__global__ __launch_bounds__(64) void k_fcg_rho0(FcgState *st, const double *part, int G) {
-    if (st->flag) return;
-    double v[2];
-    dev::reduce_partials<64, 2>(part, G, v);
-    if (threadIdx.x != 0) return;
-    const double rho = v[0];
-    if (!(rho > 0.0)) {
-        st->status = isfinite(rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
-        st->flag = 1;
-        return;
-    }
-    st->rho = rho;
-    st->beta = 0.0;
-}
-
+// p = z + beta p_old, w = A p and the partials of p.w.  Prologue: r.z and
+// z.w of the last preconditioner application give rho and, after the first
+// iteration, beta = -(z.w) / delta_prev (FCG(1)); r.z <= 0 is a breakdown.
 __global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, const int32_t *__restrict__ rowptr,
                                                      const int32_t *__restrict__ col, const double *__restrict__ val,
                                                      const double *__restrict__ z, const double *__restrict__ pold,
                                                      double *__restrict__ pnew, double *__restrict__ w,
-                                                     const FcgState *st, double *part, int64_t per_block) {
+                                                     FcgState *st, int parity, double *partials,
+                                                     int64_t per_block) {
     if (st->flag) return;
-    const double beta = st->beta;
+    double rz[2];
+    dev::reduce_partials<TBF, 2>(partials + (size_t)S_RZ * kMaxBlocks, gridDim.x, rz);
+    // no iteration done yet: z.w of the first application is not used (w unset)
+    const bool first = st->rec[parity ^ 1].its == 0;
+    int status = 0;
+    double beta = 0.0;
+    if (!isfinite(rz[0]) || (!first && !isfinite(rz[1]))) status = APCG_SOLVE_NAN;
+    else if (!(rz[0] > 0.0)) status = APCG_SOLVE_BREAKDOWN_RZ;
+    else if (!first) beta = -rz[1] / st->delta;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        if (status) {
+            st->status = status;
+            st->flag = 1;
+        } else {
+            st->rho = rz[0];
+            st->beta = beta;
+        }
+    }
+    if (status) return;
     const dev::Chunk ch = dev::block_chunk(n, per_block);
     double v[1] = {0.0};
     for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
@@ -241,29 +308,31 @@ __global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, const int32_t *_
         w[i] = sum;
         v[0] = fma(pi, sum, v[0]);
     }
-    dev::store_partials<TBF, 1>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
+    dev::store_partials<TBF, 1>(v, partials + (size_t)S_DELTA * kMaxBlocks, gridDim.x,
+                                dev::xcd_block(blockIdx.x, gridDim.x));
 }
 
-__global__ __launch_bounds__(64) void k_fcg_alpha(FcgState *st, const double *part, int G) {
-    if (st->flag) return;
-    double v[1];
-    dev::reduce_partials<64, 1>(part, G, v);
-    if (threadIdx.x != 0) return;
-    const double delta = v[0];
-    st->delta = delta;
-    if (!(delta > 0.0)) {
-        st->status = isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN;
-        st->flag = 1;
-    } else {
-        st->alpha = st->rho / delta;
-    }
-}
-
+// x += alpha p, r -= alpha w and the partials of ||r||^2.  Prologue:
+// delta = p.w (a breakdown when <= 0) and alpha = rho / delta.
 __global__ __launch_bounds__(TBF) void k_fcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                     const double *__restrict__ p, const double *__restrict__ w,
-                                                    const FcgState *st, double *part, int64_t per_block) {
+                                                    FcgState *st, double *partials, int64_t per_block) {
     if (st->flag) return;
-    const double alpha = st->alpha;
+    double d[1];
+    dev::reduce_partials<TBF, 1>(partials + (size_t)S_DELTA * kMaxBlocks, gridDim.x, d);
+    const double delta = d[0];
+    const int status = !(delta > 0.0) ? (isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN) : 0;
+    const double alpha = status ? 0.0 : st->rho / delta;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        st->delta = delta;
+        if (status) {
+            st->status = status;
+            st->flag = 1;
+        } else {
+            st->alpha = alpha;
+        }
+    }
+    if (status) return;
     const dev::Chunk ch = dev::block_chunk(n, per_block);
     double v[1] = {0.0};
     for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
@@ -272,72 +341,27 @@ __global__ __launch_bounds__(TBF) void k_fcg_update(int64_t n, double *__restric
         r[i] = ri;
         v[0] = fma(ri, ri, v[0]);
     }
-    dev::store_partials<TBF, 1>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
-}
-
-__global__ __launch_bounds__(64) void k_fcg_check(FcgState *st, const double *part, int G) {
-    if (st->flag) return;
-    double v[1];
-    dev::reduce_partials<64, 1>(part, G, v);
-    if (threadIdx.x != 0) return;
-    const double res = sqrt(v[0]);
-    const int its = st->its + 1;
-    st->its = its;
-    st->res = res;
-    int status = 0;
-    if (!isfinite(res)) status = APCG_SOLVE_NAN;
-    else if (res <= st->rtol * st->ref) status = APCG_SOLVE_CONVERGED;
-    else {
-        if (res < st->best_res) {
-            st->best_res = res;
-            st->best_its = its;
-        } else {
-            double win = st->stall_frac * (double)its;
-            if (win < (double)st->stall_min) win = (double)st->stall_min;
-            if ((double)(its - st->best_its) >= win) status = APCG_SOLVE_STALL;
-        }
-        if (!status && its >= st->maxit) status = APCG_SOLVE_MAXIT;
-    }
-    if (status) {
-        st->status = status;
-        st->flag = 1;
-    }
-}
-
-__global__ __launch_bounds__(64) void k_fcg_beta(FcgState *st, const double *part, int G) {
-    if (st->flag) return;
-    double v[2];
-    dev::reduce_partials<64, 2>(part, G, v);
-    if (threadIdx.x != 0) return;
-    const double rho_new = v[0], zeta = v[1];
-    if (!isfinite(rho_new) || !isfinite(zeta)) {
-        st->status = APCG_SOLVE_NAN;
-        st->flag = 1;
-    } else if (!(rho_new > 0.0)) {
-        st->status = APCG_SOLVE_BREAKDOWN_RZ;
-        st->flag = 1;
-    } else {
-        st->beta = -zeta / st->delta;
-        st->rho = rho_new;
-    }
+    dev::store_partials<TBF, 1>(v, partials + (size_t)S_RES * kMaxBlocks, gridDim.x,
+                                dev::xcd_block(blockIdx.x, gridDim.x));
 }
 
 // Writes the result record; with a fallback solve, adds its iterations.
 __global__ void k_fcg_finish(const FcgState *st, const apcg_solve_info *fallback, apcg_solve_info *out) {
     if (threadIdx.x != 0) return;
     int status = st->status ? st->status : APCG_SOLVE_MAXIT;
+    const FcgRec last = st->rec[0].its >= st->rec[1].its ? st->rec[0] : st->rec[1];
     apcg_solve_info o;
-    o.fcg_iterations = st->its;
+    o.fcg_iterations = last.its;
     o.reserved = 0;
     o.ref_norm = st->ref;
     if (fallback) {
-        o.iterations = st->its + fallback->iterations;
+        o.iterations = last.its + fallback->iterations;
         o.status = fallback->status | APCG_SOLVE_FALLBACK | status;
         o.res_norm = fallback->res_norm;
     } else {
-        o.iterations = st->its;
+        o.iterations = last.its;
         o.status = status;
-        o.res_norm = st->res;
+        o.res_norm = last.res;
     }
     *out = o;
 }
@@ -471,24 +495,26 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
         const int64_t cap = fc->cap;
         double *r = fc->ws, *dinv = fc->ws + cap, *z = fc->ws + 2 * cap, *pb[2] = {fc->ws + 3 * cap, fc->ws + 4 * cap};
         double *w = fc->ws + 5 * cap, *t[3] = {fc->ws + 6 * cap, fc->ws + 7 * cap, fc->ws + 8 * cap};
-        double *part = ctx->partials;
+        double *part = ctx->partials;  // slices S_INIT, S_DELTA, S_RES, S_RZ
         int G;
         int64_t pbk;
-        elementwise_grid(n, &G, &pbk);
+        fcg_grid(n, &G, &pbk);
         const int x0z = opts.x0_is_zero ? 1 : 0;
 
         hipLaunchKernelGGL(k_fcg_init, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d, r, dinv,
-                           pb[0], part, pbk, x0z);
+                           pb[0], part + (size_t)S_INIT * kMaxBlocks, pbk, x0z);
         APCG_CHECK_LAUNCH("k_fcg_init");
-        hipLaunchKernelGGL(k_fcg_init_final, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G, dev_coeffs,
-                           dev_lmax, rtol, maxit, fo.stall_min, fo.stall_frac);
+        hipLaunchKernelGGL(k_fcg_init_final, dim3(1), dim3(64), 0, st, fc->st,
+                           (const double *)(part + (size_t)S_INIT * kMaxBlocks), G, dev_coeffs, dev_lmax, rtol, maxit,
+                           fo.stall_min, fo.stall_frac);
         APCG_CHECK_LAUNCH("k_fcg_init_final");
         if (!x0z) {
             hipLaunchKernelGGL(k_fcg_zero_x_if, dim3(G), dim3(TBF), 0, st, x->d, n, pbk, (const FcgState *)fc->st);
             APCG_CHECK_LAUNCH("k_fcg_zero_x_if");
         }
-        // z = P r: b_7 -> t[7%3], ..., b_1 -> t[1%3], z
-        auto precondition = [&]() -> apcg_status {
+        // z = P r: b_7 -> t[7%3], ..., b_1 -> t[1%3], z.  check: the first
+        // step runs the test of the iteration (parity) that just updated r.
+        auto precondition = [&](int check, int parity) -> apcg_status {
             for (int j = DEG - 1; j >= 0; --j) {
                 const int stage = j == DEG - 1 ? 0 : (j == 0 ? 2 : 1);
                 const double *bj1 = stage == 0 ? nullptr : t[(j + 1) % 3];
@@ -496,34 +522,26 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
                 double *outp = stage == 2 ? z : t[j % 3];
                 hipLaunchKernelGGL(k_cheb, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val,
                                    (const double *)r, (const double *)dinv, bj1, bj2, outp, (const double *)w,
-                                   (const FcgState *)fc->st, j, stage, part, pbk);
+                                   fc->st, j, stage, stage == 0 ? check : 0, parity, part, pbk);
                 APCG_CHECK_LAUNCH("k_cheb");
             }
             return APCG_SUCCESS;
         };
-        // the first application (z0; w is not read in the zeta partials used)
-        if ((s = precondition())) return s;
-        hipLaunchKernelGGL(k_fcg_rho0, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
-        APCG_CHECK_LAUNCH("k_fcg_rho0");
+        // the first application (z0); its r.z is checked by the first product
+        if ((s = precondition(0, 0))) return s;
 
+        // iteration k (parity k & 1; K is even, so the parity of the k-th
+        // iteration of a captured period is that of the global iteration)
         auto iteration = [&](int k) -> apcg_status {
             const double *pold = pb[(k + 1) & 1];
             double *pnew = pb[k & 1];
             hipLaunchKernelGGL(k_fcg_product, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val,
-                               (const double *)z, pold, pnew, w, (const FcgState *)fc->st, part, pbk);
+                               (const double *)z, pold, pnew, w, fc->st, k & 1, part, pbk);
             APCG_CHECK_LAUNCH("k_fcg_product");
-            hipLaunchKernelGGL(k_fcg_alpha, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
-            APCG_CHECK_LAUNCH("k_fcg_alpha");
             hipLaunchKernelGGL(k_fcg_update, dim3(G), dim3(TBF), 0, st, n, x->d, r, (const double *)pnew,
-                               (const double *)w, (const FcgState *)fc->st, part, pbk);
+                               (const double *)w, fc->st, part, pbk);
             APCG_CHECK_LAUNCH("k_fcg_update");
-            hipLaunchKernelGGL(k_fcg_check, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
-            APCG_CHECK_LAUNCH("k_fcg_check");
-            apcg_status ps = precondition();
-            if (ps) return ps;
-            hipLaunchKernelGGL(k_fcg_beta, dim3(1), dim3(64), 0, st, fc->st, (const double *)part, G);
-            APCG_CHECK_LAUNCH("k_fcg_beta");
-            return APCG_SUCCESS;
+            return precondition(1, k & 1);
         };
 
         if (maxit > 0) {
@@ -554,7 +572,7 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
                         return cs;
                     }
                     if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(fcg)");
-                    g_counters.kernel_launches -= (int64_t)(4 + DEG + 1) * K;
+                    g_counters.kernel_launches -= (int64_t)(2 + DEG) * K;
                     e = hipGraphInstantiate(&fc->exec, g, nullptr, nullptr, 0);
                     if (e != hipSuccess) {
                         hipGraphDestroy(g);
@@ -602,6 +620,7 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
             APCG_HIP(hipMemcpyAsync(&hs, fc->st, sizeof hs, hipMemcpyDeviceToHost, st));
             APCG_HIP(hipStreamSynchronize(st));
             const int bad = APCG_SOLVE_BREAKDOWN_PAP | APCG_SOLVE_BREAKDOWN_RZ | APCG_SOLVE_STALL;
+            const int32_t done = std::max(hs.rec[0].its, hs.rec[1].its);
             if ((hs.status & bad) && !(hs.status & APCG_SOLVE_SETUP_ERROR)) {
                 apcg_solve_opts po;
                 apcg_solve_opts_default(&po);
@@ -609,7 +628,7 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
                 po.iters_per_graph = opts.iters_per_graph;
                 po.lookahead = opts.lookahead;
                 po.x0_is_zero = 0;
-                const int32_t left = std::max(0, maxit - hs.its);
+                const int32_t left = std::max(0, maxit - done);
                 if ((s = pcg_solve_marked(ctx, A, b, x, rtol, left, &po, fc->fb_info, 0, nullptr, 0))) return s;
                 fb = fc->fb_info->d;
             }

@@ -3,8 +3,8 @@
 //   * features of one system: row statistics of A, Gershgorin bounds of
 //     D^-1 A, and the Ritz values of the Lanczos tridiagonal that 12
 //     Jacobi-PCG iterations build (the CG-Lanczos relation; the iterations
-//     run on the solve kernels, the tridiagonal's eigenproblem on one device
-//     thread with cyclic Jacobi rotations);
+//     run on the solve kernels, the tridiagonal's eigenvalues by Sturm-count
+//     bisection, one thread per eigenvalue);
 //   * the training label of one system: the smallest Ritz value lmin of its
 //     full Jacobi-PCG solve (Sturm-sequence multisection on the tridiagonal
 //     of all iterations), a = 3 lmin clamped to [1e-6 lmax, lmax / 2], and
@@ -132,7 +132,7 @@ __global__ __launch_bounds__(FB) void k_feat_rows2(int32_t n, const int32_t *__r
     dev::store_partials<FB, 1>(v, part, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
 }
 
-__device__ double cheb(int j, double y) {
+__device__ double cheb(int j, double y) {  // T_j(y) by the recurrence, any real y
     double t0 = 1.0, t1 = y;
     if (j == 0) return t0;
     for (int k = 2; k <= j; ++k) {
@@ -141,98 +141,6 @@ __device__ double cheb(int j, double y) {
         t1 = t2;
     }
     return t1;
-}
-
-// Cyclic Jacobi eigen-decomposition of a symmetric m x m matrix (m <= 16) in
-// place: on return the diagonal holds the eigenvalues and V's columns the
-// eigenvectors (Golub & Van Loan, Matrix Computations, the cyclic Jacobi
-// method with the symmetric Schur 2x2 rotation).
-__device__ void jacobi_eigen(double (&A)[16][16], double (&V)[16][16], int m) {  // V: eigenvectors
-    for (int i = 0; i < m; ++i)
-        for (int j = 0; j < m; ++j) V[i][j] = i == j ? 1.0 : 0.0;
-    for (int sweep = 0; sweep < 60; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < m; ++i)
-            for (int j = 0; j < m; ++j) {
-                tot += A[i][j] * A[i][j];
-                if (i != j) off += A[i][j] * A[i][j];
-            }
-        if (off <= 1e-30 * tot) break;
-        for (int p = 0; p < m - 1; ++p)
-            for (int q = p + 1; q < m; ++q) {
-                if (A[p][q] == 0.0) continue;
-                const double tau = (A[q][q] - A[p][p]) / (2.0 * A[p][q]);
-                const double t = (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                const double cs = 1.0 / sqrt(1.0 + t * t), sn = t * cs;
-                for (int k = 0; k < m; ++k) {  // A <- A J (columns p, q)
-                    const double akp = A[k][p], akq = A[k][q];
-                    A[k][p] = cs * akp - sn * akq;
-                    A[k][q] = sn * akp + cs * akq;
-                }
-                for (int k = 0; k < m; ++k) {  // A <- J' A (rows p, q)
-                    const double apk = A[p][k], aqk = A[q][k];
-                    A[p][k] = cs * apk - sn * aqk;
-                    A[q][k] = sn * apk + cs * aqk;
-                }
-                for (int k = 0; k < m; ++k) {  // V <- V J
-                    const double vkp = V[k][p], vkq = V[k][q];
-                    V[k][p] = cs * vkp - sn * vkq;
-                    V[k][q] = sn * vkp + cs * vkq;
-                }
-            }
-    }
-}
-
-// One thread: Lanczos tridiagonal from alpha/beta, its eigenvalues, the 16
-// features (FP32) and lmax (FP64).
-__global__ void k_feat_final(const double *stats, const double *var_part, int Gv, const double *hist, int hist_cap,
-                             const apcg_solve_info *info, int32_t n, int64_t nnz, float *feat,
-                             double *lmax_out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    double var = 0.0;
-    for (int t = 0; t < Gv; ++t) var += var_part[t];
-    const double lo = stats[0], hi = stats[1];
-    int m = info->iterations;
-    if (m > hist_cap) m = hist_cap;
-    if (m > 16) m = 16;
-    double T[16][16], V[16][16];
-    for (int i = 0; i < 16; ++i)
-        for (int j = 0; j < 16; ++j) T[i][j] = 0.0;
-    const double *al = hist, *be = hist + hist_cap;
-    for (int j = 0; j < m; ++j) {
-        T[j][j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
-        if (j + 1 < m) T[j][j + 1] = T[j + 1][j] = sqrt(be[j]) / al[j];
-    }
-    jacobi_eigen(T, V, m);
-    double th[16];
-    for (int i = 0; i < m; ++i) th[i] = T[i][i];
-    for (int i = 1; i < m; ++i)  // insertion sort
-        for (int j = i; j > 0 && th[j] < th[j - 1]; --j) {
-            const double a = th[j];
-            th[j] = th[j - 1];
-            th[j - 1] = a;
-        }
-    const double relres = info->ref_norm > 0.0 ? info->res_norm / info->ref_norm : 1.0;
-    const int top = m - 1;
-    double f[NF];
-    f[0] = log10((double)n);
-    f[1] = (double)nnz / (double)n;
-    f[2] = lo;
-    f[3] = hi;
-    f[4] = (stats[3] - stats[2]) / log(10.0);
-    f[5] = sqrt(var / (double)n);
-    f[6] = stats[6] > 0.0 ? stats[5] / stats[6] : 0.0;
-    // k-th smallest / largest Ritz values; with fewer than three, the index
-    // clamps to the values that exist
-    for (int k = 0; k < 3; ++k) {
-        f[7 + k] = th[k < top ? k : top] / hi;
-        f[10 + k] = th[top - 2 + k > 0 ? top - 2 + k : 0] / hi;
-    }
-    f[13] = log10(th[top] / th[0]);
-    f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
-    f[15] = log10(th[0] / hi);
-    for (int k = 0; k < NF; ++k) feat[k] = (float)f[k];
-    *lmax_out = hi;
 }
 
 // Number of eigenvalues below x of the symmetric tridiagonal with diagonal
@@ -253,15 +161,61 @@ __device__ int sturm_below(const double *al, const double *be, int m, double x) 
     return cnt;
 }
 
-__device__ double cheb_T_at(int j, double s) {  // T_j(s) by the recurrence, any real s
-    double t0 = 1.0, t1 = s;
-    if (j == 0) return t0;
-    for (int k = 2; k <= j; ++k) {
-        const double t2 = 2.0 * s * t1 - t0;
-        t0 = t1;
-        t1 = t2;
+// One workgroup of 64: thread i < m finds the i-th smallest eigenvalue of the
+// Lanczos tridiagonal (the Ritz values) by bisection on the Sturm count
+// inside the tridiagonal's Gershgorin interval; thread 0 then forms the 16
+// features (FP32) and lmax (FP64).
+__global__ __launch_bounds__(64) void k_feat_final(const double *stats, const double *var_part, int Gv,
+                                                   const double *hist, int hist_cap, const apcg_solve_info *info,
+                                                   int32_t n, int64_t nnz, float *feat, double *lmax_out) {
+    int m = info->iterations;
+    if (m > hist_cap) m = hist_cap;
+    if (m > 16) m = 16;
+    const double *al = hist, *be = hist + hist_cap;
+    __shared__ double th[16];
+    const int i = threadIdx.x;
+    if (i < m) {
+        double lo = INFINITY, up = -INFINITY;
+        for (int j = 0; j < m; ++j) {
+            const double d = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+            const double r = (j > 0 ? sqrt(be[j - 1]) / al[j - 1] : 0.0) + (j + 1 < m ? sqrt(be[j]) / al[j] : 0.0);
+            lo = fmin(lo, d - r);
+            up = fmax(up, d + r);
+        }
+        for (int it = 0; it < 128; ++it) {
+            const double mid = 0.5 * (lo + up);
+            if (mid <= lo || mid >= up) break;
+            if (sturm_below(al, be, m, mid) >= i + 1) up = mid;
+            else lo = mid;
+        }
+        th[i] = 0.5 * (lo + up);
     }
-    return t1;
+    __syncthreads();
+    if (i != 0) return;
+    double var = 0.0;
+    for (int t = 0; t < Gv; ++t) var += var_part[t];
+    const double glo = stats[0], hi = stats[1];
+    const double relres = info->ref_norm > 0.0 ? info->res_norm / info->ref_norm : 1.0;
+    const int top = m - 1;
+    double f[NF];
+    f[0] = log10((double)n);
+    f[1] = (double)nnz / (double)n;
+    f[2] = glo;
+    f[3] = hi;
+    f[4] = (stats[3] - stats[2]) / log(10.0);
+    f[5] = sqrt(var / (double)n);
+    f[6] = stats[6] > 0.0 ? stats[5] / stats[6] : 0.0;
+    // k-th smallest / largest Ritz values; with fewer than three, the index
+    // clamps to the values that exist
+    for (int k = 0; k < 3; ++k) {
+        f[7 + k] = th[k < top ? k : top] / hi;
+        f[10 + k] = th[top - 2 + k > 0 ? top - 2 + k : 0] / hi;
+    }
+    f[13] = log10(th[top] / th[0]);
+    f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
+    f[15] = log10(th[0] / hi);
+    for (int k = 0; k < NF; ++k) feat[k] = (float)f[k];
+    *lmax_out = hi;
 }
 
 // One workgroup of 64: the smallest eigenvalue by multisection (each round
@@ -306,14 +260,14 @@ __global__ __launch_bounds__(64) void k_label(const double *stats, const double 
     double a = 0.5 * hi;
     if (m > 0) a = fmin(fmax(LABEL_SHIFT * lmin, 1e-6 * hi), 0.5 * hi);
     // target coefficients
-    const double s0 = (hi + a) / (hi - a), T9s0 = cheb_T_at(9, s0);
+    const double s0 = (hi + a) / (hi - a), T9s0 = cheb(9, s0);
     double cs[NC];
     for (int j = 0; j < NC; ++j) cs[j] = 0.0;
     for (int k = 0; k < NC; ++k) {
         const double y = cos(M_PI * (k + 0.5) / NC);
         const double t = 0.5 * (y + 1.0) * hi;
-        const double pv = (1.0 - cheb_T_at(9, (hi + a - 2.0 * t) / (hi - a)) / T9s0) / t;
-        for (int j = 0; j < NC; ++j) cs[j] += pv * cheb_T_at(j, y);
+        const double pv = (1.0 - cheb(9, (hi + a - 2.0 * t) / (hi - a)) / T9s0) / t;
+        for (int j = 0; j < NC; ++j) cs[j] += pv * cheb(j, y);
     }
     for (int j = 0; j < NC; ++j) cs[j] *= (j == 0 ? 1.0 : 2.0) / NC;
     // G0 over the Gauss-Chebyshev rule on [a, hi]
@@ -696,8 +650,7 @@ static apcg_status features_into(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *de
     apcg_solve_opts o;
     apcg_solve_opts_default(&o);
     o.x0_is_zero = 1;
-    o.mode = APCG_MODE_STREAM;  // a one-off 12-step run: no graph to capture
-    o.iters_per_graph = MSTEPS;
+    o.iters_per_graph = MSTEPS;  // one captured period, cached per matrix like the solve's
     if ((s = pcg_solve_marked(ctx, A, b, &xv, 0.0, MSTEPS, &o, fs->info, 0, fs->hist, MSTEPS))) return s;
     Acc acc[2] = {{&A->rec, ACC_R}, {&b->rec, ACC_R}};
     if ((s = op_begin(ctx, acc, 2))) return s;
