@@ -467,6 +467,21 @@ apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_v
                                     const float *dev_coeffs, const double *dev_lmax, const apcg_solve_opts *opts,
                                     const apcg_fcg_opts *fopts, apcg_info info, int32_t info_index);
 
+/* Solves the nsys independent systems A[i] x[i] = b[i], each with FCG(1) and
+ * its own polynomial (dev_coeffs[nsys][9], float; dev_lmax[nsys], double),
+ * the batch run as one block-diagonal iteration (tiles of 256 rows; K
+ * iterations per captured graph; the host polls a device count of running
+ * systems).  Every system follows apcg_ksp_solve_fcg_poly: the positivity
+ * check, the breakdown and stall tests, and -- with fopts->fallback -- the
+ * switch to Jacobi-PCG from its current x, taken on the device for that
+ * system alone (its status then carries APCG_SOLVE_FALLBACK and the reason).
+ * info[i] receives system i's record.  opts: mode (graph/stream),
+ * iters_per_graph, lookahead, x0_is_zero.  x vectors must be distinct. */
+apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                            const apcg_vec *x, double rtol, int32_t maxit, const float *dev_coeffs,
+                                            const double *dev_lmax, const apcg_solve_opts *opts,
+                                            const apcg_fcg_opts *fopts, apcg_info info);
+
 /* The learned solve in one call: features of (A, b), standardised with
  * dev_mean[16] / dev_std[16], the network dev_params[5833] -> coefficients,
  * then apcg_ksp_solve_fcg_poly with them (same options, result record and

@@ -393,6 +393,21 @@ def apcg_ksp_solve_learned(ctx, A, b, x, rtol: float, maxit: int, params, mean, 
                                                                 po, pf, _h(info), int(info_index)))
 
 
+def apcg_ksp_solve_batched_fcg_poly(ctx, A_list, b_list, x_list, rtol: float, maxit: int, coeffs, lmax, opts=None,
+                                    fopts=None, info=None) -> None:
+    """coeffs: float32[nsys * 9], lmax: float64[nsys] GPU tensors."""
+    n = len(A_list)
+    if len(b_list) != n or len(x_list) != n:
+        raise ValueError("A_list, b_list and x_list must have the same length")
+    arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[int(h) for h in hs])  # noqa: E731
+    po = ctypes.byref(opts) if opts is not None else None
+    pf = ctypes.byref(fopts) if fopts is not None else None
+    check("apcg_ksp_solve_batched_fcg_poly",
+          _L().apcg_ksp_solve_batched_fcg_poly(_h(ctx), n, arr(A_list), arr(b_list), arr(x_list), float(rtol),
+                                               int(maxit), _dptr(coeffs, "float32"), _dptr(lmax, "float64"), po, pf,
+                                               _h(info)))
+
+
 # ------------------------------------------------------------------ timers
 
 def apcg_timer_create() -> int:

@@ -1,0 +1,780 @@
+// batched_fcg.hip -- many FCG(1) solves, each with its own Chebyshev-basis
+// polynomial preconditioner and its own fallback to Jacobi-PCG, run as one
+// segmented (block-diagonal) iteration.
+//
+// Rows of every system are cut into tiles of FT rows (a tile never crosses
+// two systems).  One iteration is thirteen kernels, K iterations per
+// captured graph:
+//   product (tiles)   p = z + beta_s p_old, w = A p, a partial of p.w per tile
+//   alpha   (systems) delta_s from the tiles in order; p.w <= 0 is a breakdown
+//   update  (tiles)   x += alpha_s p, r -= alpha_s w, a partial of ||r||^2
+//   check   (systems) convergence, stall window and iteration cap
+//   cheb x8 (tiles)   Clenshaw steps of z = p_s(D^-1 A) D^-1 r (a system in
+//                     Jacobi mode only forms z = D^-1 r in the last step);
+//                     the last writes partials of r.z and z.w
+//   beta    (systems) FCG(1): beta = -(z.w) / delta; Jacobi mode: the PCG
+//                     beta = (r.z)_new / (r.z)_old; r.z <= 0 is a breakdown
+// A system switches to Jacobi mode -- continuing from its current x with a
+// fresh direction -- when its polynomial is not positive on [0, lmax]
+// (checked first, on 1024 points), on a breakdown, or on a stall, if the
+// fallback is enabled.  A switch, and the first application of the
+// preconditioner, take one "restart" slot: the product, alpha, update and
+// check skip the system, the Clenshaw kernels form its z and the beta kernel
+// starts its recurrence (beta = 0).  Per-system kernels own the per-system
+// state; tile kernels only read it.  A device count of running systems lets
+// the host stop queueing graphs.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstring>
+#include <vector>
+
+#include "internal.h"
+
+namespace apcg {
+namespace {
+
+constexpr int FT = 256;  // rows per tile = threads per tile workgroup
+constexpr int FDEG = 8;
+constexpr int MODE_FLEX = 0, MODE_JACOBI = 1;
+
+struct FSys {
+    const int32_t *rowptr;
+    const int32_t *col;
+    const double *val;
+    const double *b;
+    double *x;
+    double *ws;  // 9 n: r, dinv, z, p0, p1, w, t0, t1, t2
+    int32_t n;
+    int32_t pad;
+};
+
+struct FState {
+    double c[FDEG + 1];
+    double lmax;
+    double rho, delta, alpha, beta;
+    double res, ref, best_res;
+    int32_t its, fcg_its, best_its, status;
+    int32_t flag, mode, restart, reason;
+    int32_t zero_x, pad;
+};
+
+struct FPlan {
+    const FSys *sys;                      // [nsys]
+    const int32_t *tile_sys, *tile_row0;  // [ntiles]
+    const int32_t *sys_tile0;             // [nsys + 1]
+    FState *st;                           // [nsys]
+    double *part;                         // [4][ntiles]
+    unsigned *running;
+    int32_t nsys, ntiles, tiles_per_block;
+    int32_t maxit, stall_min, fallback;
+    double rtol, stall_frac;
+};
+
+__device__ __forceinline__ void ftile_range(const FPlan &P, int *t0, int *t1) {
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    *t0 = lb * P.tiles_per_block;
+    *t1 = min(P.ntiles, *t0 + P.tiles_per_block);
+}
+
+// sum_k a_k u(col_k) over row i's entries; rows of up to 8 entries issue all
+// gathers first (padded slots gather the row's own entry and are not added)
+template <typename F>
+__device__ __forceinline__ double frow(const int32_t *__restrict__ col, const double *__restrict__ val, int s, int e,
+                                       int row, F u) {
+    const int len = e - s;
+    double sum = 0.0;
+    if (len <= 8) {
+        int jj[8];
+        double aa[8], uj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool in = q < len;
+            jj[q] = in ? col[s + q] : row;
+            aa[q] = in ? val[s + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) uj[q] = u(jj[q]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < len) sum = fma(aa[q], uj[q], sum);
+    } else {
+        for (int k = s; k < e; ++k) sum = fma(val[k], u(col[k]), sum);
+    }
+    return sum;
+}
+
+// The tiles of system s, added in index order (one 64-thread workgroup);
+// the result is valid in thread 0.
+template <int NV>
+__device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV]) {
+    __shared__ double lds[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int t = P.sys_tile0[s] + (int)threadIdx.x; t < P.sys_tile0[s + 1]; t += 64) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += P.part[(size_t)(slot0 + k) * P.ntiles + t];
+    }
+    dev::block_sum<64, NV>(v, lds);
+}
+
+template <int NV>
+__device__ __forceinline__ void ftile_store(const FPlan &P, int t, int slot0, double (&v)[NV]) {
+    __shared__ double lds[NV * (FT / 64)];
+    dev::block_sum<FT, NV>(v, lds);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) P.part[(size_t)(slot0 + k) * P.ntiles + t] = v[k];
+    }
+    __syncthreads();
+}
+
+__device__ double fpoly_at(const double *c, double t, double lmax) {  // Clenshaw at one point
+    const double y = 2.0 * t / lmax - 1.0;
+    double b1 = 0.0, b2 = 0.0;
+    for (int j = FDEG; j >= 1; --j) {
+        const double b0 = c[j] + 2.0 * y * b1 - b2;
+        b2 = b1;
+        b1 = b0;
+    }
+    return c[0] + y * b1 - b2;
+}
+
+// Stops system s (thread 0 of its workgroup) with status, adding the fallback
+// bits when it runs in Jacobi mode.
+__device__ void fstop(const FPlan &P, FState *q, int status) {
+    if (q->mode == MODE_JACOBI) status |= APCG_SOLVE_FALLBACK | q->reason;
+    q->status = status;
+    q->flag = 1;
+    atomicSub(P.running, 1u);
+}
+
+// Hands system s over to Jacobi mode (reason: the failed test), or stops it
+// when that is not possible.
+__device__ void fswitch(const FPlan &P, FState *q, int reason) {
+    if (q->mode == MODE_FLEX && P.fallback) {
+        q->mode = MODE_JACOBI;
+        q->reason = reason;
+        q->restart = 1;
+    } else {
+        fstop(P, q, reason);
+    }
+}
+
+__global__ __launch_bounds__(FT) void k_bf_init(FPlan P, int x0_zero) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    for (int t = t0; t < t1; ++t) {
+        const FSys S = P.sys[P.tile_sys[t]];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[3] = {0.0, 0.0, 0.0};  // ||b||^2, ||r||^2, bad diagonals
+        if (i < S.n) {
+            const int64_t n = S.n;
+            double d = 0.0, ax = 0.0;
+            bool found = false;
+            for (int k = S.rowptr[i]; k < S.rowptr[i + 1]; ++k) {
+                const int j = S.col[k];
+                if (j == i) {
+                    d = S.val[k];
+                    found = true;
+                }
+                if (!x0_zero) ax = fma(S.val[k], S.x[j], ax);
+            }
+            const bool ok = found && d > 0.0;
+            const double bi = S.b[i], ri = x0_zero ? bi : bi - ax;
+            S.ws[i] = ri;
+            S.ws[n + i] = ok ? 1.0 / d : 0.0;
+            S.ws[3 * n + i] = 0.0;  // both direction buffers: the first beta is 0
+            S.ws[4 * n + i] = 0.0;
+            if (x0_zero) S.x[i] = 0.0;
+            v[0] = bi * bi;
+            v[1] = ri * ri;
+            v[2] = ok ? 0.0 : 1.0;
+        }
+        ftile_store<3>(P, t, 0, v);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef, const double *lmax) {
+    const int s = blockIdx.x;
+    double v[3];
+    fsys_sum<3>(P, s, 0, v);
+    __shared__ double cc[FDEG + 1];
+    __shared__ int bad_point;
+    if (threadIdx.x <= FDEG) cc[threadIdx.x] = (double)coef[(size_t)s * (FDEG + 1) + threadIdx.x];
+    if (threadIdx.x == 0) bad_point = 0;
+    __syncthreads();
+    const double lm = lmax[s];
+    for (int q = threadIdx.x; q < 1024; q += 64)
+        if (!(fpoly_at(cc, lm * q / 1023.0, lm) > 0.0)) atomicOr(&bad_point, 1);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    FState q;
+    for (int j = 0; j <= FDEG; ++j) q.c[j] = cc[j];
+    q.lmax = lm;
+    q.rho = q.delta = q.alpha = q.beta = 0.0;
+    q.ref = sqrt(v[0]);
+    q.res = sqrt(v[1]);
+    q.best_res = q.res;
+    q.its = q.fcg_its = q.best_its = 0;
+    q.mode = MODE_FLEX;
+    q.restart = 1;  // the first application of the preconditioner
+    q.reason = 0;
+    q.zero_x = 0;
+    q.pad = 0;
+    int status = 0;
+    if (v[2] > 0.0) status = APCG_SOLVE_SETUP_ERROR;
+    else if (q.ref == 0.0) {
+        status = APCG_SOLVE_CONVERGED;
+        q.zero_x = 1;
+        q.res = 0.0;
+    } else if (!isfinite(q.res) || !isfinite(q.ref)) status = APCG_SOLVE_NAN;
+    else if (q.res <= P.rtol * q.ref) status = APCG_SOLVE_CONVERGED;
+    else if (P.maxit <= 0) status = APCG_SOLVE_MAXIT;
+    q.status = status;
+    q.flag = status != 0;
+    if (!q.flag && (bad_point || !(lm > 0.0) || !isfinite(lm))) {
+        // the preconditioner would not be SPD
+        if (P.fallback) {
+            q.mode = MODE_JACOBI;
+            q.reason = APCG_SOLVE_BREAKDOWN_RZ;
+        } else {
+            q.status = APCG_SOLVE_BREAKDOWN_RZ;
+            q.flag = 1;
+        }
+    }
+    P.st[s] = q;
+    if (!q.flag) atomicAdd(P.running, 1u);
+}
+
+__global__ __launch_bounds__(FT) void k_bf_zero_x(FPlan P) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        if (!P.st[s].zero_x) continue;
+        const FSys S = P.sys[s];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        if (i < S.n) S.x[i] = 0.0;
+    }
+}
+
+__global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        const FState *q = P.st + s;
+        if (q->flag || q->restart) continue;  // uniform across the workgroup
+        const double beta = q->beta;
+        const FSys S = P.sys[s];
+        const int64_t n = S.n;
+        const double *z = S.ws + 2 * n;
+        const double *pold = S.ws + (3 + ((parity + 1) & 1)) * n;
+        double *pnew = S.ws + (3 + (parity & 1)) * n;
+        double *w = S.ws + 5 * n;
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[1] = {0.0};
+        if (i < S.n) {
+            const double sum = frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i,
+                                    [&](int j) { return fma(beta, pold[j], z[j]); });
+            const double pi = fma(beta, pold[i], z[i]);
+            pnew[i] = pi;
+            w[i] = sum;
+            v[0] = pi * sum;
+        }
+        ftile_store<1>(P, t, 0, v);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bf_alpha(FPlan P) {
+    const int s = blockIdx.x;
+    FState *q = P.st + s;
+    if (q->flag || q->restart) return;
+    double v[1];
+    fsys_sum<1>(P, s, 0, v);
+    if (threadIdx.x != 0) return;
+    const double delta = v[0];
+    q->delta = delta;
+    if (!(delta > 0.0)) {
+        if (!isfinite(delta)) fstop(P, q, APCG_SOLVE_NAN);
+        else fswitch(P, q, APCG_SOLVE_BREAKDOWN_PAP);
+    } else {
+        q->alpha = q->rho / delta;
+    }
+}
+
+__global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        const FState *q = P.st + s;
+        if (q->flag || q->restart) continue;
+        const double alpha = q->alpha;
+        const FSys S = P.sys[s];
+        const int64_t n = S.n;
+        double *r = S.ws;
+        const double *p = S.ws + (3 + (parity & 1)) * n;
+        const double *w = S.ws + 5 * n;
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[1] = {0.0};
+        if (i < S.n) {
+            S.x[i] = fma(alpha, p[i], S.x[i]);
+            const double ri = fma(-alpha, w[i], r[i]);
+            r[i] = ri;
+            v[0] = ri * ri;
+        }
+        ftile_store<1>(P, t, 1, v);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bf_check(FPlan P) {
+    const int s = blockIdx.x;
+    FState *q = P.st + s;
+    if (q->flag || q->restart) return;
+    double v[1];
+    fsys_sum<1>(P, s, 1, v);
+    if (threadIdx.x != 0) return;
+    const double res = sqrt(v[0]);
+    const int its = q->its + 1;
+    q->its = its;
+    q->res = res;
+    if (q->mode == MODE_FLEX) q->fcg_its = its;
+    if (!isfinite(res)) {
+        fstop(P, q, APCG_SOLVE_NAN);
+        return;
+    }
+    if (res <= P.rtol * q->ref) {
+        fstop(P, q, APCG_SOLVE_CONVERGED);
+        return;
+    }
+    if (q->mode == MODE_FLEX) {
+        if (res < q->best_res) {
+            q->best_res = res;
+            q->best_its = its;
+        } else {
+            double win = P.stall_frac * (double)its;
+            if (win < (double)P.stall_min) win = (double)P.stall_min;
+            if ((double)(its - q->best_its) >= win) {
+                fswitch(P, q, APCG_SOLVE_STALL);
+                if (q->flag) return;
+            }
+        }
+    }
+    if (its >= P.maxit) fstop(P, q, APCG_SOLVE_MAXIT);
+}
+
+// One Clenshaw step of system s's polynomial.  stage 0: b_7 = c_7 v + 2 c_8 Y v;
+// stage 1: b_j = c_j v + 2 Y b_{j+1} - b_{j+2}; stage 2: z = c_0 v + Y b_1 - b_2
+// and the partials of r.z, z.w (Jacobi mode: z = v).  Y = (2/lmax) D^-1 A - I,
+// v = D^-1 r; b_8 = c_8 v is formed where it is needed.
+__global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o_b1, int o_b2, int o_out) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        const FState *q = P.st + s;
+        if (q->flag) continue;
+        const bool jac = q->mode == MODE_JACOBI;
+        if (jac && stage != 2) continue;
+        const FSys S = P.sys[s];
+        const int64_t n = S.n;
+        const double *r = S.ws, *dinv = S.ws + n, *w = S.ws + 5 * n;
+        const double *bj1 = o_b1 >= 0 ? S.ws + (6 + o_b1) * n : nullptr;
+        const double *bj2 = o_b2 >= 0 ? S.ws + (6 + o_b2) * n : nullptr;
+        double *out = o_out >= 0 ? S.ws + (6 + o_out) * n : S.ws + 2 * n;
+        const double s2 = 2.0 / q->lmax, cj = q->c[j], cd = q->c[FDEG];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[2] = {0.0, 0.0};
+        if (i < S.n) {
+            const int rs = S.rowptr[i], re = S.rowptr[i + 1];
+            const double vi = dinv[i] * r[i];
+            double res;
+            if (jac) {
+                res = vi;
+            } else if (stage == 0) {
+                const double av = frow(S.col, S.val, rs, re, i, [&](int k) { return dinv[k] * r[k]; });
+                res = fma(2.0 * cd, s2 * dinv[i] * av - vi, cj * vi);
+            } else {
+                const double au = frow(S.col, S.val, rs, re, i, [&](int k) { return bj1[k]; });
+                const double yu = s2 * dinv[i] * au - bj1[i];
+                const double b2v = bj2 ? bj2[i] : cd * vi;
+                res = stage == 1 ? fma(2.0, yu, cj * vi) - b2v : cj * vi + yu - b2v;
+            }
+            out[i] = res;
+            if (stage == 2) {
+                v[0] = r[i] * res;
+                v[1] = res * w[i];
+            }
+        }
+        if (stage == 2) ftile_store<2>(P, t, 2, v);
+    }
+}
+
+__global__ __launch_bounds__(64) void k_bf_beta(FPlan P) {
+    const int s = blockIdx.x;
+    FState *q = P.st + s;
+    if (q->flag) return;
+    double v[2];
+    fsys_sum<2>(P, s, 2, v);
+    if (threadIdx.x != 0) return;
+    const double rz = v[0], zw = v[1];
+    if (q->restart) {  // a fresh recurrence from the current x
+        if (!isfinite(rz)) fstop(P, q, APCG_SOLVE_NAN);
+        else if (!(rz > 0.0)) fswitch(P, q, APCG_SOLVE_BREAKDOWN_RZ);  // stays in restart when switching
+        else {
+            q->rho = rz;
+            q->beta = 0.0;
+            q->restart = 0;
+        }
+        return;
+    }
+    if (!isfinite(rz) || !isfinite(zw)) fstop(P, q, APCG_SOLVE_NAN);
+    else if (!(rz > 0.0)) fswitch(P, q, APCG_SOLVE_BREAKDOWN_RZ);
+    else {
+        q->beta = q->mode == MODE_FLEX ? -zw / q->delta : rz / q->rho;
+        q->rho = rz;
+    }
+}
+
+__global__ void k_bf_finish(FPlan P, apcg_solve_info *info) {
+    const int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= P.nsys) return;
+    const FState q = P.st[s];
+    int status = q.status;
+    if (!status) status = APCG_SOLVE_MAXIT | (q.mode == MODE_JACOBI ? APCG_SOLVE_FALLBACK | q.reason : 0);
+    info[s].iterations = q.its;
+    info[s].status = status;
+    info[s].fcg_iterations = q.fcg_its;
+    info[s].reserved = 0;
+    info[s].res_norm = q.res;
+    info[s].ref_norm = q.ref;
+}
+
+__global__ void k_bf_reset(unsigned *running) {
+    if (threadIdx.x == 0) *running = 0u;
+}
+
+uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
+    const unsigned char *c = static_cast<const unsigned char *>(p);
+    for (size_t i = 0; i < n; ++i) h = (h ^ c[i]) * 1099511628211ull;
+    return h;
+}
+
+}  // namespace
+
+struct BfCache {
+    int device = 0;
+    FSys *d_sys = nullptr;
+    int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr;
+    FState *d_st = nullptr;
+    double *d_part = nullptr;  // 4 * tiles_cap
+    double *d_ws = nullptr;
+    unsigned *d_running = nullptr;
+    int64_t sys_cap = 0, tiles_cap = 0, ws_cap = 0;
+    uint64_t hash = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    uint64_t graph_hash = 0;
+    int32_t *pinned = nullptr;
+    EventRef poll_ev[kMaxLookahead];
+};
+
+static std::mutex g_bf_mu;
+static std::vector<std::pair<uint64_t, BfCache *>> g_bf;
+
+static BfCache *bf_cache(apcg_ctx c) {
+    std::lock_guard<std::mutex> lk(g_bf_mu);
+    for (auto &p : g_bf)
+        if (p.first == c->id) return p.second;
+    BfCache *b = new BfCache();
+    b->device = c->device;
+    g_bf.emplace_back(c->id, b);
+    return b;
+}
+
+static void bf_free(BfCache &b) {
+    if (b.exec) hipGraphExecDestroy(b.exec);
+    if (b.graph) hipGraphDestroy(b.graph);
+    hipFree(b.d_sys);
+    hipFree(b.d_tile_sys);
+    hipFree(b.d_tile_row0);
+    hipFree(b.d_sys_tile0);
+    hipFree(b.d_st);
+    hipFree(b.d_part);
+    hipFree(b.d_ws);
+    hipFree(b.d_running);
+}
+
+void bfcg_cache_release(uint64_t ctx_id, int device) {
+    BfCache *b = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(g_bf_mu);
+        for (auto it = g_bf.begin(); it != g_bf.end(); ++it)
+            if (it->first == ctx_id) {
+                b = it->second;
+                g_bf.erase(it);
+                break;
+            }
+    }
+    if (!b) return;
+    hipSetDevice(device);
+    bf_free(*b);
+    if (b->pinned) hipHostFree(b->pinned);
+    delete b;
+}
+
+}  // namespace apcg
+
+using namespace apcg;
+
+extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsys, const apcg_mat *A,
+                                                       const apcg_vec *b, const apcg_vec *x, double rtol,
+                                                       int32_t maxit, const float *dev_coeffs,
+                                                       const double *dev_lmax, const apcg_solve_opts *opts_in,
+                                                       const apcg_fcg_opts *fopts_in, apcg_info info) {
+    try {
+        if (!ctx || nsys < 1 || !A || !b || !x || !info || !dev_coeffs || !dev_lmax)
+            return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (info->count < nsys) return set_error(APCG_ERR_INVALID_ARG, "info has fewer records than systems");
+        if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(APCG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
+        if (maxit < 0) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0");
+        if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING && ctx->is_default_global)
+            return set_error(APCG_ERR_INVALID_ARG, "pass a context created with apcg_ctx_create");
+        apcg_solve_opts opts;
+        if (opts_in) opts = *opts_in;
+        else apcg_solve_opts_default(&opts);
+        apcg_fcg_opts fo;
+        if (fopts_in) fo = *fopts_in;
+        else apcg_fcg_opts_default(&fo);
+        if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        const int dev = ctx->device;
+        std::vector<FSys> hs(nsys);
+        int64_t ws_total = 0;
+        for (int32_t i = 0; i < nsys; ++i) {
+            if (!A[i] || !b[i] || !x[i]) return set_error(APCG_ERR_INVALID_ARG, "NULL system handle");
+            if (A[i]->device != dev || b[i]->device != dev || x[i]->device != dev || info->device != dev)
+                return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+            if (b[i]->n != A[i]->n || x[i]->n != A[i]->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
+            if (b[i] == x[i] || (b[i]->d == x[i]->d && A[i]->n > 0))
+                return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
+            const int64_t n = A[i]->n;
+            hs[i] = FSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x[i]->d,
+                         reinterpret_cast<double *>(ws_total), (int32_t)n, 0};
+            ws_total += ((9 * n + 63) / 64) * 64;
+        }
+        {
+            std::vector<std::pair<const double *, int32_t>> xs(nsys);
+            for (int32_t i = 0; i < nsys; ++i) xs[i] = {x[i]->d, i};
+            std::sort(xs.begin(), xs.end());
+            for (int32_t i = 1; i < nsys; ++i)
+                if (xs[i].first == xs[i - 1].first && x[xs[i].second]->n > 0)
+                    return set_error(APCG_ERR_INVALID_ARG, "two systems share one solution vector");
+        }
+        std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
+        for (int32_t s = 0; s < nsys; ++s) {
+            sys_tile0[s] = (int32_t)tile_sys.size();
+            for (int32_t r0 = 0; r0 < hs[s].n; r0 += FT) {
+                tile_sys.push_back(s);
+                tile_row0.push_back(r0);
+            }
+        }
+        sys_tile0[nsys] = (int32_t)tile_sys.size();
+        const int32_t ntiles = (int32_t)tile_sys.size();
+        if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well formed
+            tile_sys.push_back(0);
+            tile_row0.push_back(0);
+        }
+        const int32_t nt_alloc = std::max<int32_t>(ntiles, 1);
+
+        BfCache *bc = bf_cache(ctx);
+        std::vector<Acc> acc;
+        acc.reserve(3 * nsys + 1);
+        for (int32_t i = 0; i < nsys; ++i) {
+            acc.push_back({&x[i]->rec, ACC_RW});
+            acc.push_back({&A[i]->rec, ACC_R});
+            acc.push_back({&b[i]->rec, ACC_R});
+        }
+        acc.push_back({&info->rec, ACC_W});
+        apcg_status s;
+        if ((s = op_begin(ctx, acc.data(), (int)acc.size()))) return s;
+        hipStream_t st = ctx->stream;
+        APCG_HIP(hipSetDevice(dev));
+        const int64_t ws_need = std::max<int64_t>(ws_total, 64);
+        if (bc->sys_cap < nsys || bc->tiles_cap < nt_alloc || bc->ws_cap < ws_need) {
+            EventRef ev = event_get(dev);
+            if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+            APCG_HIP(hipEventRecord(ev->e, st));
+            BfCache old = *bc;
+            defer_release({ev}, [old]() mutable {
+                hipSetDevice(old.device);
+                bf_free(old);
+            });
+            bc->exec = nullptr;
+            bc->graph = nullptr;
+            bc->graph_hash = 0;
+            bc->hash = 0;
+            bc->sys_cap = std::max<int64_t>(nsys, bc->sys_cap);
+            bc->tiles_cap = std::max<int64_t>(nt_alloc, bc->tiles_cap);
+            bc->ws_cap = std::max<int64_t>(ws_need, bc->ws_cap);
+            APCG_HIP(hipMalloc((void **)&bc->d_sys, sizeof(FSys) * bc->sys_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_st, sizeof(FState) * bc->sys_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_sys_tile0, sizeof(int32_t) * (bc->sys_cap + 1)));
+            APCG_HIP(hipMalloc((void **)&bc->d_tile_sys, sizeof(int32_t) * bc->tiles_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_tile_row0, sizeof(int32_t) * bc->tiles_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * bc->tiles_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_ws, sizeof(double) * bc->ws_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_running, 256));
+        }
+        if (!bc->pinned)
+            APCG_HIP(hipHostMalloc((void **)&bc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
+        for (int32_t i = 0; i < nsys; ++i) hs[i].ws = bc->d_ws + reinterpret_cast<int64_t>(hs[i].ws);
+        uint64_t h = fnv(hs.data(), sizeof(FSys) * nsys);
+        h = fnv(tile_sys.data(), sizeof(int32_t) * tile_sys.size(), h);
+        h = fnv(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
+        h = fnv(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
+        if (h != bc->hash) {
+            g_counters.h2d_copies += 4;
+            APCG_HIP(hipMemcpyAsync(bc->d_sys, hs.data(), sizeof(FSys) * nsys, hipMemcpyHostToDevice, st));
+            APCG_HIP(hipMemcpyAsync(bc->d_tile_sys, tile_sys.data(), sizeof(int32_t) * tile_sys.size(),
+                                    hipMemcpyHostToDevice, st));
+            APCG_HIP(hipMemcpyAsync(bc->d_tile_row0, tile_row0.data(), sizeof(int32_t) * tile_row0.size(),
+                                    hipMemcpyHostToDevice, st));
+            APCG_HIP(hipMemcpyAsync(bc->d_sys_tile0, sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(),
+                                    hipMemcpyHostToDevice, st));
+            g_counters.host_syncs++;
+            APCG_HIP(hipStreamSynchronize(st));  // the host tables are local
+            bc->hash = h;
+        }
+        FPlan P;
+        P.sys = bc->d_sys;
+        P.tile_sys = bc->d_tile_sys;
+        P.tile_row0 = bc->d_tile_row0;
+        P.sys_tile0 = bc->d_sys_tile0;
+        P.st = bc->d_st;
+        P.part = bc->d_part;
+        P.running = bc->d_running;
+        P.nsys = nsys;
+        P.ntiles = ntiles;
+        const int G = normalise_blocks(2048, std::max<int32_t>(ntiles, 1));
+        P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
+        P.maxit = maxit;
+        P.stall_min = fo.stall_min;
+        P.fallback = fo.fallback ? 1 : 0;
+        P.rtol = rtol;
+        P.stall_frac = fo.stall_frac;
+        const int x0z = opts.x0_is_zero ? 1 : 0;
+
+        hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, bc->d_running);
+        APCG_CHECK_LAUNCH("k_bf_reset");
+        hipLaunchKernelGGL(k_bf_init, dim3(G), dim3(FT), 0, st, P, x0z);
+        APCG_CHECK_LAUNCH("k_bf_init");
+        hipLaunchKernelGGL(k_bf_init_final, dim3(nsys), dim3(64), 0, st, P, dev_coeffs, dev_lmax);
+        APCG_CHECK_LAUNCH("k_bf_init_final");
+        if (!x0z) {
+            hipLaunchKernelGGL(k_bf_zero_x, dim3(G), dim3(FT), 0, st, P);
+            APCG_CHECK_LAUNCH("k_bf_zero_x");
+        }
+        int K = std::max(2, opts.iters_per_graph);
+        if (K & 1) ++K;
+        const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
+        // Clenshaw buffers t0..t2 round robin: b_j in t[j % 3]
+        auto launch_iter = [&](int j) -> apcg_status {
+            hipLaunchKernelGGL(k_bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
+            APCG_CHECK_LAUNCH("k_bf_product");
+            hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(64), 0, st, P);
+            APCG_CHECK_LAUNCH("k_bf_alpha");
+            hipLaunchKernelGGL(k_bf_update, dim3(G), dim3(FT), 0, st, P, j & 1);
+            APCG_CHECK_LAUNCH("k_bf_update");
+            hipLaunchKernelGGL(k_bf_check, dim3(nsys), dim3(64), 0, st, P);
+            APCG_CHECK_LAUNCH("k_bf_check");
+            for (int d = FDEG - 1; d >= 0; --d) {
+                const int stage = d == FDEG - 1 ? 0 : (d == 0 ? 2 : 1);
+                const int ob1 = stage == 0 ? -1 : (d + 1) % 3;
+                const int ob2 = (stage == 0 || d + 2 == FDEG) ? -1 : (d + 2) % 3;
+                const int oout = stage == 2 ? -1 : d % 3;
+                hipLaunchKernelGGL(k_bf_cheb, dim3(G), dim3(FT), 0, st, P, d, stage, ob1, ob2, oout);
+                APCG_CHECK_LAUNCH("k_bf_cheb");
+            }
+            hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(64), 0, st, P);
+            APCG_CHECK_LAUNCH("k_bf_beta");
+            return APCG_SUCCESS;
+        };
+        uint64_t gh = fnv(&h, sizeof h);
+        const double prm[2] = {rtol, fo.stall_frac};
+        const int iprm[7] = {K, maxit, G, nsys, fo.stall_min, P.fallback, P.tiles_per_block};
+        gh = fnv(prm, sizeof prm, gh);
+        gh = fnv(iprm, sizeof iprm, gh);
+        const void *ptrs[3] = {bc->d_st, bc->d_part, bc->d_running};
+        gh = fnv(ptrs, sizeof ptrs, gh);
+        if (maxit > 0) {
+            if (opts.mode == APCG_MODE_GRAPH && (!bc->exec || bc->graph_hash != gh)) {
+                if (bc->exec) {
+                    EventRef ev = event_get(dev);
+                    if (ev) hipEventRecord(ev->e, st);
+                    hipGraphExec_t oe = bc->exec;
+                    hipGraph_t og = bc->graph;
+                    defer_release({ev}, [oe, og, dev]() {
+                        hipSetDevice(dev);
+                        hipGraphExecDestroy(oe);
+                        hipGraphDestroy(og);
+                    });
+                    bc->exec = nullptr;
+                    bc->graph = nullptr;
+                }
+                APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+                apcg_status cs = APCG_SUCCESS;
+                for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &g);
+                if (cs) {
+                    if (g) hipGraphDestroy(g);
+                    return cs;
+                }
+                if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(batched fcg)");
+                g_counters.kernel_launches -= (int64_t)(5 + FDEG) * K;
+                e = hipGraphInstantiate(&bc->exec, g, nullptr, nullptr, 0);
+                if (e != hipSuccess) {
+                    hipGraphDestroy(g);
+                    return hip_error(e, "hipGraphInstantiate(batched fcg)");
+                }
+                bc->graph = g;
+                bc->graph_hash = gh;
+            }
+            // iteration slots: maxit counted iterations plus at most two
+            // restarts per system (the first application and one switch)
+            const int64_t periods = ((int64_t)maxit + 2 + K - 1) / K;
+            for (int64_t g = 0; g < periods; ++g) {
+                if (opts.mode == APCG_MODE_GRAPH) {
+                    g_counters.graph_launches++;
+                    APCG_HIP(hipGraphLaunch(bc->exec, st));
+                } else {
+                    for (int j = 1; j <= K; ++j)
+                        if ((s = launch_iter(j))) return s;
+                }
+                const int slot = (int)(g % L);
+                if (!bc->poll_ev[slot]) {
+                    bc->poll_ev[slot] = event_get(dev);
+                    if (!bc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
+                }
+                g_counters.d2h_copies++;
+                APCG_HIP(hipMemcpyAsync(&bc->pinned[slot], bc->d_running, sizeof(int32_t), hipMemcpyDeviceToHost,
+                                        st));
+                APCG_HIP(hipEventRecord(bc->poll_ev[slot]->e, st));
+                if (g >= L - 1) {
+                    const int ps = (int)((g - (L - 1)) % L);
+                    g_counters.host_polls++;
+                    APCG_HIP(hipEventSynchronize(bc->poll_ev[ps]->e));
+                    if (bc->pinned[ps] == 0) break;  // every system has stopped
+                }
+            }
+        }
+        hipLaunchKernelGGL(k_bf_finish, dim3((nsys + 63) / 64), dim3(64), 0, st, P, info->d);
+        APCG_CHECK_LAUNCH("k_bf_finish");
+        return op_end(ctx, acc.data(), (int)acc.size());
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}

@@ -194,6 +194,7 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
 void seg_cache_release(uint64_t ctx_id, int device);    // batched.hip
 void learn_cache_release(uint64_t ctx_id, int device);  // learn.hip
 void fcg_cache_release(uint64_t ctx_id, int device);    // fcg.hip
+void bfcg_cache_release(uint64_t ctx_id, int device);   // batched_fcg.hip
 void spmv_default_config(int32_t n, int64_t nnz, apcg_spmv_config *cfg);
 int32_t normalise_blocks(int32_t blocks, int64_t units);  // multiple of 8, <= kMaxBlocks
 

@@ -153,6 +153,7 @@ static void ctx_release_now(apcg_ctx c) {
     seg_cache_release(c->id, c->device);
     learn_cache_release(c->id, c->device);
     fcg_cache_release(c->id, c->device);
+    bfcg_cache_release(c->id, c->device);
     for (auto &g : c->graphs) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         if (g.graph) hipGraphDestroy(g.graph);

@@ -1,0 +1,182 @@
+"""GPU parity of the batched FCG(1) solve (each system with its own
+polynomial and its own device-side fallback to Jacobi-PCG) against the
+oracle's FCG, system by system, through the C ABI.
+
+Bar (as for the single solves): status equal, iterations +-1, flexible
+iterations +-1 and ||x - x_ref|| / ||x_ref|| <= 1e-9 at rtol 1e-10; the
+fallback restarts from the recursive residual where the oracle recomputes
+b - A x, which only changes rounding.
+"""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_17801_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def apcg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_17801_amd as m
+
+    m.load()
+    return m
+
+
+@pytest.fixture(scope="module")
+def ctx(apcg):
+    c = apcg.apcg_ctx_create(0)
+    yield c
+    apcg.apcg_ctx_synchronize(c)
+    apcg.apcg_ctx_destroy(c)
+
+
+def cheb_coeffs(lmax, a):
+    from numpy.polynomial import chebyshev as Ch
+
+    T9 = [0] * 9 + [1]
+    s0 = (lmax + a) / (lmax - a)
+
+    def f(y):
+        t = (y + 1) * lmax / 2
+        return (1 - Ch.chebval((lmax + a - 2 * t) / (lmax - a), T9) / Ch.chebval(s0, T9)) / t
+
+    return Ch.chebinterpolate(f, 8)
+
+
+def one_row(d, bval):
+    A = P.CSR(n=1, rowptr=np.array([0, 1], np.int32), col=np.array([0], np.int32), val=np.array([d]))
+    return A, np.array([bval])
+
+
+def mixed_cases():
+    """(A, b, c (float32[9]), lmax, label) covering the paths."""
+    rng = np.random.default_rng(61)
+    out = []
+    for k, (dim, side, sigma, aniso) in enumerate([(2, 30, 1.0, 1.0), (3, 11, 1.5, 20.0), (2, 47, 2.0, 5.0),
+                                                   (3, 9, 0.7, 1.0), (2, 5, 1.0, 1.0)]):
+        s = P._lognormal_system(rng, dim, side, sigma, aniso)
+        lm = oracle.gershgorin(s.A)[1]
+        out.append((s.A, s.b, cheb_coeffs(lm, lm / (20 + 10 * k)).astype(np.float32), lm, f"cheb{dim}d_{side}"))
+    s = P._lognormal_system(rng, 2, 20, 1.0, 1.0)
+    lm = oracle.gershgorin(s.A)[1]
+    e0 = np.zeros(9, np.float32)
+    e0[0] = 1
+    out.append((s.A, s.b, e0, lm, "identity_poly"))
+    bad = np.zeros(9, np.float32)
+    bad[0], bad[1] = 0.2, -0.5
+    s = P._lognormal_system(rng, 2, 24, 1.0, 1.0)
+    out.append((s.A, s.b, bad, oracle.gershgorin(s.A)[1], "rejected_poly"))
+    A1, b1 = one_row(4.0, 2.0)
+    out.append((A1, b1, e0, 1.0, "one_row"))
+    s = P._lognormal_system(rng, 2, 12, 1.0, 1.0)
+    out.append((s.A, np.zeros(s.A.n), cheb_coeffs(2.0, 0.04).astype(np.float32), 2.0, "zero_rhs"))
+    Ab = P.laplace_2d(6)
+    k = Ab.rowptr[0] + int(np.nonzero(Ab.col[Ab.rowptr[0]:Ab.rowptr[1]] == 0)[0][0])
+    Ab.val[k] = -1.0  # row 0's diagonal: Jacobi is undefined
+    out.append((Ab, np.ones(Ab.n), e0, 2.0, "bad_diagonal"))
+    return out
+
+
+def run_batch(apcg, ctx, cases, rtol, maxit, x0=None, fopts=None, **opt):
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    As = [DeviceCSR(c[0]) for c in cases]
+    bs = [DeviceVec(c[1]) for c in cases]
+    xs = [DeviceVec(np.zeros(c[0].n) if x0 is None else x0[i]) for i, c in enumerate(cases)]
+    coef = torch.from_numpy(np.concatenate([c[2] for c in cases]).astype(np.float32)).to("cuda:0")
+    lm = torch.from_numpy(np.array([c[3] for c in cases], np.float64)).to("cuda:0")
+    torch.cuda.synchronize()
+    info = apcg.apcg_info_create(0, len(cases))
+    if x0 is None and "x0_is_zero" not in opt:
+        opt["x0_is_zero"] = 1
+    opts = apcg.apcg_solve_opts_default(**opt)
+    fo = apcg.apcg_fcg_opts_default(**(fopts or {}))
+    apcg.apcg_ksp_solve_batched_fcg_poly(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], rtol, maxit,
+                                         coef, lm, opts, fo, info)
+    res = [apcg.apcg_info_get(info, i) for i in range(len(cases))]
+    xo = [x.numpy() for x in xs]
+    apcg.apcg_info_destroy(info)
+    return res, xo
+
+
+def rel(a, b):
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def check_against_oracle(apcg, cases, res, xs, rtol, maxit, x0=None, **fo):
+    for i, (A, b, c, lm, name) in enumerate(cases):
+        ref = oracle.fcg_poly(A, b, c.astype(np.float64), lm, x0=None if x0 is None else x0[i], rtol=rtol,
+                              maxit=maxit, **fo)
+        r = res[i]
+        print(f"  {name}: gpu its {r['iterations']} fcg {r['fcg_iterations']} st {r['status']} | "
+              f"oracle its {ref.its} fcg {ref.fcg_its} st {ref.status}", flush=True)
+        assert r["status"] == ref.status, name
+        assert abs(r["iterations"] - ref.its) <= 1, name
+        assert abs(r["fcg_iterations"] - ref.fcg_its) <= 1, name
+        if ref.status & oracle.CONVERGED:
+            assert rel(xs[i], ref.x) <= 1e-9, name
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_mixed_batch_parity(apcg, ctx, mode):
+    print(f"case batched-fcg mixed mode={mode}", flush=True)
+    cases = mixed_cases()
+    res, xs = run_batch(apcg, ctx, cases, 1e-10, 20000, mode=mode)
+    check_against_oracle(apcg, cases, res, xs, 1e-10, 20000)
+    names = [c[4] for c in cases]
+    rj = res[names.index("rejected_poly")]
+    assert rj["fcg_iterations"] == 0 and rj["status"] & apcg.APCG_SOLVE_FALLBACK
+    assert res[names.index("bad_diagonal")]["status"] == apcg.APCG_SOLVE_SETUP_ERROR
+    z = names.index("zero_rhs")
+    assert res[z]["iterations"] == 0 and np.all(xs[z] == 0)
+
+
+def test_graph_and_stream_bitwise_and_repeatable(apcg, ctx):
+    cases = mixed_cases()
+    runs = [run_batch(apcg, ctx, cases, 1e-9, 20000, mode=m) for m in (0, 0, 1)]
+    for res, xs in runs[1:]:
+        assert res == runs[0][0]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, runs[0][1]))
+
+
+def test_without_fallback_and_with_x0(apcg, ctx):
+    cases = mixed_cases()
+    res, xs = run_batch(apcg, ctx, cases, 1e-10, 20000, fopts={"fallback": 0})
+    check_against_oracle(apcg, cases, res, xs, 1e-10, 20000, fallback=False)
+    names = [c[4] for c in cases]
+    rj = names.index("rejected_poly")
+    assert res[rj]["status"] == apcg.APCG_SOLVE_BREAKDOWN_RZ and np.all(xs[rj] == 0)
+    # nonzero initial guesses (the zero right-hand side still returns x = 0)
+    rng = np.random.default_rng(5)
+    x0 = [rng.uniform(-1, 1, c[0].n) for c in cases]
+    res, xs = run_batch(apcg, ctx, cases, 1e-10, 20000, x0=x0, x0_is_zero=0)
+    check_against_oracle(apcg, cases, res, xs, 1e-10, 20000, x0=x0)
+    assert np.all(xs[names.index("zero_rhs")] == 0)
+
+
+def test_iteration_cap_and_stall_window(apcg, ctx):
+    cases = [c for c in mixed_cases() if c[4] not in ("bad_diagonal",)]
+    res, xs = run_batch(apcg, ctx, cases, 1e-12, 5)
+    for i, (A, b, c, lm, name) in enumerate(cases):
+        ref = oracle.fcg_poly(A, b, c.astype(np.float64), lm, rtol=1e-12, maxit=5)
+        assert res[i]["status"] == ref.status and res[i]["iterations"] == ref.its, name
+        assert rel(xs[i], ref.x) <= 1e-11, name
+    # a window of one iteration: the first iteration without a new minimum of
+    # ||r|| hands the system to Jacobi-PCG
+    e0 = np.zeros(9, np.float32)
+    e0[0] = 1
+    rng = np.random.default_rng(77)
+    sts = [P._lognormal_system(rng, 2, side, 2.0, 1.0) for side in (30, 40, 25)]
+    cases = [(s.A, s.b, e0, oracle.gershgorin(s.A)[1], f"stall{i}") for i, s in enumerate(sts)]
+    fo = {"stall_min": 1, "stall_frac": 0.0}
+    res, xs = run_batch(apcg, ctx, cases, 1e-10, 20000, fopts=fo)
+    check_against_oracle(apcg, cases, res, xs, 1e-10, 20000, **fo)
+    assert all(r["status"] & apcg.APCG_SOLVE_STALL for r in res)
