@@ -345,8 +345,8 @@ def main():
     solve(topts)
     prod_us, prod_cnt = apcg.apcg_ctx_kernel_times(ctx, 0)
     upd_us, upd_cnt = apcg.apcg_ctx_kernel_times(ctx, 1)
-    prod_bytes = 12 * nnz + 4 * (n + 1) + 40 * n
-    upd_bytes = 56 * n
+    prod_bytes = 12 * nnz + 4 * (n + 1) + 32 * n  # A; z, p_old read; p, w written
+    upd_bytes = 64 * n  # x, r, p, w, dinv read; x, r, z written
     iter_bytes = 12 * nnz + 4 * (n + 1) + 96 * n
     achieved = prod_bytes / (prod_us * 1e-6) / 1e9
     traffic = None
@@ -356,8 +356,8 @@ def main():
         if tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n:
             traffic = tr.get("bytes_per_launch")
     cfg_now = apcg.apcg_mat_get_spmv_config(A.h)
-    kname = ("k_pcg_product_stream" if cfg_now["schedule"] == apcg.APCG_SPMV_STREAM else "k_pcg_product") + \
-        f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)"
+    kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell"}.get(
+        cfg_now["schedule"], "k_pcg_product") + f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)"
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": prod_bytes,

@@ -251,12 +251,21 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       thread reduces one row (lanes_per_row is ignored).  Needs every such
  *       row block to hold at most 5376 nonzeros (about 21 per row at block
  *       256, 10 at block 512); apcg_mat_set_spmv_config rejects it otherwise.
+ *   schedule APCG_SPMV_SELL (PCG solves): one wavefront per slice of 64
+ *       consecutive rows, the slice's entries stored column-major in a
+ *       library-owned copy (sliced ELLPACK, padded to the slice's longest
+ *       row), so every load of a column index or value is one coalesced
+ *       512-byte access.  The copy (12 bytes per stored entry) is allocated
+ *       on first use and refilled from the CSR arrays at the start of every
+ *       solve, so values may change between solves; MatMult uses the
+ *       row-group kernel for this schedule.
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so
  * each XCD owns a contiguous slice of the matrix. */
 #define APCG_SPMV_ROWGROUP 0
 #define APCG_SPMV_STREAM 1
+#define APCG_SPMV_SELL 2
 typedef struct apcg_spmv_config {
     int32_t lanes_per_row;
     int32_t block_size;

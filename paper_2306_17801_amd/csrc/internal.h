@@ -110,12 +110,13 @@ inline bool stream_fits(const apcg_mat_s *A, int tb);
 
 struct Workspace {
     int64_t cap = 0;          // elements per vector
-    double *base = nullptr;   // 5 * cap doubles: r, dinv, p0, p1, w
+    double *base = nullptr;   // 6 * cap doubles: r, dinv, p0, p1, w, z
     SolveState *state = nullptr;  // 256 bytes
     double *r() const { return base; }
     double *dinv() const { return base + cap; }
     double *p(int i) const { return base + (2 + i) * cap; }
     double *w() const { return base + 4 * cap; }
+    double *z() const { return base + 5 * cap; }  // D^-1 r, stored by the update for the product's gather
 };
 
 }  // namespace apcg
@@ -164,6 +165,16 @@ struct apcg_mat_s {
     const double *val = nullptr;
     apcg_spmv_config cfg{};
     int64_t max_block_nnz[2] = {0, 0};  // most nonzeros in any 256- / 512-row block
+    // Sliced layout (64-row slices, entries of a slice column-major), used
+    // by the SELL schedule: built on the host at wrap time (slice offset and
+    // width), filled on the device from the CSR arrays at the start of every
+    // solve that uses it.
+    std::vector<int32_t> sell_meta_h;  // [2 * nslices]: offset, width
+    int64_t sell_entries = 0;          // -1: too large for int32 offsets
+    int32_t sell_maxw = 0;
+    int32_t *sell_meta = nullptr;      // device copies, allocated on first use
+    int32_t *sell_col = nullptr;
+    double *sell_val = nullptr;
     apcg::Record rec;
 };
 

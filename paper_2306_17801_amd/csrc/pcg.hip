@@ -68,11 +68,11 @@ constexpr int VB = 256;  // block size of the vector-shaped kernels
 constexpr int kSliceResidual = 0;  // 4 slices: z.r, ||.||^2, reference^2, bad rows
 constexpr int kSliceDelta = 4;     // 1 slice: p.Ap
 
-// The direction entry p_j = z_j + beta p_j with z_j = d_j r_j; one function
-// so the stored p and the gathered p agree bit for bit.
-__device__ __forceinline__ double pdir(double d, double r, double beta, double pold) {
-    return fma(beta, pold, d * r);
-}
+// The direction entry p_j = z_j + beta p_old_j.  z = D^-1 r is stored (as
+// the rounded products d_j r_j) by the setup and update kernels, so the
+// product kernels gather two arrays (z, p_old) instead of three, and the
+// stored p and every gathered p agree bit for bit.
+__device__ __forceinline__ double pdir(double z, double beta, double pold) { return fma(beta, pold, z); }
 
 // Tests applied after iteration m (oracle order: NaN, convergence, r.z
 // breakdown, iteration limit).  Returns the status bit or 0.
@@ -92,14 +92,15 @@ __device__ __forceinline__ void terminate(SolveState *st, int its, int status, d
 }
 
 // ----------------------------------------------------------------- setup
-// dinv = 1/diag(A) (or 1), r0 = b - A x0 (or b), p_old = 0; partials of
+// dinv = 1/diag(A) (or 1), r0 = b - A x0 (or b), z0 = dinv r0, p_old = 0; partials of
 // z0.r0, residual norm^2, reference norm^2 and the count of bad diagonals.
 __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__restrict__ rowptr,
                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
                                                  const double *__restrict__ b, double *__restrict__ x,
                                                  double *__restrict__ r, double *__restrict__ dinv,
-                                                 double *__restrict__ pold, double *partials, int64_t per_block,
-                                                 int x0_zero, int pc, int norm_pre) {
+                                                 double *__restrict__ z, double *__restrict__ pold,
+                                                 double *partials, int64_t per_block, int x0_zero, int pc,
+                                                 int norm_pre) {
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double rz = 0.0, nres = 0.0, nref = 0.0, bad = 0.0;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += VB) {
@@ -128,6 +129,7 @@ __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__res
         pold[i] = 0.0;
         if (x0_zero) x[i] = 0.0;  // x is not read when x0 is taken as zero
         const double zi = di * ri;
+        z[i] = zi;
         rz = fma(zi, ri, rz);
         if (norm_pre) {
             const double zb = di * bi;
@@ -224,7 +226,7 @@ __device__ __forceinline__ bool product_prologue(SolveState *st, const double *p
 template <int LPR, int TB>
 __global__ __launch_bounds__(TB) void k_pcg_product(int32_t n, const int32_t *__restrict__ rowptr,
                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                    const double *__restrict__ dinv, const double *__restrict__ r,
+                                                    const double *__restrict__ z,
                                                     const double *__restrict__ pold, double *__restrict__ pnew,
                                                     double *__restrict__ w, SolveState *st, const double *part_res,
                                                     int g_res, double *part_delta, int32_t rows_per_block,
@@ -244,13 +246,13 @@ __global__ __launch_bounds__(TB) void k_pcg_product(int32_t n, const int32_t *__
             const int e = rowptr[row + 1];
             for (int k = rowptr[row] + lane; k < e; k += LPR) {
                 const int j = col[k];
-                sum = fma(val[k], pdir(dinv[j], r[j], beta, pold[j]), sum);
+                sum = fma(val[k], pdir(z[j], beta, pold[j]), sum);
             }
         }
 #pragma unroll
         for (int o = LPR / 2; o > 0; o >>= 1) sum += __shfl_xor(sum, o, LPR);
         if (row < row1 && lane == 0) {
-            const double pi = pdir(dinv[row], r[row], beta, pold[row]);
+            const double pi = pdir(z[row], beta, pold[row]);
             pnew[row] = pi;
             w[row] = sum;
             acc = fma(pi, sum, acc);
@@ -267,8 +269,8 @@ __global__ __launch_bounds__(TB) void k_pcg_product(int32_t n, const int32_t *__
 // rows take the plain loop.  Both paths add in column-storage order, so the
 // result does not depend on which one ran.
 __device__ __forceinline__ double staged_row_product(const double *sv, const int32_t *sc, int s, int e, int row,
-                                                     const double *__restrict__ dinv, const double *__restrict__ r,
-                                                     const double *__restrict__ pold, double beta) {
+                                                     const double *__restrict__ z, const double *__restrict__ pold,
+                                                     double beta) {
     const int len = e - s;
     double sum = 0.0;
     if (len <= 8) {
@@ -281,14 +283,14 @@ __device__ __forceinline__ double staged_row_product(const double *sv, const int
             aa[q] = in ? sv[s + q] : 0.0;
         }
 #pragma unroll
-        for (int q = 0; q < 8; ++q) pj[q] = pdir(dinv[jj[q]], r[jj[q]], beta, pold[jj[q]]);
+        for (int q = 0; q < 8; ++q) pj[q] = pdir(z[jj[q]], beta, pold[jj[q]]);
 #pragma unroll
         for (int q = 0; q < 8; ++q)
             if (q < len) sum = fma(aa[q], pj[q], sum);
     } else {
         for (int k = s; k < e; ++k) {
             const int j = sc[k];
-            sum = fma(sv[k], pdir(dinv[j], r[j], beta, pold[j]), sum);
+            sum = fma(sv[k], pdir(z[j], beta, pold[j]), sum);
         }
     }
     return sum;
@@ -297,7 +299,7 @@ __device__ __forceinline__ double staged_row_product(const double *sv, const int
 // Staged schedule: each workgroup walks its contiguous run of TB-row chunks;
 // per chunk the nonzeros are moved to LDS with coalesced (non-temporal)
 // loads, then thread t reduces row t of the chunk.  With one row per thread,
-// neighbouring lanes gather neighbouring entries of p, dinv and r, which
+// neighbouring lanes gather neighbouring entries of z and p_old, which
 // coalesces for banded/stencil matrices.  The chunk loop is software
 // pipelined: the next chunk's nonzeros are loaded into registers (PF per
 // thread) while the current chunk is reduced, so staging does not serialise
@@ -307,8 +309,7 @@ template <int TB, int PF>
 __global__ __launch_bounds__(TB) void k_pcg_product_stream(int32_t n, const int32_t *__restrict__ rowptr,
                                                            const int32_t *__restrict__ col,
                                                            const double *__restrict__ val,
-                                                           const double *__restrict__ dinv,
-                                                           const double *__restrict__ r,
+                                                           const double *__restrict__ z,
                                                            const double *__restrict__ pold, double *__restrict__ pnew,
                                                            double *__restrict__ w, SolveState *st,
                                                            const double *part_res, int g_res, double *part_delta,
@@ -360,8 +361,8 @@ __global__ __launch_bounds__(TB) void k_pcg_product_stream(int32_t n, const int3
         const int row = row0 + threadIdx.x;
         if (row < row1) {
             const double sum =
-                staged_row_product(sv, sc, rowptr[row] - k0, rowptr[row + 1] - k0, row, dinv, r, pold, beta);
-            const double pi = pdir(dinv[row], r[row], beta, pold[row]);
+                staged_row_product(sv, sc, rowptr[row] - k0, rowptr[row + 1] - k0, row, z, pold, beta);
+            const double pi = pdir(z[row], beta, pold[row]);
             pnew[row] = pi;
             w[row] = sum;
             acc = fma(pi, sum, acc);
@@ -371,10 +372,99 @@ __global__ __launch_bounds__(TB) void k_pcg_product_stream(int32_t n, const int3
     dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
 }
 
+// Sliced schedule (SELL-64): wavefront v of a workgroup takes slices
+// s0 + v, s0 + v + TB/64, ... of the workgroup's contiguous range, lane l
+// reduces row 64 s + l.  meta[2 s] is the slice's offset and meta[2 s + 1]
+// its width W; entry k of lane l sits at offset + 64 k + l, so each load of
+// a column index or value is one coalesced 512-byte access.  Padding entries
+// have column -1 and are not added: each row adds its own entries in
+// column-storage order, as in the other schedules.  Slices of up to 8
+// columns issue every load before the first multiply-add.
+template <int TB>
+__global__ __launch_bounds__(TB) void k_pcg_product_sell(int32_t n, const int32_t *__restrict__ meta,
+                                                         const int32_t *__restrict__ scol,
+                                                         const double *__restrict__ sval, const double *__restrict__ z,
+                                                         const double *__restrict__ pold, double *__restrict__ pnew,
+                                                         double *__restrict__ w, SolveState *st,
+                                                         const double *part_res, int g_res, double *part_delta,
+                                                         int32_t slices_per_block, int parity, int tune,
+                                                         int32_t /*lds_nnz: staged only*/) {
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int nsl = (n + 63) / 64;
+    const int s0 = lb * slices_per_block;
+    const int s1 = min(nsl, s0 + slices_per_block);
+    const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    double acc = 0.0;
+    for (int sl = s0 + wave; sl < s1; sl += TB / 64) {
+        const int row = sl * 64 + lane;
+        const int off = meta[2 * sl], W = meta[2 * sl + 1];
+        double sum = 0.0;
+        if (W <= 8) {
+            int jj[8];
+            double aa[8], pj[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const bool in = k < W;
+                jj[k] = in ? __builtin_nontemporal_load(scol + off + 64 * k + lane) : -1;
+                aa[k] = in ? __builtin_nontemporal_load(sval + off + 64 * k + lane) : 0.0;
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                const int j = jj[k] >= 0 ? jj[k] : 0;  // padding gathers row 0 and is not added
+                pj[k] = pdir(z[j], beta, pold[j]);
+            }
+#pragma unroll
+            for (int k = 0; k < 8; ++k)
+                if (jj[k] >= 0) sum = fma(aa[k], pj[k], sum);
+        } else {
+            for (int k = 0; k < W; ++k) {
+                const int j = __builtin_nontemporal_load(scol + off + 64 * k + lane);
+                if (j >= 0) sum = fma(__builtin_nontemporal_load(sval + off + 64 * k + lane), pdir(z[j], beta, pold[j]), sum);
+            }
+        }
+        if (row < n) {
+            const double pi = pdir(z[row], beta, pold[row]);
+            pnew[row] = pi;
+            w[row] = sum;
+            acc = fma(pi, sum, acc);
+        }
+    }
+    double v[1] = {acc};
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
+}
+
+// Fills the sliced copy from the CSR arrays: thread (slice, lane) copies its
+// row's entries to offset + 64 k + lane and pads to the slice's width with
+// column -1 and value 0.
+__global__ __launch_bounds__(256) void k_sell_fill(int32_t n, const int32_t *__restrict__ rowptr,
+                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                   const int32_t *__restrict__ meta, int32_t *__restrict__ scol,
+                                                   double *__restrict__ sval) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nsl = ((int64_t)n + 63) / 64;
+    if (g >= nsl * 64) return;
+    const int sl = (int)(g >> 6), lane = (int)(g & 63);
+    const int row = sl * 64 + lane;
+    const int off = meta[2 * sl], W = meta[2 * sl + 1];
+    int s = 0, len = 0;
+    if (row < n) {
+        s = rowptr[row];
+        len = rowptr[row + 1] - s;
+    }
+    for (int k = 0; k < W; ++k) {
+        const bool in = k < len;
+        scol[off + 64 * k + lane] = in ? col[s + k] : -1;
+        sval[off + 64 * k + lane] = in ? val[s + k] : 0.0;
+    }
+}
+
 // ----------------------------------------------------------------- update
 __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                    const double *__restrict__ p, const double *__restrict__ w,
-                                                   const double *__restrict__ dinv, SolveState *st,
+                                                   const double *__restrict__ dinv, double *__restrict__ z,
+                                                   SolveState *st,
                                                    const double *part_delta, int g_delta, double *part_res,
                                                    int64_t per_block, int parity, int norm_pre, int tune) {
     double alpha = 0.0;
@@ -403,6 +493,7 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
         x[i] = xi;
         r[i] = ri;
         const double zi = dinv[i] * ri;
+        z[i] = zi;
         rz = fma(zi, ri, rz);
         nn = norm_pre ? fma(zi, zi, nn) : fma(ri, ri, nn);
     }
@@ -435,17 +526,18 @@ __global__ __launch_bounds__(64) void k_pcg_finish(SolveState *st, const double 
     out->ref_norm = st->ref;
 }
 
-__global__ __launch_bounds__(VB) void k_tune_fill(double *r, double *dinv, double *p, int64_t n) {
+__global__ __launch_bounds__(VB) void k_tune_fill(double *r, double *dinv, double *p, double *z, int64_t n) {
     for (int64_t i = (int64_t)blockIdx.x * VB + threadIdx.x; i < n; i += (int64_t)gridDim.x * VB) {
         r[i] = 1.0 + 1e-3 * (double)(i % 97);
         dinv[i] = 0.25;
         p[i] = 0.125;
+        z[i] = 0.25 * r[i];
     }
 }
 
 using ProductFn = void (*)(int32_t, const int32_t *, const int32_t *, const double *, const double *,
-                           const double *, const double *, double *, double *, SolveState *, const double *, int,
-                           double *, int32_t, int, int, int32_t);
+                           const double *, double *, double *, SolveState *, const double *, int, double *, int32_t,
+                           int, int, int32_t);
 
 template <int TB>
 ProductFn product_fn_tb(int lpr) {
@@ -474,6 +566,7 @@ ProductFn stream_fn(int32_t lds_nnz) {
 }
 
 ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz) {
+    if (cfg.schedule == APCG_SPMV_SELL) return cfg.block_size == 512 ? k_pcg_product_sell<512> : k_pcg_product_sell<256>;
     if (cfg.schedule == APCG_SPMV_STREAM) {
         if (cfg.block_size == 512) return stream_fn<512>(lds_nnz);
         return stream_fn<256>(lds_nnz);
@@ -485,9 +578,11 @@ ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz) {
 struct Plan {
     int32_t n;
     ProductFn prod;
+    const int32_t *a0, *a1;  // matrix arrays the product reads: CSR rowptr, col -- or slice meta, column copy
+    const double *a2;        //   CSR values -- or the value copy
     int tb;
     int g_prod;
-    int32_t rpb;  // rows per workgroup (row groups) or chunks per workgroup (staged)
+    int32_t rpb;  // rows (row groups), chunks (staged) or slices (sliced) per workgroup
     int g_vec;
     int64_t pb_vec;
     int32_t lds_nnz;     // staged schedule: LDS entries per workgroup
@@ -511,7 +606,19 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         return set_error(APCG_ERR_UNSUPPORTED, "rows too long for the staged schedule");
     pl->lds_nnz = 0;
     pl->lds_bytes = 0;
-    if (cfg.schedule == APCG_SPMV_STREAM) {
+    pl->a0 = A->rowptr;
+    pl->a1 = A->col;
+    pl->a2 = A->val;
+    if (cfg.schedule == APCG_SPMV_SELL) {
+        if (!A->sell_meta) return set_error(APCG_ERR_INVALID_STATE, "sliced copy not prepared");
+        pl->a0 = A->sell_meta;
+        pl->a1 = A->sell_col;
+        pl->a2 = A->sell_val;
+        const int64_t nsl = ((int64_t)A->n + 63) / 64;
+        const int64_t waves = pl->tb / 64;
+        pl->g_prod = normalise_blocks(cfg.blocks, (nsl + waves - 1) / waves);
+        pl->rpb = (int32_t)std::max<int64_t>(1, (nsl + pl->g_prod - 1) / pl->g_prod);
+    } else if (cfg.schedule == APCG_SPMV_STREAM) {
         const int64_t most = A->max_block_nnz[pl->tb == 512 ? 1 : 0];
         pl->lds_nnz = (int32_t)std::max<int64_t>(2, ((most + 1) / 2) * 2);  // keeps the int32 stage 8-byte aligned
         pl->lds_bytes = (size_t)pl->lds_nnz * (sizeof(double) + sizeof(int32_t));
@@ -530,6 +637,33 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
     return APCG_SUCCESS;
 }
 
+// Allocates the matrix's sliced copy on first use (uploading the slice
+// table once) and queues its refill from the CSR arrays on stream s.
+apcg_status prepare_sell(apcg_mat_s *A, hipStream_t s) {
+    if (A->sell_entries < 0) return set_error(APCG_ERR_UNSUPPORTED, "matrix too large for the sliced layout");
+    const int64_t nsl = ((int64_t)A->n + 63) / 64;
+    if (!A->sell_meta) {
+        const int64_t ent = std::max<int64_t>(A->sell_entries, 1);
+        APCG_HIP(hipMalloc((void **)&A->sell_meta, sizeof(int32_t) * std::max<int64_t>(2 * nsl, 2)));
+        APCG_HIP(hipMalloc((void **)&A->sell_col, sizeof(int32_t) * ent));
+        APCG_HIP(hipMalloc((void **)&A->sell_val, sizeof(double) * ent));
+        if (nsl > 0) {
+            g_counters.h2d_copies++;
+            APCG_HIP(hipMemcpyAsync(A->sell_meta, A->sell_meta_h.data(), sizeof(int32_t) * 2 * nsl,
+                                    hipMemcpyHostToDevice, s));
+            g_counters.host_syncs++;
+            APCG_HIP(hipStreamSynchronize(s));  // once per matrix
+        }
+    }
+    if (nsl > 0) {
+        const int64_t blocks = (nsl * 64 + 255) / 256;
+        hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->rowptr, A->col, A->val,
+                           (const int32_t *)A->sell_meta, A->sell_col, A->sell_val);
+        APCG_CHECK_LAUNCH("k_sell_fill");
+    }
+    return APCG_SUCCESS;
+}
+
 struct Bufs {
     const apcg_mat_s *A;
     double *x;
@@ -543,8 +677,8 @@ struct Bufs {
 apcg_status launch_product(hipStream_t s, const Plan &pl, const Bufs &bf, int iter, int tune = 0) {
     const double *pold = bf.ws.p((iter + 1) & 1);
     double *pnew = bf.ws.p(iter & 1);
-    hipLaunchKernelGGL(pl.prod, dim3(pl.g_prod), dim3(pl.tb), pl.lds_bytes, s, pl.n, bf.A->rowptr, bf.A->col,
-                       bf.A->val, (const double *)bf.ws.dinv(), (const double *)bf.ws.r(), pold, pnew, bf.ws.w(),
+    hipLaunchKernelGGL(pl.prod, dim3(pl.g_prod), dim3(pl.tb), pl.lds_bytes, s, pl.n, pl.a0, pl.a1, pl.a2,
+                       (const double *)bf.ws.z(), pold, pnew, bf.ws.w(),
                        bf.ws.state, (const double *)bf.part_res(), pl.g_vec, bf.part_delta(), pl.rpb, iter & 1, tune,
                        pl.lds_nnz);
     APCG_CHECK_LAUNCH("k_pcg_product");
@@ -554,7 +688,7 @@ apcg_status launch_product(hipStream_t s, const Plan &pl, const Bufs &bf, int it
 apcg_status launch_update(hipStream_t s, const Plan &pl, const Bufs &bf, int iter, int norm_pre, int tune = 0) {
     const double *p = bf.ws.p(iter & 1);
     hipLaunchKernelGGL(k_pcg_update, dim3(pl.g_vec), dim3(VB), 0, s, (int64_t)pl.n, bf.x, bf.ws.r(), p,
-                       (const double *)bf.ws.w(), (const double *)bf.ws.dinv(), bf.ws.state,
+                       (const double *)bf.ws.w(), (const double *)bf.ws.dinv(), bf.ws.z(), bf.ws.state,
                        (const double *)bf.part_delta(), pl.g_prod, bf.part_res(), pl.pb_vec, iter & 1, norm_pre,
                        tune);
     APCG_CHECK_LAUNCH("k_pcg_update");
@@ -565,9 +699,9 @@ apcg_status get_graph(apcg_ctx c, const Plan &pl, const Bufs &bf, int K, int pc,
                       hipGraphExec_t *exec) {
     GraphKey key;
     key.mat_uid = bf.A->uid;
-    key.rowptr = bf.A->rowptr;
-    key.col = bf.A->col;
-    key.val = bf.A->val;
+    key.rowptr = pl.a0;
+    key.col = pl.a1;
+    key.val = pl.a2;
     key.x = bf.x;
     key.ws = bf.ws.base;
     key.state = bf.ws.state;
@@ -734,6 +868,7 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
         Acc acc[4] = {{&x->rec, ACC_RW}, {&info->rec, ACC_W}, {&A->rec, ACC_R}, {&b->rec, ACC_R}};
         if ((s = op_begin(c, acc, 4))) return s;
         if ((s = ensure_workspace(c, A->n))) return s;
+        if (A->cfg.schedule == APCG_SPMV_SELL && (s = prepare_sell(A, c->stream))) return s;
         Plan pl;
         if ((s = make_plan(A, A->cfg, &pl))) return s;
         Bufs bf{A, x->d, b->d, c->ws, c->partials};
@@ -741,8 +876,8 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
         hipStream_t st = c->stream;
 
         hipLaunchKernelGGL(k_pcg_init, dim3(pl.g_vec), dim3(VB), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d,
-                           c->ws.r(), c->ws.dinv(), c->ws.p(0), bf.part_res(), pl.pb_vec, opts.x0_is_zero ? 1 : 0,
-                           opts.pc, norm_pre);
+                           c->ws.r(), c->ws.dinv(), c->ws.z(), c->ws.p(0), bf.part_res(), pl.pb_vec,
+                           opts.x0_is_zero ? 1 : 0, opts.pc, norm_pre);
         APCG_CHECK_LAUNCH("k_pcg_init");
         hipLaunchKernelGGL(k_pcg_init_final, dim3(1), dim3(64), 0, st, c->ws.state, (const double *)bf.part_res(),
                            pl.g_vec, rtol, maxit, hist, hist_cap);
@@ -866,7 +1001,8 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         if ((s = ensure_workspace(ctx, A->n))) return s;
         hipStream_t st = ctx->stream;
         const int64_t n = A->n;
-        hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(VB), 0, st, ctx->ws.r(), ctx->ws.dinv(), ctx->ws.p(0), n);
+        hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(VB), 0, st, ctx->ws.r(), ctx->ws.dinv(), ctx->ws.p(0),
+                           ctx->ws.z(), n);
         APCG_CHECK_LAUNCH("k_tune_fill");
         double *xs = nullptr;  // stand-in for x: the tuned update writes it
         APCG_HIP(hipMalloc((void **)&xs, sizeof(double) * std::max<int64_t>(n, 1)));
@@ -878,13 +1014,17 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         APCG_HIP(hipEventCreate(&e1));
         double best_t = 1e300;
         apcg_spmv_config best_cfg = A->cfg;
-        for (int lpr : {0, 1, 2, 4, 8, 16, 32, 64}) {  // 0: the staged schedule
+        const bool sell_ok = A->sell_entries >= 0;
+        if (sell_ok && (s = prepare_sell(A, st))) return s;
+        for (int lpr : {-1, 0, 1, 2, 4, 8, 16, 32, 64}) {  // -1: the sliced schedule, 0: the staged one
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
+            if (lpr == -1 && !sell_ok) continue;
             for (int tb : {256, 512}) {
                 if (lpr == 0 && !stream_fits(A, tb)) continue;
                 for (int blocks : {256, 512, 1024, 2048, 4096, 8192}) {
-                    apcg_spmv_config cfg = lpr == 0 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_STREAM}
-                                                    : apcg_spmv_config{lpr, tb, blocks, APCG_SPMV_ROWGROUP};
+                    apcg_spmv_config cfg = lpr == -1  ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}
+                                           : lpr == 0 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_STREAM}
+                                                      : apcg_spmv_config{lpr, tb, blocks, APCG_SPMV_ROWGROUP};
                     Plan pl;
                     if ((s = make_plan(A, cfg, &pl))) return s;
                     if (pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller candidate

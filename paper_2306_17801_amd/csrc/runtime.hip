@@ -293,7 +293,7 @@ apcg_status ensure_workspace(apcg_ctx c, int64_t n) {
         c->ws.base = nullptr;
     }
     int64_t cap = ((n + 63) / 64) * 64;
-    APCG_HIP(hipMalloc((void **)&c->ws.base, sizeof(double) * 5 * cap));
+    APCG_HIP(hipMalloc((void **)&c->ws.base, sizeof(double) * 6 * cap));
     c->ws.cap = cap;
     if (!c->ws.state) APCG_HIP(hipMalloc((void **)&c->ws.state, 256));
     return APCG_SUCCESS;
@@ -860,6 +860,22 @@ apcg_status apcg_mat_wrap_csr(int32_t device, int32_t n, int64_t nnz, const int3
         for (int64_t r0 = 0; r0 < n; r0 += rows) mx = std::max<int64_t>(mx, rp[std::min<int64_t>(n, r0 + rows)] - rp[r0]);
         A->max_block_nnz[t] = mx;
     }
+    {  // 64-row slices: offset and width (longest row) of each
+        const int64_t nsl = ((int64_t)n + 63) / 64;
+        A->sell_meta_h.resize(2 * nsl);
+        int64_t off = 0;
+        int32_t maxw = 0;
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            int32_t w = 0;
+            for (int64_t i = sl * 64; i < std::min<int64_t>(n, sl * 64 + 64); ++i) w = std::max(w, rp[i + 1] - rp[i]);
+            A->sell_meta_h[2 * sl] = (int32_t)std::min<int64_t>(off, INT32_MAX);
+            A->sell_meta_h[2 * sl + 1] = w;
+            off += 64 * (int64_t)w;
+            maxw = std::max(maxw, w);
+        }
+        A->sell_entries = off > INT32_MAX ? -1 : off;
+        A->sell_maxw = maxw;
+    }
     spmv_default_config(n, nnz, &A->cfg);
     if (stream_fits(A, 256)) A->cfg = apcg_spmv_config{1, 256, 1024, APCG_SPMV_STREAM};
     *out = A;
@@ -875,8 +891,18 @@ apcg_status apcg_mat_destroy(apcg_mat A) {
         std::lock_guard<std::recursive_mutex> lk(g_mu);
         deps = record_deps(A->rec);
     }
+    const int dev = A->device;
+    int32_t *smeta = A->sell_meta, *scol = A->sell_col;
+    double *sval = A->sell_val;
     delete A;
-    defer_release(std::move(deps), []() {});
+    defer_release(std::move(deps), [dev, smeta, scol, sval]() {
+        if (smeta || scol || sval) {
+            hipSetDevice(dev);
+            hipFree(smeta);
+            hipFree(scol);
+            hipFree(sval);
+        }
+    });
     reap();
     return APCG_SUCCESS;
     API_END();
@@ -886,7 +912,8 @@ static bool valid_spmv_config(const apcg_spmv_config *cfg) {
     int l = cfg->lanes_per_row, b = cfg->block_size;
     bool lok = l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64;
     bool bok = b == 256 || b == 512;
-    bool sok = cfg->schedule == APCG_SPMV_ROWGROUP || cfg->schedule == APCG_SPMV_STREAM;
+    bool sok = cfg->schedule == APCG_SPMV_ROWGROUP || cfg->schedule == APCG_SPMV_STREAM ||
+               cfg->schedule == APCG_SPMV_SELL;
     return lok && bok && sok && cfg->blocks >= 0;
 }
 
@@ -896,6 +923,8 @@ apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg) {
         return set_error(APCG_ERR_INVALID_ARG, "invalid SpMV configuration (block_size must be 256 or 512)");
     if (cfg->schedule == APCG_SPMV_STREAM && !stream_fits(A, cfg->block_size))
         return set_error(APCG_ERR_UNSUPPORTED, "rows too long for the staged schedule at this block size");
+    if (cfg->schedule == APCG_SPMV_SELL && A->sell_entries < 0)
+        return set_error(APCG_ERR_UNSUPPORTED, "matrix too large for the sliced layout's int32 offsets");
     A->cfg = *cfg;
     return APCG_SUCCESS;
 }
