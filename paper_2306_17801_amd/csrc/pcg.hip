@@ -378,9 +378,12 @@ __global__ __launch_bounds__(TB) void k_pcg_product_stream(int32_t n, const int3
 // its width W; entry k of lane l sits at offset + 64 k + l, so each load of
 // a column index or value is one coalesced 512-byte access.  Padding entries
 // have column -1 and are not added: each row adds its own entries in
-// column-storage order, as in the other schedules.  Slices of up to 8
-// columns issue every load before the first multiply-add.
-template <int TB>
+// column-storage order, as in the other schedules.
+// NARROW (every slice at most 8 wide): software pipelined -- the next
+// slice's column and value loads are issued before the current slice's
+// gathers, so the HBM stream of the matrix overlaps the cache-bound gathers.
+// Otherwise slices are reduced one entry at a time.
+template <int TB, int NARROW>
 __global__ __launch_bounds__(TB) void k_pcg_product_sell(int32_t n, const int32_t *__restrict__ meta,
                                                          const int32_t *__restrict__ scol,
                                                          const double *__restrict__ sval, const double *__restrict__ z,
@@ -389,46 +392,72 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sell(int32_t n, const int32_
                                                          const double *part_res, int g_res, double *part_delta,
                                                          int32_t slices_per_block, int parity, int tune,
                                                          int32_t /*lds_nnz: staged only*/) {
-    double beta;
-    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
     const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
     const int nsl = (n + 63) / 64;
     const int s0 = lb * slices_per_block;
     const int s1 = min(nsl, s0 + slices_per_block);
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    double acc = 0.0;
-    for (int sl = s0 + wave; sl < s1; sl += TB / 64) {
-        const int row = sl * 64 + lane;
+    constexpr int STEP = TB / 64;
+    int jn[8];
+    double an[8];
+    auto load = [&](int sl) {
         const int off = meta[2 * sl], W = meta[2 * sl + 1];
-        double sum = 0.0;
-        if (W <= 8) {
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const bool in = k < W;
+            jn[k] = in ? __builtin_nontemporal_load(scol + off + 64 * k + lane) : -1;
+            an[k] = in ? __builtin_nontemporal_load(sval + off + 64 * k + lane) : 0.0;
+        }
+    };
+    // the first slice's matrix loads do not depend on beta: issued before the
+    // prologue's reduction so that its latency overlaps them
+    if (NARROW && s0 + wave < s1) load(s0 + wave);
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    double acc = 0.0;
+    if (NARROW) {
+        for (int sl = s0 + wave; sl < s1; sl += STEP) {
             int jj[8];
             double aa[8], pj[8];
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
-                const bool in = k < W;
-                jj[k] = in ? __builtin_nontemporal_load(scol + off + 64 * k + lane) : -1;
-                aa[k] = in ? __builtin_nontemporal_load(sval + off + 64 * k + lane) : 0.0;
+                jj[k] = jn[k];
+                aa[k] = an[k];
             }
+            if (sl + STEP < s1) load(sl + STEP);  // in flight during the gathers below
 #pragma unroll
             for (int k = 0; k < 8; ++k) {
                 const int j = jj[k] >= 0 ? jj[k] : 0;  // padding gathers row 0 and is not added
                 pj[k] = pdir(z[j], beta, pold[j]);
             }
+            double sum = 0.0;
 #pragma unroll
             for (int k = 0; k < 8; ++k)
                 if (jj[k] >= 0) sum = fma(aa[k], pj[k], sum);
-        } else {
-            for (int k = 0; k < W; ++k) {
-                const int j = __builtin_nontemporal_load(scol + off + 64 * k + lane);
-                if (j >= 0) sum = fma(__builtin_nontemporal_load(sval + off + 64 * k + lane), pdir(z[j], beta, pold[j]), sum);
+            const int row = sl * 64 + lane;
+            if (row < n) {
+                const double pi = pdir(z[row], beta, pold[row]);
+                pnew[row] = pi;
+                w[row] = sum;
+                acc = fma(pi, sum, acc);
             }
         }
-        if (row < n) {
-            const double pi = pdir(z[row], beta, pold[row]);
-            pnew[row] = pi;
-            w[row] = sum;
-            acc = fma(pi, sum, acc);
+    } else {
+        for (int sl = s0 + wave; sl < s1; sl += STEP) {
+            const int off = meta[2 * sl], W = meta[2 * sl + 1];
+            double sum = 0.0;
+            for (int k = 0; k < W; ++k) {
+                const int j = __builtin_nontemporal_load(scol + off + 64 * k + lane);
+                if (j >= 0)
+                    sum = fma(__builtin_nontemporal_load(sval + off + 64 * k + lane), pdir(z[j], beta, pold[j]), sum);
+            }
+            const int row = sl * 64 + lane;
+            if (row < n) {
+                const double pi = pdir(z[row], beta, pold[row]);
+                pnew[row] = pi;
+                w[row] = sum;
+                acc = fma(pi, sum, acc);
+            }
         }
     }
     double v[1] = {acc};
@@ -467,6 +496,18 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
                                                    SolveState *st,
                                                    const double *part_delta, int g_delta, double *part_res,
                                                    int64_t per_block, int parity, int norm_pre, int tune) {
+    // the first entries' loads do not depend on alpha: issued before the
+    // reduction of p.Ap so that its latency overlaps them
+    const dev::Chunk c = dev::block_chunk(n, per_block);
+    const int64_t i0 = c.lo + threadIdx.x;
+    double x0 = 0.0, r0 = 0.0, p0 = 0.0, w0 = 0.0, d0 = 0.0;
+    if (i0 < c.hi) {
+        x0 = x[i0];
+        r0 = r[i0];
+        p0 = p[i0];
+        w0 = w[i0];
+        d0 = dinv[i0];
+    }
     double alpha = 0.0;
     double d[1];
     if (tune) {
@@ -485,14 +526,19 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
         alpha = rec.rho / delta;
         if (blockIdx.x == 0 && threadIdx.x == 0 && rec.k <= st->hist_cap) st->hist[rec.k - 1] = alpha;
     }
-    const dev::Chunk c = dev::block_chunk(n, per_block);
     double rz = 0.0, nn = 0.0;
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += VB) {
-        const double xi = fma(alpha, p[i], x[i]);
-        const double ri = fma(-alpha, w[i], r[i]);
+    for (int64_t i = i0; i < c.hi; i += VB) {
+        double xi, ri, pi, wi, di;
+        if (i == i0) {
+            xi = x0, ri = r0, pi = p0, wi = w0, di = d0;
+        } else {
+            xi = x[i], ri = r[i], pi = p[i], wi = w[i], di = dinv[i];
+        }
+        xi = fma(alpha, pi, xi);
+        ri = fma(-alpha, wi, ri);
         x[i] = xi;
         r[i] = ri;
-        const double zi = dinv[i] * ri;
+        const double zi = di * ri;
         z[i] = zi;
         rz = fma(zi, ri, rz);
         nn = norm_pre ? fma(zi, zi, nn) : fma(ri, ri, nn);
@@ -565,8 +611,12 @@ ProductFn stream_fn(int32_t lds_nnz) {
     return k_pcg_product_stream<TB, 21>;  // 21 * 256 >= kStreamMaxNnz
 }
 
-ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz) {
-    if (cfg.schedule == APCG_SPMV_SELL) return cfg.block_size == 512 ? k_pcg_product_sell<512> : k_pcg_product_sell<256>;
+ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw) {
+    if (cfg.schedule == APCG_SPMV_SELL) {
+        if (sell_maxw <= 8)
+            return cfg.block_size == 512 ? k_pcg_product_sell<512, 1> : k_pcg_product_sell<256, 1>;
+        return cfg.block_size == 512 ? k_pcg_product_sell<512, 0> : k_pcg_product_sell<256, 0>;
+    }
     if (cfg.schedule == APCG_SPMV_STREAM) {
         if (cfg.block_size == 512) return stream_fn<512>(lds_nnz);
         return stream_fn<256>(lds_nnz);
@@ -631,7 +681,7 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         int64_t rpb = ((int64_t)A->n + pl->g_prod - 1) / pl->g_prod;
         pl->rpb = (int32_t)std::max<int64_t>(1, rpb);
     }
-    pl->prod = product_fn(cfg, pl->lds_nnz);
+    pl->prod = product_fn(cfg, pl->lds_nnz, A->sell_maxw);
     if (!pl->prod) return set_error(APCG_ERR_INVALID_ARG, "unsupported lanes_per_row");
     vector_grid(A->n, &pl->g_vec, &pl->pb_vec);
     return APCG_SUCCESS;
