@@ -491,6 +491,24 @@ apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsys, const ap
                                             const double *dev_lmax, const apcg_solve_opts *opts,
                                             const apcg_fcg_opts *fopts, apcg_info info);
 
+/* Features of nsys systems at once (dev_feat[nsys][16], dev_lmax[nsys];
+ * the same values as apcg_pc_features per system): one batched 12-step
+ * Jacobi-PCG run from x0 = 0 on library scratch (the block-diagonal
+ * iteration of apcg_ksp_solve_batched_fcg_poly with every system in Jacobi
+ * mode), two passes of row statistics over all tiles and the Ritz values of
+ * each system.  A system with b = 0 takes lmax as its only Ritz value. */
+apcg_status apcg_pc_features_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                     float *dev_feat, double *dev_lmax);
+
+/* The learned batched solve: apcg_pc_features_batched, the network
+ * (standardised with dev_mean / dev_std) for all systems at once, then
+ * apcg_ksp_solve_batched_fcg_poly with the network's coefficients -- each
+ * system with its own polynomial and its own fallback to Jacobi-PCG. */
+apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                           const apcg_vec *x, double rtol, int32_t maxit, const float *dev_params,
+                                           const float *dev_mean, const float *dev_std, const apcg_solve_opts *opts,
+                                           const apcg_fcg_opts *fopts, apcg_info info);
+
 /* The learned solve in one call: features of (A, b), standardised with
  * dev_mean[16] / dev_std[16], the network dev_params[5833] -> coefficients,
  * then apcg_ksp_solve_fcg_poly with them (same options, result record and

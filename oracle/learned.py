@@ -82,7 +82,7 @@ def lanczos_data(A, b, m: int = M_STEPS):
     relative residual after the last step."""
     r = pcg(A, b, rtol=0.0, maxit=m, history=True)
     k = r.its
-    return r.alpha[:k], r.beta[: max(k - 1, 0)], r.res / r.ref
+    return r.alpha[:k], r.beta[: max(k - 1, 0)], (r.res / r.ref if r.ref > 0 else 1.0)
 
 
 def features(A, b):
@@ -93,12 +93,17 @@ def features(A, b):
       three largest Ritz values / Gershgorin upper, 13 log10(theta_max /
       theta_min), 14 log10 of the relative residual after the steps (floored
       at 1e-30, so a system that CG solves exactly in fewer steps still has
-      a finite feature), 15 log10(theta_min / Gershgorin upper)."""
+      a finite feature), 15 log10(theta_min / Gershgorin upper).
+    b = 0 (no iteration): the Gershgorin upper bound stands in as the only
+    Ritz value and the relative residual is taken as 1."""
     lo, hi = gershgorin(A)
     st = matrix_stats(A)
     al, be, relres = lanczos_data(A, b)
-    th, _ = gauss_nodes_weights(al, np.append(be, 0.0)[: al.size])
-    th = np.sort(th)
+    if al.size:
+        th, _ = gauss_nodes_weights(al, np.append(be, 0.0)[: al.size])
+        th = np.sort(th)
+    else:  # b = 0: no iteration; lmax stands in as the only Ritz value
+        th = np.array([hi])
     m = th.size  # fewer than three Ritz values (m < 3): the k-th smallest and
     lo3 = [th[min(k, m - 1)] for k in range(3)]          # k-th largest clamp to
     hi3 = [th[max(m - 3 + k, 0)] for k in range(3)]      # the ones that exist

@@ -408,6 +408,31 @@ def apcg_ksp_solve_batched_fcg_poly(ctx, A_list, b_list, x_list, rtol: float, ma
                                                _h(info)))
 
 
+def apcg_pc_features_batched(ctx, A_list, b_list, feat, lmax) -> None:
+    """feat: float32[nsys * 16], lmax: float64[nsys] GPU tensors (written on ctx)."""
+    n = len(A_list)
+    if len(b_list) != n:
+        raise ValueError("A_list and b_list must have the same length")
+    arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[int(h) for h in hs])  # noqa: E731
+    check("apcg_pc_features_batched", _L().apcg_pc_features_batched(_h(ctx), n, arr(A_list), arr(b_list),
+                                                                    _dptr(feat, "float32"), _dptr(lmax, "float64")))
+
+
+def apcg_ksp_solve_batched_learned(ctx, A_list, b_list, x_list, rtol: float, maxit: int, params, mean, std,
+                                   opts=None, fopts=None, info=None) -> None:
+    """params: float32[5833], mean / std: float32[16] GPU tensors."""
+    n = len(A_list)
+    if len(b_list) != n or len(x_list) != n:
+        raise ValueError("A_list, b_list and x_list must have the same length")
+    arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[int(h) for h in hs])  # noqa: E731
+    po = ctypes.byref(opts) if opts is not None else None
+    pf = ctypes.byref(fopts) if fopts is not None else None
+    check("apcg_ksp_solve_batched_learned",
+          _L().apcg_ksp_solve_batched_learned(_h(ctx), n, arr(A_list), arr(b_list), arr(x_list), float(rtol),
+                                              int(maxit), _dptr(params, "float32"), _dptr(mean, "float32"),
+                                              _dptr(std, "float32"), po, pf, _h(info)))
+
+
 # ------------------------------------------------------------------ timers
 
 def apcg_timer_create() -> int:

@@ -161,6 +161,9 @@ SIGNATURES = {
                                 P(apcg_fcg_opts), c_vp, c_i32],
     "apcg_ksp_solve_batched_fcg_poly": [c_vp, c_i32, c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, P(apcg_solve_opts),
                                         P(apcg_fcg_opts), c_vp],
+    "apcg_pc_features_batched": [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp],
+    "apcg_ksp_solve_batched_learned": [c_vp, c_i32, c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, c_vp,
+                                       P(apcg_solve_opts), P(apcg_fcg_opts), c_vp],
     "apcg_ksp_solve_learned": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, c_vp, c_vp, c_vp, P(apcg_solve_opts),
                                P(apcg_fcg_opts), c_vp, c_i32],
     "apcg_timer_create": [P(c_vp)],

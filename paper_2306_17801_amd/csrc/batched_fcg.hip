@@ -70,6 +70,9 @@ struct FPlan {
     int32_t nsys, ntiles, tiles_per_block;
     int32_t maxit, stall_min, fallback;
     double rtol, stall_frac;
+    int32_t force_jacobi;  // feature runs: every system in Jacobi mode from the start
+    int32_t hist_cap;      // > 0: alpha, beta of the first hist_cap iterations
+    double *hist;          // [nsys][2][hist_cap]
 };
 
 __device__ __forceinline__ void ftile_range(const FPlan &P, int *t0, int *t1) {
@@ -202,12 +205,15 @@ __global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef
     fsys_sum<3>(P, s, 0, v);
     __shared__ double cc[FDEG + 1];
     __shared__ int bad_point;
-    if (threadIdx.x <= FDEG) cc[threadIdx.x] = (double)coef[(size_t)s * (FDEG + 1) + threadIdx.x];
+    const bool jac = P.force_jacobi != 0;
+    if (threadIdx.x <= FDEG) cc[threadIdx.x] = jac ? (threadIdx.x == 0 ? 1.0 : 0.0)
+                                                   : (double)coef[(size_t)s * (FDEG + 1) + threadIdx.x];
     if (threadIdx.x == 0) bad_point = 0;
     __syncthreads();
-    const double lm = lmax[s];
-    for (int q = threadIdx.x; q < 1024; q += 64)
-        if (!(fpoly_at(cc, lm * q / 1023.0, lm) > 0.0)) atomicOr(&bad_point, 1);
+    const double lm = jac ? 1.0 : lmax[s];
+    if (!jac)
+        for (int q = threadIdx.x; q < 1024; q += 64)
+            if (!(fpoly_at(cc, lm * q / 1023.0, lm) > 0.0)) atomicOr(&bad_point, 1);
     __syncthreads();
     if (threadIdx.x != 0) return;
     FState q;
@@ -244,6 +250,7 @@ __global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef
             q.flag = 1;
         }
     }
+    if (jac) q.mode = MODE_JACOBI;  // reason 0: a plain Jacobi-PCG run
     P.st[s] = q;
     if (!q.flag) atomicAdd(P.running, 1u);
 }
@@ -302,6 +309,7 @@ __global__ __launch_bounds__(64) void k_bf_alpha(FPlan P) {
         else fswitch(P, q, APCG_SOLVE_BREAKDOWN_PAP);
     } else {
         q->alpha = q->rho / delta;
+        if (q->its < P.hist_cap) P.hist[(size_t)s * 2 * P.hist_cap + q->its] = q->alpha;
     }
 }
 
@@ -436,7 +444,97 @@ __global__ __launch_bounds__(64) void k_bf_beta(FPlan P) {
     else {
         q->beta = q->mode == MODE_FLEX ? -zw / q->delta : rz / q->rho;
         q->rho = rz;
+        if (q->its - 1 < P.hist_cap) P.hist[(size_t)s * 2 * P.hist_cap + P.hist_cap + q->its - 1] = q->beta;
     }
+}
+
+// ---- batched features (the learned preconditioner's inputs) -------------
+// Row statistics per tile -> fpart[k][t], k < 7 (dev::RowStats order).
+__global__ __launch_bounds__(FT) void k_bf_rows(FPlan P, double *fpart) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    __shared__ double sh[7][FT];
+    for (int t = t0; t < t1; ++t) {
+        const FSys S = P.sys[P.tile_sys[t]];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        dev::RowStats a;
+        if (i < S.n) dev::row_stats_add(a, S.rowptr, S.col, S.val, i);
+        for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = a.v[k];
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            dev::RowStats m;
+            for (int th = 0; th < FT; ++th) {
+                double b[7];
+                for (int k = 0; k < 7; ++k) b[k] = sh[k][th];
+                dev::row_stats_merge(m, b);
+            }
+            for (int k = 0; k < 7; ++k) fpart[(size_t)k * P.ntiles + t] = m.v[k];
+        }
+        __syncthreads();
+    }
+}
+
+// Per system (thread 0): the tiles merged in order -> fstats[s][0..6],
+// fstats[s][7] = mean ln d.
+__global__ __launch_bounds__(64) void k_bf_rows_final(FPlan P, const double *fpart, double *fstats) {
+    const int s = blockIdx.x;
+    if (threadIdx.x != 0) return;
+    dev::RowStats m;
+    for (int t = P.sys_tile0[s]; t < P.sys_tile0[s + 1]; ++t) {
+        double b[7];
+        for (int k = 0; k < 7; ++k) b[k] = fpart[(size_t)k * P.ntiles + t];
+        dev::row_stats_merge(m, b);
+    }
+    for (int k = 0; k < 7; ++k) fstats[8 * s + k] = m.v[k];
+    const int n = P.sys[s].n;
+    fstats[8 * s + 7] = n > 0 ? m.v[4] / (double)n : 0.0;
+}
+
+// sum (ln d_i - mean)^2 per tile -> fpart[7][t].
+__global__ __launch_bounds__(FT) void k_bf_rows2(FPlan P, const double *fstats, double *fpart) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    __shared__ double lds[FT / 64];
+    for (int t = t0; t < t1; ++t) {
+        const int s = P.tile_sys[t];
+        const FSys S = P.sys[s];
+        const int i = P.tile_row0[t] + threadIdx.x;
+        double v[1] = {0.0};
+        if (i < S.n) {
+            const double e = dev::row_logdiag(S.rowptr, S.col, S.val, i) - fstats[8 * s + 7];
+            v[0] = e * e;
+        }
+        dev::block_sum<FT, 1>(v, lds);
+        if (threadIdx.x == 0) fpart[(size_t)7 * P.ntiles + t] = v[0];
+        __syncthreads();
+    }
+}
+
+// Per system: Ritz values of its recorded run (thread i < m: the i-th
+// smallest), then the 16 features and lmax.  A system the run did not
+// iterate on (b = 0) takes lmax as its only Ritz value.
+__global__ __launch_bounds__(64) void k_bf_feat(FPlan P, const double *fpart, const double *fstats, float *feat,
+                                                double *lmax_out) {
+    const int s = blockIdx.x;
+    const FState q = P.st[s];
+    const double *al = P.hist + (size_t)s * 2 * P.hist_cap, *be = al + P.hist_cap;
+    int m = q.its < P.hist_cap ? q.its : P.hist_cap;
+    if (m > 16) m = 16;
+    const double *st = fstats + 8 * s;
+    __shared__ double th[16];
+    if ((int)threadIdx.x < m) th[threadIdx.x] = dev::lanczos_eig(al, be, m, threadIdx.x);
+    __syncthreads();
+    if (threadIdx.x != 0) return;
+    if (m < 1) {
+        th[0] = st[1];
+        m = 1;
+    }
+    double var = 0.0;
+    for (int t = P.sys_tile0[s]; t < P.sys_tile0[s + 1]; ++t) var += fpart[(size_t)7 * P.ntiles + t];
+    const FSys S = P.sys[s];
+    const double relres = q.ref > 0.0 ? q.res / q.ref : 1.0;
+    dev::feature_vector(st, var, th, m, relres, S.n, (int64_t)S.rowptr[S.n], feat + (size_t)16 * s);
+    lmax_out[s] = st[1];
 }
 
 __global__ void k_bf_finish(FPlan P, apcg_solve_info *info) {
@@ -480,6 +578,15 @@ struct BfCache {
     uint64_t graph_hash = 0;
     int32_t *pinned = nullptr;
     EventRef poll_ev[kMaxLookahead];
+    // feature runs
+    double *d_xs = nullptr;     // scratch iterates, offsets as the workspace's
+    double *d_hist = nullptr;   // [sys_cap][2][FEAT_STEPS]
+    double *d_fpart = nullptr;  // [8][tiles_cap]
+    double *d_fstats = nullptr; // [sys_cap][8]
+    float *d_X = nullptr;       // [sys_cap][16] features (learned solve)
+    float *d_C = nullptr;       // [sys_cap][9] coefficients (learned solve)
+    double *d_L = nullptr;      // [sys_cap] lmax (learned solve)
+    int64_t feat_sys_cap = 0, feat_tiles_cap = 0, xs_cap = 0;
 };
 
 static std::mutex g_bf_mu;
@@ -493,6 +600,16 @@ static BfCache *bf_cache(apcg_ctx c) {
     b->device = c->device;
     g_bf.emplace_back(c->id, b);
     return b;
+}
+
+static void bf_free_features(BfCache &b) {
+    hipFree(b.d_xs);
+    hipFree(b.d_hist);
+    hipFree(b.d_fpart);
+    hipFree(b.d_fstats);
+    hipFree(b.d_X);
+    hipFree(b.d_C);
+    hipFree(b.d_L);
 }
 
 static void bf_free(BfCache &b) {
@@ -522,8 +639,348 @@ void bfcg_cache_release(uint64_t ctx_id, int device) {
     if (!b) return;
     hipSetDevice(device);
     bf_free(*b);
+    bf_free_features(*b);
     if (b->pinned) hipHostFree(b->pinned);
     delete b;
+}
+
+}  // namespace apcg
+
+namespace apcg {
+
+constexpr int FEAT_STEPS = 12;  // Jacobi-PCG steps of the feature run
+
+// What one run of the batched iteration computes.
+struct BfRun {
+    const float *coeffs = nullptr;   // [nsys][9]
+    const double *lmax = nullptr;    // [nsys]
+    int force_jacobi = 0;            // feature run: plain Jacobi-PCG for every system
+    double *hist = nullptr;          // [nsys][2][hist_cap]
+    int32_t hist_cap = 0;
+};
+
+// Enqueues one run of the batched iteration on ctx's stream.  hs: the
+// systems (ws holds workspace offsets on entry); xs_base != nullptr: x of
+// system i is xs_base + its workspace offset / 9 (the feature run's scratch).
+static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<FSys> &hs, int64_t ws_total,
+                           double rtol, int32_t maxit, const apcg_solve_opts &opts, const apcg_fcg_opts &fo,
+                           const BfRun &run, apcg_solve_info *d_info) {
+    const int dev = ctx->device;
+    hipStream_t st = ctx->stream;
+    std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
+    for (int32_t q = 0; q < nsys; ++q) {
+        sys_tile0[q] = (int32_t)tile_sys.size();
+        for (int32_t r0 = 0; r0 < hs[q].n; r0 += FT) {
+            tile_sys.push_back(q);
+            tile_row0.push_back(r0);
+        }
+    }
+    sys_tile0[nsys] = (int32_t)tile_sys.size();
+    const int32_t ntiles = (int32_t)tile_sys.size();
+    if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well formed
+        tile_sys.push_back(0);
+        tile_row0.push_back(0);
+    }
+    const int32_t nt_alloc = std::max<int32_t>(ntiles, 1);
+    APCG_HIP(hipSetDevice(dev));
+    const int64_t ws_need = std::max<int64_t>(ws_total, 64);
+    if (bc->sys_cap < nsys || bc->tiles_cap < nt_alloc || bc->ws_cap < ws_need) {
+        EventRef ev = event_get(dev);
+        if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+        APCG_HIP(hipEventRecord(ev->e, st));
+        BfCache old = *bc;
+        defer_release({ev}, [old]() mutable {
+            hipSetDevice(old.device);
+            bf_free(old);
+        });
+        bc->exec = nullptr;
+        bc->graph = nullptr;
+        bc->graph_hash = 0;
+        bc->hash = 0;
+        bc->sys_cap = std::max<int64_t>(nsys, bc->sys_cap);
+        bc->tiles_cap = std::max<int64_t>(nt_alloc, bc->tiles_cap);
+        bc->ws_cap = std::max<int64_t>(ws_need, bc->ws_cap);
+        APCG_HIP(hipMalloc((void **)&bc->d_sys, sizeof(FSys) * bc->sys_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_st, sizeof(FState) * bc->sys_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_sys_tile0, sizeof(int32_t) * (bc->sys_cap + 1)));
+        APCG_HIP(hipMalloc((void **)&bc->d_tile_sys, sizeof(int32_t) * bc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_tile_row0, sizeof(int32_t) * bc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * bc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_ws, sizeof(double) * bc->ws_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_running, 256));
+    }
+    if (!bc->pinned)
+        APCG_HIP(hipHostMalloc((void **)&bc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
+    for (int32_t i = 0; i < nsys; ++i) hs[i].ws = bc->d_ws + reinterpret_cast<int64_t>(hs[i].ws);
+    uint64_t h = fnv(hs.data(), sizeof(FSys) * nsys);
+    h = fnv(tile_sys.data(), sizeof(int32_t) * tile_sys.size(), h);
+    h = fnv(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
+    h = fnv(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
+    if (h != bc->hash) {
+        g_counters.h2d_copies += 4;
+        APCG_HIP(hipMemcpyAsync(bc->d_sys, hs.data(), sizeof(FSys) * nsys, hipMemcpyHostToDevice, st));
+        APCG_HIP(hipMemcpyAsync(bc->d_tile_sys, tile_sys.data(), sizeof(int32_t) * tile_sys.size(),
+                                hipMemcpyHostToDevice, st));
+        APCG_HIP(hipMemcpyAsync(bc->d_tile_row0, tile_row0.data(), sizeof(int32_t) * tile_row0.size(),
+                                hipMemcpyHostToDevice, st));
+        APCG_HIP(hipMemcpyAsync(bc->d_sys_tile0, sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(),
+                                hipMemcpyHostToDevice, st));
+        g_counters.host_syncs++;
+        APCG_HIP(hipStreamSynchronize(st));  // the host tables are local
+        bc->hash = h;
+    }
+    FPlan P;
+    P.sys = bc->d_sys;
+    P.tile_sys = bc->d_tile_sys;
+    P.tile_row0 = bc->d_tile_row0;
+    P.sys_tile0 = bc->d_sys_tile0;
+    P.st = bc->d_st;
+    P.part = bc->d_part;
+    P.running = bc->d_running;
+    P.nsys = nsys;
+    P.ntiles = ntiles;
+    const int G = normalise_blocks(2048, std::max<int32_t>(ntiles, 1));
+    P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
+    P.maxit = maxit;
+    P.stall_min = fo.stall_min;
+    P.fallback = fo.fallback ? 1 : 0;
+    P.rtol = rtol;
+    P.stall_frac = fo.stall_frac;
+    P.force_jacobi = run.force_jacobi;
+    P.hist_cap = run.hist ? run.hist_cap : 0;
+    P.hist = run.hist;
+    const int x0z = opts.x0_is_zero ? 1 : 0;
+    apcg_status s;
+
+    hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, bc->d_running);
+    APCG_CHECK_LAUNCH("k_bf_reset");
+    hipLaunchKernelGGL(k_bf_init, dim3(G), dim3(FT), 0, st, P, x0z);
+    APCG_CHECK_LAUNCH("k_bf_init");
+    hipLaunchKernelGGL(k_bf_init_final, dim3(nsys), dim3(64), 0, st, P, run.coeffs, run.lmax);
+    APCG_CHECK_LAUNCH("k_bf_init_final");
+    if (!x0z) {
+        hipLaunchKernelGGL(k_bf_zero_x, dim3(G), dim3(FT), 0, st, P);
+        APCG_CHECK_LAUNCH("k_bf_zero_x");
+    }
+    int K = std::max(2, opts.iters_per_graph);
+    if (K & 1) ++K;
+    const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
+    // Clenshaw buffers t0..t2 round robin: b_j in t[j % 3]
+    auto launch_iter = [&](int j) -> apcg_status {
+        hipLaunchKernelGGL(k_bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
+        APCG_CHECK_LAUNCH("k_bf_product");
+        hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(64), 0, st, P);
+        APCG_CHECK_LAUNCH("k_bf_alpha");
+        hipLaunchKernelGGL(k_bf_update, dim3(G), dim3(FT), 0, st, P, j & 1);
+        APCG_CHECK_LAUNCH("k_bf_update");
+        hipLaunchKernelGGL(k_bf_check, dim3(nsys), dim3(64), 0, st, P);
+        APCG_CHECK_LAUNCH("k_bf_check");
+        for (int d = FDEG - 1; d >= 0; --d) {
+            const int stage = d == FDEG - 1 ? 0 : (d == 0 ? 2 : 1);
+            if (run.force_jacobi && stage != 2) continue;  // Jacobi mode: only z = D^-1 r
+            const int ob1 = stage == 0 ? -1 : (d + 1) % 3;
+            const int ob2 = (stage == 0 || d + 2 == FDEG) ? -1 : (d + 2) % 3;
+            const int oout = stage == 2 ? -1 : d % 3;
+            hipLaunchKernelGGL(k_bf_cheb, dim3(G), dim3(FT), 0, st, P, d, stage, ob1, ob2, oout);
+            APCG_CHECK_LAUNCH("k_bf_cheb");
+        }
+        hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(64), 0, st, P);
+        APCG_CHECK_LAUNCH("k_bf_beta");
+        return APCG_SUCCESS;
+    };
+    const bool graph = opts.mode == APCG_MODE_GRAPH && !run.force_jacobi;  // feature runs are short: no capture
+    uint64_t gh = fnv(&h, sizeof h);
+    const double prm[2] = {rtol, fo.stall_frac};
+    const int iprm[7] = {K, maxit, G, nsys, fo.stall_min, P.fallback, P.tiles_per_block};
+    gh = fnv(prm, sizeof prm, gh);
+    gh = fnv(iprm, sizeof iprm, gh);
+    const void *ptrs[3] = {bc->d_st, bc->d_part, bc->d_running};
+    gh = fnv(ptrs, sizeof ptrs, gh);
+    if (maxit > 0) {
+        if (graph && (!bc->exec || bc->graph_hash != gh)) {
+            if (bc->exec) {
+                EventRef ev = event_get(dev);
+                if (ev) hipEventRecord(ev->e, st);
+                hipGraphExec_t oe = bc->exec;
+                hipGraph_t og = bc->graph;
+                defer_release({ev}, [oe, og, dev]() {
+                    hipSetDevice(dev);
+                    hipGraphExecDestroy(oe);
+                    hipGraphDestroy(og);
+                });
+                bc->exec = nullptr;
+                bc->graph = nullptr;
+            }
+            APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+            apcg_status cs = APCG_SUCCESS;
+            for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j);
+            hipGraph_t g = nullptr;
+            hipError_t e = hipStreamEndCapture(st, &g);
+            if (cs) {
+                if (g) hipGraphDestroy(g);
+                return cs;
+            }
+            if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(batched fcg)");
+            g_counters.kernel_launches -= (int64_t)(5 + FDEG) * K;
+            e = hipGraphInstantiate(&bc->exec, g, nullptr, nullptr, 0);
+            if (e != hipSuccess) {
+                hipGraphDestroy(g);
+                return hip_error(e, "hipGraphInstantiate(batched fcg)");
+            }
+            bc->graph = g;
+            bc->graph_hash = gh;
+        }
+        // iteration slots: maxit counted iterations plus at most two
+        // restarts per system (the first application and one switch)
+        const int64_t periods = ((int64_t)maxit + 2 + K - 1) / K;
+        for (int64_t g = 0; g < periods; ++g) {
+            if (graph) {
+                g_counters.graph_launches++;
+                APCG_HIP(hipGraphLaunch(bc->exec, st));
+            } else {
+                for (int j = 1; j <= K; ++j)
+                    if ((s = launch_iter(j))) return s;
+            }
+            const int slot = (int)(g % L);
+            if (!bc->poll_ev[slot]) {
+                bc->poll_ev[slot] = event_get(dev);
+                if (!bc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
+            }
+            g_counters.d2h_copies++;
+            APCG_HIP(hipMemcpyAsync(&bc->pinned[slot], bc->d_running, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            APCG_HIP(hipEventRecord(bc->poll_ev[slot]->e, st));
+            if (g >= L - 1) {
+                const int ps = (int)((g - (L - 1)) % L);
+                g_counters.host_polls++;
+                APCG_HIP(hipEventSynchronize(bc->poll_ev[ps]->e));
+                if (bc->pinned[ps] == 0) break;  // every system has stopped
+            }
+        }
+    }
+    if (d_info) {
+        hipLaunchKernelGGL(k_bf_finish, dim3((nsys + 63) / 64), dim3(64), 0, st, P, d_info);
+        APCG_CHECK_LAUNCH("k_bf_finish");
+    }
+    return APCG_SUCCESS;
+}
+
+// Checks the systems and builds their descriptors (workspace offsets in ws).
+static apcg_status bf_systems(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b, const apcg_vec *x,
+                              std::vector<FSys> &hs, int64_t *ws_total) {
+    const int dev = ctx->device;
+    hs.resize(nsys);
+    int64_t tot = 0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        if (!A[i] || !b[i] || (x && !x[i])) return set_error(APCG_ERR_INVALID_ARG, "NULL system handle");
+        if (A[i]->device != dev || b[i]->device != dev || (x && x[i]->device != dev))
+            return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+        if (b[i]->n != A[i]->n || (x && x[i]->n != A[i]->n))
+            return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
+        if (x && (b[i] == x[i] || (b[i]->d == x[i]->d && A[i]->n > 0)))
+            return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
+        const int64_t n = A[i]->n;
+        hs[i] = FSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x ? x[i]->d : nullptr,
+                     reinterpret_cast<double *>(tot), (int32_t)n, 0};
+        tot += ((9 * n + 63) / 64) * 64;
+    }
+    if (x) {
+        std::vector<std::pair<const double *, int32_t>> xs(nsys);
+        for (int32_t i = 0; i < nsys; ++i) xs[i] = {x[i]->d, i};
+        std::sort(xs.begin(), xs.end());
+        for (int32_t i = 1; i < nsys; ++i)
+            if (xs[i].first == xs[i - 1].first && x[xs[i].second]->n > 0)
+                return set_error(APCG_ERR_INVALID_ARG, "two systems share one solution vector");
+    }
+    *ws_total = tot;
+    return APCG_SUCCESS;
+}
+
+static apcg_status bf_common_checks(apcg_ctx ctx, int32_t nsys, const void *A, const void *b) {
+    if (!ctx || nsys < 1 || !A || !b) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+    if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING && ctx->is_default_global)
+        return set_error(APCG_ERR_INVALID_ARG, "pass a context created with apcg_ctx_create");
+    return APCG_SUCCESS;
+}
+
+// Features of every system into feat[nsys][16] / lmax[nsys] (device), on
+// ctx: one batched 12-step Jacobi-PCG run from x0 = 0 on scratch iterates
+// with alpha/beta recorded, two passes of row statistics, the Ritz values.
+static apcg_status bf_features(apcg_ctx ctx, BfCache *bc, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                               float *feat, double *lmax) {
+    std::vector<FSys> hs;
+    int64_t ws_total = 0;
+    apcg_status s;
+    if ((s = bf_systems(ctx, nsys, A, b, nullptr, hs, &ws_total))) return s;
+    const int dev = ctx->device;
+    hipStream_t st = ctx->stream;
+    APCG_HIP(hipSetDevice(dev));
+    int64_t ntiles = 0;
+    for (auto &f : hs) ntiles += (f.n + FT - 1) / FT;
+    ntiles = std::max<int64_t>(ntiles, 1);
+    const int64_t xs_need = std::max<int64_t>(ws_total / 9 + 64, 64);
+    if (bc->feat_sys_cap < nsys || bc->feat_tiles_cap < ntiles || bc->xs_cap < xs_need) {
+        EventRef ev = event_get(dev);
+        if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+        APCG_HIP(hipEventRecord(ev->e, st));
+        BfCache old = *bc;
+        defer_release({ev}, [old]() mutable {
+            hipSetDevice(old.device);
+            bf_free_features(old);
+        });
+        bc->feat_sys_cap = std::max<int64_t>(nsys, bc->feat_sys_cap);
+        bc->feat_tiles_cap = std::max<int64_t>(ntiles, bc->feat_tiles_cap);
+        bc->xs_cap = std::max<int64_t>(xs_need, bc->xs_cap);
+        APCG_HIP(hipMalloc((void **)&bc->d_xs, sizeof(double) * bc->xs_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_hist, sizeof(double) * 2 * FEAT_STEPS * bc->feat_sys_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_fpart, sizeof(double) * 8 * bc->feat_tiles_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_fstats, sizeof(double) * 8 * bc->feat_sys_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_X, sizeof(float) * 16 * bc->feat_sys_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_C, sizeof(float) * 9 * bc->feat_sys_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_L, sizeof(double) * bc->feat_sys_cap));
+    }
+    if (!feat) feat = bc->d_X;  // the learned solve keeps them in the cache
+    if (!lmax) lmax = bc->d_L;
+    // scratch iterates: the workspace offset / 9 keeps every system's range apart
+    for (auto &f : hs) f.x = bc->d_xs + reinterpret_cast<int64_t>(f.ws) / 9;
+    apcg_solve_opts o;
+    apcg_solve_opts_default(&o);
+    o.x0_is_zero = 1;
+    o.mode = APCG_MODE_STREAM;
+    o.iters_per_graph = FEAT_STEPS + 2;  // one period: the first application and the steps
+    apcg_fcg_opts fo;
+    apcg_fcg_opts_default(&fo);
+    fo.fallback = 0;
+    BfRun run;
+    run.force_jacobi = 1;
+    run.hist = bc->d_hist;
+    run.hist_cap = FEAT_STEPS;
+    if ((s = bf_core(ctx, bc, nsys, hs, ws_total, 0.0, FEAT_STEPS, o, fo, run, nullptr))) return s;
+    FPlan P;
+    P.sys = bc->d_sys;
+    P.tile_sys = bc->d_tile_sys;
+    P.tile_row0 = bc->d_tile_row0;
+    P.sys_tile0 = bc->d_sys_tile0;
+    P.st = bc->d_st;
+    P.part = bc->d_part;
+    P.running = bc->d_running;
+    P.nsys = nsys;
+    int32_t nt = 0;
+    for (auto &f : hs) nt += (f.n + FT - 1) / FT;
+    P.ntiles = nt;
+    const int G = normalise_blocks(2048, std::max<int32_t>(nt, 1));
+    P.tiles_per_block = std::max<int32_t>(1, (nt + G - 1) / G);
+    P.hist = bc->d_hist;
+    P.hist_cap = FEAT_STEPS;
+    hipLaunchKernelGGL(k_bf_rows, dim3(G), dim3(FT), 0, st, P, bc->d_fpart);
+    APCG_CHECK_LAUNCH("k_bf_rows");
+    hipLaunchKernelGGL(k_bf_rows_final, dim3(nsys), dim3(64), 0, st, P, (const double *)bc->d_fpart, bc->d_fstats);
+    APCG_CHECK_LAUNCH("k_bf_rows_final");
+    hipLaunchKernelGGL(k_bf_rows2, dim3(G), dim3(FT), 0, st, P, (const double *)bc->d_fstats, bc->d_fpart);
+    APCG_CHECK_LAUNCH("k_bf_rows2");
+    hipLaunchKernelGGL(k_bf_feat, dim3(nsys), dim3(64), 0, st, P, (const double *)bc->d_fpart,
+                       (const double *)bc->d_fstats, feat, lmax);
+    APCG_CHECK_LAUNCH("k_bf_feat");
+    return APCG_SUCCESS;
 }
 
 }  // namespace apcg
@@ -536,13 +993,13 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
                                                        const double *dev_lmax, const apcg_solve_opts *opts_in,
                                                        const apcg_fcg_opts *fopts_in, apcg_info info) {
     try {
-        if (!ctx || nsys < 1 || !A || !b || !x || !info || !dev_coeffs || !dev_lmax)
-            return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
-        if (info->count < nsys) return set_error(APCG_ERR_INVALID_ARG, "info has fewer records than systems");
+        apcg_status s;
+        if ((s = bf_common_checks(ctx, nsys, A, b))) return s;
+        if (!x || !info || !dev_coeffs || !dev_lmax) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (info->count < nsys || info->device != ctx->device)
+            return set_error(APCG_ERR_INVALID_ARG, "info has fewer records than systems or another device");
         if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(APCG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
         if (maxit < 0) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0");
-        if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING && ctx->is_default_global)
-            return set_error(APCG_ERR_INVALID_ARG, "pass a context created with apcg_ctx_create");
         apcg_solve_opts opts;
         if (opts_in) opts = *opts_in;
         else apcg_solve_opts_default(&opts);
@@ -550,46 +1007,9 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
         if (fopts_in) fo = *fopts_in;
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
-        const int dev = ctx->device;
-        std::vector<FSys> hs(nsys);
+        std::vector<FSys> hs;
         int64_t ws_total = 0;
-        for (int32_t i = 0; i < nsys; ++i) {
-            if (!A[i] || !b[i] || !x[i]) return set_error(APCG_ERR_INVALID_ARG, "NULL system handle");
-            if (A[i]->device != dev || b[i]->device != dev || x[i]->device != dev || info->device != dev)
-                return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
-            if (b[i]->n != A[i]->n || x[i]->n != A[i]->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
-            if (b[i] == x[i] || (b[i]->d == x[i]->d && A[i]->n > 0))
-                return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
-            const int64_t n = A[i]->n;
-            hs[i] = FSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x[i]->d,
-                         reinterpret_cast<double *>(ws_total), (int32_t)n, 0};
-            ws_total += ((9 * n + 63) / 64) * 64;
-        }
-        {
-            std::vector<std::pair<const double *, int32_t>> xs(nsys);
-            for (int32_t i = 0; i < nsys; ++i) xs[i] = {x[i]->d, i};
-            std::sort(xs.begin(), xs.end());
-            for (int32_t i = 1; i < nsys; ++i)
-                if (xs[i].first == xs[i - 1].first && x[xs[i].second]->n > 0)
-                    return set_error(APCG_ERR_INVALID_ARG, "two systems share one solution vector");
-        }
-        std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
-        for (int32_t s = 0; s < nsys; ++s) {
-            sys_tile0[s] = (int32_t)tile_sys.size();
-            for (int32_t r0 = 0; r0 < hs[s].n; r0 += FT) {
-                tile_sys.push_back(s);
-                tile_row0.push_back(r0);
-            }
-        }
-        sys_tile0[nsys] = (int32_t)tile_sys.size();
-        const int32_t ntiles = (int32_t)tile_sys.size();
-        if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well formed
-            tile_sys.push_back(0);
-            tile_row0.push_back(0);
-        }
-        const int32_t nt_alloc = std::max<int32_t>(ntiles, 1);
-
-        BfCache *bc = bf_cache(ctx);
+        if ((s = bf_systems(ctx, nsys, A, b, x, hs, &ws_total))) return s;
         std::vector<Acc> acc;
         acc.reserve(3 * nsys + 1);
         for (int32_t i = 0; i < nsys; ++i) {
@@ -598,181 +1018,78 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
             acc.push_back({&b[i]->rec, ACC_R});
         }
         acc.push_back({&info->rec, ACC_W});
-        apcg_status s;
         if ((s = op_begin(ctx, acc.data(), (int)acc.size()))) return s;
-        hipStream_t st = ctx->stream;
-        APCG_HIP(hipSetDevice(dev));
-        const int64_t ws_need = std::max<int64_t>(ws_total, 64);
-        if (bc->sys_cap < nsys || bc->tiles_cap < nt_alloc || bc->ws_cap < ws_need) {
-            EventRef ev = event_get(dev);
-            if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
-            APCG_HIP(hipEventRecord(ev->e, st));
-            BfCache old = *bc;
-            defer_release({ev}, [old]() mutable {
-                hipSetDevice(old.device);
-                bf_free(old);
-            });
-            bc->exec = nullptr;
-            bc->graph = nullptr;
-            bc->graph_hash = 0;
-            bc->hash = 0;
-            bc->sys_cap = std::max<int64_t>(nsys, bc->sys_cap);
-            bc->tiles_cap = std::max<int64_t>(nt_alloc, bc->tiles_cap);
-            bc->ws_cap = std::max<int64_t>(ws_need, bc->ws_cap);
-            APCG_HIP(hipMalloc((void **)&bc->d_sys, sizeof(FSys) * bc->sys_cap));
-            APCG_HIP(hipMalloc((void **)&bc->d_st, sizeof(FState) * bc->sys_cap));
-            APCG_HIP(hipMalloc((void **)&bc->d_sys_tile0, sizeof(int32_t) * (bc->sys_cap + 1)));
-            APCG_HIP(hipMalloc((void **)&bc->d_tile_sys, sizeof(int32_t) * bc->tiles_cap));
-            APCG_HIP(hipMalloc((void **)&bc->d_tile_row0, sizeof(int32_t) * bc->tiles_cap));
-            APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * bc->tiles_cap));
-            APCG_HIP(hipMalloc((void **)&bc->d_ws, sizeof(double) * bc->ws_cap));
-            APCG_HIP(hipMalloc((void **)&bc->d_running, 256));
-        }
-        if (!bc->pinned)
-            APCG_HIP(hipHostMalloc((void **)&bc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
-        for (int32_t i = 0; i < nsys; ++i) hs[i].ws = bc->d_ws + reinterpret_cast<int64_t>(hs[i].ws);
-        uint64_t h = fnv(hs.data(), sizeof(FSys) * nsys);
-        h = fnv(tile_sys.data(), sizeof(int32_t) * tile_sys.size(), h);
-        h = fnv(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
-        h = fnv(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
-        if (h != bc->hash) {
-            g_counters.h2d_copies += 4;
-            APCG_HIP(hipMemcpyAsync(bc->d_sys, hs.data(), sizeof(FSys) * nsys, hipMemcpyHostToDevice, st));
-            APCG_HIP(hipMemcpyAsync(bc->d_tile_sys, tile_sys.data(), sizeof(int32_t) * tile_sys.size(),
-                                    hipMemcpyHostToDevice, st));
-            APCG_HIP(hipMemcpyAsync(bc->d_tile_row0, tile_row0.data(), sizeof(int32_t) * tile_row0.size(),
-                                    hipMemcpyHostToDevice, st));
-            APCG_HIP(hipMemcpyAsync(bc->d_sys_tile0, sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(),
-                                    hipMemcpyHostToDevice, st));
-            g_counters.host_syncs++;
-            APCG_HIP(hipStreamSynchronize(st));  // the host tables are local
-            bc->hash = h;
-        }
-        FPlan P;
-        P.sys = bc->d_sys;
-        P.tile_sys = bc->d_tile_sys;
-        P.tile_row0 = bc->d_tile_row0;
-        P.sys_tile0 = bc->d_sys_tile0;
-        P.st = bc->d_st;
-        P.part = bc->d_part;
-        P.running = bc->d_running;
-        P.nsys = nsys;
-        P.ntiles = ntiles;
-        const int G = normalise_blocks(2048, std::max<int32_t>(ntiles, 1));
-        P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
-        P.maxit = maxit;
-        P.stall_min = fo.stall_min;
-        P.fallback = fo.fallback ? 1 : 0;
-        P.rtol = rtol;
-        P.stall_frac = fo.stall_frac;
-        const int x0z = opts.x0_is_zero ? 1 : 0;
+        BfRun run;
+        run.coeffs = dev_coeffs;
+        run.lmax = dev_lmax;
+        if ((s = bf_core(ctx, bf_cache(ctx), nsys, hs, ws_total, rtol, maxit, opts, fo, run, info->d))) return s;
+        return op_end(ctx, acc.data(), (int)acc.size());
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
 
-        hipLaunchKernelGGL(k_bf_reset, dim3(1), dim3(64), 0, st, bc->d_running);
-        APCG_CHECK_LAUNCH("k_bf_reset");
-        hipLaunchKernelGGL(k_bf_init, dim3(G), dim3(FT), 0, st, P, x0z);
-        APCG_CHECK_LAUNCH("k_bf_init");
-        hipLaunchKernelGGL(k_bf_init_final, dim3(nsys), dim3(64), 0, st, P, dev_coeffs, dev_lmax);
-        APCG_CHECK_LAUNCH("k_bf_init_final");
-        if (!x0z) {
-            hipLaunchKernelGGL(k_bf_zero_x, dim3(G), dim3(FT), 0, st, P);
-            APCG_CHECK_LAUNCH("k_bf_zero_x");
+extern "C" apcg_status apcg_pc_features_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                                float *dev_feat, double *dev_lmax) {
+    try {
+        apcg_status s;
+        if ((s = bf_common_checks(ctx, nsys, A, b))) return s;
+        if (!dev_feat || !dev_lmax) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        std::vector<Acc> acc;
+        acc.reserve(2 * nsys);
+        for (int32_t i = 0; i < nsys; ++i) {
+            if (!A[i] || !b[i]) return set_error(APCG_ERR_INVALID_ARG, "NULL system handle");
+            acc.push_back({&A[i]->rec, ACC_R});
+            acc.push_back({&b[i]->rec, ACC_R});
         }
-        int K = std::max(2, opts.iters_per_graph);
-        if (K & 1) ++K;
-        const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
-        // Clenshaw buffers t0..t2 round robin: b_j in t[j % 3]
-        auto launch_iter = [&](int j) -> apcg_status {
-            hipLaunchKernelGGL(k_bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
-            APCG_CHECK_LAUNCH("k_bf_product");
-            hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(64), 0, st, P);
-            APCG_CHECK_LAUNCH("k_bf_alpha");
-            hipLaunchKernelGGL(k_bf_update, dim3(G), dim3(FT), 0, st, P, j & 1);
-            APCG_CHECK_LAUNCH("k_bf_update");
-            hipLaunchKernelGGL(k_bf_check, dim3(nsys), dim3(64), 0, st, P);
-            APCG_CHECK_LAUNCH("k_bf_check");
-            for (int d = FDEG - 1; d >= 0; --d) {
-                const int stage = d == FDEG - 1 ? 0 : (d == 0 ? 2 : 1);
-                const int ob1 = stage == 0 ? -1 : (d + 1) % 3;
-                const int ob2 = (stage == 0 || d + 2 == FDEG) ? -1 : (d + 2) % 3;
-                const int oout = stage == 2 ? -1 : d % 3;
-                hipLaunchKernelGGL(k_bf_cheb, dim3(G), dim3(FT), 0, st, P, d, stage, ob1, ob2, oout);
-                APCG_CHECK_LAUNCH("k_bf_cheb");
-            }
-            hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(64), 0, st, P);
-            APCG_CHECK_LAUNCH("k_bf_beta");
-            return APCG_SUCCESS;
-        };
-        uint64_t gh = fnv(&h, sizeof h);
-        const double prm[2] = {rtol, fo.stall_frac};
-        const int iprm[7] = {K, maxit, G, nsys, fo.stall_min, P.fallback, P.tiles_per_block};
-        gh = fnv(prm, sizeof prm, gh);
-        gh = fnv(iprm, sizeof iprm, gh);
-        const void *ptrs[3] = {bc->d_st, bc->d_part, bc->d_running};
-        gh = fnv(ptrs, sizeof ptrs, gh);
-        if (maxit > 0) {
-            if (opts.mode == APCG_MODE_GRAPH && (!bc->exec || bc->graph_hash != gh)) {
-                if (bc->exec) {
-                    EventRef ev = event_get(dev);
-                    if (ev) hipEventRecord(ev->e, st);
-                    hipGraphExec_t oe = bc->exec;
-                    hipGraph_t og = bc->graph;
-                    defer_release({ev}, [oe, og, dev]() {
-                        hipSetDevice(dev);
-                        hipGraphExecDestroy(oe);
-                        hipGraphDestroy(og);
-                    });
-                    bc->exec = nullptr;
-                    bc->graph = nullptr;
-                }
-                APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-                apcg_status cs = APCG_SUCCESS;
-                for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j);
-                hipGraph_t g = nullptr;
-                hipError_t e = hipStreamEndCapture(st, &g);
-                if (cs) {
-                    if (g) hipGraphDestroy(g);
-                    return cs;
-                }
-                if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(batched fcg)");
-                g_counters.kernel_launches -= (int64_t)(5 + FDEG) * K;
-                e = hipGraphInstantiate(&bc->exec, g, nullptr, nullptr, 0);
-                if (e != hipSuccess) {
-                    hipGraphDestroy(g);
-                    return hip_error(e, "hipGraphInstantiate(batched fcg)");
-                }
-                bc->graph = g;
-                bc->graph_hash = gh;
-            }
-            // iteration slots: maxit counted iterations plus at most two
-            // restarts per system (the first application and one switch)
-            const int64_t periods = ((int64_t)maxit + 2 + K - 1) / K;
-            for (int64_t g = 0; g < periods; ++g) {
-                if (opts.mode == APCG_MODE_GRAPH) {
-                    g_counters.graph_launches++;
-                    APCG_HIP(hipGraphLaunch(bc->exec, st));
-                } else {
-                    for (int j = 1; j <= K; ++j)
-                        if ((s = launch_iter(j))) return s;
-                }
-                const int slot = (int)(g % L);
-                if (!bc->poll_ev[slot]) {
-                    bc->poll_ev[slot] = event_get(dev);
-                    if (!bc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
-                }
-                g_counters.d2h_copies++;
-                APCG_HIP(hipMemcpyAsync(&bc->pinned[slot], bc->d_running, sizeof(int32_t), hipMemcpyDeviceToHost,
-                                        st));
-                APCG_HIP(hipEventRecord(bc->poll_ev[slot]->e, st));
-                if (g >= L - 1) {
-                    const int ps = (int)((g - (L - 1)) % L);
-                    g_counters.host_polls++;
-                    APCG_HIP(hipEventSynchronize(bc->poll_ev[ps]->e));
-                    if (bc->pinned[ps] == 0) break;  // every system has stopped
-                }
-            }
+        if ((s = op_begin(ctx, acc.data(), (int)acc.size()))) return s;
+        if ((s = bf_features(ctx, bf_cache(ctx), nsys, A, b, dev_feat, dev_lmax))) return s;
+        return op_end(ctx, acc.data(), (int)acc.size());
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+extern "C" apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys, const apcg_mat *A,
+                                                      const apcg_vec *b, const apcg_vec *x, double rtol,
+                                                      int32_t maxit, const float *dev_params, const float *dev_mean,
+                                                      const float *dev_std, const apcg_solve_opts *opts_in,
+                                                      const apcg_fcg_opts *fopts_in, apcg_info info) {
+    try {
+        apcg_status s;
+        if ((s = bf_common_checks(ctx, nsys, A, b))) return s;
+        if (!x || !info || !dev_params || !dev_mean || !dev_std)
+            return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+        if (info->count < nsys || info->device != ctx->device)
+            return set_error(APCG_ERR_INVALID_ARG, "info has fewer records than systems or another device");
+        if (!(rtol >= 0.0) || !std::isfinite(rtol)) return set_error(APCG_ERR_INVALID_ARG, "rtol must be finite and >= 0");
+        if (maxit < 0) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0");
+        apcg_solve_opts opts;
+        if (opts_in) opts = *opts_in;
+        else apcg_solve_opts_default(&opts);
+        apcg_fcg_opts fo;
+        if (fopts_in) fo = *fopts_in;
+        else apcg_fcg_opts_default(&fo);
+        if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        std::vector<FSys> hs;
+        int64_t ws_total = 0;
+        if ((s = bf_systems(ctx, nsys, A, b, x, hs, &ws_total))) return s;
+        std::vector<Acc> acc;
+        acc.reserve(3 * nsys + 1);
+        for (int32_t i = 0; i < nsys; ++i) {
+            acc.push_back({&x[i]->rec, ACC_RW});
+            acc.push_back({&A[i]->rec, ACC_R});
+            acc.push_back({&b[i]->rec, ACC_R});
         }
-        hipLaunchKernelGGL(k_bf_finish, dim3((nsys + 63) / 64), dim3(64), 0, st, P, info->d);
-        APCG_CHECK_LAUNCH("k_bf_finish");
+        acc.push_back({&info->rec, ACC_W});
+        if ((s = op_begin(ctx, acc.data(), (int)acc.size()))) return s;
+        BfCache *bc = bf_cache(ctx);
+        if ((s = bf_features(ctx, bc, nsys, A, b, nullptr, nullptr))) return s;
+        if ((s = mlp_infer(ctx, dev_params, dev_mean, dev_std, bc->d_X, nsys, bc->d_C))) return s;
+        BfRun run;
+        run.coeffs = bc->d_C;
+        run.lmax = bc->d_L;
+        if ((s = bf_core(ctx, bc, nsys, hs, ws_total, rtol, maxit, opts, fo, run, info->d))) return s;
         return op_end(ctx, acc.data(), (int)acc.size());
     } catch (const std::bad_alloc &) {
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");

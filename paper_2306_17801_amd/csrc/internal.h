@@ -206,6 +206,10 @@ void seg_cache_release(uint64_t ctx_id, int device);    // batched.hip
 void learn_cache_release(uint64_t ctx_id, int device);  // learn.hip
 void fcg_cache_release(uint64_t ctx_id, int device);    // fcg.hip
 void bfcg_cache_release(uint64_t ctx_id, int device);   // batched_fcg.hip
+// Standardises X[B][16] in place with mean/std and writes the network's
+// coefficients C[B][9] (learn.hip); ordered on ctx's stream.
+apcg_status mlp_infer(apcg_ctx ctx, const float *params, const float *mean, const float *std, float *X, int32_t B,
+                      float *C);
 void spmv_default_config(int32_t n, int64_t nnz, apcg_spmv_config *cfg);
 int32_t normalise_blocks(int32_t blocks, int64_t units);  // multiple of 8, <= kMaxBlocks
 
@@ -326,6 +330,125 @@ __device__ __forceinline__ void reduce_partials(const double *partials, int G, d
     __syncthreads();
 #pragma unroll
     for (int k = 0; k < NV; ++k) out[k] = bcast[k];
+}
+
+
+// ---------------------------------------------------------------------------
+// learned-preconditioner features (learn.hip, batched_fcg.hip)
+// ---------------------------------------------------------------------------
+// Per-row statistics, accumulated over rows: min(1 - R_i), max(1 + R_i) with
+// R_i = sum |offdiag| / |d_i| (Gershgorin bounds of D^-1 A), min / max / sum
+// of ln d_i, sum over rows with off-diagonals of ln(max |off| / min |off|)
+// and the count of such rows.
+struct RowStats {
+    double v[7] = {INFINITY, -INFINITY, INFINITY, -INFINITY, 0.0, 0.0, 0.0};
+};
+
+__device__ inline void row_stats_add(RowStats &a, const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                     const double *__restrict__ val, int64_t i) {
+    double d = 0.0, off = 0.0, omax = 0.0, omin = INFINITY;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
+        const double x = val[k];
+        if (col[k] == (int)i) d = x;
+        else {
+            const double ax = fabs(x);
+            off += ax;
+            omax = fmax(omax, ax);
+            omin = fmin(omin, ax);
+        }
+    }
+    const double R = off / fabs(d), ld = log(d);
+    a.v[0] = fmin(a.v[0], 1.0 - R);
+    a.v[1] = fmax(a.v[1], 1.0 + R);
+    a.v[2] = fmin(a.v[2], ld);
+    a.v[3] = fmax(a.v[3], ld);
+    a.v[4] += ld;
+    if (omax > 0.0) {
+        a.v[5] += log(omax / omin);
+        a.v[6] += 1.0;
+    }
+}
+
+__device__ inline void row_stats_merge(RowStats &a, const double *b) {
+    a.v[0] = fmin(a.v[0], b[0]);
+    a.v[1] = fmax(a.v[1], b[1]);
+    a.v[2] = fmin(a.v[2], b[2]);
+    a.v[3] = fmax(a.v[3], b[3]);
+    a.v[4] += b[4];
+    a.v[5] += b[5];
+    a.v[6] += b[6];
+}
+
+__device__ inline double row_logdiag(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
+                                     const double *__restrict__ val, int64_t i) {
+    double d = 0.0;
+    for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
+        if (col[k] == (int)i) d = val[k];
+    return log(d);
+}
+
+// Eigenvalues below x of the symmetric tridiagonal with diagonal
+// 1/al_j + be_{j-1}/al_{j-1} and squared off-diagonal be_j / al_j^2 (the
+// CG-Lanczos tridiagonal of alpha_j = al[j], beta_j = be[j]): negative
+// pivots of the LDL' factorisation of T - x I (Sturm sequence; Golub & Van
+// Loan, Sec. 8.4.1), a zero pivot replaced by a tiny negative one.
+__device__ inline int sturm_below(const double *al, const double *be, int m, double x) {
+    int cnt = 0;
+    double q = 1.0;
+    for (int j = 0; j < m; ++j) {
+        double d = 1.0 / al[j] - x;
+        if (j > 0) d += be[j - 1] / al[j - 1] - (be[j - 1] / (al[j - 1] * al[j - 1])) / q;
+        q = d;
+        if (fabs(q) < 1e-300) q = -1e-300;
+        if (q < 0.0) ++cnt;
+    }
+    return cnt;
+}
+
+// The i-th smallest eigenvalue (0-based, i < m) of that tridiagonal: bisection
+// on the Sturm count inside its Gershgorin interval.
+__device__ inline double lanczos_eig(const double *al, const double *be, int m, int i) {
+    double lo = INFINITY, up = -INFINITY;
+    for (int j = 0; j < m; ++j) {
+        const double d = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+        const double r = (j > 0 ? sqrt(be[j - 1]) / al[j - 1] : 0.0) + (j + 1 < m ? sqrt(be[j]) / al[j] : 0.0);
+        lo = fmin(lo, d - r);
+        up = fmax(up, d + r);
+    }
+    for (int it = 0; it < 128; ++it) {
+        const double mid = 0.5 * (lo + up);
+        if (mid <= lo || mid >= up) break;
+        if (sturm_below(al, be, m, mid) >= i + 1) up = mid;
+        else lo = mid;
+    }
+    return 0.5 * (lo + up);
+}
+
+// The 16 features from the row statistics (RowStats order), the sum of
+// squared deviations of ln d_i from their mean, the m sorted Ritz values
+// th[0..m-1] and the relative residual after the steps.
+__device__ inline void feature_vector(const double *st, double var, const double *th, int m, double relres, int32_t n,
+                                      int64_t nnz, float *feat) {
+    const double hi = st[1];
+    const int top = m - 1;
+    double f[16];
+    f[0] = log10((double)n);
+    f[1] = (double)nnz / (double)n;
+    f[2] = st[0];
+    f[3] = hi;
+    f[4] = (st[3] - st[2]) / log(10.0);
+    f[5] = sqrt(var / (double)n);
+    f[6] = st[6] > 0.0 ? st[5] / st[6] : 0.0;
+    // k-th smallest / largest Ritz values; with fewer than three, the index
+    // clamps to the values that exist
+    for (int k = 0; k < 3; ++k) {
+        f[7 + k] = th[k < top ? k : top] / hi;
+        f[10 + k] = th[top - 2 + k > 0 ? top - 2 + k : 0] / hi;
+    }
+    f[13] = log10(th[top] / th[0]);
+    f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
+    f[15] = log10(th[0] / hi);
+    for (int k = 0; k < 16; ++k) feat[k] = (float)f[k];
 }
 
 }  // namespace dev

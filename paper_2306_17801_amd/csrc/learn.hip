@@ -40,78 +40,39 @@ constexpr int LABEL_Q = 16;
 constexpr double LABEL_SHIFT = 3.0;
 constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5824;
 
-// Row statistics, pass 1 -> partials [7][G]:
-// min(1 - R_i), max(1 + R_i), min ln d_i, max ln d_i, sum ln d_i,
-// sum ln(max|off| / min|off|), rows with off-diagonals; R_i = sum|off| / |d_i|.
+// Row statistics, pass 1 -> partials [7][G] (dev::RowStats order).
 __global__ __launch_bounds__(FB) void k_feat_rows(int32_t n, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
                                                   double *part, int64_t per_block) {
     const dev::Chunk c = dev::block_chunk(n, per_block);
-    double lo = INFINITY, hi = -INFINITY, ldmin = INFINITY, ldmax = -INFINITY, ldsum = 0.0, an = 0.0, cnt = 0.0;
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += FB) {
-        double d = 0.0, off = 0.0, omax = 0.0, omin = INFINITY;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k) {
-            const double a = val[k];
-            if (col[k] == (int)i) d = a;
-            else {
-                const double aa = fabs(a);
-                off += aa;
-                omax = fmax(omax, aa);
-                omin = fmin(omin, aa);
-            }
-        }
-        const double R = off / fabs(d);
-        lo = fmin(lo, 1.0 - R);
-        hi = fmax(hi, 1.0 + R);
-        const double ld = log(d);
-        ldmin = fmin(ldmin, ld);
-        ldmax = fmax(ldmax, ld);
-        ldsum += ld;
-        if (omax > 0.0) {
-            an += log(omax / omin);
-            cnt += 1.0;
-        }
-    }
+    dev::RowStats a;
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += FB) dev::row_stats_add(a, rowptr, col, val, i);
     __shared__ double s[7][FB];
-    s[0][threadIdx.x] = lo;
-    s[1][threadIdx.x] = hi;
-    s[2][threadIdx.x] = ldmin;
-    s[3][threadIdx.x] = ldmax;
-    s[4][threadIdx.x] = ldsum;
-    s[5][threadIdx.x] = an;
-    s[6][threadIdx.x] = cnt;
+    for (int k = 0; k < 7; ++k) s[k][threadIdx.x] = a.v[k];
     __syncthreads();
     if (threadIdx.x == 0) {
-        double v[7] = {s[0][0], s[1][0], s[2][0], s[3][0], s[4][0], s[5][0], s[6][0]};
-        for (int t = 1; t < FB; ++t) {
-            v[0] = fmin(v[0], s[0][t]);
-            v[1] = fmax(v[1], s[1][t]);
-            v[2] = fmin(v[2], s[2][t]);
-            v[3] = fmax(v[3], s[3][t]);
-            v[4] += s[4][t];
-            v[5] += s[5][t];
-            v[6] += s[6][t];
+        dev::RowStats t;
+        for (int th = 0; th < FB; ++th) {
+            double b[7];
+            for (int k = 0; k < 7; ++k) b[k] = s[k][th];
+            dev::row_stats_merge(t, b);
         }
         const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-        for (int k = 0; k < 7; ++k) part[k * gridDim.x + lb] = v[k];
+        for (int k = 0; k < 7; ++k) part[k * gridDim.x + lb] = t.v[k];
     }
 }
 
 // One thread: pass-1 totals -> stats[0..6] (stats[7] = mean ln d).
 __global__ void k_feat_rows_final(const double *part, int G, int32_t n, double *stats) {
     if (threadIdx.x != 0) return;
-    double v[7] = {part[0], part[G], part[2 * G], part[3 * G], part[4 * G], part[5 * G], part[6 * G]};
-    for (int t = 1; t < G; ++t) {
-        v[0] = fmin(v[0], part[t]);
-        v[1] = fmax(v[1], part[G + t]);
-        v[2] = fmin(v[2], part[2 * G + t]);
-        v[3] = fmax(v[3], part[3 * G + t]);
-        v[4] += part[4 * G + t];
-        v[5] += part[5 * G + t];
-        v[6] += part[6 * G + t];
+    dev::RowStats t;
+    for (int g = 0; g < G; ++g) {
+        double b[7];
+        for (int k = 0; k < 7; ++k) b[k] = part[k * G + g];
+        dev::row_stats_merge(t, b);
     }
-    for (int k = 0; k < 7; ++k) stats[k] = v[k];
-    stats[7] = v[4] / (double)n;
+    for (int k = 0; k < 7; ++k) stats[k] = t.v[k];
+    stats[7] = t.v[4] / (double)n;
 }
 
 // Pass 2: partials of sum (ln d_i - mean)^2 (two-pass variance).
@@ -122,10 +83,7 @@ __global__ __launch_bounds__(FB) void k_feat_rows2(int32_t n, const int32_t *__r
     const double mean = stats[7];
     double acc = 0.0;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += FB) {
-        double d = 0.0;
-        for (int k = rowptr[i]; k < rowptr[i + 1]; ++k)
-            if (col[k] == (int)i) d = val[k];
-        const double e = log(d) - mean;
+        const double e = dev::row_logdiag(rowptr, col, val, i) - mean;
         acc = fma(e, e, acc);
     }
     double v[1] = {acc};
@@ -143,28 +101,9 @@ __device__ double cheb(int j, double y) {  // T_j(y) by the recurrence, any real
     return t1;
 }
 
-// Number of eigenvalues below x of the symmetric tridiagonal with diagonal
-// 1/al_j + be_{j-1}/al_{j-1} and squared off-diagonal be_j / al_j^2 (the
-// CG-Lanczos tridiagonal): negative pivots of the LDL' factorisation of
-// T - x I (Sturm sequence; Golub & Van Loan, Sec. 8.4.1), with a zero
-// pivot replaced by a tiny negative one.
-__device__ int sturm_below(const double *al, const double *be, int m, double x) {
-    int cnt = 0;
-    double q = 1.0;
-    for (int j = 0; j < m; ++j) {
-        double d = 1.0 / al[j] - x;
-        if (j > 0) d += be[j - 1] / al[j - 1] - (be[j - 1] / (al[j - 1] * al[j - 1])) / q;
-        q = d;
-        if (fabs(q) < 1e-300) q = -1e-300;
-        if (q < 0.0) ++cnt;
-    }
-    return cnt;
-}
-
-// One workgroup of 64: thread i < m finds the i-th smallest eigenvalue of the
-// Lanczos tridiagonal (the Ritz values) by bisection on the Sturm count
-// inside the tridiagonal's Gershgorin interval; thread 0 then forms the 16
-// features (FP32) and lmax (FP64).
+// One workgroup of 64: thread i < m finds the i-th smallest Ritz value (the
+// eigenvalues of the 12-step Lanczos tridiagonal); thread 0 then forms the
+// 16 features (FP32) and lmax (FP64).
 __global__ __launch_bounds__(64) void k_feat_final(const double *stats, const double *var_part, int Gv,
                                                    const double *hist, int hist_cap, const apcg_solve_info *info,
                                                    int32_t n, int64_t nnz, float *feat, double *lmax_out) {
@@ -173,49 +112,18 @@ __global__ __launch_bounds__(64) void k_feat_final(const double *stats, const do
     if (m > 16) m = 16;
     const double *al = hist, *be = hist + hist_cap;
     __shared__ double th[16];
-    const int i = threadIdx.x;
-    if (i < m) {
-        double lo = INFINITY, up = -INFINITY;
-        for (int j = 0; j < m; ++j) {
-            const double d = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
-            const double r = (j > 0 ? sqrt(be[j - 1]) / al[j - 1] : 0.0) + (j + 1 < m ? sqrt(be[j]) / al[j] : 0.0);
-            lo = fmin(lo, d - r);
-            up = fmax(up, d + r);
-        }
-        for (int it = 0; it < 128; ++it) {
-            const double mid = 0.5 * (lo + up);
-            if (mid <= lo || mid >= up) break;
-            if (sturm_below(al, be, m, mid) >= i + 1) up = mid;
-            else lo = mid;
-        }
-        th[i] = 0.5 * (lo + up);
-    }
+    if ((int)threadIdx.x < m) th[threadIdx.x] = dev::lanczos_eig(al, be, m, threadIdx.x);
     __syncthreads();
-    if (i != 0) return;
+    if (threadIdx.x != 0) return;
+    if (m < 1) {  // no iteration (b = 0): lmax stands in as the only Ritz value
+        th[0] = stats[1];
+        m = 1;
+    }
     double var = 0.0;
     for (int t = 0; t < Gv; ++t) var += var_part[t];
-    const double glo = stats[0], hi = stats[1];
     const double relres = info->ref_norm > 0.0 ? info->res_norm / info->ref_norm : 1.0;
-    const int top = m - 1;
-    double f[NF];
-    f[0] = log10((double)n);
-    f[1] = (double)nnz / (double)n;
-    f[2] = glo;
-    f[3] = hi;
-    f[4] = (stats[3] - stats[2]) / log(10.0);
-    f[5] = sqrt(var / (double)n);
-    f[6] = stats[6] > 0.0 ? stats[5] / stats[6] : 0.0;
-    // k-th smallest / largest Ritz values; with fewer than three, the index
-    // clamps to the values that exist
-    for (int k = 0; k < 3; ++k) {
-        f[7 + k] = th[k < top ? k : top] / hi;
-        f[10 + k] = th[top - 2 + k > 0 ? top - 2 + k : 0] / hi;
-    }
-    f[13] = log10(th[top] / th[0]);
-    f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
-    f[15] = log10(th[0] / hi);
-    for (int k = 0; k < NF; ++k) feat[k] = (float)f[k];
-    *lmax_out = hi;
+    dev::feature_vector(stats, var, th, m, relres, n, nnz, feat);
+    *lmax_out = stats[1];
 }
 
 // One workgroup of 64: the smallest eigenvalue by multisection (each round
@@ -242,7 +150,7 @@ __global__ __launch_bounds__(64) void k_label(const double *stats, const double 
         for (int round = 0; round < 10; ++round) {
             const double lo = s_lo, w = (s_hi - lo) / 65.0;
             const double x = lo + w * (threadIdx.x + 1);
-            const bool hit = sturm_below(al, be, m, x) >= 1;
+            const bool hit = dev::sturm_below(al, be, m, x) >= 1;
             if (threadIdx.x == 0) first = 64;
             __syncthreads();
             if (hit) atomicMin(&first, (int)threadIdx.x);
@@ -577,6 +485,17 @@ static apcg_status ensure_mlp(apcg_ctx c, MlpScratch *s, int64_t B) {
     s->cap = cap;
     hipLaunchKernelGGL(k_phi_grid, dim3(1), dim3(64), 0, c->stream, s->phi());
     APCG_CHECK_LAUNCH("k_phi_grid");
+    return APCG_SUCCESS;
+}
+
+apcg_status mlp_infer(apcg_ctx ctx, const float *params, const float *mean, const float *std, float *X, int32_t B,
+                      float *C) {
+    if (B < 1) return APCG_SUCCESS;
+    hipLaunchKernelGGL(k_standardize, dim3(1), dim3(64), 0, ctx->stream, X, B, (float *)mean, (float *)std, 0);
+    APCG_CHECK_LAUNCH("k_standardize");
+    hipLaunchKernelGGL(k_mlp_fwd, dim3(B), dim3(64), 0, ctx->stream, params, (const float *)X, B, (float *)nullptr,
+                       (float *)nullptr, C);
+    APCG_CHECK_LAUNCH("k_mlp_fwd");
     return APCG_SUCCESS;
 }
 

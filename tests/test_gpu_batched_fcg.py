@@ -180,3 +180,84 @@ def test_iteration_cap_and_stall_window(apcg, ctx):
     res, xs = run_batch(apcg, ctx, cases, 1e-10, 20000, fopts=fo)
     check_against_oracle(apcg, cases, res, xs, 1e-10, 20000, **fo)
     assert all(r["status"] & apcg.APCG_SOLVE_STALL for r in res)
+
+
+def feature_systems():
+    rng = np.random.default_rng(91)
+    out = [P._lognormal_system(rng, 2, 40, 2.0, 1.0), P._lognormal_system(rng, 3, 12, 1.5, 20.0),
+           P._lognormal_system(rng, 3, 7, 0.5, 3.0)]
+    sys_ = [(s.A, s.b) for s in out]
+    lap = P.laplace_2d(20)
+    sys_.append((lap, rng.uniform(-1, 1, lap.n)))
+    sys_.append(one_row(2.0, 3.0))
+    z = P.laplace_2d(5)
+    sys_.append((z, np.zeros(z.n)))
+    return sys_
+
+
+def test_batched_features_parity(apcg, ctx):
+    """Features of a mixed batch in one call against the oracle, system by
+    system (incl. n = 1 and b = 0)."""
+    import torch
+    from oracle import learned as OL
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    sys_ = feature_systems()
+    As = [DeviceCSR(A) for A, _ in sys_]
+    bs = [DeviceVec(b) for _, b in sys_]
+    feat = torch.zeros(16 * len(sys_), dtype=torch.float32, device="cuda:0")
+    lm = torch.zeros(len(sys_), dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    apcg.apcg_pc_features_batched(ctx, [a.h for a in As], [b.h for b in bs], feat, lm)
+    apcg.apcg_ctx_synchronize(ctx)
+    F = feat.cpu().numpy().astype(np.float64).reshape(len(sys_), 16)
+    L = lm.cpu().numpy()
+    for i, (A, b) in enumerate(sys_):
+        ref = OL.features(A, b)
+        print(f"  system {i} n={A.n}: max |diff| {np.max(np.abs(F[i] - ref)):.2e}", flush=True)
+        assert np.all(np.abs(F[i] - ref) <= 2e-6 * np.maximum(1.0, np.abs(ref))), (i, F[i], ref)
+        assert L[i] == pytest.approx(oracle.gershgorin(A)[1], rel=1e-15)
+
+
+def test_batched_learned_solve_equals_its_steps(apcg, ctx):
+    """apcg_ksp_solve_batched_learned = batched features -> standardise ->
+    network -> apcg_ksp_solve_batched_fcg_poly, bit for bit; every system
+    converges (through its fallback where the polynomial is rejected)."""
+    import torch
+    from oracle import learned as OL
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    sys_ = [s for s in feature_systems()]
+    As = [DeviceCSR(A) for A, _ in sys_]
+    bs = [DeviceVec(b) for _, b in sys_]
+    nsys = len(sys_)
+    params = P.mlp_initial_params(3)
+    params["b3"] = np.array([1.2, -0.5, 0.2, -0.05, 0, 0, 0, 0, 0])
+    pv = np.concatenate([params[k].reshape(-1) for k, _ in OL.SHAPES]).astype(np.float32)
+    dev = lambda a, dt=torch.float32: torch.from_numpy(np.ascontiguousarray(a)).to("cuda:0", dt)
+    dP, dM, dS = dev(pv), dev(np.linspace(-1, 1, 16).astype(np.float32)), dev(np.linspace(0.5, 3, 16).astype(np.float32))
+    feat = torch.zeros((nsys, 16), dtype=torch.float32, device="cuda:0")
+    lm = torch.zeros(nsys, dtype=torch.float64, device="cuda:0")
+    C = torch.zeros((nsys, 9), dtype=torch.float32, device="cuda:0")
+    torch.cuda.synchronize()
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    info = apcg.apcg_info_create(0, 2 * nsys)
+    x1 = [DeviceVec.zeros(A.n) for A, _ in sys_]
+    x2 = [DeviceVec.zeros(A.n) for A, _ in sys_]
+    apcg.apcg_pc_features_batched(ctx, [a.h for a in As], [b.h for b in bs], feat.view(-1), lm)
+    apcg.apcg_mlp_standardize(ctx, feat, dM, dS, False)
+    apcg.apcg_mlp_forward(ctx, dP, feat, C)
+    info1 = apcg.apcg_info_create(0, nsys)
+    info2 = apcg.apcg_info_create(0, nsys)
+    apcg.apcg_ksp_solve_batched_fcg_poly(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in x1], 1e-9, 20000,
+                                         C.view(-1), lm, opts, None, info1)
+    apcg.apcg_ksp_solve_batched_learned(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in x2], 1e-9, 20000,
+                                        dP, dM, dS, opts, None, info2)
+    r1 = [apcg.apcg_info_get(info1, i) for i in range(nsys)]
+    r2 = [apcg.apcg_info_get(info2, i) for i in range(nsys)]
+    assert r1 == r2
+    for i in range(nsys):
+        assert r1[i]["status"] & apcg.APCG_SOLVE_CONVERGED, (i, r1[i])
+        assert np.array_equal(x1[i].numpy(), x2[i].numpy())
+    for inf in (info, info1, info2):
+        apcg.apcg_info_destroy(inf)

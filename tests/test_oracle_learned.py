@@ -226,3 +226,11 @@ def test_label_target_is_the_minimax_residual_polynomial(a, b):
     assert np.all(oracle.poly_eval(cstar, np.linspace(0, b, 2001), b) > 0)
     assert cstar @ G @ cstar - 2 * h @ cstar + 1 == pytest.approx(0.0, abs=1e-12)
     assert np.linalg.eigvalsh(G).min() > 0
+
+
+def test_features_of_a_zero_right_hand_side():
+    """b = 0: no Lanczos step; lmax is the only Ritz value, relres 1."""
+    A = P.laplace_2d(5)
+    f = LO.features(A, np.zeros(A.n))
+    assert np.all(np.isfinite(f))
+    assert np.allclose(f[7:13], 1.0) and f[13] == 0.0 and f[14] == 0.0 and f[15] == 0.0
