@@ -12,7 +12,9 @@ solves bracketed by device synchronisation; solves/s = K / elapsed.
 Also reported on the same JSON line (under "extra"): the 256-system batch
 (one batched launch against a per-solve loop), the learned polynomial
 preconditioner (FCG(1) with the network's polynomial against Jacobi-PCG on
-held-out systems), and:
+held-out systems), the mixed 2D/3D batch solved in one call with the learned
+preconditioner and a per-system fallback (against batched Jacobi-PCG and the
+per-solve loop), and:
   roofline      -- the fused product kernel (SpMV + direction update + p.Ap):
                    algorithmic bytes per launch / mean launch duration, the
                    duration taken with HIP events on the solve's stream by a
@@ -246,6 +248,117 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     return out
 
 
+def pool_map(fn, args, workers):
+    """Host generation of many systems (numpy-bound) in worker processes."""
+    if workers <= 1 or len(args) < 16:
+        return [fn(a) for a in args]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(fn, args, chunksize=4))
+
+
+def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers):
+    """Mixed batch: the first `count` systems of the 1024-system batch (2D
+    5-point and 3D 7-point, N ~ log-U[1e3, 1e6], sigma ~ U[0.5, 2],
+    anisotropy ~ log-U[1, 1000], seed 5), rtol 1e-8.  A network trained on
+    the GPU on `n_train` systems of the same distribution (seed 6, N capped
+    at train_nhi) drives the learned batched solve (features, network and
+    FCG(1) with a per-system fallback, all systems in one block-diagonal
+    iteration); compared with the batched Jacobi-PCG and with the plain path
+    (one apcg_ksp_solve per system over 8 forked contexts)."""
+    import numpy as np
+
+    from paper_2306_17801_amd import learned as L
+    from paper_2306_17801_amd import problems
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    t0 = time.perf_counter()
+    eval_set = pool_map(problems.mixed_system, [(5, i, 1e3, 1e6) for i in range(count)], workers)
+    train_set = pool_map(problems.mixed_system, [(6, i, 1e3, train_nhi) for i in range(n_train)], workers)
+    t_gen = time.perf_counter() - t0
+    ctx = apcg.apcg_ctx_create(0)
+    t0 = time.perf_counter()
+    dtrain = L.collect(ctx, train_set, rtol=1e-8, maxit=50000)
+    t_collect = time.perf_counter() - t0
+    del train_set
+    t0 = time.perf_counter()
+    pc, _ = L.train(ctx, dtrain, epochs=epochs, batch=32, lr=3e-3)
+    t_train = time.perf_counter() - t0
+    log(f"[bench] mixed: generated {t_gen:.1f}s, collected {t_collect:.1f}s, trained {t_train:.2f}s")
+    As = [DeviceCSR(s.A) for s in eval_set]
+    bs = [DeviceVec(s.b) for s in eval_set]
+    xs = [DeviceVec.zeros(s.A.n) for s in eval_set]
+    nsys = len(eval_set)
+    info = apcg.apcg_info_create(0, nsys)
+    out = {"systems": nsys, "rows": int(sum(s.A.n for s in eval_set)), "nnz": int(sum(s.A.nnz for s in eval_set)),
+           "train_systems": n_train, "train_n_max": train_nhi, "generate_s": round(t_gen, 1),
+           "collect_s": round(t_collect, 2), "train_s": round(t_train, 3)}
+    del eval_set
+    hA, hb, hx = [a.h for a in As], [b.h for b in bs], [x.h for x in xs]
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+
+    def timed(run):
+        run()  # warm-up (graph capture, uploads)
+        apcg.apcg_ctx_synchronize(ctx)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        apcg.apcg_ctx_synchronize(ctx)
+        return (time.perf_counter() - t1) / reps
+
+    def summary(prefix, dt):
+        res = [apcg.apcg_info_get(info, i) for i in range(nsys)]
+        its = [r["iterations"] for r in res]
+        out[f"{prefix}_ms"] = round(1000 * dt, 2)
+        out[f"{prefix}_solves_per_s"] = round(nsys / dt, 2)
+        out[f"{prefix}_converged"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_CONVERGED)
+        out[f"{prefix}_iterations_mean"] = round(float(np.mean(its)), 1)
+        return res
+
+    dt = timed(lambda: apcg.apcg_ksp_solve_batched_learned(ctx, hA, hb, hx, 1e-8, 50000, pc.params, pc.mean, pc.std,
+                                                           opts, None, info))
+    res = summary("batched_learned", dt)
+    out["batched_learned_fallbacks"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_FALLBACK)
+    out["batched_learned_fallback_reasons"] = {
+        k: sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_FALLBACK and r["status"] & bit)
+        for k, bit in (("p.Ap", apcg.APCG_SOLVE_BREAKDOWN_PAP), ("r.z_or_rejected", apcg.APCG_SOLVE_BREAKDOWN_RZ),
+                       ("stall", apcg.APCG_SOLVE_STALL))}
+    out["batched_learned_iterations_max"] = max(r["iterations"] for r in res)
+    out["batched_learned_fcg_iterations_mean"] = round(float(np.mean([r["fcg_iterations"] for r in res])), 1)
+    log(f"[bench] mixed batched learned: {1000 * dt:.1f} ms")
+    dt = timed(lambda: apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-8, 50000, opts, info))
+    res = summary("batched_jacobi", dt)
+    out["batched_jacobi_iterations_max"] = max(r["iterations"] for r in res)
+    log(f"[bench] mixed batched Jacobi: {1000 * dt:.1f} ms")
+    kids = apcg.apcg_ctx_fork(ctx, 8)
+    infos = apcg.apcg_info_create(0, nsys)
+
+    def loop():
+        for i in range(nsys):
+            apcg.apcg_ksp_solve(kids[i % 8], hA[i], hb[i], hx[i], 1e-8, 50000, opts, infos, i)
+        for k in kids:
+            apcg.apcg_ctx_synchronize(k)
+
+    dt = timed(loop)
+    res = [apcg.apcg_info_get(infos, i) for i in range(nsys)]
+    out["per_solve_loop_ms"] = round(1000 * dt, 2)
+    out["per_solve_loop_solves_per_s"] = round(nsys / dt, 2)
+    out["per_solve_loop_iterations_mean"] = round(float(np.mean([r["iterations"] for r in res])), 1)
+    out["per_solve_loop_converged"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_CONVERGED)
+    out["batched_learned_speedup_vs_per_solve_loop"] = round(out["per_solve_loop_ms"] / out["batched_learned_ms"], 3)
+    out["batched_learned_speedup_vs_batched_jacobi"] = round(out["batched_jacobi_ms"] / out["batched_learned_ms"], 3)
+    log(f"[bench] mixed per-solve loop: {1000 * dt:.1f} ms")
+    apcg.apcg_ctx_join(ctx, kids, apcg.APCG_JOIN_DESTROY)
+    apcg.apcg_info_destroy(infos)
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_synchronize(ctx)
+    apcg.apcg_ctx_destroy(ctx)
+    log(f"[bench] mixed: {out}")
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -265,6 +378,11 @@ def main():
     ap.add_argument("--learned-epochs", type=int, default=300)
     ap.add_argument("--learned-reps", type=int, default=3)
     ap.add_argument("--workers", type=int, default=8, help="host processes generating the learned systems")
+    ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-batch (learned + batched) measurement")
+    ap.add_argument("--mixed-count", type=int, default=128,
+                    help="first systems of the 1024-system mixed batch to solve (the full workload: 1024)")
+    ap.add_argument("--mixed-train", type=int, default=192, help="training systems for the mixed batch's network")
+    ap.add_argument("--mixed-train-nmax", type=float, default=1e6, help="largest training system (rows)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
     args = ap.parse_args()
@@ -399,6 +517,10 @@ def main():
         extra["learned_pc"] = bench_learned(apcg, torch, args.learned_train, args.learned_eval,
                                             args.learned_sides[0], args.learned_sides[1], args.learned_epochs,
                                             args.learned_reps, args.workers)
+
+    if not args.no_mixed:
+        extra["mixed_batch"] = bench_mixed(apcg, torch, args.mixed_count, args.mixed_train, args.mixed_train_nmax,
+                                           args.learned_epochs, 2, args.workers)
 
     cpu = None
     if not args.no_cpu_baseline:

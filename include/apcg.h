@@ -416,7 +416,7 @@ apcg_status apcg_pc_features(apcg_ctx ctx, apcg_mat A, apcg_vec b, float *dev_fe
 /* Training label of one system, from its own Jacobi-PCG solve (x0 = 0, rtol,
  * maxit >= 1; the tridiagonal of all its iterations):
  * dev_label[3] (double): lmin = the smallest Ritz value of the solve (0 when
- *   it takes no iteration), a = 3 lmin clamped to [1e-6 lmax, lmax / 2]
+ *   it takes no iteration), a = 3 lmin clamped to [1e-3 lmax, lmax / 2]
  *   (lmax / 2 without iterations), lmax;
  * dev_G[81], dev_h[9] (float): the loss's quadratic form c'G c - 2 h'c + 1 =
  *   sum_q w_q t_q^2 (p(t_q) - p*(t_q))^2 / sum_q w_q t_q^2 p*(t_q)^2 over the

@@ -18,7 +18,7 @@ ed., Sec. 6.7.3).
 Label of one training system: lmin = the smallest Ritz value of the full
 Jacobi-PCG solve of that system (CG finds the extreme eigenvalues first, so
 after convergence it matches lambda_min(M) closely), the interval [a, lmax]
-with a = 3 lmin clamped to [1e-6 lmax, lmax / 2], and the target p* = the
+with a = 3 lmin clamped to [1e-3 lmax, lmax / 2], and the target p* = the
 Chebyshev semi-iterative polynomial of degree 8 on [a, lmax], whose residual
 polynomial 1 - t p*(t) = T_9(s(t)) / T_9(s(0)), s(t) = (lmax + a - 2t) /
 (lmax - a), is the minimax one there.  Loss:
@@ -48,6 +48,7 @@ M_STEPS = 12
 Q_GRID = 64
 LABEL_Q = 16
 LABEL_SHIFT = 3.0
+LABEL_FLOOR = 1e-3
 
 
 def positivity_grid(q: int = Q_GRID) -> np.ndarray:
@@ -152,11 +153,13 @@ def chebyshev_rule(a, b, q=LABEL_Q):
 
 
 def label_interval(lmin, lmax):
-    """a = 3 lmin clamped to [1e-6 lmax, lmax / 2]; a system the solve does
-    not iterate on (lmin None) takes a = lmax / 2."""
+    """a = 3 lmin clamped to [1e-3 lmax, lmax / 2]; a system the solve does
+    not iterate on (lmin None) takes a = lmax / 2.  The floor keeps the
+    target's minimum on [0, lmax] away from zero for very ill-conditioned
+    systems (about 0.07 / lmax at the floor) at no cost in iterations."""
     if lmin is None:
         return 0.5 * lmax
-    return min(max(LABEL_SHIFT * lmin, 1e-6 * lmax), 0.5 * lmax)
+    return min(max(LABEL_SHIFT * lmin, LABEL_FLOOR * lmax), 0.5 * lmax)
 
 
 def chebyshev_iteration_coeffs(a, lmax):

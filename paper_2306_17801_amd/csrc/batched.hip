@@ -537,6 +537,28 @@ __device__ __forceinline__ void tile_range(const SegPlan &P, int *t0, int *t1) {
     *t1 = min(P.ntiles, *t0 + P.tiles_per_block);
 }
 
+// Runs body(t) for every tile t of this workgroup's range whose system
+// passes keep(state): tiles are screened ST at a time (one per thread) and
+// the survivors compacted in LDS, so the tiles of stopped systems cost one
+// round of loads per ST tiles.  Each tile writes only its own outputs.
+template <typename Keep, typename Body>
+__device__ __forceinline__ void for_active_tiles(const SegPlan &P, Keep keep, Body body) {
+    int t0, t1;
+    tile_range(P, &t0, &t1);
+    __shared__ int list[ST];
+    __shared__ int cnt;
+    for (int base = t0; base < t1; base += ST) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        const int t = base + (int)threadIdx.x;
+        if (t < t1 && keep(P.st[P.tile_sys[t]])) list[atomicAdd(&cnt, 1)] = t;
+        __syncthreads();
+        const int m = cnt;
+        for (int k = 0; k < m; ++k) body(list[k]);
+        __syncthreads();  // the list is reused by the next round
+    }
+}
+
 __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc, int norm_pre) {
     int t0, t1;
     tile_range(P, &t0, &t1);
@@ -634,24 +656,17 @@ __global__ __launch_bounds__(64) void k_seg_init_final(SegPlan P, double rtol, i
 }
 
 __global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
-    int t0, t1;
-    tile_range(P, &t0, &t1);
-    for (int t = t0; t < t1; ++t) {
-        const int s = P.tile_sys[t];
-        if (!P.st[s].zero_x) continue;
-        const BatchSys S = P.sys[s];
+    for_active_tiles(P, [](const SegSys &q) { return q.zero_x != 0; }, [&](int t) {
+        const BatchSys S = P.sys[P.tile_sys[t]];
         const int i = P.tile_row0[t] + threadIdx.x;
         if (i < S.n) S.x[i] = 0.0;
-    }
+    });
 }
 
 __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
-    int t0, t1;
-    tile_range(P, &t0, &t1);
     __shared__ double lds[ST / 64];
-    for (int t = t0; t < t1; ++t) {
+    for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
         const int s = P.tile_sys[t];
-        if (P.st[s].flag) continue;  // uniform across the workgroup
         const double beta = P.st[s].beta;
         const BatchSys S = P.sys[s];
         const int64_t n = S.n;
@@ -671,7 +686,7 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
         dev::block_sum<ST, 1>(v, lds);
         if (threadIdx.x == 0) P.part_delta[t] = v[0];
         __syncthreads();
-    }
+    });
 }
 
 __global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
@@ -694,12 +709,9 @@ __global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
 }
 
 __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int norm_pre) {
-    int t0, t1;
-    tile_range(P, &t0, &t1);
     __shared__ double lds[2 * (ST / 64)];
-    for (int t = t0; t < t1; ++t) {
+    for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
         const int s = P.tile_sys[t];
-        if (P.st[s].flag) continue;
         const double alpha = P.st[s].alpha;
         const BatchSys S = P.sys[s];
         const int64_t n = S.n;
@@ -724,7 +736,7 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
             P.part_res[P.ntiles + t] = v[1];
         }
         __syncthreads();
-    }
+    });
 }
 
 __global__ __launch_bounds__(64) void k_seg_beta(SegPlan P, double rtol, int32_t maxit) {

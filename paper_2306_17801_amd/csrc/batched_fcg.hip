@@ -81,6 +81,30 @@ __device__ __forceinline__ void ftile_range(const FPlan &P, int *t0, int *t1) {
     *t1 = min(P.ntiles, *t0 + P.tiles_per_block);
 }
 
+// Runs body(t) for every tile t of this workgroup's range whose system
+// passes keep(state).  Tiles are screened FT at a time -- each thread tests
+// one tile, the survivors are compacted in LDS -- so a tail of stopped
+// systems costs one round of loads per FT tiles, not a dependent chain per
+// tile.  Each tile writes only its own outputs, so the order in which the
+// survivors run does not change any result.
+template <typename Keep, typename Body>
+__device__ __forceinline__ void for_active_tiles(const FPlan &P, Keep keep, Body body) {
+    int t0, t1;
+    ftile_range(P, &t0, &t1);
+    __shared__ int list[FT];
+    __shared__ int cnt;
+    for (int base = t0; base < t1; base += FT) {
+        if (threadIdx.x == 0) cnt = 0;
+        __syncthreads();
+        const int t = base + (int)threadIdx.x;
+        if (t < t1 && keep(P.st[P.tile_sys[t]])) list[atomicAdd(&cnt, 1)] = t;
+        __syncthreads();
+        const int m = cnt;
+        for (int k = 0; k < m; ++k) body(list[k]);
+        __syncthreads();  // the list is reused by the next round
+    }
+}
+
 // sum_k a_k u(col_k) over row i's entries; rows of up to 8 entries issue all
 // gathers first (padded slots gather the row's own entry and are not added)
 template <typename F>
@@ -256,24 +280,17 @@ __global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef
 }
 
 __global__ __launch_bounds__(FT) void k_bf_zero_x(FPlan P) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
-    for (int t = t0; t < t1; ++t) {
-        const int s = P.tile_sys[t];
-        if (!P.st[s].zero_x) continue;
-        const FSys S = P.sys[s];
+    for_active_tiles(P, [](const FState &q) { return q.zero_x != 0; }, [&](int t) {
+        const FSys S = P.sys[P.tile_sys[t]];
         const int i = P.tile_row0[t] + threadIdx.x;
         if (i < S.n) S.x[i] = 0.0;
-    }
+    });
 }
 
 __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
-    for (int t = t0; t < t1; ++t) {
+    for_active_tiles(P, [](const FState &q) { return !q.flag && !q.restart; }, [&](int t) {
         const int s = P.tile_sys[t];
         const FState *q = P.st + s;
-        if (q->flag || q->restart) continue;  // uniform across the workgroup
         const double beta = q->beta;
         const FSys S = P.sys[s];
         const int64_t n = S.n;
@@ -292,7 +309,7 @@ __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
             v[0] = pi * sum;
         }
         ftile_store<1>(P, t, 0, v);
-    }
+    });
 }
 
 __global__ __launch_bounds__(64) void k_bf_alpha(FPlan P) {
@@ -314,12 +331,9 @@ __global__ __launch_bounds__(64) void k_bf_alpha(FPlan P) {
 }
 
 __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
-    for (int t = t0; t < t1; ++t) {
+    for_active_tiles(P, [](const FState &q) { return !q.flag && !q.restart; }, [&](int t) {
         const int s = P.tile_sys[t];
         const FState *q = P.st + s;
-        if (q->flag || q->restart) continue;
         const double alpha = q->alpha;
         const FSys S = P.sys[s];
         const int64_t n = S.n;
@@ -335,7 +349,7 @@ __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
             v[0] = ri * ri;
         }
         ftile_store<1>(P, t, 1, v);
-    }
+    });
 }
 
 __global__ __launch_bounds__(64) void k_bf_check(FPlan P) {
@@ -379,14 +393,11 @@ __global__ __launch_bounds__(64) void k_bf_check(FPlan P) {
 // and the partials of r.z, z.w (Jacobi mode: z = v).  Y = (2/lmax) D^-1 A - I,
 // v = D^-1 r; b_8 = c_8 v is formed where it is needed.
 __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o_b1, int o_b2, int o_out) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
-    for (int t = t0; t < t1; ++t) {
+    for_active_tiles(P, [stage](const FState &q) { return !q.flag && (stage == 2 || q.mode != MODE_JACOBI); },
+                     [&](int t) {
         const int s = P.tile_sys[t];
         const FState *q = P.st + s;
-        if (q->flag) continue;
         const bool jac = q->mode == MODE_JACOBI;
-        if (jac && stage != 2) continue;
         const FSys S = P.sys[s];
         const int64_t n = S.n;
         const double *r = S.ws, *dinv = S.ws + n, *w = S.ws + 5 * n;
@@ -418,7 +429,7 @@ __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o
             }
         }
         if (stage == 2) ftile_store<2>(P, t, 2, v);
-    }
+    });
 }
 
 __global__ __launch_bounds__(64) void k_bf_beta(FPlan P) {

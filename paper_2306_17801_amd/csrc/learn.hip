@@ -7,7 +7,7 @@
 //     bisection, one thread per eigenvalue);
 //   * the training label of one system: the smallest Ritz value lmin of its
 //     full Jacobi-PCG solve (Sturm-sequence multisection on the tridiagonal
-//     of all iterations), a = 3 lmin clamped to [1e-6 lmax, lmax / 2], and
+//     of all iterations), a = 3 lmin clamped to [1e-3 lmax, lmax / 2], and
 //     the target p* = the Chebyshev semi-iterative polynomial on [a, lmax]
 //     (its residual polynomial is the minimax one there), as the quadratic
 //     form (G, h) of the loss;
@@ -38,6 +38,7 @@ constexpr int MSTEPS = 12;
 constexpr int NF = 16, NH = 64, NC = 9, NPARAM = 5833, QGRID = 64;
 constexpr int LABEL_Q = 16;
 constexpr double LABEL_SHIFT = 3.0;
+constexpr double LABEL_FLOOR = 1e-3;  // keeps the target's minimum away from zero
 constexpr int OFF_W1 = 0, OFF_B1 = 1024, OFF_W2 = 1088, OFF_B2 = 5184, OFF_W3 = 5248, OFF_B3 = 5824;
 
 // Row statistics, pass 1 -> partials [7][G] (dev::RowStats order).
@@ -166,7 +167,7 @@ __global__ __launch_bounds__(64) void k_label(const double *stats, const double 
     if (threadIdx.x != 0) return;
     const double lmin = m > 0 ? 0.5 * (s_lo + s_hi) : 0.0;
     double a = 0.5 * hi;
-    if (m > 0) a = fmin(fmax(LABEL_SHIFT * lmin, 1e-6 * hi), 0.5 * hi);
+    if (m > 0) a = fmin(fmax(LABEL_SHIFT * lmin, LABEL_FLOOR * hi), 0.5 * hi);
     // target coefficients
     const double s0 = (hi + a) / (hi - a), T9s0 = cheb(9, s0);
     double cs[NC];

@@ -284,6 +284,22 @@ def mixed_batch(count: int = 1024, seed: int = 5, limit: int | None = None) -> l
     return out
 
 
+def mixed_system(args) -> System:
+    """System ``index`` of ``mixed_batch(count, seed)`` alone (args = (seed,
+    index, n_lo, n_hi)): child i of SeedSequence(seed).spawn(...) is
+    SeedSequence(seed, spawn_key=(i,)), drawn in the same order."""
+    seed, index, n_lo, n_hi = args
+    rng = np.random.default_rng(np.random.SeedSequence(seed, spawn_key=(index,)))
+    dim = 2 + int(rng.integers(0, 2))
+    nt = math.exp(rng.uniform(math.log(n_lo), math.log(n_hi)))
+    side = max(2, int(round(nt ** (1.0 / dim))))
+    sigma = float(rng.uniform(0.5, 2.0))
+    aniso = float(math.exp(rng.uniform(0.0, math.log(1000.0))))
+    s = _lognormal_system(rng, dim, side, sigma, aniso)
+    s.meta["index"] = index
+    return s
+
+
 def random_csr(n: int, max_per_row: int, seed: int, empty_rows: bool = True) -> CSR:
     """Random square CSR with sorted columns (for SpMV/reduction edge cases):
     row lengths ~ U{0..max_per_row} (or U{1..} without empty rows)."""

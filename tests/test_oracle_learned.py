@@ -207,7 +207,7 @@ def test_label_of_a_system_without_iterations():
     assert lmin is None and a == hi / 2
 
 
-@pytest.mark.parametrize("a,b", [(0.02, 2.0), (1e-3, 1.7), (0.5, 2.0)])
+@pytest.mark.parametrize("a,b", [(0.02, 2.0), (3e-3, 1.7), (0.5, 2.0)])
 def test_label_target_is_the_minimax_residual_polynomial(a, b):
     """1 - t p*(t) equioscillates on [a, b] with amplitude 1/T_9(s0)
     (Chebyshev's minimax theorem), p* > 0 on [0, b], and the loss's form is
@@ -234,3 +234,11 @@ def test_features_of_a_zero_right_hand_side():
     f = LO.features(A, np.zeros(A.n))
     assert np.all(np.isfinite(f))
     assert np.allclose(f[7:13], 1.0) and f[13] == 0.0 and f[14] == 0.0 and f[15] == 0.0
+
+
+def test_label_interval_clamps():
+    """a = 3 lmin within [1e-3 lmax, lmax / 2]."""
+    assert LO.label_interval(1e-7, 2.0) == pytest.approx(2e-3)
+    assert LO.label_interval(0.1, 2.0) == pytest.approx(0.3)
+    assert LO.label_interval(0.9, 2.0) == 1.0
+    assert LO.label_interval(None, 2.0) == 1.0

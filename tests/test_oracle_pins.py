@@ -481,3 +481,11 @@ def test_learned_pc_system_is_the_sets_member():
         s = P.learned_pc_system((4, i, 6, 8, 12))
         assert np.array_equal(s.A.val, full[i].A.val) and np.array_equal(s.b, full[i].b)
         assert s.meta == full[i].meta
+
+
+def test_mixed_system_is_the_batchs_member():
+    full = P.mixed_batch(6, 5, limit=4)
+    for i in (0, 3):
+        s = P.mixed_system((5, i, 1e3, 1e6))
+        assert np.array_equal(s.A.val, full[i].A.val) and np.array_equal(s.b, full[i].b)
+        assert s.meta == full[i].meta
