@@ -914,7 +914,7 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     P.running = sc->d_running;
     P.nsys = nsys;
     P.ntiles = ntiles;
-    const int G = normalise_blocks(2048, std::max<int32_t>(ntiles, 1));
+    const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
     const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
     const int x0z = opts.x0_is_zero ? 1 : 0;

@@ -750,7 +750,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     P.running = bc->d_running;
     P.nsys = nsys;
     P.ntiles = ntiles;
-    const int G = normalise_blocks(2048, std::max<int32_t>(ntiles, 1));
+    const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
     P.maxit = maxit;
     P.stall_min = fo.stall_min;
@@ -978,7 +978,7 @@ static apcg_status bf_features(apcg_ctx ctx, BfCache *bc, int32_t nsys, const ap
     int32_t nt = 0;
     for (auto &f : hs) nt += (f.n + FT - 1) / FT;
     P.ntiles = nt;
-    const int G = normalise_blocks(2048, std::max<int32_t>(nt, 1));
+    const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(nt, 1));
     P.tiles_per_block = std::max<int32_t>(1, (nt + G - 1) / G);
     P.hist = bc->d_hist;
     P.hist_cap = FEAT_STEPS;
