@@ -368,6 +368,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-autotune", action="store_true")
+    ap.add_argument("--spmv-config", type=str, default=None,
+                    help="lanes,block,blocks,schedule: a fixed SpMV configuration instead of the autotuner's")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched measurement")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
@@ -423,7 +425,11 @@ def main():
     rtol, maxit = 1e-8, 50000
 
     tuned = None
-    if not args.no_autotune:
+    if args.spmv_config:
+        cfg = [int(v) for v in args.spmv_config.split(",")]
+        apcg.apcg_mat_set_spmv_config(A.h, *cfg)
+        tuned = {"config": apcg.apcg_mat_get_spmv_config(A.h), "fixed": True}
+    elif not args.no_autotune:
         cfg, us = apcg.apcg_mat_autotune(A.h, ctx, 10)
         tuned = {"config": cfg, "product_us": round(us, 2)}
         log(f"[bench] autotune: {cfg} {us:.1f} us")
