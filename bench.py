@@ -201,6 +201,7 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     its = {k: [] for k in tot}
     fallbacks = 0
     unconverged = 0
+    feat_t = 0.0
     for s in eval_set:
         dA, db, dx = DeviceCSR(s.A), DeviceVec(s.b), DeviceVec.zeros(s.A.n)
         feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
@@ -216,6 +217,14 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
             "control": lambda: apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, dx.h, 1e-8, 50000, cc, lm, opts,
                                                              None, info, 0),
         }
+        # the learned solve's first step alone: features of the system
+        apcg.apcg_pc_features(ctx, dA.h, db.h, feat, lm)
+        apcg.apcg_ctx_synchronize(ctx)
+        t1 = time.perf_counter()
+        for _ in range(reps):
+            apcg.apcg_pc_features(ctx, dA.h, db.h, feat, lm)
+        apcg.apcg_ctx_synchronize(ctx)
+        feat_t += (time.perf_counter() - t1) / reps
         for k, run in runs.items():
             run()  # warm-up (graph capture)
             apcg.apcg_ctx_synchronize(ctx)
@@ -240,6 +249,7 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
         out[f"{k}_mean_iterations"] = round(float(np.mean(its[k])), 2)
         out[f"{k}_ms_per_solve"] = round(1000 * tot[k] / n_eval, 4)
         out[f"{k}_solves_per_s"] = round(n_eval / tot[k], 3)
+    out["features_ms_per_call"] = round(1000 * feat_t / n_eval, 4)
     out["learned_speedup_vs_jacobi"] = round(tot["jacobi"] / tot["learned"], 3)
     out["learned_speedup_vs_control"] = round(tot["control"] / tot["learned"], 3)
     out["learned_fallbacks"] = fallbacks

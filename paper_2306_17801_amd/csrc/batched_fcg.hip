@@ -135,13 +135,15 @@ __device__ __forceinline__ double frow(const int32_t *__restrict__ col, const do
 // The tiles of system s, added in index order (one 64-thread workgroup);
 // the result is valid in thread 0.
 template <int NV>
-__device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV]) {
+__device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV],
+                                         const double *base = nullptr) {
     __shared__ double lds[NV];
+    const double *part = base ? base : P.part;
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
     for (int t = P.sys_tile0[s] + (int)threadIdx.x; t < P.sys_tile0[s + 1]; t += 64) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += P.part[(size_t)(slot0 + k) * P.ntiles + t];
+        for (int k = 0; k < NV; ++k) v[k] += part[(size_t)(slot0 + k) * P.ntiles + t];
     }
     dev::block_sum<64, NV>(v, lds);
 }
@@ -470,32 +472,26 @@ __global__ __launch_bounds__(FT) void k_bf_rows(FPlan P, double *fpart) {
         const int i = P.tile_row0[t] + threadIdx.x;
         dev::RowStats a;
         if (i < S.n) dev::row_stats_add(a, S.rowptr, S.col, S.val, i);
-        for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = a.v[k];
-        __syncthreads();
-        if (threadIdx.x == 0) {
-            dev::RowStats m;
-            for (int th = 0; th < FT; ++th) {
-                double b[7];
-                for (int k = 0; k < 7; ++k) b[k] = sh[k][th];
-                dev::row_stats_merge(m, b);
-            }
-            for (int k = 0; k < 7; ++k) fpart[(size_t)k * P.ntiles + t] = m.v[k];
-        }
+        dev::row_stats_block<FT>(a, sh);
+        if (threadIdx.x == 0)
+            for (int k = 0; k < 7; ++k) fpart[(size_t)k * P.ntiles + t] = a.v[k];
         __syncthreads();
     }
 }
 
-// Per system (thread 0): the tiles merged in order -> fstats[s][0..6],
-// fstats[s][7] = mean ln d.
+// Per system (64 threads): thread l merges tiles l, l + 64, ... of the
+// system, then the fixed tree -> fstats[s][0..6], fstats[s][7] = mean ln d.
 __global__ __launch_bounds__(64) void k_bf_rows_final(FPlan P, const double *fpart, double *fstats) {
     const int s = blockIdx.x;
-    if (threadIdx.x != 0) return;
     dev::RowStats m;
-    for (int t = P.sys_tile0[s]; t < P.sys_tile0[s + 1]; ++t) {
+    for (int t = P.sys_tile0[s] + (int)threadIdx.x; t < P.sys_tile0[s + 1]; t += 64) {
         double b[7];
         for (int k = 0; k < 7; ++k) b[k] = fpart[(size_t)k * P.ntiles + t];
         dev::row_stats_merge(m, b);
     }
+    __shared__ double sh[7][64];
+    dev::row_stats_block<64>(m, sh);
+    if (threadIdx.x != 0) return;
     for (int k = 0; k < 7; ++k) fstats[8 * s + k] = m.v[k];
     const int n = P.sys[s].n;
     fstats[8 * s + 7] = n > 0 ? m.v[4] / (double)n : 0.0;
@@ -532,16 +528,17 @@ __global__ __launch_bounds__(64) void k_bf_feat(FPlan P, const double *fpart, co
     int m = q.its < P.hist_cap ? q.its : P.hist_cap;
     if (m > 16) m = 16;
     const double *st = fstats + 8 * s;
-    __shared__ double th[16];
-    if ((int)threadIdx.x < m) th[threadIdx.x] = dev::lanczos_eig(al, be, m, threadIdx.x);
+    __shared__ double th[16], td[16], te2[16];
+    dev::ritz_values(al, be, m, td, te2, th);
+    double vs[1];
+    fsys_sum<1>(P, s, 0, vs, fpart + (size_t)7 * P.ntiles);  // squared deviations over the tiles, fixed order
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (m < 1) {
         th[0] = st[1];
         m = 1;
     }
-    double var = 0.0;
-    for (int t = P.sys_tile0[s]; t < P.sys_tile0[s + 1]; ++t) var += fpart[(size_t)7 * P.ntiles + t];
+    const double var = vs[0];
     const FSys S = P.sys[s];
     const double relres = q.ref > 0.0 ? q.res / q.ref : 1.0;
     dev::feature_vector(st, var, th, m, relres, S.n, (int64_t)S.rowptr[S.n], feat + (size_t)16 * s);

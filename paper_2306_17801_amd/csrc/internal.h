@@ -379,6 +379,28 @@ __device__ inline void row_stats_merge(RowStats &a, const double *b) {
     a.v[6] += b[6];
 }
 
+// Merges the RowStats of a workgroup's BS threads by a fixed tree in LDS
+// (sh: 7 x BS doubles); the result is valid in thread 0.
+template <int BS>
+__device__ inline void row_stats_block(RowStats &a, double (*sh)[BS]) {
+    for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = a.v[k];
+    __syncthreads();
+    for (int off = BS / 2; off > 0; off >>= 1) {
+        if ((int)threadIdx.x < off) {
+            RowStats t;
+            double b[7];
+            for (int k = 0; k < 7; ++k) {
+                t.v[k] = sh[k][threadIdx.x];
+                b[k] = sh[k][threadIdx.x + off];
+            }
+            row_stats_merge(t, b);
+            for (int k = 0; k < 7; ++k) sh[k][threadIdx.x] = t.v[k];
+        }
+        __syncthreads();
+    }
+    for (int k = 0; k < 7; ++k) a.v[k] = sh[k][0];
+}
+
 __device__ inline double row_logdiag(const int32_t *__restrict__ rowptr, const int32_t *__restrict__ col,
                                      const double *__restrict__ val, int64_t i) {
     double d = 0.0;
@@ -405,23 +427,41 @@ __device__ inline int sturm_below(const double *al, const double *be, int m, dou
     return cnt;
 }
 
-// The i-th smallest eigenvalue (0-based, i < m) of that tridiagonal: bisection
-// on the Sturm count inside its Gershgorin interval.
-__device__ inline double lanczos_eig(const double *al, const double *be, int m, int i) {
-    double lo = INFINITY, up = -INFINITY;
-    for (int j = 0; j < m; ++j) {
-        const double d = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
-        const double r = (j > 0 ? sqrt(be[j - 1]) / al[j - 1] : 0.0) + (j + 1 < m ? sqrt(be[j]) / al[j] : 0.0);
-        lo = fmin(lo, d - r);
-        up = fmax(up, d + r);
+// Ritz values of at most 16 CG steps, one workgroup: threads j < m write the
+// CG-Lanczos tridiagonal (diagonal d, squared off-diagonal e2) to LDS, then
+// thread i < m bisects for the i-th smallest eigenvalue on the Sturm count of
+// that copy (one division per step); th[i] receives it.
+__device__ inline void ritz_values(const double *al, const double *be, int m, double *d, double *e2, double *th) {
+    const int j = threadIdx.x;
+    if (j < m) {
+        d[j] = 1.0 / al[j] + (j > 0 ? be[j - 1] / al[j - 1] : 0.0);
+        e2[j] = j + 1 < m ? be[j] / (al[j] * al[j]) : 0.0;
     }
-    for (int it = 0; it < 128; ++it) {
-        const double mid = 0.5 * (lo + up);
-        if (mid <= lo || mid >= up) break;
-        if (sturm_below(al, be, m, mid) >= i + 1) up = mid;
-        else lo = mid;
+    __syncthreads();
+    const int i = threadIdx.x;
+    if (i < m) {
+        double lo = INFINITY, up = -INFINITY;
+        for (int k = 0; k < m; ++k) {
+            const double r = (k > 0 ? sqrt(e2[k - 1]) : 0.0) + sqrt(e2[k]);
+            lo = fmin(lo, d[k] - r);
+            up = fmax(up, d[k] + r);
+        }
+        for (int it = 0; it < 128; ++it) {
+            const double x = 0.5 * (lo + up);
+            if (x <= lo || x >= up) break;
+            int cnt = 0;
+            double q = 1.0;
+            for (int k = 0; k < m; ++k) {
+                q = (d[k] - x) - (k > 0 ? e2[k - 1] / q : 0.0);
+                if (fabs(q) < 1e-300) q = -1e-300;
+                cnt += q < 0.0;
+            }
+            if (cnt >= i + 1) up = x;
+            else lo = x;
+        }
+        th[i] = 0.5 * (lo + up);
     }
-    return 0.5 * (lo + up);
+    __syncthreads();
 }
 
 // The 16 features from the row statistics (RowStats order), the sum of

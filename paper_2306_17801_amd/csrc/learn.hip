@@ -48,32 +48,28 @@ __global__ __launch_bounds__(FB) void k_feat_rows(int32_t n, const int32_t *__re
     const dev::Chunk c = dev::block_chunk(n, per_block);
     dev::RowStats a;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += FB) dev::row_stats_add(a, rowptr, col, val, i);
-    __shared__ double s[7][FB];
-    for (int k = 0; k < 7; ++k) s[k][threadIdx.x] = a.v[k];
-    __syncthreads();
+    __shared__ double sh[7][FB];
+    dev::row_stats_block<FB>(a, sh);
     if (threadIdx.x == 0) {
-        dev::RowStats t;
-        for (int th = 0; th < FB; ++th) {
-            double b[7];
-            for (int k = 0; k < 7; ++k) b[k] = s[k][th];
-            dev::row_stats_merge(t, b);
-        }
         const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-        for (int k = 0; k < 7; ++k) part[k * gridDim.x + lb] = t.v[k];
+        for (int k = 0; k < 7; ++k) part[k * gridDim.x + lb] = a.v[k];
     }
 }
 
-// One thread: pass-1 totals -> stats[0..6] (stats[7] = mean ln d).
-__global__ void k_feat_rows_final(const double *part, int G, int32_t n, double *stats) {
-    if (threadIdx.x != 0) return;
-    dev::RowStats t;
-    for (int g = 0; g < G; ++g) {
+// One workgroup of FB: pass-1 totals -> stats[0..6] (stats[7] = mean ln d);
+// thread t merges partials t, t + FB, ..., then the fixed tree.
+__global__ __launch_bounds__(FB) void k_feat_rows_final(const double *part, int G, int32_t n, double *stats) {
+    dev::RowStats a;
+    for (int g = threadIdx.x; g < G; g += FB) {
         double b[7];
         for (int k = 0; k < 7; ++k) b[k] = part[k * G + g];
-        dev::row_stats_merge(t, b);
+        dev::row_stats_merge(a, b);
     }
-    for (int k = 0; k < 7; ++k) stats[k] = t.v[k];
-    stats[7] = t.v[4] / (double)n;
+    __shared__ double sh[7][FB];
+    dev::row_stats_block<FB>(a, sh);
+    if (threadIdx.x != 0) return;
+    for (int k = 0; k < 7; ++k) stats[k] = a.v[k];
+    stats[7] = a.v[4] / (double)n;
 }
 
 // Pass 2: partials of sum (ln d_i - mean)^2 (two-pass variance).
@@ -112,16 +108,17 @@ __global__ __launch_bounds__(64) void k_feat_final(const double *stats, const do
     if (m > hist_cap) m = hist_cap;
     if (m > 16) m = 16;
     const double *al = hist, *be = hist + hist_cap;
-    __shared__ double th[16];
-    if ((int)threadIdx.x < m) th[threadIdx.x] = dev::lanczos_eig(al, be, m, threadIdx.x);
+    __shared__ double th[16], td[16], te2[16];
+    dev::ritz_values(al, be, m, td, te2, th);
+    double vs[1];
+    dev::reduce_partials<64, 1>(var_part, Gv, vs);  // sum of squared deviations, fixed order
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (m < 1) {  // no iteration (b = 0): lmax stands in as the only Ritz value
         th[0] = stats[1];
         m = 1;
     }
-    double var = 0.0;
-    for (int t = 0; t < Gv; ++t) var += var_part[t];
+    const double var = vs[0];
     const double relres = info->ref_norm > 0.0 ? info->res_norm / info->ref_norm : 1.0;
     dev::feature_vector(stats, var, th, m, relres, n, nnz, feat);
     *lmax_out = stats[1];
@@ -539,7 +536,7 @@ static apcg_status feat_rows(apcg_ctx ctx, apcg_mat A, FeatScratch *fs, int *G_o
     double *part = fs->stats + 8;
     hipLaunchKernelGGL(k_feat_rows, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val, part, pb);
     APCG_CHECK_LAUNCH("k_feat_rows");
-    hipLaunchKernelGGL(k_feat_rows_final, dim3(1), dim3(64), 0, st, (const double *)part, G, A->n, fs->stats);
+    hipLaunchKernelGGL(k_feat_rows_final, dim3(1), dim3(FB), 0, st, (const double *)part, G, A->n, fs->stats);
     APCG_CHECK_LAUNCH("k_feat_rows_final");
     hipLaunchKernelGGL(k_feat_rows2, dim3(G), dim3(FB), 0, st, A->n, A->rowptr, A->col, A->val,
                        (const double *)fs->stats, part, pb);
