@@ -487,7 +487,9 @@ def main():
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
-        if tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n:
+        cfg_chosen = apcg.apcg_mat_get_spmv_config(A.h)
+        if (tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n
+                and tr.get("spmv_config") == cfg_chosen):
             traffic = tr.get("bytes_per_launch")
     cfg_now = apcg.apcg_mat_get_spmv_config(A.h)
     kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell"}.get(
