@@ -52,6 +52,19 @@ def source_hash(path):
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
+def sdia_shape(A):
+    """Value slots U per 64-row slice of the sliced-diagonal layout (the most
+    distinct column offsets of any slice) and offset/mask slots (U rounded up
+    to a multiple of 8)."""
+    import numpy as np
+
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
+    key = (rows // 64) * (2 * A.n + 1) + (A.col.astype(np.int64) - rows + A.n)
+    sl = np.unique(key) // (2 * A.n + 1)
+    u = int(np.bincount(sl).max()) if sl.size else 1
+    return u, (u + 7) // 8 * 8
+
+
 def copy_calibration(apcg, torch):
     """Five copies of 2^27 doubles (1 GiB read + 1 GiB written each) with the
     library's copy kernel: the reference reading for the HBM byte counters."""
@@ -479,9 +492,19 @@ def main():
     solve(topts)
     prod_us, prod_cnt = apcg.apcg_ctx_kernel_times(ctx, 0)
     upd_us, upd_cnt = apcg.apcg_ctx_kernel_times(ctx, 1)
-    prod_bytes = 12 * nnz + 4 * (n + 1) + 32 * n  # A; z, p_old read; p, w written
+    cfg_now = apcg.apcg_mat_get_spmv_config(A.h)
+    if cfg_now["schedule"] == apcg.APCG_SPMV_SDIA:
+        # sliced diagonals: 8 bytes per stored value slot (absent entries of a
+        # slice's shared offsets included), 12 per offset/mask slot; z, p_old
+        # read, p, w written
+        u, mp = sdia_shape(A_h)
+        nsl = (n + 63) // 64
+        prod_bytes = 8 * 64 * nsl * u + 12 * nsl * mp + 32 * n
+    else:
+        prod_bytes = 12 * nnz + 4 * (n + 1) + 32 * n  # A; z, p_old read; p, w written
+    csr_bytes = 12 * nnz + 4 * (n + 1) + 32 * n
     upd_bytes = 64 * n  # x, r, p, w, dinv read; x, r, z written
-    iter_bytes = 12 * nnz + 4 * (n + 1) + 96 * n
+    iter_bytes = prod_bytes + upd_bytes
     achieved = prod_bytes / (prod_us * 1e-6) / 1e9
     traffic = None
     if os.path.exists(TRAFFIC_FILE):
@@ -491,12 +514,13 @@ def main():
         if (tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n
                 and tr.get("spmv_config") == cfg_chosen):
             traffic = tr.get("bytes_per_launch")
-    cfg_now = apcg.apcg_mat_get_spmv_config(A.h)
-    kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell"}.get(
+    kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell",
+             apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia"}.get(
         cfg_now["schedule"], "k_pcg_product") + f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)"
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": prod_bytes,
+                "csr_product_bytes_per_launch": csr_bytes,
                 "mean_launch_us": round(prod_us, 3), "launches_timed": prod_cnt}
     per_iter_us = 1000.0 * ms_per_step / max(its, 1)
     extra = {

@@ -259,6 +259,22 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       on first use and refilled from the CSR arrays at the start of every
  *       solve, so values may change between solves; MatMult uses the
  *       row-group kernel for this schedule.
+ *   schedule APCG_SPMV_SDIA (PCG solves): sliced diagonals.  The rows of
+ *       a 64-row slice share one sorted list of column offsets
+ *       (column - row); a 64-bit mask per offset marks the rows that hold
+ *       the entry, and only the values are stored per entry (column-major by
+ *       offset), so the matrix stream is 8 bytes per stored entry instead of
+ *       12, and the gathers of a wavefront read contiguous windows of the
+ *       vectors.  Every row adds its entries in column order with the same
+ *       fused multiply-adds as the row-per-thread and sliced schedules, so
+ *       A p is bitwise the same.  Applicable when every row's columns are
+ *       strictly increasing, no slice has more than 32 distinct offsets, and
+ *       the padded value copy is smaller than the sliced one's column and
+ *       value arrays; apcg_mat_set_spmv_config returns APCG_ERR_UNSUPPORTED
+ *       otherwise.  Selecting it copies the column indices to the host once
+ *       (synchronously) and snapshots the pattern: the columns must not
+ *       change afterwards (values may, they are refilled at the start of
+ *       every solve).  MatMult uses the row-group kernel for this schedule.
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so
@@ -266,6 +282,7 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
 #define APCG_SPMV_ROWGROUP 0
 #define APCG_SPMV_STREAM 1
 #define APCG_SPMV_SELL 2
+#define APCG_SPMV_SDIA 3
 typedef struct apcg_spmv_config {
     int32_t lanes_per_row;
     int32_t block_size;

@@ -62,6 +62,7 @@ APCG_MODE_HOST_CHECK = 2
 APCG_SPMV_ROWGROUP = 0
 APCG_SPMV_STREAM = 1
 APCG_SPMV_SELL = 2
+APCG_SPMV_SDIA = 3
 APCG_BATCH_AUTO = 0
 APCG_BATCH_PERSISTENT = 1
 APCG_BATCH_SEGMENTED = 2

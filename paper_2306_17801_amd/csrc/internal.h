@@ -175,6 +175,20 @@ struct apcg_mat_s {
     int32_t *sell_meta = nullptr;      // device copies, allocated on first use
     int32_t *sell_col = nullptr;
     double *sell_val = nullptr;
+    // Sliced-diagonal layout (SDIA schedule): the rows of a 64-row slice
+    // share one sorted list of column offsets (column - row); per offset a
+    // 64-bit mask says which rows hold that entry, and the values are stored
+    // column-major by offset.  The offsets and masks are built on the host
+    // the first time the schedule is selected (a snapshot of the sparsity
+    // pattern), the values are refilled from the CSR arrays at the start of
+    // every solve that uses it.
+    int32_t sdia_state = 0;          // 0: not analysed, 1: available, -1: not applicable
+    const char *sdia_reason = "";    // why not applicable
+    int32_t sdia_u = 0;              // value slots per slice (largest offset count of any slice)
+    int32_t sdia_mp = 0;             // offset / mask slots per slice: sdia_u rounded up to a multiple of 8
+    int32_t *sdia_off = nullptr;     // device [nslices * sdia_mp] offsets, padding 0
+    uint64_t *sdia_msk = nullptr;    // device [nslices * sdia_mp] row masks, padding 0
+    double *sdia_val = nullptr;      // device [nslices * sdia_u * 64] values, absent entries 0
     apcg::Record rec;
 };
 
@@ -197,6 +211,8 @@ apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
 void batch_cache_release(uint64_t ctx_id, int device);  // batched.hip
+// sliced-diagonal pattern analysis (pcg.hip): synchronous, once per matrix
+apcg_status sdia_analyse(apcg_mat_s *A);
 // Jacobi-PCG solve with registry marking (pcg.hip); hist (2 hist_cap doubles,
 // device) receives alpha_k and beta_k of the first hist_cap iterations.
 apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,

@@ -489,6 +489,130 @@ __global__ __launch_bounds__(256) void k_sell_fill(int32_t n, const int32_t *__r
     }
 }
 
+// Sliced-diagonal schedule (SDIA): wavefront v of a workgroup takes slices
+// s0 + v, s0 + v + TB/64, ... of the workgroup's contiguous range, lane l
+// reduces row 64 s + l.  Slice s has offset slots s*MP .. s*MP+MP-1 (sorted
+// column offsets, a 64-bit row mask each, mask 0 beyond the slice's own
+// offsets) and value slots s*U .. s*U+U-1 of 64 values, one per lane.  The
+// row adds the entries its mask bits select in offset order, i.e. in column
+// order, with one fused multiply-add each: the same sum as the row-per-thread
+// and sliced schedules.  shape = U | MP << 8.  Branch-free: every load is
+// issued unconditionally (value slot clamped to U-1, the gather index of an
+// absent entry to the row itself), absent entries are dropped by selects, so
+// all loads of a slice are in flight together; the offsets and masks of
+// 8 slots are one scalar load each.
+// PIPE (MP == 8): the next slice's offsets, masks and values are loaded
+// before the current slice's gathers.  Otherwise 8 slots at a time.
+template <int TB, int PIPE>
+__global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_t *__restrict__ soff,
+                                                         const int32_t *__restrict__ smask_words,
+                                                         const double *__restrict__ sval, const double *__restrict__ z,
+                                                         const double *__restrict__ pold, double *__restrict__ pnew,
+                                                         double *__restrict__ w, SolveState *st,
+                                                         const double *part_res, int g_res, double *part_delta,
+                                                         int32_t slices_per_block, int parity, int tune,
+                                                         int32_t shape) {
+    const uint64_t *smask = reinterpret_cast<const uint64_t *>(smask_words);
+    const int U = shape & 0xff, MP = shape >> 8;
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int nsl = (n + 63) / 64;
+    const int s0 = lb * slices_per_block;
+    const int s1 = min(nsl, s0 + slices_per_block);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    constexpr int STEP = TB / 64;
+    int on[8];
+    uint64_t mn[8];
+    double an[8];
+    auto load = [&](int sl, int c) {  // slots 8c .. 8c+7 of slice sl
+        const int32_t *o = soff + (int64_t)sl * MP + 8 * c;
+        const uint64_t *m = smask + (int64_t)sl * MP + 8 * c;
+        const double *v = sval + (int64_t)sl * U * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            on[k] = o[k];
+            mn[k] = m[k];
+            an[k] = __builtin_nontemporal_load(v + (int64_t)min(8 * c + k, U - 1) * 64);
+        }
+    };
+    // adds the 8 slots held in (oc, mc, ac) to sum for row (rc: row clamped to n-1)
+    auto add8 = [&](const int *oc, const uint64_t *mc, const double *ac, int row, int rc, double beta,
+                    double sum) {
+        double zj[8], pj[8];
+        bool in[8];
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            in[k] = (mc[k] >> lane) & 1ull;
+            const int j = in[k] ? row + oc[k] : rc;
+            zj[k] = z[j];
+            pj[k] = pold[j];
+        }
+#pragma unroll
+        for (int k = 0; k < 8; ++k) {
+            const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
+            sum = in[k] ? t : sum;
+        }
+        return sum;
+    };
+    // the first slice's loads do not depend on beta: issued before the
+    // prologue's reduction so that its latency overlaps them
+    if (PIPE && s0 + wave < s1) load(s0 + wave, 0);
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    double acc = 0.0;
+    for (int sl = s0 + wave; sl < s1; sl += STEP) {
+        const int row = sl * 64 + lane;
+        const int rc = min(row, n - 1);
+        double sum = 0.0;
+        if (PIPE) {
+            int oc[8];
+            uint64_t mc[8];
+            double ac[8];
+#pragma unroll
+            for (int k = 0; k < 8; ++k) {
+                oc[k] = on[k];
+                mc[k] = mn[k];
+                ac[k] = an[k];
+            }
+            if (sl + STEP < s1) load(sl + STEP, 0);  // in flight during the gathers below
+            sum = add8(oc, mc, ac, row, rc, beta, sum);
+        } else {
+            for (int c = 0; c < MP / 8; ++c) {
+                load(sl, c);
+                sum = add8(on, mn, an, row, rc, beta, sum);
+            }
+        }
+        const double zi = z[rc], po = pold[rc];
+        if (row < n) {
+            const double pi = pdir(zi, beta, po);
+            pnew[row] = pi;
+            w[row] = sum;
+            acc = fma(pi, sum, acc);
+        }
+    }
+    double v[1] = {acc};
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
+}
+
+// Fills the sliced-diagonal value copy from the CSR values: thread
+// (slice, lane) walks its row's entries in order, one per set mask bit, and
+// writes 0 to the slots its row does not hold.
+__global__ __launch_bounds__(256) void k_sdia_fill(int32_t n, const int32_t *__restrict__ rowptr,
+                                                   const double *__restrict__ val, const uint64_t *__restrict__ smask,
+                                                   int32_t U, int32_t MP, double *__restrict__ sval) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nsl = ((int64_t)n + 63) / 64;
+    if (g >= nsl * 64) return;
+    const int64_t sl = g >> 6;
+    const int lane = (int)(g & 63);
+    const int64_t row = sl * 64 + lane;
+    int64_t e = row < n ? rowptr[row] : 0;
+    for (int k = 0; k < U; ++k) {
+        const bool in = (smask[sl * MP + k] >> lane) & 1ull;
+        sval[(sl * U + k) * 64 + lane] = in ? val[e] : 0.0;
+        e += in ? 1 : 0;
+    }
+}
+
 // ----------------------------------------------------------------- update
 __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                    const double *__restrict__ p, const double *__restrict__ w,
@@ -611,7 +735,12 @@ ProductFn stream_fn(int32_t lds_nnz) {
     return k_pcg_product_stream<TB, 21>;  // 21 * 256 >= kStreamMaxNnz
 }
 
-ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw) {
+ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw, int32_t sdia_mp) {
+    if (cfg.schedule == APCG_SPMV_SDIA) {
+        if (sdia_mp == 8)
+            return cfg.block_size == 512 ? k_pcg_product_sdia<512, 1> : k_pcg_product_sdia<256, 1>;
+        return cfg.block_size == 512 ? k_pcg_product_sdia<512, 0> : k_pcg_product_sdia<256, 0>;
+    }
     if (cfg.schedule == APCG_SPMV_SELL) {
         if (sell_maxw <= 8)
             return cfg.block_size == 512 ? k_pcg_product_sell<512, 1> : k_pcg_product_sell<256, 1>;
@@ -635,7 +764,7 @@ struct Plan {
     int32_t rpb;  // rows (row groups), chunks (staged) or slices (sliced) per workgroup
     int g_vec;
     int64_t pb_vec;
-    int32_t lds_nnz;     // staged schedule: LDS entries per workgroup
+    int32_t lds_nnz;     // staged schedule: LDS entries per workgroup; sliced diagonals: U | MP << 8
     size_t lds_bytes;
 };
 
@@ -659,7 +788,18 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
     pl->a0 = A->rowptr;
     pl->a1 = A->col;
     pl->a2 = A->val;
-    if (cfg.schedule == APCG_SPMV_SELL) {
+    if (cfg.schedule == APCG_SPMV_SDIA) {
+        if (A->sdia_state != 1 || !A->sdia_val)
+            return set_error(APCG_ERR_INVALID_STATE, "sliced-diagonal copy not prepared");
+        pl->a0 = A->sdia_off;
+        pl->a1 = reinterpret_cast<const int32_t *>(A->sdia_msk);
+        pl->a2 = A->sdia_val;
+        const int64_t nsl = ((int64_t)A->n + 63) / 64;
+        const int64_t waves = pl->tb / 64;
+        pl->g_prod = normalise_blocks(cfg.blocks, (nsl + waves - 1) / waves);
+        pl->rpb = (int32_t)std::max<int64_t>(1, (nsl + pl->g_prod - 1) / pl->g_prod);
+        pl->lds_nnz = A->sdia_u | (A->sdia_mp << 8);  // the kernel's shape argument
+    } else if (cfg.schedule == APCG_SPMV_SELL) {
         if (!A->sell_meta) return set_error(APCG_ERR_INVALID_STATE, "sliced copy not prepared");
         pl->a0 = A->sell_meta;
         pl->a1 = A->sell_col;
@@ -681,7 +821,7 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         int64_t rpb = ((int64_t)A->n + pl->g_prod - 1) / pl->g_prod;
         pl->rpb = (int32_t)std::max<int64_t>(1, rpb);
     }
-    pl->prod = product_fn(cfg, pl->lds_nnz, A->sell_maxw);
+    pl->prod = product_fn(cfg, pl->lds_nnz, A->sell_maxw, A->sdia_mp);
     if (!pl->prod) return set_error(APCG_ERR_INVALID_ARG, "unsupported lanes_per_row");
     vector_grid(A->n, &pl->g_vec, &pl->pb_vec);
     return APCG_SUCCESS;
@@ -711,6 +851,91 @@ apcg_status prepare_sell(apcg_mat_s *A, hipStream_t s) {
                            (const int32_t *)A->sell_meta, A->sell_col, A->sell_val);
         APCG_CHECK_LAUNCH("k_sell_fill");
     }
+    return APCG_SUCCESS;
+}
+
+}  // namespace
+
+// Builds the sliced-diagonal offsets and masks on the host from a copy of
+// the CSR pattern (once per matrix) and allocates the device copies.  Leaves
+// sdia_state -1 with a reason when the layout does not apply.
+apcg_status sdia_analyse(apcg_mat_s *A) {
+    if (A->sdia_state != 0) return APCG_SUCCESS;
+    auto reject = [&](const char *why) {
+        A->sdia_state = -1;
+        A->sdia_reason = why;
+        return APCG_SUCCESS;
+    };
+    const int64_t n = A->n, nnz = A->nnz;
+    const int64_t nsl = (n + 63) / 64;
+    if (n == 0) return reject("empty matrix");
+    try {
+        std::vector<int32_t> rp((size_t)n + 1), cl((size_t)std::max<int64_t>(nnz, 1));
+        APCG_HIP(hipSetDevice(A->device));
+        g_counters.d2h_copies += 2;
+        APCG_HIP(hipMemcpy(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        if (nnz > 0) APCG_HIP(hipMemcpy(cl.data(), A->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+        std::vector<int32_t> offs;
+        auto slice_offsets = [&](int64_t sl) {  // sorted distinct column offsets of slice sl
+            offs.clear();
+            for (int64_t i = sl * 64; i < std::min<int64_t>(n, sl * 64 + 64); ++i)
+                for (int64_t e = rp[i]; e < rp[i + 1]; ++e) offs.push_back(cl[e] - (int32_t)i);
+            std::sort(offs.begin(), offs.end());
+            offs.erase(std::unique(offs.begin(), offs.end()), offs.end());
+        };
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = rp[i] + 1; e < rp[i + 1]; ++e)
+                if (cl[e] <= cl[e - 1]) return reject("a row's columns are not strictly increasing");
+        int32_t U = 0;
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            slice_offsets(sl);
+            if (offs.size() > 32) return reject("a slice has more than 32 distinct column offsets");
+            U = std::max<int32_t>(U, (int32_t)offs.size());
+        }
+        U = std::max<int32_t>(U, 1);
+        const int64_t slots = nsl * U * 64;
+        const int64_t sell_bytes = 12 * (A->sell_entries >= 0 ? A->sell_entries : nnz);
+        if (8 * slots > sell_bytes) return reject("the padded value copy would exceed the sliced copy");
+        const int32_t MP = (U + 7) / 8 * 8;
+        std::vector<int32_t> off_h((size_t)(nsl * MP), 0);
+        std::vector<uint64_t> msk_h((size_t)(nsl * MP), 0);
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            slice_offsets(sl);
+            for (size_t k = 0; k < offs.size(); ++k) off_h[sl * MP + k] = offs[k];
+            for (int64_t i = sl * 64; i < std::min<int64_t>(n, sl * 64 + 64); ++i)
+                for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+                    const int64_t k = std::lower_bound(offs.begin(), offs.end(), cl[e] - (int32_t)i) - offs.begin();
+                    msk_h[sl * MP + k] |= 1ull << (i - sl * 64);
+                }
+        }
+        APCG_HIP(hipMalloc((void **)&A->sdia_off, sizeof(int32_t) * nsl * MP));
+        APCG_HIP(hipMalloc((void **)&A->sdia_msk, sizeof(uint64_t) * nsl * MP));
+        APCG_HIP(hipMalloc((void **)&A->sdia_val, sizeof(double) * slots));
+        g_counters.h2d_copies += 2;
+        APCG_HIP(hipMemcpy(A->sdia_off, off_h.data(), sizeof(int32_t) * nsl * MP, hipMemcpyHostToDevice));
+        APCG_HIP(hipMemcpy(A->sdia_msk, msk_h.data(), sizeof(uint64_t) * nsl * MP, hipMemcpyHostToDevice));
+        A->sdia_u = U;
+        A->sdia_mp = MP;
+        A->sdia_state = 1;
+        return APCG_SUCCESS;
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+namespace {
+
+// Queues the refill of the sliced-diagonal values from the CSR values on
+// stream s (analysing the pattern first if needed).
+apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s) {
+    apcg_status st = sdia_analyse(A);
+    if (st) return st;
+    if (A->sdia_state < 0) return set_error(APCG_ERR_UNSUPPORTED, A->sdia_reason);
+    const int64_t nsl = ((int64_t)A->n + 63) / 64;
+    const int64_t blocks = (nsl * 64 + 255) / 256;
+    hipLaunchKernelGGL(k_sdia_fill, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->rowptr, A->val,
+                       (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val);
+    APCG_CHECK_LAUNCH("k_sdia_fill");
     return APCG_SUCCESS;
 }
 
@@ -919,6 +1144,7 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
         if ((s = op_begin(c, acc, 4))) return s;
         if ((s = ensure_workspace(c, A->n))) return s;
         if (A->cfg.schedule == APCG_SPMV_SELL && (s = prepare_sell(A, c->stream))) return s;
+        if (A->cfg.schedule == APCG_SPMV_SDIA && (s = prepare_sdia(A, c->stream))) return s;
         Plan pl;
         if ((s = make_plan(A, A->cfg, &pl))) return s;
         Bufs bf{A, x->d, b->d, c->ws, c->partials};
@@ -1066,13 +1292,19 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         apcg_spmv_config best_cfg = A->cfg;
         const bool sell_ok = A->sell_entries >= 0;
         if (sell_ok && (s = prepare_sell(A, st))) return s;
-        for (int lpr : {-1, 0, 1, 2, 4, 8, 16, 32, 64}) {  // -1: the sliced schedule, 0: the staged one
+        if ((s = sdia_analyse(A))) return s;
+        const bool sdia_ok = A->sdia_state == 1;
+        if (sdia_ok && (s = prepare_sdia(A, st))) return s;
+        // -2: sliced diagonals, -1: the sliced schedule, 0: the staged one
+        for (int lpr : {-2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
             if (lpr == -1 && !sell_ok) continue;
+            if (lpr == -2 && !sdia_ok) continue;
             for (int tb : {256, 512}) {
                 if (lpr == 0 && !stream_fits(A, tb)) continue;
                 for (int blocks : {256, 512, 1024, 2048, 4096, 8192}) {
-                    apcg_spmv_config cfg = lpr == -1  ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}
+                    apcg_spmv_config cfg = lpr == -2  ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SDIA}
+                                           : lpr == -1 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}
                                            : lpr == 0 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_STREAM}
                                                       : apcg_spmv_config{lpr, tb, blocks, APCG_SPMV_ROWGROUP};
                     Plan pl;

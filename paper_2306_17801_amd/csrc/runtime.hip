@@ -892,15 +892,19 @@ apcg_status apcg_mat_destroy(apcg_mat A) {
         deps = record_deps(A->rec);
     }
     const int dev = A->device;
-    int32_t *smeta = A->sell_meta, *scol = A->sell_col;
-    double *sval = A->sell_val;
+    int32_t *smeta = A->sell_meta, *scol = A->sell_col, *doff = A->sdia_off;
+    double *sval = A->sell_val, *dval = A->sdia_val;
+    uint64_t *dmsk = A->sdia_msk;
     delete A;
-    defer_release(std::move(deps), [dev, smeta, scol, sval]() {
-        if (smeta || scol || sval) {
+    defer_release(std::move(deps), [dev, smeta, scol, sval, doff, dmsk, dval]() {
+        if (smeta || scol || sval || doff || dmsk || dval) {
             hipSetDevice(dev);
             hipFree(smeta);
             hipFree(scol);
             hipFree(sval);
+            hipFree(doff);
+            hipFree(dmsk);
+            hipFree(dval);
         }
     });
     reap();
@@ -913,7 +917,7 @@ static bool valid_spmv_config(const apcg_spmv_config *cfg) {
     bool lok = l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64;
     bool bok = b == 256 || b == 512;
     bool sok = cfg->schedule == APCG_SPMV_ROWGROUP || cfg->schedule == APCG_SPMV_STREAM ||
-               cfg->schedule == APCG_SPMV_SELL;
+               cfg->schedule == APCG_SPMV_SELL || cfg->schedule == APCG_SPMV_SDIA;
     return lok && bok && sok && cfg->blocks >= 0;
 }
 
@@ -925,6 +929,11 @@ apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg) {
         return set_error(APCG_ERR_UNSUPPORTED, "rows too long for the staged schedule at this block size");
     if (cfg->schedule == APCG_SPMV_SELL && A->sell_entries < 0)
         return set_error(APCG_ERR_UNSUPPORTED, "matrix too large for the sliced layout's int32 offsets");
+    if (cfg->schedule == APCG_SPMV_SDIA) {
+        apcg_status s = apcg::sdia_analyse(A);
+        if (s) return s;
+        if (A->sdia_state < 0) return set_error(APCG_ERR_UNSUPPORTED, A->sdia_reason);
+    }
     A->cfg = *cfg;
     return APCG_SUCCESS;
 }

@@ -189,5 +189,5 @@ def test_autotune_picks_a_valid_schedule(apcg, ctx):
     A = P.laplace_3d(40)
     dA = DeviceCSR(A)
     cfg, us = apcg.apcg_mat_autotune(dA.h, ctx, 3)
-    assert us > 0 and cfg["block_size"] in (256, 512) and cfg["schedule"] in (0, 1, 2)
+    assert us > 0 and cfg["block_size"] in (256, 512) and cfg["schedule"] in (0, 1, 2, 3)
     assert apcg.apcg_mat_get_spmv_config(dA.h) == cfg

@@ -75,18 +75,18 @@ def test_poisson64_parity(apcg, ctx, mode, pc):
     assert res["ref_norm"] == pytest.approx(ref.ref, rel=1e-13)
 
 
-@pytest.mark.parametrize("lpr", [-1, 0, 1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("lpr", [-2, -1, 0, 1, 2, 4, 8, 16, 32, 64])
 @pytest.mark.parametrize("tb", [256, 512])
 def test_spmv_schedules_same_solve(apcg, ctx, lpr, tb):
-    """Every SpMV schedule (lpr 0: the LDS-staged one, -1: the sliced one)
-    gives the oracle's iteration count on a ragged 3D variable-coefficient
-    system (n = 21 * 17 * 13, not a multiple of 64)."""
+    """Every SpMV schedule (lpr 0: the LDS-staged one, -1: the sliced one,
+    -2: sliced diagonals) gives the oracle's iteration count on a ragged 3D
+    variable-coefficient system (n = 21 * 17 * 13, not a multiple of 64)."""
     print(f"case schedule lpr={lpr} tb={tb}", flush=True)
     rng = np.random.default_rng(40)
     A = P.diffusion_csr(np.exp(rng.standard_normal((13, 17, 21))), aniso=7.0)
     b = rng.uniform(-1, 1, A.n)
     ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
-    spmv = (1, tb, 0, 2) if lpr == -1 else (1, tb, 0, 1) if lpr == 0 else (lpr, tb, 0, 0)
+    spmv = {-2: (1, tb, 0, 3), -1: (1, tb, 0, 2), 0: (1, tb, 0, 1)}.get(lpr, (lpr, tb, 0, 0))
     res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=spmv)
     assert res["status"] == apcg.APCG_SOLVE_CONVERGED
     assert abs(res["iterations"] - ref.its) <= 1
@@ -248,8 +248,9 @@ def nine_point(m):
 
 @pytest.mark.parametrize("which", ["diffusion3d_ragged", "ninepoint_45"])
 def test_row_ordered_schedules_agree(apcg, ctx, which):
-    """The sliced schedule (both block sizes, the 9-entry rows taking its
-    looped path) against the staged and one-lane-per-row ones: each meets the
+    """The sliced and sliced-diagonal schedules (both block sizes, the
+    9-entry rows and 9 offsets per slice taking their looped paths) against
+    the staged and one-lane-per-row ones: each meets the
     oracle's bar, and at a fixed iteration count the iterates agree to
     rounding (the reductions' trees follow the launch shape, so only the
     products themselves are bit for bit equal)."""
@@ -261,10 +262,116 @@ def test_row_ordered_schedules_agree(apcg, ctx, which):
     b = rng.uniform(-1, 1, A.n)
     ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
     ref20 = oracle.pcg(A, b, rtol=0.0, maxit=20)
-    for spmv in [(1, 256, 0, 2), (1, 512, 40, 2), (1, 256, 0, 1), (1, 256, 0, 0)]:
+    for spmv in [(1, 256, 0, 2), (1, 512, 40, 2), (1, 256, 0, 3), (1, 512, 40, 3), (1, 256, 0, 1), (1, 256, 0, 0)]:
         print(f"case {which} spmv={spmv}", flush=True)
         res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=spmv)
         assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
         assert rel(x, ref.x) <= 1e-9
         res, x = gpu_solve(apcg, ctx, A, b, 0.0, 20, spmv=spmv)
         assert res["iterations"] == 20 and rel(x, ref20.x) <= 1e-12
+
+
+def random_pattern(n, per_row, seed):
+    """SPD, diagonally dominant, with per_row random off-diagonal columns
+    per row (symmetrised): slices see many distinct column offsets."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(seed)
+    rows = np.repeat(np.arange(n), per_row)
+    cols = rng.integers(0, n, n * per_row)
+    M = sp.coo_matrix((-rng.uniform(0.1, 1.0, n * per_row), (rows, cols)), shape=(n, n)).tocsr()
+    M = (M + M.T).tocsr()
+    M.setdiag(0.0)
+    M.eliminate_zeros()
+    M = M + sp.diags(np.asarray(abs(M).sum(axis=1)).ravel() + 1.0)
+    M = M.tocsr()
+    M.sort_indices()
+    return P.CSR(n=n, rowptr=M.indptr.astype(np.int32), col=M.indices.astype(np.int32), val=M.data.copy())
+
+
+@pytest.mark.parametrize("which", ["diffusion3d_ragged", "ninepoint_45", "laplace1d_50"])
+@pytest.mark.parametrize("tb,blocks", [(256, 0), (512, 24)])
+def test_sliced_diagonals_bitwise_equal_sliced(apcg, ctx, which, tb, blocks):
+    """Sliced diagonals and the sliced schedule at the same launch shape walk
+    the same slices in the same order and add every row's entries in column
+    order with the same fused multiply-adds, so whole solves (products,
+    reductions, iterates) are bit for bit equal; both meet the oracle's bar.
+    laplace1d_50: fewer rows than one slice."""
+    rng = np.random.default_rng(44)
+    if which == "ninepoint_45":
+        A = nine_point(45)
+    elif which == "laplace1d_50":
+        import scipy.sparse as sp
+
+        M = sp.diags([-np.ones(49), 2.5 * np.ones(50), -np.ones(49)], [-1, 0, 1]).tocsr()
+        M.sort_indices()
+        A = P.CSR(n=50, rowptr=M.indptr.astype(np.int32), col=M.indices.astype(np.int32), val=M.data.copy())
+    else:
+        A = P.diffusion_csr(np.exp(rng.standard_normal((11, 19, 23))), aniso=3.0)
+    b = rng.uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
+    print(f"case sdia-vs-sell {which} tb={tb} blocks={blocks}", flush=True)
+    r_sell, x_sell = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=(1, tb, blocks, 2))
+    r_sdia, x_sdia = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=(1, tb, blocks, 3))
+    assert r_sdia["status"] == apcg.APCG_SOLVE_CONVERGED and abs(r_sdia["iterations"] - ref.its) <= 1
+    assert rel(x_sdia, ref.x) <= 1e-9
+    assert r_sdia["iterations"] == r_sell["iterations"]
+    assert r_sdia["res_norm"] == r_sell["res_norm"]
+    assert np.array_equal(x_sdia, x_sell)
+
+
+def test_sliced_diagonals_values_refilled(apcg, ctx):
+    """The value copy is refilled at the start of every solve: scaling the
+    CSR values in place between two solves of one wrapped matrix gives the
+    oracle's solution of the scaled system."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    rng = np.random.default_rng(45)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((9, 14, 17))))
+    b = rng.uniform(-1, 1, A.n)
+    dA, db = DeviceCSR(A), DeviceVec(b)
+    apcg.apcg_mat_set_spmv_config(dA.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+    info = apcg.apcg_info_create(0, 1)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    for scale in (1.0, 3.0):
+        print(f"case sdia refill scale={scale}", flush=True)
+        if scale != 1.0:
+            dA.val.mul_(scale)
+            torch.cuda.synchronize()
+        dx = DeviceVec.zeros(A.n)
+        apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, 1e-10, 5000, opts, info, 0)
+        res = apcg.apcg_info_get(info, 0)
+        As = P.CSR(n=A.n, rowptr=A.rowptr, col=A.col, val=A.val * scale)
+        ref = oracle.pcg(As, b, rtol=1e-10, maxit=5000)
+        assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
+        assert rel(dx.numpy(), ref.x) <= 1e-9
+    apcg.apcg_info_destroy(info)
+
+
+def test_sliced_diagonals_rejected(apcg, ctx):
+    """The schedule is refused (APCG_ERR_UNSUPPORTED, the matrix keeps its
+    configuration) for unsorted rows and for patterns with more than 32
+    distinct column offsets in a slice; the autotuner then skips it."""
+    from paper_2306_17801_amd.device import DeviceCSR
+
+    A = random_pattern(700, 6, 46)
+    dA = DeviceCSR(A)
+    before = apcg.apcg_mat_get_spmv_config(dA.h)
+    with pytest.raises(apcg.ApcgError) as e:
+        apcg.apcg_mat_set_spmv_config(dA.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+    assert e.value.code == apcg.APCG_ERR_UNSUPPORTED
+    assert apcg.apcg_mat_get_spmv_config(dA.h) == before
+    best, _ = apcg.apcg_mat_autotune(dA.h, ctx, 2)
+    assert best["schedule"] != apcg.APCG_SPMV_SDIA
+    # a row with its columns out of order (same matrix, one row's two
+    # entries swapped together with their values)
+    B = nine_point(12)
+    col, val = B.col.copy(), B.val.copy()
+    s0 = B.rowptr[30]
+    col[s0], col[s0 + 1] = col[s0 + 1], col[s0]
+    val[s0], val[s0 + 1] = val[s0 + 1], val[s0]
+    dB = DeviceCSR(P.CSR(n=B.n, rowptr=B.rowptr, col=col, val=val))
+    with pytest.raises(apcg.ApcgError) as e:
+        apcg.apcg_mat_set_spmv_config(dB.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+    assert e.value.code == apcg.APCG_ERR_UNSUPPORTED
