@@ -382,6 +382,126 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers):
     return out
 
 
+def bench_sweep(apcg, torch, targets, reps, cpu_max_nnz, stencils):
+    """The paper's CG benchmark shape (Section 4.1): constant-coefficient
+    Laplace operators with 5-/9-point (2D) and 7-/27-point (3D) stencils,
+    NNZ from 1e4 to 1e8, exactly 20 Jacobi-PCG iterations (rtol 0), minimum
+    over the repetitions of the end-to-end time to host-visible completion.
+    Variants: the fused solve in graph mode (asynchronous), in stream mode,
+    and in host-check mode (the host waits after every kernel, the paper's
+    synchronous baseline shape); CG composed from the asynchronous
+    primitives with device scalars, and the same with every reduction read
+    back to the host before the next call; the CPU oracle (serial) up to
+    cpu_max_nnz.  Also a bandwidth check of the vector kernels outside the
+    256 MB last-level cache (2^27-entry vectors)."""
+    import numpy as np
+
+    import oracle
+    from paper_2306_17801_amd import problems
+    from paper_2306_17801_amd.composed import ComposedCG
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    ctx = apcg.apcg_ctx_create(0)
+    info = apcg.apcg_info_create(0, 1)
+    out = []
+    diag = {5: 4.0, 9: 8.0, 7: 6.0, 27: 26.0}
+
+    def tmin(run, prep=None, r=reps):
+        best = float("inf")
+        for i in range(r + 1):  # the first is the warm-up
+            if prep:
+                prep()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            run()
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if i > 0:
+                best = min(best, dt)
+        return best
+
+    for points in stencils:
+        dim = 2 if points in (5, 9) else 3
+        for target in targets:
+            side = max(2, int(round((target / points) ** (1.0 / dim))))
+            t0 = time.time()
+            A_h = problems.stencil_laplacian((side,) * dim, points)
+            b_h = np.random.default_rng(10 + points).uniform(-1, 1, A_h.n)
+            gen_s = time.time() - t0
+            A, b, x = DeviceCSR(A_h), DeviceVec(b_h), DeviceVec.zeros(A_h.n)
+            cfg, _ = apcg.apcg_mat_autotune(A.h, ctx, 3)
+            row = {"stencil": points, "side": side, "n": A_h.n, "nnz": A_h.nnz, "spmv_config": cfg}
+            xs = {}
+            for name, mode in (("graph", apcg.APCG_MODE_GRAPH), ("stream", apcg.APCG_MODE_STREAM),
+                               ("host_check", apcg.APCG_MODE_HOST_CHECK)):
+                o = apcg.apcg_solve_opts_default(x0_is_zero=1, mode=mode)
+
+                def run(o=o):
+                    apcg.apcg_ksp_solve(ctx, A.h, b.h, x.h, 0.0, 20, o, info, 0)
+                    res = apcg.apcg_info_get(info, 0)
+                    assert res["iterations"] == 20, res
+
+                row[name + "_ms"] = round(1e3 * tmin(run), 4)
+                xs[name] = x.numpy()
+            cg = ComposedCG(ctx, A_h.n)
+            for name, sync in (("composed_async", False), ("composed_sync", True)):
+                row[name + "_ms"] = round(1e3 * tmin(lambda: cg.solve(A.h, b.h, x.h, diag[points], 20, sync),
+                                                     prep=lambda: x.t.zero_()), 4)
+                xs[name] = x.numpy()
+            cg.close()
+            ref = xs["graph"]
+            nr = np.linalg.norm(ref)
+            row["max_rel_diff_variants"] = float(max(np.linalg.norm(v - ref) / nr for v in xs.values()))
+            if A_h.nnz <= cpu_max_nnz:
+                t_cpu = float("inf")
+                for _ in range(2 if A_h.nnz > 1e6 else 3):
+                    t1 = time.perf_counter()
+                    r = oracle.pcg(A_h, b_h, rtol=0.0, maxit=20)
+                    t_cpu = min(t_cpu, time.perf_counter() - t1)
+                row["cpu_oracle_ms"] = round(1e3 * t_cpu, 4)
+                row["rel_diff_vs_oracle"] = float(np.linalg.norm(ref - r.x) / np.linalg.norm(r.x))
+            it_bytes = 12 * A_h.nnz + 4 * (A_h.n + 1) + 96 * A_h.n
+            row["graph_us_per_iteration"] = round(1e3 * row["graph_ms"] / 20, 3)
+            row["graph_gbs_csr_bytes"] = round(20 * it_bytes / (row["graph_ms"] * 1e-3) / 1e9, 1)
+            row["async_speedup_vs_host_check"] = round(row["host_check_ms"] / row["graph_ms"], 3)
+            row["composed_async_speedup_vs_sync"] = round(row["composed_sync_ms"] / row["composed_async_ms"], 3)
+            log(f"[sweep] {points}-pt side {side} nnz {A_h.nnz:.3g} (gen {gen_s:.1f}s): " +
+                ", ".join(f"{k[:-3]} {v:.3f}" for k, v in row.items() if k.endswith("_ms")) + " ms")
+            out.append(row)
+            del A, b, x
+            torch.cuda.empty_cache()
+
+    # vector kernels outside the last-level cache: 2^27 doubles (1 GiB) per vector
+    nv = 1 << 27
+    u = torch.ones(nv, dtype=torch.float64, device="cuda:0")
+    v = torch.full((nv,), 0.5, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    hu, hv = apcg.apcg_vec_wrap(u), apcg.apcg_vec_wrap(v)
+    a = apcg.apcg_scalar_create(ctx)
+    apcg.apcg_scalar_set(a, 1e-3, ctx)
+    t = apcg.apcg_timer_create()
+    vec = {}
+    for name, fn, nbytes in (("axpy", lambda: apcg.apcg_vec_axpy_async(hv, a, False, hu, ctx), 24 * nv),
+                             ("dot", lambda: apcg.apcg_vec_dot_async(hu, hv, a, ctx), 16 * nv),
+                             ("copy", lambda: apcg.apcg_vec_copy_async(hv, hu, ctx), 16 * nv)):
+        fn()
+        apcg.apcg_timer_start(t, ctx)
+        for _ in range(10):
+            fn()
+        apcg.apcg_timer_stop(t, ctx)
+        ms = apcg.apcg_timer_elapsed_ms(t) / 10
+        vec[name] = {"n": nv, "bytes": nbytes, "ms": round(ms, 4), "gbs": round(nbytes / (ms * 1e-3) / 1e9, 1)}
+        log(f"[sweep] {name} 2^27: {ms:.3f} ms, {vec[name]['gbs']} GB/s")
+    apcg.apcg_timer_destroy(t)
+    apcg.apcg_scalar_destroy(a)
+    apcg.apcg_vec_destroy(hu)
+    apcg.apcg_vec_destroy(hv)
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_synchronize(ctx)
+    apcg.apcg_ctx_destroy(ctx)
+    return {"cg_20_iterations": out, "vector_kernels_out_of_cache": vec}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -410,6 +530,12 @@ def main():
     ap.add_argument("--mixed-train-nmax", type=float, default=1e6, help="largest training system (rows)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="only run a plain 1 GiB device copy (HBM counter calibration)")
+    ap.add_argument("--sweep", action="store_true",
+                    help="only run the 20-iteration CG sweep over stencils and NNZ (prints one JSON line)")
+    ap.add_argument("--sweep-nnz", type=float, nargs="+", default=[1e4, 1e5, 1e6, 1e7, 1e8])
+    ap.add_argument("--sweep-stencils", type=int, nargs="+", default=[5, 9, 7, 27])
+    ap.add_argument("--sweep-reps", type=int, default=5)
+    ap.add_argument("--sweep-cpu-max-nnz", type=float, default=2e7)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -432,6 +558,10 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(apcg, torch)
+        return
+    if args.sweep:
+        res = bench_sweep(apcg, torch, args.sweep_nnz, args.sweep_reps, args.sweep_cpu_max_nnz, args.sweep_stencils)
+        print(json.dumps({"sweep": res, "cpu_cores": 1, "timing": "min over repetitions, end to end"}), flush=True)
         return
 
     t0 = time.time()

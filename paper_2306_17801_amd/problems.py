@@ -149,6 +149,65 @@ def laplace_3d(n: int) -> CSR:
     return diffusion_csr(np.ones((n, n, n)))
 
 
+def stencil_laplacian(shape: tuple, points: int) -> CSR:
+    """Constant-coefficient Laplace operator on an interior grid of ``shape``
+    ((y, x) or (z, y, x), x fastest) with Dirichlet boundaries, for the four
+    stencils of the paper's CG benchmark (Section 4.1):
+
+      * star (5 points in 2D, 7 in 3D): -1 to each face neighbour, 2 d on
+        the diagonal (the same matrix as laplace_2d / laplace_3d);
+      * box (9 points in 2D, 27 in 3D): -1 to each of the 3^d - 1 neighbours
+        sharing a face, edge or corner, 3^d - 1 on the diagonal; this is
+        3^d I - S (x) ... (x) S with S = tridiag(1, 1, 1) per axis, SPD
+        because every eigenvalue of S lies in (-1, 3).
+
+    Neighbours outside the grid are dropped (their rows keep the full
+    diagonal).  Built directly in CSR order: the neighbour offsets are taken
+    in lexicographic order of (dz, dy, dx), which is increasing column order,
+    so no sort is needed even for 10^8 nonzeros."""
+    dim = len(shape)
+    if (dim, points) not in ((2, 5), (2, 9), (3, 7), (3, 27)):
+        raise ValueError("stencils: 5 or 9 points in 2D, 7 or 27 in 3D")
+    box = points in (9, 27)
+    deltas = [d for d in np.ndindex(*([3] * dim))]
+    deltas = [tuple(c - 1 for c in d) for d in deltas]
+    if not box:
+        deltas = [d for d in deltas if sum(abs(c) for c in d) <= 1]
+    n = int(np.prod(shape))
+    strides = [int(np.prod(shape[a + 1:])) for a in range(dim)]
+    coords = np.indices(shape, dtype=np.int32).reshape(dim, -1)
+    cols = np.empty((n, len(deltas)), dtype=np.int32)
+    vals = np.empty((n, len(deltas)), dtype=np.float64)
+    center = float(len(deltas) - 1) if box else float(2 * dim)
+    for q, d in enumerate(deltas):
+        ok = np.ones(n, dtype=bool)
+        off = 0
+        for a in range(dim):
+            c = coords[a] + d[a]
+            ok &= (c >= 0) & (c < shape[a])
+            off += d[a] * strides[a]
+        cols[:, q] = np.where(ok, np.arange(n, dtype=np.int32) + off, -1)
+        vals[:, q] = center if not any(d) else -1.0
+    keep = cols >= 0
+    rowptr = np.zeros(n + 1, dtype=np.int32)
+    np.cumsum(keep.sum(axis=1), out=rowptr[1:])
+    A = CSR(n=n, rowptr=rowptr, col=np.ascontiguousarray(cols[keep]), val=np.ascontiguousarray(vals[keep]),
+            shape=tuple(shape))
+    A.meta["stencil"] = f"{points}-point"
+    return A
+
+
+def stencil_eigval(shape: tuple, points: int, modes: tuple) -> float:
+    """Eigenvalue of stencil_laplacian(shape, points) for the Dirichlet sine
+    mode ``modes`` (one 1-based mode number per axis; the eigenvector is
+    laplace_eigvec(shape, modes)): star: sum of 2 - 2 cos(m pi / (n + 1));
+    box: 3^d - prod of (1 + 2 cos(m pi / (n + 1)))."""
+    cs = [math.cos(m * math.pi / (n_ax + 1)) for n_ax, m in zip(shape, modes)]
+    if points in (5, 7):
+        return float(sum(2.0 - 2.0 * c for c in cs))
+    return float(3 ** len(shape) - math.prod(1.0 + 2.0 * c for c in cs))
+
+
 def laplace_eigvec(shape: tuple, modes: tuple) -> np.ndarray:
     """Dirichlet sine eigenvector with mode numbers ``modes`` (one per axis,
     1-based, axis order matching ``shape``), flattened in row order."""

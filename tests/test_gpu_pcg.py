@@ -375,3 +375,53 @@ def test_sliced_diagonals_rejected(apcg, ctx):
     with pytest.raises(apcg.ApcgError) as e:
         apcg.apcg_mat_set_spmv_config(dB.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
     assert e.value.code == apcg.APCG_ERR_UNSUPPORTED
+
+
+@pytest.mark.parametrize("shape,points", [((40, 37), 9), ((12, 11, 9), 27), ((30, 20), 5), ((9, 10, 11), 7)])
+def test_stencil_operators_all_schedules(apcg, ctx, shape, points):
+    """The four stencils of the paper's CG benchmark (Section 4.1).  The
+    27-point operator takes the wide paths: 27 offsets per slice (sliced
+    diagonals, 32 offset slots) and 27-entry rows (sliced, row groups).
+    Every schedule meets the oracle's bar; sliced diagonals equal the sliced
+    schedule bit for bit at the same launch shape; at exactly 20 iterations
+    (the benchmark's protocol) the iterates agree with the oracle to
+    rounding."""
+    A = P.stencil_laplacian(shape, points)
+    b = np.random.default_rng(47).uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
+    ref20 = oracle.pcg(A, b, rtol=0.0, maxit=20)
+    xs = {}
+    for spmv in [(1, 256, 0, 3), (1, 256, 0, 2), (1, 512, 16, 3), (1, 512, 16, 2), (4, 256, 0, 0), (8, 512, 0, 0)]:
+        print(f"case stencil {points}-pt {shape} spmv={spmv}", flush=True)
+        res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=spmv)
+        assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
+        assert rel(x, ref.x) <= 1e-9
+        xs[spmv] = x
+        res, x = gpu_solve(apcg, ctx, A, b, 0.0, 20, spmv=spmv)
+        assert res["iterations"] == 20 and res["status"] == apcg.APCG_SOLVE_MAXIT
+        assert rel(x, ref20.x) <= 1e-12
+    assert np.array_equal(xs[(1, 256, 0, 3)], xs[(1, 256, 0, 2)])
+    assert np.array_equal(xs[(1, 512, 16, 3)], xs[(1, 512, 16, 2)])
+
+
+@pytest.mark.parametrize("sync", [False, True])
+@pytest.mark.parametrize("shape,points,diag", [((33, 29), 9, 8.0), ((10, 9, 8), 27, 26.0), ((41, 23), 5, 4.0)])
+def test_composed_cg_matches_oracle(apcg, ctx, shape, points, diag, sync):
+    """CG written from the asynchronous primitives (MatMult, VecDot, VecNorm,
+    AXPY, AYPX, scalar division; Section 3.3) with device scalars, with and
+    without reading every reduction back to the host: 20 iterations agree
+    with the oracle's Jacobi-PCG to rounding, and the returned residual norm
+    with the oracle's."""
+    from paper_2306_17801_amd.composed import ComposedCG
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    A = P.stencil_laplacian(shape, points)
+    b = np.random.default_rng(48).uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, rtol=0.0, maxit=20)
+    print(f"case composed {points}-pt {shape} sync={sync}", flush=True)
+    dA, db, dx = DeviceCSR(A), DeviceVec(b), DeviceVec.zeros(A.n)
+    cg = ComposedCG(ctx, A.n)
+    res = cg.solve(dA.h, db.h, dx.h, diag, 20, sync=sync)
+    cg.close()
+    assert rel(dx.numpy(), ref.x) <= 1e-12
+    assert res == pytest.approx(ref.res, rel=1e-10)

@@ -69,6 +69,49 @@ def test_generator_variable_coefficients_spd():
     assert D[0, 1] == pytest.approx(-13.0 * 2 * k0 * k1 / (k0 + k1), rel=1e-15)
 
 
+@pytest.mark.parametrize("shape,points", [((6, 7), 5), ((5, 4, 6), 7)])
+def test_stencil_star_equals_laplace(shape, points):
+    """The star stencils of the sweep are the textbook matrices above."""
+    A = P.stencil_laplacian(shape, points)
+    B = P.diffusion_csr(np.ones(shape))
+    assert np.array_equal(A.rowptr, B.rowptr) and np.array_equal(A.col, B.col) and np.array_equal(A.val, B.val)
+
+
+def _ones_tri(n):
+    return sp.diags([np.ones(n - 1), np.ones(n), np.ones(n - 1)], [-1, 0, 1])
+
+
+@pytest.mark.parametrize("shape", [(5, 7), (3, 4, 5), (1, 6), (2, 2, 2)])
+def test_stencil_box_is_kronecker_form(shape):
+    """Box stencils (9 / 27 points) equal 3^d I - S (x) ... (x) S with
+    S = tridiag(1, 1, 1), rows column-sorted, SPD, nnz by counting."""
+    points = 9 if len(shape) == 2 else 27
+    A = P.stencil_laplacian(shape, points)
+    K = _ones_tri(shape[0])
+    for m in shape[1:]:
+        K = sp.kron(K, _ones_tri(m))
+    ref = (3 ** len(shape) * sp.identity(A.n) - K).toarray()
+    D = dense(A)
+    assert np.array_equal(D, ref)
+    for i in range(A.n):
+        assert np.all(np.diff(A.col[A.rowptr[i]:A.rowptr[i + 1]]) > 0)
+    assert np.linalg.eigvalsh(D).min() > 0
+    # nnz: per axis the number of (cell, neighbour-or-self) pairs is 3 m - 2
+    assert A.nnz == math.prod(3 * m - 2 for m in shape)
+
+
+@pytest.mark.parametrize("shape,points,modes", [((12, 9), 9, (1, 1)), ((12, 9), 9, (7, 3)), ((6, 5, 7), 27, (1, 1, 1)),
+                                                ((6, 5, 7), 27, (4, 2, 6)), ((10, 11), 5, (3, 9)), ((5, 6, 4), 7, (2, 2, 3))])
+def test_stencil_eigenpairs(shape, points, modes):
+    """A v = lambda v for the Dirichlet sine modes with the closed-form
+    eigenvalues (star: sum of 2 - 2 cos; box: 3^d - prod of 1 + 2 cos)."""
+    A = P.stencil_laplacian(shape, points)
+    v = P.laplace_eigvec(shape, modes)
+    lam = P.stencil_eigval(shape, points, modes)
+    Av = oracle.spmv(A, v)
+    assert np.linalg.norm(Av - lam * v) <= 1e-13 * np.linalg.norm(v) * abs(lam) + 1e-13
+
+
 @pytest.mark.parametrize("shape,modes", [((64, 64), (1, 1)), ((64, 64), (5, 17)), ((9, 13), (2, 12)),
                                          ((6, 7, 8), (1, 3, 8)), ((10, 10, 10), (10, 1, 4))])
 def test_spmv_laplacian_eigenvectors(shape, modes):
