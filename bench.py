@@ -55,14 +55,14 @@ def source_hash(path):
 def sdia_shape(A):
     """Value slots U per 64-row slice of the sliced-diagonal layout (the most
     distinct column offsets of any slice) and offset/mask slots (U rounded up
-    to a multiple of 8)."""
+    to 8, 16 or 32)."""
     import numpy as np
 
     rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
     key = (rows // 64) * (2 * A.n + 1) + (A.col.astype(np.int64) - rows + A.n)
     sl = np.unique(key) // (2 * A.n + 1)
     u = int(np.bincount(sl).max()) if sl.size else 1
-    return u, (u + 7) // 8 * 8
+    return u, 8 if u <= 8 else 16 if u <= 16 else 32
 
 
 def copy_calibration(apcg, torch):

@@ -75,6 +75,8 @@ def lib():
         L.or_pcg.restype = i32
         L.or_poly_apply.argtypes = [i32, P, P, P, P, f64, i32, P, P, P]
         L.or_poly_apply.restype = i32
+        L.or_tfqmr.argtypes = [i32, P, P, P, P, P, i32, f64, i32, i32, P, P, P, P, P]
+        L.or_tfqmr.restype = i32
         L.or_fcg_poly.argtypes = [i32, P, P, P, P, P, f64, i32, i32, P, f64, i32, f64, i32, i32, P, P, P, P]
         L.or_fcg_poly.restype = i32
         _lib = L
@@ -162,6 +164,28 @@ def pcg(A, b, x0=None, rtol=1e-8, maxit=None, pc=PC_JACOBI, norm_type=NORM_UNPRE
         out.res_hist = rh[:k].copy()
     if ndir > 0:
         out.dirs = dh[: min(ndir, max(its.value, 0) + 1)].copy()
+    return out
+
+
+def tfqmr(A, b, x0=None, rtol=1e-8, maxit=None, pc=PC_JACOBI, history=False):
+    """TFQMR, left-preconditioned by D^{-1} (see or_tfqmr in apcg_oracle.c).
+    Returns PCGResult with x, its (iterations, two products each), half
+    (half-steps), status, res (the quasi-residual bound tau sqrt(m + 1) of
+    the last half-step) and ref (||D^{-1} (b - A x0)||); with ``history``
+    also tau after every half-step."""
+    rp, c, v = _csr(A)
+    n = A.n
+    maxit = n if maxit is None else int(maxit)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(n) if x0 is None else np.array(x0, dtype=np.float64, copy=True)
+    its, half = ctypes.c_int32(), ctypes.c_int32()
+    res, ref = ctypes.c_double(), ctypes.c_double()
+    th = np.zeros(max(2 * maxit, 1)) if history else None
+    st = lib().or_tfqmr(n, _p(rp), _p(c), _p(v), _p(b), _p(x), 1 if x0 is None else 0, float(rtol), maxit, int(pc),
+                        ctypes.byref(its), ctypes.byref(half), ctypes.byref(res), ctypes.byref(ref), _p(th))
+    out = PCGResult(x=x, its=its.value, half=half.value, status=st, res=res.value, ref=ref.value)
+    if history:
+        out.tau = th[: half.value].copy()
     return out
 
 

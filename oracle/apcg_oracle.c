@@ -26,6 +26,9 @@
  *     Y = (2/lmax) D^{-1} A - I, evaluated by the forward three-term
  *     recurrence T_{j+1} = 2 Y T_j - T_{j-1}.
  *   - Gershgorin discs of D^{-1} A: centre 1, radius sum_{j!=i} |a_ij|/|a_ii|.
+ *   - TFQMR (the paper's second benchmark method): Freund (1993), two
+ *     products per iteration as in Saad (2nd ed., Section 7.4.3) and Kelley
+ *     (1995, Section 3.6.3), left-preconditioned by D^{-1}.
  */
 #include <math.h>
 #include <stddef.h>
@@ -388,5 +391,133 @@ finish:
     *fcg_its = k;
 done:
     free(dinv); free(r); free(z); free(p); free(w);
+    return status;
+}
+
+/* ---------------------------------------------------------------------- */
+/* TFQMR                                                                   */
+/* ---------------------------------------------------------------------- */
+
+/*
+ * Transpose-free QMR, the paper's second benchmark method (Section 4,
+ * "Transpose-Free Quasi-Minimal Residual"; Freund, SIAM J. Sci. Comput. 14,
+ * 1993), in the arrangement with two products per iteration (Saad, Iterative
+ * Methods for Sparse Linear Systems, 2nd ed., Section 7.4.3; Kelley,
+ * Iterative Methods for Linear and Nonlinear Equations, 1995, Section 3.6.3),
+ * applied to the left-preconditioned system B A x = B b with B = D^{-1}
+ * (pc = Jacobi, every a_ii nonzero) or B = I:
+ *
+ *   r0 = B (b - A x0);  w = y1 = r0;  u1 = B A y1;  v = u1;  d = 0
+ *   tau = ref = ||r0||;  theta = eta = 0;  rho = r0 . r0
+ *   iteration k = 1, 2, ...:
+ *     sigma = r0 . v (0: breakdown);  alpha = rho / sigma
+ *     y2 = y1 - alpha v;  u2 = B A y2
+ *     half-steps j = 1, 2 (m = 2k - 2 + j) with (y, u) = (y1, u1), (y2, u2):
+ *       w = w - alpha u
+ *       d = y + (theta^2 eta / alpha) d
+ *       theta = ||w|| / tau;  c = 1 / sqrt(1 + theta^2);  tau = tau theta c
+ *       eta = c^2 alpha;  x = x + eta d
+ *       converged when tau sqrt(m + 1) <= rtol ref
+ *     rho' = r0 . w (0: breakdown);  beta = rho' / rho;  rho = rho'
+ *     y1 = w + beta y2;  u1 = B A y1;  v = u1 + beta (u2 + beta v)
+ *
+ * tau sqrt(m + 1) bounds ||B (b - A x_m)|| (Freund's estimate); it is the
+ * reported residual (*bound) and the tested one.  *its counts iterations k
+ * (two products each), *halfsteps the last m.  tau_hist (optional, 2 maxit
+ * doubles) receives tau after every half-step.  Returns the status bits.
+ */
+int32_t or_tfqmr(int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                 const double *b, double *x, int32_t x0_zero, double rtol, int32_t maxit, int32_t pc,
+                 int32_t *its, int32_t *halfsteps, double *bound, double *ref_out, double *tau_hist)
+{
+    double *bd = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *r0 = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *w = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *y1 = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *y2 = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *u1 = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *u2 = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *v = malloc(sizeof(double) * (n > 0 ? n : 1));
+    double *d = malloc(sizeof(double) * (n > 0 ? n : 1));
+    int32_t status = 0, k = 0, m = 0;
+    double tau = 0.0, ref = 0.0;
+    *its = 0;
+    *halfsteps = 0;
+    *bound = 0.0;
+    *ref_out = 0.0;
+
+    /* B = D^{-1}: every diagonal entry present and nonzero */
+    for (int32_t i = 0; i < n; ++i) {
+        if (pc == OR_PC_NONE) { bd[i] = 1.0; continue; }
+        double a = 0.0;
+        int found = 0;
+        for (int32_t q = rowptr[i]; q < rowptr[i + 1]; ++q)
+            if (col[q] == i) { a = val[q]; found = 1; }
+        if (!found || a == 0.0 || !isfinite(a)) { status = OR_SETUP_ERROR; goto done; }
+        bd[i] = 1.0 / a;
+    }
+    /* r0 = B (b - A x0) */
+    if (x0_zero) {
+        for (int32_t i = 0; i < n; ++i) { x[i] = 0.0; r0[i] = bd[i] * b[i]; }
+    } else {
+        or_spmv(n, rowptr, col, val, x, w);
+        for (int32_t i = 0; i < n; ++i) r0[i] = bd[i] * (b[i] - w[i]);
+    }
+    ref = or_norm2(n, r0);
+    *ref_out = ref;
+    if (!isfinite(ref)) { status = OR_NAN; goto done; }
+    if (ref == 0.0) { status = OR_CONVERGED; goto done; }
+    if (maxit <= 0) { status = OR_MAXIT; *bound = ref; goto done; }
+    for (int32_t i = 0; i < n; ++i) { w[i] = r0[i]; y1[i] = r0[i]; d[i] = 0.0; }
+    or_spmv(n, rowptr, col, val, y1, u1);
+    for (int32_t i = 0; i < n; ++i) { u1[i] *= bd[i]; v[i] = u1[i]; }
+    tau = ref;
+    double theta = 0.0, eta = 0.0, rho = or_dot(n, r0, r0);
+
+    for (k = 1; k <= maxit; ++k) {
+        const double sigma = or_dot(n, r0, v);
+        if (!isfinite(sigma)) { status = OR_NAN; --k; goto finish; }
+        if (sigma == 0.0) { status = OR_BREAKDOWN_PAP; --k; goto finish; }
+        const double alpha = rho / sigma;
+        for (int32_t i = 0; i < n; ++i) y2[i] = y1[i] - alpha * v[i];
+        or_spmv(n, rowptr, col, val, y2, u2);
+        for (int32_t i = 0; i < n; ++i) u2[i] *= bd[i];
+        for (int j = 1; j <= 2; ++j) {
+            const double *y = j == 1 ? y1 : y2, *u = j == 1 ? u1 : u2;
+            m = 2 * k - 2 + j;
+            const double f = theta * theta * eta / alpha;
+            for (int32_t i = 0; i < n; ++i) {
+                w[i] = w[i] - alpha * u[i];
+                d[i] = y[i] + f * d[i];
+            }
+            theta = or_norm2(n, w) / tau;
+            const double c = 1.0 / sqrt(1.0 + theta * theta);
+            tau = tau * theta * c;
+            eta = c * c * alpha;
+            for (int32_t i = 0; i < n; ++i) x[i] = x[i] + eta * d[i];
+            if (tau_hist) tau_hist[m - 1] = tau;
+            *bound = tau * sqrt((double)m + 1.0);
+            if (!isfinite(*bound)) { status = OR_NAN; goto finish; }
+            if (*bound <= rtol * ref) { status = OR_CONVERGED; goto finish; }
+        }
+        const double rho_new = or_dot(n, r0, w);
+        if (!isfinite(rho_new)) { status = OR_NAN; goto finish; }
+        if (rho_new == 0.0) { status = OR_BREAKDOWN_RZ; goto finish; }
+        const double beta = rho_new / rho;
+        rho = rho_new;
+        for (int32_t i = 0; i < n; ++i) y1[i] = w[i] + beta * y2[i];
+        or_spmv(n, rowptr, col, val, y1, u1);
+        for (int32_t i = 0; i < n; ++i) {
+            u1[i] *= bd[i];
+            v[i] = u1[i] + beta * (u2[i] + beta * v[i]);
+        }
+    }
+    k = maxit;
+    status = OR_MAXIT;
+finish:
+    *its = k;
+    *halfsteps = m;
+done:
+    free(bd); free(r0); free(w); free(y1); free(y2); free(u1); free(u2); free(v); free(d);
     return status;
 }

@@ -491,19 +491,19 @@ __global__ __launch_bounds__(256) void k_sell_fill(int32_t n, const int32_t *__r
 
 // Sliced-diagonal schedule (SDIA): wavefront v of a workgroup takes slices
 // s0 + v, s0 + v + TB/64, ... of the workgroup's contiguous range, lane l
-// reduces row 64 s + l.  Slice s has offset slots s*MP .. s*MP+MP-1 (sorted
+// reduces row 64 s + l.  Slice s has W offset slots s*W .. s*W+W-1 (sorted
 // column offsets, a 64-bit row mask each, mask 0 beyond the slice's own
-// offsets) and value slots s*U .. s*U+U-1 of 64 values, one per lane.  The
-// row adds the entries its mask bits select in offset order, i.e. in column
-// order, with one fused multiply-add each: the same sum as the row-per-thread
-// and sliced schedules.  shape = U | MP << 8.  Branch-free: every load is
+// offsets; W in {8, 16, 32}) and value slots s*U .. s*U+U-1 of 64 values,
+// one per lane.  The row adds the entries its mask bits select in offset
+// order, i.e. in column order, with one fused multiply-add each: the same sum
+// as the row-per-thread and sliced schedules.  Branch-free: every load is
 // issued unconditionally (value slot clamped to U-1, the gather index of an
-// absent entry to the row itself), absent entries are dropped by selects, so
-// all loads of a slice are in flight together; the offsets and masks of
-// 8 slots are one scalar load each.
-// PIPE (MP == 8): the next slice's offsets, masks and values are loaded
-// before the current slice's gathers.  Otherwise 8 slots at a time.
-template <int TB, int PIPE>
+// absent entry pointed at the row itself) and absent entries are dropped by
+// selects, so all W slots' loads of a slice are in flight together; the
+// offsets and masks of 8 slots are one scalar load each.
+// W == 8: software pipelined -- the next slice's offsets, masks and values
+// are loaded before the current slice's gathers.
+template <int TB, int W>
 __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_t *__restrict__ soff,
                                                          const int32_t *__restrict__ smask_words,
                                                          const double *__restrict__ sval, const double *__restrict__ z,
@@ -511,77 +511,73 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
                                                          double *__restrict__ w, SolveState *st,
                                                          const double *part_res, int g_res, double *part_delta,
                                                          int32_t slices_per_block, int parity, int tune,
-                                                         int32_t shape) {
+                                                         int32_t U) {
     const uint64_t *smask = reinterpret_cast<const uint64_t *>(smask_words);
-    const int U = shape & 0xff, MP = shape >> 8;
     const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
     const int nsl = (n + 63) / 64;
     const int s0 = lb * slices_per_block;
     const int s1 = min(nsl, s0 + slices_per_block);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     constexpr int STEP = TB / 64;
-    int on[8];
-    uint64_t mn[8];
-    double an[8];
-    auto load = [&](int sl, int c) {  // slots 8c .. 8c+7 of slice sl
-        const int32_t *o = soff + (int64_t)sl * MP + 8 * c;
-        const uint64_t *m = smask + (int64_t)sl * MP + 8 * c;
+    int on[W];
+    uint64_t mn[W];
+    double an[W];
+    auto load = [&](int sl) {
+        const int32_t *o = soff + (int64_t)sl * W;
+        const uint64_t *m = smask + (int64_t)sl * W;
         const double *v = sval + (int64_t)sl * U * 64 + lane;
 #pragma unroll
-        for (int k = 0; k < 8; ++k) {
+        for (int k = 0; k < W; ++k) {
             on[k] = o[k];
             mn[k] = m[k];
-            an[k] = __builtin_nontemporal_load(v + (int64_t)min(8 * c + k, U - 1) * 64);
+            an[k] = __builtin_nontemporal_load(v + (int64_t)min(k, U - 1) * 64);
         }
-    };
-    // adds the 8 slots held in (oc, mc, ac) to sum for row (rc: row clamped to n-1)
-    auto add8 = [&](const int *oc, const uint64_t *mc, const double *ac, int row, int rc, double beta,
-                    double sum) {
-        double zj[8], pj[8];
-        bool in[8];
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            in[k] = (mc[k] >> lane) & 1ull;
-            const int j = in[k] ? row + oc[k] : rc;
-            zj[k] = z[j];
-            pj[k] = pold[j];
-        }
-#pragma unroll
-        for (int k = 0; k < 8; ++k) {
-            const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
-            sum = in[k] ? t : sum;
-        }
-        return sum;
     };
     // the first slice's loads do not depend on beta: issued before the
     // prologue's reduction so that its latency overlaps them
-    if (PIPE && s0 + wave < s1) load(s0 + wave, 0);
+    if (W == 8 && s0 + wave < s1) load(s0 + wave);
     double beta;
     if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
     double acc = 0.0;
     for (int sl = s0 + wave; sl < s1; sl += STEP) {
         const int row = sl * 64 + lane;
         const int rc = min(row, n - 1);
-        double sum = 0.0;
-        if (PIPE) {
-            int oc[8];
-            uint64_t mc[8];
-            double ac[8];
+        int oc[W];
+        uint64_t mc[W];
+        double ac[W];
+        if (W == 8) {
 #pragma unroll
-            for (int k = 0; k < 8; ++k) {
+            for (int k = 0; k < W; ++k) {
                 oc[k] = on[k];
                 mc[k] = mn[k];
                 ac[k] = an[k];
             }
-            if (sl + STEP < s1) load(sl + STEP, 0);  // in flight during the gathers below
-            sum = add8(oc, mc, ac, row, rc, beta, sum);
+            if (sl + STEP < s1) load(sl + STEP);  // in flight during the gathers below
         } else {
-            for (int c = 0; c < MP / 8; ++c) {
-                load(sl, c);
-                sum = add8(on, mn, an, row, rc, beta, sum);
+            load(sl);
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                oc[k] = on[k];
+                mc[k] = mn[k];
+                ac[k] = an[k];
             }
         }
+        double zj[W], pj[W];
+        bool in[W];
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            in[k] = (mc[k] >> lane) & 1ull;
+            const int j = in[k] ? row + oc[k] : rc;
+            zj[k] = z[j];
+            pj[k] = pold[j];
+        }
         const double zi = z[rc], po = pold[rc];
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < W; ++k) {
+            const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
+            sum = in[k] ? t : sum;
+        }
         if (row < n) {
             const double pi = pdir(zi, beta, po);
             pnew[row] = pi;
@@ -737,9 +733,10 @@ ProductFn stream_fn(int32_t lds_nnz) {
 
 ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw, int32_t sdia_mp) {
     if (cfg.schedule == APCG_SPMV_SDIA) {
-        if (sdia_mp == 8)
-            return cfg.block_size == 512 ? k_pcg_product_sdia<512, 1> : k_pcg_product_sdia<256, 1>;
-        return cfg.block_size == 512 ? k_pcg_product_sdia<512, 0> : k_pcg_product_sdia<256, 0>;
+        const bool b512 = cfg.block_size == 512;
+        if (sdia_mp == 8) return b512 ? k_pcg_product_sdia<512, 8> : k_pcg_product_sdia<256, 8>;
+        if (sdia_mp == 16) return b512 ? k_pcg_product_sdia<512, 16> : k_pcg_product_sdia<256, 16>;
+        return b512 ? k_pcg_product_sdia<512, 32> : k_pcg_product_sdia<256, 32>;
     }
     if (cfg.schedule == APCG_SPMV_SELL) {
         if (sell_maxw <= 8)
@@ -764,7 +761,7 @@ struct Plan {
     int32_t rpb;  // rows (row groups), chunks (staged) or slices (sliced) per workgroup
     int g_vec;
     int64_t pb_vec;
-    int32_t lds_nnz;     // staged schedule: LDS entries per workgroup; sliced diagonals: U | MP << 8
+    int32_t lds_nnz;     // staged schedule: LDS entries per workgroup; sliced diagonals: value slots per slice
     size_t lds_bytes;
 };
 
@@ -798,7 +795,7 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         const int64_t waves = pl->tb / 64;
         pl->g_prod = normalise_blocks(cfg.blocks, (nsl + waves - 1) / waves);
         pl->rpb = (int32_t)std::max<int64_t>(1, (nsl + pl->g_prod - 1) / pl->g_prod);
-        pl->lds_nnz = A->sdia_u | (A->sdia_mp << 8);  // the kernel's shape argument
+        pl->lds_nnz = A->sdia_u;  // the kernel's value slots per slice
     } else if (cfg.schedule == APCG_SPMV_SELL) {
         if (!A->sell_meta) return set_error(APCG_ERR_INVALID_STATE, "sliced copy not prepared");
         pl->a0 = A->sell_meta;
@@ -896,7 +893,7 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
         const int64_t slots = nsl * U * 64;
         const int64_t sell_bytes = 12 * (A->sell_entries >= 0 ? A->sell_entries : nnz);
         if (8 * slots > sell_bytes) return reject("the padded value copy would exceed the sliced copy");
-        const int32_t MP = (U + 7) / 8 * 8;
+        const int32_t MP = U <= 8 ? 8 : U <= 16 ? 16 : 32;
         std::vector<int32_t> off_h((size_t)(nsl * MP), 0);
         std::vector<uint64_t> msk_h((size_t)(nsl * MP), 0);
         for (int64_t sl = 0; sl < nsl; ++sl) {

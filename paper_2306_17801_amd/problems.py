@@ -197,6 +197,28 @@ def stencil_laplacian(shape: tuple, points: int) -> CSR:
     return A
 
 
+def convection_diffusion(shape: tuple, conv: tuple) -> CSR:
+    """Nonsymmetric test operator for TFQMR: the star Laplacian of
+    stencil_laplacian plus centred first differences along each axis,
+    -1 + c_a/2 to the +1 neighbour and -1 - c_a/2 to the -1 neighbour of
+    axis a (c_a = velocity x cell width along a; |c_a| < 2 keeps every
+    off-diagonal negative, so the matrix is a nonsingular M-matrix)."""
+    dim = len(shape)
+    if len(conv) != dim:
+        raise ValueError("one convection coefficient per axis")
+    A = stencil_laplacian(shape, 5 if dim == 2 else 7)
+    strides = [int(np.prod(shape[a + 1:])) for a in range(dim)]
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
+    off = A.col.astype(np.int64) - rows
+    val = A.val.copy()
+    for a in range(dim):
+        val[off == strides[a]] += conv[a] / 2.0
+        val[off == -strides[a]] -= conv[a] / 2.0
+    A.val = val
+    A.meta["stencil"] = f"convection-diffusion {conv}"
+    return A
+
+
 def stencil_eigval(shape: tuple, points: int, modes: tuple) -> float:
     """Eigenvalue of stencil_laplacian(shape, points) for the Dirichlet sine
     mode ``modes`` (one 1-based mode number per axis; the eigenvector is

@@ -532,3 +532,102 @@ def test_mixed_system_is_the_batchs_member():
         s = P.mixed_system((5, i, 1e3, 1e6))
         assert np.array_equal(s.A.val, full[i].A.val) and np.array_equal(s.b, full[i].b)
         assert s.meta == full[i].meta
+
+
+# ---------------------------------------------------------------------------
+# TFQMR (the paper's second benchmark method)
+# ---------------------------------------------------------------------------
+
+def _scaled(A):
+    """The explicitly left-scaled operator D^{-1} A (scipy) and D^{-1}."""
+    M = A.to_scipy()
+    dinv = 1.0 / M.diagonal()
+    return (sp.diags(dinv) @ M).tocsr(), dinv
+
+
+@pytest.mark.parametrize("which", ["convdiff2d", "convdiff3d", "laplace2d"])
+@pytest.mark.parametrize("k", [1, 3, 12])
+@pytest.mark.parametrize("pc", [oracle.PC_NONE, oracle.PC_JACOBI])
+def test_tfqmr_matches_scipy(which, k, pc):
+    """k iterations of the oracle equal 2k half-steps of scipy's independent
+    TFQMR applied to the explicitly preconditioned system (D^{-1} A,
+    D^{-1} b), to rounding."""
+    rng = np.random.default_rng(60 + k)
+    if which == "convdiff2d":
+        A = P.convection_diffusion((13, 17), (0.9, -0.4))
+    elif which == "convdiff3d":
+        A = P.convection_diffusion((6, 7, 5), (0.3, 0.7, -1.1))
+    else:
+        A = P.laplace_2d(15)
+    b = rng.uniform(-1, 1, A.n)
+    if pc == oracle.PC_JACOBI:
+        S, dinv = _scaled(A)
+        bs = dinv * b
+    else:
+        S, bs = A.to_scipy(), b
+    ref, _ = spla.tfqmr(S, bs, rtol=0.0, atol=0.0, maxiter=2 * k)
+    r = oracle.tfqmr(A, b, rtol=0.0, maxit=k, pc=pc)
+    assert r.status == oracle.MAXIT and r.its == k and r.half == 2 * k
+    assert np.linalg.norm(r.x - ref) <= 1e-11 * np.linalg.norm(ref)
+
+
+def test_tfqmr_exact_on_a_diagonal_operator():
+    """D^{-1} A = I: the first half-step gives x = D^{-1} b (to the rounding
+    of (1/a_ii) a_ii) and a quasi-residual bound at rounding level."""
+    n = 50
+    d = np.linspace(0.5, 7.0, n)
+    A = P.CSR(n=n, rowptr=np.arange(n + 1, dtype=np.int32), col=np.arange(n, dtype=np.int32), val=d)
+    b = np.random.default_rng(61).uniform(-1, 1, n)
+    r = oracle.tfqmr(A, b, rtol=1e-12, maxit=10, pc=oracle.PC_JACOBI)
+    assert r.status == oracle.CONVERGED and r.its == 1 and r.half == 1 and r.res <= 1e-15 * r.ref
+    assert np.linalg.norm(r.x - b / d) <= 1e-15 * np.linalg.norm(b / d)
+
+
+def test_tfqmr_quasi_residual_bound():
+    """Freund's bound: ||D^{-1}(b - A x_m)|| <= tau_m sqrt(m + 1) after every
+    even half-step, on a nonsymmetric system; tau decreases monotonically."""
+    A = P.convection_diffusion((11, 9), (1.2, 0.5))
+    b = np.random.default_rng(62).uniform(-1, 1, A.n)
+    M = A.to_scipy()
+    dinv = 1.0 / M.diagonal()
+    for k in range(1, 16):
+        r = oracle.tfqmr(A, b, rtol=0.0, maxit=k, history=True)
+        true = np.linalg.norm(dinv * (b - M @ r.x))
+        assert true <= r.res * (1 + 1e-9)
+        assert np.all(np.diff(r.tau) <= 1e-15 * r.tau[:-1])
+
+
+def test_tfqmr_finite_termination_rank_one():
+    """A = I + u v^T has a minimal polynomial of degree 2: TFQMR (no
+    preconditioner) reaches the solution within 2 iterations."""
+    n = 40
+    rng = np.random.default_rng(63)
+    u, v = rng.uniform(-1, 1, n), rng.uniform(0, 1, n) / n
+    M = sp.csr_matrix(np.eye(n) + np.outer(u, v))
+    M.sort_indices()
+    A = P.CSR(n=n, rowptr=M.indptr.astype(np.int32), col=M.indices.astype(np.int32), val=M.data.copy())
+    b = rng.uniform(-1, 1, n)
+    r = oracle.tfqmr(A, b, rtol=1e-13, maxit=2, pc=oracle.PC_NONE)
+    assert np.linalg.norm(b - M @ r.x) <= 1e-12 * np.linalg.norm(b)
+
+
+def test_tfqmr_status_cases():
+    A = P.convection_diffusion((8, 8), (0.5, 0.5))
+    # zero right-hand side: converged at once with x = 0
+    r = oracle.tfqmr(A, np.zeros(A.n), rtol=1e-8, maxit=10)
+    assert r.status == oracle.CONVERGED and r.its == 0 and np.all(r.x == 0.0)
+    # maxit = 0
+    b = np.ones(A.n)
+    r = oracle.tfqmr(A, b, rtol=1e-8, maxit=0)
+    assert r.status == oracle.MAXIT and r.its == 0
+    # a zero diagonal entry: the Jacobi preconditioner is undefined
+    B = P.CSR(n=A.n, rowptr=A.rowptr, col=A.col, val=A.val.copy())
+    q = B.rowptr[20] + int(np.nonzero(B.col[B.rowptr[20]:B.rowptr[21]] == 20)[0][0])
+    B.val[q] = 0.0
+    r = oracle.tfqmr(B, b, rtol=1e-8, maxit=10)
+    assert r.status == oracle.SETUP_ERROR
+    # the initial guess already solves the system
+    xs = np.random.default_rng(64).uniform(-1, 1, A.n)
+    r = oracle.tfqmr(A, A.to_scipy() @ xs, x0=xs, rtol=1e-8, maxit=10)
+    assert r.status == oracle.CONVERGED
+    assert np.linalg.norm(r.x - xs) <= 1e-12 * np.linalg.norm(xs)
