@@ -349,7 +349,7 @@ typedef struct apcg_solve_info {
     int32_t iterations;     /* products A p performed (PETSc's count)       */
     int32_t status;         /* APCG_SOLVE_* bits                             */
     int32_t fcg_iterations; /* iterations run by the flexible method         */
-    int32_t reserved;
+    int32_t half_steps;     /* TFQMR: half-steps m of the last iteration; 0 otherwise */
     double res_norm;        /* final stopping norm                           */
     double ref_norm;        /* ||b|| (or ||D^-1 b|| for the preconditioned norm) */
 } apcg_solve_info;
@@ -374,6 +374,23 @@ apcg_status apcg_info_get(apcg_info info, int32_t index, apcg_solve_info *out);
  * the solve has finished. */
 apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                            const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
+
+/* TFQMR (Section 4, the paper's second benchmark method; Freund 1993) for
+ * square, possibly nonsymmetric or indefinite A, left-preconditioned by
+ * B = D^{-1} (opts->pc == APCG_PC_JACOBI: every a_ii present, finite and
+ * nonzero, else APCG_SOLVE_SETUP_ERROR) or B = I (APCG_PC_NONE); two
+ * products with A per iteration.  The arguments, modes, x0 handling, the
+ * graph period K and the lookahead are those of apcg_ksp_solve;
+ * opts->norm_type is ignored.  Test: after every half-step m the quasi-
+ * residual bound tau_m sqrt(m + 1) (which bounds ||B (b - A x_m)||) is
+ * compared with rtol ||B (b - A x0)||.  The record holds iterations (two
+ * products each), half_steps (the last m), res_norm (the last bound) and
+ * ref_norm (||B (b - A x0)||).  Breakdowns: r0.v = 0 (the denominator of
+ * alpha) -> APCG_SOLVE_BREAKDOWN_PAP, r0.w = 0 (that of beta) ->
+ * APCG_SOLVE_BREAKDOWN_RZ.  Workspace: 9 n doubles per context, kept
+ * between solves. */
+apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
+                                 const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
 
 /* Solves the nsys independent systems A[i] x[i] = b[i] with Jacobi-PCG (or
  * CG): same stopping rule, tests and order as apcg_ksp_solve (Section 3.3

@@ -303,6 +303,12 @@ def apcg_ksp_solve(ctx, A, b, x, rtol: float, maxit: int, opts=None, info=None, 
                                                 int(info_index)))
 
 
+def apcg_ksp_solve_tfqmr(ctx, A, b, x, rtol: float, maxit: int, opts=None, info=None, info_index: int = 0) -> None:
+    po = ctypes.byref(opts) if opts is not None else None
+    check("apcg_ksp_solve_tfqmr", _L().apcg_ksp_solve_tfqmr(_h(ctx), _h(A), _h(b), _h(x), float(rtol), int(maxit),
+                                                            po, _h(info), int(info_index)))
+
+
 def apcg_ksp_solve_batched(ctx, A_list, b_list, x_list, rtol: float, maxit: int, opts=None, info=None) -> None:
     """A_list, b_list, x_list: equal-length sequences of handles."""
     n = len(A_list)

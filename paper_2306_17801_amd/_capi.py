@@ -79,12 +79,12 @@ class apcg_solve_opts(ctypes.Structure):
 
 
 class apcg_solve_info(ctypes.Structure):
-    _fields_ = [("iterations", c_i32), ("status", c_i32), ("fcg_iterations", c_i32), ("reserved", c_i32),
+    _fields_ = [("iterations", c_i32), ("status", c_i32), ("fcg_iterations", c_i32), ("half_steps", c_i32),
                 ("res_norm", c_f64), ("ref_norm", c_f64)]
 
     def as_dict(self):
         return {"iterations": self.iterations, "status": self.status, "fcg_iterations": self.fcg_iterations,
-                "res_norm": self.res_norm, "ref_norm": self.ref_norm}
+                "half_steps": self.half_steps, "res_norm": self.res_norm, "ref_norm": self.ref_norm}
 
 
 class apcg_fcg_opts(ctypes.Structure):
@@ -148,6 +148,7 @@ SIGNATURES = {
     "apcg_info_destroy": [c_vp],
     "apcg_info_get": [c_vp, c_i32, P(apcg_solve_info)],
     "apcg_ksp_solve": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts), c_vp, c_i32],
+    "apcg_ksp_solve_tfqmr": [c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts), c_vp, c_i32],
     "apcg_ksp_solve_batched": [c_vp, c_i32, P(c_vp), P(c_vp), P(c_vp), c_f64, c_i32, P(apcg_solve_opts), c_vp],
     "apcg_ctx_kernel_times": [c_vp, c_i32, P(c_f64), P(c_i32)],
     "apcg_pc_features": [c_vp, c_vp, c_vp, c_vp, c_vp],

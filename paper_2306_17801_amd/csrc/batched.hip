@@ -207,7 +207,7 @@ __device__ void solve_one(const BatchSys &S, double rtol, int32_t maxit, int x0_
         out->iterations = its;
         out->status = status;
         out->fcg_iterations = 0;
-        out->reserved = 0;
+        out->half_steps = 0;
         out->res_norm = res;
         out->ref_norm = ref;
     }
@@ -773,7 +773,7 @@ __global__ void k_seg_finish(SegPlan P, apcg_solve_info *info) {
     info[s].iterations = q.its;
     info[s].status = q.status ? q.status : APCG_SOLVE_MAXIT;
     info[s].fcg_iterations = 0;
-    info[s].reserved = 0;
+    info[s].half_steps = 0;
     info[s].res_norm = q.res;
     info[s].ref_norm = q.ref;
 }

@@ -554,7 +554,7 @@ __global__ void k_bf_finish(FPlan P, apcg_solve_info *info) {
     info[s].iterations = q.its;
     info[s].status = status;
     info[s].fcg_iterations = q.fcg_its;
-    info[s].reserved = 0;
+    info[s].half_steps = 0;
     info[s].res_norm = q.res;
     info[s].ref_norm = q.ref;
 }

@@ -352,7 +352,7 @@ __global__ void k_fcg_finish(const FcgState *st, const apcg_solve_info *fallback
     const FcgRec last = st->rec[0].its >= st->rec[1].its ? st->rec[0] : st->rec[1];
     apcg_solve_info o;
     o.fcg_iterations = last.its;
-    o.reserved = 0;
+    o.half_steps = 0;
     o.ref_norm = st->ref;
     if (fallback) {
         o.iterations = last.its + fallback->iterations;

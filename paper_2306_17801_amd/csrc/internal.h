@@ -222,6 +222,7 @@ void seg_cache_release(uint64_t ctx_id, int device);    // batched.hip
 void learn_cache_release(uint64_t ctx_id, int device);  // learn.hip
 void fcg_cache_release(uint64_t ctx_id, int device);    // fcg.hip
 void bfcg_cache_release(uint64_t ctx_id, int device);   // batched_fcg.hip
+void tq_cache_release(uint64_t ctx_id, int device);     // tfqmr.hip
 // Standardises X[B][16] in place with mean/std and writes the network's
 // coefficients C[B][9] (learn.hip); ordered on ctx's stream.
 apcg_status mlp_infer(apcg_ctx ctx, const float *params, const float *mean, const float *std, float *X, int32_t B,

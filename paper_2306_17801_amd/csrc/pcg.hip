@@ -687,7 +687,7 @@ __global__ __launch_bounds__(64) void k_pcg_finish(SolveState *st, const double 
     out->iterations = st->out_its;
     out->status = st->out_status;
     out->fcg_iterations = 0;
-    out->reserved = 0;
+    out->half_steps = 0;
     out->res_norm = st->out_res;
     out->ref_norm = st->ref;
 }

@@ -154,6 +154,7 @@ static void ctx_release_now(apcg_ctx c) {
     learn_cache_release(c->id, c->device);
     fcg_cache_release(c->id, c->device);
     bfcg_cache_release(c->id, c->device);
+    tq_cache_release(c->id, c->device);
     for (auto &g : c->graphs) {
         if (g.exec) hipGraphExecDestroy(g.exec);
         if (g.graph) hipGraphDestroy(g.graph);
