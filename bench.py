@@ -387,7 +387,9 @@ def bench_sweep(apcg, torch, targets, reps, cpu_max_nnz, stencils):
     Laplace operators with 5-/9-point (2D) and 7-/27-point (3D) stencils,
     NNZ from 1e4 to 1e8, exactly 20 Jacobi-PCG iterations (rtol 0), minimum
     over the repetitions of the end-to-end time to host-visible completion.
-    Variants: the fused solve in graph mode (asynchronous), in stream mode,
+    The same for TFQMR (Section 4's second method): graph mode, host-check
+    mode and the CPU oracle.  CG variants: the fused solve in graph mode
+    (asynchronous), in stream mode,
     and in host-check mode (the host waits after every kernel, the paper's
     synchronous baseline shape); CG composed from the asynchronous
     primitives with device scalars, and the same with every reduction read
@@ -443,6 +445,17 @@ def bench_sweep(apcg, torch, targets, reps, cpu_max_nnz, stencils):
 
                 row[name + "_ms"] = round(1e3 * tmin(run), 4)
                 xs[name] = x.numpy()
+            xt = {}
+            for name, mode in (("tfqmr_graph", apcg.APCG_MODE_GRAPH), ("tfqmr_host_check", apcg.APCG_MODE_HOST_CHECK)):
+                o = apcg.apcg_solve_opts_default(x0_is_zero=1, mode=mode)
+
+                def run(o=o):
+                    apcg.apcg_ksp_solve_tfqmr(ctx, A.h, b.h, x.h, 0.0, 20, o, info, 0)
+                    res = apcg.apcg_info_get(info, 0)
+                    assert res["iterations"] == 20, res
+
+                row[name + "_ms"] = round(1e3 * tmin(run), 4)
+                xt[name] = x.numpy()
             cg = ComposedCG(ctx, A_h.n)
             for name, sync in (("composed_async", False), ("composed_sync", True)):
                 row[name + "_ms"] = round(1e3 * tmin(lambda: cg.solve(A.h, b.h, x.h, diag[points], 20, sync),
@@ -460,11 +473,20 @@ def bench_sweep(apcg, torch, targets, reps, cpu_max_nnz, stencils):
                     t_cpu = min(t_cpu, time.perf_counter() - t1)
                 row["cpu_oracle_ms"] = round(1e3 * t_cpu, 4)
                 row["rel_diff_vs_oracle"] = float(np.linalg.norm(ref - r.x) / np.linalg.norm(r.x))
+                t_cpu = float("inf")
+                for _ in range(2 if A_h.nnz > 1e6 else 3):
+                    t1 = time.perf_counter()
+                    rt = oracle.tfqmr(A_h, b_h, rtol=0.0, maxit=20)
+                    t_cpu = min(t_cpu, time.perf_counter() - t1)
+                row["tfqmr_cpu_oracle_ms"] = round(1e3 * t_cpu, 4)
+                row["tfqmr_rel_diff_vs_oracle"] = float(max(np.linalg.norm(v - rt.x) / np.linalg.norm(rt.x)
+                                                            for v in xt.values()))
             it_bytes = 12 * A_h.nnz + 4 * (A_h.n + 1) + 96 * A_h.n
             row["graph_us_per_iteration"] = round(1e3 * row["graph_ms"] / 20, 3)
             row["graph_gbs_csr_bytes"] = round(20 * it_bytes / (row["graph_ms"] * 1e-3) / 1e9, 1)
             row["async_speedup_vs_host_check"] = round(row["host_check_ms"] / row["graph_ms"], 3)
             row["composed_async_speedup_vs_sync"] = round(row["composed_sync_ms"] / row["composed_async_ms"], 3)
+            row["tfqmr_async_speedup_vs_host_check"] = round(row["tfqmr_host_check_ms"] / row["tfqmr_graph_ms"], 3)
             log(f"[sweep] {points}-pt side {side} nnz {A_h.nnz:.3g} (gen {gen_s:.1f}s): " +
                 ", ".join(f"{k[:-3]} {v:.3f}" for k, v in row.items() if k.endswith("_ms")) + " ms")
             out.append(row)
