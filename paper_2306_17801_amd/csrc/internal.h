@@ -213,6 +213,9 @@ apcg_status ensure_workspace(apcg_ctx c, int64_t n);
 void batch_cache_release(uint64_t ctx_id, int device);  // batched.hip
 // sliced-diagonal pattern analysis (pcg.hip): synchronous, once per matrix
 apcg_status sdia_analyse(apcg_mat_s *A);
+// queues the refill of the sliced-diagonal values on stream s (pcg.hip);
+// analyses first if needed, APCG_ERR_UNSUPPORTED when the layout does not apply
+apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s);
 // Jacobi-PCG solve with registry marking (pcg.hip); hist (2 hist_cap doubles,
 // device) receives alpha_k and beta_k of the first hist_cap iterations.
 apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
@@ -506,6 +509,40 @@ __device__ inline void feature_vector(const double *st, double var, const double
     f[14] = log10(fmax(relres, 1e-30));  // floored: exact early convergence stays finite
     f[15] = log10(th[0] / hi);
     for (int k = 0; k < 16; ++k) feat[k] = (float)f[k];
+}
+
+// Row sum of a sliced-diagonal matrix (the layout of the SDIA schedule:
+// offset/mask slots s*W .. s*W+W-1, value slots s*U .. s*U+U-1 of 64 lanes
+// each): sum over the entries of row `row` in offset (column) order of
+// fma(a_ij, u(j), sum).  Every active lane of the calling wavefront must hold
+// a row of the same 64-row slice; rows >= n contribute nothing (their masks
+// are 0).  All loads are issued unconditionally at in-bounds addresses.
+template <int W, typename F>
+__device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
+                                           const double *__restrict__ sval, int U, int64_t n, int64_t row, F u) {
+    const int64_t sl = __builtin_amdgcn_readfirstlane((int)(row >> 6));
+    const int lane = (int)(row & 63);
+    const int32_t *o = soff + sl * W;
+    const uint64_t *m = smask + sl * W;
+    const double *v = sval + sl * U * 64 + lane;
+    const int rc = (int)(row < n ? row : n - 1);
+    double a[W], g[W];
+    bool in[W];
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const int ok = o[k];
+        const uint64_t mk = m[k];
+        a[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
+        in[k] = (mk >> lane) & 1ull;
+        g[k] = u(in[k] ? (int)row + ok : rc);
+    }
+    double sum = 0.0;
+#pragma unroll
+    for (int k = 0; k < W; ++k) {
+        const double t = fma(a[k], g[k], sum);
+        sum = in[k] ? t : sum;
+    }
+    return sum;
 }
 
 }  // namespace dev

@@ -920,8 +920,6 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
     }
 }
 
-namespace {
-
 // Queues the refill of the sliced-diagonal values from the CSR values on
 // stream s (analysing the pattern first if needed).
 apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s) {
@@ -935,6 +933,8 @@ apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s) {
     APCG_CHECK_LAUNCH("k_sdia_fill");
     return APCG_SUCCESS;
 }
+
+namespace {
 
 struct Bufs {
     const apcg_mat_s *A;

@@ -91,6 +91,26 @@ __device__ __forceinline__ double row_apply(const int32_t *__restrict__ col, con
     return sum;
 }
 
+// The matrix as the products read it: CSR, and the sliced-diagonal copy when
+// the matrix's SpMV schedule is APCG_SPMV_SDIA (then L = its slot width).
+struct TqMat {
+    const int32_t *rowptr, *col;
+    const double *val;
+    const int32_t *soff;
+    const uint64_t *smask;
+    const double *sval;
+    int U;
+};
+
+// B-less row product sum_j a_ij u(j) of row i; with L > 0 each wavefront's
+// rows are one 64-row slice (the row loops below step by the workgroup size
+// from a multiple of 64).
+template <int L, typename F>
+__device__ __forceinline__ double tq_row(const TqMat &M, int64_t n, int64_t i, F u) {
+    if constexpr (L == 0) return row_apply(M.col, M.val, M.rowptr[i], M.rowptr[i + 1], (int)i, u);
+    else return dev::sdia_row<L>(M.soff, M.smask, M.sval, M.U, n, i, u);
+}
+
 __device__ __forceinline__ void set_stop(TqState *st, int status) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         st->status = status;
@@ -166,9 +186,8 @@ __global__ __launch_bounds__(64) void k_tq_init_final(TqState *st, const double 
 }
 
 // u1 = B A y1, v = u1 and the partials of r0.v (sigma of iteration 1).
-__global__ __launch_bounds__(TBQ) void k_tq_init_product(int32_t n, const int32_t *__restrict__ rowptr,
-                                                         const int32_t *__restrict__ col,
-                                                         const double *__restrict__ val,
+template <int L>
+__global__ __launch_bounds__(TBQ) void k_tq_init_product(int32_t n, TqMat M,
                                                          const double *__restrict__ bd, const double *__restrict__ r0,
                                                          const double *__restrict__ y1, double *__restrict__ u1,
                                                          double *__restrict__ v, const TqState *st, double *part,
@@ -177,7 +196,7 @@ __global__ __launch_bounds__(TBQ) void k_tq_init_product(int32_t n, const int32_
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double s[1] = {0.0};
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBQ) {
-        const double ui = bd[i] * row_apply(col, val, rowptr[i], rowptr[i + 1], (int)i, [&](int q) { return y1[q]; });
+        const double ui = bd[i] * tq_row<L>(M, n, i, [&](int q) { return y1[q]; });
         u1[i] = ui;
         v[i] = ui;
         s[0] = fma(r0[i], ui, s[0]);
@@ -187,9 +206,9 @@ __global__ __launch_bounds__(TBQ) void k_tq_init_product(int32_t n, const int32_
 }
 
 // Kernel A of iteration (parity p).
-__global__ __launch_bounds__(TBQ) void k_tq_a(int32_t n, const int32_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col, const double *__restrict__ val,
-                                              const double *__restrict__ bd, const double *__restrict__ y1,
+template <int L>
+__global__ __launch_bounds__(TBQ) void k_tq_a(int32_t n, TqMat M, const double *__restrict__ bd,
+                                              const double *__restrict__ y1,
                                               const double *__restrict__ v, const double *__restrict__ u1,
                                               double *__restrict__ y2, double *__restrict__ u2,
                                               double *__restrict__ w, double *__restrict__ d, TqState *st, int p,
@@ -210,8 +229,7 @@ __global__ __launch_bounds__(TBQ) void k_tq_a(int32_t n, const int32_t *__restri
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double s[1] = {0.0};
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBQ) {
-        const double ui = bd[i] * row_apply(col, val, rowptr[i], rowptr[i + 1], (int)i,
-                                            [&](int q) { return fma(-alpha, v[q], y1[q]); });
+        const double ui = bd[i] * tq_row<L>(M, n, i, [&](int q) { return fma(-alpha, v[q], y1[q]); });
         y2[i] = fma(-alpha, v[i], y1[i]);
         u2[i] = ui;
         const double wi = fma(-alpha, u1[i], w[i]);
@@ -304,9 +322,9 @@ __global__ __launch_bounds__(TBQ) void k_tq_c(int64_t n, double *__restrict__ x,
 }
 
 // Kernel D of iteration (parity p).
-__global__ __launch_bounds__(TBQ) void k_tq_d(int32_t n, const int32_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col, const double *__restrict__ val,
-                                              const double *__restrict__ bd, const double *__restrict__ r0,
+template <int L>
+__global__ __launch_bounds__(TBQ) void k_tq_d(int32_t n, TqMat M, const double *__restrict__ bd,
+                                              const double *__restrict__ r0,
                                               const double *__restrict__ w, const double *__restrict__ y2,
                                               const double *__restrict__ u2, double *__restrict__ y1,
                                               double *__restrict__ u1, double *__restrict__ v, TqState *st, int p,
@@ -322,8 +340,7 @@ __global__ __launch_bounds__(TBQ) void k_tq_d(int32_t n, const int32_t *__restri
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double s[1] = {0.0};
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBQ) {
-        const double ui = bd[i] * row_apply(col, val, rowptr[i], rowptr[i + 1], (int)i,
-                                            [&](int q) { return fma(beta, y2[q], w[q]); });
+        const double ui = bd[i] * tq_row<L>(M, n, i, [&](int q) { return fma(beta, y2[q], w[q]); });
         y1[i] = fma(beta, y2[i], w[i]);
         u1[i] = ui;
         const double vi = fma(beta, fma(beta, v[i], u2[i]), ui);
@@ -357,7 +374,7 @@ struct TqCache {
     EventRef poll_ev[kMaxLookahead];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void *gkey[9] = {};
+    const void *gkey[11] = {};
     int32_t gK = 0;
 };
 
@@ -473,6 +490,13 @@ extern "C" apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b
         int64_t pb;
         tq_grid(n, &G, &pb);
         const int x0z = opts.x0_is_zero ? 1 : 0;
+        // products on the sliced-diagonal copy when that is the matrix's schedule
+        int lw = 0;  // slot width of the sliced-diagonal copy, 0: CSR
+        if (A->cfg.schedule == APCG_SPMV_SDIA) {
+            if ((s = prepare_sdia(A, st))) return s;
+            lw = A->sdia_mp;
+        }
+        const TqMat M{A->rowptr, A->col, A->val, A->sdia_off, A->sdia_msk, A->sdia_val, A->sdia_u};
         auto sync_if = [&]() -> apcg_status {
             if (host_check) {
                 g_counters.host_syncs++;
@@ -487,17 +511,21 @@ extern "C" apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b
         APCG_CHECK_LAUNCH("k_tq_init");
         hipLaunchKernelGGL(k_tq_init_final, dim3(1), dim3(64), 0, st, tc->st, (const double *)part, G, rtol, maxit);
         APCG_CHECK_LAUNCH("k_tq_init_final");
-        hipLaunchKernelGGL(k_tq_init_product, dim3(G), dim3(TBQ), 0, st, A->n, A->rowptr, A->col, A->val,
-                           (const double *)bd, (const double *)r0, (const double *)y1, u1, v,
-                           (const TqState *)tc->st, part, pb);
-        APCG_CHECK_LAUNCH("k_tq_init_product");
+        {
+            auto f = lw == 8 ? k_tq_init_product<8> : lw == 16 ? k_tq_init_product<16>
+                   : lw == 32 ? k_tq_init_product<32> : k_tq_init_product<0>;
+            hipLaunchKernelGGL(f, dim3(G), dim3(TBQ), 0, st, A->n, M, (const double *)bd, (const double *)r0,
+                               (const double *)y1, u1, v, (const TqState *)tc->st, part, pb);
+            APCG_CHECK_LAUNCH("k_tq_init_product");
+        }
+        auto fa = lw == 8 ? k_tq_a<8> : lw == 16 ? k_tq_a<16> : lw == 32 ? k_tq_a<32> : k_tq_a<0>;
+        auto fd = lw == 8 ? k_tq_d<8> : lw == 16 ? k_tq_d<16> : lw == 32 ? k_tq_d<32> : k_tq_d<0>;
         if ((s = sync_if())) return s;
 
         auto iteration = [&](int j) -> apcg_status {
             const int p = j & 1;
-            hipLaunchKernelGGL(k_tq_a, dim3(G), dim3(TBQ), 0, st, A->n, A->rowptr, A->col, A->val,
-                               (const double *)bd, (const double *)y1, (const double *)v, (const double *)u1, y2, u2,
-                               w, d, tc->st, p, part, pb);
+            hipLaunchKernelGGL(fa, dim3(G), dim3(TBQ), 0, st, A->n, M, (const double *)bd, (const double *)y1,
+                               (const double *)v, (const double *)u1, y2, u2, w, d, tc->st, p, part, pb);
             APCG_CHECK_LAUNCH("k_tq_a");
             apcg_status e;
             if ((e = sync_if())) return e;
@@ -509,18 +537,18 @@ extern "C" apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b
                                (const double *)r0, tc->st, p, part, pb);
             APCG_CHECK_LAUNCH("k_tq_c");
             if ((e = sync_if())) return e;
-            hipLaunchKernelGGL(k_tq_d, dim3(G), dim3(TBQ), 0, st, A->n, A->rowptr, A->col, A->val,
-                               (const double *)bd, (const double *)r0, (const double *)w, (const double *)y2,
-                               (const double *)u2, y1, u1, v, tc->st, p, part, pb);
+            hipLaunchKernelGGL(fd, dim3(G), dim3(TBQ), 0, st, A->n, M, (const double *)bd, (const double *)r0,
+                               (const double *)w, (const double *)y2, (const double *)u2, y1, u1, v, tc->st, p, part,
+                               pb);
             APCG_CHECK_LAUNCH("k_tq_d");
             return sync_if();
         };
 
         if (maxit > 0) {
             if (opts.mode == APCG_MODE_GRAPH) {
-                const void *key[9] = {(const void *)(uintptr_t)A->uid, A->rowptr, A->col, A->val, x->d, tc->ws,
-                                      (const void *)ctx->partials, (const void *)(intptr_t)n,
-                                      (const void *)(intptr_t)opts.pc};
+                const void *key[11] = {(const void *)(uintptr_t)A->uid, A->rowptr, A->col, A->val, x->d, tc->ws,
+                                       (const void *)ctx->partials, (const void *)(intptr_t)n,
+                                       (const void *)(intptr_t)opts.pc, (const void *)(intptr_t)lw, A->sdia_val};
                 if (!tc->exec || tc->gK != K || memcmp(key, tc->gkey, sizeof key) != 0) {
                     if (tc->exec) {
                         EventRef ev = event_get(dev);

@@ -34,10 +34,12 @@ def ctx(apcg):
     apcg.apcg_ctx_destroy(c)
 
 
-def tfqmr_gpu(apcg, ctx, A, b, rtol, maxit, x0=None, **opt):
+def tfqmr_gpu(apcg, ctx, A, b, rtol, maxit, x0=None, spmv=None, **opt):
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
     dA, db = DeviceCSR(A), DeviceVec(b)
+    if spmv is not None:
+        apcg.apcg_mat_set_spmv_config(dA.h, *spmv)
     dx = DeviceVec(np.zeros(A.n) if x0 is None else x0)
     if x0 is None:
         opt.setdefault("x0_is_zero", 1)
@@ -146,3 +148,22 @@ def test_tfqmr_large_twenty_iterations(apcg, ctx):
     ref = oracle.tfqmr(A, b, rtol=0.0, maxit=20)
     res, x = tfqmr_gpu(apcg, ctx, A, b, 0.0, 20)
     assert res["iterations"] == 20 and rel(x, ref.x) <= 1e-10
+
+
+@pytest.mark.parametrize("which", ["convdiff2d", "convdiff3d", "box27", "diffusion3d"])
+def test_tfqmr_sliced_diagonals_bitwise(apcg, ctx, which):
+    """With the matrix on the sliced-diagonal schedule the products read the
+    sliced-diagonal copy (8, 16 or 32 offset slots per slice); every row
+    still adds its entries in column order with one FMA each, so the solve is
+    bit for bit the CSR one, converged and at 20 iterations."""
+    A, b = system(which, 76)
+    for rtol, maxit in ((1e-10, 5000), (0.0, 20)):
+        print(f"case tfqmr-sdia {which} rtol={rtol}", flush=True)
+        r_csr, x_csr = tfqmr_gpu(apcg, ctx, A, b, rtol, maxit)
+        r_sd, x_sd = tfqmr_gpu(apcg, ctx, A, b, rtol, maxit, spmv=(1, 256, 0, apcg.APCG_SPMV_SDIA))
+        assert r_sd == r_csr
+        assert np.array_equal(x_sd, x_csr)
+    ref = oracle.tfqmr(A, b, rtol=1e-10, maxit=5000)
+    res, x = tfqmr_gpu(apcg, ctx, A, b, 1e-10, 5000, spmv=(1, 256, 0, apcg.APCG_SPMV_SDIA))
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
+    assert rel(x, ref.x) <= 1e-9
