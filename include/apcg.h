@@ -257,8 +257,9 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       row), so every load of a column index or value is one coalesced
  *       512-byte access.  The copy (12 bytes per stored entry) is allocated
  *       on first use and refilled from the CSR arrays at the start of every
- *       solve, so values may change between solves; MatMult uses the
- *       row-group kernel for this schedule.
+ *       solve, so values may change between solves.  A lone MatMult
+ *       reads the CSR arrays with row groups (this configuration's block
+ *       size and grid, lanes per row from the mean row length).
  *   schedule APCG_SPMV_SDIA (PCG solves): sliced diagonals.  The rows of
  *       a 64-row slice share one sorted list of column offsets
  *       (column - row); a 64-bit mask per offset marks the rows that hold
@@ -274,7 +275,8 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       otherwise.  Selecting it copies the column indices to the host once
  *       (synchronously) and snapshots the pattern: the columns must not
  *       change afterwards (values may, they are refilled at the start of
- *       every solve).  MatMult uses the row-group kernel for this schedule.
+ *       every solve).  A lone MatMult reads the CSR arrays, as for
+ *       APCG_SPMV_SELL.
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so
@@ -388,7 +390,10 @@ apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, dou
  * ref_norm (||B (b - A x0)||).  Breakdowns: r0.v = 0 (the denominator of
  * alpha) -> APCG_SOLVE_BREAKDOWN_PAP, r0.w = 0 (that of beta) ->
  * APCG_SOLVE_BREAKDOWN_RZ.  Workspace: 9 n doubles per context, kept
- * between solves. */
+ * between solves.  The products read the matrix's sliced-diagonal copy when
+ * its pattern allows one (see APCG_SPMV_SDIA; the first such solve of a
+ * matrix copies the pattern to the host once, synchronously), else the CSR
+ * arrays; both add every row's entries in column order, bitwise alike. */
 apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                                  const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
 

@@ -152,10 +152,10 @@ __global__ __launch_bounds__(TB) void k_spmv_stream(int32_t n, const int32_t *__
 }
 
 template <int TB>
-apcg_status spmv_tb(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
-    const int lpr = A->cfg.lanes_per_row;
+apcg_status spmv_tb(hipStream_t s, const apcg_mat_s *A, const apcg_spmv_config &cfg, const double *x, double *y) {
+    const int lpr = cfg.lanes_per_row;
     const int64_t rpp = TB / lpr;
-    const int G = normalise_blocks(A->cfg.blocks, (A->n + rpp - 1) / rpp);
+    const int G = normalise_blocks(cfg.blocks, (A->n + rpp - 1) / rpp);
     int32_t rpb = (int32_t)((A->n + G - 1) / G);
     if (rpb < 1) rpb = 1;
 #define APCG_SPMV_CASE(L)                                                                          \
@@ -253,12 +253,14 @@ apcg_status launch_scalar_set(hipStream_t s, double *out, double v) {
     return APCG_SUCCESS;
 }
 
-apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
-    if (A->n == 0) return APCG_SUCCESS;
-    if (A->cfg.schedule == APCG_SPMV_STREAM && stream_fits(A, A->cfg.block_size)) {
-        const int tb = A->cfg.block_size;
+// y = A x with configuration cfg (the matrix's own, or the CSR one chosen
+// for a lone product on a sliced schedule).
+static apcg_status spmv_with(hipStream_t s, const apcg_mat_s *A, const apcg_spmv_config &cfg, const double *x,
+                             double *y) {
+    if (cfg.schedule == APCG_SPMV_STREAM && stream_fits(A, cfg.block_size)) {
+        const int tb = cfg.block_size;
         const int64_t nchunks = ((int64_t)A->n + tb - 1) / tb;
-        const int G = normalise_blocks(A->cfg.blocks, nchunks);
+        const int G = normalise_blocks(cfg.blocks, nchunks);
         const int32_t cpb = (int32_t)std::max<int64_t>(1, (nchunks + G - 1) / G);
         const int32_t lds_nnz = (int32_t)std::max<int64_t>(2, ((A->max_block_nnz[tb == 512 ? 1 : 0] + 1) / 2) * 2);
         const size_t lds = (size_t)lds_nnz * (sizeof(double) + sizeof(int32_t));
@@ -271,8 +273,22 @@ apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, dou
         APCG_CHECK_LAUNCH("k_spmv_stream");
         return APCG_SUCCESS;
     }
-    if (A->cfg.block_size == 512) return spmv_tb<512>(s, A, x, y);
-    return spmv_tb<256>(s, A, x, y);
+    if (cfg.block_size == 512) return spmv_tb<512>(s, A, cfg, x, y);
+    return spmv_tb<256>(s, A, cfg, x, y);
+}
+
+apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
+    if (A->n == 0) return APCG_SUCCESS;
+    if (A->cfg.schedule == APCG_SPMV_SELL || A->cfg.schedule == APCG_SPMV_SDIA) {
+        // The sliced copies are refilled per solve, not per product: a lone
+        // product reads the CSR arrays with row groups of the configured
+        // block size and grid, lanes per row from the mean row length.
+        const double mean = (double)A->nnz / (double)A->n;
+        const int lpr = mean <= 8 ? 1 : mean <= 16 ? 2 : mean <= 32 ? 4 : mean <= 64 ? 8 : 16;
+        const apcg_spmv_config cfg{lpr, A->cfg.block_size, A->cfg.blocks, APCG_SPMV_ROWGROUP};
+        return spmv_with(s, A, cfg, x, y);
+    }
+    return spmv_with(s, A, A->cfg, x, y);
 }
 
 }  // namespace apcg

@@ -92,7 +92,7 @@ __device__ __forceinline__ double row_apply(const int32_t *__restrict__ col, con
 }
 
 // The matrix as the products read it: CSR, and the sliced-diagonal copy when
-// the matrix's SpMV schedule is APCG_SPMV_SDIA (then L = its slot width).
+// the pattern has one (then L = its slot width).
 struct TqMat {
     const int32_t *rowptr, *col;
     const double *val;
@@ -490,9 +490,12 @@ extern "C" apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b
         int64_t pb;
         tq_grid(n, &G, &pb);
         const int x0z = opts.x0_is_zero ? 1 : 0;
-        // products on the sliced-diagonal copy when that is the matrix's schedule
+        // products on the sliced-diagonal copy whenever the pattern allows it
+        // (the analysis is a one-time host pass per matrix; the sums are
+        // bitwise those of the CSR rows)
         int lw = 0;  // slot width of the sliced-diagonal copy, 0: CSR
-        if (A->cfg.schedule == APCG_SPMV_SDIA) {
+        if ((s = sdia_analyse(A))) return s;
+        if (A->sdia_state == 1) {
             if ((s = prepare_sdia(A, st))) return s;
             lw = A->sdia_mp;
         }
