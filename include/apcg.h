@@ -144,6 +144,56 @@ apcg_status apcg_ctx_join(apcg_ctx parent, int32_t n, int32_t mode, apcg_ctx *ch
 apcg_status apcg_ctx_get_stream_type(apcg_ctx ctx, int32_t *stream_type);
 
 /* ---------------------------------------------------------------------- */
+/* Dependency marking on arbitrary objects (Section 3.1.2)                 */
+/* ---------------------------------------------------------------------- */
+
+/* Access modes of a marked operation. */
+#define APCG_ACCESS_READ 1
+#define APCG_ACCESS_WRITE 2
+#define APCG_ACCESS_READ_WRITE 3
+
+/* *stream receives the context's hipStream_t (as void *), for enqueuing the
+ * caller's own work between apcg_mark_intent_begin and _end.  The stream
+ * stays owned by the library: never destroy it, and never use it after the
+ * context is destroyed. */
+apcg_status apcg_ctx_get_stream(apcg_ctx ctx, void **stream);
+
+/* Registers the device memory region [ptr, ptr + bytes) of `device` as an
+ * object for dependency marking and returns its id (never 0, never reused).
+ * Registering the same start pointer again with the same size returns the
+ * existing id; with another size, or for a region that overlaps a
+ * registered one, APCG_ERR_INVALID_ARG.  The library never dereferences
+ * ptr.  A region registered here and a vector wrapping the same memory are
+ * different objects for ordering; mark the vector through its own id. */
+apcg_status apcg_memory_register(int32_t device, const void *ptr, int64_t bytes, uint64_t *id);
+
+/* Finds the registered region of `device` containing ptr: *id and (if not
+ * NULL) *start and *bytes; APCG_ERR_INVALID_ARG when there is none. */
+apcg_status apcg_memory_lookup(int32_t device, const void *ptr, uint64_t *id, const void **start, int64_t *bytes);
+
+/* Forgets a registered region (the caller's memory is untouched; pending
+ * work on it keeps its own ordering). */
+apcg_status apcg_memory_unregister(uint64_t id);
+
+/* Ids of library objects, for marking the caller's own work on them. */
+apcg_status apcg_vec_get_id(apcg_vec v, uint64_t *id);
+apcg_status apcg_scalar_get_id(apcg_scalar s, uint64_t *id);
+apcg_status apcg_mat_get_id(apcg_mat A, uint64_t *id);
+
+/* Bracket the caller's own work on object `id` enqueued on ctx's stream
+ * (Section 3.1.2, MarkIntent).  _begin makes ctx's stream wait (on the
+ * device, no host wait) for the conflicting earlier accesses of other
+ * contexts: a write waits for the last write and every read since it, a
+ * read for the last write; reads are not ordered among themselves; earlier
+ * operations of the same context are ordered by the stream.  _end records
+ * the completion point of this access.  The begin/end pair must use the
+ * same ctx, id and mode; description (may be NULL) names the operation in
+ * error messages.  On a globally blocking context, _begin waits for the
+ * whole device and _end for the stream. */
+apcg_status apcg_mark_intent_begin(apcg_ctx ctx, uint64_t id, int32_t mode, const char *description);
+apcg_status apcg_mark_intent_end(apcg_ctx ctx, uint64_t id, int32_t mode, const char *description);
+
+/* ---------------------------------------------------------------------- */
 /* Device scalars: futures of one double (Sections 3.2 and 3.2.2)          */
 /* ---------------------------------------------------------------------- */
 
@@ -176,6 +226,59 @@ apcg_status apcg_scalar_get(apcg_scalar s, double *host_value);
 #define APCG_SCALAR_MUL 6   /* out = a * b  */
 #define APCG_SCALAR_DIV 7   /* out = a / b  */
 apcg_status apcg_scalar_op(int32_t opcode, apcg_scalar out, apcg_scalar a, apcg_scalar b, apcg_ctx ctx);
+
+/* Scalar expressions (Section 3.2.1: expression templates, Eval, CSE,
+ * constant folding; MultiEval: several results of one program).
+ * A program is a postfix token list over up to 16 input scalars producing
+ * up to 16 output scalars: INPUT pushes input `arg`, CONST pushes `value`,
+ * a unary op replaces the top, a binary op pops b then a and pushes a op b,
+ * OUTPUT pops the top into output `arg`.  The stack must be empty at the
+ * end and every output written exactly once. */
+#define APCG_EXPR_INPUT 1
+#define APCG_EXPR_CONST 2
+#define APCG_EXPR_NEG 10
+#define APCG_EXPR_RECIP 11 /* 1 / a */
+#define APCG_EXPR_SQRT 12
+#define APCG_EXPR_ABS 13
+#define APCG_EXPR_EXP 14
+#define APCG_EXPR_LOG 15
+#define APCG_EXPR_SIN 16
+#define APCG_EXPR_COS 17
+#define APCG_EXPR_ADD 20
+#define APCG_EXPR_SUB 21
+#define APCG_EXPR_MUL 22
+#define APCG_EXPR_DIV 23
+#define APCG_EXPR_MIN 24 /* IEEE minNum: a NaN operand yields the other */
+#define APCG_EXPR_MAX 25
+#define APCG_EXPR_OUTPUT 30
+typedef struct apcg_expr_token {
+    int32_t op;
+    int32_t arg;  /* input or output index */
+    double value; /* CONST */
+} apcg_expr_token;
+typedef struct apcg_expr_s *apcg_expr;
+
+/* Eval: compiles a program (host only, no device work) into a register
+ * program: identical subexpressions are computed once (within and across
+ * outputs), subexpressions of constants are folded when the operation is
+ * correctly rounded (everything but EXP/LOG/SIN/COS), and only rewrites
+ * that are exact in IEEE double are applied (x*1, 1*x, x/1, x-0, x+(-0),
+ * -(-x)).  At most 256 tokens and 128 instructions; malformed programs are
+ * APCG_ERR_INVALID_ARG. */
+apcg_status apcg_expr_compile(const apcg_expr_token *prog, int32_t ntokens, int32_t ninputs, int32_t noutputs,
+                              apcg_expr *out);
+
+/* Instructions of the compiled program, constants folded and repeated
+ * subexpressions shared during compilation (any pointer may be NULL). */
+apcg_status apcg_expr_stats(apcg_expr e, int32_t *instructions, int32_t *folded, int32_t *shared);
+
+/* Execute: one single-workgroup kernel on ctx's stream reads the inputs
+ * and writes every output (ordered like any library operation: inputs
+ * read, outputs written; a scalar may be both).  The scalars must live on
+ * ctx's device.  inputs/outputs: arrays of ninputs / noutputs handles. */
+apcg_status apcg_expr_execute(apcg_expr e, apcg_ctx ctx, const apcg_scalar *inputs, const apcg_scalar *outputs);
+
+apcg_status apcg_expr_destroy(apcg_expr e);
 
 /* ---------------------------------------------------------------------- */
 /* Vectors (borrowed device memory)                                        */

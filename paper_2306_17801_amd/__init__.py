@@ -162,6 +162,87 @@ def apcg_scalar_op(opcode: int, out, a, b=None, ctx=None) -> None:
     check("apcg_scalar_op", _L().apcg_scalar_op(opcode, _h(out), _h(a), _h(b), _h(ctx)))
 
 
+# ------------------------------------------------------ dependency marking
+
+def apcg_ctx_get_stream(ctx) -> int:
+    out = ctypes.c_void_p()
+    check("apcg_ctx_get_stream", _L().apcg_ctx_get_stream(_h(ctx), ctypes.byref(out)))
+    return out.value
+
+
+def apcg_memory_register(device: int, ptr: int, nbytes: int) -> int:
+    out = ctypes.c_uint64()
+    check("apcg_memory_register", _L().apcg_memory_register(device, ctypes.c_void_p(ptr), nbytes, ctypes.byref(out)))
+    return out.value
+
+
+def apcg_memory_lookup(device: int, ptr: int):
+    """(id, start, bytes) of the registered region holding ptr."""
+    i, st, nb = ctypes.c_uint64(), ctypes.c_void_p(), ctypes.c_int64()
+    check("apcg_memory_lookup", _L().apcg_memory_lookup(device, ctypes.c_void_p(ptr), ctypes.byref(i),
+                                                        ctypes.byref(st), ctypes.byref(nb)))
+    return i.value, st.value, nb.value
+
+
+def apcg_memory_unregister(mid: int) -> None:
+    check("apcg_memory_unregister", _L().apcg_memory_unregister(mid))
+
+
+def _get_id(fn, h) -> int:
+    out = ctypes.c_uint64()
+    check(fn, getattr(_L(), fn)(_h(h), ctypes.byref(out)))
+    return out.value
+
+
+def apcg_vec_get_id(v) -> int:
+    return _get_id("apcg_vec_get_id", v)
+
+
+def apcg_scalar_get_id(s) -> int:
+    return _get_id("apcg_scalar_get_id", s)
+
+
+def apcg_mat_get_id(A) -> int:
+    return _get_id("apcg_mat_get_id", A)
+
+
+def apcg_mark_intent_begin(ctx, mid: int, mode: int, description: str | None = None) -> None:
+    d = description.encode() if description else None
+    check("apcg_mark_intent_begin", _L().apcg_mark_intent_begin(_h(ctx), mid, mode, d))
+
+
+def apcg_mark_intent_end(ctx, mid: int, mode: int, description: str | None = None) -> None:
+    d = description.encode() if description else None
+    check("apcg_mark_intent_end", _L().apcg_mark_intent_end(_h(ctx), mid, mode, d))
+
+
+# ------------------------------------------------------ scalar expressions
+
+def apcg_expr_compile(tokens, ninputs: int, noutputs: int) -> int:
+    """tokens: sequence of (op, arg, value) postfix tokens."""
+    arr = (_capi.apcg_expr_token * len(tokens))(*[_capi.apcg_expr_token(int(o), int(a), float(v))
+                                                  for o, a, v in tokens])
+    out = ctypes.c_void_p()
+    check("apcg_expr_compile", _L().apcg_expr_compile(arr, len(tokens), ninputs, noutputs, ctypes.byref(out)))
+    return out.value
+
+
+def apcg_expr_stats(e) -> dict:
+    n, f, sh = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+    check("apcg_expr_stats", _L().apcg_expr_stats(_h(e), ctypes.byref(n), ctypes.byref(f), ctypes.byref(sh)))
+    return {"instructions": n.value, "folded": f.value, "shared": sh.value}
+
+
+def apcg_expr_execute(e, ctx, inputs, outputs) -> None:
+    ins = (ctypes.c_void_p * max(len(inputs), 1))(*[_h(i) for i in inputs])
+    outs = (ctypes.c_void_p * len(outputs))(*[_h(o) for o in outputs])
+    check("apcg_expr_execute", _L().apcg_expr_execute(_h(e), _h(ctx), ins, outs))
+
+
+def apcg_expr_destroy(e) -> None:
+    check("apcg_expr_destroy", _L().apcg_expr_destroy(_h(e)))
+
+
 # ------------------------------------------------------------------ vectors
 
 def apcg_vec_wrap(tensor) -> int:

@@ -106,10 +106,49 @@ class apcg_device_props(ctypes.Structure):
                 ("l2_bytes", c_i32), ("lds_bytes_per_block", c_i32), ("reserved", c_i32 * 7)]
 
 
+APCG_ACCESS_READ = 1
+APCG_ACCESS_WRITE = 2
+APCG_ACCESS_READ_WRITE = 3
+APCG_EXPR_INPUT = 1
+APCG_EXPR_CONST = 2
+APCG_EXPR_NEG = 10
+APCG_EXPR_RECIP = 11
+APCG_EXPR_SQRT = 12
+APCG_EXPR_ABS = 13
+APCG_EXPR_EXP = 14
+APCG_EXPR_LOG = 15
+APCG_EXPR_SIN = 16
+APCG_EXPR_COS = 17
+APCG_EXPR_ADD = 20
+APCG_EXPR_SUB = 21
+APCG_EXPR_MUL = 22
+APCG_EXPR_DIV = 23
+APCG_EXPR_MIN = 24
+APCG_EXPR_MAX = 25
+APCG_EXPR_OUTPUT = 30
+
+
+class apcg_expr_token(ctypes.Structure):
+    _fields_ = [("op", c_i32), ("arg", c_i32), ("value", c_f64)]
+
+
 P = ctypes.POINTER
 # name -> argtypes (restype apcg_status unless listed in _RESTYPE)
 SIGNATURES = {
     "apcg_abi_version": [],
+    "apcg_ctx_get_stream": [c_vp, P(c_vp)],
+    "apcg_memory_register": [c_i32, c_vp, c_i64, P(ctypes.c_uint64)],
+    "apcg_memory_lookup": [c_i32, c_vp, P(ctypes.c_uint64), P(c_vp), P(c_i64)],
+    "apcg_memory_unregister": [ctypes.c_uint64],
+    "apcg_vec_get_id": [c_vp, P(ctypes.c_uint64)],
+    "apcg_scalar_get_id": [c_vp, P(ctypes.c_uint64)],
+    "apcg_mat_get_id": [c_vp, P(ctypes.c_uint64)],
+    "apcg_mark_intent_begin": [c_vp, ctypes.c_uint64, c_i32, ctypes.c_char_p],
+    "apcg_mark_intent_end": [c_vp, ctypes.c_uint64, c_i32, ctypes.c_char_p],
+    "apcg_expr_compile": [P(apcg_expr_token), c_i32, c_i32, c_i32, P(c_vp)],
+    "apcg_expr_stats": [c_vp, P(c_i32), P(c_i32), P(c_i32)],
+    "apcg_expr_execute": [c_vp, c_vp, P(c_vp), P(c_vp)],
+    "apcg_expr_destroy": [c_vp],
     "apcg_last_error": [],
     "apcg_device_count": [P(c_i32)],
     "apcg_device_props_get": [c_i32, P(apcg_device_props)],

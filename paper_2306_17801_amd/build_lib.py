@@ -7,7 +7,7 @@ import subprocess
 import sys
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-SOURCES = ["runtime.hip", "blas.hip", "pcg.hip", "batched.hip", "learn.hip", "fcg.hip", "batched_fcg.hip", "tfqmr.hip"]
+SOURCES = ["runtime.hip", "blas.hip", "pcg.hip", "batched.hip", "learn.hip", "fcg.hip", "batched_fcg.hip", "tfqmr.hip", "intent.hip", "expr.hip"]
 LIB = os.path.join(HERE, "libapcg.so")
 
 HIPCC_FLAGS = [

@@ -147,6 +147,7 @@ struct apcg_scalar_s {
     double *d = nullptr;  // slot in the device scalar pool
     int64_t slot = -1;
     apcg::Record rec;
+    uint64_t mark_id = 0;  // id for dependency marking, assigned on request
 };
 
 struct apcg_vec_s {
@@ -154,6 +155,7 @@ struct apcg_vec_s {
     double *d = nullptr;
     int64_t n = 0;
     apcg::Record rec;
+    uint64_t mark_id = 0;
 };
 
 struct apcg_mat_s {
@@ -190,6 +192,7 @@ struct apcg_mat_s {
     uint64_t *sdia_msk = nullptr;    // device [nslices * sdia_mp] row masks, padding 0
     double *sdia_val = nullptr;      // device [nslices * sdia_u * 64] values, absent entries 0
     apcg::Record rec;
+    uint64_t mark_id = 0;
 };
 
 struct apcg_info_s {
@@ -226,6 +229,10 @@ void learn_cache_release(uint64_t ctx_id, int device);  // learn.hip
 void fcg_cache_release(uint64_t ctx_id, int device);    // fcg.hip
 void bfcg_cache_release(uint64_t ctx_id, int device);   // batched_fcg.hip
 void tq_cache_release(uint64_t ctx_id, int device);     // tfqmr.hip
+// dependency-marking ids of library objects (intent.hip): an object's id
+// maps to its Record until the object is destroyed
+uint64_t intent_object_id(uint64_t *slot, int device, Record *rec);
+void intent_forget(uint64_t id);
 // Standardises X[B][16] in place with mean/std and writes the network's
 // coefficients C[B][9] (learn.hip); ordered on ctx's stream.
 apcg_status mlp_infer(apcg_ctx ctx, const float *params, const float *mean, const float *std, float *X, int32_t B,

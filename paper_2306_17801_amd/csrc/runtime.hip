@@ -577,6 +577,7 @@ apcg_status apcg_scalar_destroy(apcg_scalar s) {
     }
     int dev = s->device;
     int64_t slot = s->slot;
+    if (s->mark_id) intent_forget(s->mark_id);
     delete s;
     defer_release(std::move(deps), [dev, slot]() { scalar_slot_free(dev, slot); });
     reap();
@@ -672,6 +673,7 @@ apcg_status apcg_vec_destroy(apcg_vec v) {
         std::lock_guard<std::recursive_mutex> lk(g_mu);
         deps = record_deps(v->rec);
     }
+    if (v->mark_id) intent_forget(v->mark_id);
     delete v;
     defer_release(std::move(deps), []() {});
     reap();
@@ -896,6 +898,7 @@ apcg_status apcg_mat_destroy(apcg_mat A) {
     int32_t *smeta = A->sell_meta, *scol = A->sell_col, *doff = A->sdia_off;
     double *sval = A->sell_val, *dval = A->sdia_val;
     uint64_t *dmsk = A->sdia_msk;
+    if (A->mark_id) intent_forget(A->mark_id);
     delete A;
     defer_release(std::move(deps), [dev, smeta, scol, sval, doff, dmsk, dval]() {
         if (smeta || scol || sval || doff || dmsk || dval) {
