@@ -188,6 +188,7 @@ struct apcg_mat_s {
     const char *sdia_reason = "";    // why not applicable
     int32_t sdia_u = 0;              // value slots per slice (largest offset count of any slice)
     int32_t sdia_mp = 0;             // offset / mask slots per slice: 8, 16 or 32 (>= sdia_u)
+    int32_t sdia_ps = 0;             // plane stride in slices for plane marching (0: none)
     int32_t *sdia_off = nullptr;     // device [nslices * sdia_mp] offsets, padding 0
     uint64_t *sdia_msk = nullptr;    // device [nslices * sdia_mp] row masks, padding 0
     double *sdia_val = nullptr;      // device [nslices * sdia_u * 64] values, absent entries 0

@@ -34,6 +34,7 @@
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
+#include <map>
 #include <cmath>
 #include <cstring>
 
@@ -589,6 +590,102 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
     dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
 }
 
+// Sliced diagonals, plane marching (lanes_per_row = seg > 1 selects it when
+// the pattern has a plane stride): the slices form Ps columns (Ps = the
+// pattern's plane stride in slices, i.e. the offset +-64 Ps is a
+// neighbouring plane); task (segment g, column c) walks slices
+// s_j = j Ps + c for j in [g seg, (g+1) seg).  The window of offset +64 Ps
+// of slice s_j is slice s_{j+1}'s own window: loaded once, it serves as the
+// +plane neighbour now and as the own window (and then the -plane
+// neighbour) of the next slices, so those windows are neither gathered
+// through the cache twice nor dependent on the slice's offset loads.  Other
+// offsets are gathered as in k_pcg_product_sdia; the sums are bitwise the
+// same.  shape = U | seg << 8 | Ps << 16.  Tasks are spread over the grid
+// (task += waves in the grid).
+template <int TB, int W>
+__global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const int32_t *__restrict__ soff,
+                                                               const int32_t *__restrict__ smask_words,
+                                                               const double *__restrict__ sval,
+                                                               const double *__restrict__ z,
+                                                               const double *__restrict__ pold,
+                                                               double *__restrict__ pnew, double *__restrict__ w,
+                                                               SolveState *st, const double *part_res, int g_res,
+                                                               double *part_delta, int32_t /*unused*/, int parity,
+                                                               int tune, int32_t shape) {
+    const uint64_t *smask = reinterpret_cast<const uint64_t *>(smask_words);
+    const int U = shape & 0xff, seg = (shape >> 8) & 0xff, Ps = (shape >> 16) & 0xffff;
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int nsl = (n + 63) / 64;
+    const int nz = (nsl + Ps - 1) / Ps;  // planes (the last may be partial)
+    const int nseg = (nz + seg - 1) / seg;
+    const int ntask = Ps * nseg;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (TB / 64);
+    const int up = 64 * Ps;
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    double acc = 0.0;
+    for (int task = lb * (TB / 64) + wave; task < ntask; task += nwaves) {
+        const int c = task % Ps, g = task / Ps;
+        const int j0 = g * seg, j1 = min(nz, j0 + seg);
+        // own and -plane windows of the first slice
+        int row = (j0 * Ps + c) * 64 + lane;
+        int rc = min(row, n - 1);
+        double zo = z[rc], po = pold[rc];
+        const int rp = max(rc - up, 0);
+        double zm = z[rp], pm = pold[rp];
+        for (int j = j0; j < j1; ++j) {
+            const int sl = j * Ps + c;
+            if (sl >= nsl) break;  // the partial last plane
+            row = sl * 64 + lane;
+            rc = min(row, n - 1);
+            const int32_t *o = soff + (int64_t)sl * W;
+            const uint64_t *m = smask + (int64_t)sl * W;
+            const double *v = sval + (int64_t)sl * U * 64 + lane;
+            const int rn = min(rc + up, n - 1);
+            const double zn = z[rn], pn = pold[rn];  // +plane window = the next slice's own
+            int oc[W];
+            uint64_t mc[W];
+            double ac[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                oc[k] = o[k];
+                mc[k] = m[k];
+                ac[k] = __builtin_nontemporal_load(v + (int64_t)min(k, U - 1) * 64);
+            }
+            double zj[W], pj[W];
+            bool in[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                in[k] = (mc[k] >> lane) & 1ull;
+                const bool carried = oc[k] == up || oc[k] == -up || oc[k] == 0;
+                const int jx = (in[k] && !carried) ? row + oc[k] : rc;
+                const double zg = carried ? 0.0 : z[jx], pg = carried ? 0.0 : pold[jx];
+                zj[k] = oc[k] == up ? zn : oc[k] == -up ? zm : oc[k] == 0 ? zo : zg;
+                pj[k] = oc[k] == up ? pn : oc[k] == -up ? pm : oc[k] == 0 ? po : pg;
+            }
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
+                const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
+                sum = in[k] ? t : sum;
+            }
+            if (row < n) {
+                const double pi = pdir(zo, beta, po);
+                pnew[row] = pi;
+                w[row] = sum;
+                acc = fma(pi, sum, acc);
+            }
+            zm = zo;
+            pm = po;
+            zo = zn;
+            po = pn;
+        }
+    }
+    double v[1] = {acc};
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
+}
+
 // Fills the sliced-diagonal value copy from the CSR values: thread
 // (slice, lane) walks its row's entries in order, one per set mask bit, and
 // writes 0 to the slots its row does not hold.
@@ -731,9 +828,15 @@ ProductFn stream_fn(int32_t lds_nnz) {
     return k_pcg_product_stream<TB, 21>;  // 21 * 256 >= kStreamMaxNnz
 }
 
-ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw, int32_t sdia_mp) {
+ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw, int32_t sdia_mp,
+                     int32_t sdia_ps) {
     if (cfg.schedule == APCG_SPMV_SDIA) {
         const bool b512 = cfg.block_size == 512;
+        if (cfg.lanes_per_row > 1 && sdia_ps > 0) {  // plane marching
+            if (sdia_mp == 8) return b512 ? k_pcg_product_sdia_march<512, 8> : k_pcg_product_sdia_march<256, 8>;
+            if (sdia_mp == 16) return b512 ? k_pcg_product_sdia_march<512, 16> : k_pcg_product_sdia_march<256, 16>;
+            return b512 ? k_pcg_product_sdia_march<512, 32> : k_pcg_product_sdia_march<256, 32>;
+        }
         if (sdia_mp == 8) return b512 ? k_pcg_product_sdia<512, 8> : k_pcg_product_sdia<256, 8>;
         if (sdia_mp == 16) return b512 ? k_pcg_product_sdia<512, 16> : k_pcg_product_sdia<256, 16>;
         return b512 ? k_pcg_product_sdia<512, 32> : k_pcg_product_sdia<256, 32>;
@@ -793,9 +896,17 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         pl->a2 = A->sdia_val;
         const int64_t nsl = ((int64_t)A->n + 63) / 64;
         const int64_t waves = pl->tb / 64;
-        pl->g_prod = normalise_blocks(cfg.blocks, (nsl + waves - 1) / waves);
-        pl->rpb = (int32_t)std::max<int64_t>(1, (nsl + pl->g_prod - 1) / pl->g_prod);
-        pl->lds_nnz = A->sdia_u;  // the kernel's value slots per slice
+        if (cfg.lanes_per_row > 1 && A->sdia_ps > 0) {  // plane marching: seg planes per task
+            const int64_t seg = cfg.lanes_per_row, ps = A->sdia_ps;
+            const int64_t nz = (nsl + ps - 1) / ps, tasks = ps * ((nz + seg - 1) / seg);
+            pl->g_prod = normalise_blocks(kMaxBlocks, (tasks + waves - 1) / waves);
+            pl->rpb = 0;
+            pl->lds_nnz = A->sdia_u | (int32_t)(seg << 8) | (int32_t)(ps << 16);
+        } else {
+            pl->g_prod = normalise_blocks(cfg.blocks, (nsl + waves - 1) / waves);
+            pl->rpb = (int32_t)std::max<int64_t>(1, (nsl + pl->g_prod - 1) / pl->g_prod);
+            pl->lds_nnz = A->sdia_u;  // the kernel's value slots per slice
+        }
     } else if (cfg.schedule == APCG_SPMV_SELL) {
         if (!A->sell_meta) return set_error(APCG_ERR_INVALID_STATE, "sliced copy not prepared");
         pl->a0 = A->sell_meta;
@@ -818,7 +929,7 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         int64_t rpb = ((int64_t)A->n + pl->g_prod - 1) / pl->g_prod;
         pl->rpb = (int32_t)std::max<int64_t>(1, rpb);
     }
-    pl->prod = product_fn(cfg, pl->lds_nnz, A->sell_maxw, A->sdia_mp);
+    pl->prod = product_fn(cfg, pl->lds_nnz, A->sell_maxw, A->sdia_mp, A->sdia_ps);
     if (!pl->prod) return set_error(APCG_ERR_INVALID_ARG, "unsupported lanes_per_row");
     vector_grid(A->n, &pl->g_vec, &pl->pb_vec);
     return APCG_SUCCESS;
@@ -894,6 +1005,17 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
         const int64_t sell_bytes = 12 * (A->sell_entries >= 0 ? A->sell_entries : nnz);
         if (8 * slots > sell_bytes) return reject("the padded value copy would exceed the sliced copy");
         const int32_t MP = U <= 8 ? 8 : U <= 16 ? 16 : 32;
+        // plane stride for marching: the largest offset o = 64 Ps (Ps < 65536)
+        // present with both signs in at least half of the slices
+        std::map<int32_t, int64_t> both;
+        for (int64_t sl = 0; sl < nsl; ++sl) {
+            slice_offsets(sl);
+            for (int32_t o : offs)
+                if (o > 0 && o % 64 == 0 && o / 64 < 65536 && std::binary_search(offs.begin(), offs.end(), -o)) ++both[o];
+        }
+        int32_t ps = 0;
+        for (auto &kv : both)
+            if (2 * kv.second >= nsl) ps = kv.first / 64;
         std::vector<int32_t> off_h((size_t)(nsl * MP), 0);
         std::vector<uint64_t> msk_h((size_t)(nsl * MP), 0);
         for (int64_t sl = 0; sl < nsl; ++sl) {
@@ -913,6 +1035,7 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
         APCG_HIP(hipMemcpy(A->sdia_msk, msk_h.data(), sizeof(uint64_t) * nsl * MP, hipMemcpyHostToDevice));
         A->sdia_u = U;
         A->sdia_mp = MP;
+        A->sdia_ps = ps;
         A->sdia_state = 1;
         return APCG_SUCCESS;
     } catch (const std::bad_alloc &) {
@@ -1293,20 +1416,27 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         const bool sdia_ok = A->sdia_state == 1;
         if (sdia_ok && (s = prepare_sdia(A, st))) return s;
         // -2: sliced diagonals, -1: the sliced schedule, 0: the staged one
-        for (int lpr : {-2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
+        // -3: sliced diagonals with plane marching (the inner value is the
+        // number of planes per task, not a grid)
+        for (int lpr : {-3, -2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
             if (lpr == -1 && !sell_ok) continue;
             if (lpr == -2 && !sdia_ok) continue;
+            if (lpr == -3 && !(sdia_ok && A->sdia_ps > 0)) continue;
             for (int tb : {256, 512}) {
                 if (lpr == 0 && !stream_fits(A, tb)) continue;
                 for (int blocks : {256, 512, 1024, 2048, 4096, 8192}) {
-                    apcg_spmv_config cfg = lpr == -2  ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SDIA}
+                    if (lpr == -3 && blocks > 2048) continue;
+                    const int seg = blocks / 256;  // 1, 2, 4, 8 -> 2, 4, 8 planes (1 is skipped)
+                    if (lpr == -3 && seg < 2) continue;
+                    apcg_spmv_config cfg = lpr == -3  ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_SDIA}
+                                           : lpr == -2 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SDIA}
                                            : lpr == -1 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}
                                            : lpr == 0 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_STREAM}
                                                       : apcg_spmv_config{lpr, tb, blocks, APCG_SPMV_ROWGROUP};
                     Plan pl;
                     if ((s = make_plan(A, cfg, &pl))) return s;
-                    if (pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller candidate
+                    if (lpr != -3 && pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller one
                     // one product + update pair, both with their partial reductions
                     for (int w = 0; w < 2; ++w) {
                         if ((s = launch_product(st, pl, bf, 1, 1))) return s;
