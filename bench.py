@@ -667,7 +667,7 @@ def main():
                 and tr.get("spmv_config") == cfg_chosen):
             traffic = tr.get("bytes_per_launch")
     kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell",
-             apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia"}.get(
+             apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia" + ("_march" if cfg_now["lanes_per_row"] > 1 else "")}.get(
         cfg_now["schedule"], "k_pcg_product") + f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)"
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),

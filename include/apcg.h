@@ -379,7 +379,12 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       (synchronously) and snapshots the pattern: the columns must not
  *       change afterwards (values may, they are refilled at the start of
  *       every solve).  A lone MatMult reads the CSR arrays, as for
- *       APCG_SPMV_SELL.
+ *       APCG_SPMV_SELL.  lanes_per_row > 1 selects plane marching when the
+ *       pattern has a plane stride (an offset 64 Ps, Ps < 65536 slices,
+ *       present with both signs in at least half of the slices): each
+ *       wavefront walks lanes_per_row slices one plane apart and carries the
+ *       +-plane windows between them instead of gathering them (blocks is
+ *       then ignored); without a plane stride it is the plain kernel.
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so
