@@ -668,7 +668,10 @@ def main():
             traffic = tr.get("bytes_per_launch")
     kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell",
              apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia" + ("_march" if cfg_now["lanes_per_row"] > 1 else "")}.get(
-        cfg_now["schedule"], "k_pcg_product") + f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)"
+        cfg_now["schedule"], "k_pcg_product") + (
+        f" (block {cfg_now['block_size']}, {cfg_now['lanes_per_row']} planes per task)"
+        if cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1
+        else f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)")
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "algorithmic_bytes_per_launch": prod_bytes,
