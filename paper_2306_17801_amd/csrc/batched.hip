@@ -96,6 +96,37 @@ __device__ __forceinline__ double row_product(const int32_t *__restrict__ col, c
     return sum;
 }
 
+// Row i of A p with p_j = z_j + beta pold_j (z = D^-1 r as stored by the
+// segmented schedule; the same rounded value as d_j r_j above, so the sums are
+// bitwise those of row_product).
+__device__ __forceinline__ double row_product_z(const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                int s, int e, int row, const double *__restrict__ z,
+                                                const double *__restrict__ pold, double beta) {
+    const int len = e - s;
+    double sum = 0.0;
+    if (len <= 8) {
+        int jj[8];
+        double aa[8], pj[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+            const bool in = q < len;
+            jj[q] = in ? col[s + q] : row;
+            aa[q] = in ? val[s + q] : 0.0;
+        }
+#pragma unroll
+        for (int q = 0; q < 8; ++q) pj[q] = fma(beta, pold[jj[q]], z[jj[q]]);
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+            if (q < len) sum = fma(aa[q], pj[q], sum);
+    } else {
+        for (int k = s; k < e; ++k) {
+            const int j = col[k];
+            sum = fma(val[k], fma(beta, pold[j], z[j]), sum);
+        }
+    }
+    return sum;
+}
+
 template <int TB>
 __device__ void solve_one(const BatchSys &S, double rtol, int32_t maxit, int x0_zero, int pc, int norm_pre,
                           apcg_solve_info *out, double *lds) {
@@ -345,7 +376,7 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
             const int64_t n = A[i]->n;
             hs[i] = BatchSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x[i]->d, nullptr, (int32_t)n, 0};
             hs[i].ws = reinterpret_cast<double *>(ws_total);  // offset for now
-            ws_total += ((5 * n + 63) / 64) * 64;
+            ws_total += ((6 * n + 63) / 64) * 64;  // r, dinv, p0, p1, w, z (z: segmented schedule only)
             // CG iterations grow like sqrt(condition) ~ n^(1/2) in 2D (n^(1/3) in 3D):
             // estimated cost = nnz * sqrt(n)
             cost[i] = (double)(A[i]->nnz + n) * std::sqrt((double)std::max<int64_t>(n, 1));
@@ -594,6 +625,7 @@ __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc,
             S.ws[2 * n + i] = 0.0;    // p[0]
             if (x0_zero) S.x[i] = 0.0;
             const double zi = di * ri;
+            S.ws[5 * n + i] = zi;     // z
             v[0] = zi * ri;
             if (norm_pre) {
                 const double zb = di * bi;
@@ -670,15 +702,15 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
         const double beta = P.st[s].beta;
         const BatchSys S = P.sys[s];
         const int64_t n = S.n;
-        const double *r = S.ws, *dinv = S.ws + n;
+        const double *z = S.ws + 5 * n;
         const double *pold = S.ws + (2 + ((parity + 1) & 1)) * n;
         double *pnew = S.ws + (2 + (parity & 1)) * n;
         double *w = S.ws + 4 * n;
         const int i = P.tile_row0[t] + threadIdx.x;
         double v[1] = {0.0};
         if (i < S.n) {
-            const double sum = row_product(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, dinv, r, pold, beta);
-            const double pi = pdir_b(dinv[i], r[i], beta, pold[i]);
+            const double sum = row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
+            const double pi = fma(beta, pold[i], z[i]);
             pnew[i] = pi;
             w[i] = sum;
             v[0] = pi * sum;
@@ -727,6 +759,7 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
             S.x[i] = xi;
             r[i] = ri;
             const double zi = dinv[i] * ri;
+            S.ws[5 * n + i] = zi;  // gathered by the next product
             v[0] = zi * ri;
             v[1] = norm_pre ? zi * zi : ri * ri;
         }
