@@ -69,32 +69,6 @@ static_assert(sizeof(FcgState) <= 512, "FCG state exceeds its allocation");
 
 __device__ __forceinline__ double pdir_f(double z, double beta, double pold) { return fma(beta, pold, z); }
 
-// sum_j a_ij u_j for row i; rows of up to 8 entries gather before adding.
-template <typename F>
-__device__ __forceinline__ double row_dot(const int32_t *__restrict__ col, const double *__restrict__ val, int s,
-                                          int e, int row, F u) {
-    const int len = e - s;
-    double sum = 0.0;
-    if (len <= 8) {
-        int jj[8];
-        double aa[8], uj[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const bool in = q < len;
-            jj[q] = in ? col[s + q] : row;
-            aa[q] = in ? val[s + q] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) uj[q] = u(jj[q]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (q < len) sum = fma(aa[q], uj[q], sum);
-    } else {
-        for (int k = s; k < e; ++k) sum = fma(val[k], u(col[k]), sum);
-    }
-    return sum;
-}
-
 __global__ __launch_bounds__(TBF) void k_fcg_init(int32_t n, const int32_t *__restrict__ rowptr,
                                                   const int32_t *__restrict__ col, const double *__restrict__ val,
                                                   const double *__restrict__ b, double *__restrict__ x,
@@ -230,8 +204,9 @@ __device__ bool fcg_check(FcgState *st, const double *part_res, int G, int parit
 // (forms z and the partials of r.z and z.w).  check != 0 (inside the
 // iteration): the first step first runs the test above for the iteration of
 // the given parity.
-__global__ __launch_bounds__(TBF) void k_cheb(int32_t n, const int32_t *__restrict__ rowptr,
-                                              const int32_t *__restrict__ col, const double *__restrict__ val,
+// L: 0 = CSR products, 8/16/32 = the sliced-diagonal copy (dev::mat_row).
+template <int L>
+__global__ __launch_bounds__(TBF) void k_cheb(int32_t n, dev::RowMat M,
                                               const double *__restrict__ r, const double *__restrict__ dinv,
                                               const double *__restrict__ bj1, const double *__restrict__ bj2,
                                               double *__restrict__ out, const double *__restrict__ w,
@@ -244,15 +219,14 @@ __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, const int32_t *__restri
     const dev::Chunk ch = dev::block_chunk(n, per_block);
     double v[2] = {0.0, 0.0};
     for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
-        const int s = rowptr[i], e = rowptr[i + 1];
         const double vi = dinv[i] * r[i];
         double res;
         if (stage == 0) {  // b_{d-1} = c_{d-1} v + 2 c_d Y v
-            const double av = row_dot(col, val, s, e, (int)i, [&](int q) { return dinv[q] * r[q]; });
+            const double av = dev::mat_row<L>(M, n, i, [&](int q) { return dinv[q] * r[q]; });
             const double yv = s2 * dinv[i] * av - vi;
             res = fma(2.0 * cd, yv, cj * vi);
         } else {
-            const double au = row_dot(col, val, s, e, (int)i, [&](int q) { return bj1[q]; });
+            const double au = dev::mat_row<L>(M, n, i, [&](int q) { return bj1[q]; });
             const double yu = s2 * dinv[i] * au - bj1[i];
             const double b2v = bj2 ? bj2[i] : cd * vi;  // b_{d} = c_d v is not stored
             if (stage == 1) res = fma(2.0, yu, cj * vi) - b2v;
@@ -272,8 +246,8 @@ __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, const int32_t *__restri
 // p = z + beta p_old, w = A p and the partials of p.w.  Prologue: r.z and
 // z.w of the last preconditioner application give rho and, after the first
 // iteration, beta = -(z.w) / delta_prev (FCG(1)); r.z <= 0 is a breakdown.
-__global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, const int32_t *__restrict__ rowptr,
-                                                     const int32_t *__restrict__ col, const double *__restrict__ val,
+template <int L>
+__global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, dev::RowMat M,
                                                      const double *__restrict__ z, const double *__restrict__ pold,
                                                      double *__restrict__ pnew, double *__restrict__ w,
                                                      FcgState *st, int parity, double *partials,
@@ -301,8 +275,7 @@ __global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, const int32_t *_
     const dev::Chunk ch = dev::block_chunk(n, per_block);
     double v[1] = {0.0};
     for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
-        const double sum = row_dot(col, val, rowptr[i], rowptr[i + 1], (int)i,
-                                   [&](int q) { return pdir_f(z[q], beta, pold[q]); });
+        const double sum = dev::mat_row<L>(M, n, i, [&](int q) { return pdir_f(z[q], beta, pold[q]); });
         const double pi = pdir_f(z[i], beta, pold[i]);
         pnew[i] = pi;
         w[i] = sum;
@@ -376,7 +349,7 @@ struct FcgCache {
     EventRef poll_ev[kMaxLookahead];
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    const void *gkey[8] = {};
+    const void *gkey[10] = {};
     int32_t gK = 0;
 };
 
@@ -500,6 +473,18 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
         int64_t pbk;
         fcg_grid(n, &G, &pbk);
         const int x0z = opts.x0_is_zero ? 1 : 0;
+        // products on the sliced-diagonal copy whenever the pattern allows it
+        // (a one-time host analysis per matrix; bitwise the CSR sums)
+        int lw = 0;
+        if ((s = sdia_analyse(A))) return s;
+        if (A->sdia_state == 1) {
+            if ((s = prepare_sdia(A, st))) return s;
+            lw = A->sdia_mp;
+        }
+        const dev::RowMat M{A->rowptr, A->col, A->val, A->sdia_off, A->sdia_msk, A->sdia_val, A->sdia_u};
+        auto fcheb = lw == 8 ? k_cheb<8> : lw == 16 ? k_cheb<16> : lw == 32 ? k_cheb<32> : k_cheb<0>;
+        auto fprod = lw == 8 ? k_fcg_product<8> : lw == 16 ? k_fcg_product<16> : lw == 32 ? k_fcg_product<32>
+                                                                                      : k_fcg_product<0>;
 
         hipLaunchKernelGGL(k_fcg_init, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d, r, dinv,
                            pb[0], part + (size_t)S_INIT * kMaxBlocks, pbk, x0z);
@@ -520,7 +505,7 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
                 const double *bj1 = stage == 0 ? nullptr : t[(j + 1) % 3];
                 const double *bj2 = (stage == 0 || j + 2 == DEG) ? nullptr : t[(j + 2) % 3];
                 double *outp = stage == 2 ? z : t[j % 3];
-                hipLaunchKernelGGL(k_cheb, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val,
+                hipLaunchKernelGGL(fcheb, dim3(G), dim3(TBF), 0, st, A->n, M,
                                    (const double *)r, (const double *)dinv, bj1, bj2, outp, (const double *)w,
                                    fc->st, j, stage, stage == 0 ? check : 0, parity, part, pbk);
                 APCG_CHECK_LAUNCH("k_cheb");
@@ -535,8 +520,8 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
         auto iteration = [&](int k) -> apcg_status {
             const double *pold = pb[(k + 1) & 1];
             double *pnew = pb[k & 1];
-            hipLaunchKernelGGL(k_fcg_product, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val,
-                               (const double *)z, pold, pnew, w, fc->st, k & 1, part, pbk);
+            hipLaunchKernelGGL(fprod, dim3(G), dim3(TBF), 0, st, A->n, M, (const double *)z, pold, pnew, w, fc->st,
+                               k & 1, part, pbk);
             APCG_CHECK_LAUNCH("k_fcg_product");
             hipLaunchKernelGGL(k_fcg_update, dim3(G), dim3(TBF), 0, st, n, x->d, r, (const double *)pnew,
                                (const double *)w, fc->st, part, pbk);
@@ -546,8 +531,9 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
 
         if (maxit > 0) {
             if (opts.mode == APCG_MODE_GRAPH) {
-                const void *key[8] = {(const void *)(uintptr_t)A->uid, A->rowptr, A->col, A->val, x->d, fc->ws,
-                                      (const void *)ctx->partials, (const void *)(intptr_t)n};
+                const void *key[10] = {(const void *)(uintptr_t)A->uid, A->rowptr, A->col, A->val, x->d, fc->ws,
+                                       (const void *)ctx->partials, (const void *)(intptr_t)n,
+                                       (const void *)(intptr_t)lw, A->sdia_val};
                 if (!fc->exec || fc->gK != K || memcmp(key, fc->gkey, sizeof key) != 0) {
                     if (fc->exec) {
                         EventRef ev = event_get(dev);

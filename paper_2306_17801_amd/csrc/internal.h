@@ -553,5 +553,49 @@ __device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, con
     return sum;
 }
 
+// A matrix as the row-per-thread kernels read it: the CSR arrays, and the
+// sliced-diagonal copy when there is one.
+struct RowMat {
+    const int32_t *rowptr, *col;
+    const double *val;
+    const int32_t *soff;
+    const uint64_t *smask;
+    const double *sval;
+    int U;
+};
+
+// sum_j a_ij u(j) of row i, entries in column-storage order with one FMA
+// each: L = 0 reads the CSR arrays (rows of up to 8 entries issue every
+// gather before the first FMA), L = 8/16/32 the sliced-diagonal copy of that
+// slot width (then each wavefront's rows must be one 64-row slice).
+template <int L, typename F>
+__device__ __forceinline__ double mat_row(const RowMat &M, int64_t n, int64_t i, F u) {
+    if constexpr (L > 0) {
+        return sdia_row<L>(M.soff, M.smask, M.sval, M.U, n, i, u);
+    } else {
+        const int s = M.rowptr[i], e = M.rowptr[i + 1];
+        const int len = e - s;
+        double sum = 0.0;
+        if (len <= 8) {
+            int jj[8];
+            double aa[8], uj[8];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const bool in = q < len;
+                jj[q] = in ? M.col[s + q] : (int)i;
+                aa[q] = in ? M.val[s + q] : 0.0;
+            }
+#pragma unroll
+            for (int q = 0; q < 8; ++q) uj[q] = u(jj[q]);
+#pragma unroll
+            for (int q = 0; q < 8; ++q)
+                if (q < len) sum = fma(aa[q], uj[q], sum);
+        } else {
+            for (int k = s; k < e; ++k) sum = fma(M.val[k], u(M.col[k]), sum);
+        }
+        return sum;
+    }
+}
+
 }  // namespace dev
 }  // namespace apcg

@@ -65,51 +65,7 @@ struct TqState {
 };
 static_assert(sizeof(TqState) <= 512, "TFQMR state exceeds its allocation");
 
-// B_ii (sum_j a_ij u(j)) for row i, entries added in storage order
-template <typename F>
-__device__ __forceinline__ double row_apply(const int32_t *__restrict__ col, const double *__restrict__ val, int s,
-                                            int e, int row, F u) {
-    const int len = e - s;
-    double sum = 0.0;
-    if (len <= 8) {
-        int jj[8];
-        double aa[8], uj[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-            const bool in = q < len;
-            jj[q] = in ? col[s + q] : row;
-            aa[q] = in ? val[s + q] : 0.0;
-        }
-#pragma unroll
-        for (int q = 0; q < 8; ++q) uj[q] = u(jj[q]);
-#pragma unroll
-        for (int q = 0; q < 8; ++q)
-            if (q < len) sum = fma(aa[q], uj[q], sum);
-    } else {
-        for (int k = s; k < e; ++k) sum = fma(val[k], u(col[k]), sum);
-    }
-    return sum;
-}
-
-// The matrix as the products read it: CSR, and the sliced-diagonal copy when
-// the pattern has one (then L = its slot width).
-struct TqMat {
-    const int32_t *rowptr, *col;
-    const double *val;
-    const int32_t *soff;
-    const uint64_t *smask;
-    const double *sval;
-    int U;
-};
-
-// B-less row product sum_j a_ij u(j) of row i; with L > 0 each wavefront's
-// rows are one 64-row slice (the row loops below step by the workgroup size
-// from a multiple of 64).
-template <int L, typename F>
-__device__ __forceinline__ double tq_row(const TqMat &M, int64_t n, int64_t i, F u) {
-    if constexpr (L == 0) return row_apply(M.col, M.val, M.rowptr[i], M.rowptr[i + 1], (int)i, u);
-    else return dev::sdia_row<L>(M.soff, M.smask, M.sval, M.U, n, i, u);
-}
+using TqMat = dev::RowMat;
 
 __device__ __forceinline__ void set_stop(TqState *st, int status) {
     if (blockIdx.x == 0 && threadIdx.x == 0) {
@@ -196,7 +152,7 @@ __global__ __launch_bounds__(TBQ) void k_tq_init_product(int32_t n, TqMat M,
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double s[1] = {0.0};
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBQ) {
-        const double ui = bd[i] * tq_row<L>(M, n, i, [&](int q) { return y1[q]; });
+        const double ui = bd[i] * dev::mat_row<L>(M, n, i, [&](int q) { return y1[q]; });
         u1[i] = ui;
         v[i] = ui;
         s[0] = fma(r0[i], ui, s[0]);
@@ -229,7 +185,7 @@ __global__ __launch_bounds__(TBQ) void k_tq_a(int32_t n, TqMat M, const double *
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double s[1] = {0.0};
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBQ) {
-        const double ui = bd[i] * tq_row<L>(M, n, i, [&](int q) { return fma(-alpha, v[q], y1[q]); });
+        const double ui = bd[i] * dev::mat_row<L>(M, n, i, [&](int q) { return fma(-alpha, v[q], y1[q]); });
         y2[i] = fma(-alpha, v[i], y1[i]);
         u2[i] = ui;
         const double wi = fma(-alpha, u1[i], w[i]);
@@ -340,7 +296,7 @@ __global__ __launch_bounds__(TBQ) void k_tq_d(int32_t n, TqMat M, const double *
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double s[1] = {0.0};
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += TBQ) {
-        const double ui = bd[i] * tq_row<L>(M, n, i, [&](int q) { return fma(beta, y2[q], w[q]); });
+        const double ui = bd[i] * dev::mat_row<L>(M, n, i, [&](int q) { return fma(beta, y2[q], w[q]); });
         y1[i] = fma(beta, y2[i], w[i]);
         u1[i] = ui;
         const double vi = fma(beta, fma(beta, v[i], u2[i]), ui);
