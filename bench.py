@@ -149,6 +149,21 @@ def bench_batch(apcg, torch, reps):
     return out
 
 
+def learned_systems_range(count, seed, lo, hi, workers, i0, i1):
+    """Members i0 .. i1-1 of the learned-PC set of ``count`` systems (the same
+    systems a full call generates)."""
+    from paper_2306_17801_amd import problems
+
+    args = [(seed, i, count, lo, hi) for i in range(i0, i1)]
+    if workers <= 1 or i1 - i0 < 16:
+        return [problems.learned_pc_system(a) for a in args]
+    import multiprocessing as mp
+    from concurrent.futures import ProcessPoolExecutor
+
+    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
+        return list(ex.map(problems.learned_pc_system, args, chunksize=4))
+
+
 def learned_systems(count, seed, lo, hi, workers):
     """The learned-PC workload's systems, generated on the host (in worker
     processes when there are many: generation is numpy-bound)."""
@@ -179,15 +194,27 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     from paper_2306_17801_amd import learned as L
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
-    t0 = time.perf_counter()
-    train_set = learned_systems(n_train, 4, side_lo, side_hi, workers)
-    eval_set = learned_systems(n_eval, 40, side_lo, side_hi, workers)
-    t_gen = time.perf_counter() - t0
     ctx = apcg.apcg_ctx_create(0)
+    # the training set is generated and collected in chunks, so that the full
+    # workload (2000 systems of up to 96^3 rows) never sits in host memory at once
+    t_gen = t_collect = 0.0
+    parts = []
+    chunk = 128
+    for c0 in range(0, n_train, chunk):
+        t0 = time.perf_counter()
+        part = learned_systems_range(n_train, 4, side_lo, side_hi, workers, c0, min(n_train, c0 + chunk))
+        t_gen += time.perf_counter() - t0
+        t0 = time.perf_counter()
+        parts.append(L.collect(ctx, part))
+        t_collect += time.perf_counter() - t0
+        del part
+        if n_train > chunk:
+            log(f"[bench] learned: training systems {min(n_train, c0 + chunk)}/{n_train} collected")
+    dtrain = L.Dataset(*[torch.cat([getattr(d, k) for d in parts]) for k in ("X", "G", "h", "label", "lmax")])
+    del parts
     t0 = time.perf_counter()
-    dtrain = L.collect(ctx, train_set)
-    t_collect = time.perf_counter() - t0
-    del train_set
+    eval_set = learned_systems(n_eval, 40, side_lo, side_hi, workers)
+    t_gen += time.perf_counter() - t0
     deval = L.collect(ctx, eval_set)
     t0 = time.perf_counter()
     pc, losses = L.train(ctx, dtrain, epochs=epochs, batch=32, lr=3e-3)
