@@ -20,11 +20,28 @@ constexpr int BS = 256;
 using dev::Chunk;
 using dev::block_chunk;
 
+// Each thread handles UNR entries per step (UNR * BS per workgroup step),
+// every load of a step issued before its first store, so several loads per
+// thread are in flight: with two or fewer streams per entry, one entry per
+// step leaves the HBM pipe short of requests.
+constexpr int UNR = 4;
+
 __global__ __launch_bounds__(BS) void k_dot(const double *__restrict__ x, const double *__restrict__ y, int64_t n,
                                             int64_t per_block, double *partials) {
     const Chunk c = block_chunk(n, per_block);
     double acc = 0.0;
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) acc = fma(x[i], y[i], acc);
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += UNR * BS) {
+        double xv[UNR], yv[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            const int64_t j = i + (int64_t)k * BS;
+            const bool in = j < c.hi;
+            xv[k] = in ? x[j] : 0.0;
+            yv[k] = in ? y[j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) acc = fma(xv[k], yv[k], acc);
+    }
     double v[1] = {acc};
     dev::store_partials<BS, 1>(v, partials, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
 }
@@ -37,36 +54,51 @@ __global__ __launch_bounds__(64) void k_dot_final(const double *partials, int G,
     if (threadIdx.x == 0) *out = take_sqrt ? sqrt(t[0]) : t[0];
 }
 
-__global__ __launch_bounds__(BS) void k_axpy(double *__restrict__ y, const double *a, double sign,
-                                             const double *__restrict__ x, int64_t n, int64_t per_block) {
-    const double s = sign * *a;
-    const Chunk c = block_chunk(n, per_block);
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) y[i] = fma(s, x[i], y[i]);
+// out[j] = f(a[j], b[j]) over the workgroup's chunk (b may alias out; a and
+// b are read before out is written within each step).
+template <typename F>
+__device__ __forceinline__ void stream2(double *out, const double *a, const double *b, const Chunk &c, F f) {
+    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += UNR * BS) {
+        double av[UNR], bv[UNR];
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            const int64_t j = i + (int64_t)k * BS;
+            const bool in = j < c.hi;
+            av[k] = in && a ? a[j] : 0.0;
+            bv[k] = in && b ? b[j] : 0.0;
+        }
+#pragma unroll
+        for (int k = 0; k < UNR; ++k) {
+            const int64_t j = i + (int64_t)k * BS;
+            if (j < c.hi) out[j] = f(av[k], bv[k]);
+        }
+    }
 }
 
-__global__ __launch_bounds__(BS) void k_aypx(double *__restrict__ y, const double *b, const double *__restrict__ x,
+__global__ __launch_bounds__(BS) void k_axpy(double *y, const double *a, double sign, const double *__restrict__ x,
                                              int64_t n, int64_t per_block) {
-    const double s = *b;
-    const Chunk c = block_chunk(n, per_block);
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) y[i] = fma(s, y[i], x[i]);
+    const double s = sign * *a;
+    stream2(y, x, y, block_chunk(n, per_block), [s](double xv, double yv) { return fma(s, xv, yv); });
 }
 
-__global__ __launch_bounds__(BS) void k_scale(double *__restrict__ x, const double *a, int64_t n,
-                                              int64_t per_block) {
+__global__ __launch_bounds__(BS) void k_aypx(double *y, const double *b, const double *__restrict__ x, int64_t n,
+                                             int64_t per_block) {
+    const double s = *b;
+    stream2(y, x, y, block_chunk(n, per_block), [s](double xv, double yv) { return fma(s, yv, xv); });
+}
+
+__global__ __launch_bounds__(BS) void k_scale(double *x, const double *a, int64_t n, int64_t per_block) {
     const double s = *a;
-    const Chunk c = block_chunk(n, per_block);
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) x[i] = s * x[i];
+    stream2(x, x, nullptr, block_chunk(n, per_block), [s](double xv, double) { return s * xv; });
 }
 
 __global__ __launch_bounds__(BS) void k_copy(double *__restrict__ d, const double *__restrict__ s, int64_t n,
                                              int64_t per_block) {
-    const Chunk c = block_chunk(n, per_block);
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) d[i] = s[i];
+    stream2(d, s, nullptr, block_chunk(n, per_block), [](double sv, double) { return sv; });
 }
 
 __global__ __launch_bounds__(BS) void k_fill(double *__restrict__ x, double v, int64_t n, int64_t per_block) {
-    const Chunk c = block_chunk(n, per_block);
-    for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += BS) x[i] = v;
+    stream2(x, nullptr, nullptr, block_chunk(n, per_block), [v](double, double) { return v; });
 }
 
 __global__ void k_scalar_op(int op, double *out, const double *a, const double *b) {
