@@ -104,7 +104,16 @@ def bench_batch(apcg, torch, reps):
     out = {"systems": nsys, "rows": int(sum(s.A.n for s in systems)), "nnz": int(sum(s.A.nnz for s in systems))}
     best = None
     for name, sched, tb in (("persistent256", 1, 256), ("persistent512", 1, 512), ("persistent1024", 1, 1024),
-                            ("segmented", 2, 0)):
+                            ("segmented", 2, 0), ("segmented_sdia", 2, 0)):
+        if name == "segmented_sdia":
+            # the matrices on the sliced-diagonal schedule (a one-time host
+            # analysis each): the segmented tile product reads those copies,
+            # and so does the plain per-solve loop below
+            for a in As:
+                try:
+                    apcg.apcg_mat_set_spmv_config(a.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+                except apcg.ApcgError:
+                    pass
         o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_block_size=tb, batch_schedule=sched)
         apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o, info)
         torch.cuda.synchronize()

@@ -517,14 +517,16 @@ apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec 
  *     256-row tiles; per iteration a tile product, a per-system alpha, a
  *     tile update and a per-system test, K iterations per captured graph;
  *     stopped systems' tiles return at once.  Best when a few large systems
- *     dominate.
+ *     dominate.  A system whose matrix is on APCG_SPMV_SDIA with 8
+ *     offset slots per slice has its tile product read the sliced-diagonal
+ *     copy (same row sums, bit for bit); every other system reads CSR.
  *   APCG_BATCH_AUTO: persistent when no system costs more than 1/CUs of the
  *     batch, else segmented.
  * A, b, x: arrays of nsys handles on ctx's device (the x[i] distinct and not
  * aliasing any b[i]); x[i] holds x0 (ignored with x0_is_zero) and receives
  * the solution; info must hold >= nsys records, record i for system i.
  * opts->mode APCG_MODE_GRAPH (default) replays captured graphs (cached while
- * the batch is unchanged).  The context keeps 5 sum(n_i) doubles of
+ * the batch is unchanged).  The context keeps 6 sum(n_i) doubles of
  * workspace and the batch descriptors.  Returns once the work is enqueued
  * (after a one-time upload of the descriptors when the batch changed; the
  * segmented schedule polls the device's count of running systems one graph

@@ -27,9 +27,15 @@ struct BatchSys {
     const double *val;
     const double *b;
     double *x;
-    double *ws;  // 5 n doubles: r, dinv, p0, p1, w
+    double *ws;  // 6 n doubles: r, dinv, p0, p1, w, z
+    // the matrix's sliced-diagonal copy (8 offset slots per slice), used by
+    // the segmented schedule's product when the matrix's SpMV schedule is
+    // APCG_SPMV_SDIA; null otherwise
+    const int32_t *soff;
+    const uint64_t *smask;
+    const double *sval;
     int32_t n;
-    int32_t pad;
+    int32_t U;
 };
 
 // segmented schedule (below)
@@ -374,7 +380,14 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
             if (b[i] == x[i] || (b[i]->d == x[i]->d && A[i]->n > 0))
                 return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
             const int64_t n = A[i]->n;
-            hs[i] = BatchSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x[i]->d, nullptr, (int32_t)n, 0};
+            hs[i] = BatchSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x[i]->d, nullptr,
+                             nullptr, nullptr, nullptr, (int32_t)n, 0};
+            if (A[i]->cfg.schedule == APCG_SPMV_SDIA && A[i]->sdia_state == 1 && A[i]->sdia_mp == 8) {
+                hs[i].soff = A[i]->sdia_off;
+                hs[i].smask = A[i]->sdia_msk;
+                hs[i].sval = A[i]->sdia_val;
+                hs[i].U = A[i]->sdia_u;
+            }
             hs[i].ws = reinterpret_cast<double *>(ws_total);  // offset for now
             ws_total += ((6 * n + 63) / 64) * 64;  // r, dinv, p0, p1, w, z (z: segmented schedule only)
             // CG iterations grow like sqrt(condition) ~ n^(1/2) in 2D (n^(1/3) in 3D):
@@ -432,6 +445,9 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
             bc->ws_cap = std::max<int64_t>(ws_total, 64);
         }
         for (int32_t i = 0; i < nsys; ++i) hs[i].ws = bc->d_ws + reinterpret_cast<int64_t>(hs[i].ws);
+        // refill the sliced-diagonal values of the systems that use them
+        for (int32_t i = 0; i < nsys; ++i)
+            if (hs[i].sval && (s = prepare_sdia(A[i], st))) return s;
         uint64_t h = fnv1a(hs.data(), sizeof(BatchSys) * nsys);
         h = fnv1a(order.data(), sizeof(int32_t) * nsys, h);
         if (h != bc->desc_hash) {
@@ -709,7 +725,12 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
         const int i = P.tile_row0[t] + threadIdx.x;
         double v[1] = {0.0};
         if (i < S.n) {
-            const double sum = row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
+            // the tile's rows start at a multiple of 256 of its system, so
+            // each wavefront's rows are one 64-row slice
+            const double sum =
+                S.sval ? dev::sdia_row<8>(S.soff, S.smask, S.sval, S.U, n, i,
+                                          [&](int q) { return fma(beta, pold[q], z[q]); })
+                       : row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
             const double pi = fma(beta, pold[i], z[i]);
             pnew[i] = pi;
             w[i] = sum;

@@ -29,10 +29,17 @@ def ctx(apcg):
     apcg.apcg_ctx_destroy(c)
 
 
-def run_batch(apcg, ctx, systems, rtol, maxit, x0s=None, **opt):
+def run_batch(apcg, ctx, systems, rtol, maxit, x0s=None, sdia=(), **opt):
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
     As = [DeviceCSR(s.A) for s in systems]
+    run_batch.switched = []
+    for i in sdia:  # these systems' matrices on the sliced-diagonal schedule, where the pattern allows it
+        try:
+            apcg.apcg_mat_set_spmv_config(As[i].h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+            run_batch.switched.append(i)
+        except apcg.ApcgError:
+            pass
     bs = [DeviceVec(s.b) for s in systems]
     xs = [DeviceVec(np.zeros(s.A.n) if x0s is None else x0s[i]) for i, s in enumerate(systems)]
     if x0s is None:
@@ -141,3 +148,24 @@ def test_batch2d_all_256_in_bench_configuration(apcg, ctx, batch256, sched):
     for i in (0, 37, 64, 101, 150, 199, 230, 255):
         ref = oracle.pcg(batch256[i].A, batch256[i].b, rtol=1e-8, maxit=20000)
         assert abs(res[i]["iterations"] - ref.its) <= 1
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_segmented_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
+    """Systems whose matrices are on the sliced-diagonal schedule have their
+    tile products read the sliced-diagonal copy in the segmented schedule;
+    each row's sum is the CSR one (column order, one FMA per entry), so the
+    batch is bit for bit the all-CSR batch (every system whose pattern allows
+    it switched, the others left on CSR; sizes not multiples of 64 included)."""
+    systems = mixed_small_batch()[:24]
+    print(f"case batched seg sdia mode={mode}", flush=True)
+    r_csr, x_csr = run_batch(apcg, ctx, systems, 1e-10, 5000, batch_schedule=2, mode=mode)
+    r_sd, x_sd = run_batch(apcg, ctx, systems, 1e-10, 5000, sdia=range(24), batch_schedule=2, mode=mode)
+    print("switched", run_batch.switched, flush=True)
+    assert len(run_batch.switched) >= 4 and len(run_batch.switched) < 24
+    for a, b2, xa, xb in zip(r_csr, r_sd, x_csr, x_sd):
+        assert a == b2
+        assert np.array_equal(xa, xb)
+    for s, r, x in zip(systems, r_sd, x_sd):
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=5000)
+        assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
