@@ -60,9 +60,35 @@ def sdia_shape(A):
 
     rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
     key = (rows // 64) * (2 * A.n + 1) + (A.col.astype(np.int64) - rows + A.n)
-    sl = np.unique(key) // (2 * A.n + 1)
+    uk = np.unique(key)
+    sl = uk // (2 * A.n + 1)
     u = int(np.bincount(sl).max()) if sl.size else 1
     return u, 8 if u <= 8 else 16 if u <= 16 else 32
+
+
+def sdia_upper_slots(A):
+    """Value slots on or right of the diagonal, summed over the slices: what
+    the marching product streams when the matrix is symmetric (the entries
+    left of the diagonal are read as their transposes)."""
+    import numpy as np
+
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
+    off = A.col.astype(np.int64) - rows
+    key = (rows // 64) * (2 * A.n + 1) + (off + A.n)
+    return int(np.unique(key[off >= 0]).size)
+
+
+def is_symmetric(A):
+    """Pattern and values symmetric bit for bit."""
+    import numpy as np
+
+    M = A.to_scipy()
+    T = M.T.tocsr()
+    T.sort_indices()
+    M = M.tocsr()
+    M.sort_indices()
+    return (np.array_equal(M.indptr, T.indptr) and np.array_equal(M.indices, T.indices)
+            and np.array_equal(M.data.view(np.int64), T.data.view(np.int64)))
 
 
 def copy_calibration(apcg, torch):
@@ -687,7 +713,11 @@ def main():
         # read, p, w written
         u, mp = sdia_shape(A_h)
         nsl = (n + 63) // 64
-        prod_bytes = 8 * 64 * nsl * u + 12 * nsl * mp + 32 * n
+        sym_reads = cfg_now["lanes_per_row"] > 1 and is_symmetric(A_h)
+        if sym_reads:  # marching with symmetric values: the upper slots stream, plus the partner table
+            prod_bytes = 8 * 64 * sdia_upper_slots(A_h) + 16 * nsl * mp + 32 * n
+        else:
+            prod_bytes = 8 * 64 * nsl * u + 12 * nsl * mp + 32 * n
     else:
         prod_bytes = 12 * nnz + 4 * (n + 1) + 32 * n  # A; z, p_old read; p, w written
     csr_bytes = 12 * nnz + 4 * (n + 1) + 32 * n
@@ -702,10 +732,12 @@ def main():
         if (tr.get("source_sha256_16") == source_hash(KERNEL_SOURCE) and tr.get("n") == n
                 and tr.get("spmv_config") == cfg_chosen):
             traffic = tr.get("bytes_per_launch")
+    sym_reads = cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1 and is_symmetric(A_h)
     kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell",
              apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia" + ("_march" if cfg_now["lanes_per_row"] > 1 else "")}.get(
         cfg_now["schedule"], "k_pcg_product") + (
-        f" (block {cfg_now['block_size']}, {cfg_now['lanes_per_row']} planes per task)"
+        f" (block {cfg_now['block_size']}, {cfg_now['lanes_per_row']} planes per task"
+        + (", symmetric reads)" if sym_reads else ")")
         if cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1
         else f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)")
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),

@@ -384,7 +384,12 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       present with both signs in at least half of the slices): each
  *       wavefront walks lanes_per_row slices one plane apart and carries the
  *       +-plane windows between them instead of gathering them (blocks is
- *       then ignored); without a plane stride it is the plain kernel.
+ *       then ignored); without a plane stride it is the plain kernel.  When
+ *       the pattern is structurally symmetric (found by the same analysis)
+ *       and the values are symmetric bit for bit (checked on the device at
+ *       every refill), the marching product reads each entry left of the
+ *       diagonal as its transpose, so only the slots on and right of the
+ *       diagonal stream from memory; the sums are unchanged.
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so

@@ -189,7 +189,10 @@ struct apcg_mat_s {
     int32_t sdia_u = 0;              // value slots per slice (largest offset count of any slice)
     int32_t sdia_mp = 0;             // offset / mask slots per slice: 8, 16 or 32 (>= sdia_u)
     int32_t sdia_ps = 0;             // plane stride in slices for plane marching (0: none)
-    int32_t *sdia_off = nullptr;     // device [nslices * sdia_mp] offsets, padding 0
+    int32_t sdia_sym = 0;            // 1: the pattern is structurally symmetric
+    int32_t *sdia_off = nullptr;     // device [nslices * sdia_mp] offsets (padding 0), then
+                                     //   [nslices * sdia_mp] partner slots of the entries left of
+                                     //   the diagonal, then the value-symmetry flag (64 ints)
     uint64_t *sdia_msk = nullptr;    // device [nslices * sdia_mp] row masks, padding 0
     double *sdia_val = nullptr;      // device [nslices * sdia_u * 64] values, absent entries 0
     apcg::Record rec;

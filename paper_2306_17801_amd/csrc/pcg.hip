@@ -602,19 +602,23 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
 // offsets are gathered as in k_pcg_product_sdia; the sums are bitwise the
 // same.  shape = U | seg << 8 | Ps << 16.  Tasks are spread over the grid
 // (task += waves in the grid).
-template <int TB, int W>
-__global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const int32_t *__restrict__ soff,
-                                                               const int32_t *__restrict__ smask_words,
-                                                               const double *__restrict__ sval,
-                                                               const double *__restrict__ z,
-                                                               const double *__restrict__ pold,
-                                                               double *__restrict__ pnew, double *__restrict__ w,
-                                                               SolveState *st, const double *part_res, int g_res,
-                                                               double *part_delta, int32_t /*unused*/, int parity,
-                                                               int tune, int32_t shape) {
-    const uint64_t *smask = reinterpret_cast<const uint64_t *>(smask_words);
-    const int U = shape & 0xff, seg = (shape >> 8) & 0xff, Ps = (shape >> 16) & 0xffff;
-    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+// Symmetric values (the flag behind the partner table set by the fill and
+// check kernels): an entry left of the diagonal, (i, i - q), is read as its
+// transpose (i - q, i) from that row's slot of offset +q -- for q = 64 Ps
+// the value of the previous slice's +plane slot, carried in a register, for
+// the other offsets a load of a line the product reads anyway (the same
+// slice, or a slice a few rows back), so only the slots on and right of the
+// diagonal stream from memory.  The values are bitwise the same, and so is
+// the sum.
+// The marching tasks of one wavefront; returns its share of p.Ap.  SYM:
+// entries left of the diagonal read as their transposes (one load each, at
+// the partner slot's address; no branches on the offsets).
+template <int TB, int W, bool SYM>
+__device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restrict__ soff,
+                                              const uint64_t *__restrict__ smask, const double *__restrict__ sval,
+                                              const double *__restrict__ z, const double *__restrict__ pold,
+                                              double *__restrict__ pnew, double *__restrict__ w, int lb, double beta,
+                                              int U, int seg, int Ps) {
     const int nsl = (n + 63) / 64;
     const int nz = (nsl + Ps - 1) / Ps;  // planes (the last may be partial)
     const int nseg = (nz + seg - 1) / seg;
@@ -622,8 +626,7 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const 
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     const int nwaves = gridDim.x * (TB / 64);
     const int up = 64 * Ps;
-    double beta;
-    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    const int32_t *part = soff + (int64_t)nsl * W;
     double acc = 0.0;
     for (int task = lb * (TB / 64) + wave; task < ntask; task += nwaves) {
         const int c = task % Ps, g = task / Ps;
@@ -641,23 +644,39 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const 
             rc = min(row, n - 1);
             const int32_t *o = soff + (int64_t)sl * W;
             const uint64_t *m = smask + (int64_t)sl * W;
-            const double *v = sval + (int64_t)sl * U * 64 + lane;
+            const int32_t *pt = part + (int64_t)sl * W;
             const int rn = min(rc + up, n - 1);
             const double zn = z[rn], pn = pold[rn];  // +plane window = the next slice's own
-            int oc[W];
+            int oc[W], qc[W];
             uint64_t mc[W];
             double ac[W];
+            bool in[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 oc[k] = o[k];
                 mc[k] = m[k];
-                ac[k] = __builtin_nontemporal_load(v + (int64_t)min(k, U - 1) * 64);
+                qc[k] = SYM ? pt[k] : 0;
             }
-            double zj[W], pj[W];
-            bool in[W];
 #pragma unroll
             for (int k = 0; k < W; ++k) {
                 in[k] = (mc[k] >> lane) & 1ull;
+                if constexpr (SYM) {
+                    // own slot, or for an entry left of the diagonal the
+                    // slot of its transpose (row row + offset); bit
+                    // arithmetic rather than selects keeps this one
+                    // straight-line block whose loads are all in flight
+                    const int lowm = oc[k] >> 31;  // all ones left of the diagonal
+                    const int r = sl * 64 + lane + (in[k] ? (oc[k] & lowm) : 0);
+                    const int ps = (lane >= ((-oc[k]) & 63) ? qc[k] : (qc[k] >> 8)) & 0xff;
+                    const int slot = (ps & lowm) | (min(k, U - 1) & ~lowm);
+                    ac[k] = sval[((int64_t)(r >> 6) * U + slot) * 64 + (r & 63)];
+                } else {
+                    ac[k] = __builtin_nontemporal_load(sval + ((int64_t)sl * U + min(k, U - 1)) * 64 + lane);
+                }
+            }
+            double zj[W], pj[W];
+#pragma unroll
+            for (int k = 0; k < W; ++k) {
                 const bool carried = oc[k] == up || oc[k] == -up || oc[k] == 0;
                 const int jx = (in[k] && !carried) ? row + oc[k] : rc;
                 const double zg = carried ? 0.0 : z[jx], pg = carried ? 0.0 : pold[jx];
@@ -670,18 +689,42 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const 
                 const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
                 sum = in[k] ? t : sum;
             }
-            if (row < n) {
-                const double pi = pdir(zo, beta, po);
-                pnew[row] = pi;
-                w[row] = sum;
-                acc = fma(pi, sum, acc);
-            }
+            // stored for the rows past n of the last slice too: p and w
+            // are workspace vectors padded to whole slices, so the stores
+            // need no branch (whose join would make the next slice wait for
+            // them)
+            const double pi = pdir(zo, beta, po);
+            pnew[row] = pi;
+            w[row] = sum;
+            acc = row < n ? fma(pi, sum, acc) : acc;
             zm = zo;
             pm = po;
             zo = zn;
             po = pn;
         }
     }
+    return acc;
+}
+
+template <int TB, int W>
+__global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const int32_t *__restrict__ soff,
+                                                               const int32_t *__restrict__ smask_words,
+                                                               const double *__restrict__ sval,
+                                                               const double *__restrict__ z,
+                                                               const double *__restrict__ pold,
+                                                               double *__restrict__ pnew, double *__restrict__ w,
+                                                               SolveState *st, const double *part_res, int g_res,
+                                                               double *part_delta, int32_t /*unused*/, int parity,
+                                                               int tune, int32_t shape) {
+    const uint64_t *smask = reinterpret_cast<const uint64_t *>(smask_words);
+    const int U = shape & 0xff, seg = (shape >> 8) & 0xff, Ps = (shape >> 16) & 0xffff;
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int nsl = (n + 63) / 64;
+    const int sym = __builtin_amdgcn_readfirstlane(soff[2 * (int64_t)nsl * W]);
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    const double acc = sym ? march_tasks<TB, W, true>(n, soff, smask, sval, z, pold, pnew, w, lb, beta, U, seg, Ps)
+                           : march_tasks<TB, W, false>(n, soff, smask, sval, z, pold, pnew, w, lb, beta, U, seg, Ps);
     double v[1] = {acc};
     dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
 }
@@ -689,11 +732,15 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const 
 // Fills the sliced-diagonal value copy from the CSR values: thread
 // (slice, lane) walks its row's entries in order, one per set mask bit, and
 // writes 0 to the slots its row does not hold.
+// Thread 0 also sets the value-symmetry flag to the pattern's structural
+// symmetry (k_sdia_symcheck, queued after it, clears it on a mismatch).
 __global__ __launch_bounds__(256) void k_sdia_fill(int32_t n, const int32_t *__restrict__ rowptr,
                                                    const double *__restrict__ val, const uint64_t *__restrict__ smask,
-                                                   int32_t U, int32_t MP, double *__restrict__ sval) {
+                                                   int32_t U, int32_t MP, double *__restrict__ sval,
+                                                   int32_t *__restrict__ symflag, int32_t structural) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t nsl = ((int64_t)n + 63) / 64;
+    if (g == 0) symflag[0] = structural;
     if (g >= nsl * 64) return;
     const int64_t sl = g >> 6;
     const int lane = (int)(g & 63);
@@ -704,6 +751,33 @@ __global__ __launch_bounds__(256) void k_sdia_fill(int32_t n, const int32_t *__r
         sval[(sl * U + k) * 64 + lane] = in ? val[e] : 0.0;
         e += in ? 1 : 0;
     }
+}
+
+// Value symmetry of a structurally symmetric pattern: thread (slice, lane)
+// compares each of its row's entries left of the diagonal, bit for bit, with
+// its transpose's copy (the partner slot, see sdia_analyse) and clears the
+// flag on any difference, so that the products read every slot themselves.
+__global__ __launch_bounds__(256) void k_sdia_symcheck(int32_t n, const int32_t *__restrict__ soff,
+                                                       const uint64_t *__restrict__ smask, int32_t U, int32_t MP,
+                                                       const double *__restrict__ sval, int32_t *__restrict__ symflag) {
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t nsl = ((int64_t)n + 63) / 64;
+    if (g >= nsl * 64) return;
+    const int64_t sl = g >> 6;
+    const int lane = (int)(g & 63);
+    const int32_t *part = soff + nsl * MP;
+    bool same = true;
+    for (int k = 0; k < U; ++k) {
+        const int32_t o = soff[sl * MP + k];
+        if (o >= 0 || !((smask[sl * MP + k] >> lane) & 1ull)) continue;
+        const int64_t r = sl * 64 + lane + o;  // the transpose's row, >= 0 for a present entry
+        const int pk = part[sl * MP + k];
+        const int slot = lane >= ((-o) & 63) ? (pk & 0xff) : ((pk >> 8) & 0xff);
+        const double a = sval[(sl * U + k) * 64 + lane];
+        const double t = sval[((r >> 6) * U + slot) * 64 + (r & 63)];
+        same = same && __double_as_longlong(a) == __double_as_longlong(t);
+    }
+    if (!same) symflag[0] = 0;
 }
 
 // ----------------------------------------------------------------- update
@@ -1016,7 +1090,8 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
         int32_t ps = 0;
         for (auto &kv : both)
             if (2 * kv.second >= nsl) ps = kv.first / 64;
-        std::vector<int32_t> off_h((size_t)(nsl * MP), 0);
+        // offsets, then the partner slots, then the value-symmetry flag
+        std::vector<int32_t> off_h((size_t)(2 * nsl * MP + 64), 0);
         std::vector<uint64_t> msk_h((size_t)(nsl * MP), 0);
         for (int64_t sl = 0; sl < nsl; ++sl) {
             slice_offsets(sl);
@@ -1027,11 +1102,43 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
                     msk_h[sl * MP + k] |= 1ull << (i - sl * 64);
                 }
         }
-        APCG_HIP(hipMalloc((void **)&A->sdia_off, sizeof(int32_t) * nsl * MP));
+        // Structural symmetry: every entry (i, j) has its transpose (j, i).
+        // Then entry (i, i - q) of slice s, lane l is the transpose of entry
+        // (i - q, i), which sits in the slot of offset +q of slice
+        // (i - q) >> 6: slice s - q/64 for lanes l >= q mod 64, the slice
+        // before it for the lanes below.  Those two slot indices are kept per
+        // lower slot (low byte: upper lanes, next byte: lower lanes).
+        bool sym = true;
+        for (int64_t i = 0; i < n && sym; ++i)
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+                const int32_t j = cl[e];
+                if (j < 0 || j >= n || !std::binary_search(cl.begin() + rp[j], cl.begin() + rp[j + 1], (int32_t)i)) {
+                    sym = false;
+                    break;
+                }
+            }
+        int32_t *part_h = off_h.data() + nsl * MP;
+        if (sym) {
+            auto slot_of = [&](int64_t sl, int32_t o) -> int32_t {  // slot of offset o in slice sl, 0 if absent
+                if (sl < 0) return 0;
+                for (int32_t k = 0; k < MP; ++k)
+                    if (off_h[sl * MP + k] == o) return k;
+                return 0;
+            };
+            for (int64_t sl = 0; sl < nsl; ++sl)
+                for (int32_t k = 0; k < MP; ++k) {
+                    const int32_t o = off_h[sl * MP + k];
+                    if (msk_h[sl * MP + k] == 0 || o >= 0) continue;
+                    const int32_t q = -o, qs = q >> 6, qr = q & 63;
+                    part_h[sl * MP + k] = slot_of(sl - qs, q) | (qr ? slot_of(sl - qs - 1, q) << 8 : 0);
+                }
+        }
+        A->sdia_sym = sym ? 1 : 0;
+        APCG_HIP(hipMalloc((void **)&A->sdia_off, sizeof(int32_t) * off_h.size()));
         APCG_HIP(hipMalloc((void **)&A->sdia_msk, sizeof(uint64_t) * nsl * MP));
         APCG_HIP(hipMalloc((void **)&A->sdia_val, sizeof(double) * slots));
         g_counters.h2d_copies += 2;
-        APCG_HIP(hipMemcpy(A->sdia_off, off_h.data(), sizeof(int32_t) * nsl * MP, hipMemcpyHostToDevice));
+        APCG_HIP(hipMemcpy(A->sdia_off, off_h.data(), sizeof(int32_t) * off_h.size(), hipMemcpyHostToDevice));
         APCG_HIP(hipMemcpy(A->sdia_msk, msk_h.data(), sizeof(uint64_t) * nsl * MP, hipMemcpyHostToDevice));
         A->sdia_u = U;
         A->sdia_mp = MP;
@@ -1051,9 +1158,15 @@ apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s) {
     if (A->sdia_state < 0) return set_error(APCG_ERR_UNSUPPORTED, A->sdia_reason);
     const int64_t nsl = ((int64_t)A->n + 63) / 64;
     const int64_t blocks = (nsl * 64 + 255) / 256;
+    int32_t *flag = A->sdia_off + 2 * nsl * A->sdia_mp;
     hipLaunchKernelGGL(k_sdia_fill, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->rowptr, A->val,
-                       (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val);
+                       (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val, flag, A->sdia_sym);
     APCG_CHECK_LAUNCH("k_sdia_fill");
+    if (A->sdia_sym) {
+        hipLaunchKernelGGL(k_sdia_symcheck, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->sdia_off,
+                           (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val, flag);
+        APCG_CHECK_LAUNCH("k_sdia_symcheck");
+    }
     return APCG_SUCCESS;
 }
 

@@ -463,3 +463,74 @@ def test_sliced_diagonals_plane_marching(apcg, ctx, which):
         assert rel(x, ref.x) <= 1e-9
         res, x = gpu_solve(apcg, ctx, A, b, 0.0, 20, spmv=spmv)
         assert res["iterations"] == 20 and rel(x, x_plain) <= 1e-13
+
+
+def with_stored_zero(A):
+    """A with one explicitly stored zero at (0, n-1) and none at (n-1, 0): the
+    same operator, a structurally unsymmetric pattern."""
+    rowptr = A.rowptr.copy()
+    rowptr[1:] += 1
+    e = int(A.rowptr[1])
+    col = np.insert(A.col, e, A.n - 1).astype(np.int32)
+    val = np.insert(A.val, e, 0.0)
+    return P.CSR(n=A.n, rowptr=rowptr, col=col, val=val)
+
+
+@pytest.mark.parametrize("which", ["diffusion_10x16x16", "banded_1050_128", "box27_8x8x16"])
+def test_sliced_diagonals_symmetric_reads_bitwise(apcg, ctx, which):
+    """With symmetric values the marching product reads each entry left of
+    the diagonal as its transpose (carried for the -plane offset, from the
+    same or an earlier slice otherwise).  A twin with one stored zero that
+    breaks the pattern's symmetry (same operator, every slot read directly)
+    gives bit for bit the same solves at the same launch shape."""
+    rng = np.random.default_rng(50)
+    if which == "diffusion_10x16x16":
+        A = P.diffusion_csr(np.exp(rng.standard_normal((10, 16, 16))), aniso=2.0)
+    elif which == "banded_1050_128":
+        A = banded(1050, 128)
+    else:
+        A = P.stencil_laplacian((8, 8, 16), 27)
+    T = with_stored_zero(A)
+    b = rng.uniform(-1, 1, A.n)
+    ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
+    for spmv in [(2, 256, 0, 3), (8, 512, 0, 3)]:
+        print(f"case symmetric reads {which} spmv={spmv}", flush=True)
+        r_s, x_s = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=spmv)
+        r_t, x_t = gpu_solve(apcg, ctx, T, b, 1e-10, 5000, spmv=spmv)
+        assert r_s["status"] == apcg.APCG_SOLVE_CONVERGED and abs(r_s["iterations"] - ref.its) <= 1
+        assert rel(x_s, ref.x) <= 1e-9
+        assert r_s["iterations"] == r_t["iterations"] and r_s["res_norm"] == r_t["res_norm"]
+        assert np.array_equal(x_s, x_t)
+
+
+def test_sliced_diagonals_symmetry_rechecked_each_solve(apcg, ctx):
+    """The value-symmetry check runs with every refill: one entry left of the
+    diagonal changed in place (values no longer symmetric) is read as
+    stored, and restoring it brings the transposed reads back; each solve
+    meets the oracle's bar for the values it was given."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    rng = np.random.default_rng(51)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((10, 16, 16))), aniso=2.0)
+    b = rng.uniform(-1, 1, A.n)
+    dA, db = DeviceCSR(A), DeviceVec(b)
+    apcg.apcg_mat_set_spmv_config(dA.h, 4, 256, 0, apcg.APCG_SPMV_SDIA)
+    row = A.n // 2 + 7
+    k = int(A.rowptr[row])  # the row's first entry, left of the diagonal
+    assert A.col[k] < row
+    info = apcg.apcg_info_create(0, 1)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    for factor in (1.0, 1.25, 1.0):
+        print(f"case symmetry recheck factor={factor}", flush=True)
+        val = A.val.copy()
+        val[k] *= factor
+        dA.val.copy_(torch.from_numpy(val))
+        torch.cuda.synchronize()
+        dx = DeviceVec.zeros(A.n)
+        apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, 1e-10, 5000, opts, info, 0)
+        res = apcg.apcg_info_get(info, 0)
+        ref = oracle.pcg(P.CSR(n=A.n, rowptr=A.rowptr, col=A.col, val=val), b, rtol=1e-10, maxit=5000)
+        assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
+        assert rel(dx.numpy(), ref.x) <= 1e-9
+    apcg.apcg_info_destroy(info)
