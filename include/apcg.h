@@ -379,7 +379,8 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       (synchronously) and snapshots the pattern: the columns must not
  *       change afterwards (values may, they are refilled at the start of
  *       every solve).  A lone MatMult reads the CSR arrays, as for
- *       APCG_SPMV_SELL.  lanes_per_row > 1 selects plane marching when the
+ *       APCG_SPMV_SELL.  lanes_per_row > 1 (any value up to 64 for this
+ *       schedule: planes per task) selects plane marching when the
  *       pattern has a plane stride (an offset 64 Ps, Ps < 65536 slices,
  *       present with both signs in at least half of the slices): each
  *       wavefront walks lanes_per_row slices one plane apart and carries the

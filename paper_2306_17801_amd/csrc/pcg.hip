@@ -1538,10 +1538,15 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
             if (lpr == -3 && !(sdia_ok && A->sdia_ps > 0)) continue;
             for (int tb : {256, 512}) {
                 if (lpr == 0 && !stream_fits(A, tb)) continue;
-                for (int blocks : {256, 512, 1024, 2048, 4096, 8192}) {
-                    if (lpr == -3 && blocks > 2048) continue;
-                    const int seg = blocks / 256;  // 1, 2, 4, 8 -> 2, 4, 8 planes (1 is skipped)
-                    if (lpr == -3 && seg < 2) continue;
+                // marching: planes per task (how many tasks fill the resident
+                // wavefronts depends on the grid's plane count); otherwise
+                // the grid size
+                static const int kGrids[] = {256, 512, 1024, 2048, 4096, 8192};
+                static const int kPlanes[] = {2, 3, 4, 5, 6, 7, 8, 12, 16};
+                const int *inner = lpr == -3 ? kPlanes : kGrids;
+                const int ninner = lpr == -3 ? 9 : 6;
+                for (int q = 0; q < ninner; ++q) {
+                    const int blocks = inner[q], seg = inner[q];
                     apcg_spmv_config cfg = lpr == -3  ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_SDIA}
                                            : lpr == -2 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SDIA}
                                            : lpr == -1 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}

@@ -439,7 +439,7 @@ def banded(n, far):
 
 @pytest.mark.parametrize("which", ["diffusion_10x16x16", "banded_1050_128", "box27_8x8x16"])
 def test_sliced_diagonals_plane_marching(apcg, ctx, which):
-    """Plane marching (lanes_per_row = planes per task > 1): the +-plane
+    """Plane marching (lanes_per_row = planes per task > 1, any count): the +-plane
     windows are carried between the slices of a column instead of gathered.
     Patterns: a 3D grid whose planes are 4 slices, a banded matrix whose far
     band is 2 slices away with a partial last plane (17 slices), a 27-point
@@ -456,7 +456,7 @@ def test_sliced_diagonals_plane_marching(apcg, ctx, which):
     b = rng.uniform(-1, 1, A.n)
     ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
     _, x_plain = gpu_solve(apcg, ctx, A, b, 0.0, 20, spmv=(1, 256, 0, 3))
-    for spmv in [(2, 256, 0, 3), (4, 512, 0, 3), (8, 256, 0, 3), (64, 512, 0, 3)]:
+    for spmv in [(2, 256, 0, 3), (3, 512, 0, 3), (4, 512, 0, 3), (6, 256, 0, 3), (8, 256, 0, 3), (64, 512, 0, 3)]:
         print(f"case march {which} spmv={spmv}", flush=True)
         res, x = gpu_solve(apcg, ctx, A, b, 1e-10, 5000, spmv=spmv)
         assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
