@@ -418,6 +418,15 @@ apcg_status apcg_mat_get_spmv_config(apcg_mat A, apcg_spmv_config *cfg);
 apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best,
                               double *best_us);
 
+/* Times the two kernels of one PCG iteration at A's current SpMV
+ * configuration: reps launches of the fused product kernel back to back,
+ * then reps launches of the update kernel, each run between a pair of HIP
+ * events on ctx's stream, in the autotuner's timing mode (every load,
+ * reduction and store of the solve; the scalar decisions are not taken).
+ * *product_us and *update_us receive the mean time per launch.  Same
+ * scratch use as apcg_mat_autotune; blocks the host until the runs end. */
+apcg_status apcg_mat_time_kernels(apcg_mat A, apcg_ctx ctx, int32_t reps, double *product_us, double *update_us);
+
 /* ---------------------------------------------------------------------- */
 /* Krylov solve (Section 3.3, the PCG loop; Section 4.1, Jacobi CG)        */
 /* ---------------------------------------------------------------------- */

@@ -352,6 +352,14 @@ def apcg_mat_autotune(A, ctx, reps: int = 20):
             "schedule": cfg.schedule}, us.value
 
 
+def apcg_mat_time_kernels(A, ctx, reps: int = 100):
+    """Mean microseconds per launch of the product and update kernels at
+    A's SpMV configuration (back-to-back launches, HIP events)."""
+    pu, uu = ctypes.c_double(), ctypes.c_double()
+    check("apcg_mat_time_kernels", _L().apcg_mat_time_kernels(_h(A), _h(ctx), reps, ctypes.byref(pu), ctypes.byref(uu)))
+    return pu.value, uu.value
+
+
 # ------------------------------------------------------------------ solve
 
 def apcg_solve_opts_default(**overrides):

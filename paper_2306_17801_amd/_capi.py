@@ -182,6 +182,7 @@ SIGNATURES = {
     "apcg_mat_set_spmv_config": [c_vp, P(apcg_spmv_config)],
     "apcg_mat_get_spmv_config": [c_vp, P(apcg_spmv_config)],
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
+    "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
     "apcg_solve_opts_default": [P(apcg_solve_opts)],
     "apcg_info_create": [c_i32, c_i32, P(c_vp)],
     "apcg_info_destroy": [c_vp],

@@ -1498,6 +1498,58 @@ apcg_status apcg_ctx_kernel_times(apcg_ctx ctx, int32_t kind, double *mean_us, i
     return APCG_SUCCESS;
 }
 
+apcg_status apcg_mat_time_kernels(apcg_mat A, apcg_ctx ctx, int32_t reps, double *product_us, double *update_us) {
+    try {
+        if (!A || !ctx || reps < 1 || !product_us || !update_us)
+            return set_error(APCG_ERR_INVALID_ARG, "bad timing arguments");
+        if (ctx->device != A->device) return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
+        if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING)
+            return set_error(APCG_ERR_INVALID_ARG, "kernel timing needs a default-stream context");
+        Acc acc[1] = {{&A->rec, ACC_R}};
+        apcg_status s;
+        if ((s = op_begin(ctx, acc, 1))) return s;
+        if ((s = ensure_workspace(ctx, A->n))) return s;
+        hipStream_t st = ctx->stream;
+        const int64_t n = A->n;
+        hipLaunchKernelGGL(k_tune_fill, dim3(1024), dim3(VB), 0, st, ctx->ws.r(), ctx->ws.dinv(), ctx->ws.p(0),
+                           ctx->ws.z(), n);
+        APCG_CHECK_LAUNCH("k_tune_fill");
+        if (A->cfg.schedule == APCG_SPMV_SELL && (s = prepare_sell(A, st))) return s;
+        if (A->cfg.schedule == APCG_SPMV_SDIA && (s = prepare_sdia(A, st))) return s;
+        Plan pl;
+        if ((s = make_plan(A, A->cfg, &pl))) return s;
+        double *xs = nullptr;  // stand-in for x: the timed update writes it
+        APCG_HIP(hipMalloc((void **)&xs, sizeof(double) * std::max<int64_t>(n, 1)));
+        APCG_HIP(hipMemsetAsync(xs, 0, sizeof(double) * std::max<int64_t>(n, 1), st));
+        Bufs bf{A, xs, nullptr, ctx->ws, ctx->partials};
+        hipEvent_t ev[3];
+        for (auto &e : ev) APCG_HIP(hipEventCreate(&e));
+        for (int w = 0; w < 2; ++w) {
+            if ((s = launch_product(st, pl, bf, 1, 1))) return s;
+            if ((s = launch_update(st, pl, bf, 1, 0, 1))) return s;
+        }
+        APCG_HIP(hipEventRecord(ev[0], st));
+        for (int r = 0; r < reps; ++r)
+            if ((s = launch_product(st, pl, bf, 1, 1))) return s;
+        APCG_HIP(hipEventRecord(ev[1], st));
+        for (int r = 0; r < reps; ++r)
+            if ((s = launch_update(st, pl, bf, 1, 0, 1))) return s;
+        APCG_HIP(hipEventRecord(ev[2], st));
+        g_counters.host_syncs++;
+        APCG_HIP(hipEventSynchronize(ev[2]));
+        float m0 = 0.f, m1 = 0.f;
+        APCG_HIP(hipEventElapsedTime(&m0, ev[0], ev[1]));
+        APCG_HIP(hipEventElapsedTime(&m1, ev[1], ev[2]));
+        for (auto &e : ev) hipEventDestroy(e);
+        hipFree(xs);  // the stream is idle here (synchronised on the last event)
+        *product_us = 1000.0 * m0 / reps;
+        *update_us = 1000.0 * m1 / reps;
+        return op_end(ctx, acc, 1);
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
 apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best, double *best_us) {
     try {
         if (!A || !ctx || reps < 1) return set_error(APCG_ERR_INVALID_ARG, "bad autotune arguments");

@@ -191,3 +191,30 @@ def test_autotune_picks_a_valid_schedule(apcg, ctx):
     cfg, us = apcg.apcg_mat_autotune(dA.h, ctx, 3)
     assert us > 0 and cfg["block_size"] in (256, 512) and cfg["schedule"] in (0, 1, 2, 3)
     assert apcg.apcg_mat_get_spmv_config(dA.h) == cfg
+
+
+@pytest.mark.parametrize("spmv", [(1, 256, 0, 0), (1, 512, 64, 2), (4, 512, 0, 3), (1, 256, 0, 3)])
+def test_time_kernels(apcg, ctx, spmv):
+    """Back-to-back timing of the product and update kernels at the matrix's
+    configuration: positive means, the configuration unchanged, and the
+    matrix still solves to the oracle's bar afterwards (the timing runs on
+    scratch vectors)."""
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    A = P.laplace_3d(24)
+    dA = DeviceCSR(A)
+    apcg.apcg_mat_set_spmv_config(dA.h, *spmv)
+    before = apcg.apcg_mat_get_spmv_config(dA.h)
+    print(f"case time_kernels spmv={spmv}", flush=True)
+    pu, uu = apcg.apcg_mat_time_kernels(dA.h, ctx, 5)
+    assert pu > 0 and uu > 0 and pu < 1e5 and uu < 1e5
+    assert apcg.apcg_mat_get_spmv_config(dA.h) == before
+    b = np.random.default_rng(53).uniform(-1, 1, A.n)
+    db, dx = DeviceVec(b), DeviceVec.zeros(A.n)
+    info = apcg.apcg_info_create(0, 1)
+    apcg.apcg_ksp_solve(ctx, dA.h, db.h, dx.h, 1e-10, 5000, apcg.apcg_solve_opts_default(x0_is_zero=1), info, 0)
+    res = apcg.apcg_info_get(info, 0)
+    apcg.apcg_info_destroy(info)
+    ref = oracle.pcg(A, b, rtol=1e-10, maxit=5000)
+    assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
+    assert np.linalg.norm(dx.numpy() - ref.x) <= 1e-9 * np.linalg.norm(ref.x)
