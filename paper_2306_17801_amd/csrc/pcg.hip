@@ -613,7 +613,7 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
 // The marching tasks of one wavefront; returns its share of p.Ap.  SYM:
 // entries left of the diagonal read as their transposes (one load each, at
 // the partner slot's address; no branches on the offsets).
-template <int TB, int W, bool SYM>
+template <int TB, int W, int UC, bool SYM>
 __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restrict__ soff,
                                               const uint64_t *__restrict__ smask, const double *__restrict__ sval,
                                               const double *__restrict__ z, const double *__restrict__ pold,
@@ -652,13 +652,13 @@ __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restri
             double ac[W];
             bool in[W];
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
+            for (int k = 0; k < UC; ++k) {
                 oc[k] = o[k];
                 mc[k] = m[k];
                 qc[k] = SYM ? pt[k] : 0;
             }
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
+            for (int k = 0; k < UC; ++k) {
                 in[k] = (mc[k] >> lane) & 1ull;
                 if constexpr (SYM) {
                     // own slot, or for an entry left of the diagonal the
@@ -676,7 +676,7 @@ __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restri
             }
             double zj[W], pj[W];
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
+            for (int k = 0; k < UC; ++k) {
                 const bool carried = oc[k] == up || oc[k] == -up || oc[k] == 0;
                 const int jx = (in[k] && !carried) ? row + oc[k] : rc;
                 const double zg = carried ? 0.0 : z[jx], pg = carried ? 0.0 : pold[jx];
@@ -685,7 +685,7 @@ __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restri
             }
             double sum = 0.0;
 #pragma unroll
-            for (int k = 0; k < W; ++k) {
+            for (int k = 0; k < UC; ++k) {
                 const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
                 sum = in[k] ? t : sum;
             }
@@ -706,8 +706,12 @@ __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restri
     return acc;
 }
 
-template <int TB, int W>
-__global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const int32_t *__restrict__ soff,
+// UC: offset slots walked per slice, a compile-time bound >= U (the slots
+// past U hold no entry in any slice): 5 or 7 for the 2D and 3D 5/7-point
+// patterns keeps the unused slot's loads and registers out of the kernel,
+// and at most 72 VGPRs (asked for below) let 7 wavefronts share a SIMD.
+template <int TB, int W, int UC>
+__global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(UC <= 7 ? 7 : 1))) void k_pcg_product_sdia_march(int32_t n, const int32_t *__restrict__ soff,
                                                                const int32_t *__restrict__ smask_words,
                                                                const double *__restrict__ sval,
                                                                const double *__restrict__ z,
@@ -723,8 +727,8 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia_march(int32_t n, const 
     const int sym = __builtin_amdgcn_readfirstlane(soff[2 * (int64_t)nsl * W]);
     double beta;
     if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
-    const double acc = sym ? march_tasks<TB, W, true>(n, soff, smask, sval, z, pold, pnew, w, lb, beta, U, seg, Ps)
-                           : march_tasks<TB, W, false>(n, soff, smask, sval, z, pold, pnew, w, lb, beta, U, seg, Ps);
+    const double acc = sym ? march_tasks<TB, W, UC, true>(n, soff, smask, sval, z, pold, pnew, w, lb, beta, U, seg, Ps)
+                           : march_tasks<TB, W, UC, false>(n, soff, smask, sval, z, pold, pnew, w, lb, beta, U, seg, Ps);
     double v[1] = {acc};
     dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
 }
@@ -907,9 +911,15 @@ ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_
     if (cfg.schedule == APCG_SPMV_SDIA) {
         const bool b512 = cfg.block_size == 512;
         if (cfg.lanes_per_row > 1 && sdia_ps > 0) {  // plane marching
-            if (sdia_mp == 8) return b512 ? k_pcg_product_sdia_march<512, 8> : k_pcg_product_sdia_march<256, 8>;
-            if (sdia_mp == 16) return b512 ? k_pcg_product_sdia_march<512, 16> : k_pcg_product_sdia_march<256, 16>;
-            return b512 ? k_pcg_product_sdia_march<512, 32> : k_pcg_product_sdia_march<256, 32>;
+            const int U = lds_nnz & 0xff;
+            if (sdia_mp == 8 && U <= 5)
+                return b512 ? k_pcg_product_sdia_march<512, 8, 5> : k_pcg_product_sdia_march<256, 8, 5>;
+            if (sdia_mp == 8 && U <= 7)
+                return b512 ? k_pcg_product_sdia_march<512, 8, 7> : k_pcg_product_sdia_march<256, 8, 7>;
+            if (sdia_mp == 8) return b512 ? k_pcg_product_sdia_march<512, 8, 8> : k_pcg_product_sdia_march<256, 8, 8>;
+            if (sdia_mp == 16)
+                return b512 ? k_pcg_product_sdia_march<512, 16, 16> : k_pcg_product_sdia_march<256, 16, 16>;
+            return b512 ? k_pcg_product_sdia_march<512, 32, 32> : k_pcg_product_sdia_march<256, 32, 32>;
         }
         if (sdia_mp == 8) return b512 ? k_pcg_product_sdia<512, 8> : k_pcg_product_sdia<256, 8>;
         if (sdia_mp == 16) return b512 ? k_pcg_product_sdia<512, 16> : k_pcg_product_sdia<256, 16>;
