@@ -390,7 +390,10 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       and the values are symmetric bit for bit (checked on the device at
  *       every refill), the marching product reads each entry left of the
  *       diagonal as its transpose, so only the slots on and right of the
- *       diagonal stream from memory; the sums are unchanged.
+ *       diagonal stream from memory; the sums are unchanged.  Once a refill
+ *       finds the values unsymmetric, the matrix reads every slot from then
+ *       on (until its schedule is analysed again, i.e. never for this
+ *       handle).
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so

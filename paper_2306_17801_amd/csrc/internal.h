@@ -192,7 +192,8 @@ struct apcg_mat_s {
     int32_t sdia_sym = 0;            // 1: the pattern is structurally symmetric
     int32_t *sdia_off = nullptr;     // device [nslices * sdia_mp] offsets (padding 0), then
                                      //   [nslices * sdia_mp] partner slots of the entries left of
-                                     //   the diagonal, then the value-symmetry flag (64 ints)
+                                     //   the diagonal, then the value-symmetry flag (64 ints; set
+                                     //   by the analysis, only ever cleared on the device)
     uint64_t *sdia_msk = nullptr;    // device [nslices * sdia_mp] row masks, padding 0
     double *sdia_val = nullptr;      // device [nslices * sdia_u * 64] values, absent entries 0
     apcg::Record rec;

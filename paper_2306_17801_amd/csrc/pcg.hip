@@ -736,15 +736,11 @@ __global__ __launch_bounds__(TB) __attribute__((amdgpu_waves_per_eu(UC <= 7 ? 7 
 // Fills the sliced-diagonal value copy from the CSR values: thread
 // (slice, lane) walks its row's entries in order, one per set mask bit, and
 // writes 0 to the slots its row does not hold.
-// Thread 0 also sets the value-symmetry flag to the pattern's structural
-// symmetry (k_sdia_symcheck, queued after it, clears it on a mismatch).
 __global__ __launch_bounds__(256) void k_sdia_fill(int32_t n, const int32_t *__restrict__ rowptr,
                                                    const double *__restrict__ val, const uint64_t *__restrict__ smask,
-                                                   int32_t U, int32_t MP, double *__restrict__ sval,
-                                                   int32_t *__restrict__ symflag, int32_t structural) {
+                                                   int32_t U, int32_t MP, double *__restrict__ sval) {
     const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t nsl = ((int64_t)n + 63) / 64;
-    if (g == 0) symflag[0] = structural;
     if (g >= nsl * 64) return;
     const int64_t sl = g >> 6;
     const int lane = (int)(g & 63);
@@ -761,6 +757,9 @@ __global__ __launch_bounds__(256) void k_sdia_fill(int32_t n, const int32_t *__r
 // compares each of its row's entries left of the diagonal, bit for bit, with
 // its transpose's copy (the partner slot, see sdia_analyse) and clears the
 // flag on any difference, so that the products read every slot themselves.
+// The flag is only ever cleared on the device (the analysis sets it once):
+// a product running on another stream never sees it set for values found
+// unequal, and after such a refill the matrix keeps reading every slot.
 __global__ __launch_bounds__(256) void k_sdia_symcheck(int32_t n, const int32_t *__restrict__ soff,
                                                        const uint64_t *__restrict__ smask, int32_t U, int32_t MP,
                                                        const double *__restrict__ sval, int32_t *__restrict__ symflag) {
@@ -1144,6 +1143,7 @@ apcg_status sdia_analyse(apcg_mat_s *A) {
                 }
         }
         A->sdia_sym = sym ? 1 : 0;
+        off_h[2 * nsl * MP] = A->sdia_sym;  // the value-symmetry flag, cleared by the check at a mismatch
         APCG_HIP(hipMalloc((void **)&A->sdia_off, sizeof(int32_t) * off_h.size()));
         APCG_HIP(hipMalloc((void **)&A->sdia_msk, sizeof(uint64_t) * nsl * MP));
         APCG_HIP(hipMalloc((void **)&A->sdia_val, sizeof(double) * slots));
@@ -1170,7 +1170,7 @@ apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s) {
     const int64_t blocks = (nsl * 64 + 255) / 256;
     int32_t *flag = A->sdia_off + 2 * nsl * A->sdia_mp;
     hipLaunchKernelGGL(k_sdia_fill, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->rowptr, A->val,
-                       (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val, flag, A->sdia_sym);
+                       (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val);
     APCG_CHECK_LAUNCH("k_sdia_fill");
     if (A->sdia_sym) {
         hipLaunchKernelGGL(k_sdia_symcheck, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->sdia_off,

@@ -506,8 +506,9 @@ def test_sliced_diagonals_symmetric_reads_bitwise(apcg, ctx, which):
 def test_sliced_diagonals_symmetry_rechecked_each_solve(apcg, ctx):
     """The value-symmetry check runs with every refill: one entry left of the
     diagonal changed in place (values no longer symmetric) is read as
-    stored, and restoring it brings the transposed reads back; each solve
-    meets the oracle's bar for the values it was given."""
+    stored, and after restoring it the matrix keeps reading every slot (the
+    flag is only cleared); each solve meets the oracle's bar for the values
+    it was given."""
     import torch
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
