@@ -538,6 +538,8 @@ apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec 
  *     dominate.  A system whose matrix is on APCG_SPMV_SDIA with 8
  *     offset slots per slice has its tile product read the sliced-diagonal
  *     copy (same row sums, bit for bit); every other system reads CSR.
+ *     The tile product walks 5, 7 or 8 offset slots per row, the fewest
+ *     that cover every such system of the batch.
  *   APCG_BATCH_AUTO: persistent when no system costs more than 1/CUs of the
  *     batch, else segmented.
  * A, b, x: arrays of nsys handles on ctx's device (the x[i] distinct and not

@@ -711,6 +711,8 @@ __global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
     });
 }
 
+// UC: sliced-diagonal slots walked per row (>= every such system's U).
+template <int UC>
 __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
     __shared__ double lds[ST / 64];
     for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
@@ -728,7 +730,7 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
             // the tile's rows start at a multiple of 256 of its system, so
             // each wavefront's rows are one 64-row slice
             const double sum =
-                S.sval ? dev::sdia_row<8>(S.soff, S.smask, S.sval, S.U, n, i,
+                S.sval ? dev::sdia_row<8, UC>(S.soff, S.smask, S.sval, S.U, n, i,
                                           [&](int q) { return fma(beta, pold[q], z[q]); })
                        : row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
             const double pi = fma(beta, pold[i], z[i]);
@@ -985,8 +987,14 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     int K = std::max(2, opts.iters_per_graph);
     if (K & 1) ++K;
     const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
+    int umax = 0;  // most sliced-diagonal slots of any system that reads them
+    for (int32_t i = 0; i < nsys; ++i)
+        if (hsys[i].sval) umax = std::max<int>(umax, hsys[i].U);
+    void (*seg_product)(SegPlan, int) = umax <= 5   ? k_seg_product<5>
+                                        : umax <= 7 ? k_seg_product<7>
+                                                    : k_seg_product<8>;
     auto launch_iter = [&](int j) -> apcg_status {
-        hipLaunchKernelGGL(k_seg_product, dim3(G), dim3(ST), 0, st, P, j & 1);
+        hipLaunchKernelGGL(seg_product, dim3(G), dim3(ST), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_seg_product");
         hipLaunchKernelGGL(k_seg_alpha, dim3(nsys), dim3(64), 0, st, P);
         APCG_CHECK_LAUNCH("k_seg_alpha");
@@ -1000,7 +1008,8 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     const void *dsp = d_sys;
     gh = fnv1a(&dsp, sizeof dsp, gh);
     double prm[1] = {rtol};
-    int iprm[5] = {K, maxit, norm_pre, G, nsys};
+    const int uc = umax <= 5 ? 5 : umax <= 7 ? 7 : 8;  // which tile product the graph holds
+    int iprm[6] = {K, maxit, norm_pre, G, nsys, uc};
     gh = fnv1a(prm, sizeof prm, gh);
     gh = fnv1a(iprm, sizeof iprm, gh);
     apcg_status s;

@@ -204,7 +204,7 @@ __device__ bool fcg_check(FcgState *st, const double *part_res, int G, int parit
 // (forms z and the partials of r.z and z.w).  check != 0 (inside the
 // iteration): the first step first runs the test above for the iteration of
 // the given parity.
-// L: 0 = CSR products, 8/16/32 = the sliced-diagonal copy (dev::mat_row).
+// L: 0 = CSR products, 5/7/8/16/32 = the sliced-diagonal copy (dev::mat_row).
 template <int L>
 __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, dev::RowMat M,
                                               const double *__restrict__ r, const double *__restrict__ dinv,
@@ -479,12 +479,13 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
         if ((s = sdia_analyse(A))) return s;
         if (A->sdia_state == 1) {
             if ((s = prepare_sdia(A, st))) return s;
-            lw = A->sdia_mp;
+            lw = sdia_walk(A);
         }
         const dev::RowMat M{A->rowptr, A->col, A->val, A->sdia_off, A->sdia_msk, A->sdia_val, A->sdia_u};
-        auto fcheb = lw == 8 ? k_cheb<8> : lw == 16 ? k_cheb<16> : lw == 32 ? k_cheb<32> : k_cheb<0>;
-        auto fprod = lw == 8 ? k_fcg_product<8> : lw == 16 ? k_fcg_product<16> : lw == 32 ? k_fcg_product<32>
-                                                                                      : k_fcg_product<0>;
+        auto fcheb = lw == 5 ? k_cheb<5> : lw == 7 ? k_cheb<7> : lw == 8 ? k_cheb<8> : lw == 16 ? k_cheb<16>
+                   : lw == 32 ? k_cheb<32> : k_cheb<0>;
+        auto fprod = lw == 5 ? k_fcg_product<5> : lw == 7 ? k_fcg_product<7> : lw == 8 ? k_fcg_product<8>
+                   : lw == 16 ? k_fcg_product<16> : lw == 32 ? k_fcg_product<32> : k_fcg_product<0>;
 
         hipLaunchKernelGGL(k_fcg_init, dim3(G), dim3(TBF), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d, r, dinv,
                            pb[0], part + (size_t)S_INIT * kMaxBlocks, pbk, x0z);

@@ -224,6 +224,12 @@ apcg_status sdia_analyse(apcg_mat_s *A);
 // queues the refill of the sliced-diagonal values on stream s (pcg.hip);
 // analyses first if needed, APCG_ERR_UNSUPPORTED when the layout does not apply
 apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s);
+// Row-helper width for an analysed sliced-diagonal matrix: 5 or 7 when the
+// 8-wide copy holds at most that many offsets per slice, else its width.
+inline int sdia_walk(const apcg_mat_s *A) {
+    if (A->sdia_mp != 8) return A->sdia_mp;
+    return A->sdia_u <= 5 ? 5 : A->sdia_u <= 7 ? 7 : 8;
+}
 // Jacobi-PCG solve with registry marking (pcg.hip); hist (2 hist_cap doubles,
 // device) receives alpha_k and beta_k of the first hist_cap iterations.
 apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
@@ -529,7 +535,9 @@ __device__ inline void feature_vector(const double *st, double var, const double
 // fma(a_ij, u(j), sum).  Every active lane of the calling wavefront must hold
 // a row of the same 64-row slice; rows >= n contribute nothing (their masks
 // are 0).  All loads are issued unconditionally at in-bounds addresses.
-template <int W, typename F>
+// UC <= W: the slots walked, a compile-time bound >= the matrix's U (slots
+// past U hold no entry in any slice).
+template <int W, int UC = W, typename F>
 __device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
                                            const double *__restrict__ sval, int U, int64_t n, int64_t row, F u) {
     const int64_t sl = __builtin_amdgcn_readfirstlane((int)(row >> 6));
@@ -541,7 +549,7 @@ __device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, con
     double a[W], g[W];
     bool in[W];
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
+    for (int k = 0; k < UC; ++k) {
         const int ok = o[k];
         const uint64_t mk = m[k];
         a[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
@@ -550,7 +558,7 @@ __device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, con
     }
     double sum = 0.0;
 #pragma unroll
-    for (int k = 0; k < W; ++k) {
+    for (int k = 0; k < UC; ++k) {
         const double t = fma(a[k], g[k], sum);
         sum = in[k] ? t : sum;
     }
@@ -571,11 +579,12 @@ struct RowMat {
 // sum_j a_ij u(j) of row i, entries in column-storage order with one FMA
 // each: L = 0 reads the CSR arrays (rows of up to 8 entries issue every
 // gather before the first FMA), L = 8/16/32 the sliced-diagonal copy of that
-// slot width (then each wavefront's rows must be one 64-row slice).
+// slot width, L = 5/7 the 8-wide copy walking 5/7 slots (U <= L) (then each
+// wavefront's rows must be one 64-row slice).
 template <int L, typename F>
 __device__ __forceinline__ double mat_row(const RowMat &M, int64_t n, int64_t i, F u) {
     if constexpr (L > 0) {
-        return sdia_row<L>(M.soff, M.smask, M.sval, M.U, n, i, u);
+        return sdia_row<(L < 8 ? 8 : L), L>(M.soff, M.smask, M.sval, M.U, n, i, u);
     } else {
         const int s = M.rowptr[i], e = M.rowptr[i + 1];
         const int len = e - s;

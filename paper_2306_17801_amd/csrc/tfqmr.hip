@@ -453,7 +453,7 @@ extern "C" apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b
         if ((s = sdia_analyse(A))) return s;
         if (A->sdia_state == 1) {
             if ((s = prepare_sdia(A, st))) return s;
-            lw = A->sdia_mp;
+            lw = sdia_walk(A);
         }
         const TqMat M{A->rowptr, A->col, A->val, A->sdia_off, A->sdia_msk, A->sdia_val, A->sdia_u};
         auto sync_if = [&]() -> apcg_status {
@@ -471,14 +471,17 @@ extern "C" apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b
         hipLaunchKernelGGL(k_tq_init_final, dim3(1), dim3(64), 0, st, tc->st, (const double *)part, G, rtol, maxit);
         APCG_CHECK_LAUNCH("k_tq_init_final");
         {
-            auto f = lw == 8 ? k_tq_init_product<8> : lw == 16 ? k_tq_init_product<16>
+            auto f = lw == 5 ? k_tq_init_product<5> : lw == 7 ? k_tq_init_product<7>
+                   : lw == 8 ? k_tq_init_product<8> : lw == 16 ? k_tq_init_product<16>
                    : lw == 32 ? k_tq_init_product<32> : k_tq_init_product<0>;
             hipLaunchKernelGGL(f, dim3(G), dim3(TBQ), 0, st, A->n, M, (const double *)bd, (const double *)r0,
                                (const double *)y1, u1, v, (const TqState *)tc->st, part, pb);
             APCG_CHECK_LAUNCH("k_tq_init_product");
         }
-        auto fa = lw == 8 ? k_tq_a<8> : lw == 16 ? k_tq_a<16> : lw == 32 ? k_tq_a<32> : k_tq_a<0>;
-        auto fd = lw == 8 ? k_tq_d<8> : lw == 16 ? k_tq_d<16> : lw == 32 ? k_tq_d<32> : k_tq_d<0>;
+        auto fa = lw == 5 ? k_tq_a<5> : lw == 7 ? k_tq_a<7> : lw == 8 ? k_tq_a<8> : lw == 16 ? k_tq_a<16>
+                : lw == 32 ? k_tq_a<32> : k_tq_a<0>;
+        auto fd = lw == 5 ? k_tq_d<5> : lw == 7 ? k_tq_d<7> : lw == 8 ? k_tq_d<8> : lw == 16 ? k_tq_d<16>
+                : lw == 32 ? k_tq_d<32> : k_tq_d<0>;
         if ((s = sync_if())) return s;
 
         auto iteration = [&](int j) -> apcg_status {
