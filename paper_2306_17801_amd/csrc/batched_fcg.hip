@@ -46,8 +46,13 @@ struct FSys {
     const double *b;
     double *x;
     double *ws;  // 9 n: r, dinv, z, p0, p1, w, t0, t1, t2
+    // the sliced-diagonal copy (8 offset slots per slice) when the matrix is
+    // on that schedule, else null: the tile products read it
+    const int32_t *soff;
+    const uint64_t *smask;
+    const double *sval;
     int32_t n;
-    int32_t pad;
+    int32_t U;
 };
 
 struct FState {
@@ -289,6 +294,8 @@ __global__ __launch_bounds__(FT) void k_bf_zero_x(FPlan P) {
     });
 }
 
+// UC: sliced-diagonal slots walked per row (>= every such system's U).
+template <int UC>
 __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
     for_active_tiles(P, [](const FState &q) { return !q.flag && !q.restart; }, [&](int t) {
         const int s = P.tile_sys[t];
@@ -303,8 +310,10 @@ __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
         const int i = P.tile_row0[t] + threadIdx.x;
         double v[1] = {0.0};
         if (i < S.n) {
-            const double sum = frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i,
-                                    [&](int j) { return fma(beta, pold[j], z[j]); });
+            auto u = [&](int j) { return fma(beta, pold[j], z[j]); };
+            // tiles start at multiples of FT rows: a wavefront's rows are one slice
+            const double sum = S.sval ? dev::sdia_row<8, UC>(S.soff, S.smask, S.sval, S.U, n, i, u)
+                                      : frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u);
             const double pi = fma(beta, pold[i], z[i]);
             pnew[i] = pi;
             w[i] = sum;
@@ -394,6 +403,7 @@ __global__ __launch_bounds__(64) void k_bf_check(FPlan P) {
 // stage 1: b_j = c_j v + 2 Y b_{j+1} - b_{j+2}; stage 2: z = c_0 v + Y b_1 - b_2
 // and the partials of r.z, z.w (Jacobi mode: z = v).  Y = (2/lmax) D^-1 A - I,
 // v = D^-1 r; b_8 = c_8 v is formed where it is needed.
+template <int UC>
 __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o_b1, int o_b2, int o_out) {
     for_active_tiles(P, [stage](const FState &q) { return !q.flag && (stage == 2 || q.mode != MODE_JACOBI); },
                      [&](int t) {
@@ -410,16 +420,19 @@ __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o
         const int i = P.tile_row0[t] + threadIdx.x;
         double v[2] = {0.0, 0.0};
         if (i < S.n) {
-            const int rs = S.rowptr[i], re = S.rowptr[i + 1];
+            auto row = [&](auto u) {
+                return S.sval ? dev::sdia_row<8, UC>(S.soff, S.smask, S.sval, S.U, n, i, u)
+                              : frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u);
+            };
             const double vi = dinv[i] * r[i];
             double res;
             if (jac) {
                 res = vi;
             } else if (stage == 0) {
-                const double av = frow(S.col, S.val, rs, re, i, [&](int k) { return dinv[k] * r[k]; });
+                const double av = row([&](int k) { return dinv[k] * r[k]; });
                 res = fma(2.0 * cd, s2 * dinv[i] * av - vi, cj * vi);
             } else {
-                const double au = frow(S.col, S.val, rs, re, i, [&](int k) { return bj1[k]; });
+                const double au = row([&](int k) { return bj1[k]; });
                 const double yu = s2 * dinv[i] * au - bj1[i];
                 const double b2v = bj2 ? bj2[i] : cd * vi;
                 res = stage == 1 ? fma(2.0, yu, cj * vi) - b2v : cj * vi + yu - b2v;
@@ -671,10 +684,15 @@ struct BfRun {
 // systems (ws holds workspace offsets on entry); xs_base != nullptr: x of
 // system i is xs_base + its workspace offset / 9 (the feature run's scratch).
 static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<FSys> &hs, int64_t ws_total,
-                           double rtol, int32_t maxit, const apcg_solve_opts &opts, const apcg_fcg_opts &fo,
-                           const BfRun &run, apcg_solve_info *d_info) {
+                           const std::vector<apcg_mat_s *> &refill, double rtol, int32_t maxit,
+                           const apcg_solve_opts &opts, const apcg_fcg_opts &fo, const BfRun &run,
+                           apcg_solve_info *d_info) {
     const int dev = ctx->device;
     hipStream_t st = ctx->stream;
+    for (apcg_mat_s *m : refill) {  // the sliced-diagonal values of the systems that read them
+        apcg_status ps = prepare_sdia(m, st);
+        if (ps) return ps;
+    }
     std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
     for (int32_t q = 0; q < nsys; ++q) {
         sys_tile0[q] = (int32_t)tile_sys.size();
@@ -773,9 +791,15 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     int K = std::max(2, opts.iters_per_graph);
     if (K & 1) ++K;
     const int L = std::max(1, std::min(kMaxLookahead, opts.lookahead));
+    int umax = 0;  // most sliced-diagonal slots of any system that reads them
+    for (int32_t i = 0; i < nsys; ++i)
+        if (hs[i].sval) umax = std::max<int>(umax, hs[i].U);
+    const int uc = umax <= 5 ? 5 : umax <= 7 ? 7 : 8;
+    void (*bf_product)(FPlan, int) = uc == 5 ? k_bf_product<5> : uc == 7 ? k_bf_product<7> : k_bf_product<8>;
+    void (*bf_cheb)(FPlan, int, int, int, int, int) = uc == 5 ? k_bf_cheb<5> : uc == 7 ? k_bf_cheb<7> : k_bf_cheb<8>;
     // Clenshaw buffers t0..t2 round robin: b_j in t[j % 3]
     auto launch_iter = [&](int j) -> apcg_status {
-        hipLaunchKernelGGL(k_bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
+        hipLaunchKernelGGL(bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_bf_product");
         hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(64), 0, st, P);
         APCG_CHECK_LAUNCH("k_bf_alpha");
@@ -789,7 +813,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
             const int ob1 = stage == 0 ? -1 : (d + 1) % 3;
             const int ob2 = (stage == 0 || d + 2 == FDEG) ? -1 : (d + 2) % 3;
             const int oout = stage == 2 ? -1 : d % 3;
-            hipLaunchKernelGGL(k_bf_cheb, dim3(G), dim3(FT), 0, st, P, d, stage, ob1, ob2, oout);
+            hipLaunchKernelGGL(bf_cheb, dim3(G), dim3(FT), 0, st, P, d, stage, ob1, ob2, oout);
             APCG_CHECK_LAUNCH("k_bf_cheb");
         }
         hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(64), 0, st, P);
@@ -799,7 +823,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     const bool graph = opts.mode == APCG_MODE_GRAPH && !run.force_jacobi;  // feature runs are short: no capture
     uint64_t gh = fnv(&h, sizeof h);
     const double prm[2] = {rtol, fo.stall_frac};
-    const int iprm[7] = {K, maxit, G, nsys, fo.stall_min, P.fallback, P.tiles_per_block};
+    const int iprm[8] = {K, maxit, G, nsys, fo.stall_min, P.fallback, P.tiles_per_block, uc};
     gh = fnv(prm, sizeof prm, gh);
     gh = fnv(iprm, sizeof iprm, gh);
     const void *ptrs[3] = {bc->d_st, bc->d_part, bc->d_running};
@@ -874,7 +898,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
 
 // Checks the systems and builds their descriptors (workspace offsets in ws).
 static apcg_status bf_systems(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b, const apcg_vec *x,
-                              std::vector<FSys> &hs, int64_t *ws_total) {
+                              std::vector<FSys> &hs, int64_t *ws_total, std::vector<apcg_mat_s *> &refill) {
     const int dev = ctx->device;
     hs.resize(nsys);
     int64_t tot = 0;
@@ -888,7 +912,14 @@ static apcg_status bf_systems(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, con
             return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
         const int64_t n = A[i]->n;
         hs[i] = FSys{A[i]->rowptr, A[i]->col, A[i]->val, b[i]->d, x ? x[i]->d : nullptr,
-                     reinterpret_cast<double *>(tot), (int32_t)n, 0};
+                     reinterpret_cast<double *>(tot), nullptr, nullptr, nullptr, (int32_t)n, 0};
+        if (A[i]->cfg.schedule == APCG_SPMV_SDIA && A[i]->sdia_state == 1 && A[i]->sdia_mp == 8) {
+            hs[i].soff = A[i]->sdia_off;
+            hs[i].smask = A[i]->sdia_msk;
+            hs[i].sval = A[i]->sdia_val;
+            hs[i].U = A[i]->sdia_u;
+            refill.push_back(A[i]);
+        }
         tot += ((9 * n + 63) / 64) * 64;
     }
     if (x) {
@@ -916,9 +947,10 @@ static apcg_status bf_common_checks(apcg_ctx ctx, int32_t nsys, const void *A, c
 static apcg_status bf_features(apcg_ctx ctx, BfCache *bc, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
                                float *feat, double *lmax) {
     std::vector<FSys> hs;
+    std::vector<apcg_mat_s *> refill;
     int64_t ws_total = 0;
     apcg_status s;
-    if ((s = bf_systems(ctx, nsys, A, b, nullptr, hs, &ws_total))) return s;
+    if ((s = bf_systems(ctx, nsys, A, b, nullptr, hs, &ws_total, refill))) return s;
     const int dev = ctx->device;
     hipStream_t st = ctx->stream;
     APCG_HIP(hipSetDevice(dev));
@@ -962,7 +994,7 @@ static apcg_status bf_features(apcg_ctx ctx, BfCache *bc, int32_t nsys, const ap
     run.force_jacobi = 1;
     run.hist = bc->d_hist;
     run.hist_cap = FEAT_STEPS;
-    if ((s = bf_core(ctx, bc, nsys, hs, ws_total, 0.0, FEAT_STEPS, o, fo, run, nullptr))) return s;
+    if ((s = bf_core(ctx, bc, nsys, hs, ws_total, refill, 0.0, FEAT_STEPS, o, fo, run, nullptr))) return s;
     FPlan P;
     P.sys = bc->d_sys;
     P.tile_sys = bc->d_tile_sys;
@@ -1016,8 +1048,9 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
         std::vector<FSys> hs;
+        std::vector<apcg_mat_s *> refill;
         int64_t ws_total = 0;
-        if ((s = bf_systems(ctx, nsys, A, b, x, hs, &ws_total))) return s;
+        if ((s = bf_systems(ctx, nsys, A, b, x, hs, &ws_total, refill))) return s;
         std::vector<Acc> acc;
         acc.reserve(3 * nsys + 1);
         for (int32_t i = 0; i < nsys; ++i) {
@@ -1030,7 +1063,7 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
         BfRun run;
         run.coeffs = dev_coeffs;
         run.lmax = dev_lmax;
-        if ((s = bf_core(ctx, bf_cache(ctx), nsys, hs, ws_total, rtol, maxit, opts, fo, run, info->d))) return s;
+        if ((s = bf_core(ctx, bf_cache(ctx), nsys, hs, ws_total, refill, rtol, maxit, opts, fo, run, info->d))) return s;
         return op_end(ctx, acc.data(), (int)acc.size());
     } catch (const std::bad_alloc &) {
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
@@ -1080,8 +1113,9 @@ extern "C" apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
         std::vector<FSys> hs;
+        std::vector<apcg_mat_s *> refill;
         int64_t ws_total = 0;
-        if ((s = bf_systems(ctx, nsys, A, b, x, hs, &ws_total))) return s;
+        if ((s = bf_systems(ctx, nsys, A, b, x, hs, &ws_total, refill))) return s;
         std::vector<Acc> acc;
         acc.reserve(3 * nsys + 1);
         for (int32_t i = 0; i < nsys; ++i) {
@@ -1097,7 +1131,7 @@ extern "C" apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys
         BfRun run;
         run.coeffs = bc->d_C;
         run.lmax = bc->d_L;
-        if ((s = bf_core(ctx, bc, nsys, hs, ws_total, rtol, maxit, opts, fo, run, info->d))) return s;
+        if ((s = bf_core(ctx, bc, nsys, hs, ws_total, refill, rtol, maxit, opts, fo, run, info->d))) return s;
         return op_end(ctx, acc.data(), (int)acc.size());
     } catch (const std::bad_alloc &) {
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");

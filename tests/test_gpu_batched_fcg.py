@@ -83,11 +83,19 @@ def mixed_cases():
     return out
 
 
-def run_batch(apcg, ctx, cases, rtol, maxit, x0=None, fopts=None, **opt):
+def run_batch(apcg, ctx, cases, rtol, maxit, x0=None, fopts=None, sdia=False, **opt):
     import torch
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
     As = [DeviceCSR(c[0]) for c in cases]
+    run_batch.switched = []
+    if sdia:  # every matrix whose pattern allows it on the sliced-diagonal schedule
+        for i, a in enumerate(As):
+            try:
+                apcg.apcg_mat_set_spmv_config(a.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+                run_batch.switched.append(i)
+            except apcg.ApcgError:
+                pass
     bs = [DeviceVec(c[1]) for c in cases]
     xs = [DeviceVec(np.zeros(c[0].n) if x0 is None else x0[i]) for i, c in enumerate(cases)]
     coef = torch.from_numpy(np.concatenate([c[2] for c in cases]).astype(np.float32)).to("cuda:0")
@@ -261,3 +269,21 @@ def test_batched_learned_solve_equals_its_steps(apcg, ctx):
         assert np.array_equal(x1[i].numpy(), x2[i].numpy())
     for inf in (info, info1, info2):
         apcg.apcg_info_destroy(inf)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
+    """Systems whose matrices are on the sliced-diagonal schedule have the
+    tile products and Clenshaw steps read that copy; each row's sum is the
+    CSR one, so the batch is bit for bit the all-CSR batch, and the oracle's
+    bar holds."""
+    cases = mixed_cases()
+    print(f"case batched fcg sdia mode={mode}", flush=True)
+    r_csr, x_csr = run_batch(apcg, ctx, cases, 1e-10, 20000, mode=mode)
+    r_sd, x_sd = run_batch(apcg, ctx, cases, 1e-10, 20000, sdia=True, mode=mode)
+    print("switched", run_batch.switched, flush=True)
+    assert len(run_batch.switched) >= 3
+    for a, b2, xa, xb in zip(r_csr, r_sd, x_csr, x_sd):
+        assert a == b2
+        assert np.array_equal(xa, xb)
+    check_against_oracle(apcg, cases, r_sd, x_sd, 1e-10, 20000)
