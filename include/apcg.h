@@ -654,7 +654,10 @@ apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_v
  * switch to Jacobi-PCG from its current x, taken on the device for that
  * system alone (its status then carries APCG_SOLVE_FALLBACK and the reason).
  * info[i] receives system i's record.  opts: mode (graph/stream),
- * iters_per_graph, lookahead, x0_is_zero.  x vectors must be distinct. */
+ * iters_per_graph, lookahead, x0_is_zero.  x vectors must be distinct.  A
+ * system whose matrix is on APCG_SPMV_SDIA with 8 offset slots per slice
+ * has its products and Clenshaw steps read the sliced-diagonal copy (same
+ * row sums, bit for bit; refilled at the start of every call). */
 apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
                                             const apcg_vec *x, double rtol, int32_t maxit, const float *dev_coeffs,
                                             const double *dev_lmax, const apcg_solve_opts *opts,
