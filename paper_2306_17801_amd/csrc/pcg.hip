@@ -790,18 +790,28 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
                                                    SolveState *st,
                                                    const double *part_delta, int g_delta, double *part_res,
                                                    int64_t per_block, int parity, int norm_pre, int tune) {
-    // the first entries' loads do not depend on alpha: issued before the
-    // reduction of p.Ap so that its latency overlaps them
+    // a thread's entries i0, i0 + VB, i0 + 2 VB, ... in groups of UN whose
+    // loads are all issued before the group's arithmetic (same order of
+    // accumulation as one entry at a time); the first group's loads do not
+    // depend on alpha and are issued before the reduction of p.Ap so that
+    // its latency overlaps them
+    constexpr int UN = 4;
     const dev::Chunk c = dev::block_chunk(n, per_block);
     const int64_t i0 = c.lo + threadIdx.x;
-    double x0 = 0.0, r0 = 0.0, p0 = 0.0, w0 = 0.0, d0 = 0.0;
-    if (i0 < c.hi) {
-        x0 = x[i0];
-        r0 = r[i0];
-        p0 = p[i0];
-        w0 = w[i0];
-        d0 = dinv[i0];
-    }
+    double xs[UN], rs[UN], ps[UN], ws[UN], ds[UN];
+    auto load = [&](int64_t ib) {
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int64_t i = ib + (int64_t)u * VB;
+            const bool ok = i < c.hi;
+            xs[u] = ok ? x[i] : 0.0;
+            rs[u] = ok ? r[i] : 0.0;
+            ps[u] = ok ? p[i] : 0.0;
+            ws[u] = ok ? w[i] : 0.0;
+            ds[u] = ok ? dinv[i] : 0.0;
+        }
+    };
+    load(i0);
     double alpha = 0.0;
     double d[1];
     if (tune) {
@@ -821,21 +831,22 @@ __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict
         if (blockIdx.x == 0 && threadIdx.x == 0 && rec.k <= st->hist_cap) st->hist[rec.k - 1] = alpha;
     }
     double rz = 0.0, nn = 0.0;
-    for (int64_t i = i0; i < c.hi; i += VB) {
-        double xi, ri, pi, wi, di;
-        if (i == i0) {
-            xi = x0, ri = r0, pi = p0, wi = w0, di = d0;
-        } else {
-            xi = x[i], ri = r[i], pi = p[i], wi = w[i], di = dinv[i];
+    for (int64_t ib = i0; ib < c.hi; ib += (int64_t)UN * VB) {
+        if (ib != i0) load(ib);
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+            const int64_t i = ib + (int64_t)u * VB;
+            if (i < c.hi) {
+                const double xi = fma(alpha, ps[u], xs[u]);
+                const double ri = fma(-alpha, ws[u], rs[u]);
+                x[i] = xi;
+                r[i] = ri;
+                const double zi = ds[u] * ri;
+                z[i] = zi;
+                rz = fma(zi, ri, rz);
+                nn = norm_pre ? fma(zi, zi, nn) : fma(ri, ri, nn);
+            }
         }
-        xi = fma(alpha, pi, xi);
-        ri = fma(-alpha, wi, ri);
-        x[i] = xi;
-        r[i] = ri;
-        const double zi = di * ri;
-        z[i] = zi;
-        rz = fma(zi, ri, rz);
-        nn = norm_pre ? fma(zi, zi, nn) : fma(ri, ri, nn);
     }
     double v[2] = {rz, nn};
     dev::store_partials<VB, 2>(v, part_res, gridDim.x, dev::xcd_block(blockIdx.x, gridDim.x));
