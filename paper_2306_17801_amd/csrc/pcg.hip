@@ -1615,9 +1615,9 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
                 // wavefronts depends on the grid's plane count); otherwise
                 // the grid size
                 static const int kGrids[] = {256, 512, 1024, 2048, 4096, 8192};
-                static const int kPlanes[] = {2, 3, 4, 5, 6, 7, 8, 12, 16};
+                static const int kPlanes[] = {4, 6, 8};
                 const int *inner = lpr == -3 ? kPlanes : kGrids;
-                const int ninner = lpr == -3 ? 9 : 6;
+                const int ninner = lpr == -3 ? 3 : 6;
                 for (int q = 0; q < ninner; ++q) {
                     const int blocks = inner[q], seg = inner[q];
                     apcg_spmv_config cfg = lpr == -3  ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_SDIA}
