@@ -602,8 +602,9 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
 // offsets are gathered as in k_pcg_product_sdia; the sums are bitwise the
 // same.  shape = U | seg << 8 | Ps << 16.  Tasks are spread over the grid
 // (task += waves in the grid).
-// Symmetric values (the flag behind the partner table set by the fill and
-// check kernels): an entry left of the diagonal, (i, i - q), is read as its
+// Symmetric values (the flag behind the partner table: set by the analysis
+// for a structurally symmetric pattern, cleared by the check kernel when a
+// refill finds the values unequal): an entry left of the diagonal, (i, i - q), is read as its
 // transpose (i - q, i) from that row's slot of offset +q -- for q = 64 Ps
 // the value of the previous slice's +plane slot, carried in a register, for
 // the other offsets a load of a line the product reads anyway (the same
