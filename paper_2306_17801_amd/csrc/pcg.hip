@@ -646,6 +646,7 @@ __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restri
             const int32_t *o = soff + (int64_t)sl * W;
             const uint64_t *m = smask + (int64_t)sl * W;
             const int32_t *pt = part + (int64_t)sl * W;
+            __builtin_amdgcn_s_setprio(2);  // the slice's loads issued ahead of other waves' arithmetic
             const int rn = min(rc + up, n - 1);
             const double zn = z[rn], pn = pold[rn];  // +plane window = the next slice's own
             int oc[W], qc[W];
@@ -684,6 +685,7 @@ __device__ __forceinline__ double march_tasks(int32_t n, const int32_t *__restri
                 zj[k] = oc[k] == up ? zn : oc[k] == -up ? zm : oc[k] == 0 ? zo : zg;
                 pj[k] = oc[k] == up ? pn : oc[k] == -up ? pm : oc[k] == 0 ? po : pg;
             }
+            __builtin_amdgcn_s_setprio(0);
             double sum = 0.0;
 #pragma unroll
             for (int k = 0; k < UC; ++k) {
