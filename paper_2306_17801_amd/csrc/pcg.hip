@@ -546,6 +546,7 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
         int oc[W];
         uint64_t mc[W];
         double ac[W];
+        __builtin_amdgcn_s_setprio(2);  // the slice's loads issued ahead of other waves' arithmetic
         if (W == 8) {
 #pragma unroll
             for (int k = 0; k < W; ++k) {
@@ -573,18 +574,20 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
             pj[k] = pold[j];
         }
         const double zi = z[rc], po = pold[rc];
+        __builtin_amdgcn_s_setprio(0);
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < W; ++k) {
             const double t = fma(ac[k], pdir(zj[k], beta, pj[k]), sum);
             sum = in[k] ? t : sum;
         }
-        if (row < n) {
-            const double pi = pdir(zi, beta, po);
-            pnew[row] = pi;
-            w[row] = sum;
-            acc = fma(pi, sum, acc);
-        }
+        // stored for the rows past n of the last slice too (workspace
+        // vectors padded to whole slices): no branch for the next slice to
+        // wait behind
+        const double pi = pdir(zi, beta, po);
+        pnew[row] = pi;
+        w[row] = sum;
+        acc = row < n ? fma(pi, sum, acc) : acc;
     }
     double v[1] = {acc};
     dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
