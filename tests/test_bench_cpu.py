@@ -1,0 +1,60 @@
+"""Host logic of bench.py that the roofline depends on: the byte model of
+the marching product with symmetric reads, the symmetry test that selects
+it, and the source hash that ties the committed counters to the kernel's
+code."""
+import os
+import sys
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+import bench  # noqa: E402
+from paper_2306_17801_amd import problems as P  # noqa: E402
+
+
+def test_upper_slots_of_a_7_point_grid():
+    """16^3 grid: 64 slices of 64 rows, planes of 4 slices.  Every slice
+    holds the offsets 0, +1, +16 and +256 on or right of the diagonal (a
+    slice spans 4 grid rows, so the last grid row of a plane, which lacks
+    +16, shares its slice with rows that have it), except the top plane's 4
+    slices, which have no +256."""
+    A = P.stencil_laplacian((16, 16, 16), 7)
+    assert bench.sdia_shape(A) == (7, 8)
+    assert bench.sdia_upper_slots(A) == 64 * 4 - 4
+
+
+def test_upper_slots_count_brute_force():
+    """Distinct (slice, offset >= 0) pairs, counted with a Python set."""
+    rng = np.random.default_rng(3)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((5, 9, 13))), aniso=2.0)
+    pairs = set()
+    for i in range(A.n):
+        for e in range(A.rowptr[i], A.rowptr[i + 1]):
+            o = int(A.col[e]) - i
+            if o >= 0:
+                pairs.add((i // 64, o))
+    assert bench.sdia_upper_slots(A) == len(pairs)
+
+
+def test_is_symmetric():
+    A = P.stencil_laplacian((6, 7, 5), 7)
+    assert bench.is_symmetric(A)
+    B = P.CSR(n=A.n, rowptr=A.rowptr, col=A.col, val=A.val.copy())
+    row = A.n // 2
+    k = int(A.rowptr[row])  # the row's first entry, left of the diagonal
+    assert A.col[k] < row
+    B.val[k] = np.nextafter(B.val[k], 0.0)  # one ulp: no longer symmetric bit for bit
+    assert not bench.is_symmetric(B)
+
+
+def test_source_hash_ignores_comments_and_whitespace(tmp_path):
+    a = tmp_path / "a.hip"
+    b = tmp_path / "b.hip"
+    c = tmp_path / "c.hip"
+    a.write_text("int f(int x) {\n    return x + 1;  // one more\n}\n")
+    b.write_text("/* header */\nint f(int x) {\n  return x + 1;\n}\n")
+    c.write_text("int f(int x) {\n    return x + 2;\n}\n")
+    assert bench.source_hash(str(a)) == bench.source_hash(str(b))
+    assert bench.source_hash(str(a)) != bench.source_hash(str(c))
