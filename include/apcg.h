@@ -412,6 +412,19 @@ typedef struct apcg_spmv_config {
 apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg);
 apcg_status apcg_mat_get_spmv_config(apcg_mat A, apcg_spmv_config *cfg);
 
+/* What the sliced-diagonal analysis found for A (it runs when
+ * APCG_SPMV_SDIA is selected or a solve first needs the layout; this call
+ * does not run it).  out[0]: 1 the layout applies, -1 it does not, 0 not
+ * analysed; out[1]: value slots per slice (U); out[2]: offset/mask slots per
+ * slice (8, 16 or 32); out[3]: plane stride in slices for marching (0:
+ * none); out[4]: 1 if the pattern is structurally symmetric; out[5]: 1 while
+ * the values have been found symmetric bit for bit at every refill so far
+ * (the marching product then reads the entries left of the diagonal as
+ * their transposes).  Reading out[5] waits for the device to go idle
+ * (hipDeviceSynchronize) and copies one word back: a diagnostic, not for
+ * hot loops. */
+apcg_status apcg_mat_get_sdia_info(apcg_mat A, int32_t out[6]);
+
 /* Autotuner: times every candidate schedule of one PCG iteration (the
  * fused product kernel and the update kernel with their reductions; reps
  * iterations each, HIP events on ctx's stream), keeps the fastest in A and

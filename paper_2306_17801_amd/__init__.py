@@ -337,6 +337,15 @@ def apcg_mat_set_spmv_config(A, lanes_per_row: int, block_size: int = 256, block
     check("apcg_mat_set_spmv_config", _L().apcg_mat_set_spmv_config(_h(A), ctypes.byref(cfg)))
 
 
+def apcg_mat_get_sdia_info(A) -> dict:
+    """The sliced-diagonal analysis of A (see include/apcg.h); waits for the
+    device to go idle."""
+    out = (ctypes.c_int32 * 6)()
+    check("apcg_mat_get_sdia_info", _L().apcg_mat_get_sdia_info(_h(A), out))
+    return {"state": out[0], "value_slots": out[1], "offset_slots": out[2], "plane_stride": out[3],
+            "structurally_symmetric": out[4], "values_symmetric": out[5]}
+
+
 def apcg_mat_get_spmv_config(A) -> dict:
     cfg = _capi.apcg_spmv_config()
     check("apcg_mat_get_spmv_config", _L().apcg_mat_get_spmv_config(_h(A), ctypes.byref(cfg)))

@@ -181,6 +181,7 @@ SIGNATURES = {
     "apcg_mat_mult_async": [c_vp, c_vp, c_vp, c_vp],
     "apcg_mat_set_spmv_config": [c_vp, P(apcg_spmv_config)],
     "apcg_mat_get_spmv_config": [c_vp, P(apcg_spmv_config)],
+    "apcg_mat_get_sdia_info": [c_vp, P(c_i32)],
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
     "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
     "apcg_solve_opts_default": [P(apcg_solve_opts)],

@@ -943,6 +943,27 @@ apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg) {
     return APCG_SUCCESS;
 }
 
+apcg_status apcg_mat_get_sdia_info(apcg_mat A, int32_t out[6]) {
+    if (!A || !out) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+    out[0] = A->sdia_state;
+    out[1] = A->sdia_u;
+    out[2] = A->sdia_mp;
+    out[3] = A->sdia_ps;
+    out[4] = A->sdia_sym;
+    out[5] = 0;
+    if (A->sdia_state == 1 && A->sdia_off) {
+        // the flag word after the offsets and the partner slots; every queued
+        // refill and check has finished once the device is idle
+        const int64_t nsl = ((int64_t)A->n + 63) / 64;
+        APCG_HIP(hipSetDevice(A->device));
+        apcg::g_counters.host_syncs++;
+        APCG_HIP(hipDeviceSynchronize());
+        apcg::g_counters.d2h_copies++;
+        APCG_HIP(hipMemcpy(&out[5], A->sdia_off + 2 * nsl * A->sdia_mp, sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return APCG_SUCCESS;
+}
+
 apcg_status apcg_mat_get_spmv_config(apcg_mat A, apcg_spmv_config *cfg) {
     if (!A || !cfg) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
     *cfg = A->cfg;

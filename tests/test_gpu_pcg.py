@@ -522,6 +522,7 @@ def test_sliced_diagonals_symmetry_rechecked_each_solve(apcg, ctx):
     assert A.col[k] < row
     info = apcg.apcg_info_create(0, 1)
     opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    seen = []
     for factor in (1.0, 1.25, 1.0):
         print(f"case symmetry recheck factor={factor}", flush=True)
         val = A.val.copy()
@@ -534,4 +535,36 @@ def test_sliced_diagonals_symmetry_rechecked_each_solve(apcg, ctx):
         ref = oracle.pcg(P.CSR(n=A.n, rowptr=A.rowptr, col=A.col, val=val), b, rtol=1e-10, maxit=5000)
         assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
         assert rel(dx.numpy(), ref.x) <= 1e-9
+        seen.append(apcg.apcg_mat_get_sdia_info(dA.h)["values_symmetric"])
+    # transposed reads while the values were symmetric, then never again
+    assert seen == [1, 0, 0]
     apcg.apcg_info_destroy(info)
+
+
+def test_sliced_diagonal_info(apcg, ctx):
+    """The analysis as apcg_mat_get_sdia_info reports it: the 3D grid (planes
+    of 4 slices) is structurally symmetric with symmetric values and a plane
+    stride; the twin with one unmatched stored zero is not structurally
+    symmetric; an unsorted pattern is rejected; a matrix never put on the
+    schedule reads as not analysed."""
+    from paper_2306_17801_amd.device import DeviceCSR
+
+    rng = np.random.default_rng(52)
+    A = P.diffusion_csr(np.exp(rng.standard_normal((10, 16, 16))), aniso=2.0)
+    dA, dT = DeviceCSR(A), DeviceCSR(with_stored_zero(A))
+    assert apcg.apcg_mat_get_sdia_info(dA.h)["state"] == 0
+    for d in (dA, dT):
+        apcg.apcg_mat_set_spmv_config(d.h, 4, 256, 0, apcg.APCG_SPMV_SDIA)
+    ia, it = apcg.apcg_mat_get_sdia_info(dA.h), apcg.apcg_mat_get_sdia_info(dT.h)
+    print("info", ia, it, flush=True)
+    assert ia == {"state": 1, "value_slots": 7, "offset_slots": 8, "plane_stride": 4,
+                  "structurally_symmetric": 1, "values_symmetric": 1}
+    assert it["state"] == 1 and it["structurally_symmetric"] == 0 and it["values_symmetric"] == 0
+    # slice 0 lies in the bottom plane (no -256), so the extra offset n - 1
+    # keeps it at 7 distinct offsets
+    assert it["value_slots"] == 7 and it["plane_stride"] == 4
+    B = random_pattern(700, 6, 46)
+    dB = DeviceCSR(B)
+    with pytest.raises(apcg.ApcgError):
+        apcg.apcg_mat_set_spmv_config(dB.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+    assert apcg.apcg_mat_get_sdia_info(dB.h)["state"] == -1
