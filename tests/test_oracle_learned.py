@@ -242,3 +242,129 @@ def test_label_interval_clamps():
     assert LO.label_interval(0.1, 2.0) == pytest.approx(0.3)
     assert LO.label_interval(0.9, 2.0) == 1.0
     assert LO.label_interval(None, 2.0) == 1.0
+
+
+# ---------------------------------------------------------------------------
+# pins of the feature statistics and the positivity penalty against values
+# worked out by hand or by an independent dense computation
+# ---------------------------------------------------------------------------
+
+def _three_row_matrix():
+    """SPD (diagonally dominant) 3 x 3 matrix with diagonal 1, e^2, e^4 and
+    off-diagonal magnitudes 0.1 (rows 0-1) and 0.1 e^3 (rows 1-2)."""
+    e2, e3, e4 = math.exp(2.0), math.exp(3.0), math.exp(4.0)
+    val = np.array([1.0, -0.1, -0.1, e2, -0.1 * e3, -0.1 * e3, e4])
+    return P.CSR(n=3, rowptr=np.array([0, 2, 5, 7], np.int32), col=np.array([0, 1, 0, 1, 2, 1, 2], np.int32),
+                 val=val)
+
+
+def test_matrix_stats_hand_values():
+    """Features 4-6 on the 3-row matrix, worked out by hand:
+      ln diag = 0, 2, 4 -> log10 contrast = 4 log10(e) = 1.7371779276130073,
+      population std = sqrt(((0-2)^2 + 0 + (4-2)^2) / 3) = sqrt(8/3)
+      = 1.6329931618554521 (the sample std would be 2);
+      ln(max/min |offdiag|) per row = 0, ln(e^3) = 3, 0 -> mean 1 (a log10
+      would give 3 log10(e) / 3 = 0.434...)."""
+    A = _three_row_matrix()
+    st = LO.matrix_stats(A)
+    assert st["log10_diag_contrast"] == pytest.approx(1.7371779276130073, rel=1e-13)
+    assert st["std_log_diag"] == pytest.approx(1.6329931618554521, rel=1e-13)
+    assert st["mean_log_offdiag_ratio"] == pytest.approx(1.0, rel=1e-13)
+    f = LO.features(A, np.array([1.0, -2.0, 0.5]))
+    assert f[4] == pytest.approx(1.7371779276130073, rel=1e-13)
+    assert f[5] == pytest.approx(1.6329931618554521, rel=1e-13)
+    assert f[6] == pytest.approx(1.0, rel=1e-13)
+    # features 0-3 by hand: log10 3, 7/3 entries per row, Gershgorin of D^-1 A
+    # (row 1 has the widest disc: 1 -+ (0.1 + 0.1 e^3) / e^2)
+    assert f[0] == pytest.approx(math.log10(3.0), rel=1e-15)
+    assert f[1] == pytest.approx(7.0 / 3.0, rel=1e-15)
+    assert f[3] == pytest.approx(1.0 + (0.1 + 0.1 * math.exp(3.0)) / math.exp(2.0), rel=1e-13)
+
+
+def _dense_rayleigh_ritz(A, b, m):
+    """Ritz values and the m-th Jacobi-PCG iterate's relative residual by an
+    independent route: Arnoldi with full reorthogonalisation on the
+    symmetrically scaled operator D^-1/2 A D^-1/2 from D^-1/2 b, the
+    Rayleigh quotient V'AV formed explicitly, and the Galerkin solution on
+    the same subspace (the CG iterate is the A-norm minimiser there)."""
+    Ad = A.to_scipy().toarray()
+    d = np.diag(Ad).copy()
+    s = 1.0 / np.sqrt(d)
+    Ah = Ad * np.outer(s, s)
+    bh = b * s
+    V = np.zeros((A.n, m))
+    v = bh / np.linalg.norm(bh)
+    for j in range(m):
+        for _ in range(2):
+            v = v - V[:, :j] @ (V[:, :j].T @ v)
+        V[:, j] = v / np.linalg.norm(v)
+        v = Ah @ V[:, j]
+    H = V.T @ Ah @ V
+    H = 0.5 * (H + H.T)
+    theta = np.linalg.eigvalsh(H)
+    y = np.linalg.solve(H, V.T @ bh)
+    x = s * (V @ y)
+    relres = np.linalg.norm(b - Ad @ x) / np.linalg.norm(b)
+    gersh_hi = float(np.max(np.abs(Ad).sum(1) / d))
+    return theta, relres, gersh_hi
+
+
+@pytest.mark.parametrize("seed,dim,side,sigma,aniso", [(11, 2, 7, 0.5, 3.0), (12, 3, 4, 1.0, 1.0),
+                                                       (13, 2, 9, 1.5, 20.0)])
+def test_ritz_and_residual_features_against_dense_rayleigh_ritz(seed, dim, side, sigma, aniso):
+    """Features 2-3 and 7-15 against the dense computation above: the three
+    smallest and largest Ritz values over the Gershgorin bound, log10 of
+    their spread, log10 of the relative residual after the 12 steps and
+    log10(theta_min / Gershgorin upper).  A wrong log base, a swapped ratio,
+    a wrong index or a residual taken one step early fails here."""
+    s = P._lognormal_system(np.random.default_rng(seed), dim, side, sigma, aniso)
+    A, b = s.A, s.b
+    theta, relres, hi = _dense_rayleigh_ritz(A, b, LO.M_STEPS)
+    assert 1e-12 < relres < 1e-1  # the 12-step subspace is full and the solve unfinished
+    f = LO.features(A, b)
+    assert f[3] == pytest.approx(hi, rel=1e-14)
+    want = np.concatenate([theta[:3] / hi, theta[-3:] / hi])
+    assert np.allclose(f[7:13], want, rtol=1e-9, atol=0)
+    assert f[13] == pytest.approx(math.log10(theta[-1] / theta[0]), rel=1e-8)
+    assert f[14] == pytest.approx(math.log10(relres), rel=1e-6)
+    assert f[15] == pytest.approx(math.log10(theta[0] / hi), rel=1e-8)
+
+
+def test_positivity_penalty_at_zero_coefficients():
+    """c = 0: p = 0 < eps on all Q points, so the penalty is mu/Q * Q * eps^2
+    = mu eps^2 (0.0025 at mu = 1, eps = 0.05; 0.02 at mu = 2, eps = 0.1),
+    whatever G and h are.  dL/dc_0 = -2 h_0 - 2 mu eps (sum of T_0 = Q);
+    for odd j the grid is symmetric about y = 0 and T_j is odd, so the
+    penalty's gradient vanishes."""
+    Phi = LO.positivity_grid()
+    rng = np.random.default_rng(3)
+    M = rng.standard_normal((9, 9))
+    G, h = M @ M.T, rng.standard_normal(9)
+    L, dc = LO.loss_terms(np.zeros(9), G, h, Phi)
+    assert L == pytest.approx(1.0025, rel=1e-15)
+    assert dc[0] == pytest.approx(-2.0 * h[0] - 0.1, rel=1e-14)
+    assert np.allclose(dc[1::2], -2.0 * h[1::2], rtol=0, atol=1e-14)
+    L2, _ = LO.loss_terms(np.zeros(9), G, h, Phi, mu=2.0, eps=0.1)
+    assert L2 == pytest.approx(1.02, rel=1e-15)
+
+
+def test_positivity_penalty_with_known_violations():
+    """c = e_1: p(s) = y = -1 + 2q/63 on the grid, so exactly q = 0..33 fall
+    below eps = 1/20 (y_33 = 3/63 < 1/20 < y_34 = 5/63).  The penalty and
+    its gradient summed in exact rational arithmetic over those points."""
+    from fractions import Fraction as Fr
+
+    Phi = LO.positivity_grid()
+    c = np.zeros(9)
+    c[1] = 1.0
+    eps = Fr(1, 20)
+    ys = [Fr(-63 + 2 * q, 63) for q in range(64)]
+    viol = [max(Fr(0), eps - y) for y in ys]
+    assert [q for q in range(64) if viol[q] > 0] == list(range(34))
+    pen = sum(v * v for v in viol) / 64
+    L, dc = LO.loss_terms(c, np.zeros((9, 9)), np.zeros(9), Phi)
+    assert L == pytest.approx(1.0 + float(pen), rel=1e-14)
+    d0 = -2 * sum(viol) / 64
+    d1 = -2 * sum(y * v for y, v in zip(ys, viol)) / 64
+    assert dc[0] == pytest.approx(float(d0), rel=1e-13)
+    assert dc[1] == pytest.approx(float(d1), rel=1e-13)
