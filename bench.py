@@ -9,12 +9,14 @@ device-side convergence test fires) with A, b and x resident in HBM.  Timing
 follows the paper's protocol (Section 4.1): warm-up solves, then K timed
 solves bracketed by device synchronisation; solves/s = K / elapsed.
 
-Also reported on the same JSON line (under "extra"): the 256-system batch
-(one batched launch against a per-solve loop), the learned polynomial
-preconditioner (FCG(1) with the network's polynomial against Jacobi-PCG on
-held-out systems), the mixed 2D/3D batch solved in one call with the learned
-preconditioner and a per-system fallback (against batched Jacobi-PCG and the
-per-solve loop), and:
+Also reported on the same JSON line (under "extra"), at the workloads' full
+sizes: the 256-system batch (one batched launch against a per-solve loop),
+the learned polynomial preconditioner (2000 training systems, FCG(1) with
+the network's polynomial against Jacobi-PCG on 200 held-out systems), the
+1024-system mixed 2D/3D batch solved in one call with the learned
+preconditioner and a per-system fallback (against the per-solve loop and
+batched Jacobi-PCG), the three batched/learned-vs-plain ratios gathered
+under "batched_learned_vs_plain", and:
   roofline      -- the fused product kernel (SpMV + direction update + p.Ap):
                    algorithmic bytes per launch / mean launch duration, the
                    duration taken with HIP events on the solve's stream
@@ -22,8 +24,10 @@ per-solve loop), and:
                    timed solves used, right after the timed region (a
                    kernel-timed solve's per-launch event pairs, which add
                    each launch's dispatch, are reported beside it);
-  cpu_baseline  -- the CPU oracle (serial C, one thread) timed on one full
-                   solve of the same system;
+  cpu_baseline  -- the CPU oracle's Jacobi-PCG loop with its row loops on
+                   every host thread (at most 16), the minimum of a few full
+                   solves of the same system (the serial oracle's rate is
+                   reported beside it);
   variants      -- the same solve with the loop launched kernel by kernel
                    (stream) and with a host check after every kernel
                    (the synchronous shape the paper compares against).
@@ -123,6 +127,64 @@ def copy_calibration(apcg, torch):
     apcg.apcg_ctx_synchronize(ctx)
 
 
+def bench_latency(apcg, torch, reps=50):
+    """The latency-bound regime (Section 4.2): the 64 x 64 Poisson system
+    (4,096 rows, 20,224 nonzeros, x* ~ U[-1,1], b = A x*, seed 0), Jacobi-PCG
+    at rtol 1e-10 from x0 = 0, one solve at a time, end to end (host call to
+    host-visible completion), min and median of `reps` solves per mode after
+    a warm-up; beside it the device's latency floors and the serial CPU
+    oracle on the same system."""
+    import numpy as np
+
+    import oracle
+    from paper_2306_17801_amd import problems
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    s = problems.poisson2d_manufactured(64, seed=0)
+    ctx = apcg.apcg_ctx_create(0)
+    A, b, x = DeviceCSR(s.A), DeviceVec(s.b), DeviceVec.zeros(s.A.n)
+    info = apcg.apcg_info_create(0, 1)
+    floors = apcg.apcg_latency_floors(0, 2000)
+    out = {"workload": "poisson2d_64x64_jacobi_pcg_rtol1e-10", "n": s.A.n, "nnz": s.A.nnz, "reps": reps,
+           "floors_us": {k: round(v, 3) for k, v in floors.items()}, "modes": {}}
+    for name, mode in (("persistent", apcg.APCG_MODE_PERSISTENT), ("graph", apcg.APCG_MODE_GRAPH),
+                       ("stream", apcg.APCG_MODE_STREAM), ("host_check", apcg.APCG_MODE_HOST_CHECK)):
+        o = apcg.apcg_solve_opts_default(x0_is_zero=1, mode=mode)
+        times = []
+        for i in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            apcg.apcg_ksp_solve(ctx, A.h, b.h, x.h, 1e-10, 10000, o, info, 0)
+            apcg.apcg_ctx_synchronize(ctx)
+            if i:
+                times.append(time.perf_counter() - t0)
+        r = apcg.apcg_info_get(info, 0)
+        xe = x.numpy()
+        tmin, tmed = min(times), sorted(times)[len(times) // 2]
+        out["modes"][name] = {"iterations": r["iterations"], "status": r["status"], "min_ms": round(1e3 * tmin, 4),
+                              "median_ms": round(1e3 * tmed, 4), "solves_per_s": round(1 / tmin, 1),
+                              "us_per_iteration": round(1e6 * tmin / max(r["iterations"], 1), 3),
+                              "err_vs_manufactured": float(np.linalg.norm(xe - s.x_exact) / np.linalg.norm(s.x_exact))}
+    t_cpu = []
+    for _ in range(5):
+        t0 = time.perf_counter()
+        rc = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=10000)
+        t_cpu.append(time.perf_counter() - t0)
+    out["cpu_oracle_serial"] = {"iterations": rc.its, "min_ms": round(1e3 * min(t_cpu), 4),
+                                "solves_per_s": round(1 / min(t_cpu), 1)}
+    m = out["modes"]
+    out["persistent_speedup_vs_graph"] = round(m["graph"]["min_ms"] / m["persistent"]["min_ms"], 2)
+    out["persistent_us_per_iteration_over_workgroup_floor"] = round(
+        m["persistent"]["us_per_iteration"] / floors["workgroup_iteration_us"], 2)
+    out["graph_us_per_iteration_over_two_graph_nodes"] = round(
+        m["graph"]["us_per_iteration"] / (2 * floors["graph_node_us"]), 2)
+    log(f"[bench] latency: {out}")
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_synchronize(ctx)
+    apcg.apcg_ctx_destroy(ctx)
+    return out
+
+
 def bench_batch(apcg, torch, reps):
     """256 independent 2D 5-point systems (side ~ U{32..256}, k = exp(N(0,1)),
     b ~ U[-1,1], seed 3), Jacobi-PCG rtol 1e-8: one batched persistent launch
@@ -195,35 +257,27 @@ def bench_batch(apcg, torch, reps):
     return out
 
 
-def learned_systems_range(count, seed, lo, hi, workers, i0, i1):
-    """Members i0 .. i1-1 of the learned-PC set of ``count`` systems (the same
-    systems a full call generates)."""
+def device_system(fields, device=0):
+    """Uploads host-drawn coefficients and right-hand side and assembles the
+    matrix on the GPU (problems.diffusion_csr_torch; the same bits as the
+    host assembly).  Returns (DeviceCSR, DeviceVec)."""
+    import torch
+
     from paper_2306_17801_amd import problems
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
-    args = [(seed, i, count, lo, hi) for i in range(i0, i1)]
-    if workers <= 1 or i1 - i0 < 16:
-        return [problems.learned_pc_system(a) for a in args]
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(problems.learned_pc_system, args, chunksize=4))
+    k = torch.from_numpy(fields.k).to(f"cuda:{device}")
+    rp, col, val = problems.diffusion_csr_torch(k, fields.aniso)
+    del k
+    return DeviceCSR.from_tensors(rp, col, val, device), DeviceVec(fields.b, device)
 
 
-def learned_systems(count, seed, lo, hi, workers):
-    """The learned-PC workload's systems, generated on the host (in worker
-    processes when there are many: generation is numpy-bound)."""
-    from paper_2306_17801_amd import problems
-
-    if workers <= 1 or count < 64:
-        return problems.learned_pc_set(count, seed, lo, hi)
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-
-    # the same per-system seeds as one call: SeedSequence(seed).spawn(count)
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(problems.learned_pc_system, [(seed, i, count, lo, hi) for i in range(count)],
-                           chunksize=8))
+def host_threads():
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
 
 
 def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, workers):
@@ -241,28 +295,33 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     from paper_2306_17801_amd import learned as L
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
+    from paper_2306_17801_amd import problems
+
     ctx = apcg.apcg_ctx_create(0)
-    # the training set is generated and collected in chunks, so that the full
-    # workload (2000 systems of up to 96^3 rows) never sits in host memory at once
+    # the training set is drawn (host threads), assembled on the GPU and
+    # collected in chunks, so that the full workload (2000 systems of up to
+    # 96^3 rows) never sits in memory at once
     t_gen = t_collect = 0.0
     parts = []
-    chunk = 128
+    chunk = 256
     for c0 in range(0, n_train, chunk):
+        c1 = min(n_train, c0 + chunk)
         t0 = time.perf_counter()
-        part = learned_systems_range(n_train, 4, side_lo, side_hi, workers, c0, min(n_train, c0 + chunk))
+        fl = problems.fields_threaded(problems.learned_pc_fields,
+                                      [(4, i, n_train, side_lo, side_hi) for i in range(c0, c1)], workers)
         t_gen += time.perf_counter() - t0
         t0 = time.perf_counter()
-        parts.append(L.collect(ctx, part))
+        parts.append(L.collect(ctx, (device_system(f) for f in fl), count=len(fl)))
         t_collect += time.perf_counter() - t0
-        del part
-        if n_train > chunk:
-            log(f"[bench] learned: training systems {min(n_train, c0 + chunk)}/{n_train} collected")
+        del fl
+        log(f"[bench] learned: training systems {c1}/{n_train} collected")
     dtrain = L.Dataset(*[torch.cat([getattr(d, k) for d in parts]) for k in ("X", "G", "h", "label", "lmax")])
     del parts
     t0 = time.perf_counter()
-    eval_set = learned_systems(n_eval, 40, side_lo, side_hi, workers)
+    eval_set = problems.fields_threaded(problems.learned_pc_fields,
+                                        [(40, i, n_eval, side_lo, side_hi) for i in range(n_eval)], workers)
     t_gen += time.perf_counter() - t0
-    deval = L.collect(ctx, eval_set)
+    deval = L.collect(ctx, (device_system(f) for f in eval_set), count=n_eval)
     t0 = time.perf_counter()
     pc, losses = L.train(ctx, dtrain, epochs=epochs, batch=32, lr=3e-3)
     t_train = time.perf_counter() - t0
@@ -290,11 +349,12 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     unconverged = 0
     feat_t = 0.0
     for s in eval_set:
-        dA, db, dx = DeviceCSR(s.A), DeviceVec(s.b), DeviceVec.zeros(s.A.n)
+        dA, db = device_system(s)
+        dx = DeviceVec.zeros(dA.n)
         # the plain path on its fastest product schedule for this matrix, as
         # in the headline (the FCG solves read the sliced-diagonal copy
         # whenever the pattern has one, whatever the schedule)
-        apcg.apcg_mat_autotune(dA.h, ctx, 5)
+        apcg.apcg_mat_autotune(dA.h, ctx, 3)
         feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
         lm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         torch.cuda.synchronize()
@@ -349,71 +409,78 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     return out
 
 
-def pool_map(fn, args, workers):
-    """Host generation of many systems (numpy-bound) in worker processes."""
-    if workers <= 1 or len(args) < 16:
-        return [fn(a) for a in args]
-    import multiprocessing as mp
-    from concurrent.futures import ProcessPoolExecutor
-
-    with ProcessPoolExecutor(max_workers=workers, mp_context=mp.get_context("spawn")) as ex:
-        return list(ex.map(fn, args, chunksize=4))
-
-
-def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers):
+def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, batched_jacobi=True):
     """Mixed batch: the first `count` systems of the 1024-system batch (2D
     5-point and 3D 7-point, N ~ log-U[1e3, 1e6], sigma ~ U[0.5, 2],
     anisotropy ~ log-U[1, 1000], seed 5), rtol 1e-8.  A network trained on
     the GPU on `n_train` systems of the same distribution (seed 6, N capped
     at train_nhi) drives the learned batched solve (features, network and
     FCG(1) with a per-system fallback, all systems in one block-diagonal
-    iteration); compared with the batched Jacobi-PCG and with the plain path
-    (one apcg_ksp_solve per system over 8 forked contexts)."""
+    iteration); compared with the plain path (one apcg_ksp_solve per system
+    over 8 forked contexts) and with the batched Jacobi-PCG.  Each path runs
+    once untimed (the batched ones with maxit 0: uploads and workspace; the
+    per-solve loop with 16 iterations: every system's graph), then `reps`
+    timed runs; the mean is reported."""
     import numpy as np
+    from concurrent.futures import ThreadPoolExecutor
 
     from paper_2306_17801_amd import learned as L
     from paper_2306_17801_amd import problems
-    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+    from paper_2306_17801_amd.device import DeviceVec
 
     t0 = time.perf_counter()
-    eval_set = pool_map(problems.mixed_system, [(5, i, 1e3, 1e6) for i in range(count)], workers)
-    train_set = pool_map(problems.mixed_system, [(6, i, 1e3, train_nhi) for i in range(n_train)], workers)
+    train_f = problems.fields_threaded(problems.mixed_fields, [(6, i, 1e3, train_nhi) for i in range(n_train)],
+                                       workers)
     t_gen = time.perf_counter() - t0
     ctx = apcg.apcg_ctx_create(0)
     t0 = time.perf_counter()
-    dtrain = L.collect(ctx, train_set, rtol=1e-8, maxit=50000)
+    dtrain = L.collect(ctx, (device_system(f) for f in train_f), rtol=1e-8, maxit=50000, count=n_train)
     t_collect = time.perf_counter() - t0
-    del train_set
+    del train_f
     t0 = time.perf_counter()
     pc, _ = L.train(ctx, dtrain, epochs=epochs, batch=32, lr=3e-3)
     t_train = time.perf_counter() - t0
-    log(f"[bench] mixed: generated {t_gen:.1f}s, collected {t_collect:.1f}s, trained {t_train:.2f}s")
-    As = [DeviceCSR(s.A) for s in eval_set]
-    bs = [DeviceVec(s.b) for s in eval_set]
-    xs = [DeviceVec.zeros(s.A.n) for s in eval_set]
-    nsys = len(eval_set)
+    t0 = time.perf_counter()
+    eval_f = problems.fields_threaded(problems.mixed_fields, [(5, i, 1e3, 1e6) for i in range(count)], workers)
+    t_gen += time.perf_counter() - t0
+    t0 = time.perf_counter()
+    dev = [device_system(f) for f in eval_f]
+    t_asm = time.perf_counter() - t0
+    rows = int(sum(f.b.size for f in eval_f))
+    del eval_f
+    As = [d[0] for d in dev]
+    bs = [d[1] for d in dev]
+    xs = [DeviceVec.zeros(a.n) for a in As]
+    nsys = len(As)
+    log(f"[bench] mixed: drew {t_gen:.1f}s, assembled on the GPU {t_asm:.1f}s, collected {t_collect:.1f}s, "
+        f"trained {t_train:.2f}s")
     info = apcg.apcg_info_create(0, nsys)
     # every matrix on the sliced-diagonal schedule (a one-time host analysis
-    # each, outside the timed runs): the batched tile products, the batched
-    # Clenshaw steps and the per-solve loop read those copies
+    # each, outside the timed runs, on host threads): the batched tile
+    # products, the batched Clenshaw steps and the per-solve loop read those
+    # copies
     t0 = time.perf_counter()
-    n_sdia = 0
-    for a in As:
+
+    def to_sdia(a):
         try:
             apcg.apcg_mat_set_spmv_config(a.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
-            n_sdia += 1
+            return 1
         except apcg.ApcgError:
-            pass
-    log(f"[bench] mixed: {n_sdia} of {nsys} matrices on sliced diagonals ({time.perf_counter() - t0:.1f}s)")
-    out = {"systems": nsys, "rows": int(sum(s.A.n for s in eval_set)), "nnz": int(sum(s.A.nnz for s in eval_set)),
+            return 0
+
+    with ThreadPoolExecutor(workers) as ex:
+        n_sdia = sum(ex.map(to_sdia, As))
+    t_sdia = time.perf_counter() - t0
+    log(f"[bench] mixed: {n_sdia} of {nsys} matrices on sliced diagonals ({t_sdia:.1f}s)")
+    out = {"systems": nsys, "rows": rows, "nnz": int(sum(a.nnz for a in As)),
            "train_systems": n_train, "train_n_max": train_nhi, "generate_s": round(t_gen, 1),
-           "collect_s": round(t_collect, 2), "train_s": round(t_train, 3), "sliced_diagonal_systems": n_sdia}
-    del eval_set
+           "assemble_s": round(t_asm, 1), "collect_s": round(t_collect, 2), "train_s": round(t_train, 3),
+           "sliced_diagonal_systems": n_sdia, "sdia_analysis_s": round(t_sdia, 1), "timed_runs": reps}
     hA, hb, hx = [a.h for a in As], [b.h for b in bs], [x.h for x in xs]
     opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
 
-    def timed(run):
-        run()  # warm-up (graph capture, uploads)
+    def timed(run, warm):
+        warm()
         apcg.apcg_ctx_synchronize(ctx)
         t1 = time.perf_counter()
         for _ in range(reps):
@@ -430,8 +497,11 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers):
         out[f"{prefix}_iterations_mean"] = round(float(np.mean(its)), 1)
         return res
 
-    dt = timed(lambda: apcg.apcg_ksp_solve_batched_learned(ctx, hA, hb, hx, 1e-8, 50000, pc.params, pc.mean, pc.std,
-                                                           opts, None, info))
+    def learned(maxit):
+        apcg.apcg_ksp_solve_batched_learned(ctx, hA, hb, hx, 1e-8, maxit, pc.params, pc.mean, pc.std, opts, None,
+                                            info)
+
+    dt = timed(lambda: learned(50000), lambda: learned(0))
     res = summary("batched_learned", dt)
     out["batched_learned_fallbacks"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_FALLBACK)
     out["batched_learned_fallback_reasons"] = {
@@ -441,33 +511,44 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers):
     out["batched_learned_iterations_max"] = max(r["iterations"] for r in res)
     out["batched_learned_fcg_iterations_mean"] = round(float(np.mean([r["fcg_iterations"] for r in res])), 1)
     log(f"[bench] mixed batched learned: {1000 * dt:.1f} ms")
-    dt = timed(lambda: apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-8, 50000, opts, info))
-    res = summary("batched_jacobi", dt)
-    out["batched_jacobi_iterations_max"] = max(r["iterations"] for r in res)
-    log(f"[bench] mixed batched Jacobi: {1000 * dt:.1f} ms")
+    if batched_jacobi:
+        def bj(maxit):
+            apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-8, maxit, opts, info)
+
+        dt = timed(lambda: bj(50000), lambda: bj(0))
+        res = summary("batched_jacobi", dt)
+        out["batched_jacobi_iterations_max"] = max(r["iterations"] for r in res)
+        out["batched_learned_speedup_vs_batched_jacobi"] = round(out["batched_jacobi_ms"] / out["batched_learned_ms"], 3)
+        log(f"[bench] mixed batched Jacobi: {1000 * dt:.1f} ms")
     kids = apcg.apcg_ctx_fork(ctx, 8)
     infos = apcg.apcg_info_create(0, nsys)
 
-    def loop():
+    def loop(maxit):
         for i in range(nsys):
-            apcg.apcg_ksp_solve(kids[i % 8], hA[i], hb[i], hx[i], 1e-8, 50000, opts, infos, i)
+            apcg.apcg_ksp_solve(kids[i % 8], hA[i], hb[i], hx[i], 1e-8, maxit, opts, infos, i)
         for k in kids:
             apcg.apcg_ctx_synchronize(k)
 
-    dt = timed(loop)
+    dt = timed(lambda: loop(50000), lambda: loop(16))
     res = [apcg.apcg_info_get(infos, i) for i in range(nsys)]
     out["per_solve_loop_ms"] = round(1000 * dt, 2)
     out["per_solve_loop_solves_per_s"] = round(nsys / dt, 2)
     out["per_solve_loop_iterations_mean"] = round(float(np.mean([r["iterations"] for r in res])), 1)
+    out["per_solve_loop_iterations_max"] = max(r["iterations"] for r in res)
     out["per_solve_loop_converged"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_CONVERGED)
     out["batched_learned_speedup_vs_per_solve_loop"] = round(out["per_solve_loop_ms"] / out["batched_learned_ms"], 3)
-    out["batched_learned_speedup_vs_batched_jacobi"] = round(out["batched_jacobi_ms"] / out["batched_learned_ms"], 3)
     log(f"[bench] mixed per-solve loop: {1000 * dt:.1f} ms")
     apcg.apcg_ctx_join(ctx, kids, apcg.APCG_JOIN_DESTROY)
     apcg.apcg_info_destroy(infos)
     apcg.apcg_info_destroy(info)
     apcg.apcg_ctx_synchronize(ctx)
     apcg.apcg_ctx_destroy(ctx)
+    for x in xs:
+        x.close()
+    for b in bs:
+        b.close()
+    for a in As:
+        a.close()
     log(f"[bench] mixed: {out}")
     return out
 
@@ -625,19 +706,23 @@ def main():
     ap.add_argument("--no-autotune", action="store_true")
     ap.add_argument("--spmv-config", type=str, default=None,
                     help="lanes,block,blocks,schedule: a fixed SpMV configuration instead of the autotuner's")
+    ap.add_argument("--no-latency", action="store_true",
+                    help="skip the latency-bound 64 x 64 Poisson measurement and the latency floors")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched measurement")
     ap.add_argument("--batch-reps", type=int, default=3)
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
-    ap.add_argument("--learned-train", type=int, default=128, help="training systems (the full workload: 2000)")
-    ap.add_argument("--learned-eval", type=int, default=16, help="held-out systems (the full workload: 200)")
-    ap.add_argument("--learned-sides", type=int, nargs=2, default=[32, 64],
-                    help="side range of the learned workload (the full workload: 32 96)")
+    ap.add_argument("--learned-train", type=int, default=2000, help="training systems")
+    ap.add_argument("--learned-eval", type=int, default=200, help="held-out systems")
+    ap.add_argument("--learned-sides", type=int, nargs=2, default=[32, 96], help="side range of the learned workload")
     ap.add_argument("--learned-epochs", type=int, default=300)
-    ap.add_argument("--learned-reps", type=int, default=3)
-    ap.add_argument("--workers", type=int, default=8, help="host processes generating the learned systems")
+    ap.add_argument("--learned-reps", type=int, default=1, help="timed solves per held-out system and solver")
+    ap.add_argument("--workers", type=int, default=0, help="host threads drawing the systems (0: the host's CPUs, <= 16)")
     ap.add_argument("--no-mixed", action="store_true", help="skip the mixed-batch (learned + batched) measurement")
-    ap.add_argument("--mixed-count", type=int, default=128,
-                    help="first systems of the 1024-system mixed batch to solve (the full workload: 1024)")
+    ap.add_argument("--mixed-count", type=int, default=1024, help="first systems of the 1024-system mixed batch to solve")
+    ap.add_argument("--mixed-reps", type=int, default=1, help="timed runs of each mixed-batch path")
+    ap.add_argument("--no-mixed-batched-jacobi", action="store_true",
+                    help="skip the batched Jacobi-PCG run of the mixed batch")
+    ap.add_argument("--cpu-reps", type=int, default=3, help="repetitions of the CPU baseline's solve (min taken)")
     ap.add_argument("--mixed-train", type=int, default=192, help="training systems for the mixed batch's network")
     ap.add_argument("--mixed-train-nmax", type=float, default=1e6, help="largest training system (rows)")
     ap.add_argument("--copy-calibration", action="store_true",
@@ -813,31 +898,69 @@ def main():
         var["graph_speedup_vs_host_check"] = round(var["host_check"]["ms_per_solve"] / ms_per_step, 3)
         extra["variants"] = var
 
+    if not args.no_latency:
+        extra["latency_poisson64"] = bench_latency(apcg, torch)
+
     if not args.no_batch:
         extra["batch2d_256"] = bench_batch(apcg, torch, args.batch_reps)
 
+    workers = args.workers if args.workers > 0 else host_threads()
     if not args.no_learned:
         extra["learned_pc"] = bench_learned(apcg, torch, args.learned_train, args.learned_eval,
                                             args.learned_sides[0], args.learned_sides[1], args.learned_epochs,
-                                            args.learned_reps, args.workers)
+                                            args.learned_reps, workers)
 
     if not args.no_mixed:
         extra["mixed_batch"] = bench_mixed(apcg, torch, args.mixed_count, args.mixed_train, args.mixed_train_nmax,
-                                           args.learned_epochs, 2, args.workers)
+                                           args.learned_epochs, args.mixed_reps, workers,
+                                           batched_jacobi=not args.no_mixed_batched_jacobi)
+    # the metric's comparison in one place: batched + learned against the
+    # plain path (one Jacobi-PCG solve per system) on the same GPU
+    summ = {}
+    if "mixed_batch" in extra:
+        m = extra["mixed_batch"]
+        summ["mixed_batch"] = {"systems": m["systems"], "batched_learned_solves_per_s": m["batched_learned_solves_per_s"],
+                               "plain_per_solve_solves_per_s": m["per_solve_loop_solves_per_s"],
+                               "speedup": m["batched_learned_speedup_vs_per_solve_loop"]}
+    if "learned_pc" in extra:
+        m = extra["learned_pc"]
+        summ["learned_heldout"] = {"systems": m["eval_systems"], "learned_solves_per_s": m["learned_solves_per_s"],
+                                   "plain_per_solve_solves_per_s": m["jacobi_solves_per_s"],
+                                   "speedup": m["learned_speedup_vs_jacobi"]}
+    if "batch2d_256" in extra:
+        m = extra["batch2d_256"]
+        summ["batch2d_256"] = {"systems": m["systems"], "batched_solves_per_s": m["batched_solves_per_s"],
+                               "plain_per_solve_solves_per_s": m["per_solve_loop_solves_per_s"],
+                               "speedup": m["batched_speedup_vs_per_solve_loop"]}
+    if summ:
+        extra["batched_learned_vs_plain"] = summ
 
     cpu = None
     if not args.no_cpu_baseline:
         import oracle
 
-        log("[bench] timing the CPU oracle on one full solve ...")
+        threads = oracle.host_threads()
+        log(f"[bench] timing the CPU oracle's Jacobi-PCG on {threads} host threads ...")
+        times = []
+        for _ in range(max(1, args.cpu_reps)):
+            t1 = time.perf_counter()
+            r = oracle.pcg_threads(A_h, sysm.b, rtol=rtol, maxit=maxit, threads=threads)
+            times.append(time.perf_counter() - t1)
+        dt = min(times)
+        # the serial oracle (one thread, the parity configuration) on its
+        # first 40 iterations, scaled to the full solve
         t1 = time.perf_counter()
-        r = oracle.pcg(A_h, sysm.b, rtol=rtol, maxit=maxit)
-        dt = time.perf_counter() - t1
-        cpu = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": 1, "kind": "oracle",
-               "sample": f"one full serial FP64 Jacobi-PCG solve of the same system ({r.its} iterations, "
-                         f"{dt:.1f} s) on the host",
-               "iterations": r.its}
-        log(f"[bench] oracle: {dt:.1f} s, its={r.its}")
+        oracle.pcg(A_h, sysm.b, rtol=0.0, maxit=40)
+        ser = (time.perf_counter() - t1) / 40 * r.its
+        cpu = {"value": round(1.0 / dt, 5), "unit": "solves/s", "cores": threads, "kind": "oracle",
+               "sample": f"{len(times)} full FP64 Jacobi-PCG solves of the same system ({r.its} iterations each) "
+                         f"with the oracle's loop spread over {threads} host threads (OpenMP over rows, static "
+                         f"schedule); min {dt:.2f} s, median {sorted(times)[len(times) // 2]:.2f} s",
+               "iterations": r.its, "min_s": round(dt, 3), "median_s": round(sorted(times)[len(times) // 2], 3),
+               "serial_solves_per_s": round(1.0 / ser, 5),
+               "serial_sample": "the serial oracle's first 40 iterations on one thread, scaled to the solve's "
+                                f"{r.its} iterations"}
+        log(f"[bench] oracle: min {dt:.2f} s on {threads} threads, its={r.its}; serial estimate {ser:.1f} s")
 
     props = apcg.apcg_device_props_get(0)
     line = {

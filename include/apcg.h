@@ -459,6 +459,12 @@ apcg_status apcg_mat_time_kernels(apcg_mat A, apcg_ctx ctx, int32_t reps, double
 #define APCG_MODE_STREAM 1     /* same kernels launched one by one           */
 #define APCG_MODE_HOST_CHECK 2 /* host reads the convergence flag after     */
                                /* every iteration (the synchronous shape)   */
+#define APCG_MODE_PERSISTENT 3 /* one workgroup runs the whole solve in one  */
+                               /* launch (n <= APCG_PERSISTENT_MAX_N; the    */
+                               /* latency-bound regime of Section 4.2)       */
+#define APCG_MODE_AUTO 4       /* PERSISTENT when n <= APCG_PERSISTENT_MAX_N */
+                               /* (and no kernel timing), else GRAPH         */
+#define APCG_PERSISTENT_MAX_N 4096
 
 typedef struct apcg_solve_opts {
     int32_t pc;              /* APCG_PC_*                                    */
@@ -507,14 +513,33 @@ apcg_status apcg_info_get(apcg_info info, int32_t index, apcg_solve_info *out);
  * (ignored when opts->x0_is_zero) and the solution on exit.  Stops when the
  * chosen norm is <= rtol times its reference, or after maxit iterations
  * (maxit >= 0).  The result is written to info[info_index] on the device.
- * Workspace (5 n doubles plus a few scalars) is owned by ctx and reused.
+ * Workspace (6 n doubles plus a few scalars) is owned by ctx and reused.
  * With APCG_MODE_GRAPH/STREAM no kernel waits on the host: the host thread
  * returns once it has enqueued enough work to reach convergence or maxit,
  * having observed the device flag only through events `lookahead` periods
- * behind the queue.  On a globally blocking context the call returns after
- * the solve has finished. */
+ * behind the queue.  With APCG_MODE_PERSISTENT (or AUTO at n <=
+ * APCG_PERSISTENT_MAX_N) the whole solve is one launch of one 512-thread
+ * workgroup that keeps each row's r, D^-1, p and A p in registers and shares
+ * p through n doubles of the context's workspace; its sums run in another
+ * fixed order than the multi-kernel modes' (same tests, same counts up to
+ * rounding).  n > APCG_PERSISTENT_MAX_N with PERSISTENT returns
+ * APCG_ERR_INVALID_ARG.  On a globally blocking context the call returns
+ * after the solve has finished. */
 apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                            const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
+
+/* Latency floors of the device (Section 4.2: below about 1e5 nonzeros the
+ * GPU solve is bound by latency).  Runs on a private stream of `device`,
+ * blocks the host, and writes microseconds to out_us:
+ *   [0] per launch of an empty kernel, `reps` launches back to back;
+ *   [1] per node of a captured graph of min(reps, 1000) empty kernels;
+ *   [2] per iteration of the one-workgroup persistent solve's
+ *       synchronisation alone (three barriers, two workgroup sums),
+ *       `reps` iterations in one launch;
+ *   [3] host round trip: one empty kernel launched and waited for
+ *       (min(reps, 200) times, host clock).
+ * reps in [1, 100000]; APCG_ERR_INVALID_ARG otherwise. */
+apcg_status apcg_latency_floors(int32_t device, int32_t reps, double out_us[4]);
 
 /* TFQMR (Section 4, the paper's second benchmark method; Freund 1993) for
  * square, possibly nonsymmetric or indefinite A, left-preconditioned by

@@ -22,6 +22,8 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "apcg_oracle.c")
 _LIB = os.path.join(_HERE, "liboracle.so")
+_SRC_T = os.path.join(_HERE, "oracle_threads.c")
+_LIB_T = os.path.join(_HERE, "liboracle_threads.so")
 
 # status bits, as numbered inside apcg_oracle.c
 CONVERGED = 1
@@ -47,6 +49,12 @@ def build(force: bool = True) -> str:
                "-Wall", "-Wno-jump-misses-init", _SRC, "-o", tmp, "-lm"]
         subprocess.run(cmd, check=True)
         os.replace(tmp, _LIB)
+    if force or not os.path.exists(_LIB_T) or os.path.getmtime(_LIB_T) < os.path.getmtime(_SRC_T):
+        tmp = _LIB_T + ".tmp"
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+               "-Wall", _SRC_T, "-o", tmp, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB_T)
     return _LIB
 
 
@@ -81,6 +89,24 @@ def lib():
         L.or_fcg_poly.restype = i32
         _lib = L
     return _lib
+
+
+_lib_t = None
+
+
+def lib_threads():
+    """The threaded timing copy of the Jacobi-PCG loop (oracle_threads.c)."""
+    global _lib_t
+    if _lib_t is None:
+        if not os.path.exists(_LIB_T) or os.path.getmtime(_LIB_T) < os.path.getmtime(_SRC_T):
+            build(force=True)
+        L = ctypes.CDLL(_LIB_T)
+        P = ctypes.c_void_p
+        i32, f64 = ctypes.c_int32, ctypes.c_double
+        L.or_pcg_threads.argtypes = [i32, P, P, P, P, P, f64, i32, i32, P, P, P]
+        L.or_pcg_threads.restype = i32
+        _lib_t = L
+    return _lib_t
 
 
 def _p(a):
@@ -165,6 +191,32 @@ def pcg(A, b, x0=None, rtol=1e-8, maxit=None, pc=PC_JACOBI, norm_type=NORM_UNPRE
     if ndir > 0:
         out.dirs = dh[: min(ndir, max(its.value, 0) + 1)].copy()
     return out
+
+
+def pcg_threads(A, b, rtol=1e-8, maxit=None, threads=1):
+    """Jacobi-PCG from x0 = 0 with its row loops on ``threads`` host threads
+    (or_pcg_threads; for timing the host).  With one thread it equals
+    :func:`pcg` bit for bit."""
+    rp, c, v = _csr(A)
+    n = A.n
+    maxit = n if maxit is None else int(maxit)
+    b = np.ascontiguousarray(b, dtype=np.float64)
+    x = np.zeros(n)
+    its = ctypes.c_int32()
+    res, ref = ctypes.c_double(), ctypes.c_double()
+    st = lib_threads().or_pcg_threads(n, _p(rp), _p(c), _p(v), _p(b), _p(x), float(rtol), maxit, int(threads),
+                                      ctypes.byref(its), ctypes.byref(res), ctypes.byref(ref))
+    return PCGResult(x=x, its=its.value, status=st, res=res.value, ref=ref.value)
+
+
+def host_threads() -> int:
+    """Host threads for CPU timing: the CPUs this process may run on, capped
+    at 16 (the host share that goes with one GPU)."""
+    try:
+        n = len(os.sched_getaffinity(0))
+    except AttributeError:
+        n = os.cpu_count() or 1
+    return max(1, min(n, 16))
 
 
 def tfqmr(A, b, x0=None, rtol=1e-8, maxit=None, pc=PC_JACOBI, history=False):

@@ -369,6 +369,16 @@ def apcg_mat_time_kernels(A, ctx, reps: int = 100):
     return pu.value, uu.value
 
 
+def apcg_latency_floors(device: int = 0, reps: int = 1000) -> dict:
+    """Microseconds: empty kernel back to back, per captured graph node,
+    per iteration of the one-workgroup loop's synchronisation, host round
+    trip (see include/apcg.h)."""
+    out = (ctypes.c_double * 4)()
+    check("apcg_latency_floors", _L().apcg_latency_floors(int(device), int(reps), out))
+    return {"empty_kernel_us": out[0], "graph_node_us": out[1], "workgroup_iteration_us": out[2],
+            "host_round_trip_us": out[3]}
+
+
 # ------------------------------------------------------------------ solve
 
 def apcg_solve_opts_default(**overrides):

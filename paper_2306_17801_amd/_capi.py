@@ -59,6 +59,9 @@ APCG_NORM_PRECONDITIONED = 1
 APCG_MODE_GRAPH = 0
 APCG_MODE_STREAM = 1
 APCG_MODE_HOST_CHECK = 2
+APCG_MODE_PERSISTENT = 3
+APCG_MODE_AUTO = 4
+APCG_PERSISTENT_MAX_N = 4096
 APCG_SPMV_ROWGROUP = 0
 APCG_SPMV_STREAM = 1
 APCG_SPMV_SELL = 2
@@ -184,6 +187,7 @@ SIGNATURES = {
     "apcg_mat_get_sdia_info": [c_vp, P(c_i32)],
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
     "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
+    "apcg_latency_floors": [c_i32, c_i32, P(c_f64)],
     "apcg_solve_opts_default": [P(apcg_solve_opts)],
     "apcg_info_create": [c_i32, c_i32, P(c_vp)],
     "apcg_info_destroy": [c_vp],

@@ -30,7 +30,7 @@ class ComposedCG:
         self.ctx = ctx
         self.n = n
         self.r, self.z, self.p, self.w = (DeviceVec.zeros(n, device) for _ in range(4))
-        names = ("rho", "rho_new", "delta", "alpha", "beta", "res", "dinv")
+        names = ("rho", "rho_new", "delta", "alpha", "beta", "res", "diag", "dinv")
         self.s = {k: apcg_scalar_create(ctx) for k in names}
 
     def close(self):
@@ -46,7 +46,8 @@ class ComposedCG:
         of the asynchronous variant)."""
         c, s = self.ctx, self.s
         r, z, p, w = self.r.h, self.z.h, self.p.h, self.w.h
-        apcg_scalar_set(s["dinv"], 1.0 / diag, c)
+        apcg_scalar_set(s["diag"], diag, c)
+        apcg_scalar_op(_capi.APCG_SCALAR_RECIP, s["dinv"], s["diag"], None, c)  # 1/diag on the device
         apcg_vec_copy_async(r, b, c)  # r = b - A x0 with x0 = 0
         apcg_vec_copy_async(z, r, c)
         apcg_vec_scale_async(z, s["dinv"], c)  # z = D^-1 r

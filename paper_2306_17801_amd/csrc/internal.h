@@ -218,6 +218,12 @@ apcg_status resolve_ctx(apcg_ctx in, int device, apcg_ctx *out);  // NULL -> glo
 apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
+// one-workgroup persistent Jacobi-PCG (persist.hip): p is n doubles of device
+// memory the workgroup shares; maxrow the longest row (< 0: unknown)
+int persistent_rows_per_thread(int64_t n);
+apcg_status launch_pcg_wg(hipStream_t st, int32_t n, const int32_t *rowptr, const int32_t *col, const double *val,
+                          const double *b, double *x, double *p, double rtol, int32_t maxit, int x0_zero, int pc,
+                          int norm_pre, int32_t maxrow, apcg_solve_info *out);
 void batch_cache_release(uint64_t ctx_id, int device);  // batched.hip
 // sliced-diagonal pattern analysis (pcg.hip): synchronous, once per matrix
 apcg_status sdia_analyse(apcg_mat_s *A);

@@ -12,7 +12,8 @@
 //       share of delta_k = p_k . w.
 //   update U_k:  every workgroup reduces the delta partials of P_k, stops on
 //       delta <= 0, else alpha_k = rho_{k-1} / delta_k; x += alpha p,
-//       r -= alpha w, z = D^-1 r (not stored) and its shares of z.r, ||r||^2.
+//       r -= alpha w, z = D^-1 r (stored, so the next product gathers z and
+//       p_{k-1}) and its shares of z.r, ||r||^2.
 //
 // There is no atomic and no fence in any kernel: a reduction's first stage
 // writes one partial per workgroup, and the consuming kernel (which starts
@@ -1388,8 +1389,13 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
             return set_error(APCG_ERR_UNSUPPORTED, "unsupported preconditioner for apcg_ksp_solve");
         if (opts.norm_type != APCG_NORM_UNPRECONDITIONED && opts.norm_type != APCG_NORM_PRECONDITIONED)
             return set_error(APCG_ERR_INVALID_ARG, "unknown norm type");
-        if (opts.mode < APCG_MODE_GRAPH || opts.mode > APCG_MODE_HOST_CHECK)
+        if (opts.mode < APCG_MODE_GRAPH || opts.mode > APCG_MODE_AUTO)
             return set_error(APCG_ERR_INVALID_ARG, "unknown mode");
+        if (opts.mode == APCG_MODE_AUTO)
+            opts.mode = A->n <= APCG_PERSISTENT_MAX_N && !hist && !opts.kernel_timing ? APCG_MODE_PERSISTENT
+                                                                                     : APCG_MODE_GRAPH;
+        if (opts.mode == APCG_MODE_PERSISTENT && (A->n > APCG_PERSISTENT_MAX_N || hist))
+            return set_error(APCG_ERR_INVALID_ARG, "the persistent mode takes n <= APCG_PERSISTENT_MAX_N");
         if (opts.iters_per_graph < 1) return set_error(APCG_ERR_INVALID_ARG, "iters_per_graph must be >= 1");
         if (opts.lookahead < 1 || opts.lookahead > kMaxLookahead)
             return set_error(APCG_ERR_INVALID_ARG, "lookahead must be in [1, 8]");
@@ -1403,13 +1409,19 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
         Acc acc[4] = {{&x->rec, ACC_RW}, {&info->rec, ACC_W}, {&A->rec, ACC_R}, {&b->rec, ACC_R}};
         if ((s = op_begin(c, acc, 4))) return s;
         if ((s = ensure_workspace(c, A->n))) return s;
+        const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
+        hipStream_t st = c->stream;
+        if (opts.mode == APCG_MODE_PERSISTENT) {  // reads the CSR arrays; p in the workspace
+            if ((s = launch_pcg_wg(st, A->n, A->rowptr, A->col, A->val, b->d, x->d, c->ws.p(0), rtol, maxit,
+                                   opts.x0_is_zero ? 1 : 0, opts.pc, norm_pre, A->sell_maxw, info->d + info_index)))
+                return s;
+            return op_end(c, acc, 4);
+        }
         if (A->cfg.schedule == APCG_SPMV_SELL && (s = prepare_sell(A, c->stream))) return s;
         if (A->cfg.schedule == APCG_SPMV_SDIA && (s = prepare_sdia(A, c->stream))) return s;
         Plan pl;
         if ((s = make_plan(A, A->cfg, &pl))) return s;
         Bufs bf{A, x->d, b->d, c->ws, c->partials};
-        const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
-        hipStream_t st = c->stream;
 
         hipLaunchKernelGGL(k_pcg_init, dim3(pl.g_vec), dim3(VB), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d,
                            c->ws.r(), c->ws.dinv(), c->ws.z(), c->ws.p(0), bf.part_res(), pl.pb_vec,

@@ -18,7 +18,8 @@ class DeviceVec:
             t = data.to(device=f"cuda:{device}", dtype=torch.float64).contiguous()
         else:
             t = torch.from_numpy(np.ascontiguousarray(data, dtype=np.float64)).to(f"cuda:{device}")
-        torch.cuda.synchronize(device)
+        # the copy is on torch's stream; the library's streams start after it
+        torch.cuda.current_stream(device).synchronize()
         self.t = t
         self.n = t.numel()
         self.h = apcg_vec_wrap(t)
@@ -59,8 +60,26 @@ class DeviceCSR:
         self.rowptr = torch.from_numpy(np.ascontiguousarray(A.rowptr, dtype=np.int32)).to(dev)
         self.col = torch.from_numpy(np.ascontiguousarray(A.col, dtype=np.int32)).to(dev)
         self.val = torch.from_numpy(np.ascontiguousarray(A.val, dtype=np.float64)).to(dev)
-        torch.cuda.synchronize(device)
+        torch.cuda.current_stream(device).synchronize()
         self.h = apcg_mat_wrap_csr(self.rowptr, self.col, self.val, host_rowptr=np.asarray(A.rowptr, np.int32))
+
+    @classmethod
+    def from_tensors(cls, rowptr, col, val, device: int = 0):
+        """Wraps CSR arrays that already live in torch tensors (moved to the
+        device if they are not there yet)."""
+        import torch
+
+        dev = f"cuda:{device}"
+        obj = cls.__new__(cls)
+        obj.rowptr = rowptr.to(device=dev, dtype=torch.int32).contiguous()
+        obj.col = col.to(device=dev, dtype=torch.int32).contiguous()
+        obj.val = val.to(device=dev, dtype=torch.float64).contiguous()
+        obj.n = int(obj.rowptr.numel() - 1)
+        obj.nnz = int(obj.val.numel())
+        host_rowptr = obj.rowptr.cpu().numpy()
+        torch.cuda.current_stream(device).synchronize()
+        obj.h = apcg_mat_wrap_csr(obj.rowptr, obj.col, obj.val, host_rowptr=host_rowptr)
+        return obj
 
     def close(self):
         if self.h is not None:

@@ -65,13 +65,15 @@ class Dataset:
 
 
 def collect(ctx, systems, rtol: float = 1e-8, maxit: int = 20000, labels: bool = True,
-            device: int = 0) -> Dataset:
+            device: int = 0, count: int | None = None) -> Dataset:
     """Features (and, with ``labels``, the training labels) of each system.
-    One system is resident at a time; the context is synchronised before its
-    upload is released."""
+    ``systems`` holds host systems (uploaded here) or already uploaded
+    (DeviceCSR, DeviceVec) pairs, which this call then owns; it may be an
+    iterator, with ``count`` giving its length.  One system is resident at a
+    time; the context is synchronised before its upload is released."""
     import torch
 
-    B = len(systems)
+    B = len(systems) if count is None else int(count)
     dev = _cuda(device)
     X = torch.zeros((B, NFEAT), dtype=torch.float32, device=dev)
     G = torch.zeros((B, NCOEF * NCOEF), dtype=torch.float32, device=dev)
@@ -80,7 +82,9 @@ def collect(ctx, systems, rtol: float = 1e-8, maxit: int = 20000, labels: bool =
     lmax = torch.zeros(B, dtype=torch.float64, device=dev)
     torch.cuda.synchronize(device)
     for i, s in enumerate(systems):
-        dA, db = DeviceCSR(s.A, device), DeviceVec(s.b, device)
+        if i >= B:
+            raise ValueError("more systems than count")
+        dA, db = s if isinstance(s, tuple) else (DeviceCSR(s.A, device), DeviceVec(s.b, device))
         apcg_pc_features(ctx, dA.h, db.h, X[i], lmax[i:i + 1])
         if labels:
             apcg_pc_label(ctx, dA.h, db.h, rtol, maxit, G[i], h[i], lab[i])

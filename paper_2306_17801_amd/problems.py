@@ -249,6 +249,69 @@ def laplace_eigval(shape: tuple, modes: tuple) -> float:
     return float(sum(2.0 - 2.0 * math.cos(m * math.pi / (n_ax + 1)) for n_ax, m in zip(shape, modes)))
 
 
+def diffusion_csr_torch(k, aniso: float = 1.0):
+    """The matrix of :func:`diffusion_csr` assembled with torch tensor
+    operations on ``k``'s device (the bulk workloads are assembled on the GPU
+    from host-drawn coefficients).  Returns (rowptr int32[n+1], col
+    int32[nnz], val float64[nnz]) on that device.  The face values are the
+    same IEEE operations in the same order as the numpy assembly (one
+    elementwise operation per step, no contraction), so both give the same
+    bits from the same ``k``."""
+    import torch
+
+    k = k.to(torch.float64)
+    dim = k.dim()
+    if dim not in (2, 3):
+        raise ValueError("k must be 2-D or 3-D")
+    shape = tuple(k.shape)
+    dev = k.device
+    n = int(np.prod(shape))
+    idx = torch.arange(n, dtype=torch.int64, device=dev).reshape(shape)
+    axes = list(range(dim))
+    stride = [int(np.prod(shape[ax + 1:])) for ax in axes]
+    order = [(ax, -1) for ax in axes] + [None] + [(ax, +1) for ax in reversed(axes)]
+    S = len(order)
+    vals = torch.zeros((n, S), dtype=torch.float64, device=dev)
+    cols = torch.zeros((n, S), dtype=torch.int64, device=dev)
+    mask = torch.zeros((n, S), dtype=torch.bool, device=dev)
+    diag = torch.zeros(shape, dtype=torch.float64, device=dev)
+    centre_slot = order.index(None)
+    for slot, item in enumerate(order):
+        if item is None:
+            continue
+        ax, d = item
+        factor = aniso if ax == dim - 1 else 1.0
+        face = torch.empty(shape, dtype=torch.float64, device=dev)
+        inner = [slice(None)] * dim
+        nbr = [slice(None)] * dim
+        edge = [slice(None)] * dim
+        if d < 0:
+            inner[ax], nbr[ax], edge[ax] = slice(1, None), slice(0, shape[ax] - 1), slice(0, 1)
+        else:
+            inner[ax], nbr[ax], edge[ax] = slice(0, shape[ax] - 1), slice(1, None), slice(shape[ax] - 1, None)
+        inner, nbr, edge = tuple(inner), tuple(nbr), tuple(edge)
+        k1, k2 = k[inner], k[nbr]
+        face[inner] = factor * (2.0 * k1 * k2 / (k1 + k2))
+        face[edge] = factor * k[edge]
+        diag += face
+        has = torch.zeros(shape, dtype=torch.bool, device=dev)
+        has[inner] = True
+        v = torch.zeros(shape, dtype=torch.float64, device=dev)
+        v[inner] = -face[inner]
+        vals[:, slot] = v.reshape(-1)
+        cols[:, slot] = (idx + d * stride[ax]).reshape(-1)
+        mask[:, slot] = has.reshape(-1)
+    vals[:, centre_slot] = diag.reshape(-1)
+    cols[:, centre_slot] = idx.reshape(-1)
+    mask[:, centre_slot] = True
+    counts = mask.sum(dim=1)
+    rowptr = torch.zeros(n + 1, dtype=torch.int64, device=dev)
+    torch.cumsum(counts, 0, out=rowptr[1:])
+    if int(rowptr[-1]) > np.iinfo(np.int32).max:
+        raise ValueError("nnz exceeds the int32 index range")
+    return rowptr.to(torch.int32), cols[mask].to(torch.int32), vals[mask].contiguous()
+
+
 def box_smooth_3(g: np.ndarray) -> np.ndarray:
     """Mean over every valid 3^d window of ``g`` (shape shrinks by 2 per axis)."""
     d = g.ndim
@@ -289,13 +352,32 @@ def diffusion3d_smoothed(n: int = 128, seed: int = 2) -> System:
     return System(A=A, b=b, meta={"workload": f"diffusion3d_{n}^3_box3", "seed": seed})
 
 
-def _lognormal_system(rng: np.random.Generator, dim: int, side: int, sigma: float, aniso: float) -> System:
+@dataclass
+class Fields:
+    """The host-drawn part of a log-normal diffusion system: cell
+    coefficients k (grid-shaped), right-hand side b and the anisotropy; the
+    matrix is assembled from them by :func:`diffusion_csr` (host) or
+    :func:`diffusion_csr_torch` (any torch device)."""
+
+    k: np.ndarray
+    b: np.ndarray
+    aniso: float
+    meta: dict = field(default_factory=dict)
+
+    def system(self) -> System:
+        return System(A=diffusion_csr(self.k, aniso=self.aniso), b=self.b, meta=dict(self.meta))
+
+
+def _lognormal_fields(rng: np.random.Generator, dim: int, side: int, sigma: float, aniso: float) -> Fields:
     shape = (side,) * dim
     g = rng.standard_normal(shape)
     k = np.exp(sigma * g)
-    A = diffusion_csr(k, aniso=aniso)
-    b = rng.uniform(-1.0, 1.0, A.n)
-    return System(A=A, b=b, meta={"dim": dim, "side": side, "sigma": sigma, "aniso": aniso})
+    b = rng.uniform(-1.0, 1.0, int(np.prod(shape)))
+    return Fields(k=k, b=b, aniso=aniso, meta={"dim": dim, "side": side, "sigma": sigma, "aniso": aniso})
+
+
+def _lognormal_system(rng: np.random.Generator, dim: int, side: int, sigma: float, aniso: float) -> System:
+    return _lognormal_fields(rng, dim, side, sigma, aniso).system()
 
 
 def batch2d_lognormal(count: int = 256, seed: int = 3, side_lo: int = 32, side_hi: int = 256,
@@ -312,14 +394,18 @@ def batch2d_lognormal(count: int = 256, seed: int = 3, side_lo: int = 32, side_h
     return out
 
 
-def _learned_pc_from(child, index: int, side_lo: int, side_hi: int) -> System:
+def _learned_pc_fields_from(child, index: int, side_lo: int, side_hi: int) -> Fields:
     rng = np.random.default_rng(child)
     side = int(rng.integers(side_lo, side_hi + 1))
     sigma = float(rng.uniform(0.5, 2.0))
     aniso = float(math.exp(rng.uniform(0.0, math.log(100.0))))
-    s = _lognormal_system(rng, 3, side, sigma, aniso)
-    s.meta["index"] = index
-    return s
+    f = _lognormal_fields(rng, 3, side, sigma, aniso)
+    f.meta["index"] = index
+    return f
+
+
+def _learned_pc_from(child, index: int, side_lo: int, side_hi: int) -> System:
+    return _learned_pc_fields_from(child, index, side_lo, side_hi).system()
 
 
 def learned_pc_set(count: int, seed: int, side_lo: int = 32, side_hi: int = 96) -> list[System]:
@@ -337,6 +423,12 @@ def learned_pc_system(args) -> System:
     seed, index, count, side_lo, side_hi = args
     # child i of SeedSequence(seed).spawn(...) is SeedSequence(seed, spawn_key=(i,))
     return _learned_pc_from(np.random.SeedSequence(seed, spawn_key=(index,)), index, side_lo, side_hi)
+
+
+def learned_pc_fields(args) -> Fields:
+    """The fields of :func:`learned_pc_system` (same args, same draws)."""
+    seed, index, count, side_lo, side_hi = args
+    return _learned_pc_fields_from(np.random.SeedSequence(seed, spawn_key=(index,)), index, side_lo, side_hi)
 
 
 def mixed_batch_params(count: int = 1024, seed: int = 5, n_lo: float = 1e3, n_hi: float = 1e6):
@@ -365,10 +457,10 @@ def mixed_batch(count: int = 1024, seed: int = 5, limit: int | None = None) -> l
     return out
 
 
-def mixed_system(args) -> System:
-    """System ``index`` of ``mixed_batch(count, seed)`` alone (args = (seed,
-    index, n_lo, n_hi)): child i of SeedSequence(seed).spawn(...) is
-    SeedSequence(seed, spawn_key=(i,)), drawn in the same order."""
+def mixed_fields(args) -> Fields:
+    """The fields of system ``index`` of ``mixed_batch(count, seed)`` alone
+    (args = (seed, index, n_lo, n_hi)): child i of SeedSequence(seed).spawn(...)
+    is SeedSequence(seed, spawn_key=(i,)), drawn in the same order."""
     seed, index, n_lo, n_hi = args
     rng = np.random.default_rng(np.random.SeedSequence(seed, spawn_key=(index,)))
     dim = 2 + int(rng.integers(0, 2))
@@ -376,9 +468,26 @@ def mixed_system(args) -> System:
     side = max(2, int(round(nt ** (1.0 / dim))))
     sigma = float(rng.uniform(0.5, 2.0))
     aniso = float(math.exp(rng.uniform(0.0, math.log(1000.0))))
-    s = _lognormal_system(rng, dim, side, sigma, aniso)
-    s.meta["index"] = index
-    return s
+    f = _lognormal_fields(rng, dim, side, sigma, aniso)
+    f.meta["index"] = index
+    return f
+
+
+def mixed_system(args) -> System:
+    """System ``index`` of ``mixed_batch(count, seed)`` alone (args as for
+    :func:`mixed_fields`)."""
+    return mixed_fields(args).system()
+
+
+def fields_threaded(fn, args, threads: int = 8) -> list:
+    """fn over args in a thread pool (numpy's generators and elementwise
+    functions release the GIL on large arrays), results in args order."""
+    if threads <= 1 or len(args) < 4:
+        return [fn(a) for a in args]
+    from concurrent.futures import ThreadPoolExecutor
+
+    with ThreadPoolExecutor(threads) as ex:
+        return list(ex.map(fn, args))
 
 
 def random_csr(n: int, max_per_row: int, seed: int, empty_rows: bool = True) -> CSR:

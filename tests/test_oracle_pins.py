@@ -631,3 +631,70 @@ def test_tfqmr_status_cases():
     r = oracle.tfqmr(A, A.to_scipy() @ xs, x0=xs, rtol=1e-8, maxit=10)
     assert r.status == oracle.CONVERGED
     assert np.linalg.norm(r.x - xs) <= 1e-12 * np.linalg.norm(xs)
+
+
+# ---------------------------------------------------------------------------
+# the threaded timing copy of the Jacobi-PCG loop
+# ---------------------------------------------------------------------------
+
+def test_threaded_pcg_one_thread_is_the_serial_oracle_bit_for_bit():
+    s = P.diffusion3d_smoothed(12, seed=5)
+    ref = oracle.pcg(s.A, s.b, rtol=1e-10)
+    got = oracle.pcg_threads(s.A, s.b, rtol=1e-10, threads=1)
+    assert got.status == ref.status == oracle.CONVERGED
+    assert got.its == ref.its and got.res == ref.res and got.ref == ref.ref
+    assert np.array_equal(got.x, ref.x)
+
+
+@pytest.mark.parametrize("threads", [2, 3, 8])
+def test_threaded_pcg_matches_the_oracle(threads):
+    """Other thread counts change only the summation order of the inner
+    products: iterations +-1 and the iterate within 1e-9."""
+    s = P.batch2d_lognormal(1, seed=9, side_lo=40, side_hi=40)[0]
+    ref = oracle.pcg(s.A, s.b, rtol=1e-10)
+    got = oracle.pcg_threads(s.A, s.b, rtol=1e-10, threads=threads)
+    assert got.status == oracle.CONVERGED and abs(got.its - ref.its) <= 1
+    assert np.linalg.norm(got.x - ref.x) / np.linalg.norm(ref.x) <= 1e-9
+    again = oracle.pcg_threads(s.A, s.b, rtol=1e-10, threads=threads)
+    assert np.array_equal(again.x, got.x)
+
+
+def test_threaded_pcg_status_paths():
+    A = P.laplace_2d(6)
+    z = oracle.pcg_threads(A, np.zeros(A.n), threads=4)
+    assert z.status == oracle.CONVERGED and z.its == 0 and not z.x.any()
+    b = np.ones(A.n)
+    m = oracle.pcg_threads(A, b, rtol=1e-14, maxit=3, threads=4)
+    assert m.status == oracle.MAXIT and m.its == 3
+    bad = P.CSR(n=2, rowptr=np.array([0, 1, 2], np.int32), col=np.array([0, 1], np.int32), val=np.array([1.0, -1.0]))
+    assert oracle.pcg_threads(bad, np.ones(2), threads=2).status == oracle.SETUP_ERROR
+
+
+# ---------------------------------------------------------------------------
+# the torch assembly of the bulk workloads equals the numpy assembly
+# ---------------------------------------------------------------------------
+
+@pytest.mark.parametrize("fn,args", [(P.mixed_fields, (5, 3, 1e3, 2e4)), (P.mixed_fields, (5, 0, 1e3, 2e4)),
+                                     (P.learned_pc_fields, (4, 7, 2000, 6, 11))])
+def test_torch_assembly_is_the_numpy_assembly_bit_for_bit(fn, args):
+    import torch
+
+    f = fn(args)
+    A = f.system().A
+    rp, col, val = P.diffusion_csr_torch(torch.from_numpy(f.k), f.aniso)
+    assert np.array_equal(rp.numpy(), A.rowptr) and np.array_equal(col.numpy(), A.col)
+    assert np.array_equal(val.numpy().view(np.int64), A.val.view(np.int64))
+
+
+def test_fields_draw_the_systems_of_the_batch_recipes():
+    """mixed_fields / learned_pc_fields draw the same numbers as the batch
+    recipes (mixed_batch, learned_pc_set)."""
+    full = P.mixed_batch(6, seed=5)
+    for i in (0, 5):
+        s = P.mixed_fields((5, i, 1e3, 1e6)).system()
+        assert np.array_equal(s.b, full[i].b) and np.array_equal(s.A.val, full[i].A.val)
+    lp = P.learned_pc_set(3, 4, 6, 9)
+    s = P.learned_pc_fields((4, 2, 3, 6, 9)).system()
+    assert np.array_equal(s.b, lp[2].b) and np.array_equal(s.A.val, lp[2].A.val)
+    thr = P.fields_threaded(P.mixed_fields, [(5, i, 1e3, 1e6) for i in range(6)], threads=3)
+    assert all(np.array_equal(t.b, s.b) for t, s in zip(thr, full))
