@@ -394,6 +394,27 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
  *       finds the values unsymmetric, the matrix reads every slot from then
  *       on (until its schedule is analysed again, i.e. never for this
  *       handle).
+ *   schedule APCG_SPMV_DIA (PCG solves): diagonals.  Applicable when the
+ *       whole matrix has at most 9 distinct column offsets (column - row;
+ *       the 5-, 7- and 9-point stencil matrices) and every row's columns are
+ *       strictly increasing; apcg_mat_set_spmv_config returns
+ *       APCG_ERR_UNSUPPORTED otherwise.  Diagonal k is a library-owned array
+ *       of n (rounded up to 64) values, 0 where a row has no entry at that
+ *       offset, refilled from the CSR values at the start of every solve;
+ *       selecting the schedule copies the pattern to the host once
+ *       (synchronously) and snapshots it.  lanes_per_row must be 1; each
+ *       thread computes whole rows, workgroups own contiguous ranges of
+ *       rows (multiples of 64), and every load address is the row plus a
+ *       constant offset: no per-row or per-slice index loads.  A row's sum
+ *       adds the diagonals in offset order (= column order), the absent
+ *       entries adding exact zeros, so A p is bitwise that of the
+ *       row-per-thread schedule.  When the offset set is symmetric and the
+ *       values are symmetric bit for bit (checked on the device at every
+ *       refill, as for APCG_SPMV_SDIA), the value of an entry left of the
+ *       diagonal, (i, i - q), is read as its transpose's, i.e. from
+ *       diagonal +q at row i - q, so only the diagonals on and right of
+ *       the main one stream from memory.  A lone MatMult reads the CSR
+ *       arrays, as for APCG_SPMV_SELL.
  * block_size in {256, 512} threads; blocks is the number of workgroups
  * (rounded up to a multiple of the 8 XCDs; 0 = library default).  Each
  * workgroup owns a contiguous range of rows and workgroups are renumbered so
@@ -402,6 +423,7 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
 #define APCG_SPMV_STREAM 1
 #define APCG_SPMV_SELL 2
 #define APCG_SPMV_SDIA 3
+#define APCG_SPMV_DIA 4
 typedef struct apcg_spmv_config {
     int32_t lanes_per_row;
     int32_t block_size;
@@ -424,6 +446,15 @@ apcg_status apcg_mat_get_spmv_config(apcg_mat A, apcg_spmv_config *cfg);
  * (hipDeviceSynchronize) and copies one word back: a diagnostic, not for
  * hot loops. */
 apcg_status apcg_mat_get_sdia_info(apcg_mat A, int32_t out[6]);
+
+/* What the diagonal analysis found for A (it runs when APCG_SPMV_DIA is
+ * selected; this call does not run it).  out[0]: 1 the layout applies, -1
+ * it does not, 0 not analysed; out[1]: distinct offsets; out[2]: 1 if the
+ * offset set is symmetric; out[3]: 1 while the values have been found
+ * symmetric bit for bit at every refill so far (the product then reads the
+ * entries left of the diagonal as their transposes).  Reading out[3] waits
+ * for the device to go idle and copies one word back: a diagnostic. */
+apcg_status apcg_mat_get_dia_info(apcg_mat A, int32_t out[4]);
 
 /* Autotuner: times every candidate schedule of one PCG iteration (the
  * fused product kernel and the update kernel with their reductions; reps

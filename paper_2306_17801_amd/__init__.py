@@ -346,6 +346,14 @@ def apcg_mat_get_sdia_info(A) -> dict:
             "structurally_symmetric": out[4], "values_symmetric": out[5]}
 
 
+def apcg_mat_get_dia_info(A) -> dict:
+    """The diagonal analysis of A (see include/apcg.h); waits for the device
+    to go idle."""
+    out = (ctypes.c_int32 * 4)()
+    check("apcg_mat_get_dia_info", _L().apcg_mat_get_dia_info(_h(A), out))
+    return {"state": out[0], "diagonals": out[1], "offsets_symmetric": out[2], "values_symmetric": out[3]}
+
+
 def apcg_mat_get_spmv_config(A) -> dict:
     cfg = _capi.apcg_spmv_config()
     check("apcg_mat_get_spmv_config", _L().apcg_mat_get_spmv_config(_h(A), ctypes.byref(cfg)))

@@ -66,6 +66,7 @@ APCG_SPMV_ROWGROUP = 0
 APCG_SPMV_STREAM = 1
 APCG_SPMV_SELL = 2
 APCG_SPMV_SDIA = 3
+APCG_SPMV_DIA = 4
 APCG_BATCH_AUTO = 0
 APCG_BATCH_PERSISTENT = 1
 APCG_BATCH_SEGMENTED = 2
@@ -185,6 +186,7 @@ SIGNATURES = {
     "apcg_mat_set_spmv_config": [c_vp, P(apcg_spmv_config)],
     "apcg_mat_get_spmv_config": [c_vp, P(apcg_spmv_config)],
     "apcg_mat_get_sdia_info": [c_vp, P(c_i32)],
+    "apcg_mat_get_dia_info": [c_vp, P(c_i32)],
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
     "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
     "apcg_latency_floors": [c_i32, c_i32, P(c_f64)],

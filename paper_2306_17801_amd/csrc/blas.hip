@@ -311,7 +311,7 @@ static apcg_status spmv_with(hipStream_t s, const apcg_mat_s *A, const apcg_spmv
 
 apcg_status launch_spmv(hipStream_t s, const apcg_mat_s *A, const double *x, double *y) {
     if (A->n == 0) return APCG_SUCCESS;
-    if (A->cfg.schedule == APCG_SPMV_SELL || A->cfg.schedule == APCG_SPMV_SDIA) {
+    if (A->cfg.schedule == APCG_SPMV_SELL || A->cfg.schedule == APCG_SPMV_SDIA || A->cfg.schedule == APCG_SPMV_DIA) {
         // The sliced copies are refilled per solve, not per product: a lone
         // product reads the CSR arrays with row groups of the configured
         // block size and grid, lanes per row from the mean row length.

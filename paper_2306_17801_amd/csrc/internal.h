@@ -196,6 +196,22 @@ struct apcg_mat_s {
                                      //   by the analysis, only ever cleared on the device)
     uint64_t *sdia_msk = nullptr;    // device [nslices * sdia_mp] row masks, padding 0
     double *sdia_val = nullptr;      // device [nslices * sdia_u * 64] values, absent entries 0
+    // Diagonal layout (DIA schedule): the whole matrix has at most
+    // kDiaMaxDiags distinct column offsets; diagonal k is an array of
+    // n rounded up to 64 values (value of row i at offset dia_off[k], 0 where
+    // the row has no such entry).  The offsets are found on the host the
+    // first time the schedule is selected; the values are refilled from the
+    // CSR arrays at the start of every solve that uses it.
+    int32_t dia_state = 0;           // 0: not analysed, 1: available, -1: not applicable
+    const char *dia_reason = "";
+    int32_t dia_nd = 0;              // distinct offsets (diagonals)
+    int32_t dia_ndt = 0;             // diagonals the kernel walks (5, 7 or 9 >= dia_nd; the rest all zero)
+    int32_t dia_sym = 0;             // 1: the offset set is symmetric (o present <=> -o present)
+    int32_t dia_off_h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
+    int32_t *dia_tab = nullptr;      // device int32[32]: offsets [0..8], partner diagonal of each
+                                     //   negative offset [9..17] (-1: none), value-symmetry flag [18]
+                                     //   (set by the analysis when dia_sym, only ever cleared on the device)
+    double *dia_val = nullptr;       // device [dia_ndt][n rounded up to 64]
     apcg::Record rec;
     uint64_t mark_id = 0;
 };
@@ -218,6 +234,10 @@ apcg_status resolve_ctx(apcg_ctx in, int device, apcg_ctx *out);  // NULL -> glo
 apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
+// diagonal (DIA) layout (pcg.hip)
+constexpr int kDiaMaxDiags = 9;
+apcg_status dia_analyse(apcg_mat_s *A);
+apcg_status prepare_dia(apcg_mat_s *A, hipStream_t s);
 // one-workgroup persistent Jacobi-PCG (persist.hip): p is n doubles of device
 // memory the workgroup shares; maxrow the longest row (< 0: unknown)
 int persistent_rows_per_thread(int64_t n);

@@ -790,6 +790,138 @@ __global__ __launch_bounds__(256) void k_sdia_symcheck(int32_t n, const int32_t 
     if (!same) symflag[0] = 0;
 }
 
+// ------------------------------------------------------------- diagonals
+// The matrix as at most 9 diagonals (the distinct offsets o_k = column - row,
+// ascending): val[k][i] = a_{i, i + o_k}, 0 where row i has no such entry.
+// Table tab: offsets [0..8], for a negative offset the diagonal holding its
+// transpose's values [9..17] (-1: none), the value-symmetry flag [18].
+
+// Row i of A p for rows lo + tid, lo + tid + TB, ... < hi (the rows of the
+// row-per-thread schedule at lanes_per_row 1, in the same order), with
+// p_j = z_j + beta pold_j formed while gathering.  Every address is the row
+// plus a constant: the diagonal values at row i, the vectors at i + o_k
+// (clamped into [0, n); an absent entry's value is 0, so the clamped gather
+// only multiplies into an exact zero).  SYM: the value at a negative offset
+// -q is diagonal +q's value at row i - q (0 above the first row).  The sum
+// runs over the diagonals in offset order with one FMA each; the absent
+// entries add exact zeros (a sum started at +0 is never -0), so it is bitwise
+// the CSR row sum.  Returns the thread's share of p.Ap.
+template <int TB, int ND, bool SYM>
+__device__ __forceinline__ double dia_rows(int32_t n, const int (&off)[ND], const int (&prt)[ND], int nd,
+                                           const double *__restrict__ dval, int64_t stride,
+                                           const double *__restrict__ z, const double *__restrict__ pold,
+                                           double *__restrict__ pnew, double *__restrict__ w, double beta, int lo,
+                                           int hi) {
+    double acc = 0.0;
+    for (int row = lo + (int)threadIdx.x; row < hi; row += TB) {
+        double a[ND], g[ND];
+#pragma unroll
+        for (int k = 0; k < ND; ++k) {
+            if (k < nd) {
+                const int o = off[k];
+                const int j = min(max(row + o, 0), n - 1);
+                g[k] = pdir(z[j], beta, pold[j]);
+                if (SYM && o < 0) {
+                    const int src = row + o;
+                    const double t = dval[(int64_t)prt[k] * stride + max(src, 0)];
+                    a[k] = src >= 0 ? t : 0.0;
+                } else {
+                    a[k] = dval[(int64_t)k * stride + row];
+                }
+            } else {
+                a[k] = 0.0;
+                g[k] = 0.0;
+            }
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < ND; ++k) sum = fma(a[k], g[k], sum);
+        const double pi = pdir(z[row], beta, pold[row]);
+        pnew[row] = pi;
+        w[row] = sum;
+        acc = fma(pi, sum, acc);
+    }
+    return acc;
+}
+
+// Product with the diagonal layout: a1 unused, a2 = the diagonals,
+// lds_nnz = the diagonal count the kernel walks (ND).  rows_per_block is a
+// multiple of 64, so every wavefront's loads are contiguous windows.
+template <int TB, int ND>
+__global__ __launch_bounds__(TB) void k_pcg_product_dia(int32_t n, const int32_t *__restrict__ tab,
+                                                        const int32_t * /*unused*/, const double *__restrict__ dval,
+                                                        const double *__restrict__ z,
+                                                        const double *__restrict__ pold, double *__restrict__ pnew,
+                                                        double *__restrict__ w, SolveState *st,
+                                                        const double *part_res, int g_res, double *part_delta,
+                                                        int32_t rows_per_block, int parity, int tune,
+                                                        int32_t nd_walked) {
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    const int64_t stride = ((int64_t)n + 63) / 64 * 64;
+    int off[ND], prt[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        off[k] = __builtin_amdgcn_readfirstlane(tab[k]);
+        prt[k] = __builtin_amdgcn_readfirstlane(tab[9 + k]);
+    }
+    const int nd = __builtin_amdgcn_readfirstlane(tab[19]);
+    const int sym = __builtin_amdgcn_readfirstlane(tab[18]);
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const int lo = lb * rows_per_block, hi = min(n, lo + rows_per_block);
+    const double acc = sym ? dia_rows<TB, ND, true>(n, off, prt, nd, dval, stride, z, pold, pnew, w, beta, lo, hi)
+                           : dia_rows<TB, ND, false>(n, off, prt, nd, dval, stride, z, pold, pnew, w, beta, lo, hi);
+    double v[1] = {acc};
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
+}
+
+// Refills the diagonals from the CSR values: thread i walks row i's entries
+// (columns strictly increasing, every offset one of the table's) against the
+// ascending offsets and writes every diagonal's value of row i (0 for rows
+// >= n and for the diagonals past nd).
+__global__ __launch_bounds__(256) void k_dia_fill(int32_t n, const int32_t *__restrict__ rowptr,
+                                                  const int32_t *__restrict__ col, const double *__restrict__ val,
+                                                  const int32_t *__restrict__ tab, int32_t ndt,
+                                                  double *__restrict__ dval) {
+    const int64_t stride = ((int64_t)n + 63) / 64 * 64;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= stride) return;
+    const int nd = tab[19];
+    int e = i < n ? rowptr[i] : 0;
+    const int end = i < n ? rowptr[i + 1] : 0;
+    for (int k = 0; k < ndt; ++k) {
+        double v = 0.0;
+        if (k < nd && e < end && (int64_t)col[e] == i + tab[k]) {
+            v = val[e];
+            ++e;
+        }
+        dval[k * stride + i] = v;
+    }
+}
+
+// Clears the value-symmetry flag when an entry left of the diagonal differs
+// in any bit from its transpose's (diagonal +q at row i - q); queued after
+// every refill of a matrix with a symmetric offset set.  The flag is never
+// set on the device, so a product on another context's stream never sees it
+// set for values found unequal.
+__global__ __launch_bounds__(256) void k_dia_symcheck(int32_t n, int32_t *__restrict__ tab,
+                                                      const double *__restrict__ dval) {
+    const int64_t stride = ((int64_t)n + 63) / 64 * 64;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n) return;
+    const int nd = tab[19];
+    bool same = true;
+    for (int k = 0; k < nd; ++k) {
+        const int o = tab[k];
+        if (o >= 0) continue;
+        const int64_t src = i + o;
+        const double a = dval[k * stride + i];
+        const double t = src >= 0 ? dval[(int64_t)tab[9 + k] * stride + src] : 0.0;
+        same = same && __double_as_longlong(a) == __double_as_longlong(t);
+    }
+    if (!same) tab[18] = 0;
+}
+
 // ----------------------------------------------------------------- update
 __global__ __launch_bounds__(VB) void k_pcg_update(int64_t n, double *__restrict__ x, double *__restrict__ r,
                                                    const double *__restrict__ p, const double *__restrict__ w,
@@ -925,6 +1057,12 @@ ProductFn stream_fn(int32_t lds_nnz) {
 
 ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_maxw, int32_t sdia_mp,
                      int32_t sdia_ps) {
+    if (cfg.schedule == APCG_SPMV_DIA) {
+        const bool b512 = cfg.block_size == 512;
+        if (lds_nnz <= 5) return b512 ? k_pcg_product_dia<512, 5> : k_pcg_product_dia<256, 5>;
+        if (lds_nnz <= 7) return b512 ? k_pcg_product_dia<512, 7> : k_pcg_product_dia<256, 7>;
+        return b512 ? k_pcg_product_dia<512, 9> : k_pcg_product_dia<256, 9>;
+    }
     if (cfg.schedule == APCG_SPMV_SDIA) {
         const bool b512 = cfg.block_size == 512;
         if (cfg.lanes_per_row > 1 && sdia_ps > 0) {  // plane marching
@@ -989,7 +1127,18 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
     pl->a0 = A->rowptr;
     pl->a1 = A->col;
     pl->a2 = A->val;
-    if (cfg.schedule == APCG_SPMV_SDIA) {
+    if (cfg.schedule == APCG_SPMV_DIA) {
+        if (A->dia_state != 1 || !A->dia_val)
+            return set_error(APCG_ERR_INVALID_STATE, "diagonal copy not prepared");
+        pl->a0 = A->dia_tab;
+        pl->a1 = nullptr;
+        pl->a2 = A->dia_val;
+        const int64_t units = ((int64_t)A->n + 63) / 64;  // 64-row chunks
+        pl->g_prod = normalise_blocks(cfg.blocks, (units * 64 + pl->tb - 1) / pl->tb);
+        const int64_t upb = (units + pl->g_prod - 1) / pl->g_prod;
+        pl->rpb = (int32_t)std::max<int64_t>(64, upb * 64);
+        pl->lds_nnz = A->dia_ndt;
+    } else if (cfg.schedule == APCG_SPMV_SDIA) {
         if (A->sdia_state != 1 || !A->sdia_val)
             return set_error(APCG_ERR_INVALID_STATE, "sliced-diagonal copy not prepared");
         pl->a0 = A->sdia_off;
@@ -1194,6 +1343,87 @@ apcg_status prepare_sdia(apcg_mat_s *A, hipStream_t s) {
         hipLaunchKernelGGL(k_sdia_symcheck, dim3((unsigned)blocks), dim3(256), 0, s, A->n, A->sdia_off,
                            (const uint64_t *)A->sdia_msk, A->sdia_u, A->sdia_mp, A->sdia_val, flag);
         APCG_CHECK_LAUNCH("k_sdia_symcheck");
+    }
+    return APCG_SUCCESS;
+}
+
+// Finds the matrix's distinct column offsets on the host from a copy of the
+// CSR pattern (once per matrix) and allocates the diagonal copy and its
+// table.  Leaves dia_state -1 with a reason when the layout does not apply.
+apcg_status dia_analyse(apcg_mat_s *A) {
+    if (A->dia_state != 0) return APCG_SUCCESS;
+    auto reject = [&](const char *why) {
+        A->dia_state = -1;
+        A->dia_reason = why;
+        return APCG_SUCCESS;
+    };
+    const int64_t n = A->n, nnz = A->nnz;
+    if (n == 0) return reject("empty matrix");
+    try {
+        std::vector<int32_t> rp((size_t)n + 1), cl((size_t)std::max<int64_t>(nnz, 1));
+        APCG_HIP(hipSetDevice(A->device));
+        g_counters.d2h_copies += 2;
+        APCG_HIP(hipMemcpy(rp.data(), A->rowptr, sizeof(int32_t) * ((size_t)n + 1), hipMemcpyDeviceToHost));
+        if (nnz > 0) APCG_HIP(hipMemcpy(cl.data(), A->col, sizeof(int32_t) * (size_t)nnz, hipMemcpyDeviceToHost));
+        std::vector<int32_t> offs;  // sorted distinct offsets
+        for (int64_t i = 0; i < n; ++i)
+            for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
+                if (e > rp[i] && cl[e] <= cl[e - 1]) return reject("a row's columns are not strictly increasing");
+                const int32_t o = cl[e] - (int32_t)i;
+                auto it = std::lower_bound(offs.begin(), offs.end(), o);
+                if (it == offs.end() || *it != o) {
+                    if ((int)offs.size() == kDiaMaxDiags) return reject("more than 9 distinct column offsets");
+                    offs.insert(it, o);
+                }
+            }
+        if (offs.empty()) return reject("no entries");
+        const int nd = (int)offs.size();
+        const int ndt = nd <= 5 ? 5 : nd <= 7 ? 7 : 9;
+        int32_t tab[32];
+        for (int k = 0; k < 32; ++k) tab[k] = 0;
+        bool sym = true;
+        for (int k = 0; k < kDiaMaxDiags; ++k) {
+            tab[k] = k < nd ? offs[k] : 0;
+            tab[9 + k] = -1;
+            if (k < nd) {
+                auto it = std::lower_bound(offs.begin(), offs.end(), -offs[k]);
+                const bool has = it != offs.end() && *it == -offs[k];
+                if (!has) sym = false;
+                if (offs[k] < 0 && has) tab[9 + k] = (int32_t)(it - offs.begin());
+            }
+        }
+        tab[18] = sym ? 1 : 0;
+        tab[19] = nd;
+        const int64_t stride = (n + 63) / 64 * 64;
+        APCG_HIP(hipMalloc((void **)&A->dia_tab, sizeof(tab)));
+        APCG_HIP(hipMalloc((void **)&A->dia_val, sizeof(double) * ndt * stride));
+        g_counters.h2d_copies++;
+        APCG_HIP(hipMemcpy(A->dia_tab, tab, sizeof(tab), hipMemcpyHostToDevice));
+        for (int k = 0; k < kDiaMaxDiags; ++k) A->dia_off_h[k] = tab[k];
+        A->dia_nd = nd;
+        A->dia_ndt = ndt;
+        A->dia_sym = sym ? 1 : 0;
+        A->dia_state = 1;
+        return APCG_SUCCESS;
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}
+
+// Queues the refill of the diagonals from the CSR values on stream s (and
+// the value-symmetry check when the offset set is symmetric).
+apcg_status prepare_dia(apcg_mat_s *A, hipStream_t s) {
+    apcg_status st = dia_analyse(A);
+    if (st) return st;
+    if (A->dia_state < 0) return set_error(APCG_ERR_UNSUPPORTED, A->dia_reason);
+    const int64_t stride = ((int64_t)A->n + 63) / 64 * 64;
+    hipLaunchKernelGGL(k_dia_fill, dim3((unsigned)((stride + 255) / 256)), dim3(256), 0, s, A->n, A->rowptr,
+                       A->col, A->val, (const int32_t *)A->dia_tab, A->dia_ndt, A->dia_val);
+    APCG_CHECK_LAUNCH("k_dia_fill");
+    if (A->dia_sym) {
+        hipLaunchKernelGGL(k_dia_symcheck, dim3((unsigned)(((int64_t)A->n + 255) / 256)), dim3(256), 0, s, A->n,
+                           A->dia_tab, (const double *)A->dia_val);
+        APCG_CHECK_LAUNCH("k_dia_symcheck");
     }
     return APCG_SUCCESS;
 }
@@ -1419,6 +1649,7 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
         }
         if (A->cfg.schedule == APCG_SPMV_SELL && (s = prepare_sell(A, c->stream))) return s;
         if (A->cfg.schedule == APCG_SPMV_SDIA && (s = prepare_sdia(A, c->stream))) return s;
+        if (A->cfg.schedule == APCG_SPMV_DIA && (s = prepare_dia(A, c->stream))) return s;
         Plan pl;
         if ((s = make_plan(A, A->cfg, &pl))) return s;
         Bufs bf{A, x->d, b->d, c->ws, c->partials};
@@ -1555,6 +1786,7 @@ apcg_status apcg_mat_time_kernels(apcg_mat A, apcg_ctx ctx, int32_t reps, double
         APCG_CHECK_LAUNCH("k_tune_fill");
         if (A->cfg.schedule == APCG_SPMV_SELL && (s = prepare_sell(A, st))) return s;
         if (A->cfg.schedule == APCG_SPMV_SDIA && (s = prepare_sdia(A, st))) return s;
+        if (A->cfg.schedule == APCG_SPMV_DIA && (s = prepare_dia(A, st))) return s;
         Plan pl;
         if ((s = make_plan(A, A->cfg, &pl))) return s;
         double *xs = nullptr;  // stand-in for x: the timed update writes it
@@ -1619,11 +1851,15 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         if ((s = sdia_analyse(A))) return s;
         const bool sdia_ok = A->sdia_state == 1;
         if (sdia_ok && (s = prepare_sdia(A, st))) return s;
-        // -2: sliced diagonals, -1: the sliced schedule, 0: the staged one
-        // -3: sliced diagonals with plane marching (the inner value is the
-        // number of planes per task, not a grid)
-        for (int lpr : {-3, -2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
+        if ((s = dia_analyse(A))) return s;
+        const bool dia_ok = A->dia_state == 1;
+        if (dia_ok && (s = prepare_dia(A, st))) return s;
+        // -4: diagonals, -2: sliced diagonals, -1: the sliced schedule, 0:
+        // the staged one, -3: sliced diagonals with plane marching (the
+        // inner value is the number of planes per task, not a grid)
+        for (int lpr : {-4, -3, -2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
+            if (lpr == -4 && !dia_ok) continue;
             if (lpr == -1 && !sell_ok) continue;
             if (lpr == -2 && !sdia_ok) continue;
             if (lpr == -3 && !(sdia_ok && A->sdia_ps > 0)) continue;
@@ -1638,7 +1874,8 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
                 const int ninner = lpr == -3 ? 3 : 6;
                 for (int q = 0; q < ninner; ++q) {
                     const int blocks = inner[q], seg = inner[q];
-                    apcg_spmv_config cfg = lpr == -3  ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_SDIA}
+                    apcg_spmv_config cfg = lpr == -4  ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_DIA}
+                                           : lpr == -3 ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_SDIA}
                                            : lpr == -2 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SDIA}
                                            : lpr == -1 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}
                                            : lpr == 0 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_STREAM}

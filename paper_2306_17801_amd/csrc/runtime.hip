@@ -895,13 +895,13 @@ apcg_status apcg_mat_destroy(apcg_mat A) {
         deps = record_deps(A->rec);
     }
     const int dev = A->device;
-    int32_t *smeta = A->sell_meta, *scol = A->sell_col, *doff = A->sdia_off;
-    double *sval = A->sell_val, *dval = A->sdia_val;
+    int32_t *smeta = A->sell_meta, *scol = A->sell_col, *doff = A->sdia_off, *gtab = A->dia_tab;
+    double *sval = A->sell_val, *dval = A->sdia_val, *gval = A->dia_val;
     uint64_t *dmsk = A->sdia_msk;
     if (A->mark_id) intent_forget(A->mark_id);
     delete A;
-    defer_release(std::move(deps), [dev, smeta, scol, sval, doff, dmsk, dval]() {
-        if (smeta || scol || sval || doff || dmsk || dval) {
+    defer_release(std::move(deps), [dev, smeta, scol, sval, doff, dmsk, dval, gtab, gval]() {
+        if (smeta || scol || sval || doff || dmsk || dval || gtab || gval) {
             hipSetDevice(dev);
             hipFree(smeta);
             hipFree(scol);
@@ -909,6 +909,8 @@ apcg_status apcg_mat_destroy(apcg_mat A) {
             hipFree(doff);
             hipFree(dmsk);
             hipFree(dval);
+            hipFree(gtab);
+            hipFree(gval);
         }
     });
     reap();
@@ -920,9 +922,10 @@ static bool valid_spmv_config(const apcg_spmv_config *cfg) {
     int l = cfg->lanes_per_row, b = cfg->block_size;
     bool lok = l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64;
     if (cfg->schedule == APCG_SPMV_SDIA) lok = l >= 1 && l <= 64;  // planes per marching task
+    if (cfg->schedule == APCG_SPMV_DIA) lok = l == 1;
     bool bok = b == 256 || b == 512;
     bool sok = cfg->schedule == APCG_SPMV_ROWGROUP || cfg->schedule == APCG_SPMV_STREAM ||
-               cfg->schedule == APCG_SPMV_SELL || cfg->schedule == APCG_SPMV_SDIA;
+               cfg->schedule == APCG_SPMV_SELL || cfg->schedule == APCG_SPMV_SDIA || cfg->schedule == APCG_SPMV_DIA;
     return lok && bok && sok && cfg->blocks >= 0;
 }
 
@@ -938,6 +941,11 @@ apcg_status apcg_mat_set_spmv_config(apcg_mat A, const apcg_spmv_config *cfg) {
         apcg_status s = apcg::sdia_analyse(A);
         if (s) return s;
         if (A->sdia_state < 0) return set_error(APCG_ERR_UNSUPPORTED, A->sdia_reason);
+    }
+    if (cfg->schedule == APCG_SPMV_DIA) {
+        apcg_status s = apcg::dia_analyse(A);
+        if (s) return s;
+        if (A->dia_state < 0) return set_error(APCG_ERR_UNSUPPORTED, A->dia_reason);
     }
     A->cfg = *cfg;
     return APCG_SUCCESS;
@@ -960,6 +968,22 @@ apcg_status apcg_mat_get_sdia_info(apcg_mat A, int32_t out[6]) {
         APCG_HIP(hipDeviceSynchronize());
         apcg::g_counters.d2h_copies++;
         APCG_HIP(hipMemcpy(&out[5], A->sdia_off + 2 * nsl * A->sdia_mp, sizeof(int32_t), hipMemcpyDeviceToHost));
+    }
+    return APCG_SUCCESS;
+}
+
+apcg_status apcg_mat_get_dia_info(apcg_mat A, int32_t out[4]) {
+    if (!A || !out) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+    out[0] = A->dia_state;
+    out[1] = A->dia_nd;
+    out[2] = A->dia_sym;
+    out[3] = 0;
+    if (A->dia_state == 1 && A->dia_tab) {
+        APCG_HIP(hipSetDevice(A->device));
+        apcg::g_counters.host_syncs++;
+        APCG_HIP(hipDeviceSynchronize());
+        apcg::g_counters.d2h_copies++;
+        APCG_HIP(hipMemcpy(&out[3], A->dia_tab + 18, sizeof(int32_t), hipMemcpyDeviceToHost));
     }
     return APCG_SUCCESS;
 }
