@@ -93,6 +93,14 @@ def sdia_upper_slots(A):
     return int(np.unique(key[off >= 0]).size)
 
 
+def dia_offsets(A):
+    """The distinct column offsets (column - row) of A, ascending."""
+    import numpy as np
+
+    rows = np.repeat(np.arange(A.n, dtype=np.int64), np.diff(A.rowptr))
+    return sorted(int(o) for o in np.unique(A.col.astype(np.int64) - rows))
+
+
 def is_symmetric(A):
     """Pattern and values symmetric bit for bit."""
     import numpy as np
@@ -826,7 +834,16 @@ def main():
     prod_pair_us, _ = apcg.apcg_ctx_kernel_times(ctx, 0)
     upd_pair_us, _ = apcg.apcg_ctx_kernel_times(ctx, 1)
     cfg_now = apcg.apcg_mat_get_spmv_config(A.h)
-    if cfg_now["schedule"] == apcg.APCG_SPMV_SDIA:
+    dia_sym = False
+    if cfg_now["schedule"] == apcg.APCG_SPMV_DIA:
+        # diagonals: 8 bytes per row per diagonal streamed (with symmetric
+        # values only those on and right of the main one: the others are
+        # read as their transposes); z, p_old read, p, w written
+        offs = dia_offsets(A_h)
+        dia_sym = apcg.apcg_mat_get_dia_info(A.h)["values_symmetric"] == 1
+        streamed = sum(1 for o in offs if o >= 0) if dia_sym else len(offs)
+        prod_bytes = 8 * streamed * n + 32 * n
+    elif cfg_now["schedule"] == apcg.APCG_SPMV_SDIA:
         # sliced diagonals: 8 bytes per stored value slot (absent entries of a
         # slice's shared offsets included), 12 per offset/mask slot; z, p_old
         # read, p, w written
@@ -844,6 +861,7 @@ def main():
     iter_bytes = prod_bytes + upd_bytes
     achieved = prod_bytes / (prod_us * 1e-6) / 1e9
     traffic = None
+    traffic_note = "no counter file for this code and configuration"
     if os.path.exists(TRAFFIC_FILE):
         with open(TRAFFIC_FILE) as f:
             tr = json.load(f)
@@ -852,17 +870,23 @@ def main():
             for entry in tr.get("configs", []):  # one per SpMV configuration measured
                 if entry.get("spmv_config") == cfg_chosen:
                     traffic = entry.get("bytes_per_launch")
+                    traffic_note = (f"not measured in this run: {os.path.relpath(TRAFFIC_FILE, ROOT)}, rocprofv3 "
+                                    f"--pmc FETCH_SIZE and WRITE_SIZE passes on the same kernel code (hash "
+                                    f"{tr['source_sha256_16']}) and configuration, scaled by a 1 GiB copy "
+                                    f"calibration (fetch x{tr.get('fetch_scale')}, write x{tr.get('write_scale')})")
     sym_reads = cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1 and is_symmetric(A_h)
     kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell",
+             apcg.APCG_SPMV_DIA: "k_pcg_product_dia",
              apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia" + ("_march" if cfg_now["lanes_per_row"] > 1 else "")}.get(
         cfg_now["schedule"], "k_pcg_product") + (
         f" (block {cfg_now['block_size']}, {cfg_now['lanes_per_row']} planes per task"
         + (", symmetric reads)" if sym_reads else ")")
         if cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1
-        else f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups)")
+        else f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups"
+        + (", symmetric reads)" if dia_sym else ")"))
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes_per_launch": prod_bytes,
+                "traffic": traffic, "traffic_source": traffic_note, "algorithmic_bytes_per_launch": prod_bytes,
                 "csr_product_bytes_per_launch": csr_bytes,
                 "mean_launch_us": round(prod_us, 3), "launches_timed": prod_cnt,
                 "timing": "HIP events around back-to-back launches on the solve's stream",

@@ -58,3 +58,13 @@ def test_source_hash_ignores_comments_and_whitespace(tmp_path):
     c.write_text("int f(int x) {\n    return x + 2;\n}\n")
     assert bench.source_hash(str(a)) == bench.source_hash(str(b))
     assert bench.source_hash(str(a)) != bench.source_hash(str(c))
+
+
+def test_dia_offsets_of_stencils():
+    """Distinct column offsets: the 3D 7-point grid (nz, ny, nx) has
+    0, +-1, +-nx, +-nx ny; the 2D 9-point box stencil has the 9 offsets
+    of its 3 x 3 neighbourhood."""
+    A = P.stencil_laplacian((4, 5, 6), 7)
+    assert bench.dia_offsets(A) == [-30, -6, -1, 0, 1, 6, 30]
+    B = P.stencil_laplacian((7, 8), 9)
+    assert bench.dia_offsets(B) == [-9, -8, -7, -1, 0, 1, 7, 8, 9]
