@@ -193,7 +193,7 @@ def bench_latency(apcg, torch, reps=50):
     return out
 
 
-def bench_batch(apcg, torch, reps):
+def bench_batch(apcg, torch, reps, only=None):
     """256 independent 2D 5-point systems (side ~ U{32..256}, k = exp(N(0,1)),
     b ~ U[-1,1], seed 3), Jacobi-PCG rtol 1e-8: one batched persistent launch
     (graph) against the plain path, one apcg_ksp_solve per system spread over
@@ -212,6 +212,8 @@ def bench_batch(apcg, torch, reps):
     best = None
     for name, sched, tb in (("persistent256", 1, 256), ("persistent512", 1, 512), ("persistent1024", 1, 1024),
                             ("segmented", 2, 0), ("segmented_sdia", 2, 0)):
+        if only is not None and name != only:
+            continue
         if name == "segmented_sdia":
             # the matrices on the sliced-diagonal schedule (a one-time host
             # analysis each): the segmented tile product reads those copies,
@@ -240,6 +242,11 @@ def bench_batch(apcg, torch, reps):
     out["converged"] = sum(1 for r in res if r["status"] == apcg.APCG_SOLVE_CONVERGED)
     out["iterations_min_max"] = [min(r["iterations"] for r in res), max(r["iterations"] for r in res)]
     log(f"[bench] batch: {out} ")
+    if only is not None:  # one schedule alone (profiling runs): no per-solve loop
+        apcg.apcg_info_destroy(info)
+        apcg.apcg_ctx_synchronize(ctx)
+        apcg.apcg_ctx_destroy(ctx)
+        return out
 
     # plain path: one graph-mode solve per system, 8 contexts round robin
     kids = apcg.apcg_ctx_fork(ctx, 8)
@@ -718,6 +725,10 @@ def main():
                     help="skip the latency-bound 64 x 64 Poisson measurement and the latency floors")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-system batched measurement")
     ap.add_argument("--batch-reps", type=int, default=3)
+    ap.add_argument("--batch-only", type=str, default=None,
+                    choices=["persistent256", "persistent512", "persistent1024", "segmented", "segmented_sdia"],
+                    help="only run the 256-system batch with this schedule (no headline solve, no per-solve loop; "
+                         "for profiling) and print its figures as one JSON line")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
     ap.add_argument("--learned-train", type=int, default=2000, help="training systems")
     ap.add_argument("--learned-eval", type=int, default=200, help="held-out systems")
@@ -763,6 +774,9 @@ def main():
 
     if args.copy_calibration:
         copy_calibration(apcg, torch)
+        return
+    if args.batch_only:
+        print(json.dumps({"batch2d_256": bench_batch(apcg, torch, args.batch_reps, only=args.batch_only)}), flush=True)
         return
     if args.sweep:
         res = bench_sweep(apcg, torch, args.sweep_nnz, args.sweep_reps, args.sweep_cpu_max_nnz, args.sweep_stencils)

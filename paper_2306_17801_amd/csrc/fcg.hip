@@ -65,7 +65,10 @@ struct FcgState {
     int32_t maxit, stall_min;
     int32_t status, flag, zero_x, reject;
 };
-static_assert(sizeof(FcgState) <= 512, "FCG state exceeds its allocation");
+static_assert(sizeof(FcgState) <= 448, "FCG state exceeds its allocation");
+// The state's allocation is 512 bytes; the fallback gate (int32[2], written
+// by k_fcg_gate) sits at this byte offset after it.
+constexpr int kGateOffset = 448;
 
 __device__ __forceinline__ double pdir_f(double z, double beta, double pold) { return fma(beta, pold, z); }
 
@@ -319,7 +322,21 @@ __global__ __launch_bounds__(TBF) void k_fcg_update(int64_t n, double *__restric
 }
 
 // Writes the result record; with a fallback solve, adds its iterations.
-__global__ void k_fcg_finish(const FcgState *st, const apcg_solve_info *fallback, apcg_solve_info *out) {
+// After the flexible phase: gate[0] = 1 when it ended in a breakdown, a
+// rejected polynomial or a stall (not a setup error) and the fallback is
+// enabled, gate[1] = the iterations left for the Jacobi-PCG fallback.  The
+// fallback solve queued after it reads the gate on the device, so the host
+// never waits for this decision.
+__global__ void k_fcg_gate(const FcgState *st, int32_t *gate, int32_t maxit, int fallback) {
+    if (threadIdx.x != 0) return;
+    const int bad = APCG_SOLVE_BREAKDOWN_PAP | APCG_SOLVE_BREAKDOWN_RZ | APCG_SOLVE_STALL;
+    const int32_t done = max(st->rec[0].its, st->rec[1].its);
+    gate[0] = fallback && (st->status & bad) && !(st->status & APCG_SOLVE_SETUP_ERROR) ? 1 : 0;
+    gate[1] = max(0, maxit - done);
+}
+
+__global__ void k_fcg_finish(const FcgState *st, const apcg_solve_info *fallback, const int32_t *gate,
+                             apcg_solve_info *out) {
     if (threadIdx.x != 0) return;
     int status = st->status ? st->status : APCG_SOLVE_MAXIT;
     const FcgRec last = st->rec[0].its >= st->rec[1].its ? st->rec[0] : st->rec[1];
@@ -327,7 +344,7 @@ __global__ void k_fcg_finish(const FcgState *st, const apcg_solve_info *fallback
     o.fcg_iterations = last.its;
     o.half_steps = 0;
     o.ref_norm = st->ref;
-    if (fallback) {
+    if (fallback && gate[0]) {
         o.iterations = last.its + fallback->iterations;
         o.status = fallback->status | APCG_SOLVE_FALLBACK | status;
         o.res_norm = fallback->res_norm;
@@ -596,32 +613,30 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
                 }
             }
         }
-        // Fallback: the flexible phase ended in a breakdown, a rejected
-        // polynomial or a stall.  Reading its status is the one host wait of
-        // the solve outside the pacing polls.
+        // Fallback: when the flexible phase ended in a breakdown, a rejected
+        // polynomial or a stall, Jacobi-PCG continues from the current x for
+        // the iterations left.  The decision is taken on the device: the
+        // gate kernel writes it, and the fallback solve, always queued (one
+        // graph period ahead of its poll), reads it in its first kernels and
+        // is a no-op when not needed -- the host never waits for the
+        // flexible phase's outcome.
+        int32_t *gate = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(fc->st) + kGateOffset);
+        hipLaunchKernelGGL(k_fcg_gate, dim3(1), dim3(64), 0, st, (const FcgState *)fc->st, gate, maxit,
+                           fo.fallback ? 1 : 0);
+        APCG_CHECK_LAUNCH("k_fcg_gate");
         const apcg_solve_info *fb = nullptr;
         if (fo.fallback) {
-            FcgState hs;
-            g_counters.host_syncs++;
-            g_counters.d2h_copies++;
-            APCG_HIP(hipMemcpyAsync(&hs, fc->st, sizeof hs, hipMemcpyDeviceToHost, st));
-            APCG_HIP(hipStreamSynchronize(st));
-            const int bad = APCG_SOLVE_BREAKDOWN_PAP | APCG_SOLVE_BREAKDOWN_RZ | APCG_SOLVE_STALL;
-            const int32_t done = std::max(hs.rec[0].its, hs.rec[1].its);
-            if ((hs.status & bad) && !(hs.status & APCG_SOLVE_SETUP_ERROR)) {
-                apcg_solve_opts po;
-                apcg_solve_opts_default(&po);
-                po.mode = opts.mode;
-                po.iters_per_graph = opts.iters_per_graph;
-                po.lookahead = opts.lookahead;
-                po.x0_is_zero = 0;
-                const int32_t left = std::max(0, maxit - done);
-                if ((s = pcg_solve_marked(ctx, A, b, x, rtol, left, &po, fc->fb_info, 0, nullptr, 0))) return s;
-                fb = fc->fb_info->d;
-            }
+            apcg_solve_opts po;
+            apcg_solve_opts_default(&po);
+            po.mode = opts.mode == APCG_MODE_STREAM || opts.mode == APCG_MODE_HOST_CHECK ? opts.mode : APCG_MODE_GRAPH;
+            po.iters_per_graph = opts.iters_per_graph;
+            po.lookahead = 1;
+            po.x0_is_zero = 0;
+            if ((s = pcg_solve_marked(ctx, A, b, x, rtol, maxit, &po, fc->fb_info, 0, nullptr, 0, gate))) return s;
+            fb = fc->fb_info->d;
         }
         hipLaunchKernelGGL(k_fcg_finish, dim3(1), dim3(64), 0, st, (const FcgState *)fc->st, fb,
-                           info->d + info_index);
+                           (const int32_t *)gate, info->d + info_index);
         APCG_CHECK_LAUNCH("k_fcg_finish");
         return op_end(ctx, acc, 4);
     } catch (const std::bad_alloc &) {

@@ -258,9 +258,13 @@ inline int sdia_walk(const apcg_mat_s *A) {
 }
 // Jacobi-PCG solve with registry marking (pcg.hip); hist (2 hist_cap doubles,
 // device) receives alpha_k and beta_k of the first hist_cap iterations.
+// gate (device int32[2], may be null): read by the solve's first kernels --
+// gate[0] == 0 turns the whole solve into no-ops (x untouched, record of 0
+// iterations), otherwise gate[1] replaces maxit on the device (the host
+// queues at most maxit iterations).
 apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                              const apcg_solve_opts *opts, apcg_info info, int32_t info_index, double *hist,
-                             int32_t hist_cap);
+                             int32_t hist_cap, const int32_t *gate = nullptr);
 void seg_cache_release(uint64_t ctx_id, int device);    // batched.hip
 void learn_cache_release(uint64_t ctx_id, int device);  // learn.hip
 void fcg_cache_release(uint64_t ctx_id, int device);    // fcg.hip

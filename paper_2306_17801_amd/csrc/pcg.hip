@@ -102,7 +102,8 @@ __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__res
                                                  double *__restrict__ r, double *__restrict__ dinv,
                                                  double *__restrict__ z, double *__restrict__ pold,
                                                  double *partials, int64_t per_block, int x0_zero, int pc,
-                                                 int norm_pre) {
+                                                 int norm_pre, const int32_t *gate) {
+    if (gate && !gate[0]) return;  // gated off: the solve is a no-op
     const dev::Chunk c = dev::block_chunk(n, per_block);
     double rz = 0.0, nres = 0.0, nref = 0.0, bad = 0.0;
     for (int64_t i = c.lo + threadIdx.x; i < c.hi; i += VB) {
@@ -148,7 +149,18 @@ __global__ __launch_bounds__(VB) void k_pcg_init(int32_t n, const int32_t *__res
 
 // One workgroup: reference norm, initial tests, record 0.
 __global__ __launch_bounds__(64) void k_pcg_init_final(SolveState *st, const double *partials, int G, double rtol,
-                                                       int32_t maxit, double *hist, int32_t hist_cap) {
+                                                       int32_t maxit, double *hist, int32_t hist_cap,
+                                                       const int32_t *gate) {
+    if (gate && !gate[0]) {  // gated off: stop before the first iteration, nothing computed
+        if (threadIdx.x == 0) {
+            st->zero_x = 0;
+            st->hist = nullptr;
+            st->hist_cap = 0;
+            terminate(st, 0, 0, 0.0);
+        }
+        return;
+    }
+    if (gate) maxit = gate[1];
     double v[4];
     dev::reduce_partials<64, 4>(partials, G, v);
     if (threadIdx.x != 0) return;
@@ -1601,7 +1613,7 @@ namespace apcg {
 
 apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                              const apcg_solve_opts *opts_in, apcg_info info, int32_t info_index, double *hist,
-                             int32_t hist_cap) {
+                             int32_t hist_cap, const int32_t *gate) {
     try {
         if (!A || !b || !x || !info) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
         if (b->n != A->n || x->n != A->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
@@ -1622,9 +1634,9 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
         if (opts.mode < APCG_MODE_GRAPH || opts.mode > APCG_MODE_AUTO)
             return set_error(APCG_ERR_INVALID_ARG, "unknown mode");
         if (opts.mode == APCG_MODE_AUTO)
-            opts.mode = A->n <= APCG_PERSISTENT_MAX_N && !hist && !opts.kernel_timing ? APCG_MODE_PERSISTENT
-                                                                                     : APCG_MODE_GRAPH;
-        if (opts.mode == APCG_MODE_PERSISTENT && (A->n > APCG_PERSISTENT_MAX_N || hist))
+            opts.mode = A->n <= APCG_PERSISTENT_MAX_N && !hist && !gate && !opts.kernel_timing ? APCG_MODE_PERSISTENT
+                                                                                              : APCG_MODE_GRAPH;
+        if (opts.mode == APCG_MODE_PERSISTENT && (A->n > APCG_PERSISTENT_MAX_N || hist || gate))
             return set_error(APCG_ERR_INVALID_ARG, "the persistent mode takes n <= APCG_PERSISTENT_MAX_N");
         if (opts.iters_per_graph < 1) return set_error(APCG_ERR_INVALID_ARG, "iters_per_graph must be >= 1");
         if (opts.lookahead < 1 || opts.lookahead > kMaxLookahead)
@@ -1656,10 +1668,10 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
 
         hipLaunchKernelGGL(k_pcg_init, dim3(pl.g_vec), dim3(VB), 0, st, A->n, A->rowptr, A->col, A->val, b->d, x->d,
                            c->ws.r(), c->ws.dinv(), c->ws.z(), c->ws.p(0), bf.part_res(), pl.pb_vec,
-                           opts.x0_is_zero ? 1 : 0, opts.pc, norm_pre);
+                           opts.x0_is_zero ? 1 : 0, opts.pc, norm_pre, gate);
         APCG_CHECK_LAUNCH("k_pcg_init");
         hipLaunchKernelGGL(k_pcg_init_final, dim3(1), dim3(64), 0, st, c->ws.state, (const double *)bf.part_res(),
-                           pl.g_vec, rtol, maxit, hist, hist_cap);
+                           pl.g_vec, rtol, maxit, hist, hist_cap, gate);
         APCG_CHECK_LAUNCH("k_pcg_init_final");
         if (!opts.x0_is_zero) {
             hipLaunchKernelGGL(k_pcg_zero_x_if, dim3(pl.g_vec), dim3(VB), 0, st, x->d, (int64_t)A->n, pl.pb_vec,

@@ -516,3 +516,48 @@ def test_learned_solve_equals_its_steps(apcg, ctx):
     assert r1 == r2 and r1["status"] & apcg.APCG_SOLVE_CONVERGED
     assert np.array_equal(x1.numpy(), x2.numpy())
     apcg.apcg_info_destroy(info)
+
+
+@pytest.mark.parametrize("poly", ["chebyshev", "rejected", "learned"])
+def test_fcg_and_learned_solves_take_no_host_wait(apcg, ctx, poly):
+    """The fallback decision is taken on the device (the Jacobi-PCG fallback
+    is always queued and gated by the flexible phase's outcome): a flexible
+    solve that converges, one whose polynomial is rejected (the fallback
+    runs), and the one-call learned solve make no host synchronisation;
+    the host only polls events for pacing.  Each result meets the oracle's
+    bar."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    s = _sys2d(40, 1.0, 61)
+    lmax = oracle.gershgorin(s.A)[1]
+    dA, db, dx = DeviceCSR(s.A), DeviceVec(s.b), DeviceVec.zeros(s.A.n)
+    info = apcg.apcg_info_create(0, 1)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    if poly == "learned":
+        params = _params(3)
+        params["b3"] = np.array([1.2, -0.5, 0.2, -0.05, 0, 0, 0, 0, 0])
+        dP = dev(pack(params))
+        dM, dS = dev(np.zeros(16, np.float32)), dev(np.ones(16, np.float32))
+        torch.cuda.synchronize()
+        apcg.apcg_counters_reset()
+        apcg.apcg_ksp_solve_learned(ctx, dA.h, db.h, dx.h, 1e-10, 20000, dP, dM, dS, opts, None, info, 0)
+    else:
+        c = (cheb_iteration_coeffs(lmax, lmax / 40) if poly == "chebyshev"
+             else np.array([0.2, -0.5, 0, 0, 0, 0, 0, 0, 0]))
+        cc, lm = dev(np.asarray(c, np.float32)), dev(np.array([lmax]), "float64")
+        torch.cuda.synchronize()
+        apcg.apcg_counters_reset()
+        apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, dx.h, 1e-10, 20000, cc, lm, opts, None, info, 0)
+        ref = oracle.fcg_poly(s.A, s.b, np.asarray(c, np.float32).astype(np.float64), lmax, rtol=1e-10,
+                              maxit=20000)
+    cnt = apcg.apcg_counters_get()
+    res = apcg.apcg_info_get(info, 0)
+    print(f"case no host wait {poly}: {cnt} {res}", flush=True)
+    assert cnt["host_syncs"] == 0
+    assert res["status"] & apcg.APCG_SOLVE_CONVERGED
+    if poly != "learned":
+        assert res["status"] == ref.status and abs(res["iterations"] - ref.its) <= 1
+        assert rel(dx.numpy(), ref.x) <= 1e-9
+        assert bool(res["status"] & apcg.APCG_SOLVE_FALLBACK) == (poly == "rejected")
+    apcg.apcg_info_destroy(info)
