@@ -559,6 +559,46 @@ apcg_status apcg_info_get(apcg_info info, int32_t index, apcg_solve_info *out);
 apcg_status apcg_ksp_solve(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                            const apcg_solve_opts *opts, apcg_info info, int32_t info_index);
 
+/* Tuning table (the autotuner's results kept and reused; a8 of the hot
+ * path's autotuner row, not a passage of the paper).  A key is
+ *   "<arch>|u<U>.d<D>.p<P>.s<S>.m<M>|n<floor(log2 n)>|r<round(4 nnz/n)>"
+ * with U the most distinct column offsets (column - row) of any 64-row slice
+ * (capped at 33), D the distinct offsets of the matrix (0 when more than 9),
+ * P = 1 when an offset 64 k is present with both signs in at least half of
+ * the slices (plane marching applies), S = 1 for a structurally symmetric
+ * pattern and M the longest row.  A value is four int32 (for a product
+ * schedule: apcg_spmv_config's fields in order) and the measured
+ * microseconds.  The table is process-wide host memory guarded by a mutex.
+ *
+ * apcg_tune_key_pattern: the key of host CSR arrays for device architecture
+ *   `arch` (gcnArchName), written to out (cap bytes incl. the terminating
+ *   0).  Host only.  APCG_ERR_INVALID_ARG on bad arrays or a short buffer.
+ * apcg_mat_tune_key: the key of A on its device (reads A's pattern back
+ *   once, synchronously, and keeps the class with A).
+ * apcg_tune_cache_insert / _lookup / _clear / _size: the table itself
+ *   (lookup sets *found to 0 or 1; *us may be NULL).
+ * apcg_tune_cache_load: merges the entries of a text file written by
+ *   apcg_tune_cache_save (one "key TAB i0 i1 i2 i3 TAB us" line per entry,
+ *   '#' lines ignored); a malformed file changes nothing and returns
+ *   APCG_ERR_INVALID_ARG naming the line.  *entries (may be NULL): lines read.
+ * apcg_tune_cache_save: writes the whole table (sorted by key) to path,
+ *   through a temporary file renamed into place.
+ * apcg_mat_autotune_cached: apcg_mat_autotune unless A's key is in the
+ *   table with a configuration A accepts (apcg_mat_set_spmv_config
+ *   succeeds), in which case that configuration is set without timing and
+ *   *from_cache = 1; a fresh result is inserted under A's key. */
+apcg_status apcg_tune_key_pattern(const char *arch, int32_t n, int64_t nnz, const int32_t *rowptr,
+                                  const int32_t *col, char *out, int32_t cap);
+apcg_status apcg_mat_tune_key(apcg_mat A, char *out, int32_t cap);
+apcg_status apcg_tune_cache_insert(const char *key, const int32_t values[4], double us);
+apcg_status apcg_tune_cache_lookup(const char *key, int32_t values[4], double *us, int32_t *found);
+apcg_status apcg_tune_cache_clear(void);
+apcg_status apcg_tune_cache_size(int32_t *entries);
+apcg_status apcg_tune_cache_load(const char *path, int32_t *entries);
+apcg_status apcg_tune_cache_save(const char *path, int32_t *entries);
+apcg_status apcg_mat_autotune_cached(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best,
+                                     double *best_us, int32_t *from_cache);
+
 /* Latency floors of the device (Section 4.2: below about 1e5 nonzeros the
  * GPU solve is bound by latency).  Runs on a private stream of `device`,
  * blocks the host, and writes microseconds to out_us:

@@ -17,6 +17,7 @@ kernels must be complete before the library reads them (for example
 from __future__ import annotations
 
 import ctypes
+import os
 
 from . import _capi
 from ._capi import *  # noqa: F401,F403  -- constants and structures
@@ -367,6 +368,75 @@ def apcg_mat_autotune(A, ctx, reps: int = 20):
     check("apcg_mat_autotune", _L().apcg_mat_autotune(_h(A), _h(ctx), reps, ctypes.byref(cfg), ctypes.byref(us)))
     return {"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks,
             "schedule": cfg.schedule}, us.value
+
+
+def apcg_mat_autotune_cached(A, ctx, reps: int = 20):
+    """apcg_mat_autotune through the tuning table: (config dict, microseconds,
+    True when the configuration came from the table)."""
+    cfg = _capi.apcg_spmv_config()
+    us = ctypes.c_double()
+    hit = ctypes.c_int32()
+    check("apcg_mat_autotune_cached", _L().apcg_mat_autotune_cached(_h(A), _h(ctx), reps, ctypes.byref(cfg),
+                                                                    ctypes.byref(us), ctypes.byref(hit)))
+    return ({"lanes_per_row": cfg.lanes_per_row, "block_size": cfg.block_size, "blocks": cfg.blocks,
+             "schedule": cfg.schedule}, us.value, bool(hit.value))
+
+
+def apcg_tune_key_pattern(arch: str, rowptr, col) -> str:
+    """Tuning key of host CSR arrays (numpy int32) for architecture `arch`."""
+    import numpy as np
+
+    rp = np.ascontiguousarray(rowptr, dtype=np.int32)
+    cl = np.ascontiguousarray(col, dtype=np.int32)
+    n = rp.size - 1
+    out = ctypes.create_string_buffer(512)
+    check("apcg_tune_key_pattern", _L().apcg_tune_key_pattern(arch.encode(), n, int(rp[-1]) if n >= 0 else 0,
+                                                              rp.ctypes.data_as(ctypes.c_void_p),
+                                                              cl.ctypes.data_as(ctypes.c_void_p), out, 512))
+    return out.value.decode()
+
+
+def apcg_mat_tune_key(A) -> str:
+    out = ctypes.create_string_buffer(512)
+    check("apcg_mat_tune_key", _L().apcg_mat_tune_key(_h(A), out, 512))
+    return out.value.decode()
+
+
+def apcg_tune_cache_insert(key: str, values, us: float) -> None:
+    v = (ctypes.c_int32 * 4)(*[int(x) for x in values])
+    check("apcg_tune_cache_insert", _L().apcg_tune_cache_insert(key.encode(), v, float(us)))
+
+
+def apcg_tune_cache_lookup(key: str):
+    """(values tuple, microseconds) or None."""
+    v = (ctypes.c_int32 * 4)()
+    us = ctypes.c_double()
+    found = ctypes.c_int32()
+    check("apcg_tune_cache_lookup", _L().apcg_tune_cache_lookup(key.encode(), v, ctypes.byref(us),
+                                                                ctypes.byref(found)))
+    return (tuple(v), us.value) if found.value else None
+
+
+def apcg_tune_cache_clear() -> None:
+    check("apcg_tune_cache_clear", _L().apcg_tune_cache_clear())
+
+
+def apcg_tune_cache_size() -> int:
+    n = ctypes.c_int32()
+    check("apcg_tune_cache_size", _L().apcg_tune_cache_size(ctypes.byref(n)))
+    return n.value
+
+
+def apcg_tune_cache_load(path: str) -> int:
+    n = ctypes.c_int32()
+    check("apcg_tune_cache_load", _L().apcg_tune_cache_load(os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
+def apcg_tune_cache_save(path: str) -> int:
+    n = ctypes.c_int32()
+    check("apcg_tune_cache_save", _L().apcg_tune_cache_save(os.fsencode(path), ctypes.byref(n)))
+    return n.value
 
 
 def apcg_mat_time_kernels(A, ctx, reps: int = 100):

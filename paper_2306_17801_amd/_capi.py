@@ -18,6 +18,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libapcg.so")
 
 c_i32, c_i64, c_f64, c_vp = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_void_p
+c_char_p = ctypes.c_char_p
 
 # constants (mirror include/apcg.h)
 APCG_SUCCESS = 0
@@ -190,6 +191,15 @@ SIGNATURES = {
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
     "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
     "apcg_latency_floors": [c_i32, c_i32, P(c_f64)],
+    "apcg_tune_key_pattern": [c_char_p, c_i32, c_i64, c_vp, c_vp, c_char_p, c_i32],
+    "apcg_mat_tune_key": [c_vp, c_char_p, c_i32],
+    "apcg_tune_cache_insert": [c_char_p, P(c_i32), c_f64],
+    "apcg_tune_cache_lookup": [c_char_p, P(c_i32), P(c_f64), P(c_i32)],
+    "apcg_tune_cache_clear": [],
+    "apcg_tune_cache_size": [P(c_i32)],
+    "apcg_tune_cache_load": [c_char_p, P(c_i32)],
+    "apcg_tune_cache_save": [c_char_p, P(c_i32)],
+    "apcg_mat_autotune_cached": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64), P(c_i32)],
     "apcg_solve_opts_default": [P(apcg_solve_opts)],
     "apcg_info_create": [c_i32, c_i32, P(c_vp)],
     "apcg_info_destroy": [c_vp],

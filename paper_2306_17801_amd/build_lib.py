@@ -13,7 +13,7 @@ from concurrent.futures import ThreadPoolExecutor
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 SOURCES = ["runtime.hip", "blas.hip", "pcg.hip", "batched.hip", "learn.hip", "fcg.hip", "batched_fcg.hip",
-           "tfqmr.hip", "intent.hip", "expr.hip", "persist.hip"]
+           "tfqmr.hip", "intent.hip", "expr.hip", "persist.hip", "tune.hip"]
 LIB = os.path.join(HERE, "libapcg.so")
 OBJDIR = os.path.join(ROOT, "_build")
 

@@ -214,6 +214,7 @@ struct apcg_mat_s {
     double *dia_val = nullptr;       // device [dia_ndt][n rounded up to 64]
     apcg::Record rec;
     uint64_t mark_id = 0;
+    std::string tune_class;  // pattern class of the tuning key (tune.hip), computed once
 };
 
 struct apcg_info_s {
@@ -234,6 +235,13 @@ apcg_status resolve_ctx(apcg_ctx in, int device, apcg_ctx *out);  // NULL -> glo
 apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
+// tuning table (tune.hip): the key of a pattern, lookups and inserts
+std::string pattern_class(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cl);
+std::string tune_key(const std::string &arch, const std::string &cls, int64_t n, int64_t nnz);
+apcg_status device_arch(int device, std::string *out);
+apcg_status mat_tune_key(apcg_mat_s *A, std::string *key);
+bool tune_lookup(const std::string &key, int32_t v[4], double *us);
+void tune_insert(const std::string &key, const int32_t v[4], double us);
 // diagonal (DIA) layout (pcg.hip)
 constexpr int kDiaMaxDiags = 9;
 apcg_status dia_analyse(apcg_mat_s *A);
