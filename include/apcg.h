@@ -793,7 +793,11 @@ apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys, const apc
 /* The learned solve in one call: features of (A, b), standardised with
  * dev_mean[16] / dev_std[16], the network dev_params[5833] -> coefficients,
  * then apcg_ksp_solve_fcg_poly with them (same options, result record and
- * fallback).  Network arrays are device pointers ordered on ctx only. */
+ * fallback).  With opts->x0_is_zero the flexible solve starts
+ * from the iterate of the feature run's 12 Jacobi-PCG steps from x0 = 0
+ * (copied into x) rather than from 0, so those steps are not thrown away;
+ * the record counts the flexible solve's iterations only.  Network arrays
+ * are device pointers ordered on ctx only. */
 apcg_status apcg_ksp_solve_learned(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, double rtol, int32_t maxit,
                                    const float *dev_params, const float *dev_mean, const float *dev_std,
                                    const apcg_solve_opts *opts, const apcg_fcg_opts *fopts, apcg_info info,

@@ -665,7 +665,23 @@ apcg_status apcg_ksp_solve_learned(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_ve
         hipLaunchKernelGGL(k_mlp_fwd, dim3(1), dim3(64), 0, ctx->stream, dev_params, (const float *)feat, 1,
                            (float *)nullptr, (float *)nullptr, coef);
         APCG_CHECK_LAUNCH("k_mlp_fwd");
-        return apcg_ksp_solve_fcg_poly(ctx, A, b, x, rtol, maxit, coef, fs->dbuf, opts, fopts, info, info_index);
+        apcg_solve_opts o;
+        if (opts) o = *opts;
+        else apcg_solve_opts_default(&o);
+        if (o.x0_is_zero) {
+            // Warm start: the feature run's Jacobi-PCG steps from x0 = 0 left
+            // their iterate in the scratch x; the flexible solve continues
+            // from it instead of discarding it.
+            if (!x || x->n != A->n || x->device != A->device)
+                return set_error(APCG_ERR_INVALID_ARG, "x does not match the system");
+            Acc acc[1] = {{&x->rec, ACC_W}};
+            if ((s = op_begin(ctx, acc, 1))) return s;
+            APCG_HIP(hipMemcpyAsync(x->d, fs->x, sizeof(double) * (size_t)A->n, hipMemcpyDeviceToDevice,
+                                    ctx->stream));
+            if ((s = op_end(ctx, acc, 1))) return s;
+            o.x0_is_zero = 0;
+        }
+        return apcg_ksp_solve_fcg_poly(ctx, A, b, x, rtol, maxit, coef, fs->dbuf, &o, fopts, info, info_index);
     } catch (const std::bad_alloc &) {
         return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
     }

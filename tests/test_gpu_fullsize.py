@@ -16,8 +16,9 @@
    whose polynomial was not replaced.
 2. The learned single solve on a 3D system of side 80 from the learned
    workload's distribution (512,000 rows): the one-call learned solve equals
-   features -> network -> FCG bit for bit, and the FCG solve matches the
-   oracle at the same bar.
+   features -> network -> FCG from the feature run's 12-step iterate bit for
+   bit, and that FCG solve matches the oracle's FCG from the oracle's own
+   12-step iterate at the same bar.
 """
 import numpy as np
 import pytest
@@ -209,14 +210,18 @@ def test_learned_single_solve_side_80(apcg, ctx, network):
     opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
     info = apcg.apcg_info_create(0, 2)
     x1, x2 = DeviceVec.zeros(s.A.n), DeviceVec.zeros(s.A.n)
-    apcg.apcg_ksp_solve_fcg_poly(ctx, A.h, b.h, x1.h, RTOL, MAXIT, C.view(-1), lm, opts, None, info, 0)
+    # the learned solve starts from the feature run's 12 Jacobi-PCG steps
+    apcg.apcg_ksp_solve(ctx, A.h, b.h, x1.h, 0.0, 12, opts, info, 0)
+    warm = apcg.apcg_solve_opts_default(x0_is_zero=0)
+    apcg.apcg_ksp_solve_fcg_poly(ctx, A.h, b.h, x1.h, RTOL, MAXIT, C.view(-1), lm, warm, None, info, 0)
     L.solve(ctx, network, A.h, b.h, x2.h, RTOL, MAXIT, opts, None, info, 1)
     r1, r2 = apcg.apcg_info_get(info, 0), apcg.apcg_info_get(info, 1)
     assert r1 == r2
     xa = x1.numpy()
     assert np.array_equal(xa, x2.numpy())
     c = C.cpu().numpy().reshape(-1).astype(np.float64)
-    ref = oracle.fcg_poly(s.A, s.b, c, float(lm.cpu()[0]), rtol=RTOL, maxit=MAXIT)
+    x12 = oracle.pcg(s.A, s.b, rtol=0.0, maxit=12).x
+    ref = oracle.fcg_poly(s.A, s.b, c, float(lm.cpu()[0]), x0=x12, rtol=RTOL, maxit=MAXIT)
     e = rel(xa, ref.x)
     print(f"  gpu its {r1['iterations']} fcg {r1['fcg_iterations']} st {r1['status']} | oracle its {ref.its} "
           f"fcg {ref.fcg_its} st {ref.status} | rel {e:.2e}", flush=True)

@@ -482,8 +482,11 @@ def test_fcg_bitwise_repeatable_and_mode_independent(apcg, ctx):
 
 def test_learned_solve_equals_its_steps(apcg, ctx):
     """apcg_ksp_solve_learned = features -> standardise -> forward ->
-    apcg_ksp_solve_fcg_poly, bit for bit; the network's coefficients match
-    the oracle's FP64 forward pass on the oracle's features."""
+    apcg_ksp_solve_fcg_poly started from the iterate of the feature run's 12
+    Jacobi-PCG steps (the same kernels as 12 steps of apcg_ksp_solve with
+    rtol 0), bit for bit; the network's coefficients match the oracle's FP64
+    forward pass on the oracle's features, and the warm-started solve matches
+    the oracle's FCG started from the oracle's own 12-step iterate."""
     import torch
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
@@ -510,11 +513,19 @@ def test_learned_solve_equals_its_steps(apcg, ctx):
     info = apcg.apcg_info_create(0, 2)
     x1, x2 = DeviceVec.zeros(s.A.n), DeviceVec.zeros(s.A.n)
     opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
-    apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, x1.h, 1e-9, 5000, C.view(9), lm, opts, None, info, 0)
+    apcg.apcg_ksp_solve(ctx, dA.h, db.h, x1.h, 0.0, 12, opts, info, 0)  # the feature run's iterate
+    warm = apcg.apcg_solve_opts_default(x0_is_zero=0)
+    apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, db.h, x1.h, 1e-9, 5000, C.view(9), lm, warm, None, info, 0)
     apcg.apcg_ksp_solve_learned(ctx, dA.h, db.h, x2.h, 1e-9, 5000, dP, dM, dS, opts, None, info, 1)
     r1, r2 = apcg.apcg_info_get(info, 0), apcg.apcg_info_get(info, 1)
     assert r1 == r2 and r1["status"] & apcg.APCG_SOLVE_CONVERGED
-    assert np.array_equal(x1.numpy(), x2.numpy())
+    xg = x1.numpy()
+    assert np.array_equal(xg, x2.numpy())
+    x12 = oracle.pcg(s.A, s.b, rtol=0.0, maxit=12).x
+    ref = oracle.fcg_poly(s.A, s.b, c_gpu.astype(np.float64), float(lm.cpu()[0]), x0=x12, rtol=1e-9, maxit=5000)
+    e = np.linalg.norm(xg - ref.x) / np.linalg.norm(ref.x)
+    print(f"case learned warm start: gpu its {r1['iterations']} | oracle its {ref.its} | rel {e:.2e}", flush=True)
+    assert r1["status"] == ref.status and abs(r1["iterations"] - ref.its) <= 1 and e <= 1e-8
     apcg.apcg_info_destroy(info)
 
 
