@@ -7,10 +7,10 @@
 // 512-thread workgroup runs the whole solve in one launch: the iteration of
 // the PCG loop of Section 3.3 (Jacobi preconditioning as in Section 4.1),
 // its scalars and its tests never leave the workgroup.  Each thread owns R
-// rows (row tid + q * 512; R <= 8, so n <= 4096), keeps their r, D^-1, p and
-// A p entries in registers and, when the rows are short enough, their matrix
-// entries as well, so after the setup an iteration reads only the direction
-// vector (and updates x in place, a store nothing waits for):
+// rows (row tid + q * 512; R <= 8, so n <= 4096), keeps their x, r, D^-1, p
+// and A p entries in registers and, when the rows are short enough, their
+// matrix entries as well, so after the setup an iteration reads only the
+// direction vector, and x is written once, at the end:
 //
 //   publish p (one store per owned row into a buffer the workgroup shares),
 //   barrier; w = A p for the owned rows, delta = p.w (workgroup sum, barrier);
@@ -84,7 +84,7 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
     constexpr int LC = L > 0 ? L : 1;
     const int tid = threadIdx.x;
     const int n = a.n;
-    double rr[R], dr[R], pr[R], wr[R];
+    double rr[R], dr[R], pr[R], wr[R], xr[R];
     int jj[R][LC];
     double aa[R][LC];
     int rs[R], rl[R];  // row start and length (rows read from the CSR arrays)
@@ -95,7 +95,7 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
 #pragma unroll
     for (int q = 0; q < R; ++q) {
         const int i = tid + q * WT;
-        rr[q] = dr[q] = pr[q] = wr[q] = 0.0;
+        rr[q] = dr[q] = pr[q] = wr[q] = xr[q] = 0.0;
         rs[q] = rl[q] = 0;
 #pragma unroll
         for (int t = 0; t < LC; ++t) {
@@ -143,6 +143,7 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
             di = ok ? 1.0 / diag : 0.0;
         }
         const double bi = a.b[i];
+        if (!a.x0_zero) xr[q] = a.x[i];
         const double ri = a.x0_zero ? bi : bi - ax;
         rr[q] = ri;
         dr[q] = di;
@@ -158,15 +159,7 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
             v4[1] = fma(ri, ri, v4[1]);
         }
     }
-    // x0 was read by every thread before the barrier of this sum
     wg_sum<4>(v4, red[0]);
-    if (a.x0_zero) {
-#pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int i = tid + q * WT;
-            if (i < n) a.x[i] = 0.0;
-        }
-    }
     double rho = v4[0];
     double res = sqrt(v4[1]);
     const double ref = sqrt(v4[2]);
@@ -176,10 +169,7 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
         status = APCG_SOLVE_CONVERGED;
         res = 0.0;
 #pragma unroll
-        for (int q = 0; q < R; ++q) {
-            const int i = tid + q * WT;
-            if (i < n) a.x[i] = 0.0;
-        }
+        for (int q = 0; q < R; ++q) xr[q] = 0.0;
     } else if (!isfinite(res) || !isfinite(ref)) status = APCG_SOLVE_NAN;
     else if (res <= a.rtol * ref) status = APCG_SOLVE_CONVERGED;
     else if (!(rho > 0.0)) status = isfinite(rho) ? APCG_SOLVE_BREAKDOWN_RZ : APCG_SOLVE_NAN;
@@ -244,7 +234,7 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
         for (int q = 0; q < R; ++q) {
             const int i = tid + q * WT;
             if (i >= n) continue;
-            a.x[i] = fma(alpha, pr[q], a.x[i]);
+            xr[q] = fma(alpha, pr[q], xr[q]);
             rr[q] = fma(-alpha, wr[q], rr[q]);
             const double zi = dr[q] * rr[q];
             v2[0] = fma(zi, rr[q], v2[0]);
@@ -264,6 +254,13 @@ __global__ __launch_bounds__(WT) void k_pcg_wg(WgArgs a) {
 #pragma unroll
             for (int q = 0; q < R; ++q) pr[q] = fma(beta, pr[q], dr[q] * rr[q]);
         }
+    }
+    // x leaves the registers once, at the end (every thread read its x0
+    // entries before the first workgroup sum's barrier)
+#pragma unroll
+    for (int q = 0; q < R; ++q) {
+        const int i = tid + q * WT;
+        if (i < n) a.x[i] = xr[q];
     }
     if (tid == 0) {
         a.out->iterations = its;
@@ -313,14 +310,14 @@ apcg_status launch_pcg_wg(hipStream_t st, int32_t n, const int32_t *rowptr, cons
     WgArgs a{rowptr, col, val, b, x, p, out, rtol, n, maxit, x0_zero, pc, norm_pre};
     const int R = persistent_rows_per_thread(n < 1 ? 1 : n);
     // matrix entries in registers when they fit without spilling (rows of
-    // at most 5 or 7 entries, at most 4 rows per thread)
+    // at most 5 entries, or of at most 7 at up to 4 rows per thread)
     const bool l5 = maxrow >= 0 && maxrow <= 5, l7 = maxrow >= 0 && maxrow <= 7;
     void (*k)(WgArgs) = nullptr;
     switch (R) {
         case 1: k = l5 ? k_pcg_wg<1, 5> : l7 ? k_pcg_wg<1, 7> : k_pcg_wg<1, 0>; break;
         case 2: k = l5 ? k_pcg_wg<2, 5> : l7 ? k_pcg_wg<2, 7> : k_pcg_wg<2, 0>; break;
         case 4: k = l5 ? k_pcg_wg<4, 5> : l7 ? k_pcg_wg<4, 7> : k_pcg_wg<4, 0>; break;
-        case 8: k = k_pcg_wg<8, 0>; break;
+        case 8: k = l5 ? k_pcg_wg<8, 5> : k_pcg_wg<8, 0>; break;
         default: return set_error(APCG_ERR_INVALID_ARG, "system too large for the one-workgroup solve");
     }
     hipLaunchKernelGGL(k, dim3(1), dim3(WT), 0, st, a);
