@@ -563,54 +563,71 @@ struct SegSys {  // per-system scalars, owned by the per-system kernels
     int32_t its, status, flag, zero_x;
 };
 
+// Partials are per 64-row slice: slice j of tile t (the rows of wavefront j
+// of the tile's workgroup) is global slice g = 4 t + j, and a system's
+// slices are [4 sys_tile0[s], 4 sys_tile0[s + 1]).  A wavefront adds its 64
+// rows and stores the slice's partial itself, so no tile kernel needs a
+// workgroup barrier to reduce; the per-system kernels add the slices in
+// index order.
 struct SegPlan {
     const BatchSys *sys;   // [nsys]
     const int32_t *tile_sys, *tile_row0;  // [ntiles]
     const int32_t *sys_tile0;  // [nsys + 1]
     SegSys *st;            // [nsys]
-    double *part_res;      // 4 * ntiles
-    double *part_delta;    // ntiles
+    double *part_res;      // [4][nslices]
+    double *part_delta;    // [nslices]
     unsigned *running;     // systems still iterating
     int32_t nsys, ntiles, tiles_per_block;
+    int32_t nslices;       // 4 ntiles
 };
 
 namespace {
 
 constexpr int ST = 256;  // rows per tile = threads per tile workgroup
+constexpr int SPT = ST / 64;  // slices per tile
 
-__device__ __forceinline__ void tile_range(const SegPlan &P, int *t0, int *t1) {
-    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-    *t0 = lb * P.tiles_per_block;
-    *t1 = min(P.ntiles, *t0 + P.tiles_per_block);
+// Stores the calling wavefront's sums of v over its 64 rows as the partials
+// of global slice g (partials[k * ns + g]); lane 0 stores.
+template <int NV>
+__device__ __forceinline__ void slice_store(double (&v)[NV], double *partials, int ns, int g) {
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = dev::wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) partials[(int64_t)k * ns + g] = v[k];
+    }
 }
 
-// Runs body(t) for every tile t of this workgroup's range whose system
-// passes keep(state): tiles are screened ST at a time (one per thread) and
-// the survivors compacted in LDS, so the tiles of stopped systems cost one
-// round of loads per ST tiles.  Each tile writes only its own outputs.
+// Runs body(t) for every tile t of this workgroup whose system passes
+// keep(state).  Workgroup lb (its XCD-aware index) owns tiles lb, lb + G,
+// lb + 2G, ...: a system's consecutive tiles go to different workgroups, so
+// when only a few systems are still running their tiles are worked on side
+// by side rather than one after another by a few workgroups, and each round
+// of G tiles is split into eight contiguous runs, one per XCD.  Tiles are
+// screened ST at a time (one per thread) and the survivors compacted in
+// LDS, so the tiles of stopped systems cost one round of loads per ST tiles.
+// Each tile writes only its own outputs.
 template <typename Keep, typename Body>
 __device__ __forceinline__ void for_active_tiles(const SegPlan &P, Keep keep, Body body) {
-    int t0, t1;
-    tile_range(P, &t0, &t1);
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x), G = gridDim.x;
     __shared__ int list[ST];
     __shared__ int cnt;
-    for (int base = t0; base < t1; base += ST) {
+    for (int base = 0; lb + base * G < P.ntiles; base += ST) {
         if (threadIdx.x == 0) cnt = 0;
         __syncthreads();
-        const int t = base + (int)threadIdx.x;
-        if (t < t1 && keep(P.st[P.tile_sys[t]])) list[atomicAdd(&cnt, 1)] = t;
+        const int t = lb + (base + (int)threadIdx.x) * G;
+        if (t < P.ntiles && keep(P.st[P.tile_sys[t]])) list[atomicAdd(&cnt, 1)] = t;
         __syncthreads();
         const int m = cnt;
-        for (int k = 0; k < m; ++k) body(list[k]);
+        for (int k = 0; k < m; ++k) body(__builtin_amdgcn_readfirstlane(list[k]));
         __syncthreads();  // the list is reused by the next round
     }
 }
 
 __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc, int norm_pre) {
-    int t0, t1;
-    tile_range(P, &t0, &t1);
-    __shared__ double lds[4 * (ST / 64)];
-    for (int t = t0; t < t1; ++t) {
+    const int tb0 = dev::xcd_block(blockIdx.x, gridDim.x), tstep = gridDim.x;
+    const int g0 = (int)(threadIdx.x >> 6);
+    for (int t = tb0; t < P.ntiles; t += tstep) {
         const BatchSys S = P.sys[P.tile_sys[t]];
         const int i = P.tile_row0[t] + threadIdx.x;
         double v[4] = {0.0, 0.0, 0.0, 0.0};
@@ -652,22 +669,20 @@ __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc,
                 v[2] = bi * bi;
             }
         }
-        dev::block_sum<ST, 4>(v, lds);
-        if (threadIdx.x == 0)
-            for (int k = 0; k < 4; ++k) P.part_res[k * P.ntiles + t] = v[k];
-        __syncthreads();
+        slice_store<4>(v, P.part_res, P.nslices, SPT * t + g0);
     }
 }
 
-// Adds the partials part[k*ntiles + t] of system s's tiles (index order),
-// result in thread 0.
+// Adds the slice partials part[k*ns + g] of system s (its tiles ta..tb, so
+// slices SPT ta .. SPT tb) in a fixed order: thread l takes g = l, l + 64, ...
+// of the range, then the wavefront tree.  Result in thread 0.
 template <int NV>
-__device__ __forceinline__ void sys_sum(const double *part, int ntiles, int ta, int tb, double (&v)[NV], double *lds) {
+__device__ __forceinline__ void sys_sum(const double *part, int ns, int ta, int tb, double (&v)[NV], double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int t = ta + (int)threadIdx.x; t < tb; t += 64) {
+    for (int g = SPT * ta + (int)threadIdx.x; g < SPT * tb; g += 64) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += part[k * ntiles + t];
+        for (int k = 0; k < NV; ++k) v[k] += part[(int64_t)k * ns + g];
     }
     dev::block_sum<64, NV>(v, lds);
 }
@@ -676,7 +691,7 @@ __global__ __launch_bounds__(64) void k_seg_init_final(SegPlan P, double rtol, i
     const int s = blockIdx.x;
     __shared__ double lds[4];
     double v[4];
-    sys_sum<4>(P.part_res, P.ntiles, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    sys_sum<4>(P.part_res, P.nslices, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
     SegSys q;
     q.rho = v[0];
@@ -714,7 +729,6 @@ __global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
 // UC: sliced-diagonal slots walked per row (>= every such system's U).
 template <int UC>
 __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
-    __shared__ double lds[ST / 64];
     for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
         const int s = P.tile_sys[t];
         const double beta = P.st[s].beta;
@@ -738,9 +752,7 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
             w[i] = sum;
             v[0] = pi * sum;
         }
-        dev::block_sum<ST, 1>(v, lds);
-        if (threadIdx.x == 0) P.part_delta[t] = v[0];
-        __syncthreads();
+        slice_store<1>(v, P.part_delta, P.nslices, SPT * t + (int)(threadIdx.x >> 6));
     });
 }
 
@@ -749,7 +761,7 @@ __global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
     if (P.st[s].flag) return;
     __shared__ double lds[1];
     double v[1];
-    sys_sum<1>(P.part_delta, P.ntiles, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    sys_sum<1>(P.part_delta, P.nslices, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
     SegSys *q = P.st + s;
     const double delta = v[0];
@@ -764,7 +776,6 @@ __global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
 }
 
 __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int norm_pre) {
-    __shared__ double lds[2 * (ST / 64)];
     for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
         const int s = P.tile_sys[t];
         const double alpha = P.st[s].alpha;
@@ -786,12 +797,7 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
             v[0] = zi * ri;
             v[1] = norm_pre ? zi * zi : ri * ri;
         }
-        dev::block_sum<ST, 2>(v, lds);
-        if (threadIdx.x == 0) {
-            P.part_res[t] = v[0];
-            P.part_res[P.ntiles + t] = v[1];
-        }
-        __syncthreads();
+        slice_store<2>(v, P.part_res, P.nslices, SPT * t + (int)(threadIdx.x >> 6));
     });
 }
 
@@ -800,7 +806,7 @@ __global__ __launch_bounds__(64) void k_seg_beta(SegPlan P, double rtol, int32_t
     if (P.st[s].flag) return;
     __shared__ double lds[2];
     double v[2];
-    sys_sum<2>(P.part_res, P.ntiles, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    sys_sum<2>(P.part_res, P.nslices, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
     SegSys *q = P.st + s;
     const double rho_new = v[0], res = sqrt(v[1]);
@@ -845,7 +851,7 @@ struct SegCache {
     int device = 0;
     int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr;
     SegSys *d_st = nullptr;
-    double *d_part = nullptr;  // 5 * ntiles
+    double *d_part = nullptr;  // 5 * SPT * ntiles (slice partials)
     unsigned *d_running = nullptr;
     int64_t tiles_cap = 0, sys_cap = 0;
     uint64_t hash = 0;
@@ -940,7 +946,7 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
         APCG_HIP(hipMalloc((void **)&sc->d_tile_row0, sizeof(int32_t) * sc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&sc->d_sys_tile0, sizeof(int32_t) * (sc->sys_cap + 1)));
         APCG_HIP(hipMalloc((void **)&sc->d_st, sizeof(SegSys) * sc->sys_cap));
-        APCG_HIP(hipMalloc((void **)&sc->d_part, sizeof(double) * 5 * sc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&sc->d_part, sizeof(double) * 5 * SPT * sc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&sc->d_running, 256));
     }
     if (!sc->pinned) APCG_HIP(hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
@@ -966,10 +972,11 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     P.sys_tile0 = sc->d_sys_tile0;
     P.st = sc->d_st;
     P.part_res = sc->d_part;
-    P.part_delta = sc->d_part + 4 * (int64_t)sc->tiles_cap;
+    P.part_delta = sc->d_part + 4 * SPT * (int64_t)sc->tiles_cap;
     P.running = sc->d_running;
     P.nsys = nsys;
     P.ntiles = ntiles;
+    P.nslices = SPT * nt_alloc;
     const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
     const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;

@@ -36,6 +36,7 @@ namespace apcg {
 namespace {
 
 constexpr int FT = 256;  // rows per tile = threads per tile workgroup
+constexpr int FSPT = FT / 64;  // 64-row slices per tile (one per wavefront)
 constexpr int FDEG = 8;
 constexpr int MODE_FLEX = 0, MODE_JACOBI = 1;
 
@@ -70,9 +71,10 @@ struct FPlan {
     const int32_t *tile_sys, *tile_row0;  // [ntiles]
     const int32_t *sys_tile0;             // [nsys + 1]
     FState *st;                           // [nsys]
-    double *part;                         // [4][ntiles]
+    double *part;                         // [4][nslices]: per 64-row slice, slice j of tile t at 4 t + j
     unsigned *running;
     int32_t nsys, ntiles, tiles_per_block;
+    int32_t nslices;                      // FSPT ntiles
     int32_t maxit, stall_min, fallback;
     double rtol, stall_frac;
     int32_t force_jacobi;  // feature runs: every system in Jacobi mode from the start
@@ -80,32 +82,28 @@ struct FPlan {
     double *hist;          // [nsys][2][hist_cap]
 };
 
-__device__ __forceinline__ void ftile_range(const FPlan &P, int *t0, int *t1) {
-    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
-    *t0 = lb * P.tiles_per_block;
-    *t1 = min(P.ntiles, *t0 + P.tiles_per_block);
-}
-
-// Runs body(t) for every tile t of this workgroup's range whose system
-// passes keep(state).  Tiles are screened FT at a time -- each thread tests
+// Runs body(t) for every tile t of this workgroup whose system passes
+// keep(state).  Workgroup lb (its XCD-aware index) owns tiles lb, lb + G,
+// lb + 2G, ...: the tiles of one system are spread over the grid, so the few
+// systems still running at the end are worked on side by side.  Tiles are
+// screened FT at a time -- each thread tests
 // one tile, the survivors are compacted in LDS -- so a tail of stopped
 // systems costs one round of loads per FT tiles, not a dependent chain per
 // tile.  Each tile writes only its own outputs, so the order in which the
 // survivors run does not change any result.
 template <typename Keep, typename Body>
 __device__ __forceinline__ void for_active_tiles(const FPlan &P, Keep keep, Body body) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x), G = gridDim.x;
     __shared__ int list[FT];
     __shared__ int cnt;
-    for (int base = t0; base < t1; base += FT) {
+    for (int base = 0; lb + base * G < P.ntiles; base += FT) {
         if (threadIdx.x == 0) cnt = 0;
         __syncthreads();
-        const int t = base + (int)threadIdx.x;
-        if (t < t1 && keep(P.st[P.tile_sys[t]])) list[atomicAdd(&cnt, 1)] = t;
+        const int t = lb + (base + (int)threadIdx.x) * G;
+        if (t < P.ntiles && keep(P.st[P.tile_sys[t]])) list[atomicAdd(&cnt, 1)] = t;
         __syncthreads();
         const int m = cnt;
-        for (int k = 0; k < m; ++k) body(list[k]);
+        for (int k = 0; k < m; ++k) body(__builtin_amdgcn_readfirstlane(list[k]));
         __syncthreads();  // the list is reused by the next round
     }
 }
@@ -137,31 +135,46 @@ __device__ __forceinline__ double frow(const int32_t *__restrict__ col, const do
     return sum;
 }
 
-// The tiles of system s, added in index order (one 64-thread workgroup);
-// the result is valid in thread 0.
+// The slice partials of system s (slices FSPT sys_tile0[s] .. FSPT
+// sys_tile0[s+1] of rows slot0.. of P.part), added in a fixed order (thread
+// l takes slices l, l + 64, ..., then the wavefront tree; one 64-thread
+// workgroup); the result is valid in thread 0.
 template <int NV>
-__device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV],
-                                         const double *base = nullptr) {
+__device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV]) {
     __shared__ double lds[NV];
-    const double *part = base ? base : P.part;
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int t = P.sys_tile0[s] + (int)threadIdx.x; t < P.sys_tile0[s + 1]; t += 64) {
+    for (int g = FSPT * P.sys_tile0[s] + (int)threadIdx.x; g < FSPT * P.sys_tile0[s + 1]; g += 64) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += part[(size_t)(slot0 + k) * P.ntiles + t];
+        for (int k = 0; k < NV; ++k) v[k] += P.part[(size_t)(slot0 + k) * P.nslices + g];
     }
     dev::block_sum<64, NV>(v, lds);
 }
 
+// Per-tile partials (the feature passes): tiles of system s in index order.
+template <int NV>
+__device__ __forceinline__ void fsys_sum_tiles(const FPlan &P, int s, const double *part, double (&v)[NV]) {
+    __shared__ double lds[NV];
+#pragma unroll
+    for (int k = 0; k < NV; ++k) v[k] = 0.0;
+    for (int t = P.sys_tile0[s] + (int)threadIdx.x; t < P.sys_tile0[s + 1]; t += 64) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += part[(size_t)k * P.ntiles + t];
+    }
+    dev::block_sum<64, NV>(v, lds);
+}
+
+// The calling wavefront's sums over its 64 rows (slice 4 t + wavefront of
+// tile t) as that slice's partials; lane 0 stores.  No workgroup barrier.
 template <int NV>
 __device__ __forceinline__ void ftile_store(const FPlan &P, int t, int slot0, double (&v)[NV]) {
-    __shared__ double lds[NV * (FT / 64)];
-    dev::block_sum<FT, NV>(v, lds);
-    if (threadIdx.x == 0) {
 #pragma unroll
-        for (int k = 0; k < NV; ++k) P.part[(size_t)(slot0 + k) * P.ntiles + t] = v[k];
+    for (int k = 0; k < NV; ++k) v[k] = dev::wave_sum(v[k]);
+    if ((threadIdx.x & 63) == 0) {
+        const int g = FSPT * t + (int)(threadIdx.x >> 6);
+#pragma unroll
+        for (int k = 0; k < NV; ++k) P.part[(size_t)(slot0 + k) * P.nslices + g] = v[k];
     }
-    __syncthreads();
 }
 
 __device__ double fpoly_at(const double *c, double t, double lmax) {  // Clenshaw at one point
@@ -197,9 +210,8 @@ __device__ void fswitch(const FPlan &P, FState *q, int reason) {
 }
 
 __global__ __launch_bounds__(FT) void k_bf_init(FPlan P, int x0_zero) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
-    for (int t = t0; t < t1; ++t) {
+    const int tb0 = dev::xcd_block(blockIdx.x, gridDim.x), tstep = gridDim.x;
+    for (int t = tb0; t < P.ntiles; t += tstep) {
         const FSys S = P.sys[P.tile_sys[t]];
         const int i = P.tile_row0[t] + threadIdx.x;
         double v[3] = {0.0, 0.0, 0.0};  // ||b||^2, ||r||^2, bad diagonals
@@ -477,10 +489,9 @@ __global__ __launch_bounds__(64) void k_bf_beta(FPlan P) {
 // ---- batched features (the learned preconditioner's inputs) -------------
 // Row statistics per tile -> fpart[k][t], k < 7 (dev::RowStats order).
 __global__ __launch_bounds__(FT) void k_bf_rows(FPlan P, double *fpart) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
+    const int tb0 = dev::xcd_block(blockIdx.x, gridDim.x), tstep = gridDim.x;
     __shared__ double sh[7][FT];
-    for (int t = t0; t < t1; ++t) {
+    for (int t = tb0; t < P.ntiles; t += tstep) {
         const FSys S = P.sys[P.tile_sys[t]];
         const int i = P.tile_row0[t] + threadIdx.x;
         dev::RowStats a;
@@ -512,10 +523,9 @@ __global__ __launch_bounds__(64) void k_bf_rows_final(FPlan P, const double *fpa
 
 // sum (ln d_i - mean)^2 per tile -> fpart[7][t].
 __global__ __launch_bounds__(FT) void k_bf_rows2(FPlan P, const double *fstats, double *fpart) {
-    int t0, t1;
-    ftile_range(P, &t0, &t1);
+    const int tb0 = dev::xcd_block(blockIdx.x, gridDim.x), tstep = gridDim.x;
     __shared__ double lds[FT / 64];
-    for (int t = t0; t < t1; ++t) {
+    for (int t = tb0; t < P.ntiles; t += tstep) {
         const int s = P.tile_sys[t];
         const FSys S = P.sys[s];
         const int i = P.tile_row0[t] + threadIdx.x;
@@ -544,7 +554,7 @@ __global__ __launch_bounds__(64) void k_bf_feat(FPlan P, const double *fpart, co
     __shared__ double th[16], td[16], te2[16];
     dev::ritz_values(al, be, m, td, te2, th);
     double vs[1];
-    fsys_sum<1>(P, s, 0, vs, fpart + (size_t)7 * P.ntiles);  // squared deviations over the tiles, fixed order
+    fsys_sum_tiles<1>(P, s, fpart + (size_t)7 * P.ntiles, vs);  // squared deviations over the tiles, fixed order
     __syncthreads();
     if (threadIdx.x != 0) return;
     if (m < 1) {
@@ -589,7 +599,7 @@ struct BfCache {
     FSys *d_sys = nullptr;
     int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr;
     FState *d_st = nullptr;
-    double *d_part = nullptr;  // 4 * tiles_cap
+    double *d_part = nullptr;  // 4 * FSPT * tiles_cap (slice partials)
     double *d_ws = nullptr;
     unsigned *d_running = nullptr;
     int64_t sys_cap = 0, tiles_cap = 0, ws_cap = 0;
@@ -731,7 +741,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
         APCG_HIP(hipMalloc((void **)&bc->d_sys_tile0, sizeof(int32_t) * (bc->sys_cap + 1)));
         APCG_HIP(hipMalloc((void **)&bc->d_tile_sys, sizeof(int32_t) * bc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_tile_row0, sizeof(int32_t) * bc->tiles_cap));
-        APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * bc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * FSPT * bc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_ws, sizeof(double) * bc->ws_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_running, 256));
     }
@@ -765,6 +775,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     P.running = bc->d_running;
     P.nsys = nsys;
     P.ntiles = ntiles;
+    P.nslices = FSPT * std::max<int32_t>(ntiles, 1);
     const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
     P.maxit = maxit;
@@ -1007,6 +1018,7 @@ static apcg_status bf_features(apcg_ctx ctx, BfCache *bc, int32_t nsys, const ap
     int32_t nt = 0;
     for (auto &f : hs) nt += (f.n + FT - 1) / FT;
     P.ntiles = nt;
+    P.nslices = FSPT * std::max<int32_t>(nt, 1);
     const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(nt, 1));
     P.tiles_per_block = std::max<int32_t>(1, (nt + G - 1) / G);
     P.hist = bc->d_hist;
