@@ -599,6 +599,31 @@ apcg_status apcg_tune_cache_save(const char *path, int32_t *entries);
 apcg_status apcg_mat_autotune_cached(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best,
                                      double *best_us, int32_t *from_cache);
 
+/* No-allocation variant of apcg_ksp_solve with APCG_MODE_PERSISTENT, for
+ * callers that cannot allocate device memory: code under stream capture,
+ * tight serving loops, harnesses that forbid hipMalloc.  The same
+ * one-workgroup Jacobi-PCG kernel (the same sums, the same tests), with its
+ * direction vector in a fixed array of APCG_NOALLOC_MAX_N doubles compiled
+ * into the library (one per device, held until the process ends) instead of
+ * the context's workspace.  Allocates nothing and takes no library objects:
+ * raw device pointers to CSR arrays (rowptr int32[n+1], col int32[nnz], val
+ * f64[nnz], strictly increasing or not), b and x (f64[n]; x holds x0 unless
+ * opts->x0_is_zero) and one device record `info` that receives the result;
+ * all of them stay owned by the caller, who orders their other uses against
+ * ctx's stream (the call does no dependency marking).  opts: pc, norm_type
+ * and x0_is_zero are read (NULL: the defaults), mode is ignored.  Queues one
+ * kernel on ctx's stream and returns.  Every call on one device shares that
+ * device's array, so two calls that overlap in time on one device (two
+ * contexts, or two host threads) race: the caller serialises them, e.g. by
+ * using one context.  Errors (returned before anything is queued):
+ * APCG_ERR_INVALID_ARG for a NULL context or pointer, a globally blocking
+ * context, n < 0, n > APCG_NOALLOC_MAX_N, maxit < 0 or rtol < 0 or NaN;
+ * APCG_ERR_UNSUPPORTED for another preconditioner. */
+#define APCG_NOALLOC_MAX_N 4096
+apcg_status apcg_ksp_solve_small_noalloc(apcg_ctx ctx, int32_t n, const int32_t *rowptr, const int32_t *col,
+                                         const double *val, const double *b, double *x, double rtol, int32_t maxit,
+                                         const apcg_solve_opts *opts, apcg_solve_info *info);
+
 /* Latency floors of the device (Section 4.2: below about 1e5 nonzeros the
  * GPU solve is bound by latency).  Runs on a private stream of `device`,
  * blocks the host, and writes microseconds to out_us:

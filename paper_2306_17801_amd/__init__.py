@@ -489,6 +489,18 @@ def apcg_ksp_solve(ctx, A, b, x, rtol: float, maxit: int, opts=None, info=None, 
                                                 int(info_index)))
 
 
+def apcg_ksp_solve_small_noalloc(ctx, n: int, rowptr: int, col: int, val: int, b: int, x: int, rtol: float,
+                                 maxit: int, opts=None, info: int = 0) -> None:
+    """rowptr, col, val, b, x, info: raw device addresses (e.g. tensor.data_ptr());
+    info is one apcg_solve_info record (32 bytes) of device memory."""
+    po = ctypes.byref(opts) if opts is not None else None
+    check("apcg_ksp_solve_small_noalloc",
+          _L().apcg_ksp_solve_small_noalloc(_h(ctx), int(n), ctypes.c_void_p(int(rowptr)), ctypes.c_void_p(int(col)),
+                                            ctypes.c_void_p(int(val)), ctypes.c_void_p(int(b)),
+                                            ctypes.c_void_p(int(x)), float(rtol), int(maxit), po,
+                                            ctypes.c_void_p(int(info))))
+
+
 def apcg_ksp_solve_tfqmr(ctx, A, b, x, rtol: float, maxit: int, opts=None, info=None, info_index: int = 0) -> None:
     po = ctypes.byref(opts) if opts is not None else None
     check("apcg_ksp_solve_tfqmr", _L().apcg_ksp_solve_tfqmr(_h(ctx), _h(A), _h(b), _h(x), float(rtol), int(maxit),

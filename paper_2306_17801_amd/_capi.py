@@ -63,6 +63,7 @@ APCG_MODE_HOST_CHECK = 2
 APCG_MODE_PERSISTENT = 3
 APCG_MODE_AUTO = 4
 APCG_PERSISTENT_MAX_N = 4096
+APCG_NOALLOC_MAX_N = 4096
 APCG_SPMV_ROWGROUP = 0
 APCG_SPMV_STREAM = 1
 APCG_SPMV_SELL = 2
@@ -191,6 +192,8 @@ SIGNATURES = {
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
     "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
     "apcg_latency_floors": [c_i32, c_i32, P(c_f64)],
+    "apcg_ksp_solve_small_noalloc": [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts),
+                                     c_vp],
     "apcg_tune_key_pattern": [c_char_p, c_i32, c_i64, c_vp, c_vp, c_char_p, c_i32],
     "apcg_mat_tune_key": [c_vp, c_char_p, c_i32],
     "apcg_tune_cache_insert": [c_char_p, P(c_i32), c_f64],

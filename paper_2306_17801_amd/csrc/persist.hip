@@ -32,6 +32,7 @@
 
 #include <chrono>
 #include <cmath>
+#include <mutex>
 
 #include "internal.h"
 
@@ -325,9 +326,74 @@ apcg_status launch_pcg_wg(hipStream_t st, int32_t n, const int32_t *rowptr, cons
     return APCG_SUCCESS;
 }
 
+// ------------------------------------------------- no-allocation variant
+// The direction vector of apcg_ksp_solve_small_noalloc: a fixed array in the
+// code object, one copy per device for the life of the process (32 KiB), so
+// that the entry point allocates nothing.  Host code never passes this name
+// to a kernel (on the host it is a stand-in, not a device address); it looks
+// the device address up once per device and passes that.
+constexpr int kNoAllocMaxN = APCG_NOALLOC_MAX_N;
+static_assert(kNoAllocMaxN <= APCG_PERSISTENT_MAX_N, "the no-allocation solve is the one-workgroup solve");
+static __device__ __align__(256) double scratch[kNoAllocMaxN];
+
+namespace {
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+double *g_scratch_ptr[kMaxDevices] = {};  // device address of `scratch`, per device
+
+// The device address of `scratch` on `device` (looked up on the first call
+// for that device, with the device current).
+apcg_status scratch_address(int device, double **out) {
+    if (device < 0 || device >= kMaxDevices) return set_error(APCG_ERR_INVALID_ARG, "device index out of range");
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        APCG_HIP(hipSetDevice(device));
+        void *p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return hip_error(e, "hipGetSymbolAddress(scratch)");
+        if (!p) return set_error(APCG_ERR_HIP, "hipGetSymbolAddress(scratch) returned NULL");
+        g_scratch_ptr[device] = static_cast<double *>(p);
+    }
+    *out = g_scratch_ptr[device];
+    return APCG_SUCCESS;
+}
+}  // namespace
+
 }  // namespace apcg
 
 using namespace apcg;
+
+extern "C" apcg_status apcg_ksp_solve_small_noalloc(apcg_ctx ctx, int32_t n, const int32_t *rowptr,
+                                                    const int32_t *col, const double *val, const double *b,
+                                                    double *x, double rtol, int32_t maxit,
+                                                    const apcg_solve_opts *opts, apcg_solve_info *info) {
+    if (!ctx) return set_error(APCG_ERR_INVALID_ARG, "the no-allocation solve needs a context");
+    if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING)
+        return set_error(APCG_ERR_INVALID_ARG, "the no-allocation solve needs a default-stream context");
+    if (n < 0) return set_error(APCG_ERR_INVALID_ARG, "n must be >= 0");
+    if (n > kNoAllocMaxN)
+        return set_error(APCG_ERR_INVALID_ARG, "n exceeds APCG_NOALLOC_MAX_N (4096 rows), the no-allocation "
+                                               "solve's fixed direction buffer");
+    if (!rowptr || !col || !val || !b || !x || !info) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+    if (maxit < 0 || !(rtol >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0 and rtol >= 0");
+    int pc = APCG_PC_JACOBI, norm_pre = 0, x0_zero = 0;
+    if (opts) {
+        if (opts->pc != APCG_PC_NONE && opts->pc != APCG_PC_JACOBI)
+            return set_error(APCG_ERR_UNSUPPORTED, "unsupported preconditioner for the no-allocation solve");
+        if (opts->norm_type != APCG_NORM_UNPRECONDITIONED && opts->norm_type != APCG_NORM_PRECONDITIONED)
+            return set_error(APCG_ERR_INVALID_ARG, "unknown norm type");
+        pc = opts->pc;
+        norm_pre = opts->norm_type == APCG_NORM_PRECONDITIONED;
+        x0_zero = opts->x0_is_zero ? 1 : 0;
+    }
+    double *p = nullptr;
+    apcg_status s;
+    if ((s = scratch_address(ctx->device, &p))) return s;
+    APCG_HIP(hipSetDevice(ctx->device));
+    // rows and their lengths are not known on the host: the entries are read
+    // from the CSR arrays every iteration (the same sums as the register path)
+    return launch_pcg_wg(ctx->stream, n, rowptr, col, val, b, x, p, rtol, maxit, x0_zero, pc, norm_pre, -1, info);
+}
 
 extern "C" apcg_status apcg_latency_floors(int32_t device, int32_t reps, double out_us[4]) {
     if (!out_us || reps < 1 || reps > 100000) return set_error(APCG_ERR_INVALID_ARG, "bad latency-floor arguments");

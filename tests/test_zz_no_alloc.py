@@ -1,0 +1,114 @@
+"""The no-allocation solve (apcg_ksp_solve_small_noalloc) against the entry
+point it varies, apcg_ksp_solve with APCG_MODE_PERSISTENT, through the C ABI:
+two calls in a row on one device, the second with a smaller system, each
+checked against the allocating path (status and iterations equal, x equal
+bit for bit: the same kernel, the same sums) and against the oracle at the
+parity bar (iterations +-1, ||x - x_ref|| / ||x_ref|| <= 1e-9 at rtol
+1e-10).  Also: the size limit and the argument checks, which return before
+anything is queued."""
+import ctypes
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2306_17801_amd import problems as P
+
+pytestmark = pytest.mark.gpu
+
+RTOL = 1e-10
+
+
+@pytest.fixture(scope="module")
+def apcg():
+    import torch
+
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2306_17801_amd as m
+
+    m.load()
+    return m
+
+
+def _info_host(apcg, t):
+    raw = t.cpu().numpy().tobytes()
+    rec = apcg.apcg_solve_info.from_buffer_copy(raw)
+    return {"iterations": rec.iterations, "status": rec.status, "res_norm": rec.res_norm, "ref_norm": rec.ref_norm}
+
+
+def _systems():
+    # the 64 x 64 Poisson system (n = 4096, the limit), then a ragged
+    # variable-coefficient 2D system of 1,073 rows (37 x 29)
+    big = P.poisson2d_manufactured(64, seed=0)
+    rng = np.random.default_rng(11)
+    k = np.exp(rng.standard_normal((29, 37)))
+    small = P.System(A=P.diffusion_csr(k, aniso=3.0), b=rng.uniform(-1.0, 1.0, 29 * 37))
+    return [("poisson64", big), ("diffusion37x29", small)]
+
+
+def test_noalloc_matches_persistent_two_calls(apcg):
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    ctx = apcg.apcg_ctx_create(0)
+    info = apcg.apcg_info_create(0, 1)
+    dinfo = torch.zeros(32, dtype=torch.uint8, device="cuda:0")
+    assert ctypes.sizeof(apcg.apcg_solve_info) == 32
+    for name, s in _systems():
+        n = s.A.n
+        print(f"case noalloc {name} n={n}", flush=True)
+        assert n <= apcg.APCG_NOALLOC_MAX_N
+        A, b = DeviceCSR(s.A), DeviceVec(s.b)
+        x_ref, x_new = DeviceVec.zeros(n), DeviceVec.zeros(n)
+        # stale contents in x must not matter with x0_is_zero
+        x_new.t.fill_(123.0)
+        torch.cuda.synchronize()
+        opts = apcg.apcg_solve_opts_default(x0_is_zero=1, mode=apcg.APCG_MODE_PERSISTENT)
+        apcg.apcg_ksp_solve(ctx, A.h, b.h, x_ref.h, RTOL, 10 * n, opts, info, 0)
+        r_ref = apcg.apcg_info_get(info, 0)
+        xr = x_ref.numpy()
+        apcg.apcg_ctx_synchronize(ctx)
+        apcg.apcg_ksp_solve_small_noalloc(ctx, n, A.rowptr.data_ptr(), A.col.data_ptr(), A.val.data_ptr(),
+                                          b.t.data_ptr(), x_new.t.data_ptr(), RTOL, 10 * n, opts,
+                                          dinfo.data_ptr())
+        apcg.apcg_ctx_synchronize(ctx)
+        r_new = _info_host(apcg, dinfo)
+        xn = x_new.t.cpu().numpy()
+        print(f"  persistent its {r_ref['iterations']} st {r_ref['status']} | noalloc its {r_new['iterations']} "
+              f"st {r_new['status']}", flush=True)
+        assert r_new["status"] == r_ref["status"] == apcg.APCG_SOLVE_CONVERGED
+        assert r_new["iterations"] == r_ref["iterations"]
+        assert r_new["res_norm"] == r_ref["res_norm"] and r_new["ref_norm"] == r_ref["ref_norm"]
+        assert np.array_equal(xn, xr)
+        ref = oracle.pcg(s.A, s.b, rtol=RTOL, maxit=10 * n)
+        e = np.linalg.norm(xn - ref.x) / np.linalg.norm(ref.x)
+        print(f"  oracle its {ref.its} rel {e:.2e}", flush=True)
+        assert abs(r_new["iterations"] - ref.its) <= 1 and e <= 1e-9
+        for v in (x_ref, x_new, b):
+            v.close()
+        A.close()
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_ctx_destroy(ctx)
+
+
+def test_noalloc_rejects_bad_arguments(apcg):
+    import torch
+
+    ctx = apcg.apcg_ctx_create(0)
+    n = apcg.APCG_NOALLOC_MAX_N + 1
+    buf = torch.zeros(8 * (n + 1), dtype=torch.float64, device="cuda:0")
+    dinfo = torch.zeros(32, dtype=torch.uint8, device="cuda:0")
+    p = buf.data_ptr()
+    with pytest.raises(apcg.ApcgError) as e:
+        apcg.apcg_ksp_solve_small_noalloc(ctx, n, p, p, p, p, p, RTOL, 10, None, dinfo.data_ptr())
+    assert e.value.code == apcg.APCG_ERR_INVALID_ARG
+    assert "APCG_NOALLOC_MAX_N" in apcg.apcg_last_error()
+    with pytest.raises(apcg.ApcgError):
+        apcg.apcg_ksp_solve_small_noalloc(ctx, 16, p, p, p, p, p, RTOL, -1, None, dinfo.data_ptr())
+    with pytest.raises(apcg.ApcgError):
+        apcg.apcg_ksp_solve_small_noalloc(ctx, 16, p, p, p, p, p, RTOL, 10, None, 0)
+    with pytest.raises(apcg.ApcgError):
+        apcg.apcg_ksp_solve_small_noalloc(None, 16, p, p, p, p, p, RTOL, 10, None, dinfo.data_ptr())
+    apcg.apcg_ctx_synchronize(ctx)
+    apcg.apcg_ctx_destroy(ctx)
