@@ -193,7 +193,7 @@ def bench_latency(apcg, torch, reps=50):
     return out
 
 
-def bench_batch(apcg, torch, reps, only=None):
+def bench_batch(apcg, torch, reps, only=None, tile_rows=0):
     """256 independent 2D 5-point systems (side ~ U{32..256}, k = exp(N(0,1)),
     b ~ U[-1,1], seed 3), Jacobi-PCG rtol 1e-8: one batched persistent launch
     (graph) against the plain path, one apcg_ksp_solve per system spread over
@@ -223,7 +223,8 @@ def bench_batch(apcg, torch, reps, only=None):
                     apcg.apcg_mat_set_spmv_config(a.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
                 except apcg.ApcgError:
                     pass
-        o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_block_size=tb, batch_schedule=sched)
+        o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_block_size=tb, batch_schedule=sched,
+                                         batch_tile_rows=tile_rows)
         apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o, info)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -363,13 +364,16 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
     fallbacks = 0
     unconverged = 0
     feat_t = 0.0
+    tune_hits = 0
     for s in eval_set:
         dA, db = device_system(s)
         dx = DeviceVec.zeros(dA.n)
         # the plain path on its fastest product schedule for this matrix, as
         # in the headline (the FCG solves read the sliced-diagonal copy
-        # whenever the pattern has one, whatever the schedule)
-        apcg.apcg_mat_autotune(dA.h, ctx, 3)
+        # whenever the pattern has one, whatever the schedule); matrices of
+        # the same pattern class and size bucket reuse the tuning table
+        _, _, hit = apcg.apcg_mat_autotune_cached(dA.h, ctx, 3)
+        tune_hits += int(hit)
         feat = torch.zeros(16, dtype=torch.float32, device="cuda:0")
         lm = torch.zeros(1, dtype=torch.float64, device="cuda:0")
         torch.cuda.synchronize()
@@ -416,6 +420,7 @@ def bench_learned(apcg, torch, n_train, n_eval, side_lo, side_hi, epochs, reps, 
         out[f"{k}_ms_per_solve"] = round(1000 * tot[k] / n_eval, 4)
         out[f"{k}_solves_per_s"] = round(n_eval / tot[k], 3)
     out["features_ms_per_call"] = round(1000 * feat_t / n_eval, 4)
+    out["autotune_table_hits"] = tune_hits
     out["learned_speedup_vs_jacobi"] = round(tot["jacobi"] / tot["learned"], 3)
     out["learned_speedup_vs_control"] = round(tot["control"] / tot["learned"], 3)
     out["learned_fallbacks"] = fallbacks
@@ -729,6 +734,8 @@ def main():
                     choices=["persistent256", "persistent512", "persistent1024", "segmented", "segmented_sdia"],
                     help="only run the 256-system batch with this schedule (no headline solve, no per-solve loop; "
                          "for profiling) and print its figures as one JSON line")
+    ap.add_argument("--batch-tile-rows", type=int, default=0,
+                    help="rows per tile of the segmented batched schedules (0: the library's default)")
     ap.add_argument("--no-learned", action="store_true", help="skip the learned-preconditioner measurement")
     ap.add_argument("--learned-train", type=int, default=2000, help="training systems")
     ap.add_argument("--learned-eval", type=int, default=200, help="held-out systems")
@@ -776,7 +783,8 @@ def main():
         copy_calibration(apcg, torch)
         return
     if args.batch_only:
-        print(json.dumps({"batch2d_256": bench_batch(apcg, torch, args.batch_reps, only=args.batch_only)}), flush=True)
+        print(json.dumps({"batch2d_256": bench_batch(apcg, torch, args.batch_reps, only=args.batch_only,
+                                                     tile_rows=args.batch_tile_rows)}), flush=True)
         return
     if args.sweep:
         res = bench_sweep(apcg, torch, args.sweep_nnz, args.sweep_reps, args.sweep_cpu_max_nnz, args.sweep_stencils)
@@ -889,15 +897,13 @@ def main():
                                     f"{tr['source_sha256_16']}) and configuration, scaled by a 1 GiB copy "
                                     f"calibration (fetch x{tr.get('fetch_scale')}, write x{tr.get('write_scale')})")
     sym_reads = cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1 and is_symmetric(A_h)
+    marching = cfg_now["schedule"] in (apcg.APCG_SPMV_SDIA, apcg.APCG_SPMV_DIA) and cfg_now["lanes_per_row"] > 1
     kname = {apcg.APCG_SPMV_STREAM: "k_pcg_product_stream", apcg.APCG_SPMV_SELL: "k_pcg_product_sell",
-             apcg.APCG_SPMV_DIA: "k_pcg_product_dia",
-             apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia" + ("_march" if cfg_now["lanes_per_row"] > 1 else "")}.get(
-        cfg_now["schedule"], "k_pcg_product") + (
+             apcg.APCG_SPMV_DIA: "k_pcg_product_dia", apcg.APCG_SPMV_SDIA: "k_pcg_product_sdia"}.get(
+        cfg_now["schedule"], "k_pcg_product") + ("_march" if marching else "") + (
         f" (block {cfg_now['block_size']}, {cfg_now['lanes_per_row']} planes per task"
-        + (", symmetric reads)" if sym_reads else ")")
-        if cfg_now["schedule"] == apcg.APCG_SPMV_SDIA and cfg_now["lanes_per_row"] > 1
-        else f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups"
-        + (", symmetric reads)" if dia_sym else ")"))
+        if marching else f" (block {cfg_now['block_size']}, {cfg_now['blocks']} workgroups") + (
+        ", symmetric reads)" if (sym_reads or dia_sym) else ")")
     roofline = {"bound": "hbm", "kernel": kname, "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
                 "traffic": traffic, "traffic_source": traffic_note, "algorithmic_bytes_per_launch": prod_bytes,

@@ -510,7 +510,10 @@ typedef struct apcg_solve_opts {
     int32_t batch_block_size;/* apcg_ksp_solve_batched: threads per system   */
                              /*    (256, 512 or 1024; 0 = 512)               */
     int32_t batch_schedule;  /* APCG_BATCH_*                                 */
-    int32_t reserved[7];
+    int32_t batch_tile_rows; /* segmented batched solves: rows per tile, a    */
+                             /*    multiple of 256 in [256, 8192] (0 = 1024); */
+                             /*    changes the launch shape only, not a sum  */
+    int32_t reserved[6];
 } apcg_solve_opts;
 
 /* Schedules of apcg_ksp_solve_batched. */

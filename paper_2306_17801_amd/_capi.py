@@ -81,7 +81,8 @@ class apcg_spmv_config(ctypes.Structure):
 class apcg_solve_opts(ctypes.Structure):
     _fields_ = [("pc", c_i32), ("norm_type", c_i32), ("mode", c_i32), ("iters_per_graph", c_i32),
                 ("lookahead", c_i32), ("x0_is_zero", c_i32), ("kernel_timing", c_i32),
-                ("batch_block_size", c_i32), ("batch_schedule", c_i32), ("reserved", c_i32 * 7)]
+                ("batch_block_size", c_i32), ("batch_schedule", c_i32), ("batch_tile_rows", c_i32),
+                ("reserved", c_i32 * 6)]
 
 
 class apcg_solve_info(ctypes.Structure):
@@ -192,8 +193,6 @@ SIGNATURES = {
     "apcg_mat_autotune": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64)],
     "apcg_mat_time_kernels": [c_vp, c_vp, c_i32, P(c_f64), P(c_f64)],
     "apcg_latency_floors": [c_i32, c_i32, P(c_f64)],
-    "apcg_ksp_solve_small_noalloc": [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts),
-                                     c_vp],
     "apcg_tune_key_pattern": [c_char_p, c_i32, c_i64, c_vp, c_vp, c_char_p, c_i32],
     "apcg_mat_tune_key": [c_vp, c_char_p, c_i32],
     "apcg_tune_cache_insert": [c_char_p, P(c_i32), c_f64],
@@ -203,6 +202,8 @@ SIGNATURES = {
     "apcg_tune_cache_load": [c_char_p, P(c_i32)],
     "apcg_tune_cache_save": [c_char_p, P(c_i32)],
     "apcg_mat_autotune_cached": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64), P(c_i32)],
+    "apcg_ksp_solve_small_noalloc": [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts),
+                                     c_vp],
     "apcg_solve_opts_default": [P(apcg_solve_opts)],
     "apcg_info_create": [c_i32, c_i32, P(c_vp)],
     "apcg_info_destroy": [c_vp],

@@ -368,6 +368,8 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
         const int tb = opts.batch_block_size ? opts.batch_block_size : 512;
         const BatchedFn fn = batched_fn(tb);
         if (!fn) return set_error(APCG_ERR_INVALID_ARG, "batch block size must be 256, 512 or 1024");
+        if (!valid_batch_tile_rows(opts.batch_tile_rows))
+            return set_error(APCG_ERR_INVALID_ARG, "batch tile rows must be 0 or a multiple of 256 in [256, 8192]");
         const int dev = ctx->device;
         std::vector<BatchSys> hs(nsys);
         std::vector<double> cost(nsys);
@@ -563,28 +565,39 @@ struct SegSys {  // per-system scalars, owned by the per-system kernels
     int32_t its, status, flag, zero_x;
 };
 
-// Partials are per 64-row slice: slice j of tile t (the rows of wavefront j
-// of the tile's workgroup) is global slice g = 4 t + j, and a system's
-// slices are [4 sys_tile0[s], 4 sys_tile0[s + 1]).  A wavefront adds its 64
-// rows and stores the slice's partial itself, so no tile kernel needs a
-// workgroup barrier to reduce; the per-system kernels add the slices in
-// index order.
+// A tile is tile_rows rows of one system (a multiple of 256, starting at a
+// multiple of tile_rows); its workgroup's four wavefronts take its 64-row
+// slices in turn (wavefront j: slices j, j + 4, ...).  Partials are per
+// slice: local slice l of system s is global slice sys_slice0[s] + l.  A
+// wavefront adds its 64 rows and stores the slice's partial itself, so no
+// tile kernel needs a workgroup barrier to reduce, and the per-system kernels
+// add a system's slices in index order -- the same sums whatever the tile
+// size.
 struct SegPlan {
     const BatchSys *sys;   // [nsys]
     const int32_t *tile_sys, *tile_row0;  // [ntiles]
     const int32_t *sys_tile0;  // [nsys + 1]
+    const int32_t *sys_slice0;  // [nsys + 1]
     SegSys *st;            // [nsys]
     double *part_res;      // [4][nslices]
     double *part_delta;    // [nslices]
     unsigned *running;     // systems still iterating
     int32_t nsys, ntiles, tiles_per_block;
-    int32_t nslices;       // 4 ntiles
+    int32_t nslices;       // sys_slice0[nsys]
+    int32_t tile_rows;
 };
 
 namespace {
 
-constexpr int ST = 256;  // rows per tile = threads per tile workgroup
-constexpr int SPT = ST / 64;  // slices per tile
+constexpr int ST = 256;  // threads per tile workgroup (tiles are multiples of ST rows)
+constexpr int SW = ST / 64;  // wavefronts per tile workgroup
+
+// The local slices [sl0, sl1) of tile t (of a system of n rows).
+__device__ __forceinline__ void tile_slices(const SegPlan &P, int t, int n, int *sl0, int *sl1) {
+    const int r0 = P.tile_row0[t];
+    *sl0 = r0 >> 6;
+    *sl1 = min((n + 63) >> 6, (r0 + P.tile_rows) >> 6);
+}
 
 // Stores the calling wavefront's sums of v over its 64 rows as the partials
 // of global slice g (partials[k * ns + g]); lane 0 stores.
@@ -626,10 +639,14 @@ __device__ __forceinline__ void for_active_tiles(const SegPlan &P, Keep keep, Bo
 
 __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc, int norm_pre) {
     const int tb0 = dev::xcd_block(blockIdx.x, gridDim.x), tstep = gridDim.x;
-    const int g0 = (int)(threadIdx.x >> 6);
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for (int t = tb0; t < P.ntiles; t += tstep) {
-        const BatchSys S = P.sys[P.tile_sys[t]];
-        const int i = P.tile_row0[t] + threadIdx.x;
+      const int sys = P.tile_sys[t];
+      const BatchSys S = P.sys[sys];
+      int sl0, sl1;
+      tile_slices(P, t, S.n, &sl0, &sl1);
+      for (int sl = sl0 + wave; sl < sl1; sl += SW) {
+        const int i = sl * 64 + lane;
         double v[4] = {0.0, 0.0, 0.0, 0.0};
         if (i < S.n) {
             const int s = S.rowptr[i], e = S.rowptr[i + 1];
@@ -669,18 +686,19 @@ __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc,
                 v[2] = bi * bi;
             }
         }
-        slice_store<4>(v, P.part_res, P.nslices, SPT * t + g0);
+        slice_store<4>(v, P.part_res, P.nslices, P.sys_slice0[sys] + sl);
+      }
     }
 }
 
-// Adds the slice partials part[k*ns + g] of system s (its tiles ta..tb, so
-// slices SPT ta .. SPT tb) in a fixed order: thread l takes g = l, l + 64, ...
-// of the range, then the wavefront tree.  Result in thread 0.
+// Adds the slice partials part[k*ns + g] of a system (its slices ga..gb)
+// in a fixed order: thread l takes g = ga + l, ga + l + 64, ..., then the
+// wavefront tree.  Result in thread 0.
 template <int NV>
-__device__ __forceinline__ void sys_sum(const double *part, int ns, int ta, int tb, double (&v)[NV], double *lds) {
+__device__ __forceinline__ void sys_sum(const double *part, int ns, int ga, int gb, double (&v)[NV], double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = SPT * ta + (int)threadIdx.x; g < SPT * tb; g += 64) {
+    for (int g = ga + (int)threadIdx.x; g < gb; g += 64) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] += part[(int64_t)k * ns + g];
     }
@@ -691,7 +709,7 @@ __global__ __launch_bounds__(64) void k_seg_init_final(SegPlan P, double rtol, i
     const int s = blockIdx.x;
     __shared__ double lds[4];
     double v[4];
-    sys_sum<4>(P.part_res, P.nslices, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    sys_sum<4>(P.part_res, P.nslices, P.sys_slice0[s], P.sys_slice0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
     SegSys q;
     q.rho = v[0];
@@ -719,16 +737,90 @@ __global__ __launch_bounds__(64) void k_seg_init_final(SegPlan P, double rtol, i
 }
 
 __global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [](const SegSys &q) { return q.zero_x != 0; }, [&](int t) {
         const BatchSys S = P.sys[P.tile_sys[t]];
-        const int i = P.tile_row0[t] + threadIdx.x;
-        if (i < S.n) S.x[i] = 0.0;
+        int sl0, sl1;
+        tile_slices(P, t, S.n, &sl0, &sl1);
+        for (int sl = sl0 + wave; sl < sl1; sl += SW) {
+            const int i = sl * 64 + lane;
+            if (i < S.n) S.x[i] = 0.0;
+        }
     });
+}
+
+// A wavefront's slices sl_begin, sl_begin + SW, ... < sl_end of one system
+// on the sliced-diagonal copy (8 offset slots per slice, UC walked): w = A p
+// and p = z + beta p_old with the next slice's offsets, masks and values
+// loaded while the current slice's gathers are in flight; each row adds its
+// entries in column order with one FMA each (the sums of dev::sdia_row);
+// slice partials of p.w to part[g0 + slice].
+template <int UC>
+__device__ __forceinline__ void seg_sdia_slices(const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
+                                                const double *__restrict__ sval, int U, int n, int sl_begin,
+                                                int sl_end, const double *__restrict__ z,
+                                                const double *__restrict__ pold, double *__restrict__ pnew,
+                                                double *__restrict__ w, double beta, double *part, int ns, int g0) {
+    const int lane = threadIdx.x & 63;
+    int on[UC];
+    uint64_t mn[UC];
+    double an[UC];
+    auto load = [&](int sl) {
+        const int32_t *o = soff + (int64_t)sl * 8;
+        const uint64_t *m = smask + (int64_t)sl * 8;
+        const double *v = sval + (int64_t)sl * U * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            on[k] = o[k];
+            mn[k] = m[k];
+            an[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
+        }
+    };
+    if (sl_begin < sl_end) load(sl_begin);
+    for (int sl = sl_begin; sl < sl_end; sl += SW) {
+        int oc[UC];
+        uint64_t mc[UC];
+        double ac[UC];
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            oc[k] = on[k];
+            mc[k] = mn[k];
+            ac[k] = an[k];
+        }
+        if (sl + SW < sl_end) load(sl + SW);  // in flight during the gathers below
+        const int row = sl * 64 + lane;
+        const int rc = row < n ? row : n - 1;
+        double zj[UC], pj[UC];
+        bool in[UC];
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            in[k] = (mc[k] >> lane) & 1ull;
+            const int j = in[k] ? row + oc[k] : rc;
+            zj[k] = z[j];
+            pj[k] = pold[j];
+        }
+        const double zi = z[rc], po = pold[rc];
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            const double t = fma(ac[k], fma(beta, pj[k], zj[k]), sum);
+            sum = in[k] ? t : sum;
+        }
+        const double pi = fma(beta, po, zi);
+        double v[1] = {0.0};
+        if (row < n) {
+            pnew[row] = pi;
+            w[row] = sum;
+            v[0] = pi * sum;
+        }
+        slice_store<1>(v, part, ns, g0 + sl);
+    }
 }
 
 // UC: sliced-diagonal slots walked per row (>= every such system's U).
 template <int UC>
 __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
         const int s = P.tile_sys[t];
         const double beta = P.st[s].beta;
@@ -738,21 +830,26 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
         const double *pold = S.ws + (2 + ((parity + 1) & 1)) * n;
         double *pnew = S.ws + (2 + (parity & 1)) * n;
         double *w = S.ws + 4 * n;
-        const int i = P.tile_row0[t] + threadIdx.x;
-        double v[1] = {0.0};
-        if (i < S.n) {
-            // the tile's rows start at a multiple of 256 of its system, so
-            // each wavefront's rows are one 64-row slice
-            const double sum =
-                S.sval ? dev::sdia_row<8, UC>(S.soff, S.smask, S.sval, S.U, n, i,
-                                          [&](int q) { return fma(beta, pold[q], z[q]); })
-                       : row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
-            const double pi = fma(beta, pold[i], z[i]);
-            pnew[i] = pi;
-            w[i] = sum;
-            v[0] = pi * sum;
+        const int g0 = P.sys_slice0[s];
+        int sl0, sl1;
+        tile_slices(P, t, S.n, &sl0, &sl1);
+        if (S.sval) {
+            seg_sdia_slices<UC>(S.soff, S.smask, S.sval, S.U, S.n, sl0 + wave, sl1, z, pold, pnew, w, beta,
+                                P.part_delta, P.nslices, g0);
+            return;
         }
-        slice_store<1>(v, P.part_delta, P.nslices, SPT * t + (int)(threadIdx.x >> 6));
+        for (int sl = sl0 + wave; sl < sl1; sl += SW) {
+            const int i = sl * 64 + lane;
+            double v[1] = {0.0};
+            if (i < S.n) {
+                const double sum = row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
+                const double pi = fma(beta, pold[i], z[i]);
+                pnew[i] = pi;
+                w[i] = sum;
+                v[0] = pi * sum;
+            }
+            slice_store<1>(v, P.part_delta, P.nslices, g0 + sl);
+        }
     });
 }
 
@@ -761,7 +858,7 @@ __global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
     if (P.st[s].flag) return;
     __shared__ double lds[1];
     double v[1];
-    sys_sum<1>(P.part_delta, P.nslices, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    sys_sum<1>(P.part_delta, P.nslices, P.sys_slice0[s], P.sys_slice0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
     SegSys *q = P.st + s;
     const double delta = v[0];
@@ -776,16 +873,21 @@ __global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
 }
 
 __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int norm_pre) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [](const SegSys &q) { return !q.flag; }, [&](int t) {
-        const int s = P.tile_sys[t];
-        const double alpha = P.st[s].alpha;
-        const BatchSys S = P.sys[s];
-        const int64_t n = S.n;
-        double *r = S.ws;
-        const double *dinv = S.ws + n;
-        const double *p = S.ws + (2 + (parity & 1)) * n;
-        const double *w = S.ws + 4 * n;
-        const int i = P.tile_row0[t] + threadIdx.x;
+      const int s = P.tile_sys[t];
+      const double alpha = P.st[s].alpha;
+      const BatchSys S = P.sys[s];
+      const int64_t n = S.n;
+      double *r = S.ws;
+      const double *dinv = S.ws + n;
+      const double *p = S.ws + (2 + (parity & 1)) * n;
+      const double *w = S.ws + 4 * n;
+      const int g0 = P.sys_slice0[s];
+      int sl0, sl1;
+      tile_slices(P, t, S.n, &sl0, &sl1);
+      for (int sl = sl0 + wave; sl < sl1; sl += SW) {
+        const int i = sl * 64 + lane;
         double v[2] = {0.0, 0.0};
         if (i < S.n) {
             const double xi = fma(alpha, p[i], S.x[i]);
@@ -797,7 +899,8 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
             v[0] = zi * ri;
             v[1] = norm_pre ? zi * zi : ri * ri;
         }
-        slice_store<2>(v, P.part_res, P.nslices, SPT * t + (int)(threadIdx.x >> 6));
+        slice_store<2>(v, P.part_res, P.nslices, g0 + sl);
+      }
     });
 }
 
@@ -806,7 +909,7 @@ __global__ __launch_bounds__(64) void k_seg_beta(SegPlan P, double rtol, int32_t
     if (P.st[s].flag) return;
     __shared__ double lds[2];
     double v[2];
-    sys_sum<2>(P.part_res, P.nslices, P.sys_tile0[s], P.sys_tile0[s + 1], v, lds);
+    sys_sum<2>(P.part_res, P.nslices, P.sys_slice0[s], P.sys_slice0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
     SegSys *q = P.st + s;
     const double rho_new = v[0], res = sqrt(v[1]);
@@ -849,11 +952,11 @@ __global__ void k_seg_reset(unsigned *running) {
 // Segment resources of one context (tile tables, per-system scalars, graph).
 struct SegCache {
     int device = 0;
-    int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr;
+    int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr, *d_sys_slice0 = nullptr;
     SegSys *d_st = nullptr;
-    double *d_part = nullptr;  // 5 * SPT * ntiles (slice partials)
+    double *d_part = nullptr;  // 5 * slices_cap (slice partials)
     unsigned *d_running = nullptr;
-    int64_t tiles_cap = 0, sys_cap = 0;
+    int64_t tiles_cap = 0, sys_cap = 0, slices_cap = 0;
     uint64_t hash = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -881,6 +984,7 @@ static void seg_free_buffers(SegCache &s) {
     hipFree(s.d_tile_sys);
     hipFree(s.d_tile_row0);
     hipFree(s.d_sys_tile0);
+    hipFree(s.d_sys_slice0);
     hipFree(s.d_st);
     hipFree(s.d_part);
     hipFree(s.d_running);
@@ -911,23 +1015,30 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     SegCache *sc = seg_cache(ctx);
     const int dev = ctx->device;
     hipStream_t st = ctx->stream;
-    std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
+    const int32_t TR = batch_tile_rows(opts);
+    std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1), sys_slice0(nsys + 1);
+    int64_t nslices = 0;
     for (int32_t s = 0; s < nsys; ++s) {
         sys_tile0[s] = (int32_t)tile_sys.size();
+        sys_slice0[s] = (int32_t)nslices;
         const int32_t n = hsys[s].n;
-        for (int32_t r0 = 0; r0 < n; r0 += ST) {
+        nslices += ((int64_t)n + 63) / 64;
+        for (int32_t r0 = 0; r0 < n; r0 += TR) {
             tile_sys.push_back(s);
             tile_row0.push_back(r0);
         }
     }
     sys_tile0[nsys] = (int32_t)tile_sys.size();
+    sys_slice0[nsys] = (int32_t)nslices;
+    if (nslices > INT32_MAX / 8) return set_error(APCG_ERR_INVALID_ARG, "batch too large for the segmented schedule");
+    const int64_t ns_alloc = std::max<int64_t>(nslices, 1);
     const int32_t ntiles = (int32_t)tile_sys.size();
     if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well-formed
         tile_sys.push_back(0);
         tile_row0.push_back(0);
     }
     const int32_t nt_alloc = std::max<int32_t>(ntiles, 1);
-    if (sc->tiles_cap < nt_alloc || sc->sys_cap < nsys) {
+    if (sc->tiles_cap < nt_alloc || sc->sys_cap < nsys || sc->slices_cap < ns_alloc) {
         EventRef ev = event_get(dev);
         if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
         APCG_HIP(hipEventRecord(ev->e, st));
@@ -941,25 +1052,30 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
         sc->graph_hash = 0;
         sc->hash = 0;
         sc->tiles_cap = std::max<int64_t>(nt_alloc, sc->tiles_cap);
+        sc->slices_cap = std::max<int64_t>(ns_alloc, sc->slices_cap);
         sc->sys_cap = std::max<int64_t>(nsys, sc->sys_cap);
         APCG_HIP(hipMalloc((void **)&sc->d_tile_sys, sizeof(int32_t) * sc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&sc->d_tile_row0, sizeof(int32_t) * sc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&sc->d_sys_tile0, sizeof(int32_t) * (sc->sys_cap + 1)));
+        APCG_HIP(hipMalloc((void **)&sc->d_sys_slice0, sizeof(int32_t) * (sc->sys_cap + 1)));
         APCG_HIP(hipMalloc((void **)&sc->d_st, sizeof(SegSys) * sc->sys_cap));
-        APCG_HIP(hipMalloc((void **)&sc->d_part, sizeof(double) * 5 * SPT * sc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&sc->d_part, sizeof(double) * 5 * sc->slices_cap));
         APCG_HIP(hipMalloc((void **)&sc->d_running, 256));
     }
     if (!sc->pinned) APCG_HIP(hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
     uint64_t h = fnv1a(tile_sys.data(), sizeof(int32_t) * tile_sys.size());
     h = fnv1a(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
     h = fnv1a(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
+    h = fnv1a(sys_slice0.data(), sizeof(int32_t) * sys_slice0.size(), h);
     if (h != sc->hash) {
-        g_counters.h2d_copies += 3;
+        g_counters.h2d_copies += 4;
         APCG_HIP(hipMemcpyAsync(sc->d_tile_sys, tile_sys.data(), sizeof(int32_t) * tile_sys.size(),
                                 hipMemcpyHostToDevice, st));
         APCG_HIP(hipMemcpyAsync(sc->d_tile_row0, tile_row0.data(), sizeof(int32_t) * tile_row0.size(),
                                 hipMemcpyHostToDevice, st));
         APCG_HIP(hipMemcpyAsync(sc->d_sys_tile0, sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(),
+                                hipMemcpyHostToDevice, st));
+        APCG_HIP(hipMemcpyAsync(sc->d_sys_slice0, sys_slice0.data(), sizeof(int32_t) * sys_slice0.size(),
                                 hipMemcpyHostToDevice, st));
         g_counters.host_syncs++;
         APCG_HIP(hipStreamSynchronize(st));  // host tables are local
@@ -970,13 +1086,15 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     P.tile_sys = sc->d_tile_sys;
     P.tile_row0 = sc->d_tile_row0;
     P.sys_tile0 = sc->d_sys_tile0;
+    P.sys_slice0 = sc->d_sys_slice0;
     P.st = sc->d_st;
     P.part_res = sc->d_part;
-    P.part_delta = sc->d_part + 4 * SPT * (int64_t)sc->tiles_cap;
+    P.part_delta = sc->d_part + 4 * sc->slices_cap;
     P.running = sc->d_running;
     P.nsys = nsys;
     P.ntiles = ntiles;
-    P.nslices = SPT * nt_alloc;
+    P.nslices = (int32_t)ns_alloc;
+    P.tile_rows = TR;
     const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
     const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;

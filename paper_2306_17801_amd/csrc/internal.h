@@ -207,6 +207,7 @@ struct apcg_mat_s {
     int32_t dia_nd = 0;              // distinct offsets (diagonals)
     int32_t dia_ndt = 0;             // diagonals the kernel walks (5, 7 or 9 >= dia_nd; the rest all zero)
     int32_t dia_sym = 0;             // 1: the offset set is symmetric (o present <=> -o present)
+    int32_t dia_ps = 0;              // plane stride in 64-row slices (offset +-64 dia_ps present), 0: none
     int32_t dia_off_h[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0};
     int32_t *dia_tab = nullptr;      // device int32[32]: offsets [0..8], partner diagonal of each
                                      //   negative offset [9..17] (-1: none), value-symmetry flag [18]
@@ -235,6 +236,12 @@ apcg_status resolve_ctx(apcg_ctx in, int device, apcg_ctx *out);  // NULL -> glo
 apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
+// rows per tile of the segmented batched schedules (apcg_solve_opts.batch_tile_rows)
+constexpr int32_t kDefaultBatchTileRows = 1024;
+inline bool valid_batch_tile_rows(int32_t tr) { return tr == 0 || (tr >= 256 && tr <= 8192 && tr % 256 == 0); }
+inline int32_t batch_tile_rows(const apcg_solve_opts &o) {
+    return o.batch_tile_rows > 0 ? o.batch_tile_rows : kDefaultBatchTileRows;
+}
 // tuning table (tune.hip): the key of a pattern, lookups and inserts
 std::string pattern_class(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cl);
 std::string tune_key(const std::string &arch, const std::string &cls, int64_t n, int64_t nnz);

@@ -887,6 +887,131 @@ __global__ __launch_bounds__(TB) void k_pcg_product_dia(int32_t n, const int32_t
     dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
 }
 
+// Diagonals with plane marching (lanes_per_row = seg > 1 selects it when the
+// offsets hold a pair +-64 Ps, the plane stride in 64-row slices): the
+// slices form Ps columns and a task (wavefront) walks seg consecutive
+// slices of one column, one plane apart, as the sliced-diagonal marching
+// product does.  The window of offset +64 Ps (z and p_old of the next
+// slice's rows) is loaded once and serves as the +plane neighbour now, then
+// as the next slice's own window and then as its -plane neighbour; with
+// symmetric values the -plane entry is the previous slice's +plane value,
+// kept in a register.  Every other address is the row plus a constant the
+// whole wavefront shares, so no load waits for per-slice offsets: the
+// values of the diagonals on and right of the main one (of all of them
+// without symmetry) and the gathers of the remaining offsets are issued
+// together.  The sum runs over the diagonals in offset order with one FMA
+// each, as in k_pcg_product_dia, so the two kernels give the same bits.
+// shape = ND walked | seg << 8 | Ps << 16.
+template <int TB, int ND, bool SYM>
+__device__ __forceinline__ double dia_march_tasks(int32_t n, const int (&off)[ND], const int (&prt)[ND], int nd,
+                                                  const double *__restrict__ dval, int64_t stride,
+                                                  const double *__restrict__ z, const double *__restrict__ pold,
+                                                  double *__restrict__ pnew, double *__restrict__ w, int lb,
+                                                  double beta, int seg, int Ps) {
+    const int nsl = (n + 63) / 64;
+    const int nz = (nsl + Ps - 1) / Ps;  // planes (the last may be partial)
+    const int nseg = (nz + seg - 1) / seg;
+    const int ntask = Ps * nseg;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+    const int nwaves = gridDim.x * (TB / 64);
+    const int up = 64 * Ps;
+    int kup = -1;  // the +plane diagonal (its value carries to the next slice's -plane entry)
+#pragma unroll
+    for (int k = 0; k < ND; ++k)
+        if (k < nd && off[k] == up) kup = k;
+    double acc = 0.0;
+    for (int task = lb * (TB / 64) + wave; task < ntask; task += nwaves) {
+        const int c = task % Ps, g = task / Ps;
+        const int j0 = g * seg, j1 = min(nz, j0 + seg);
+        int row = (j0 * Ps + c) * 64 + lane;
+        int rc = min(row, n - 1);
+        double zo = z[rc], po = pold[rc];  // own window
+        const int rp = max(rc - up, 0);
+        double zm = z[rp], pm = pold[rp];  // -plane window
+        double aprev = 0.0;  // the +plane value of row - up
+        if (SYM && kup >= 0 && row - up >= 0) aprev = dval[(int64_t)kup * stride + (row - up)];
+        for (int j = j0; j < j1; ++j) {
+            const int sl = j * Ps + c;
+            if (sl >= nsl) break;  // the partial last plane
+            row = sl * 64 + lane;
+            rc = min(row, n - 1);
+            __builtin_amdgcn_s_setprio(2);  // the slice's loads issued ahead of other waves' arithmetic
+            const int rn = min(rc + up, n - 1);
+            const double zn = z[rn], pn = pold[rn];  // +plane window = the next slice's own
+            double a[ND], zg[ND], pg[ND];
+#pragma unroll
+            for (int k = 0; k < ND; ++k) {
+                const int o = off[k];
+                const bool live = k < nd;
+                const bool carried = o == up || o == -up || o == 0;
+                if (SYM && o < 0) {
+                    // the transpose's value, diagonal +q at row - q (the
+                    // -plane one carried from the previous slice)
+                    const int src = row + o;
+                    const double t = (o == -up || !live) ? 0.0 : dval[(int64_t)prt[k] * stride + max(src, 0)];
+                    a[k] = !live ? 0.0 : o == -up ? aprev : (src >= 0 ? t : 0.0);
+                } else {
+                    a[k] = live ? dval[(int64_t)k * stride + row] : 0.0;
+                }
+                const int jx = (live && !carried) ? min(max(row + o, 0), n - 1) : rc;
+                const double zl = z[jx], pl = pold[jx];
+                zg[k] = !live ? 0.0 : o == up ? zn : o == -up ? zm : o == 0 ? zo : zl;
+                pg[k] = !live ? 0.0 : o == up ? pn : o == -up ? pm : o == 0 ? po : pl;
+            }
+            __builtin_amdgcn_s_setprio(0);
+            double sum = 0.0;
+#pragma unroll
+            for (int k = 0; k < ND; ++k) sum = fma(a[k], pdir(zg[k], beta, pg[k]), sum);
+            // workspace vectors are padded to whole slices: the rows past n
+            // of the last slice store padding, without a branch
+            const double pi = pdir(zo, beta, po);
+            pnew[row] = pi;
+            w[row] = sum;
+            acc = row < n ? fma(pi, sum, acc) : acc;
+            if (SYM && kup >= 0) {
+#pragma unroll
+                for (int k = 0; k < ND; ++k)
+                    if (k == kup) aprev = a[k];
+            }
+            zm = zo;
+            pm = po;
+            zo = zn;
+            po = pn;
+        }
+    }
+    return acc;
+}
+
+template <int TB, int ND>
+__global__ __launch_bounds__(TB) void k_pcg_product_dia_march(int32_t n, const int32_t *__restrict__ tab,
+                                                              const int32_t * /*unused*/,
+                                                              const double *__restrict__ dval,
+                                                              const double *__restrict__ z,
+                                                              const double *__restrict__ pold,
+                                                              double *__restrict__ pnew, double *__restrict__ w,
+                                                              SolveState *st, const double *part_res, int g_res,
+                                                              double *part_delta, int32_t /*unused*/, int parity,
+                                                              int tune, int32_t shape) {
+    const int seg = (shape >> 8) & 0xff, Ps = (shape >> 16) & 0xffff;
+    double beta;
+    if (!product_prologue<TB>(st, part_res, g_res, parity, tune, &beta)) return;
+    const int64_t stride = ((int64_t)n + 63) / 64 * 64;
+    int off[ND], prt[ND];
+#pragma unroll
+    for (int k = 0; k < ND; ++k) {
+        off[k] = __builtin_amdgcn_readfirstlane(tab[k]);
+        prt[k] = __builtin_amdgcn_readfirstlane(tab[9 + k]);
+    }
+    const int nd = __builtin_amdgcn_readfirstlane(tab[19]);
+    const int sym = __builtin_amdgcn_readfirstlane(tab[18]);
+    const int lb = dev::xcd_block(blockIdx.x, gridDim.x);
+    const double acc =
+        sym ? dia_march_tasks<TB, ND, true>(n, off, prt, nd, dval, stride, z, pold, pnew, w, lb, beta, seg, Ps)
+            : dia_march_tasks<TB, ND, false>(n, off, prt, nd, dval, stride, z, pold, pnew, w, lb, beta, seg, Ps);
+    double v[1] = {acc};
+    dev::store_partials<TB, 1>(v, part_delta, gridDim.x, lb);
+}
+
 // Refills the diagonals from the CSR values: thread i walks row i's entries
 // (columns strictly increasing, every offset one of the table's) against the
 // ascending offsets and writes every diagonal's value of row i (0 for rows
@@ -1071,6 +1196,12 @@ ProductFn product_fn(const apcg_spmv_config &cfg, int32_t lds_nnz, int32_t sell_
                      int32_t sdia_ps) {
     if (cfg.schedule == APCG_SPMV_DIA) {
         const bool b512 = cfg.block_size == 512;
+        if (cfg.lanes_per_row > 1 && (lds_nnz >> 16) > 0) {  // plane marching
+            const int nd = lds_nnz & 0xff;
+            if (nd <= 5) return b512 ? k_pcg_product_dia_march<512, 5> : k_pcg_product_dia_march<256, 5>;
+            if (nd <= 7) return b512 ? k_pcg_product_dia_march<512, 7> : k_pcg_product_dia_march<256, 7>;
+            return b512 ? k_pcg_product_dia_march<512, 9> : k_pcg_product_dia_march<256, 9>;
+        }
         if (lds_nnz <= 5) return b512 ? k_pcg_product_dia<512, 5> : k_pcg_product_dia<256, 5>;
         if (lds_nnz <= 7) return b512 ? k_pcg_product_dia<512, 7> : k_pcg_product_dia<256, 7>;
         return b512 ? k_pcg_product_dia<512, 9> : k_pcg_product_dia<256, 9>;
@@ -1146,10 +1277,18 @@ apcg_status make_plan(const apcg_mat_s *A, const apcg_spmv_config &cfg, Plan *pl
         pl->a1 = nullptr;
         pl->a2 = A->dia_val;
         const int64_t units = ((int64_t)A->n + 63) / 64;  // 64-row chunks
-        pl->g_prod = normalise_blocks(cfg.blocks, (units * 64 + pl->tb - 1) / pl->tb);
-        const int64_t upb = (units + pl->g_prod - 1) / pl->g_prod;
-        pl->rpb = (int32_t)std::max<int64_t>(64, upb * 64);
-        pl->lds_nnz = A->dia_ndt;
+        if (cfg.lanes_per_row > 1 && A->dia_ps > 0) {  // plane marching: seg planes per task
+            const int64_t seg = cfg.lanes_per_row, ps = A->dia_ps, waves = pl->tb / 64;
+            const int64_t nz = (units + ps - 1) / ps, tasks = ps * ((nz + seg - 1) / seg);
+            pl->g_prod = normalise_blocks(kMaxBlocks, (tasks + waves - 1) / waves);
+            pl->rpb = 0;
+            pl->lds_nnz = A->dia_ndt | (int32_t)(seg << 8) | (int32_t)(ps << 16);
+        } else {
+            pl->g_prod = normalise_blocks(cfg.blocks, (units * 64 + pl->tb - 1) / pl->tb);
+            const int64_t upb = (units + pl->g_prod - 1) / pl->g_prod;
+            pl->rpb = (int32_t)std::max<int64_t>(64, upb * 64);
+            pl->lds_nnz = A->dia_ndt;
+        }
     } else if (cfg.schedule == APCG_SPMV_SDIA) {
         if (A->sdia_state != 1 || !A->sdia_val)
             return set_error(APCG_ERR_INVALID_STATE, "sliced-diagonal copy not prepared");
@@ -1406,6 +1545,14 @@ apcg_status dia_analyse(apcg_mat_s *A) {
         }
         tab[18] = sym ? 1 : 0;
         tab[19] = nd;
+        // plane stride for marching: the largest offset 64 Ps (Ps < 65536)
+        // present with both signs
+        int32_t ps = 0;
+        for (int k = 0; k < nd; ++k) {
+            const int32_t o = offs[k];
+            if (o > 0 && o % 64 == 0 && o / 64 < 65536 && std::binary_search(offs.begin(), offs.end(), -o))
+                ps = std::max<int32_t>(ps, o / 64);
+        }
         const int64_t stride = (n + 63) / 64 * 64;
         APCG_HIP(hipMalloc((void **)&A->dia_tab, sizeof(tab)));
         APCG_HIP(hipMalloc((void **)&A->dia_val, sizeof(double) * ndt * stride));
@@ -1415,6 +1562,7 @@ apcg_status dia_analyse(apcg_mat_s *A) {
         A->dia_nd = nd;
         A->dia_ndt = ndt;
         A->dia_sym = sym ? 1 : 0;
+        A->dia_ps = ps;
         A->dia_state = 1;
         return APCG_SUCCESS;
     } catch (const std::bad_alloc &) {
@@ -1867,11 +2015,13 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         const bool dia_ok = A->dia_state == 1;
         if (dia_ok && (s = prepare_dia(A, st))) return s;
         // -4: diagonals, -2: sliced diagonals, -1: the sliced schedule, 0:
-        // the staged one, -3: sliced diagonals with plane marching (the
-        // inner value is the number of planes per task, not a grid)
-        for (int lpr : {-4, -3, -2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
+        // the staged one, -3 / -5: sliced diagonals / diagonals with plane
+        // marching (the inner value is the number of planes per task, not a
+        // grid)
+        for (int lpr : {-5, -4, -3, -2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
             if (lpr == -4 && !dia_ok) continue;
+            if (lpr == -5 && !(dia_ok && A->dia_ps > 0)) continue;
             if (lpr == -1 && !sell_ok) continue;
             if (lpr == -2 && !sdia_ok) continue;
             if (lpr == -3 && !(sdia_ok && A->sdia_ps > 0)) continue;
@@ -1882,11 +2032,13 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
                 // the grid size
                 static const int kGrids[] = {256, 512, 1024, 2048, 4096, 8192};
                 static const int kPlanes[] = {4, 6, 8};
-                const int *inner = lpr == -3 ? kPlanes : kGrids;
-                const int ninner = lpr == -3 ? 3 : 6;
+                const bool march = lpr == -3 || lpr == -5;
+                const int *inner = march ? kPlanes : kGrids;
+                const int ninner = march ? 3 : 6;
                 for (int q = 0; q < ninner; ++q) {
                     const int blocks = inner[q], seg = inner[q];
-                    apcg_spmv_config cfg = lpr == -4  ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_DIA}
+                    apcg_spmv_config cfg = lpr == -5  ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_DIA}
+                                           : lpr == -4 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_DIA}
                                            : lpr == -3 ? apcg_spmv_config{seg, tb, 0, APCG_SPMV_SDIA}
                                            : lpr == -2 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SDIA}
                                            : lpr == -1 ? apcg_spmv_config{1, tb, blocks, APCG_SPMV_SELL}
@@ -1894,7 +2046,7 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
                                                       : apcg_spmv_config{lpr, tb, blocks, APCG_SPMV_ROWGROUP};
                     Plan pl;
                     if ((s = make_plan(A, cfg, &pl))) return s;
-                    if (lpr != -3 && pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller one
+                    if (!march && pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller one
                     // one product + update pair, both with their partial reductions
                     for (int w = 0; w < 2; ++w) {
                         if ((s = launch_product(st, pl, bf, 1, 1))) return s;

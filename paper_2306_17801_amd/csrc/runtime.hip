@@ -922,7 +922,7 @@ static bool valid_spmv_config(const apcg_spmv_config *cfg) {
     int l = cfg->lanes_per_row, b = cfg->block_size;
     bool lok = l == 1 || l == 2 || l == 4 || l == 8 || l == 16 || l == 32 || l == 64;
     if (cfg->schedule == APCG_SPMV_SDIA) lok = l >= 1 && l <= 64;  // planes per marching task
-    if (cfg->schedule == APCG_SPMV_DIA) lok = l == 1;
+    if (cfg->schedule == APCG_SPMV_DIA) lok = l >= 1 && l <= 64;  // > 1: planes per marching task
     bool bok = b == 256 || b == 512;
     bool sok = cfg->schedule == APCG_SPMV_ROWGROUP || cfg->schedule == APCG_SPMV_STREAM ||
                cfg->schedule == APCG_SPMV_SELL || cfg->schedule == APCG_SPMV_SDIA || cfg->schedule == APCG_SPMV_DIA;

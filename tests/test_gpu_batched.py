@@ -169,3 +169,36 @@ def test_segmented_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
     for s, r, x in zip(systems, r_sd, x_sd):
         ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=5000)
         assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
+
+
+@pytest.mark.parametrize("sdia", [False, True])
+def test_segmented_tile_rows_bitwise(apcg, ctx, sdia):
+    """The segmented schedule at 256, 1024 and 4096 rows per tile: a tile
+    only groups 64-row slices for one workgroup, each slice's partial is its
+    own wavefront's sum and every system adds its slices in index order, so
+    the tile size changes the launch shape and nothing else -- whole batched
+    solves are bit for bit equal (CSR reads and sliced-diagonal reads; sizes
+    from 4 to 12,000 rows, so some systems span many tiles and some less than
+    one slice).  The first one matches the oracle system by system."""
+    rng = np.random.default_rng(62)
+    systems = mixed_small_batch()[:12]
+    systems += [P._lognormal_system(rng, 2, side, 1.0, 3.0) for side in (70, 100, 110)]
+    print(f"case batched tile rows sdia={sdia}", flush=True)
+    sd = range(len(systems)) if sdia else ()
+    runs = [run_batch(apcg, ctx, systems, 1e-10, 20000, sdia=sd, batch_schedule=2, batch_tile_rows=tr)
+            for tr in (256, 1024, 4096)]
+    for res, xs in runs[1:]:
+        assert res == runs[0][0]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, runs[0][1]))
+    for s, r, x in zip(systems, *runs[0]):
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=20000)
+        assert r["status"] == ref.status
+        if ref.status == oracle.CONVERGED:
+            assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
+
+
+def test_segmented_tile_rows_rejected(apcg, ctx):
+    systems = mixed_small_batch()[:2]
+    for tr in (100, 128, 8448, -256):
+        with pytest.raises(apcg.ApcgError):
+            run_batch(apcg, ctx, systems, 1e-8, 100, batch_schedule=2, batch_tile_rows=tr)

@@ -231,3 +231,61 @@ def test_autotuner_offers_dia(apcg, ctx):
     assert res["status"] == apcg.APCG_SOLVE_CONVERGED and abs(res["iterations"] - ref.its) <= 1
     assert rel(dx.numpy(), ref.x) <= 1e-9
     apcg.apcg_info_destroy(info)
+
+
+def banded(n, off=128):
+    """A symmetric positive definite band matrix with offsets -off, -1, 0,
+    1, off (diagonally dominant, seeded values): n need not fill whole
+    planes of `off` rows or whole 64-row slices."""
+    import scipy.sparse as sp
+
+    rng = np.random.default_rng(70 + n)
+    e1 = -rng.uniform(0.5, 1.5, n - 1)
+    eo = -rng.uniform(0.5, 1.5, n - off)
+    d = np.zeros(n)
+    d[:-1] += -e1
+    d[1:] += -e1
+    d[:-off] += -eo
+    d[off:] += -eo
+    M = sp.diags([eo, e1, d + 0.1, e1, eo], [-off, -1, 0, 1, off]).tocsr()
+    M.sort_indices()
+    return P.CSR(n=n, rowptr=M.indptr.astype(np.int32), col=M.indices.astype(np.int32), val=M.data.copy())
+
+
+def march_matrix(which):
+    rng = np.random.default_rng(80 + len(which))
+    if which == "diffusion3d_32":
+        return matrix("diffusion3d_32")  # plane 1024 rows = 16 slices
+    if which == "diffusion2d_128x40":
+        return P.diffusion_csr(np.exp(rng.standard_normal((40, 128))), aniso=2.0)  # rows of 128 = 2 slices
+    if which == "banded_950":
+        return banded(950)  # 15 slices, the last ragged; planes of 2 slices, the last partial
+    raise KeyError(which)
+
+
+@pytest.mark.parametrize("which", ["diffusion3d_32", "diffusion2d_128x40", "banded_950"])
+@pytest.mark.parametrize("seg,tb", [(4, 256), (8, 512), (3, 256)])
+@pytest.mark.parametrize("symmetric", [True, False])
+def test_dia_march_bitwise_equal_sdia_march(apcg, ctx, which, seg, tb, symmetric):
+    """Diagonals with plane marching against sliced diagonals with plane
+    marching at the same planes per task and workgroup size: both walk the
+    same tasks (the plane stride is the same) and add each row's entries in
+    column order with one FMA each (absent entries adding exact zeros), so
+    whole solves are bit for bit equal -- with symmetric values (the -plane
+    value carried from the previous slice, the other lower entries read as
+    their transposes) and with one lower value changed (every diagonal read
+    as stored).  Each solve meets the oracle's bar."""
+    A = march_matrix(which)
+    if not symmetric:
+        A = with_lower_value_changed(A, 1.5)
+    b = np.random.default_rng(13).uniform(-1, 1, A.n)
+    print(f"case dia-march {which} n={A.n} seg={seg} tb={tb} symmetric={symmetric}", flush=True)
+    inf = []
+    r_d, x_d = gpu_solve(apcg, ctx, A, b, 1e-10, 20000, spmv=(seg, tb, 0, DIA), info_out=inf)
+    assert inf[0]["values_symmetric"] == (1 if symmetric else 0)
+    r_s, x_s = gpu_solve(apcg, ctx, A, b, 1e-10, 20000, spmv=(seg, tb, 0, 3))
+    assert r_d == r_s
+    assert np.array_equal(x_d, x_s)
+    ref = oracle.pcg(A, b, rtol=1e-10, maxit=20000)
+    assert r_d["status"] == apcg.APCG_SOLVE_CONVERGED and abs(r_d["iterations"] - ref.its) <= 1
+    assert rel(x_d, ref.x) <= 1e-9
