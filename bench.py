@@ -236,6 +236,25 @@ def bench_batch(apcg, torch, reps, only=None, tile_rows=0):
         out[f"batched_{name}_ms"] = round(1000 * dt, 3)
         if best is None or dt < best[0]:
             best = (dt, name)
+    if only is None:
+        # the batched autotuner's pick (timed on the device over 32
+        # iterations of every configuration), which the comparison uses
+        t0 = time.perf_counter()
+        cfg, ms, _ = apcg.apcg_batch_autotune(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 0, 32)
+        out["autotune"] = {"config": cfg, "ms_for_32_iterations": round(ms, 3),
+                           "seconds": round(time.perf_counter() - t0, 2)}
+        o = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_schedule=cfg["schedule"],
+                                         batch_block_size=cfg["block_size"], batch_tile_rows=cfg["tile_rows"])
+        apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o, info)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-8, 50000, o,
+                                        info)
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        out["batched_autotuned_ms"] = round(1000 * dt, 3)
+        best = (dt, "autotuned")
     res = [apcg.apcg_info_get(info, i) for i in range(nsys)]
     out["batched_schedule"] = best[1]
     out["batched_ms"] = round(1000 * best[0], 3)
@@ -498,6 +517,21 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, b
            "sliced_diagonal_systems": n_sdia, "sdia_analysis_s": round(t_sdia, 1), "timed_runs": reps}
     hA, hb, hx = [a.h for a in As], [b.h for b in bs], [x.h for x in xs]
     opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    # the batched autotuner picks each batched path's launch shape (a few
+    # iterations of each configuration, timed on the device)
+    t0 = time.perf_counter()
+    cfg_l, ms_l, _ = apcg.apcg_batch_autotune(ctx, hA, hb, hx, 1, 4)
+    opts_l = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_tile_rows=cfg_l["tile_rows"])
+    tuned = {"learned": {"config": cfg_l, "ms_for_4_iterations": round(ms_l, 3)}}
+    opts_j = opts
+    if batched_jacobi:
+        cfg_j, ms_j, _ = apcg.apcg_batch_autotune(ctx, hA, hb, hx, 0, 8)
+        opts_j = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_schedule=cfg_j["schedule"],
+                                              batch_block_size=cfg_j["block_size"], batch_tile_rows=cfg_j["tile_rows"])
+        tuned["jacobi"] = {"config": cfg_j, "ms_for_8_iterations": round(ms_j, 3)}
+    tuned["seconds"] = round(time.perf_counter() - t0, 2)
+    out["autotune"] = tuned
+    log(f"[bench] mixed: batched autotune {tuned}")
 
     def timed(run, warm):
         warm()
@@ -518,8 +552,8 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, b
         return res
 
     def learned(maxit):
-        apcg.apcg_ksp_solve_batched_learned(ctx, hA, hb, hx, 1e-8, maxit, pc.params, pc.mean, pc.std, opts, None,
-                                            info)
+        apcg.apcg_ksp_solve_batched_learned(ctx, hA, hb, hx, 1e-8, maxit, pc.params, pc.mean, pc.std, opts_l,
+                                            None, info)
 
     dt = timed(lambda: learned(50000), lambda: learned(0))
     res = summary("batched_learned", dt)
@@ -533,7 +567,7 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, b
     log(f"[bench] mixed batched learned: {1000 * dt:.1f} ms")
     if batched_jacobi:
         def bj(maxit):
-            apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-8, maxit, opts, info)
+            apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-8, maxit, opts_j, info)
 
         dt = timed(lambda: bj(50000), lambda: bj(0))
         res = summary("batched_jacobi", dt)

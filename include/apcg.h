@@ -602,6 +602,34 @@ apcg_status apcg_tune_cache_save(const char *path, int32_t *entries);
 apcg_status apcg_mat_autotune_cached(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_config *best,
                                      double *best_us, int32_t *from_cache);
 
+/* Launch configuration of a batched solve, as the batched autotuner picks it. */
+typedef struct apcg_batch_config {
+    int32_t schedule;   /* APCG_BATCH_PERSISTENT or APCG_BATCH_SEGMENTED      */
+    int32_t block_size; /* persistent: threads per system (256, 512, 1024)    */
+    int32_t tile_rows;  /* segmented: rows per tile (apcg_solve_opts field)   */
+    int32_t sdia;       /* 1: members read their sliced-diagonal copies       */
+} apcg_batch_config;
+
+/* Autotuner of the batched solves (the hot path's autotuner row: tile and
+ * schedule shapes picked by timing, not a passage of the paper).  kind 0
+ * times apcg_ksp_solve_batched (persistent at 256/512/1024 threads per
+ * system; segmented at 256-4096 rows per tile, on CSR and on the
+ * sliced-diagonal copies), kind 1 apcg_ksp_solve_batched_fcg_poly with the
+ * constant polynomial (its eight Clenshaw steps still run; segmented
+ * configurations only): `iters` iterations with rtol 0 on ctx's stream, HIP
+ * events, the better of two runs after a warm-up.  x is used as scratch (its
+ * contents are overwritten).  The result goes to the tuning table under
+ *   "batch|<arch>|pcg|fcg|m<longest row>|r<round(4 nnz/n)>|s<log2 systems>|
+ *    n<log2 rows>|x<log2 largest system>"
+ * and a later call with the same key applies it without timing
+ * (*from_cache = 1).  With sdia = 1 the members whose pattern allows it are
+ * left on APCG_SPMV_SDIA (their schedules are restored otherwise).  The
+ * caller passes *best's fields to apcg_solve_opts (batch_schedule,
+ * batch_block_size, batch_tile_rows).  Blocks the host. */
+apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b, const apcg_vec *x,
+                                int32_t kind, int32_t iters, apcg_batch_config *best, double *best_ms,
+                                int32_t *from_cache);
+
 /* No-allocation variant of apcg_ksp_solve with APCG_MODE_PERSISTENT, for
  * callers that cannot allocate device memory: code under stream capture,
  * tight serving loops, harnesses that forbid hipMalloc.  The same

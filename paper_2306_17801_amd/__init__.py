@@ -382,6 +382,24 @@ def apcg_mat_autotune_cached(A, ctx, reps: int = 20):
              "schedule": cfg.schedule}, us.value, bool(hit.value))
 
 
+def apcg_batch_autotune(ctx, A_list, b_list, x_list, kind: int = 0, iters: int = 32):
+    """Times the batched solve's launch configurations (see include/apcg.h);
+    returns (config dict, milliseconds, True when it came from the table).
+    x_list's vectors are overwritten."""
+    n = len(A_list)
+    if len(b_list) != n or len(x_list) != n:
+        raise ValueError("A_list, b_list and x_list must have the same length")
+    arr = lambda hs: (ctypes.c_void_p * max(n, 1))(*[int(h) for h in hs])  # noqa: E731
+    cfg = _capi.apcg_batch_config()
+    ms = ctypes.c_double()
+    hit = ctypes.c_int32()
+    check("apcg_batch_autotune", _L().apcg_batch_autotune(_h(ctx), n, arr(A_list), arr(b_list), arr(x_list),
+                                                          int(kind), int(iters), ctypes.byref(cfg),
+                                                          ctypes.byref(ms), ctypes.byref(hit)))
+    return ({"schedule": cfg.schedule, "block_size": cfg.block_size, "tile_rows": cfg.tile_rows,
+             "sdia": cfg.sdia}, ms.value, bool(hit.value))
+
+
 def apcg_tune_key_pattern(arch: str, rowptr, col) -> str:
     """Tuning key of host CSR arrays (numpy int32) for architecture `arch`."""
     import numpy as np

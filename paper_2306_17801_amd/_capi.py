@@ -78,6 +78,10 @@ class apcg_spmv_config(ctypes.Structure):
     _fields_ = [("lanes_per_row", c_i32), ("block_size", c_i32), ("blocks", c_i32), ("schedule", c_i32)]
 
 
+class apcg_batch_config(ctypes.Structure):
+    _fields_ = [("schedule", c_i32), ("block_size", c_i32), ("tile_rows", c_i32), ("sdia", c_i32)]
+
+
 class apcg_solve_opts(ctypes.Structure):
     _fields_ = [("pc", c_i32), ("norm_type", c_i32), ("mode", c_i32), ("iters_per_graph", c_i32),
                 ("lookahead", c_i32), ("x0_is_zero", c_i32), ("kernel_timing", c_i32),
@@ -202,6 +206,7 @@ SIGNATURES = {
     "apcg_tune_cache_load": [c_char_p, P(c_i32)],
     "apcg_tune_cache_save": [c_char_p, P(c_i32)],
     "apcg_mat_autotune_cached": [c_vp, c_vp, c_i32, P(apcg_spmv_config), P(c_f64), P(c_i32)],
+    "apcg_batch_autotune": [c_vp, c_i32, c_vp, c_vp, c_vp, c_i32, c_i32, P(apcg_batch_config), P(c_f64), P(c_i32)],
     "apcg_ksp_solve_small_noalloc": [c_vp, c_i32, c_vp, c_vp, c_vp, c_vp, c_vp, c_f64, c_i32, P(apcg_solve_opts),
                                      c_vp],
     "apcg_solve_opts_default": [P(apcg_solve_opts)],

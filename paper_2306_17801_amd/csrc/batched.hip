@@ -749,74 +749,6 @@ __global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
     });
 }
 
-// A wavefront's slices sl_begin, sl_begin + SW, ... < sl_end of one system
-// on the sliced-diagonal copy (8 offset slots per slice, UC walked): w = A p
-// and p = z + beta p_old with the next slice's offsets, masks and values
-// loaded while the current slice's gathers are in flight; each row adds its
-// entries in column order with one FMA each (the sums of dev::sdia_row);
-// slice partials of p.w to part[g0 + slice].
-template <int UC>
-__device__ __forceinline__ void seg_sdia_slices(const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
-                                                const double *__restrict__ sval, int U, int n, int sl_begin,
-                                                int sl_end, const double *__restrict__ z,
-                                                const double *__restrict__ pold, double *__restrict__ pnew,
-                                                double *__restrict__ w, double beta, double *part, int ns, int g0) {
-    const int lane = threadIdx.x & 63;
-    int on[UC];
-    uint64_t mn[UC];
-    double an[UC];
-    auto load = [&](int sl) {
-        const int32_t *o = soff + (int64_t)sl * 8;
-        const uint64_t *m = smask + (int64_t)sl * 8;
-        const double *v = sval + (int64_t)sl * U * 64 + lane;
-#pragma unroll
-        for (int k = 0; k < UC; ++k) {
-            on[k] = o[k];
-            mn[k] = m[k];
-            an[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
-        }
-    };
-    if (sl_begin < sl_end) load(sl_begin);
-    for (int sl = sl_begin; sl < sl_end; sl += SW) {
-        int oc[UC];
-        uint64_t mc[UC];
-        double ac[UC];
-#pragma unroll
-        for (int k = 0; k < UC; ++k) {
-            oc[k] = on[k];
-            mc[k] = mn[k];
-            ac[k] = an[k];
-        }
-        if (sl + SW < sl_end) load(sl + SW);  // in flight during the gathers below
-        const int row = sl * 64 + lane;
-        const int rc = row < n ? row : n - 1;
-        double zj[UC], pj[UC];
-        bool in[UC];
-#pragma unroll
-        for (int k = 0; k < UC; ++k) {
-            in[k] = (mc[k] >> lane) & 1ull;
-            const int j = in[k] ? row + oc[k] : rc;
-            zj[k] = z[j];
-            pj[k] = pold[j];
-        }
-        const double zi = z[rc], po = pold[rc];
-        double sum = 0.0;
-#pragma unroll
-        for (int k = 0; k < UC; ++k) {
-            const double t = fma(ac[k], fma(beta, pj[k], zj[k]), sum);
-            sum = in[k] ? t : sum;
-        }
-        const double pi = fma(beta, po, zi);
-        double v[1] = {0.0};
-        if (row < n) {
-            pnew[row] = pi;
-            w[row] = sum;
-            v[0] = pi * sum;
-        }
-        slice_store<1>(v, part, ns, g0 + sl);
-    }
-}
-
 // UC: sliced-diagonal slots walked per row (>= every such system's U).
 template <int UC>
 __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
@@ -833,9 +765,20 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
         const int g0 = P.sys_slice0[s];
         int sl0, sl1;
         tile_slices(P, t, S.n, &sl0, &sl1);
-        if (S.sval) {
-            seg_sdia_slices<UC>(S.soff, S.smask, S.sval, S.U, S.n, sl0 + wave, sl1, z, pold, pnew, w, beta,
-                                P.part_delta, P.nslices, g0);
+        if (S.sval) {  // the next slice's offsets and values loaded during the current gathers
+            dev::sdia_slices<UC>(
+                S.soff, S.smask, S.sval, S.U, n, sl0 + wave, sl1, SW,
+                [&](int q) { return fma(beta, pold[q], z[q]); },
+                [&](int sl, int row, int rc, double sum) {
+                    const double pi = fma(beta, pold[rc], z[rc]);
+                    double v[1] = {0.0};
+                    if (row < n) {
+                        pnew[row] = pi;
+                        w[row] = sum;
+                        v[0] = pi * sum;
+                    }
+                    slice_store<1>(v, P.part_delta, P.nslices, g0 + sl);
+                });
             return;
         }
         for (int sl = sl0 + wave; sl < sl1; sl += SW) {

@@ -35,8 +35,9 @@
 namespace apcg {
 namespace {
 
-constexpr int FT = 256;  // rows per tile = threads per tile workgroup
-constexpr int FSPT = FT / 64;  // 64-row slices per tile (one per wavefront)
+constexpr int FT = 256;  // threads per tile workgroup (tiles are multiples of FT rows)
+constexpr int FSW = FT / 64;  // its wavefronts: wavefront j takes slices j, j + 4, ... of a tile
+
 constexpr int FDEG = 8;
 constexpr int MODE_FLEX = 0, MODE_JACOBI = 1;
 
@@ -70,17 +71,26 @@ struct FPlan {
     const FSys *sys;                      // [nsys]
     const int32_t *tile_sys, *tile_row0;  // [ntiles]
     const int32_t *sys_tile0;             // [nsys + 1]
+    const int32_t *sys_slice0;            // [nsys + 1]: first global 64-row slice of each system
     FState *st;                           // [nsys]
-    double *part;                         // [4][nslices]: per 64-row slice, slice j of tile t at 4 t + j
+    double *part;                         // [4][nslices]: per 64-row slice, local slice l of system s at sys_slice0[s] + l
     unsigned *running;
     int32_t nsys, ntiles, tiles_per_block;
-    int32_t nslices;                      // FSPT ntiles
+    int32_t nslices;                      // sys_slice0[nsys]
+    int32_t tile_rows;                    // rows per tile (a multiple of FT)
     int32_t maxit, stall_min, fallback;
     double rtol, stall_frac;
     int32_t force_jacobi;  // feature runs: every system in Jacobi mode from the start
     int32_t hist_cap;      // > 0: alpha, beta of the first hist_cap iterations
     double *hist;          // [nsys][2][hist_cap]
 };
+
+// The local slices [sl0, sl1) of tile t (of a system of n rows).
+__device__ __forceinline__ void ftile_slices(const FPlan &P, int t, int n, int *sl0, int *sl1) {
+    const int r0 = P.tile_row0[t];
+    *sl0 = r0 >> 6;
+    *sl1 = min((n + 63) >> 6, (r0 + P.tile_rows) >> 6);
+}
 
 // Runs body(t) for every tile t of this workgroup whose system passes
 // keep(state).  Workgroup lb (its XCD-aware index) owns tiles lb, lb + G,
@@ -135,16 +145,16 @@ __device__ __forceinline__ double frow(const int32_t *__restrict__ col, const do
     return sum;
 }
 
-// The slice partials of system s (slices FSPT sys_tile0[s] .. FSPT
-// sys_tile0[s+1] of rows slot0.. of P.part), added in a fixed order (thread
+// The slice partials of system s (global slices sys_slice0[s] ..
+// sys_slice0[s+1] of rows slot0.. of P.part), added in a fixed order (thread
 // l takes slices l, l + 64, ..., then the wavefront tree; one 64-thread
-// workgroup); the result is valid in thread 0.
+// workgroup); the same sums whatever the tile size.  Result in thread 0.
 template <int NV>
 __device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV]) {
     __shared__ double lds[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = FSPT * P.sys_tile0[s] + (int)threadIdx.x; g < FSPT * P.sys_tile0[s + 1]; g += 64) {
+    for (int g = P.sys_slice0[s] + (int)threadIdx.x; g < P.sys_slice0[s + 1]; g += 64) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] += P.part[(size_t)(slot0 + k) * P.nslices + g];
     }
@@ -164,14 +174,14 @@ __device__ __forceinline__ void fsys_sum_tiles(const FPlan &P, int s, const doub
     dev::block_sum<64, NV>(v, lds);
 }
 
-// The calling wavefront's sums over its 64 rows (slice 4 t + wavefront of
-// tile t) as that slice's partials; lane 0 stores.  No workgroup barrier.
+// The calling wavefront's sums over its 64 rows (local slice sl of system s)
+// as that slice's partials; lane 0 stores.  No workgroup barrier.
 template <int NV>
-__device__ __forceinline__ void ftile_store(const FPlan &P, int t, int slot0, double (&v)[NV]) {
+__device__ __forceinline__ void ftile_store(const FPlan &P, int s, int sl, int slot0, double (&v)[NV]) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = dev::wave_sum(v[k]);
     if ((threadIdx.x & 63) == 0) {
-        const int g = FSPT * t + (int)(threadIdx.x >> 6);
+        const int g = P.sys_slice0[s] + sl;
 #pragma unroll
         for (int k = 0; k < NV; ++k) P.part[(size_t)(slot0 + k) * P.nslices + g] = v[k];
     }
@@ -211,9 +221,14 @@ __device__ void fswitch(const FPlan &P, FState *q, int reason) {
 
 __global__ __launch_bounds__(FT) void k_bf_init(FPlan P, int x0_zero) {
     const int tb0 = dev::xcd_block(blockIdx.x, gridDim.x), tstep = gridDim.x;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for (int t = tb0; t < P.ntiles; t += tstep) {
-        const FSys S = P.sys[P.tile_sys[t]];
-        const int i = P.tile_row0[t] + threadIdx.x;
+      const int sys = P.tile_sys[t];
+      const FSys S = P.sys[sys];
+      int sl0, sl1;
+      ftile_slices(P, t, S.n, &sl0, &sl1);
+      for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
+        const int i = sl * 64 + lane;
         double v[3] = {0.0, 0.0, 0.0};  // ||b||^2, ||r||^2, bad diagonals
         if (i < S.n) {
             const int64_t n = S.n;
@@ -238,7 +253,8 @@ __global__ __launch_bounds__(FT) void k_bf_init(FPlan P, int x0_zero) {
             v[1] = ri * ri;
             v[2] = ok ? 0.0 : 1.0;
         }
-        ftile_store<3>(P, t, 0, v);
+        ftile_store<3>(P, sys, sl, 0, v);
+      }
     }
 }
 
@@ -299,16 +315,22 @@ __global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef
 }
 
 __global__ __launch_bounds__(FT) void k_bf_zero_x(FPlan P) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [](const FState &q) { return q.zero_x != 0; }, [&](int t) {
         const FSys S = P.sys[P.tile_sys[t]];
-        const int i = P.tile_row0[t] + threadIdx.x;
-        if (i < S.n) S.x[i] = 0.0;
+        int sl0, sl1;
+        ftile_slices(P, t, S.n, &sl0, &sl1);
+        for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
+            const int i = sl * 64 + lane;
+            if (i < S.n) S.x[i] = 0.0;
+        }
     });
 }
 
 // UC: sliced-diagonal slots walked per row (>= every such system's U).
 template <int UC>
 __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [](const FState &q) { return !q.flag && !q.restart; }, [&](int t) {
         const int s = P.tile_sys[t];
         const FState *q = P.st + s;
@@ -319,19 +341,29 @@ __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
         const double *pold = S.ws + (3 + ((parity + 1) & 1)) * n;
         double *pnew = S.ws + (3 + (parity & 1)) * n;
         double *w = S.ws + 5 * n;
-        const int i = P.tile_row0[t] + threadIdx.x;
-        double v[1] = {0.0};
-        if (i < S.n) {
-            auto u = [&](int j) { return fma(beta, pold[j], z[j]); };
-            // tiles start at multiples of FT rows: a wavefront's rows are one slice
-            const double sum = S.sval ? dev::sdia_row<8, UC>(S.soff, S.smask, S.sval, S.U, n, i, u)
-                                      : frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u);
-            const double pi = fma(beta, pold[i], z[i]);
-            pnew[i] = pi;
-            w[i] = sum;
-            v[0] = pi * sum;
+        int sl0, sl1;
+        ftile_slices(P, t, S.n, &sl0, &sl1);
+        auto u = [&](int j) { return fma(beta, pold[j], z[j]); };
+        auto finish = [&](int sl, int i, int rc, double sum) {
+            const double pi = fma(beta, pold[rc], z[rc]);
+            double v[1] = {0.0};
+            if (i < n) {
+                pnew[i] = pi;
+                w[i] = sum;
+                v[0] = pi * sum;
+            }
+            ftile_store<1>(P, s, sl, 0, v);
+        };
+        if (S.sval) {  // the next slice's offsets and values loaded during the current gathers
+            dev::sdia_slices<UC>(S.soff, S.smask, S.sval, S.U, n, sl0 + wave, sl1, FSW, u, finish);
+            return;
         }
-        ftile_store<1>(P, t, 0, v);
+        for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
+            const int i = sl * 64 + lane;
+            const int rc = i < n ? i : (int)n - 1;
+            const double sum = i < n ? frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u) : 0.0;
+            finish(sl, i, rc, sum);
+        }
     });
 }
 
@@ -354,6 +386,7 @@ __global__ __launch_bounds__(64) void k_bf_alpha(FPlan P) {
 }
 
 __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [](const FState &q) { return !q.flag && !q.restart; }, [&](int t) {
         const int s = P.tile_sys[t];
         const FState *q = P.st + s;
@@ -363,15 +396,19 @@ __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
         double *r = S.ws;
         const double *p = S.ws + (3 + (parity & 1)) * n;
         const double *w = S.ws + 5 * n;
-        const int i = P.tile_row0[t] + threadIdx.x;
-        double v[1] = {0.0};
-        if (i < S.n) {
-            S.x[i] = fma(alpha, p[i], S.x[i]);
-            const double ri = fma(-alpha, w[i], r[i]);
-            r[i] = ri;
-            v[0] = ri * ri;
+        int sl0, sl1;
+        ftile_slices(P, t, S.n, &sl0, &sl1);
+        for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
+            const int i = sl * 64 + lane;
+            double v[1] = {0.0};
+            if (i < S.n) {
+                S.x[i] = fma(alpha, p[i], S.x[i]);
+                const double ri = fma(-alpha, w[i], r[i]);
+                r[i] = ri;
+                v[0] = ri * ri;
+            }
+            ftile_store<1>(P, s, sl, 1, v);
         }
-        ftile_store<1>(P, t, 1, v);
     });
 }
 
@@ -417,6 +454,7 @@ __global__ __launch_bounds__(64) void k_bf_check(FPlan P) {
 // v = D^-1 r; b_8 = c_8 v is formed where it is needed.
 template <int UC>
 __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o_b1, int o_b2, int o_out) {
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
     for_active_tiles(P, [stage](const FState &q) { return !q.flag && (stage == 2 || q.mode != MODE_JACOBI); },
                      [&](int t) {
         const int s = P.tile_sys[t];
@@ -429,33 +467,51 @@ __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o
         const double *bj2 = o_b2 >= 0 ? S.ws + (6 + o_b2) * n : nullptr;
         double *out = o_out >= 0 ? S.ws + (6 + o_out) * n : S.ws + 2 * n;
         const double s2 = 2.0 / q->lmax, cj = q->c[j], cd = q->c[FDEG];
-        const int i = P.tile_row0[t] + threadIdx.x;
-        double v[2] = {0.0, 0.0};
-        if (i < S.n) {
-            auto row = [&](auto u) {
-                return S.sval ? dev::sdia_row<8, UC>(S.soff, S.smask, S.sval, S.U, n, i, u)
-                              : frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u);
-            };
-            const double vi = dinv[i] * r[i];
-            double res;
-            if (jac) {
-                res = vi;
-            } else if (stage == 0) {
-                const double av = row([&](int k) { return dinv[k] * r[k]; });
-                res = fma(2.0 * cd, s2 * dinv[i] * av - vi, cj * vi);
-            } else {
-                const double au = row([&](int k) { return bj1[k]; });
-                const double yu = s2 * dinv[i] * au - bj1[i];
-                const double b2v = bj2 ? bj2[i] : cd * vi;
-                res = stage == 1 ? fma(2.0, yu, cj * vi) - b2v : cj * vi + yu - b2v;
+        int sl0, sl1;
+        ftile_slices(P, t, S.n, &sl0, &sl1);
+        // the step once row i's sum of A u is known (au; unused in Jacobi mode).
+        // Inlined at two call sites: contraction into FMAs is off so that
+        // both compile to the same operations and the CSR and sliced-diagonal
+        // reads give the same bits.
+        auto finish = [&](int sl, int i, double au) {
+#pragma clang fp contract(off)
+            double v[2] = {0.0, 0.0};
+            if (i < n) {
+                const double vi = dinv[i] * r[i];
+                double res;
+                if (jac) {
+                    res = vi;
+                } else if (stage == 0) {
+                    res = fma(2.0 * cd, s2 * dinv[i] * au - vi, cj * vi);
+                } else {
+                    const double yu = s2 * dinv[i] * au - bj1[i];
+                    const double b2v = bj2 ? bj2[i] : cd * vi;
+                    res = stage == 1 ? fma(2.0, yu, cj * vi) - b2v : cj * vi + yu - b2v;
+                }
+                out[i] = res;
+                if (stage == 2) {
+                    v[0] = r[i] * res;
+                    v[1] = res * w[i];
+                }
             }
-            out[i] = res;
-            if (stage == 2) {
-                v[0] = r[i] * res;
-                v[1] = res * w[i];
-            }
+            if (stage == 2) ftile_store<2>(P, s, sl, 2, v);
+        };
+        auto u0 = [&](int k) { return dinv[k] * r[k]; };
+        auto u1 = [&](int k) { return bj1[k]; };
+        if (!jac && S.sval) {  // the next slice's offsets and values loaded during the current gathers
+            auto f = [&](int sl, int i, int, double au) { finish(sl, i, au); };
+            if (stage == 0) dev::sdia_slices<UC>(S.soff, S.smask, S.sval, S.U, n, sl0 + wave, sl1, FSW, u0, f);
+            else dev::sdia_slices<UC>(S.soff, S.smask, S.sval, S.U, n, sl0 + wave, sl1, FSW, u1, f);
+            return;
         }
-        if (stage == 2) ftile_store<2>(P, t, 2, v);
+        for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
+            const int i = sl * 64 + lane;
+            double au = 0.0;
+            if (!jac && i < n)
+                au = stage == 0 ? frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u0)
+                                : frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u1);
+            finish(sl, i, au);
+        }
     });
 }
 
@@ -493,9 +549,9 @@ __global__ __launch_bounds__(FT) void k_bf_rows(FPlan P, double *fpart) {
     __shared__ double sh[7][FT];
     for (int t = tb0; t < P.ntiles; t += tstep) {
         const FSys S = P.sys[P.tile_sys[t]];
-        const int i = P.tile_row0[t] + threadIdx.x;
+        const int r0 = P.tile_row0[t], r1 = min(S.n, r0 + P.tile_rows);
         dev::RowStats a;
-        if (i < S.n) dev::row_stats_add(a, S.rowptr, S.col, S.val, i);
+        for (int i = r0 + (int)threadIdx.x; i < r1; i += FT) dev::row_stats_add(a, S.rowptr, S.col, S.val, i);
         dev::row_stats_block<FT>(a, sh);
         if (threadIdx.x == 0)
             for (int k = 0; k < 7; ++k) fpart[(size_t)k * P.ntiles + t] = a.v[k];
@@ -528,11 +584,11 @@ __global__ __launch_bounds__(FT) void k_bf_rows2(FPlan P, const double *fstats, 
     for (int t = tb0; t < P.ntiles; t += tstep) {
         const int s = P.tile_sys[t];
         const FSys S = P.sys[s];
-        const int i = P.tile_row0[t] + threadIdx.x;
+        const int r0 = P.tile_row0[t], r1 = min(S.n, r0 + P.tile_rows);
         double v[1] = {0.0};
-        if (i < S.n) {
+        for (int i = r0 + (int)threadIdx.x; i < r1; i += FT) {
             const double e = dev::row_logdiag(S.rowptr, S.col, S.val, i) - fstats[8 * s + 7];
-            v[0] = e * e;
+            v[0] = fma(e, e, v[0]);
         }
         dev::block_sum<FT, 1>(v, lds);
         if (threadIdx.x == 0) fpart[(size_t)7 * P.ntiles + t] = v[0];
@@ -597,12 +653,12 @@ uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
 struct BfCache {
     int device = 0;
     FSys *d_sys = nullptr;
-    int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr;
+    int32_t *d_tile_sys = nullptr, *d_tile_row0 = nullptr, *d_sys_tile0 = nullptr, *d_sys_slice0 = nullptr;
     FState *d_st = nullptr;
-    double *d_part = nullptr;  // 4 * FSPT * tiles_cap (slice partials)
+    double *d_part = nullptr;  // 4 * slices_cap (slice partials)
     double *d_ws = nullptr;
     unsigned *d_running = nullptr;
-    int64_t sys_cap = 0, tiles_cap = 0, ws_cap = 0;
+    int64_t sys_cap = 0, tiles_cap = 0, ws_cap = 0, slices_cap = 0;
     uint64_t hash = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -650,6 +706,7 @@ static void bf_free(BfCache &b) {
     hipFree(b.d_tile_sys);
     hipFree(b.d_tile_row0);
     hipFree(b.d_sys_tile0);
+    hipFree(b.d_sys_slice0);
     hipFree(b.d_st);
     hipFree(b.d_part);
     hipFree(b.d_ws);
@@ -696,22 +753,29 @@ struct BfRun {
 static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<FSys> &hs, int64_t ws_total,
                            const std::vector<apcg_mat_s *> &refill, double rtol, int32_t maxit,
                            const apcg_solve_opts &opts, const apcg_fcg_opts &fo, const BfRun &run,
-                           apcg_solve_info *d_info) {
+                           apcg_solve_info *d_info, FPlan *plan_out = nullptr, int *grid_out = nullptr) {
     const int dev = ctx->device;
     hipStream_t st = ctx->stream;
     for (apcg_mat_s *m : refill) {  // the sliced-diagonal values of the systems that read them
         apcg_status ps = prepare_sdia(m, st);
         if (ps) return ps;
     }
-    std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1);
+    const int32_t TR = batch_tile_rows(opts);
+    std::vector<int32_t> tile_sys, tile_row0, sys_tile0(nsys + 1), sys_slice0(nsys + 1);
+    int64_t nslices = 0;
     for (int32_t q = 0; q < nsys; ++q) {
         sys_tile0[q] = (int32_t)tile_sys.size();
-        for (int32_t r0 = 0; r0 < hs[q].n; r0 += FT) {
+        sys_slice0[q] = (int32_t)nslices;
+        nslices += ((int64_t)hs[q].n + 63) / 64;
+        for (int32_t r0 = 0; r0 < hs[q].n; r0 += TR) {
             tile_sys.push_back(q);
             tile_row0.push_back(r0);
         }
     }
     sys_tile0[nsys] = (int32_t)tile_sys.size();
+    sys_slice0[nsys] = (int32_t)nslices;
+    if (nslices > INT32_MAX / 8) return set_error(APCG_ERR_INVALID_ARG, "batch too large for the segmented schedule");
+    const int64_t ns_alloc = std::max<int64_t>(nslices, 1);
     const int32_t ntiles = (int32_t)tile_sys.size();
     if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well formed
         tile_sys.push_back(0);
@@ -720,7 +784,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     const int32_t nt_alloc = std::max<int32_t>(ntiles, 1);
     APCG_HIP(hipSetDevice(dev));
     const int64_t ws_need = std::max<int64_t>(ws_total, 64);
-    if (bc->sys_cap < nsys || bc->tiles_cap < nt_alloc || bc->ws_cap < ws_need) {
+    if (bc->sys_cap < nsys || bc->tiles_cap < nt_alloc || bc->ws_cap < ws_need || bc->slices_cap < ns_alloc) {
         EventRef ev = event_get(dev);
         if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
         APCG_HIP(hipEventRecord(ev->e, st));
@@ -735,13 +799,15 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
         bc->hash = 0;
         bc->sys_cap = std::max<int64_t>(nsys, bc->sys_cap);
         bc->tiles_cap = std::max<int64_t>(nt_alloc, bc->tiles_cap);
+        bc->slices_cap = std::max<int64_t>(ns_alloc, bc->slices_cap);
         bc->ws_cap = std::max<int64_t>(ws_need, bc->ws_cap);
         APCG_HIP(hipMalloc((void **)&bc->d_sys, sizeof(FSys) * bc->sys_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_st, sizeof(FState) * bc->sys_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_sys_tile0, sizeof(int32_t) * (bc->sys_cap + 1)));
+        APCG_HIP(hipMalloc((void **)&bc->d_sys_slice0, sizeof(int32_t) * (bc->sys_cap + 1)));
         APCG_HIP(hipMalloc((void **)&bc->d_tile_sys, sizeof(int32_t) * bc->tiles_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_tile_row0, sizeof(int32_t) * bc->tiles_cap));
-        APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * FSPT * bc->tiles_cap));
+        APCG_HIP(hipMalloc((void **)&bc->d_part, sizeof(double) * 4 * bc->slices_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_ws, sizeof(double) * bc->ws_cap));
         APCG_HIP(hipMalloc((void **)&bc->d_running, 256));
     }
@@ -752,8 +818,11 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     h = fnv(tile_sys.data(), sizeof(int32_t) * tile_sys.size(), h);
     h = fnv(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
     h = fnv(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
+    h = fnv(sys_slice0.data(), sizeof(int32_t) * sys_slice0.size(), h);
     if (h != bc->hash) {
-        g_counters.h2d_copies += 4;
+        g_counters.h2d_copies += 5;
+        APCG_HIP(hipMemcpyAsync(bc->d_sys_slice0, sys_slice0.data(), sizeof(int32_t) * sys_slice0.size(),
+                                hipMemcpyHostToDevice, st));
         APCG_HIP(hipMemcpyAsync(bc->d_sys, hs.data(), sizeof(FSys) * nsys, hipMemcpyHostToDevice, st));
         APCG_HIP(hipMemcpyAsync(bc->d_tile_sys, tile_sys.data(), sizeof(int32_t) * tile_sys.size(),
                                 hipMemcpyHostToDevice, st));
@@ -770,15 +839,19 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     P.tile_sys = bc->d_tile_sys;
     P.tile_row0 = bc->d_tile_row0;
     P.sys_tile0 = bc->d_sys_tile0;
+    P.sys_slice0 = bc->d_sys_slice0;
     P.st = bc->d_st;
     P.part = bc->d_part;
     P.running = bc->d_running;
     P.nsys = nsys;
     P.ntiles = ntiles;
-    P.nslices = FSPT * std::max<int32_t>(ntiles, 1);
+    P.nslices = (int32_t)ns_alloc;
+    P.tile_rows = TR;
     const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
     P.maxit = maxit;
+    if (plan_out) *plan_out = P;
+    if (grid_out) *grid_out = G;
     P.stall_min = fo.stall_min;
     P.fallback = fo.fallback ? 1 : 0;
     P.rtol = rtol;
@@ -1005,22 +1078,9 @@ static apcg_status bf_features(apcg_ctx ctx, BfCache *bc, int32_t nsys, const ap
     run.force_jacobi = 1;
     run.hist = bc->d_hist;
     run.hist_cap = FEAT_STEPS;
-    if ((s = bf_core(ctx, bc, nsys, hs, ws_total, refill, 0.0, FEAT_STEPS, o, fo, run, nullptr))) return s;
     FPlan P;
-    P.sys = bc->d_sys;
-    P.tile_sys = bc->d_tile_sys;
-    P.tile_row0 = bc->d_tile_row0;
-    P.sys_tile0 = bc->d_sys_tile0;
-    P.st = bc->d_st;
-    P.part = bc->d_part;
-    P.running = bc->d_running;
-    P.nsys = nsys;
-    int32_t nt = 0;
-    for (auto &f : hs) nt += (f.n + FT - 1) / FT;
-    P.ntiles = nt;
-    P.nslices = FSPT * std::max<int32_t>(nt, 1);
-    const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(nt, 1));
-    P.tiles_per_block = std::max<int32_t>(1, (nt + G - 1) / G);
+    int G = 0;
+    if ((s = bf_core(ctx, bc, nsys, hs, ws_total, refill, 0.0, FEAT_STEPS, o, fo, run, nullptr, &P, &G))) return s;
     P.hist = bc->d_hist;
     P.hist_cap = FEAT_STEPS;
     hipLaunchKernelGGL(k_bf_rows, dim3(G), dim3(FT), 0, st, P, bc->d_fpart);
@@ -1059,6 +1119,8 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
         if (fopts_in) fo = *fopts_in;
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        if (!valid_batch_tile_rows(opts.batch_tile_rows))
+            return set_error(APCG_ERR_INVALID_ARG, "batch tile rows must be 0 or a multiple of 256 in [256, 8192]");
         std::vector<FSys> hs;
         std::vector<apcg_mat_s *> refill;
         int64_t ws_total = 0;
@@ -1124,6 +1186,8 @@ extern "C" apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys
         if (fopts_in) fo = *fopts_in;
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        if (!valid_batch_tile_rows(opts.batch_tile_rows))
+            return set_error(APCG_ERR_INVALID_ARG, "batch tile rows must be 0 or a multiple of 256 in [256, 8192]");
         std::vector<FSys> hs;
         std::vector<apcg_mat_s *> refill;
         int64_t ws_total = 0;

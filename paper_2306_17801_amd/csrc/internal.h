@@ -610,6 +610,63 @@ __device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, con
     return sum;
 }
 
+// The rows of slices sl_begin, sl_begin + step, ... < sl_end of a matrix's
+// sliced-diagonal copy (8 offset slots per slice, UC <= 8 walked), walked by
+// one wavefront: for each slice, f(sl, row, rc, sum) with sum = sum_k a_k
+// u(j_k) over the row's entries (column order, one FMA each: the sums of
+// sdia_row) and rc = min(row, n - 1).  The next slice's offsets, masks and
+// values are loaded before the current slice's gathers are issued, so they
+// are in flight together.  sl must be uniform across the wavefront.
+template <int UC, typename FU, typename FF>
+__device__ __forceinline__ void sdia_slices(const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
+                                            const double *__restrict__ sval, int U, int64_t n, int sl_begin,
+                                            int sl_end, int step, FU u, FF f) {
+    const int lane = threadIdx.x & 63;
+    int on[UC];
+    uint64_t mn[UC];
+    double an[UC];
+    auto load = [&](int sl) {
+        const int32_t *o = soff + (int64_t)sl * 8;
+        const uint64_t *m = smask + (int64_t)sl * 8;
+        const double *v = sval + (int64_t)sl * U * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            on[k] = o[k];
+            mn[k] = m[k];
+            an[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
+        }
+    };
+    if (sl_begin < sl_end) load(sl_begin);
+    for (int sl = sl_begin; sl < sl_end; sl += step) {
+        int oc[UC];
+        uint64_t mc[UC];
+        double ac[UC];
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            oc[k] = on[k];
+            mc[k] = mn[k];
+            ac[k] = an[k];
+        }
+        if (sl + step < sl_end) load(sl + step);  // in flight during the gathers below
+        const int row = sl * 64 + lane;
+        const int rc = row < n ? row : (int)n - 1;
+        double g[UC];
+        bool in[UC];
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            in[k] = (mc[k] >> lane) & 1ull;
+            g[k] = u(in[k] ? row + oc[k] : rc);
+        }
+        double sum = 0.0;
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            const double t = fma(ac[k], g[k], sum);
+            sum = in[k] ? t : sum;
+        }
+        f(sl, row, rc, sum);
+    }
+}
+
 // A matrix as the row-per-thread kernels read it: the CSR arrays, and the
 // sliced-diagonal copy when there is one.
 struct RowMat {

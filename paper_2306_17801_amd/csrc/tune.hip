@@ -335,3 +335,171 @@ apcg_status apcg_mat_autotune_cached(apcg_mat A, apcg_ctx ctx, int32_t reps, apc
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------- batched schedules
+// apcg_batch_autotune: times the batched solve's launch configurations on
+// the device (a fixed number of iterations with rtol 0, HIP events on the
+// context's stream, the better of two runs after a warm-up that captures the
+// graph) and keeps the best in the tuning table under a batch key.
+
+namespace {
+
+// Key of a batch: what decides between the schedules -- the device, the
+// longest row and the mean row length (the stencil class), the number of
+// systems, the total rows and the largest system (powers of two), and the
+// kind of solve.
+std::string batch_key(const std::string &arch, int kind, int32_t nsys, const apcg_mat *A) {
+    int64_t rows = 0, nnz = 0, nmax = 0;
+    int32_t maxrow = 0;
+    for (int32_t i = 0; i < nsys; ++i) {
+        rows += A[i]->n;
+        nnz += A[i]->nnz;
+        nmax = std::max<int64_t>(nmax, A[i]->n);
+        maxrow = std::max(maxrow, A[i]->sell_maxw);
+    }
+    auto lg = [](int64_t v) {
+        int l = 0;
+        while (l < 62 && ((int64_t)1 << (l + 1)) <= v) ++l;
+        return l;
+    };
+    const long long r4 = rows > 0 ? llround(4.0 * (double)nnz / (double)rows) : 0;
+    return "batch|" + arch + "|" + (kind ? "fcg" : "pcg") + "|m" + std::to_string(maxrow) + "|r" +
+           std::to_string(r4) + "|s" + std::to_string(lg(nsys)) + "|n" + std::to_string(lg(rows)) + "|x" +
+           std::to_string(lg(nmax));
+}
+
+}  // namespace
+
+extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
+                                           const apcg_vec *x, int32_t kind, int32_t iters, apcg_batch_config *best,
+                                           double *best_ms, int32_t *from_cache) {
+    try {
+        if (!ctx || nsys < 1 || !A || !b || !x || !best || iters < 1 || iters > 100000 || (kind != 0 && kind != 1))
+            return set_error(APCG_ERR_INVALID_ARG, "bad batch autotune arguments");
+        if (ctx->type == APCG_STREAM_GLOBAL_BLOCKING)
+            return set_error(APCG_ERR_INVALID_ARG, "autotune needs a default-stream context");
+        for (int32_t i = 0; i < nsys; ++i)
+            if (!A[i] || !b[i] || !x[i]) return set_error(APCG_ERR_INVALID_ARG, "NULL system handle");
+        std::string arch;
+        apcg_status s;
+        if ((s = device_arch(ctx->device, &arch))) return s;
+        const std::string key = batch_key(arch, kind, nsys, A);
+        // the members' product schedules, restored unless the sliced-diagonal
+        // copies win
+        std::vector<apcg_spmv_config> saved(nsys);
+        for (int32_t i = 0; i < nsys; ++i) saved[i] = A[i]->cfg;
+        auto set_sdia = [&](bool on) {
+            int32_t switched = 0;
+            for (int32_t i = 0; i < nsys; ++i) {
+                if (!on) {
+                    A[i]->cfg = saved[i];
+                    continue;
+                }
+                const apcg_spmv_config c{1, 256, 0, APCG_SPMV_SDIA};
+                if (A[i]->n > 0 && apcg_mat_set_spmv_config(A[i], &c) == APCG_SUCCESS) ++switched;
+            }
+            return switched;
+        };
+        int32_t v[4];
+        double ms = 0.0;
+        if (tune_lookup(key, v, &ms)) {
+            best->schedule = v[0];
+            best->block_size = v[1];
+            best->tile_rows = v[2];
+            best->sdia = v[3];
+            if (best->sdia) set_sdia(true);
+            if (best_ms) *best_ms = ms;
+            if (from_cache) *from_cache = 1;
+            return APCG_SUCCESS;
+        }
+        APCG_HIP(hipSetDevice(ctx->device));
+        apcg_info info = nullptr;
+        if ((s = apcg_info_create(ctx->device, nsys, &info))) return s;
+        float *coef = nullptr;
+        double *lmax = nullptr;
+        hipEvent_t e0 = nullptr, e1 = nullptr;
+        auto cleanup = [&]() {
+            if (e0) hipEventDestroy(e0);
+            if (e1) hipEventDestroy(e1);
+            hipStreamSynchronize(ctx->stream);
+            hipFree(coef);
+            hipFree(lmax);
+            apcg_info_destroy(info);
+        };
+        auto fail = [&](apcg_status st) {
+            cleanup();
+            return st;
+        };
+        if (kind == 1) {  // p = 1 on [0, 2]: every Clenshaw step still runs
+            std::vector<float> hc((size_t)nsys * 9, 0.0f);
+            std::vector<double> hl((size_t)nsys, 2.0);
+            for (int32_t i = 0; i < nsys; ++i) hc[(size_t)i * 9] = 1.0f;
+            hipError_t e = hipMalloc((void **)&coef, sizeof(float) * hc.size());
+            if (e == hipSuccess) e = hipMalloc((void **)&lmax, sizeof(double) * hl.size());
+            if (e == hipSuccess) e = hipMemcpy(coef, hc.data(), sizeof(float) * hc.size(), hipMemcpyHostToDevice);
+            if (e == hipSuccess) e = hipMemcpy(lmax, hl.data(), sizeof(double) * hl.size(), hipMemcpyHostToDevice);
+            if (e != hipSuccess) return fail(hip_error(e, "batch autotune buffers"));
+        }
+        {
+            hipError_t e = hipEventCreate(&e0);
+            if (e == hipSuccess) e = hipEventCreate(&e1);
+            if (e != hipSuccess) return fail(hip_error(e, "hipEventCreate"));
+        }
+        struct Cand {
+            apcg_batch_config c;
+        };
+        std::vector<Cand> cands;
+        if (kind == 0)
+            for (int tb : {256, 512, 1024}) cands.push_back({{APCG_BATCH_PERSISTENT, tb, 0, 0}});
+        for (int sd : {0, 1})
+            for (int tr : {256, 512, 1024, 2048, 4096}) cands.push_back({{APCG_BATCH_SEGMENTED, 0, tr, sd}});
+        const int32_t can_sdia = set_sdia(true);
+        set_sdia(false);
+        double best_t = 1e300;
+        apcg_batch_config best_c{APCG_BATCH_SEGMENTED, 0, kDefaultBatchTileRows, 0};
+        for (const Cand &cd : cands) {
+            if (cd.c.sdia && !can_sdia) continue;
+            set_sdia(cd.c.sdia != 0);
+            apcg_solve_opts o;
+            apcg_solve_opts_default(&o);
+            o.x0_is_zero = 1;
+            o.batch_schedule = cd.c.schedule;
+            o.batch_block_size = cd.c.block_size;
+            o.batch_tile_rows = cd.c.tile_rows;
+            auto run = [&]() -> apcg_status {
+                if (kind == 0) return apcg_ksp_solve_batched(ctx, nsys, A, b, x, 0.0, iters, &o, info);
+                apcg_fcg_opts fo;
+                apcg_fcg_opts_default(&fo);
+                return apcg_ksp_solve_batched_fcg_poly(ctx, nsys, A, b, x, 0.0, iters, coef, lmax, &o, &fo, info);
+            };
+            if ((s = run())) return fail(s);  // warm-up: graph capture, copies refilled
+            double t = 1e300;
+            for (int rep = 0; rep < 2; ++rep) {
+                hipError_t e = hipEventRecord(e0, ctx->stream);
+                if (e != hipSuccess) return fail(hip_error(e, "hipEventRecord"));
+                if ((s = run())) return fail(s);
+                e = hipEventRecord(e1, ctx->stream);
+                if (e == hipSuccess) e = hipEventSynchronize(e1);
+                float f = 0.0f;
+                if (e == hipSuccess) e = hipEventElapsedTime(&f, e0, e1);
+                if (e != hipSuccess) return fail(hip_error(e, "batch autotune timing"));
+                g_counters.host_syncs++;
+                t = std::min(t, (double)f);
+            }
+            if (t < best_t) {
+                best_t = t;
+                best_c = cd.c;
+            }
+        }
+        set_sdia(best_c.sdia != 0);
+        cleanup();
+        const int32_t nv[4] = {best_c.schedule, best_c.block_size, best_c.tile_rows, best_c.sdia};
+        tune_insert(key, nv, best_t);
+        *best = best_c;
+        if (best_ms) *best_ms = best_t;
+        if (from_cache) *from_cache = 0;
+        return APCG_SUCCESS;
+    } catch (const std::bad_alloc &) {
+        return set_error(APCG_ERR_OUT_OF_MEMORY, "host allocation failed");
+    }
+}

@@ -202,3 +202,38 @@ def test_segmented_tile_rows_rejected(apcg, ctx):
     for tr in (100, 128, 8448, -256):
         with pytest.raises(apcg.ApcgError):
             run_batch(apcg, ctx, systems, 1e-8, 100, batch_schedule=2, batch_tile_rows=tr)
+
+
+def test_batch_autotune_and_table(apcg, ctx):
+    """The batched autotuner times the schedules on the device, keeps the
+    best under the batch's key (a second call takes it from the table
+    without timing), and the solve in the tuned configuration meets the
+    oracle's bar system by system."""
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    rng = np.random.default_rng(63)
+    systems = mixed_small_batch()[:20] + [P._lognormal_system(rng, 2, 90, 1.0, 2.0)]
+    As = [DeviceCSR(s.A) for s in systems]
+    bs = [DeviceVec(s.b) for s in systems]
+    xs = [DeviceVec.zeros(s.A.n) for s in systems]
+    apcg.apcg_tune_cache_clear()
+    cfg, ms, hit = apcg.apcg_batch_autotune(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 0, 16)
+    print(f"case batch autotune: {cfg} {ms:.3f} ms", flush=True)
+    assert not hit and ms > 0
+    assert cfg["schedule"] in (apcg.APCG_BATCH_PERSISTENT, apcg.APCG_BATCH_SEGMENTED)
+    cfg2, ms2, hit2 = apcg.apcg_batch_autotune(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 0, 16)
+    assert hit2 and cfg2 == cfg and ms2 == ms
+    assert apcg.apcg_tune_cache_size() == 1
+    info = apcg.apcg_info_create(0, len(systems))
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_schedule=cfg["schedule"],
+                                        batch_block_size=cfg["block_size"], batch_tile_rows=cfg["tile_rows"])
+    apcg.apcg_ksp_solve_batched(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 1e-10, 20000, opts,
+                                info)
+    for i, s in enumerate(systems):
+        r = apcg.apcg_info_get(info, i)
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=20000)
+        assert r["status"] == ref.status, i
+        if ref.status == oracle.CONVERGED:
+            assert abs(r["iterations"] - ref.its) <= 1 and rel(xs[i].numpy(), ref.x) <= 1e-9, i
+    apcg.apcg_info_destroy(info)
+    apcg.apcg_tune_cache_clear()

@@ -287,3 +287,20 @@ def test_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
         assert a == b2
         assert np.array_equal(xa, xb)
     check_against_oracle(apcg, cases, r_sd, x_sd, 1e-10, 20000)
+
+
+@pytest.mark.parametrize("sdia", [False, True])
+def test_tile_rows_bitwise(apcg, ctx, sdia):
+    """The batched FCG at 256, 1024 and 4096 rows per tile: tiles only group
+    64-row slices for a workgroup, every slice's partials are its own
+    wavefront's sums and each system adds its slices in index order, so the
+    whole run (flexible phases, rejected polynomials and fallbacks included)
+    is bit for bit the same at every tile size; the first run meets the
+    oracle's bar."""
+    cases = mixed_cases()
+    print(f"case batched fcg tile rows sdia={sdia}", flush=True)
+    runs = [run_batch(apcg, ctx, cases, 1e-10, 20000, sdia=sdia, batch_tile_rows=tr) for tr in (256, 1024, 4096)]
+    for res, xs in runs[1:]:
+        assert res == runs[0][0]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, runs[0][1]))
+    check_against_oracle(apcg, cases, *runs[0], 1e-10, 20000)
