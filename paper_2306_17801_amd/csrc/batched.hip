@@ -691,23 +691,26 @@ __global__ __launch_bounds__(ST) void k_seg_init(SegPlan P, int x0_zero, int pc,
     }
 }
 
+// Threads of the per-system kernels (one workgroup per system).
+constexpr int SB = 256;
+
 // Adds the slice partials part[k*ns + g] of a system (its slices ga..gb)
-// in a fixed order: thread l takes g = ga + l, ga + l + 64, ..., then the
-// wavefront tree.  Result in thread 0.
+// in a fixed order: thread l takes g = ga + l, ga + l + SB, ..., then the
+// workgroup tree.  Result in thread 0.
 template <int NV>
 __device__ __forceinline__ void sys_sum(const double *part, int ns, int ga, int gb, double (&v)[NV], double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = ga + (int)threadIdx.x; g < gb; g += 64) {
+    for (int g = ga + (int)threadIdx.x; g < gb; g += SB) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] += part[(int64_t)k * ns + g];
     }
-    dev::block_sum<64, NV>(v, lds);
+    dev::block_sum<SB, NV>(v, lds);
 }
 
-__global__ __launch_bounds__(64) void k_seg_init_final(SegPlan P, double rtol, int32_t maxit) {
+__global__ __launch_bounds__(SB) void k_seg_init_final(SegPlan P, double rtol, int32_t maxit) {
     const int s = blockIdx.x;
-    __shared__ double lds[4];
+    __shared__ double lds[4 * (SB / 64)];
     double v[4];
     sys_sum<4>(P.part_res, P.nslices, P.sys_slice0[s], P.sys_slice0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
@@ -796,10 +799,10 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
     });
 }
 
-__global__ __launch_bounds__(64) void k_seg_alpha(SegPlan P) {
+__global__ __launch_bounds__(SB) void k_seg_alpha(SegPlan P) {
     const int s = blockIdx.x;
     if (P.st[s].flag) return;
-    __shared__ double lds[1];
+    __shared__ double lds[1 * (SB / 64)];
     double v[1];
     sys_sum<1>(P.part_delta, P.nslices, P.sys_slice0[s], P.sys_slice0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
@@ -847,10 +850,10 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
     });
 }
 
-__global__ __launch_bounds__(64) void k_seg_beta(SegPlan P, double rtol, int32_t maxit) {
+__global__ __launch_bounds__(SB) void k_seg_beta(SegPlan P, double rtol, int32_t maxit) {
     const int s = blockIdx.x;
     if (P.st[s].flag) return;
-    __shared__ double lds[2];
+    __shared__ double lds[2 * (SB / 64)];
     double v[2];
     sys_sum<2>(P.part_res, P.nslices, P.sys_slice0[s], P.sys_slice0[s + 1], v, lds);
     if (threadIdx.x != 0) return;
@@ -1047,7 +1050,7 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     APCG_CHECK_LAUNCH("k_seg_reset");
     hipLaunchKernelGGL(k_seg_init, dim3(G), dim3(ST), 0, st, P, x0z, opts.pc, norm_pre);
     APCG_CHECK_LAUNCH("k_seg_init");
-    hipLaunchKernelGGL(k_seg_init_final, dim3(nsys), dim3(64), 0, st, P, rtol, maxit);
+    hipLaunchKernelGGL(k_seg_init_final, dim3(nsys), dim3(SB), 0, st, P, rtol, maxit);
     APCG_CHECK_LAUNCH("k_seg_init_final");
     hipLaunchKernelGGL(k_seg_zero_x, dim3(G), dim3(ST), 0, st, P);
     APCG_CHECK_LAUNCH("k_seg_zero_x");
@@ -1064,11 +1067,11 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     auto launch_iter = [&](int j) -> apcg_status {
         hipLaunchKernelGGL(seg_product, dim3(G), dim3(ST), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_seg_product");
-        hipLaunchKernelGGL(k_seg_alpha, dim3(nsys), dim3(64), 0, st, P);
+        hipLaunchKernelGGL(k_seg_alpha, dim3(nsys), dim3(SB), 0, st, P);
         APCG_CHECK_LAUNCH("k_seg_alpha");
         hipLaunchKernelGGL(k_seg_update, dim3(G), dim3(ST), 0, st, P, j & 1, norm_pre);
         APCG_CHECK_LAUNCH("k_seg_update");
-        hipLaunchKernelGGL(k_seg_beta, dim3(nsys), dim3(64), 0, st, P, rtol, maxit);
+        hipLaunchKernelGGL(k_seg_beta, dim3(nsys), dim3(SB), 0, st, P, rtol, maxit);
         APCG_CHECK_LAUNCH("k_seg_beta");
         return APCG_SUCCESS;
     };

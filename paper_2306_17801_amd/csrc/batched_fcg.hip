@@ -145,20 +145,23 @@ __device__ __forceinline__ double frow(const int32_t *__restrict__ col, const do
     return sum;
 }
 
+// Threads of the per-system kernels of the iteration (one workgroup per system).
+constexpr int FSB = 256;
+
 // The slice partials of system s (global slices sys_slice0[s] ..
 // sys_slice0[s+1] of rows slot0.. of P.part), added in a fixed order (thread
-// l takes slices l, l + 64, ..., then the wavefront tree; one 64-thread
+// l takes slices l, l + FSB, ..., then the workgroup tree; one FSB-thread
 // workgroup); the same sums whatever the tile size.  Result in thread 0.
 template <int NV>
 __device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, double (&v)[NV]) {
-    __shared__ double lds[NV];
+    __shared__ double lds[NV * (FSB / 64)];
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = P.sys_slice0[s] + (int)threadIdx.x; g < P.sys_slice0[s + 1]; g += 64) {
+    for (int g = P.sys_slice0[s] + (int)threadIdx.x; g < P.sys_slice0[s + 1]; g += FSB) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] += P.part[(size_t)(slot0 + k) * P.nslices + g];
     }
-    dev::block_sum<64, NV>(v, lds);
+    dev::block_sum<FSB, NV>(v, lds);
 }
 
 // Per-tile partials (the feature passes): tiles of system s in index order.
@@ -258,7 +261,7 @@ __global__ __launch_bounds__(FT) void k_bf_init(FPlan P, int x0_zero) {
     }
 }
 
-__global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef, const double *lmax) {
+__global__ __launch_bounds__(FSB) void k_bf_init_final(FPlan P, const float *coef, const double *lmax) {
     const int s = blockIdx.x;
     double v[3];
     fsys_sum<3>(P, s, 0, v);
@@ -271,7 +274,7 @@ __global__ __launch_bounds__(64) void k_bf_init_final(FPlan P, const float *coef
     __syncthreads();
     const double lm = jac ? 1.0 : lmax[s];
     if (!jac)
-        for (int q = threadIdx.x; q < 1024; q += 64)
+        for (int q = threadIdx.x; q < 1024; q += FSB)
             if (!(fpoly_at(cc, lm * q / 1023.0, lm) > 0.0)) atomicOr(&bad_point, 1);
     __syncthreads();
     if (threadIdx.x != 0) return;
@@ -367,7 +370,7 @@ __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
     });
 }
 
-__global__ __launch_bounds__(64) void k_bf_alpha(FPlan P) {
+__global__ __launch_bounds__(FSB) void k_bf_alpha(FPlan P) {
     const int s = blockIdx.x;
     FState *q = P.st + s;
     if (q->flag || q->restart) return;
@@ -412,7 +415,7 @@ __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
     });
 }
 
-__global__ __launch_bounds__(64) void k_bf_check(FPlan P) {
+__global__ __launch_bounds__(FSB) void k_bf_check(FPlan P) {
     const int s = blockIdx.x;
     FState *q = P.st + s;
     if (q->flag || q->restart) return;
@@ -515,7 +518,7 @@ __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o
     });
 }
 
-__global__ __launch_bounds__(64) void k_bf_beta(FPlan P) {
+__global__ __launch_bounds__(FSB) void k_bf_beta(FPlan P) {
     const int s = blockIdx.x;
     FState *q = P.st + s;
     if (q->flag) return;
@@ -866,7 +869,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     APCG_CHECK_LAUNCH("k_bf_reset");
     hipLaunchKernelGGL(k_bf_init, dim3(G), dim3(FT), 0, st, P, x0z);
     APCG_CHECK_LAUNCH("k_bf_init");
-    hipLaunchKernelGGL(k_bf_init_final, dim3(nsys), dim3(64), 0, st, P, run.coeffs, run.lmax);
+    hipLaunchKernelGGL(k_bf_init_final, dim3(nsys), dim3(FSB), 0, st, P, run.coeffs, run.lmax);
     APCG_CHECK_LAUNCH("k_bf_init_final");
     if (!x0z) {
         hipLaunchKernelGGL(k_bf_zero_x, dim3(G), dim3(FT), 0, st, P);
@@ -885,11 +888,11 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     auto launch_iter = [&](int j) -> apcg_status {
         hipLaunchKernelGGL(bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_bf_product");
-        hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(64), 0, st, P);
+        hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(FSB), 0, st, P);
         APCG_CHECK_LAUNCH("k_bf_alpha");
         hipLaunchKernelGGL(k_bf_update, dim3(G), dim3(FT), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_bf_update");
-        hipLaunchKernelGGL(k_bf_check, dim3(nsys), dim3(64), 0, st, P);
+        hipLaunchKernelGGL(k_bf_check, dim3(nsys), dim3(FSB), 0, st, P);
         APCG_CHECK_LAUNCH("k_bf_check");
         for (int d = FDEG - 1; d >= 0; --d) {
             const int stage = d == FDEG - 1 ? 0 : (d == 0 ? 2 : 1);
@@ -900,7 +903,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
             hipLaunchKernelGGL(bf_cheb, dim3(G), dim3(FT), 0, st, P, d, stage, ob1, ob2, oout);
             APCG_CHECK_LAUNCH("k_bf_cheb");
         }
-        hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(64), 0, st, P);
+        hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(FSB), 0, st, P);
         APCG_CHECK_LAUNCH("k_bf_beta");
         return APCG_SUCCESS;
     };
