@@ -621,12 +621,12 @@ __global__ __launch_bounds__(TB) void k_pcg_product_sdia(int32_t n, const int32_
 // Symmetric values (the flag behind the partner table: set by the analysis
 // for a structurally symmetric pattern, cleared by the check kernel when a
 // refill finds the values unequal): an entry left of the diagonal, (i, i - q), is read as its
-// transpose (i - q, i) from that row's slot of offset +q -- for q = 64 Ps
-// the value of the previous slice's +plane slot, carried in a register, for
-// the other offsets a load of a line the product reads anyway (the same
-// slice, or a slice a few rows back), so only the slots on and right of the
-// diagonal stream from memory.  The values are bitwise the same, and so is
-// the sum.
+// transpose (i - q, i) from that row's slot of offset +q: one load at the
+// partner slot's address, of a line the product reads anyway -- for q = 64
+// Ps the previous slice's +plane slot, which this wavefront loaded one step
+// earlier; for the other offsets the same slice or a slice a few rows back
+// -- so only the slots on and right of the diagonal stream from memory.  The
+// values are bitwise the same, and so is the sum.
 // The marching tasks of one wavefront; returns its share of p.Ap.  SYM:
 // entries left of the diagonal read as their transposes (one load each, at
 // the partner slot's address; no branches on the offsets).

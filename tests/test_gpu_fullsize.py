@@ -1,8 +1,8 @@
 """GPU parity at the workloads' full sizes, through the C ABI.
 
 1. The mixed 2D/3D batch: a batch of members of the 1024-system mixed batch
-   (seed 5) with more than 4.2 M rows in total, so that the batched kernels'
-   workgroups each own several 256-row tiles, including a 525,625-row 2D
+   (seed 5) with more than 4.2 M rows in total, run on 256-row tiles so that
+   the batched kernels' workgroups each own several tiles, including a 525,625-row 2D
    system with anisotropy 592 and members of up to 0.8 M rows.  The
    coefficients come from a network trained on the GPU (features ->
    standardisation -> network, read back from the device); one member gets a
@@ -135,7 +135,9 @@ def test_mixed_batch_full_size_parity(apcg, ctx, network):
     coef[members.index(IDENT)] = e0
     dcoef = torch.from_numpy(coef.reshape(-1)).to("cuda:0")
     torch.cuda.synchronize()
-    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    # 256-row tiles: more tiles than the grid's 8192 workgroups, so each
+    # workgroup screens and runs several tiles
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_tile_rows=256)
     nsys = len(systems)
     info = apcg.apcg_info_create(0, nsys)
     xs = [DeviceVec.zeros(s.A.n) for s in systems]

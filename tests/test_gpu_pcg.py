@@ -479,8 +479,8 @@ def with_stored_zero(A):
 @pytest.mark.parametrize("which", ["diffusion_10x16x16", "banded_1050_128", "box27_8x8x16"])
 def test_sliced_diagonals_symmetric_reads_bitwise(apcg, ctx, which):
     """With symmetric values the marching product reads each entry left of
-    the diagonal as its transpose (carried for the -plane offset, from the
-    same or an earlier slice otherwise).  A twin with one stored zero that
+    the diagonal as its transpose (for the -plane offset the previous
+    slice's +plane slot, otherwise the same or an earlier slice's).  A twin with one stored zero that
     breaks the pattern's symmetry (same operator, every slot read directly)
     gives bit for bit the same solves at the same launch shape."""
     rng = np.random.default_rng(50)
