@@ -844,7 +844,7 @@ def main():
         apcg.apcg_mat_set_spmv_config(A.h, *cfg)
         tuned = {"config": apcg.apcg_mat_get_spmv_config(A.h), "fixed": True}
     elif not args.no_autotune:
-        cfg, us = apcg.apcg_mat_autotune(A.h, ctx, 10)
+        cfg, us = apcg.apcg_mat_autotune(A.h, ctx, 40)
         tuned = {"config": cfg, "product_us": round(us, 2)}
         log(f"[bench] autotune: {cfg} {us:.1f} us")
 
