@@ -761,34 +761,34 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
         const double beta = P.st[s].beta;
         const BatchSys S = P.sys[s];
         const int64_t n = S.n;
-        const double *z = S.ws + 5 * n;
-        const double *pold = S.ws + (2 + ((parity + 1) & 1)) * n;
-        double *pnew = S.ws + (2 + (parity & 1)) * n;
-        double *w = S.ws + 4 * n;
+        const auto *z = dev::glb(S.ws + 5 * n);
+        const auto *pold = dev::glb(S.ws + (2 + ((parity + 1) & 1)) * n);
+        auto *pnew = dev::glb(S.ws + (2 + (parity & 1)) * n);
+        auto *w = dev::glb(S.ws + 4 * n);
         const int g0 = P.sys_slice0[s];
         int sl0, sl1;
         tile_slices(P, t, S.n, &sl0, &sl1);
         if (S.sval) {  // the next slice's offsets and values loaded during the current gathers
-            dev::sdia_slices<UC>(
-                S.soff, S.smask, S.sval, S.U, n, sl0 + wave, sl1, SW,
-                [&](int q) { return fma(beta, pold[q], z[q]); },
-                [&](int sl, int row, int rc, double sum) {
-                    const double pi = fma(beta, pold[rc], z[rc]);
-                    double v[1] = {0.0};
-                    if (row < n) {
-                        pnew[row] = pi;
-                        w[row] = sum;
-                        v[0] = pi * sum;
-                    }
-                    slice_store<1>(v, P.part_delta, P.nslices, g0 + sl);
-                });
+            auto u = [&](int q) { return fma(beta, pold[q], z[q]); };
+            auto f = [&](int sl, int row, int rc, double sum) {
+                const double pi = fma(beta, pold[rc], z[rc]);
+                double v[1] = {0.0};
+                if (row < n) {
+                    pnew[row] = pi;
+                    w[row] = sum;
+                    v[0] = pi * sum;
+                }
+                slice_store<1>(v, P.part_delta, P.nslices, g0 + sl);
+            };
+            dev::sdia_slices<UC>(S.soff, S.smask, S.sval, S.U, n, sl0 + wave, sl1, SW, u, f);
             return;
         }
         for (int sl = sl0 + wave; sl < sl1; sl += SW) {
             const int i = sl * 64 + lane;
             double v[1] = {0.0};
             if (i < S.n) {
-                const double sum = row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, z, pold, beta);
+                const double sum = row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, S.ws + 5 * n,
+                                                 S.ws + (2 + ((parity + 1) & 1)) * n, beta);
                 const double pi = fma(beta, pold[i], z[i]);
                 pnew[i] = pi;
                 w[i] = sum;
@@ -825,10 +825,12 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
       const double alpha = P.st[s].alpha;
       const BatchSys S = P.sys[s];
       const int64_t n = S.n;
-      double *r = S.ws;
-      const double *dinv = S.ws + n;
-      const double *p = S.ws + (2 + (parity & 1)) * n;
-      const double *w = S.ws + 4 * n;
+      auto *r = dev::glb(S.ws);
+      const auto *dinv = dev::glb(S.ws + n);
+      const auto *p = dev::glb(S.ws + (2 + (parity & 1)) * n);
+      const auto *w = dev::glb(S.ws + 4 * n);
+      auto *x = dev::glb(S.x);
+      auto *z = dev::glb(S.ws + 5 * n);
       const int g0 = P.sys_slice0[s];
       int sl0, sl1;
       tile_slices(P, t, S.n, &sl0, &sl1);
@@ -836,12 +838,12 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
         const int i = sl * 64 + lane;
         double v[2] = {0.0, 0.0};
         if (i < S.n) {
-            const double xi = fma(alpha, p[i], S.x[i]);
+            const double xi = fma(alpha, p[i], x[i]);
             const double ri = fma(-alpha, w[i], r[i]);
-            S.x[i] = xi;
+            x[i] = xi;
             r[i] = ri;
             const double zi = dinv[i] * ri;
-            S.ws[5 * n + i] = zi;  // gathered by the next product
+            z[i] = zi;  // gathered by the next product
             v[0] = zi * ri;
             v[1] = norm_pre ? zi * zi : ri * ri;
         }

@@ -340,10 +340,10 @@ __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
         const double beta = q->beta;
         const FSys S = P.sys[s];
         const int64_t n = S.n;
-        const double *z = S.ws + 2 * n;
-        const double *pold = S.ws + (3 + ((parity + 1) & 1)) * n;
-        double *pnew = S.ws + (3 + (parity & 1)) * n;
-        double *w = S.ws + 5 * n;
+        const auto *z = dev::glb(S.ws + 2 * n);
+        const auto *pold = dev::glb(S.ws + (3 + ((parity + 1) & 1)) * n);
+        auto *pnew = dev::glb(S.ws + (3 + (parity & 1)) * n);
+        auto *w = dev::glb(S.ws + 5 * n);
         int sl0, sl1;
         ftile_slices(P, t, S.n, &sl0, &sl1);
         auto u = [&](int j) { return fma(beta, pold[j], z[j]); };
@@ -396,16 +396,17 @@ __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
         const double alpha = q->alpha;
         const FSys S = P.sys[s];
         const int64_t n = S.n;
-        double *r = S.ws;
-        const double *p = S.ws + (3 + (parity & 1)) * n;
-        const double *w = S.ws + 5 * n;
+        auto *r = dev::glb(S.ws);
+        const auto *p = dev::glb(S.ws + (3 + (parity & 1)) * n);
+        const auto *w = dev::glb(S.ws + 5 * n);
+        auto *x = dev::glb(S.x);
         int sl0, sl1;
         ftile_slices(P, t, S.n, &sl0, &sl1);
         for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
             const int i = sl * 64 + lane;
             double v[1] = {0.0};
             if (i < S.n) {
-                S.x[i] = fma(alpha, p[i], S.x[i]);
+                x[i] = fma(alpha, p[i], x[i]);
                 const double ri = fma(-alpha, w[i], r[i]);
                 r[i] = ri;
                 v[0] = ri * ri;
@@ -465,10 +466,10 @@ __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o
         const bool jac = q->mode == MODE_JACOBI;
         const FSys S = P.sys[s];
         const int64_t n = S.n;
-        const double *r = S.ws, *dinv = S.ws + n, *w = S.ws + 5 * n;
-        const double *bj1 = o_b1 >= 0 ? S.ws + (6 + o_b1) * n : nullptr;
-        const double *bj2 = o_b2 >= 0 ? S.ws + (6 + o_b2) * n : nullptr;
-        double *out = o_out >= 0 ? S.ws + (6 + o_out) * n : S.ws + 2 * n;
+        const auto *r = dev::glb(S.ws), *dinv = dev::glb(S.ws + n), *w = dev::glb(S.ws + 5 * n);
+        const auto *bj1 = o_b1 >= 0 ? dev::glb(S.ws + (6 + o_b1) * n) : nullptr;
+        const auto *bj2 = o_b2 >= 0 ? dev::glb(S.ws + (6 + o_b2) * n) : nullptr;
+        auto *out = dev::glb(o_out >= 0 ? S.ws + (6 + o_out) * n : S.ws + 2 * n);
         const double s2 = 2.0 / q->lmax, cj = q->c[j], cd = q->c[FDEG];
         int sl0, sl1;
         ftile_slices(P, t, S.n, &sl0, &sl1);

@@ -203,11 +203,33 @@ __device__ bool fcg_check(FcgState *st, const double *part_res, int G, int parit
     return status != 0;
 }
 
+// Rows [ch.lo, ch.hi) of a workgroup (ch.lo a multiple of 64) as the
+// row-per-thread loop visits them -- thread t takes rows ch.lo + t,
+// ch.lo + t + TBF, ... -- with f(i, (A u)_i) for each row i < n.  L = 5/7/8
+// (an 8-wide sliced-diagonal copy): each wavefront walks its slices with the
+// next slice's loads in flight (dev::sdia_slices), reading the entries left
+// of the diagonal as their transposes while the copy's values are
+// symmetric; otherwise dev::mat_row.  Same sums, same order, same bits.
+template <int L, typename FU, typename FF>
+__device__ __forceinline__ void fcg_rows(int32_t n, const dev::RowMat &M, dev::Chunk ch, FU u, FF f) {
+    if constexpr (L == 5 || L == 7 || L == 8) {
+        const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        const int sb = (int)(ch.lo >> 6) + wave, se = (int)((ch.hi + 63) >> 6);
+        auto g = [&](int, int row, int, double a) {
+            if (row < n) f((int64_t)row, a);
+        };
+        if (dev::sdia_sym8(M.soff, n)) dev::sdia_slices<L, true>(M.soff, M.smask, M.sval, M.U, n, sb, se, TBF / 64, u, g);
+        else dev::sdia_slices<L>(M.soff, M.smask, M.sval, M.U, n, sb, se, TBF / 64, u, g);
+    } else {
+        for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) f(i, dev::mat_row<L>(M, n, i, u));
+    }
+}
+
 // One Clenshaw step.  stage: 0 = first (j = DEG-1), 1 = middle, 2 = last
 // (forms z and the partials of r.z and z.w).  check != 0 (inside the
 // iteration): the first step first runs the test above for the iteration of
 // the given parity.
-// L: 0 = CSR products, 5/7/8/16/32 = the sliced-diagonal copy (dev::mat_row).
+// L: 0 = CSR products, 5/7/8/16/32 = the sliced-diagonal copy.
 template <int L>
 __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, dev::RowMat M,
                                               const double *__restrict__ r, const double *__restrict__ dinv,
@@ -221,25 +243,28 @@ __global__ __launch_bounds__(TBF) void k_cheb(int32_t n, dev::RowMat M,
     const double cj = st->c[j], cd = st->c[DEG];
     const dev::Chunk ch = dev::block_chunk(n, per_block);
     double v[2] = {0.0, 0.0};
-    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
-        const double vi = dinv[i] * r[i];
-        double res;
-        if (stage == 0) {  // b_{d-1} = c_{d-1} v + 2 c_d Y v
-            const double av = dev::mat_row<L>(M, n, i, [&](int q) { return dinv[q] * r[q]; });
+    if (stage == 0) {  // b_{d-1} = c_{d-1} v + 2 c_d Y v
+        fcg_rows<L>(n, M, ch, [&](int q) { return dinv[q] * r[q]; }, [&](int64_t i, double av) {
+#pragma clang fp contract(off)
+            const double vi = dinv[i] * r[i];
             const double yv = s2 * dinv[i] * av - vi;
-            res = fma(2.0 * cd, yv, cj * vi);
-        } else {
-            const double au = dev::mat_row<L>(M, n, i, [&](int q) { return bj1[q]; });
+            out[i] = fma(2.0 * cd, yv, cj * vi);
+        });
+    } else {
+        fcg_rows<L>(n, M, ch, [&](int q) { return bj1[q]; }, [&](int64_t i, double au) {
+#pragma clang fp contract(off)
+            const double vi = dinv[i] * r[i];
             const double yu = s2 * dinv[i] * au - bj1[i];
             const double b2v = bj2 ? bj2[i] : cd * vi;  // b_{d} = c_d v is not stored
+            double res;
             if (stage == 1) res = fma(2.0, yu, cj * vi) - b2v;
             else {
                 res = cj * vi + yu - b2v;
                 v[0] = fma(r[i], res, v[0]);
                 v[1] = fma(res, w[i], v[1]);
             }
-        }
-        out[i] = res;
+            out[i] = res;
+        });
     }
     if (stage == 2)
         dev::store_partials<TBF, 2>(v, partials + (size_t)S_RZ * kMaxBlocks, gridDim.x,
@@ -277,13 +302,12 @@ __global__ __launch_bounds__(TBF) void k_fcg_product(int32_t n, dev::RowMat M,
     if (status) return;
     const dev::Chunk ch = dev::block_chunk(n, per_block);
     double v[1] = {0.0};
-    for (int64_t i = ch.lo + threadIdx.x; i < ch.hi; i += TBF) {
-        const double sum = dev::mat_row<L>(M, n, i, [&](int q) { return pdir_f(z[q], beta, pold[q]); });
+    fcg_rows<L>(n, M, ch, [&](int q) { return pdir_f(z[q], beta, pold[q]); }, [&](int64_t i, double sum) {
         const double pi = pdir_f(z[i], beta, pold[i]);
         pnew[i] = pi;
         w[i] = sum;
         v[0] = fma(pi, sum, v[0]);
-    }
+    });
     dev::store_partials<TBF, 1>(v, partials + (size_t)S_DELTA * kMaxBlocks, gridDim.x,
                                 dev::xcd_block(blockIdx.x, gridDim.x));
 }

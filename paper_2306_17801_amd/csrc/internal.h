@@ -610,61 +610,127 @@ __device__ __forceinline__ double sdia_row(const int32_t *__restrict__ soff, con
     return sum;
 }
 
+// Pointers into the constant address space: loads through them are scalar
+// (one per wavefront, into SGPRs).  Only for tables no kernel writes while
+// the reading kernel runs.
+using kc32 = const __attribute__((address_space(4))) int32_t;
+using kc64 = const __attribute__((address_space(4))) uint64_t;
+
+// Pointers into the global address space.  A pointer read from memory (a
+// batch's per-system table) is generic, and loads through it are flat
+// instructions, which count in lgkmcnt as well as vmcnt: waiting for a
+// scalar load would then also wait for every vector load in flight.  Through
+// these the loads and stores are global ones.
+template <class T>
+using glob_t = __attribute__((address_space(1))) T;
+template <class T>
+__device__ __forceinline__ glob_t<T> *glb(T *p) {
+    return (glob_t<T> *)p;
+}
+template <class T>
+__device__ __forceinline__ const glob_t<T> *glb(const T *p) {
+    return (const glob_t<T> *)p;
+}
+
 // The rows of slices sl_begin, sl_begin + step, ... < sl_end of a matrix's
 // sliced-diagonal copy (8 offset slots per slice, UC <= 8 walked), walked by
 // one wavefront: for each slice, f(sl, row, rc, sum) with sum = sum_k a_k
 // u(j_k) over the row's entries (column order, one FMA each: the sums of
-// sdia_row) and rc = min(row, n - 1).  The next slice's offsets, masks and
-// values are loaded before the current slice's gathers are issued, so they
-// are in flight together.  sl must be uniform across the wavefront.
-template <int UC, typename FU, typename FF>
+// sdia_row) and rc = min(row, n - 1).  Offsets and masks are scalar loads;
+// the gathers read row + offset clamped into [0, n) (an absent entry's
+// product is dropped by a select on the mask, which is only needed then),
+// and the next slice's values are loaded while the current slice's gathers
+// are in flight.  sl must be uniform across the wavefront.
+// SYM (the copy's value-symmetry flag set): an entry left of the diagonal,
+// (i, i - q), is read as its transpose (i - q, i) from row i - q's slot of
+// offset +q, whose index the copy's partner table holds (the table follows
+// the offsets; low byte for the lanes whose transpose lies q/64 slices back,
+// next byte for the lanes one slice further back), so only the slots on and
+// right of the diagonal stream from memory and the others are lines read a
+// few slices earlier.  Those addresses need the next slice's offsets, so
+// the next values are issued after the current gathers, once the offsets
+// (requested before the gathers) are in.  Same bits, so the same sums.
+template <int UC, bool SYM = false, typename FU, typename FF>
 __device__ __forceinline__ void sdia_slices(const int32_t *__restrict__ soff, const uint64_t *__restrict__ smask,
                                             const double *__restrict__ sval, int U, int64_t n, int sl_begin,
                                             int sl_end, int step, FU u, FF f) {
     const int lane = threadIdx.x & 63;
-    int on[UC];
-    uint64_t mn[UC];
+    const int64_t nsl = (n + 63) >> 6;
+    const int nm1 = (int)n - 1;
+    const glob_t<double> *sv = glb(sval);
+    int on[UC], qn[UC];
     double an[UC];
-    auto load = [&](int sl) {
-        const int32_t *o = soff + (int64_t)sl * 8;
-        const uint64_t *m = smask + (int64_t)sl * 8;
-        const double *v = sval + (int64_t)sl * U * 64 + lane;
+    auto offs = [&](int sl) {
+        const kc32 *o = (const kc32 *)(soff + (int64_t)sl * 8);
+        const kc32 *q = (const kc32 *)(soff + (nsl + sl) * 8);
 #pragma unroll
         for (int k = 0; k < UC; ++k) {
             on[k] = o[k];
-            mn[k] = m[k];
-            an[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
+            if constexpr (SYM) qn[k] = q[k];
         }
     };
-    if (sl_begin < sl_end) load(sl_begin);
+    auto vals = [&](int sl) {
+        const glob_t<double> *v = sv + (int64_t)sl * U * 64 + lane;
+#pragma unroll
+        for (int k = 0; k < UC; ++k) {
+            if constexpr (SYM) {
+                // own slot, or the transpose's: row + offset left of the
+                // diagonal, clamped at 0 for an absent entry (any slot of a
+                // slice at or before this one is a valid address; its value
+                // is dropped); bit arithmetic, no branch per slot, so the
+                // slice's loads stay one straight-line batch
+                const int lowm = on[k] >> 31;  // all ones left of the diagonal
+                const int r = max(sl * 64 + lane + (on[k] & lowm), 0);
+                const int ps = (lane >= ((-on[k]) & 63) ? qn[k] : (qn[k] >> 8)) & 0xff;
+                const int slot = (ps & lowm) | ((k < U ? k : U - 1) & ~lowm);
+                an[k] = sv[((int64_t)(r >> 6) * U + slot) * 64 + (r & 63)];
+            } else {
+                an[k] = __builtin_nontemporal_load(v + (int64_t)(k < U ? k : U - 1) * 64);
+            }
+        }
+    };
+    if (sl_begin < sl_end) {
+        offs(sl_begin);
+        vals(sl_begin);
+    }
     for (int sl = sl_begin; sl < sl_end; sl += step) {
         int oc[UC];
-        uint64_t mc[UC];
         double ac[UC];
+        uint64_t mc[UC];
+        const kc64 *m = (const kc64 *)(smask + (int64_t)sl * 8);
 #pragma unroll
         for (int k = 0; k < UC; ++k) {
             oc[k] = on[k];
-            mc[k] = mn[k];
             ac[k] = an[k];
+            mc[k] = m[k];
         }
-        if (sl + step < sl_end) load(sl + step);  // in flight during the gathers below
+        const bool more = sl + step < sl_end;
+        if (more) {
+            offs(sl + step);
+            if constexpr (!SYM) vals(sl + step);  // in flight during the gathers below
+        }
         const int row = sl * 64 + lane;
-        const int rc = row < n ? row : (int)n - 1;
+        const int rc = row < n ? row : nm1;
         double g[UC];
-        bool in[UC];
 #pragma unroll
-        for (int k = 0; k < UC; ++k) {
-            in[k] = (mc[k] >> lane) & 1ull;
-            g[k] = u(in[k] ? row + oc[k] : rc);
+        for (int k = 0; k < UC; ++k) g[k] = u(min(max(row + oc[k], 0), nm1));
+        if constexpr (SYM) {
+            if (more) vals(sl + step);
         }
         double sum = 0.0;
 #pragma unroll
         for (int k = 0; k < UC; ++k) {
             const double t = fma(ac[k], g[k], sum);
-            sum = in[k] ? t : sum;
+            sum = ((mc[k] >> lane) & 1ull) ? t : sum;
         }
         f(sl, row, rc, sum);
     }
+}
+
+// Whether a sliced-diagonal copy with 8 offset slots per slice may be read
+// with its transposes (the value-symmetry flag after the partner table).
+__device__ __forceinline__ bool sdia_sym8(const int32_t *soff, int64_t n) {
+    return *(const kc32 *)(soff + ((n + 63) >> 6) * 16) != 0;
 }
 
 // A matrix as the row-per-thread kernels read it: the CSR arrays, and the

@@ -40,6 +40,7 @@ def run_batch(apcg, ctx, systems, rtol, maxit, x0s=None, sdia=(), **opt):
             run_batch.switched.append(i)
         except apcg.ApcgError:
             pass
+    run_batch.mats = As
     bs = [DeviceVec(s.b) for s in systems]
     xs = [DeviceVec(np.zeros(s.A.n) if x0s is None else x0s[i]) for i, s in enumerate(systems)]
     if x0s is None:
@@ -168,6 +169,56 @@ def test_segmented_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
         assert np.array_equal(xa, xb)
     for s, r, x in zip(systems, r_sd, x_sd):
         ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=5000)
+        assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
+
+
+def unsymmetric_twin(A, frac=0.3):
+    """A copy of A with the same (symmetric) pattern whose values are no
+    longer symmetric: one entry left of the diagonal, about frac of the way
+    down the rows, changed in its last bits."""
+    T = P.CSR(n=A.n, rowptr=A.rowptr.copy(), col=A.col.copy(), val=A.val.copy())
+    for i in range(int(frac * A.n), A.n):
+        lo = [e for e in range(A.rowptr[i], A.rowptr[i + 1]) if A.col[e] < i]
+        if lo:
+            T.val[lo[0]] *= 1.0 + 2.0 ** -40
+            return T
+    raise AssertionError("no entry left of the diagonal")
+
+
+def sliced_diagonal_batch():
+    """Symmetric 2D and 3D systems spanning several tiles (offsets of one, a
+    grid row and a plane, whose columns lie in the same tile or an earlier
+    one), and twins whose values are not symmetric."""
+    rng = np.random.default_rng(63)
+    sym = [P._lognormal_system(rng, 2, 75, 1.0, 3.0), P._lognormal_system(rng, 3, 17, 1.0, 1.0),
+           P._lognormal_system(rng, 2, 130, 1.5, 1.0), P._lognormal_system(rng, 3, 22, 0.7, 5.0)]
+    twins = [P.System(A=unsymmetric_twin(s.A), b=s.b) for s in sym[:2]]
+    return sym + twins, [1] * len(sym) + [0] * len(twins)
+
+
+@pytest.mark.parametrize("mode", [0, 1])
+def test_segmented_sliced_diagonals_multi_tile_bitwise(apcg, ctx, mode):
+    """The tile product walks each slice of the sliced-diagonal copy with
+    scalar loads of its offsets and masks and gathers at row + offset clamped
+    into the system (an absent entry's product is dropped by the mask): bit
+    for bit the all-CSR batch on 2D and 3D systems over several tiles, at two
+    tile sizes, with symmetric values or not.  The copy's value-symmetry flag
+    is as the refill's check finds it: set for the symmetric matrices,
+    cleared for the twins."""
+    systems, flags = sliced_diagonal_batch()
+    print(f"case batched seg sliced diagonals multi-tile mode={mode}", flush=True)
+    r_csr, x_csr = run_batch(apcg, ctx, systems, 1e-10, 20000, batch_schedule=2, mode=mode)
+    for tr in (256, 2048):
+        r_sd, x_sd = run_batch(apcg, ctx, systems, 1e-10, 20000, sdia=range(len(systems)), batch_schedule=2,
+                               mode=mode, batch_tile_rows=tr)
+        assert run_batch.switched == list(range(len(systems)))
+        got = [apcg.apcg_mat_get_sdia_info(a.h)["values_symmetric"] for a in run_batch.mats]
+        assert got == flags
+        for a, b2, xa, xb in zip(r_csr, r_sd, x_csr, x_sd):
+            assert a == b2
+            assert np.array_equal(xa, xb)
+    for s, r, x in zip(systems[:4], r_csr, x_csr):
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=20000)
         assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
 
 

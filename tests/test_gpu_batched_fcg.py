@@ -88,6 +88,7 @@ def run_batch(apcg, ctx, cases, rtol, maxit, x0=None, fopts=None, sdia=False, **
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
     As = [DeviceCSR(c[0]) for c in cases]
+    run_batch.mats = As
     run_batch.switched = []
     if sdia:  # every matrix whose pattern allows it on the sliced-diagonal schedule
         for i, a in enumerate(As):
@@ -287,6 +288,46 @@ def test_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
         assert a == b2
         assert np.array_equal(xa, xb)
     check_against_oracle(apcg, cases, r_sd, x_sd, 1e-10, 20000)
+
+
+def unsymmetric_twin(A, frac=0.3):
+    """A copy of A with the same (symmetric) pattern whose values are no
+    longer symmetric: one entry left of the diagonal changed in its last
+    bits."""
+    T = P.CSR(n=A.n, rowptr=A.rowptr.copy(), col=A.col.copy(), val=A.val.copy())
+    for i in range(int(frac * A.n), A.n):
+        lo = [e for e in range(A.rowptr[i], A.rowptr[i + 1]) if A.col[e] < i]
+        if lo:
+            T.val[lo[0]] *= 1.0 + 2.0 ** -40
+            return T
+    raise AssertionError("no entry left of the diagonal")
+
+
+def test_sliced_diagonals_multi_tile_bitwise(apcg, ctx):
+    """The tile product and every Clenshaw step walk the sliced-diagonal copy
+    (scalar loads of offsets and masks, gathers clamped into the system):
+    bit for bit the all-CSR batch on 2D and 3D systems over several tiles,
+    symmetric or with unsymmetric values, at two tile sizes; the oracle's
+    bar holds."""
+    rng = np.random.default_rng(64)
+    cases = []
+    for dim, side, sigma, aniso in [(2, 75, 1.0, 3.0), (3, 17, 1.0, 1.0), (2, 110, 1.5, 1.0), (3, 21, 0.7, 5.0)]:
+        s = P._lognormal_system(rng, dim, side, sigma, aniso)
+        lm = oracle.gershgorin(s.A)[1]
+        cases.append((s.A, s.b, cheb_coeffs(lm, lm / 40).astype(np.float32), lm, f"sym{dim}d_{side}"))
+    for A, b, c, lm, name in cases[:2]:
+        cases.append((unsymmetric_twin(A), b, c, lm, name + "_twin"))
+    flags = [1, 1, 1, 1, 0, 0]
+    print("case batched fcg sliced diagonals multi-tile", flush=True)
+    r_csr, x_csr = run_batch(apcg, ctx, cases, 1e-10, 20000)
+    for tr in (256, 2048):
+        r_sd, x_sd = run_batch(apcg, ctx, cases, 1e-10, 20000, sdia=True, batch_tile_rows=tr)
+        assert run_batch.switched == list(range(len(cases)))
+        assert [apcg.apcg_mat_get_sdia_info(a.h)["values_symmetric"] for a in run_batch.mats] == flags
+        for a, b2, xa, xb in zip(r_csr, r_sd, x_csr, x_sd):
+            assert a == b2
+            assert np.array_equal(xa, xb)
+    check_against_oracle(apcg, cases[:4], r_csr[:4], x_csr[:4], 1e-10, 20000)
 
 
 @pytest.mark.parametrize("sdia", [False, True])

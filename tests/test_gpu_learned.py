@@ -480,6 +480,37 @@ def test_fcg_bitwise_repeatable_and_mode_independent(apcg, ctx):
         assert np.array_equal(x, outs[0][1])
 
 
+def _with_stored_zero(A):
+    """A with one explicitly stored zero at (0, n-1) and none at (n-1, 0): the
+    same operator, a structurally unsymmetric pattern."""
+    rowptr = A.rowptr.copy()
+    rowptr[1:] += 1
+    e = int(A.rowptr[1])
+    col = np.insert(A.col, e, A.n - 1).astype(np.int32)
+    val = np.insert(A.val, e, 0.0)
+    return P.CSR(n=A.n, rowptr=rowptr, col=col, val=val)
+
+
+@pytest.mark.parametrize("dim,side", [(2, 75), (3, 19)])
+def test_fcg_transposed_reads_bitwise(apcg, ctx, dim, side):
+    """With symmetric values the FCG product and Clenshaw steps read each
+    entry left of the diagonal as its transpose; a twin with one stored zero
+    that breaks the pattern's symmetry (the same operator, every slot read
+    directly) gives bit for bit the same solve, and the oracle's bar holds."""
+    s = P._lognormal_system(np.random.default_rng(40 + dim), dim, side, 1.0, 2.0)
+    T = _with_stored_zero(s.A)
+    lmax = oracle.gershgorin(s.A)[1]
+    c = cheb_iteration_coeffs(lmax, lmax / 40).astype(np.float32)
+    print(f"case fcg transposed reads {dim}d side {side}", flush=True)
+    r_s, x_s = gpu_fcg(apcg, ctx, s.A, s.b, c, lmax, 1e-10, 5000)
+    r_t, x_t = gpu_fcg(apcg, ctx, T, s.b, c, lmax, 1e-10, 5000)
+    assert r_s == r_t
+    assert np.array_equal(x_s, x_t)
+    ref = oracle.fcg_poly(s.A, s.b, c.astype(np.float64), lmax, rtol=1e-10, maxit=5000)
+    assert r_s["status"] == ref.status and abs(r_s["iterations"] - ref.its) <= 1
+    assert rel(x_s, ref.x) <= 1e-9
+
+
 def test_learned_solve_equals_its_steps(apcg, ctx):
     """apcg_ksp_solve_learned = features -> standardise -> forward ->
     apcg_ksp_solve_fcg_poly started from the iterate of the feature run's 12
