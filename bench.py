@@ -261,6 +261,7 @@ def bench_batch(apcg, torch, reps, only=None, tile_rows=0):
     out["batched_solves_per_s"] = round(nsys / best[0], 2)
     out["converged"] = sum(1 for r in res if r["status"] == apcg.APCG_SOLVE_CONVERGED)
     out["iterations_min_max"] = [min(r["iterations"] for r in res), max(r["iterations"] for r in res)]
+    out["roofline"] = batch_roofline(apcg, systems, As, res, best[0], o)
     log(f"[bench] batch: {out} ")
     if only is not None:  # one schedule alone (profiling runs): no per-solve loop
         apcg.apcg_info_destroy(info)
@@ -290,6 +291,36 @@ def bench_batch(apcg, torch, reps, only=None, tile_rows=0):
     apcg.apcg_ctx_synchronize(ctx)
     apcg.apcg_ctx_destroy(ctx)
     return out
+
+
+def batch_roofline(apcg, systems, As, res, seconds, opts):
+    """Algorithmic HBM bytes of a segmented batched solve over its wall time:
+    for every system, its iterations times the bytes of one tile product
+    (sliced-diagonal copy: 512 U + 96 per 64-row slice for the values,
+    offsets and masks, CSR: 12 nnz + 4 (n + 1); both + 32 n for z, p_old read
+    and p, w written) and one tile update (64 n: x, r, p, w, D^-1 read; x, r,
+    z written).  The per-system kernels' partial sums are not counted.  None
+    for the persistent schedule (another kernel and byte count)."""
+    if opts.batch_schedule != 2:
+        return None
+    total = 0
+    row_its = 0
+    for s, a, r in zip(systems, As, res):
+        n, its = s.A.n, r["iterations"]
+        nsl = (n + 63) // 64
+        cfg = apcg.apcg_mat_get_spmv_config(a.h)
+        info = apcg.apcg_mat_get_sdia_info(a.h) if cfg["schedule"] == apcg.APCG_SPMV_SDIA else None
+        if info and info["state"] == 1 and info["offset_slots"] == 8:
+            prod = nsl * (512 * info["value_slots"] + 96) + 32 * n
+        else:
+            prod = 12 * s.A.nnz + 4 * (n + 1) + 32 * n
+        total += its * (prod + 64 * n)
+        row_its += its * n
+    achieved = total / seconds / 1e9
+    return {"bound": "hbm", "row_iterations": row_its, "algorithmic_bytes": total, "achieved": round(achieved, 1),
+            "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "note": "whole batched solve: wall time includes the per-system kernels and the iterations where few "
+                    "systems are still running"}
 
 
 def device_system(fields, device=0):

@@ -73,9 +73,8 @@ __device__ __forceinline__ void block_allreduce(double (&v)[NV], double *lds) {
 // Row i of A p with p_j = d_j r_j + beta pold_j formed while gathering; rows
 // of up to 8 entries issue every gather before the first multiply-add.  Both
 // branches add in column-storage order.
-__device__ __forceinline__ double row_product(const int32_t *__restrict__ col, const double *__restrict__ val, int s,
-                                              int e, int row, const double *__restrict__ dinv,
-                                              const double *__restrict__ r, const double *__restrict__ pold,
+template <class PI, class PD>
+__device__ __forceinline__ double row_product(PI col, PD val, int s, int e, int row, PD dinv, PD r, PD pold,
                                               double beta) {
     const int len = e - s;
     double sum = 0.0;
@@ -137,20 +136,22 @@ template <int TB>
 __device__ void solve_one(const BatchSys &S, double rtol, int32_t maxit, int x0_zero, int pc, int norm_pre,
                           apcg_solve_info *out, double *lds) {
     const int n = S.n;
-    double *r = S.ws, *dinv = S.ws + n, *pbuf0 = S.ws + 2 * (int64_t)n, *pbuf1 = S.ws + 3 * (int64_t)n;
-    double *w = S.ws + 4 * (int64_t)n;
-    double *x = S.x;
-    const double *b = S.b;
+    // global pointers: the system's pointers come from a table in memory
+    // (generic to the compiler), and flat accesses would also count in lgkmcnt
+    auto *r = dev::glb(S.ws), *dinv = dev::glb(S.ws + n), *pbuf0 = dev::glb(S.ws + 2 * (int64_t)n);
+    auto *pbuf1 = dev::glb(S.ws + 3 * (int64_t)n), *w = dev::glb(S.ws + 4 * (int64_t)n), *x = dev::glb(S.x);
+    const auto *b = dev::glb(S.b), *val = dev::glb(S.val);
+    const auto *rowptr = dev::glb(S.rowptr), *col = dev::glb(S.col);
 
     // setup: dinv, r0, p_old = 0, rho0, reference and residual norms
     double v4[4] = {0.0, 0.0, 0.0, 0.0};  // z.r, residual^2, reference^2, bad diagonals
     for (int i = threadIdx.x; i < n; i += TB) {
-        const int s = S.rowptr[i], e = S.rowptr[i + 1];
+        const int s = rowptr[i], e = rowptr[i + 1];
         double diag = 0.0, ax = 0.0;
         bool found = false;
         for (int k = s; k < e; ++k) {
-            const int j = S.col[k];
-            const double a = S.val[k];
+            const int j = col[k];
+            const double a = val[k];
             if (j == i) {
                 diag = a;
                 found = true;
@@ -199,11 +200,12 @@ __device__ void solve_one(const BatchSys &S, double rtol, int32_t maxit, int x0_
 
     double beta = 0.0;
     for (int k = 1; !status; ++k) {
-        const double *pold = (k & 1) ? pbuf0 : pbuf1;
-        double *pnew = (k & 1) ? pbuf1 : pbuf0;
+        const auto *pold = (k & 1) ? pbuf0 : pbuf1;
+        auto *pnew = (k & 1) ? pbuf1 : pbuf0;
         double d1[1] = {0.0};
         for (int i = threadIdx.x; i < n; i += TB) {
-            const double sum = row_product(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, dinv, r, pold, beta);
+            const double sum = row_product<decltype(col), decltype(pold)>(col, val, rowptr[i], rowptr[i + 1], i,
+                                                                          dinv, r, pold, beta);
             const double pi = pdir_b(dinv[i], r[i], beta, pold[i]);
             pnew[i] = pi;
             w[i] = sum;
