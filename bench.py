@@ -269,7 +269,14 @@ def bench_batch(apcg, torch, reps, only=None, tile_rows=0):
         apcg.apcg_ctx_destroy(ctx)
         return out
 
-    # plain path: one graph-mode solve per system, 8 contexts round robin
+    # plain path: one graph-mode solve per system, 8 contexts round robin, on
+    # the sliced-diagonal copies (a batched pick of CSR reads moved the
+    # members to the row schedule)
+    for a in As:
+        try:
+            apcg.apcg_mat_set_spmv_config(a.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+        except apcg.ApcgError:
+            pass
     kids = apcg.apcg_ctx_fork(ctx, 8)
     plain = apcg.apcg_solve_opts_default(x0_is_zero=1)
     infos = apcg.apcg_info_create(0, nsys)
@@ -586,6 +593,9 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, b
         apcg.apcg_ksp_solve_batched_learned(ctx, hA, hb, hx, 1e-8, maxit, pc.params, pc.mean, pc.std, opts_l,
                                             None, info)
 
+    # the tuning table's entry puts the members back on the layout the
+    # learned solve's pick reads (the Jacobi tuning may have changed it)
+    apcg.apcg_batch_autotune(ctx, hA, hb, hx, 1, 4)
     dt = timed(lambda: learned(50000), lambda: learned(0))
     res = summary("batched_learned", dt)
     out["batched_learned_fallbacks"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_FALLBACK)
@@ -600,11 +610,16 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, b
         def bj(maxit):
             apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-8, maxit, opts_j, info)
 
+        apcg.apcg_batch_autotune(ctx, hA, hb, hx, 0, 8)  # from the table: the layout of this pick
         dt = timed(lambda: bj(50000), lambda: bj(0))
         res = summary("batched_jacobi", dt)
         out["batched_jacobi_iterations_max"] = max(r["iterations"] for r in res)
         out["batched_learned_speedup_vs_batched_jacobi"] = round(out["batched_jacobi_ms"] / out["batched_learned_ms"], 3)
         log(f"[bench] mixed batched Jacobi: {1000 * dt:.1f} ms")
+    # the plain path on the sliced-diagonal copies again (a batched pick of
+    # CSR reads moves the members to the row schedule)
+    with ThreadPoolExecutor(workers) as ex:
+        list(ex.map(to_sdia, As))
     kids = apcg.apcg_ctx_fork(ctx, 8)
     infos = apcg.apcg_info_create(0, nsys)
 

@@ -617,13 +617,20 @@ typedef struct apcg_batch_config {
  * sliced-diagonal copies), kind 1 apcg_ksp_solve_batched_fcg_poly with the
  * constant polynomial (its eight Clenshaw steps still run; segmented
  * configurations only): `iters` iterations with rtol 0 on ctx's stream, HIP
- * events, the better of two runs after a warm-up.  x is used as scratch (its
+ * events, the better of two runs after a warm-up.  That window has every
+ * system running; over a whole solve the last systems run alone, latency-
+ * bound, where the sliced-diagonal reads are faster, so a configuration on
+ * the CSR arrays is picked only when it beats the best sliced-diagonal one
+ * by more than 10% in the window.  x is used as scratch (its
  * contents are overwritten).  The result goes to the tuning table under
  *   "batch|<arch>|pcg|fcg|m<longest row>|r<round(4 nnz/n)>|s<log2 systems>|
  *    n<log2 rows>|x<log2 largest system>"
  * and a later call with the same key applies it without timing
  * (*from_cache = 1).  With sdia = 1 the members whose pattern allows it are
- * left on APCG_SPMV_SDIA (their schedules are restored otherwise).  The
+ * left on APCG_SPMV_SDIA; with sdia = 0 the members' schedules are restored,
+ * except that a member that was on APCG_SPMV_SDIA is put on
+ * APCG_SPMV_ROWGROUP (one lane per row), so that the batch reads the CSR
+ * arrays.  The
  * caller passes *best's fields to apcg_solve_opts (batch_schedule,
  * batch_block_size, batch_tile_rows).  Blocks the host. */
 apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b, const apcg_vec *x,

@@ -104,9 +104,9 @@ __device__ __forceinline__ double row_product(PI col, PD val, int s, int e, int 
 // Row i of A p with p_j = z_j + beta pold_j (z = D^-1 r as stored by the
 // segmented schedule; the same rounded value as d_j r_j above, so the sums are
 // bitwise those of row_product).
-__device__ __forceinline__ double row_product_z(const int32_t *__restrict__ col, const double *__restrict__ val,
-                                                int s, int e, int row, const double *__restrict__ z,
-                                                const double *__restrict__ pold, double beta) {
+__device__ __forceinline__ double row_product_z(const dev::glob_t<int32_t> *col, const dev::glob_t<double> *val,
+                                                int s, int e, int row, const dev::glob_t<double> *z,
+                                                const dev::glob_t<double> *pold, double beta) {
     const int len = e - s;
     double sum = 0.0;
     if (len <= 8) {
@@ -789,8 +789,8 @@ __global__ __launch_bounds__(ST) void k_seg_product(SegPlan P, int parity) {
             const int i = sl * 64 + lane;
             double v[1] = {0.0};
             if (i < S.n) {
-                const double sum = row_product_z(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, S.ws + 5 * n,
-                                                 S.ws + (2 + ((parity + 1) & 1)) * n, beta);
+                const auto *rp = dev::glb(S.rowptr);
+                const double sum = row_product_z(dev::glb(S.col), dev::glb(S.val), rp[i], rp[i + 1], i, z, pold, beta);
                 const double pi = fma(beta, pold[i], z[i]);
                 pnew[i] = pi;
                 w[i] = sum;

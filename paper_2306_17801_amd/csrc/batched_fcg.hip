@@ -121,7 +121,7 @@ __device__ __forceinline__ void for_active_tiles(const FPlan &P, Keep keep, Body
 // sum_k a_k u(col_k) over row i's entries; rows of up to 8 entries issue all
 // gathers first (padded slots gather the row's own entry and are not added)
 template <typename F>
-__device__ __forceinline__ double frow(const int32_t *__restrict__ col, const double *__restrict__ val, int s, int e,
+__device__ __forceinline__ double frow(const dev::glob_t<int32_t> *col, const dev::glob_t<double> *val, int s, int e,
                                        int row, F u) {
     const int len = e - s;
     double sum = 0.0;
@@ -364,7 +364,8 @@ __global__ __launch_bounds__(FT) void k_bf_product(FPlan P, int parity) {
         for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
             const int i = sl * 64 + lane;
             const int rc = i < n ? i : (int)n - 1;
-            const double sum = i < n ? frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u) : 0.0;
+            const auto *rp = dev::glb(S.rowptr);
+            const double sum = i < n ? frow(dev::glb(S.col), dev::glb(S.val), rp[i], rp[i + 1], i, u) : 0.0;
             finish(sl, i, rc, sum);
         }
     });
@@ -512,8 +513,10 @@ __global__ __launch_bounds__(FT) void k_bf_cheb(FPlan P, int j, int stage, int o
             const int i = sl * 64 + lane;
             double au = 0.0;
             if (!jac && i < n)
-                au = stage == 0 ? frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u0)
-                                : frow(S.col, S.val, S.rowptr[i], S.rowptr[i + 1], i, u1);
+                au = stage == 0 ? frow(dev::glb(S.col), dev::glb(S.val), dev::glb(S.rowptr)[i],
+                                       dev::glb(S.rowptr)[i + 1], i, u0)
+                                : frow(dev::glb(S.col), dev::glb(S.val), dev::glb(S.rowptr)[i],
+                                       dev::glb(S.rowptr)[i + 1], i, u1);
             finish(sl, i, au);
         }
     });

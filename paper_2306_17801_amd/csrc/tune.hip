@@ -368,6 +368,10 @@ std::string batch_key(const std::string &arch, int kind, int32_t nsys, const apc
            std::to_string(lg(nmax));
 }
 
+// A CSR candidate of the batched autotuner must beat the best
+// sliced-diagonal one by this factor of its window time.
+constexpr double kCsrMargin = 0.9;
+
 }  // namespace
 
 extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
@@ -385,7 +389,9 @@ extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apc
         if ((s = device_arch(ctx->device, &arch))) return s;
         const std::string key = batch_key(arch, kind, nsys, A);
         // the members' product schedules, restored unless the sliced-diagonal
-        // copies win
+        // copies win; a member the caller had put on the sliced-diagonal
+        // schedule goes to the CSR row schedule when CSR reads are timed or
+        // win (the batched kernels read the copy of any member on it)
         std::vector<apcg_spmv_config> saved(nsys);
         for (int32_t i = 0; i < nsys; ++i) saved[i] = A[i]->cfg;
         auto set_sdia = [&](bool on) {
@@ -393,6 +399,7 @@ extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apc
             for (int32_t i = 0; i < nsys; ++i) {
                 if (!on) {
                     A[i]->cfg = saved[i];
+                    if (A[i]->cfg.schedule == APCG_SPMV_SDIA) A[i]->cfg = apcg_spmv_config{1, 256, 0, APCG_SPMV_ROWGROUP};
                     continue;
                 }
                 const apcg_spmv_config c{1, 256, 0, APCG_SPMV_SDIA};
@@ -407,7 +414,7 @@ extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apc
             best->block_size = v[1];
             best->tile_rows = v[2];
             best->sdia = v[3];
-            if (best->sdia) set_sdia(true);
+            set_sdia(best->sdia != 0);
             if (best_ms) *best_ms = ms;
             if (from_cache) *from_cache = 1;
             return APCG_SUCCESS;
@@ -457,6 +464,10 @@ extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apc
         set_sdia(false);
         double best_t = 1e300;
         apcg_batch_config best_c{APCG_BATCH_SEGMENTED, 0, kDefaultBatchTileRows, 0};
+        // the best candidate reading the sliced-diagonal copies, kept apart:
+        // it is taken unless a CSR candidate is clearly faster (below)
+        double best_sd_t = 1e300;
+        apcg_batch_config best_sd{APCG_BATCH_SEGMENTED, 0, kDefaultBatchTileRows, 1};
         for (const Cand &cd : cands) {
             if (cd.c.sdia && !can_sdia) continue;
             set_sdia(cd.c.sdia != 0);
@@ -490,6 +501,19 @@ extern "C" apcg_status apcg_batch_autotune(apcg_ctx ctx, int32_t nsys, const apc
                 best_t = t;
                 best_c = cd.c;
             }
+            if (cd.c.sdia && t < best_sd_t) {
+                best_sd_t = t;
+                best_sd = cd.c;
+            }
+        }
+        // The timed window is the first iterations, when every system runs.
+        // Over a whole solve the last systems run alone for many
+        // iterations, latency-bound, where the sliced-diagonal walk (no
+        // row-pointer -> column -> gather chain) is the faster one: so the
+        // CSR reads are only taken when more than 10% faster in the window.
+        if (!best_c.sdia && best_sd_t < 1e300 && best_t >= kCsrMargin * best_sd_t) {
+            best_t = best_sd_t;
+            best_c = best_sd;
         }
         set_sdia(best_c.sdia != 0);
         cleanup();

@@ -68,3 +68,47 @@ def test_dia_offsets_of_stencils():
     assert bench.dia_offsets(A) == [-30, -6, -1, 0, 1, 6, 30]
     B = P.stencil_laplacian((7, 8), 9)
     assert bench.dia_offsets(B) == [-9, -8, -7, -1, 0, 1, 7, 8, 9]
+
+
+class _StubApcg:
+    """The few binding calls batch_roofline makes, answered from a table."""
+    APCG_SPMV_SDIA = 3
+
+    def __init__(self, layouts):
+        self.layouts = layouts  # handle -> (schedule, value slots)
+
+    def apcg_mat_get_spmv_config(self, h):
+        return {"schedule": self.layouts[h][0]}
+
+    def apcg_mat_get_sdia_info(self, h):
+        return {"state": 1, "offset_slots": 8, "value_slots": self.layouts[h][1]}
+
+
+class _H:
+    def __init__(self, h):
+        self.h = h
+
+
+class _Opts:
+    def __init__(self, schedule):
+        self.batch_schedule = schedule
+
+
+def test_batch_roofline_byte_model():
+    """Two systems, one on a 5-slot sliced-diagonal copy and one on CSR:
+    each system's iterations times its tile product bytes (512 U + 96 per
+    slice + 32 n, or 12 nnz + 4 (n + 1) + 32 n) plus 64 n of update,
+    written out by hand; the persistent schedule has no such count."""
+    A1 = P.laplace_2d(10)  # n = 100, 2 slices
+    A2 = P.laplace_2d(7)  # n = 49, nnz = 217
+    systems = [P.System(A=A1, b=np.zeros(A1.n)), P.System(A=A2, b=np.zeros(A2.n))]
+    apcg = _StubApcg({0: (3, 5), 1: (0, 0)})
+    res = [{"iterations": 30}, {"iterations": 11}]
+    r = bench.batch_roofline(apcg, systems, [_H(0), _H(1)], res, 0.5, _Opts(2))
+    b1 = 30 * (2 * (512 * 5 + 96) + 32 * 100 + 64 * 100)
+    b2 = 11 * (12 * 217 + 4 * 50 + 32 * 49 + 64 * 49)
+    assert A2.nnz == 217
+    assert r["algorithmic_bytes"] == b1 + b2
+    assert r["row_iterations"] == 30 * 100 + 11 * 49
+    assert abs(r["achieved"] - (b1 + b2) / 0.5 / 1e9) < 0.06
+    assert bench.batch_roofline(apcg, systems, [_H(0), _H(1)], res, 0.5, _Opts(1)) is None

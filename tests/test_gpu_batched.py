@@ -259,7 +259,10 @@ def test_batch_autotune_and_table(apcg, ctx):
     """The batched autotuner times the schedules on the device, keeps the
     best under the batch's key (a second call takes it from the table
     without timing), and the solve in the tuned configuration meets the
-    oracle's bar system by system."""
+    oracle's bar system by system.  The members start on the sliced-diagonal
+    schedule; afterwards they are on it exactly when the pick reads the
+    sliced-diagonal copies (a CSR pick moves them to the row schedule, so
+    that the batch reads what was timed)."""
     from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
 
     rng = np.random.default_rng(63)
@@ -267,13 +270,28 @@ def test_batch_autotune_and_table(apcg, ctx):
     As = [DeviceCSR(s.A) for s in systems]
     bs = [DeviceVec(s.b) for s in systems]
     xs = [DeviceVec.zeros(s.A.n) for s in systems]
+    on_sdia = []
+    for i, a in enumerate(As):
+        try:
+            apcg.apcg_mat_set_spmv_config(a.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
+            on_sdia.append(i)
+        except apcg.ApcgError:
+            pass
+    assert len(on_sdia) >= 10
+
+    def members_on_sdia():
+        return [i for i, a in enumerate(As)
+                if apcg.apcg_mat_get_spmv_config(a.h)["schedule"] == apcg.APCG_SPMV_SDIA]
+
     apcg.apcg_tune_cache_clear()
     cfg, ms, hit = apcg.apcg_batch_autotune(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 0, 16)
     print(f"case batch autotune: {cfg} {ms:.3f} ms", flush=True)
     assert not hit and ms > 0
     assert cfg["schedule"] in (apcg.APCG_BATCH_PERSISTENT, apcg.APCG_BATCH_SEGMENTED)
+    assert members_on_sdia() == (on_sdia if cfg["sdia"] else [])
     cfg2, ms2, hit2 = apcg.apcg_batch_autotune(ctx, [a.h for a in As], [b.h for b in bs], [x.h for x in xs], 0, 16)
     assert hit2 and cfg2 == cfg and ms2 == ms
+    assert members_on_sdia() == (on_sdia if cfg["sdia"] else [])
     assert apcg.apcg_tune_cache_size() == 1
     info = apcg.apcg_info_create(0, len(systems))
     opts = apcg.apcg_solve_opts_default(x0_is_zero=1, batch_schedule=cfg["schedule"],
