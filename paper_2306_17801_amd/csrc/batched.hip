@@ -836,20 +836,41 @@ __global__ __launch_bounds__(ST) void k_seg_update(SegPlan P, int parity, int no
       const int g0 = P.sys_slice0[s];
       int sl0, sl1;
       tile_slices(P, t, S.n, &sl0, &sl1);
-      for (int sl = sl0 + wave; sl < sl1; sl += SW) {
-        const int i = sl * 64 + lane;
-        double v[2] = {0.0, 0.0};
-        if (i < S.n) {
-            const double xi = fma(alpha, p[i], x[i]);
-            const double ri = fma(-alpha, w[i], r[i]);
+      // the wavefront's slices in groups of UN whose loads are all issued
+      // before the group's arithmetic and stores (each slice's partials are
+      // its own 64 rows' sums, as one slice at a time)
+      constexpr int UN = 4;
+      for (int sb = sl0 + wave; sb < sl1; sb += UN * SW) {
+        double xs[UN], rs[UN], ps[UN], ws[UN], ds[UN];
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          const int i = (sb + u * SW) * 64 + lane;
+          const bool ok = sb + u * SW < sl1 && i < S.n;
+          const int ic = ok ? i : 0;
+          xs[u] = x[ic];
+          rs[u] = r[ic];
+          ps[u] = p[ic];
+          ws[u] = w[ic];
+          ds[u] = dinv[ic];
+        }
+#pragma unroll
+        for (int u = 0; u < UN; ++u) {
+          const int sl = sb + u * SW;
+          if (sl >= sl1) break;
+          const int i = sl * 64 + lane;
+          double v[2] = {0.0, 0.0};
+          if (i < S.n) {
+            const double xi = fma(alpha, ps[u], xs[u]);
+            const double ri = fma(-alpha, ws[u], rs[u]);
             x[i] = xi;
             r[i] = ri;
-            const double zi = dinv[i] * ri;
+            const double zi = ds[u] * ri;
             z[i] = zi;  // gathered by the next product
             v[0] = zi * ri;
             v[1] = norm_pre ? zi * zi : ri * ri;
+          }
+          slice_store<2>(v, P.part_res, P.nslices, g0 + sl);
         }
-        slice_store<2>(v, P.part_res, P.nslices, g0 + sl);
       }
     });
 }

@@ -403,16 +403,34 @@ __global__ __launch_bounds__(FT) void k_bf_update(FPlan P, int parity) {
         auto *x = dev::glb(S.x);
         int sl0, sl1;
         ftile_slices(P, t, S.n, &sl0, &sl1);
-        for (int sl = sl0 + wave; sl < sl1; sl += FSW) {
-            const int i = sl * 64 + lane;
-            double v[1] = {0.0};
-            if (i < S.n) {
-                x[i] = fma(alpha, p[i], x[i]);
-                const double ri = fma(-alpha, w[i], r[i]);
-                r[i] = ri;
-                v[0] = ri * ri;
+        // the wavefront's slices in groups of UN whose loads are all issued
+        // before the group's arithmetic and stores (per-slice sums unchanged)
+        constexpr int UN = 4;
+        for (int sb = sl0 + wave; sb < sl1; sb += UN * FSW) {
+            double xs[UN], rs[UN], ps[UN], ws[UN];
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const int i = (sb + u * FSW) * 64 + lane;
+                const int ic = (sb + u * FSW < sl1 && i < S.n) ? i : 0;
+                xs[u] = x[ic];
+                rs[u] = r[ic];
+                ps[u] = p[ic];
+                ws[u] = w[ic];
             }
-            ftile_store<1>(P, s, sl, 1, v);
+#pragma unroll
+            for (int u = 0; u < UN; ++u) {
+                const int sl = sb + u * FSW;
+                if (sl >= sl1) break;
+                const int i = sl * 64 + lane;
+                double v[1] = {0.0};
+                if (i < S.n) {
+                    x[i] = fma(alpha, ps[u], xs[u]);
+                    const double ri = fma(-alpha, ws[u], rs[u]);
+                    r[i] = ri;
+                    v[0] = ri * ri;
+                }
+                ftile_store<1>(P, s, sl, 1, v);
+            }
         }
     });
 }

@@ -2018,6 +2018,28 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
         // the staged one, -3 / -5: sliced diagonals / diagonals with plane
         // marching (the inner value is the number of planes per task, not a
         // grid)
+        // one product + update pair per repetition, both with their partial
+        // reductions, after two untimed pairs
+        auto time_pair = [&](const Plan &pl, double *us) -> apcg_status {
+            apcg_status ts;
+            for (int w = 0; w < 2; ++w) {
+                if ((ts = launch_product(st, pl, bf, 1, 1))) return ts;
+                if ((ts = launch_update(st, pl, bf, 1, 0, 1))) return ts;
+            }
+            APCG_HIP(hipEventRecord(e0, st));
+            for (int r = 0; r < reps; ++r) {
+                if ((ts = launch_product(st, pl, bf, 1, 1))) return ts;
+                if ((ts = launch_update(st, pl, bf, 1, 0, 1))) return ts;
+            }
+            APCG_HIP(hipEventRecord(e1, st));
+            g_counters.host_syncs++;
+            APCG_HIP(hipEventSynchronize(e1));
+            float ms = 0.f;
+            APCG_HIP(hipEventElapsedTime(&ms, e0, e1));
+            *us = 1000.0 * ms / reps;
+            return APCG_SUCCESS;
+        };
+        std::vector<std::pair<double, apcg_spmv_config>> timed;
         for (int lpr : {-5, -4, -3, -2, -1, 0, 1, 2, 4, 8, 16, 32, 64}) {
             if (lpr > 1 && lpr > 4 * std::max(1.0, per_row)) continue;
             if (lpr == -4 && !dia_ok) continue;
@@ -2047,29 +2069,32 @@ apcg_status apcg_mat_autotune(apcg_mat A, apcg_ctx ctx, int32_t reps, apcg_spmv_
                     Plan pl;
                     if ((s = make_plan(A, cfg, &pl))) return s;
                     if (!march && pl.g_prod < blocks && blocks > 256) continue;  // same grid as a smaller one
-                    // one product + update pair, both with their partial reductions
-                    for (int w = 0; w < 2; ++w) {
-                        if ((s = launch_product(st, pl, bf, 1, 1))) return s;
-                        if ((s = launch_update(st, pl, bf, 1, 0, 1))) return s;
-                    }
-                    APCG_HIP(hipEventRecord(e0, st));
-                    for (int r = 0; r < reps; ++r) {
-                        if ((s = launch_product(st, pl, bf, 1, 1))) return s;
-                        if ((s = launch_update(st, pl, bf, 1, 0, 1))) return s;
-                    }
-                    APCG_HIP(hipEventRecord(e1, st));
-                    g_counters.host_syncs++;
-                    APCG_HIP(hipEventSynchronize(e1));
-                    float ms = 0.f;
-                    APCG_HIP(hipEventElapsedTime(&ms, e0, e1));
-                    const double us = 1000.0 * ms / reps;
-                    if (us < best_t) {
-                        best_t = us;
-                        best_cfg = cfg;
-                    }
+                    double us;
+                    if ((s = time_pair(pl, &us))) return s;
+                    timed.push_back({us, cfg});
                 }
             }
         }
+        // the four fastest timed twice more, in turn, each keeping its best
+        // time: a single window can be disturbed (clocks, other work)
+        std::sort(timed.begin(), timed.end(),
+                  [](const std::pair<double, apcg_spmv_config> &a, const std::pair<double, apcg_spmv_config> &b) {
+                      return a.first < b.first;
+                  });
+        if (timed.size() > 4) timed.resize(4);
+        for (int pass = 0; pass < 2; ++pass)
+            for (auto &tc : timed) {
+                Plan pl;
+                if ((s = make_plan(A, tc.second, &pl))) return s;
+                double us;
+                if ((s = time_pair(pl, &us))) return s;
+                tc.first = std::min(tc.first, us);
+            }
+        for (const auto &tc : timed)
+            if (tc.first < best_t) {
+                best_t = tc.first;
+                best_cfg = tc.second;
+            }
         hipEventDestroy(e0);
         hipEventDestroy(e1);
         hipFree(xs);  // the stream is idle here (synchronised on the last timing event)
