@@ -1085,6 +1085,24 @@ def main():
                "serial_sample": "the serial oracle's first 40 iterations on one thread, scaled to the solve's "
                                 f"{r.its} iterations"}
         log(f"[bench] oracle: min {dt:.2f} s on {threads} threads, its={r.its}; serial estimate {ser:.1f} s")
+        if "batch2d_256" in extra:
+            # the batch on the host: one serial oracle solve per system, the
+            # systems spread over the host threads (largest first)
+            from concurrent.futures import ThreadPoolExecutor
+
+            from paper_2306_17801_amd import problems
+
+            systems = sorted(problems.batch2d_lognormal(256, seed=3), key=lambda q: -q.A.n)
+            t1 = time.perf_counter()
+            with ThreadPoolExecutor(threads) as ex:
+                res = list(ex.map(lambda q: oracle.pcg(q.A, q.b, rtol=1e-8, maxit=50000), systems))
+            bdt = time.perf_counter() - t1
+            extra["batch2d_256"]["cpu_baseline"] = {
+                "value": round(len(systems) / bdt, 3), "unit": "solves/s", "cores": threads, "kind": "oracle",
+                "sample": f"all {len(systems)} systems of the batch, one serial FP64 oracle Jacobi-PCG solve per "
+                          f"system, the systems spread over {threads} host threads (largest first); one run",
+                "seconds": round(bdt, 3), "converged": sum(1 for q in res if q.status == oracle.CONVERGED)}
+            log(f"[bench] oracle batch: {bdt:.2f} s on {threads} threads")
 
     props = apcg.apcg_device_props_get(0)
     line = {
