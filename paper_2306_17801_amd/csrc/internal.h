@@ -513,7 +513,8 @@ __device__ inline int sturm_below(const double *al, const double *be, int m, dou
 // Ritz values of at most 16 CG steps, one workgroup: threads j < m write the
 // CG-Lanczos tridiagonal (diagonal d, squared off-diagonal e2) to LDS, then
 // thread i < m bisects for the i-th smallest eigenvalue on the Sturm count of
-// that copy (one division per step); th[i] receives it.
+// that copy (one division per step); th[i] receives it.  The bisection stops
+// at a relative bracket of 2^-30: the values only enter FP32 features.
 __device__ inline void ritz_values(const double *al, const double *be, int m, double *d, double *e2, double *th) {
     const int j = threadIdx.x;
     if (j < m) {
@@ -531,7 +532,7 @@ __device__ inline void ritz_values(const double *al, const double *be, int m, do
         }
         for (int it = 0; it < 128; ++it) {
             const double x = 0.5 * (lo + up);
-            if (x <= lo || x >= up) break;
+            if (x <= lo || x >= up || up - lo <= 0x1p-30 * fmax(fabs(lo), fabs(up))) break;
             int cnt = 0;
             double q = 1.0;
             for (int k = 0; k < m; ++k) {
