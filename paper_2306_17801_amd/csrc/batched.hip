@@ -703,7 +703,22 @@ template <int NV>
 __device__ __forceinline__ void sys_sum(const double *part, int ns, int ga, int gb, double (&v)[NV], double *lds) {
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = ga + (int)threadIdx.x; g < gb; g += SB) {
+    int g = ga + (int)threadIdx.x;
+    // eight of a thread's partials loaded before they are added (a large
+    // system has thousands of slices); the same order of addition
+    constexpr int UA = 8;
+    for (; g + (UA - 1) * SB < gb; g += UA * SB) {
+        double t[UA][NV];
+#pragma unroll
+        for (int u = 0; u < UA; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) t[u][k] = part[(int64_t)k * ns + g + u * SB];
+#pragma unroll
+        for (int u = 0; u < UA; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] += t[u][k];
+    }
+    for (; g < gb; g += SB) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) v[k] += part[(int64_t)k * ns + g];
     }

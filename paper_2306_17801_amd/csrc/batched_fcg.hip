@@ -157,9 +157,26 @@ __device__ __forceinline__ void fsys_sum(const FPlan &P, int s, int slot0, doubl
     __shared__ double lds[NV * (FSB / 64)];
 #pragma unroll
     for (int k = 0; k < NV; ++k) v[k] = 0.0;
-    for (int g = P.sys_slice0[s] + (int)threadIdx.x; g < P.sys_slice0[s + 1]; g += FSB) {
+    const int ge = P.sys_slice0[s + 1];
+    const double *part = P.part + (size_t)slot0 * P.nslices;
+    int g = P.sys_slice0[s] + (int)threadIdx.x;
+    // eight of a thread's partials loaded before they are added (a large
+    // system has thousands of slices); the same order of addition
+    constexpr int UA = 8;
+    for (; g + (UA - 1) * FSB < ge; g += UA * FSB) {
+        double t[UA][NV];
 #pragma unroll
-        for (int k = 0; k < NV; ++k) v[k] += P.part[(size_t)(slot0 + k) * P.nslices + g];
+        for (int u = 0; u < UA; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) t[u][k] = part[(size_t)k * P.nslices + g + u * FSB];
+#pragma unroll
+        for (int u = 0; u < UA; ++u)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) v[k] += t[u][k];
+    }
+    for (; g < ge; g += FSB) {
+#pragma unroll
+        for (int k = 0; k < NV; ++k) v[k] += part[(size_t)k * P.nslices + g];
     }
     dev::block_sum<FSB, NV>(v, lds);
 }
