@@ -47,24 +47,28 @@ sys.path.insert(0, ROOT)
 METRIC = "PCG solves/s at rtol 1e-8 (batched+learned vs plain); SpMV+vec HBM GB/s"
 HBM_PEAK_GBS = 8000.0
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "traffic_pcg_product_diffusion3d_128.json")
-KERNEL_SOURCE = os.path.join(ROOT, "paper_2306_17801_amd", "csrc", "pcg.hip")
+# the product and update kernels' code: their file and the device helpers they inline
+KERNEL_SOURCE = [os.path.join(ROOT, "paper_2306_17801_amd", "csrc", f) for f in ("pcg.hip", "internal.h")]
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def source_hash(path):
-    """Hash of the kernel source's code: comments and whitespace removed, so
-    that a comment edit does not invalidate counters taken on the same code."""
+def source_hash(paths):
+    """Hash of the kernel sources' code (one path or a list, in order):
+    comments and whitespace removed, so that a comment edit does not
+    invalidate counters taken on the same code."""
     import re
 
-    with open(path, encoding="utf-8") as f:
-        text = f.read()
-    text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
-    text = re.sub(r"//[^\n]*", " ", text)
-    text = " ".join(text.split())
-    return hashlib.sha256(text.encode()).hexdigest()[:16]
+    texts = []
+    for path in [paths] if isinstance(paths, str) else paths:
+        with open(path, encoding="utf-8") as f:
+            text = f.read()
+        text = re.sub(r"/\*.*?\*/", " ", text, flags=re.S)
+        text = re.sub(r"//[^\n]*", " ", text)
+        texts.append(" ".join(text.split()))
+    return hashlib.sha256("\n".join(texts).encode()).hexdigest()[:16]
 
 
 def sdia_shape(A):

@@ -401,7 +401,22 @@ __device__ __forceinline__ void reduce_partials(const double *partials, int G, d
     double t[NV];
 #pragma unroll
     for (int k = 0; k < NV; ++k) t[k] = 0.0;
-    for (int i = threadIdx.x; i < G; i += BS) {
+    // four of a thread's partials loaded before they are added (the same
+    // order of addition): the prologue's latency is that of one load
+    constexpr int UA = 4;
+    int i = threadIdx.x;
+    for (; i + (UA - 1) * BS < G; i += UA * BS) {
+        double u[UA][NV];
+#pragma unroll
+        for (int a = 0; a < UA; ++a)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) u[a][k] = partials[k * G + i + a * BS];
+#pragma unroll
+        for (int a = 0; a < UA; ++a)
+#pragma unroll
+            for (int k = 0; k < NV; ++k) t[k] += u[a][k];
+    }
+    for (; i < G; i += BS) {
 #pragma unroll
         for (int k = 0; k < NV; ++k) t[k] += partials[k * G + i];
     }

@@ -58,6 +58,12 @@ def test_source_hash_ignores_comments_and_whitespace(tmp_path):
     c.write_text("int f(int x) {\n    return x + 2;\n}\n")
     assert bench.source_hash(str(a)) == bench.source_hash(str(b))
     assert bench.source_hash(str(a)) != bench.source_hash(str(c))
+    # several files (a kernel and the helpers it inlines): a code change in
+    # either changes the hash, a comment change in either does not
+    assert bench.source_hash(str(a)) == bench.source_hash([str(a)])
+    assert bench.source_hash([str(a), str(c)]) == bench.source_hash([str(b), str(c)])
+    assert bench.source_hash([str(a), str(c)]) != bench.source_hash([str(a), str(a)])
+    assert bench.source_hash([str(a), str(c)]) != bench.source_hash([str(c), str(a)])
 
 
 def test_dia_offsets_of_stencils():
