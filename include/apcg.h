@@ -513,7 +513,14 @@ typedef struct apcg_solve_opts {
     int32_t batch_tile_rows; /* segmented batched solves: rows per tile, a    */
                              /*    multiple of 256 in [256, 8192] (0 = 1024); */
                              /*    changes the launch shape only, not a sum  */
-    int32_t reserved[6];
+    int32_t batch_tail_tile_rows; /* segmented batched solves: rows per tile */
+                             /*    once the rows of the systems still running */
+                             /*    fill fewer than two tiles per compute unit */
+                             /*    (the last, largest systems run alone): a  */
+                             /*    valid tile size below batch_tile_rows, 0 = */
+                             /*    256 (when below), -1 = keep the tiles.  The */
+                             /*    same bits either way                      */
+    int32_t reserved[5];
 } apcg_solve_opts;
 
 /* Schedules of apcg_ksp_solve_batched. */

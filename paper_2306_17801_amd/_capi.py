@@ -86,7 +86,7 @@ class apcg_solve_opts(ctypes.Structure):
     _fields_ = [("pc", c_i32), ("norm_type", c_i32), ("mode", c_i32), ("iters_per_graph", c_i32),
                 ("lookahead", c_i32), ("x0_is_zero", c_i32), ("kernel_timing", c_i32),
                 ("batch_block_size", c_i32), ("batch_schedule", c_i32), ("batch_tile_rows", c_i32),
-                ("reserved", c_i32 * 6)]
+                ("batch_tail_tile_rows", c_i32), ("reserved", c_i32 * 5)]
 
 
 class apcg_solve_info(ctypes.Structure):

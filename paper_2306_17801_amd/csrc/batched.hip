@@ -370,6 +370,8 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
         const int tb = opts.batch_block_size ? opts.batch_block_size : 512;
         const BatchedFn fn = batched_fn(tb);
         if (!fn) return set_error(APCG_ERR_INVALID_ARG, "batch block size must be 256, 512 or 1024");
+        if (!valid_batch_tail_rows(opts.batch_tail_tile_rows))
+            return set_error(APCG_ERR_INVALID_ARG, "batch tail tile rows must be -1, 0 or a multiple of 256 in [256, 8192]");
         if (!valid_batch_tile_rows(opts.batch_tile_rows))
             return set_error(APCG_ERR_INVALID_ARG, "batch tile rows must be 0 or a multiple of 256 in [256, 8192]");
         const int dev = ctx->device;
@@ -583,13 +585,18 @@ struct SegPlan {
     SegSys *st;            // [nsys]
     double *part_res;      // [4][nslices]
     double *part_delta;    // [nslices]
-    unsigned *running;     // systems still iterating
+    unsigned *running;     // [0]: systems still iterating; [2..3]: their rows (64-bit)
     int32_t nsys, ntiles, tiles_per_block;
     int32_t nslices;       // sys_slice0[nsys]
     int32_t tile_rows;
 };
 
 namespace {
+
+// Rows of the systems still running, kept beside the count.
+__device__ __forceinline__ unsigned long long *seg_running_rows(const SegPlan &P) {
+    return reinterpret_cast<unsigned long long *>(P.running + 2);
+}
 
 constexpr int ST = 256;  // threads per tile workgroup (tiles are multiples of ST rows)
 constexpr int SW = ST / 64;  // wavefronts per tile workgroup
@@ -753,7 +760,10 @@ __global__ __launch_bounds__(SB) void k_seg_init_final(SegPlan P, double rtol, i
     q.status = status;
     q.flag = status != 0;
     P.st[s] = q;
-    if (!q.flag) atomicAdd(P.running, 1u);
+    if (!q.flag) {
+        atomicAdd(P.running, 1u);
+        atomicAdd(seg_running_rows(P), (unsigned long long)P.sys[s].n);
+    }
 }
 
 __global__ __launch_bounds__(ST) void k_seg_zero_x(SegPlan P) {
@@ -830,6 +840,7 @@ __global__ __launch_bounds__(SB) void k_seg_alpha(SegPlan P) {
         q->status = isfinite(delta) ? APCG_SOLVE_BREAKDOWN_PAP : APCG_SOLVE_NAN;
         q->flag = 1;
         atomicSub(P.running, 1u);
+        atomicAdd(seg_running_rows(P), 0ull - (unsigned long long)P.sys[s].n);
     } else {
         q->alpha = q->rho / delta;
     }
@@ -911,6 +922,7 @@ __global__ __launch_bounds__(SB) void k_seg_beta(SegPlan P, double rtol, int32_t
         q->status = status;
         q->flag = 1;
         atomicSub(P.running, 1u);
+        atomicAdd(seg_running_rows(P), 0ull - (unsigned long long)P.sys[s].n);
     } else {
         q->beta = rho_new / q->rho;
         q->rho = rho_new;
@@ -930,10 +942,17 @@ __global__ void k_seg_finish(SegPlan P, apcg_solve_info *info) {
 }
 
 __global__ void k_seg_reset(unsigned *running) {
-    if (threadIdx.x == 0) *running = 0u;
+    if (threadIdx.x < 4) running[threadIdx.x] = 0u;  // the count and the 64-bit row total
 }
 
 }  // namespace
+
+// The tail plan of the segmented PCG takes over once the rows still running
+// fill fewer than this many of the large tiles per compute unit.  Unlike the
+// flexible iteration's (32), it stays low: the 2D batch (1024-row tiles, a
+// 256-row tail) took 159.8 ms at 2 or without the switch, 160.1 at 8 and
+// 216.4 at 32, where most of the solve runs on the small tiles.
+constexpr uint64_t kSegTailTilesPerCu = 2;
 
 // Segment resources of one context (tile tables, per-system scalars, graph).
 struct SegCache {
@@ -947,7 +966,15 @@ struct SegCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t graph_hash = 0;
-    int32_t *pinned = nullptr;  // lookahead flags
+    // the tail plan: smaller tiles once few rows still run
+    int32_t *d_tile_sys_t = nullptr, *d_tile_row0_t = nullptr;
+    int64_t tiles_t_cap = 0;
+    uint64_t hash_t = 0;
+    hipGraph_t graph_t = nullptr;
+    hipGraphExec_t exec_t = nullptr;
+    uint64_t graph_hash_t = 0;
+    int32_t cus = 0;            // compute units of the device
+    int32_t *pinned = nullptr;  // [kMaxLookahead][4]: running count, pad, running rows (64-bit)
     EventRef poll_ev[kMaxLookahead];
 };
 
@@ -962,6 +989,13 @@ static SegCache *seg_cache(apcg_ctx c) {
     sc->device = c->device;
     g_seg.emplace_back(c->id, sc);
     return sc;
+}
+
+static void seg_free_tail(SegCache &s) {
+    if (s.exec_t) hipGraphExecDestroy(s.exec_t);
+    if (s.graph_t) hipGraphDestroy(s.graph_t);
+    hipFree(s.d_tile_sys_t);
+    hipFree(s.d_tile_row0_t);
 }
 
 static void seg_free_buffers(SegCache &s) {
@@ -990,6 +1024,7 @@ void seg_cache_release(uint64_t ctx_id, int device) {
     if (!sc) return;
     hipSetDevice(device);
     seg_free_buffers(*sc);
+    seg_free_tail(*sc);
     if (sc->pinned) hipHostFree(sc->pinned);
     delete sc;
 }
@@ -1017,6 +1052,20 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     sys_tile0[nsys] = (int32_t)tile_sys.size();
     sys_slice0[nsys] = (int32_t)nslices;
     if (nslices > INT32_MAX / 8) return set_error(APCG_ERR_INVALID_ARG, "batch too large for the segmented schedule");
+    // the tail plan: the same systems in smaller tiles, switched to once the
+    // rows still running fill fewer than two of the large tiles per compute
+    // unit (the tiles only group slices, so the sums are those of the
+    // large tiles)
+    const int32_t TRt = batch_tail_rows(opts);
+    std::vector<int32_t> tile_sys_t, tile_row0_t;
+    if (TRt > 0)
+        for (int32_t s = 0; s < nsys; ++s)
+            for (int32_t r0 = 0; r0 < hsys[s].n; r0 += TRt) {
+                tile_sys_t.push_back(s);
+                tile_row0_t.push_back(r0);
+            }
+    const int32_t ntiles_t = (int32_t)tile_sys_t.size();
+    const bool tail_plan = ntiles_t > 0;
     const int64_t ns_alloc = std::max<int64_t>(nslices, 1);
     const int32_t ntiles = (int32_t)tile_sys.size();
     if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well-formed
@@ -1048,7 +1097,8 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
         APCG_HIP(hipMalloc((void **)&sc->d_part, sizeof(double) * 5 * sc->slices_cap));
         APCG_HIP(hipMalloc((void **)&sc->d_running, 256));
     }
-    if (!sc->pinned) APCG_HIP(hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
+    if (!sc->pinned)
+        APCG_HIP(hipHostMalloc((void **)&sc->pinned, sizeof(int32_t) * 4 * kMaxLookahead, hipHostMallocDefault));
     uint64_t h = fnv1a(tile_sys.data(), sizeof(int32_t) * tile_sys.size());
     h = fnv1a(tile_row0.data(), sizeof(int32_t) * tile_row0.size(), h);
     h = fnv1a(sys_tile0.data(), sizeof(int32_t) * sys_tile0.size(), h);
@@ -1067,6 +1117,38 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
         APCG_HIP(hipStreamSynchronize(st));  // host tables are local
         sc->hash = h;
     }
+    if (tail_plan) {
+        if (sc->tiles_t_cap < ntiles_t) {
+            EventRef ev = event_get(dev);
+            if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+            APCG_HIP(hipEventRecord(ev->e, st));
+            SegCache old = *sc;
+            defer_release({ev}, [old, dev]() mutable {
+                hipSetDevice(dev);
+                seg_free_tail(old);
+            });
+            sc->exec_t = nullptr;
+            sc->graph_t = nullptr;
+            sc->graph_hash_t = 0;
+            sc->hash_t = 0;
+            sc->tiles_t_cap = ntiles_t;
+            APCG_HIP(hipMalloc((void **)&sc->d_tile_sys_t, sizeof(int32_t) * sc->tiles_t_cap));
+            APCG_HIP(hipMalloc((void **)&sc->d_tile_row0_t, sizeof(int32_t) * sc->tiles_t_cap));
+        }
+        uint64_t ht = fnv1a(tile_sys_t.data(), sizeof(int32_t) * tile_sys_t.size());
+        ht = fnv1a(tile_row0_t.data(), sizeof(int32_t) * tile_row0_t.size(), ht);
+        if (ht != sc->hash_t) {
+            g_counters.h2d_copies += 2;
+            APCG_HIP(hipMemcpyAsync(sc->d_tile_sys_t, tile_sys_t.data(), sizeof(int32_t) * tile_sys_t.size(),
+                                    hipMemcpyHostToDevice, st));
+            APCG_HIP(hipMemcpyAsync(sc->d_tile_row0_t, tile_row0_t.data(), sizeof(int32_t) * tile_row0_t.size(),
+                                    hipMemcpyHostToDevice, st));
+            g_counters.host_syncs++;
+            APCG_HIP(hipStreamSynchronize(st));  // host tables are local
+            sc->hash_t = ht;
+        }
+        if (!sc->cus) APCG_HIP(hipDeviceGetAttribute(&sc->cus, hipDeviceAttributeMultiprocessorCount, dev));
+    }
     SegPlan P;
     P.sys = d_sys;
     P.tile_sys = sc->d_tile_sys;
@@ -1083,6 +1165,18 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     P.tile_rows = TR;
     const int G = normalise_blocks(kMaxBlocks, std::max<int32_t>(ntiles, 1));  // few tiles per workgroup: more in flight
     P.tiles_per_block = std::max<int32_t>(1, (ntiles + G - 1) / G);
+    SegPlan Pt = P;
+    int Gt = G;
+    if (tail_plan) {
+        Pt.tile_sys = sc->d_tile_sys_t;
+        Pt.tile_row0 = sc->d_tile_row0_t;
+        Pt.ntiles = ntiles_t;
+        Pt.tile_rows = TRt;
+        Gt = normalise_blocks(kMaxBlocks, ntiles_t);
+        Pt.tiles_per_block = std::max<int32_t>(1, (ntiles_t + Gt - 1) / Gt);
+    }
+    // switch when the running rows fill fewer than kSegTailTilesPerCu large tiles per CU
+    const uint64_t tail_rows = tail_plan ? kSegTailTilesPerCu * (uint64_t)sc->cus * (uint64_t)TR : 0;
     const int norm_pre = opts.norm_type == APCG_NORM_PRECONDITIONED;
     const int x0z = opts.x0_is_zero ? 1 : 0;
 
@@ -1104,7 +1198,7 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
     void (*seg_product)(SegPlan, int) = umax <= 5   ? k_seg_product<5>
                                         : umax <= 7 ? k_seg_product<7>
                                                     : k_seg_product<8>;
-    auto launch_iter = [&](int j) -> apcg_status {
+    auto launch_iter = [&](int j, const SegPlan &P, int G) -> apcg_status {
         hipLaunchKernelGGL(seg_product, dim3(G), dim3(ST), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_seg_product");
         hipLaunchKernelGGL(k_seg_alpha, dim3(nsys), dim3(SB), 0, st, P);
@@ -1113,6 +1207,27 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
         APCG_CHECK_LAUNCH("k_seg_update");
         hipLaunchKernelGGL(k_seg_beta, dim3(nsys), dim3(SB), 0, st, P, rtol, maxit);
         APCG_CHECK_LAUNCH("k_seg_beta");
+        return APCG_SUCCESS;
+    };
+    // K iterations of plan Pc on grid Gc captured into one executable graph
+    auto capture = [&](const SegPlan &Pc, int Gc, hipGraph_t *gout, hipGraphExec_t *xout) -> apcg_status {
+        APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        apcg_status cs = APCG_SUCCESS;
+        for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j, Pc, Gc);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (cs) {
+            if (g) hipGraphDestroy(g);
+            return cs;
+        }
+        if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(segmented)");
+        g_counters.kernel_launches -= 4 * K;
+        e = hipGraphInstantiate(xout, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return hip_error(e, "hipGraphInstantiate(segmented)");
+        }
+        *gout = g;
         return APCG_SUCCESS;
     };
     uint64_t gh = fnv1a(&h, sizeof h);
@@ -1140,34 +1255,42 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
                     sc->exec = nullptr;
                     sc->graph = nullptr;
                 }
-                APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-                apcg_status cs = APCG_SUCCESS;
-                for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j);
-                hipGraph_t g = nullptr;
-                hipError_t e = hipStreamEndCapture(st, &g);
-                if (cs) {
-                    if (g) hipGraphDestroy(g);
-                    return cs;
-                }
-                if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(segmented)");
-                g_counters.kernel_launches -= 4 * K;
-                e = hipGraphInstantiate(&sc->exec, g, nullptr, nullptr, 0);
-                if (e != hipSuccess) {
-                    hipGraphDestroy(g);
-                    return hip_error(e, "hipGraphInstantiate(segmented)");
-                }
-                sc->graph = g;
+                if ((s = capture(P, G, &sc->graph, &sc->exec))) return s;
                 sc->graph_hash = gh;
+            }
+            // the tail plan's period, captured alike
+            uint64_t ght = fnv1a(&sc->hash_t, sizeof sc->hash_t, gh);
+            const int tprm[3] = {Gt, TRt, Pt.tiles_per_block};
+            ght = fnv1a(tprm, sizeof tprm, ght);
+            const void *tptrs[2] = {sc->d_tile_sys_t, sc->d_tile_row0_t};
+            ght = fnv1a(tptrs, sizeof tptrs, ght);
+            if (tail_plan && (!sc->exec_t || sc->graph_hash_t != ght)) {
+                if (sc->exec_t) {
+                    EventRef ev = event_get(dev);
+                    if (ev) hipEventRecord(ev->e, st);
+                    hipGraphExec_t oe = sc->exec_t;
+                    hipGraph_t og = sc->graph_t;
+                    defer_release({ev}, [oe, og, dev]() {
+                        hipSetDevice(dev);
+                        hipGraphExecDestroy(oe);
+                        hipGraphDestroy(og);
+                    });
+                    sc->exec_t = nullptr;
+                    sc->graph_t = nullptr;
+                }
+                if ((s = capture(Pt, Gt, &sc->graph_t, &sc->exec_t))) return s;
+                sc->graph_hash_t = ght;
             }
         }
         const int64_t periods = ((int64_t)maxit + K - 1) / K;
+        bool tail = false;  // periods on the tail plan from here on
         for (int64_t g = 0; g < periods; ++g) {
             if (opts.mode == APCG_MODE_GRAPH) {
                 g_counters.graph_launches++;
-                APCG_HIP(hipGraphLaunch(sc->exec, st));
+                APCG_HIP(hipGraphLaunch(tail ? sc->exec_t : sc->exec, st));
             } else {
                 for (int j = 1; j <= K; ++j)
-                    if ((s = launch_iter(j))) return s;
+                    if ((s = launch_iter(j, tail ? Pt : P, tail ? Gt : G))) return s;
             }
             const int slot = (int)(g % L);
             if (!sc->poll_ev[slot]) {
@@ -1175,13 +1298,17 @@ apcg_status seg_solve(apcg_ctx ctx, int32_t nsys, const BatchSys *hsys, const Ba
                 if (!sc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
             }
             g_counters.d2h_copies++;
-            APCG_HIP(hipMemcpyAsync(&sc->pinned[slot], sc->d_running, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            APCG_HIP(hipMemcpyAsync(&sc->pinned[4 * slot], sc->d_running, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    st));
             APCG_HIP(hipEventRecord(sc->poll_ev[slot]->e, st));
             if (g >= L - 1) {
                 const int ps = (int)((g - (L - 1)) % L);
                 g_counters.host_polls++;
                 APCG_HIP(hipEventSynchronize(sc->poll_ev[ps]->e));
-                if (sc->pinned[ps] == 0) break;  // every system has stopped
+                if (sc->pinned[4 * ps] == 0) break;  // every system has stopped
+                uint64_t rows;
+                memcpy(&rows, &sc->pinned[4 * ps + 2], sizeof rows);
+                if (tail_plan && !tail && rows < tail_rows) tail = true;
             }
         }
     }

@@ -74,7 +74,7 @@ struct FPlan {
     const int32_t *sys_slice0;            // [nsys + 1]: first global 64-row slice of each system
     FState *st;                           // [nsys]
     double *part;                         // [4][nslices]: per 64-row slice, local slice l of system s at sys_slice0[s] + l
-    unsigned *running;
+    unsigned *running;                    // [0]: systems still running; [2..3]: their rows (64-bit)
     int32_t nsys, ntiles, tiles_per_block;
     int32_t nslices;                      // sys_slice0[nsys]
     int32_t tile_rows;                    // rows per tile (a multiple of FT)
@@ -84,6 +84,11 @@ struct FPlan {
     int32_t hist_cap;      // > 0: alpha, beta of the first hist_cap iterations
     double *hist;          // [nsys][2][hist_cap]
 };
+
+// Rows of the systems still running, kept beside the count.
+__device__ __forceinline__ unsigned long long *running_rows(const FPlan &P) {
+    return reinterpret_cast<unsigned long long *>(P.running + 2);
+}
 
 // The local slices [sl0, sl1) of tile t (of a system of n rows).
 __device__ __forceinline__ void ftile_slices(const FPlan &P, int t, int n, int *sl0, int *sl1) {
@@ -225,6 +230,7 @@ __device__ void fstop(const FPlan &P, FState *q, int status) {
     q->status = status;
     q->flag = 1;
     atomicSub(P.running, 1u);
+    atomicAdd(running_rows(P), 0ull - (unsigned long long)P.sys[q - P.st].n);
 }
 
 // Hands system s over to Jacobi mode (reason: the failed test), or stops it
@@ -331,7 +337,10 @@ __global__ __launch_bounds__(FSB) void k_bf_init_final(FPlan P, const float *coe
     }
     if (jac) q.mode = MODE_JACOBI;  // reason 0: a plain Jacobi-PCG run
     P.st[s] = q;
-    if (!q.flag) atomicAdd(P.running, 1u);
+    if (!q.flag) {
+        atomicAdd(P.running, 1u);
+        atomicAdd(running_rows(P), (unsigned long long)P.sys[s].n);
+    }
 }
 
 __global__ __launch_bounds__(FT) void k_bf_zero_x(FPlan P) {
@@ -681,7 +690,7 @@ __global__ void k_bf_finish(FPlan P, apcg_solve_info *info) {
 }
 
 __global__ void k_bf_reset(unsigned *running) {
-    if (threadIdx.x == 0) *running = 0u;
+    if (threadIdx.x < 4) running[threadIdx.x] = 0u;  // the count and the 64-bit row total
 }
 
 uint64_t fnv(const void *p, size_t n, uint64_t h = 1469598103934665603ull) {
@@ -705,7 +714,15 @@ struct BfCache {
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     uint64_t graph_hash = 0;
-    int32_t *pinned = nullptr;
+    // the tail plan: smaller tiles once few rows still run
+    int32_t *d_tile_sys_t = nullptr, *d_tile_row0_t = nullptr;
+    int64_t tiles_t_cap = 0;
+    uint64_t hash_t = 0;
+    hipGraph_t graph_t = nullptr;
+    hipGraphExec_t exec_t = nullptr;
+    uint64_t graph_hash_t = 0;
+    int32_t cus = 0;            // compute units of the device
+    int32_t *pinned = nullptr;  // [kMaxLookahead][4]: running count, pad, running rows (64-bit)
     EventRef poll_ev[kMaxLookahead];
     // feature runs
     double *d_xs = nullptr;     // scratch iterates, offsets as the workspace's
@@ -741,6 +758,13 @@ static void bf_free_features(BfCache &b) {
     hipFree(b.d_L);
 }
 
+static void bf_free_tail(BfCache &b) {
+    if (b.exec_t) hipGraphExecDestroy(b.exec_t);
+    if (b.graph_t) hipGraphDestroy(b.graph_t);
+    hipFree(b.d_tile_sys_t);
+    hipFree(b.d_tile_row0_t);
+}
+
 static void bf_free(BfCache &b) {
     if (b.exec) hipGraphExecDestroy(b.exec);
     if (b.graph) hipGraphDestroy(b.graph);
@@ -769,6 +793,7 @@ void bfcg_cache_release(uint64_t ctx_id, int device) {
     if (!b) return;
     hipSetDevice(device);
     bf_free(*b);
+    bf_free_tail(*b);
     bf_free_features(*b);
     if (b->pinned) hipHostFree(b->pinned);
     delete b;
@@ -779,6 +804,11 @@ void bfcg_cache_release(uint64_t ctx_id, int device) {
 namespace apcg {
 
 constexpr int FEAT_STEPS = 12;  // Jacobi-PCG steps of the feature run
+// The tail plan takes over once the rows still running fill fewer than this
+// many of the large tiles per compute unit: on the 1024-system mixed batch
+// (2048-row tiles, a 256-row tail) 2 -> 8.95 s, 8 -> 8.77, 16 -> 8.71,
+// 32 -> 8.68, 64 -> 8.67 s, against 8.97 s without the switch.
+constexpr uint64_t kTailTilesPerCu = 32;
 
 // What one run of the batched iteration computes.
 struct BfRun {
@@ -817,6 +847,20 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     sys_tile0[nsys] = (int32_t)tile_sys.size();
     sys_slice0[nsys] = (int32_t)nslices;
     if (nslices > INT32_MAX / 8) return set_error(APCG_ERR_INVALID_ARG, "batch too large for the segmented schedule");
+    // the tail plan: the same systems in smaller tiles, switched to once the
+    // rows still running fill fewer than two of the large tiles per compute
+    // unit (the tiles only group slices, so the sums are those of the
+    // large tiles)
+    const int32_t TRt = run.force_jacobi ? 0 : batch_tail_rows(opts);
+    std::vector<int32_t> tile_sys_t, tile_row0_t;
+    if (TRt > 0)
+        for (int32_t q = 0; q < nsys; ++q)
+            for (int32_t r0 = 0; r0 < hs[q].n; r0 += TRt) {
+                tile_sys_t.push_back(q);
+                tile_row0_t.push_back(r0);
+            }
+    const int32_t ntiles_t = (int32_t)tile_sys_t.size();
+    const bool tail_plan = ntiles_t > 0;
     const int64_t ns_alloc = std::max<int64_t>(nslices, 1);
     const int32_t ntiles = (int32_t)tile_sys.size();
     if (ntiles == 0) {  // every system is empty: one dummy tile keeps the kernels well formed
@@ -854,7 +898,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
         APCG_HIP(hipMalloc((void **)&bc->d_running, 256));
     }
     if (!bc->pinned)
-        APCG_HIP(hipHostMalloc((void **)&bc->pinned, sizeof(int32_t) * kMaxLookahead, hipHostMallocDefault));
+        APCG_HIP(hipHostMalloc((void **)&bc->pinned, sizeof(int32_t) * 4 * kMaxLookahead, hipHostMallocDefault));
     for (int32_t i = 0; i < nsys; ++i) hs[i].ws = bc->d_ws + reinterpret_cast<int64_t>(hs[i].ws);
     uint64_t h = fnv(hs.data(), sizeof(FSys) * nsys);
     h = fnv(tile_sys.data(), sizeof(int32_t) * tile_sys.size(), h);
@@ -875,6 +919,38 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
         g_counters.host_syncs++;
         APCG_HIP(hipStreamSynchronize(st));  // the host tables are local
         bc->hash = h;
+    }
+    if (tail_plan) {
+        if (bc->tiles_t_cap < ntiles_t) {
+            EventRef ev = event_get(dev);
+            if (!ev) return set_error(APCG_ERR_HIP, "event creation failed");
+            APCG_HIP(hipEventRecord(ev->e, st));
+            BfCache old = *bc;
+            defer_release({ev}, [old]() mutable {
+                hipSetDevice(old.device);
+                bf_free_tail(old);
+            });
+            bc->exec_t = nullptr;
+            bc->graph_t = nullptr;
+            bc->graph_hash_t = 0;
+            bc->hash_t = 0;
+            bc->tiles_t_cap = ntiles_t;
+            APCG_HIP(hipMalloc((void **)&bc->d_tile_sys_t, sizeof(int32_t) * bc->tiles_t_cap));
+            APCG_HIP(hipMalloc((void **)&bc->d_tile_row0_t, sizeof(int32_t) * bc->tiles_t_cap));
+        }
+        uint64_t ht = fnv(tile_sys_t.data(), sizeof(int32_t) * tile_sys_t.size());
+        ht = fnv(tile_row0_t.data(), sizeof(int32_t) * tile_row0_t.size(), ht);
+        if (ht != bc->hash_t) {
+            g_counters.h2d_copies += 2;
+            APCG_HIP(hipMemcpyAsync(bc->d_tile_sys_t, tile_sys_t.data(), sizeof(int32_t) * tile_sys_t.size(),
+                                    hipMemcpyHostToDevice, st));
+            APCG_HIP(hipMemcpyAsync(bc->d_tile_row0_t, tile_row0_t.data(), sizeof(int32_t) * tile_row0_t.size(),
+                                    hipMemcpyHostToDevice, st));
+            g_counters.host_syncs++;
+            APCG_HIP(hipStreamSynchronize(st));  // the host tables are local
+            bc->hash_t = ht;
+        }
+        if (!bc->cus) APCG_HIP(hipDeviceGetAttribute(&bc->cus, hipDeviceAttributeMultiprocessorCount, dev));
     }
     FPlan P;
     P.sys = bc->d_sys;
@@ -901,6 +977,18 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     P.force_jacobi = run.force_jacobi;
     P.hist_cap = run.hist ? run.hist_cap : 0;
     P.hist = run.hist;
+    FPlan Pt = P;
+    int Gt = G;
+    if (tail_plan) {
+        Pt.tile_sys = bc->d_tile_sys_t;
+        Pt.tile_row0 = bc->d_tile_row0_t;
+        Pt.ntiles = ntiles_t;
+        Pt.tile_rows = TRt;
+        Gt = normalise_blocks(kMaxBlocks, ntiles_t);
+        Pt.tiles_per_block = std::max<int32_t>(1, (ntiles_t + Gt - 1) / Gt);
+    }
+    // switch when the running rows fill fewer than kTailTilesPerCu large tiles per CU
+    const uint64_t tail_rows = tail_plan ? kTailTilesPerCu * (uint64_t)bc->cus * (uint64_t)TR : 0;
     const int x0z = opts.x0_is_zero ? 1 : 0;
     apcg_status s;
 
@@ -924,7 +1012,7 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
     void (*bf_product)(FPlan, int) = uc == 5 ? k_bf_product<5> : uc == 7 ? k_bf_product<7> : k_bf_product<8>;
     void (*bf_cheb)(FPlan, int, int, int, int, int) = uc == 5 ? k_bf_cheb<5> : uc == 7 ? k_bf_cheb<7> : k_bf_cheb<8>;
     // Clenshaw buffers t0..t2 round robin: b_j in t[j % 3]
-    auto launch_iter = [&](int j) -> apcg_status {
+    auto launch_iter = [&](int j, const FPlan &P, int G) -> apcg_status {
         hipLaunchKernelGGL(bf_product, dim3(G), dim3(FT), 0, st, P, j & 1);
         APCG_CHECK_LAUNCH("k_bf_product");
         hipLaunchKernelGGL(k_bf_alpha, dim3(nsys), dim3(FSB), 0, st, P);
@@ -944,6 +1032,27 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
         }
         hipLaunchKernelGGL(k_bf_beta, dim3(nsys), dim3(FSB), 0, st, P);
         APCG_CHECK_LAUNCH("k_bf_beta");
+        return APCG_SUCCESS;
+    };
+    // K iterations of plan Pc on grid Gc captured into one executable graph
+    auto capture = [&](const FPlan &Pc, int Gc, hipGraph_t *gout, hipGraphExec_t *xout) -> apcg_status {
+        APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
+        apcg_status cs = APCG_SUCCESS;
+        for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j, Pc, Gc);
+        hipGraph_t g = nullptr;
+        hipError_t e = hipStreamEndCapture(st, &g);
+        if (cs) {
+            if (g) hipGraphDestroy(g);
+            return cs;
+        }
+        if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(batched fcg)");
+        g_counters.kernel_launches -= (int64_t)(5 + FDEG) * K;
+        e = hipGraphInstantiate(xout, g, nullptr, nullptr, 0);
+        if (e != hipSuccess) {
+            hipGraphDestroy(g);
+            return hip_error(e, "hipGraphInstantiate(batched fcg)");
+        }
+        *gout = g;
         return APCG_SUCCESS;
     };
     const bool graph = opts.mode == APCG_MODE_GRAPH && !run.force_jacobi;  // feature runs are short: no capture
@@ -969,35 +1078,43 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
                 bc->exec = nullptr;
                 bc->graph = nullptr;
             }
-            APCG_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeRelaxed));
-            apcg_status cs = APCG_SUCCESS;
-            for (int j = 1; j <= K && cs == APCG_SUCCESS; ++j) cs = launch_iter(j);
-            hipGraph_t g = nullptr;
-            hipError_t e = hipStreamEndCapture(st, &g);
-            if (cs) {
-                if (g) hipGraphDestroy(g);
-                return cs;
-            }
-            if (e != hipSuccess) return hip_error(e, "hipStreamEndCapture(batched fcg)");
-            g_counters.kernel_launches -= (int64_t)(5 + FDEG) * K;
-            e = hipGraphInstantiate(&bc->exec, g, nullptr, nullptr, 0);
-            if (e != hipSuccess) {
-                hipGraphDestroy(g);
-                return hip_error(e, "hipGraphInstantiate(batched fcg)");
-            }
-            bc->graph = g;
+            if ((s = capture(P, G, &bc->graph, &bc->exec))) return s;
             bc->graph_hash = gh;
+        }
+        // the tail plan's period, captured alike
+        uint64_t ght = fnv(&bc->hash_t, sizeof bc->hash_t, gh);
+        const int tprm[3] = {Gt, TRt, Pt.tiles_per_block};
+        ght = fnv(tprm, sizeof tprm, ght);
+        const void *tptrs[2] = {bc->d_tile_sys_t, bc->d_tile_row0_t};
+        ght = fnv(tptrs, sizeof tptrs, ght);
+        if (graph && tail_plan && (!bc->exec_t || bc->graph_hash_t != ght)) {
+            if (bc->exec_t) {
+                EventRef ev = event_get(dev);
+                if (ev) hipEventRecord(ev->e, st);
+                hipGraphExec_t oe = bc->exec_t;
+                hipGraph_t og = bc->graph_t;
+                defer_release({ev}, [oe, og, dev]() {
+                    hipSetDevice(dev);
+                    hipGraphExecDestroy(oe);
+                    hipGraphDestroy(og);
+                });
+                bc->exec_t = nullptr;
+                bc->graph_t = nullptr;
+            }
+            if ((s = capture(Pt, Gt, &bc->graph_t, &bc->exec_t))) return s;
+            bc->graph_hash_t = ght;
         }
         // iteration slots: maxit counted iterations plus at most two
         // restarts per system (the first application and one switch)
         const int64_t periods = ((int64_t)maxit + 2 + K - 1) / K;
+        bool tail = false;  // periods on the tail plan from here on
         for (int64_t g = 0; g < periods; ++g) {
             if (graph) {
                 g_counters.graph_launches++;
-                APCG_HIP(hipGraphLaunch(bc->exec, st));
+                APCG_HIP(hipGraphLaunch(tail ? bc->exec_t : bc->exec, st));
             } else {
                 for (int j = 1; j <= K; ++j)
-                    if ((s = launch_iter(j))) return s;
+                    if ((s = launch_iter(j, tail ? Pt : P, tail ? Gt : G))) return s;
             }
             const int slot = (int)(g % L);
             if (!bc->poll_ev[slot]) {
@@ -1005,13 +1122,17 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
                 if (!bc->poll_ev[slot]) return set_error(APCG_ERR_HIP, "event creation failed");
             }
             g_counters.d2h_copies++;
-            APCG_HIP(hipMemcpyAsync(&bc->pinned[slot], bc->d_running, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+            APCG_HIP(hipMemcpyAsync(&bc->pinned[4 * slot], bc->d_running, 4 * sizeof(int32_t), hipMemcpyDeviceToHost,
+                                    st));
             APCG_HIP(hipEventRecord(bc->poll_ev[slot]->e, st));
             if (g >= L - 1) {
                 const int ps = (int)((g - (L - 1)) % L);
                 g_counters.host_polls++;
                 APCG_HIP(hipEventSynchronize(bc->poll_ev[ps]->e));
-                if (bc->pinned[ps] == 0) break;  // every system has stopped
+                if (bc->pinned[4 * ps] == 0) break;  // every system has stopped
+                uint64_t rows;
+                memcpy(&rows, &bc->pinned[4 * ps + 2], sizeof rows);
+                if (tail_plan && !tail && rows < tail_rows) tail = true;
             }
         }
     }
@@ -1161,6 +1282,8 @@ extern "C" apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsy
         if (fopts_in) fo = *fopts_in;
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        if (!valid_batch_tail_rows(opts.batch_tail_tile_rows))
+            return set_error(APCG_ERR_INVALID_ARG, "batch tail tile rows must be -1, 0 or a multiple of 256 in [256, 8192]");
         if (!valid_batch_tile_rows(opts.batch_tile_rows))
             return set_error(APCG_ERR_INVALID_ARG, "batch tile rows must be 0 or a multiple of 256 in [256, 8192]");
         std::vector<FSys> hs;
@@ -1228,6 +1351,8 @@ extern "C" apcg_status apcg_ksp_solve_batched_learned(apcg_ctx ctx, int32_t nsys
         if (fopts_in) fo = *fopts_in;
         else apcg_fcg_opts_default(&fo);
         if (fo.stall_min < 1 || !(fo.stall_frac >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "bad stall window");
+        if (!valid_batch_tail_rows(opts.batch_tail_tile_rows))
+            return set_error(APCG_ERR_INVALID_ARG, "batch tail tile rows must be -1, 0 or a multiple of 256 in [256, 8192]");
         if (!valid_batch_tile_rows(opts.batch_tile_rows))
             return set_error(APCG_ERR_INVALID_ARG, "batch tile rows must be 0 or a multiple of 256 in [256, 8192]");
         std::vector<FSys> hs;

@@ -242,6 +242,15 @@ inline bool valid_batch_tile_rows(int32_t tr) { return tr == 0 || (tr >= 256 && 
 inline int32_t batch_tile_rows(const apcg_solve_opts &o) {
     return o.batch_tile_rows > 0 ? o.batch_tile_rows : kDefaultBatchTileRows;
 }
+// rows per tile once few rows still run (apcg_solve_opts.batch_tail_tile_rows):
+// 0 when the tiles are kept
+constexpr int32_t kDefaultBatchTailRows = 256;
+inline bool valid_batch_tail_rows(int32_t tr) { return tr == -1 || valid_batch_tile_rows(tr); }
+inline int32_t batch_tail_rows(const apcg_solve_opts &o) {
+    const int32_t t = o.batch_tail_tile_rows > 0 ? o.batch_tail_tile_rows
+                      : o.batch_tail_tile_rows == 0 ? kDefaultBatchTailRows : 0;
+    return t < batch_tile_rows(o) ? t : 0;
+}
 // tuning table (tune.hip): the key of a pattern, lookups and inserts
 std::string pattern_class(int64_t n, int64_t nnz, const int32_t *rp, const int32_t *cl);
 std::string tune_key(const std::string &arch, const std::string &cls, int64_t n, int64_t nnz);

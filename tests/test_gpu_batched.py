@@ -248,11 +248,43 @@ def test_segmented_tile_rows_bitwise(apcg, ctx, sdia):
             assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
 
 
+@pytest.mark.parametrize("sdia", [False, True])
+def test_segmented_tail_plan_bitwise(apcg, ctx, sdia):
+    """Once the rows still running fill fewer than two large tiles per
+    compute unit, the iteration continues on a plan of smaller tiles (the
+    tiles only group slices: the same sums).  This batch is below that size
+    from the start, so the switch comes at the first poll: 4096-row tiles
+    with the tail plan at 256 or 512 rows are bit for bit the run that keeps
+    its tiles; the oracle's bar holds."""
+    rng = np.random.default_rng(66)
+    systems = mixed_small_batch()[:12]
+    systems += [P._lognormal_system(rng, 2, side, 1.0, 3.0) for side in (90, 140)]
+    print(f"case batched tail plan sdia={sdia}", flush=True)
+    sd = range(len(systems)) if sdia else ()
+    runs = [run_batch(apcg, ctx, systems, 1e-10, 20000, sdia=sd, batch_schedule=2, batch_tile_rows=4096,
+                      batch_tail_tile_rows=tt) for tt in (-1, 256, 0)]
+    for res, xs in runs[1:]:
+        assert res == runs[0][0]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, runs[0][1]))
+    for s, r, x in zip(systems, *runs[0]):
+        ref = oracle.pcg(s.A, s.b, rtol=1e-10, maxit=20000)
+        assert r["status"] == ref.status
+        if ref.status == oracle.CONVERGED:
+            assert abs(r["iterations"] - ref.its) <= 1 and rel(x, ref.x) <= 1e-9
+
+
 def test_segmented_tile_rows_rejected(apcg, ctx):
     systems = mixed_small_batch()[:2]
     for tr in (100, 128, 8448, -256):
         with pytest.raises(apcg.ApcgError):
             run_batch(apcg, ctx, systems, 1e-8, 100, batch_schedule=2, batch_tile_rows=tr)
+
+
+def test_segmented_tail_rows_rejected(apcg, ctx):
+    systems = mixed_small_batch()[:3]
+    for bad in (-2, 100, 9000):
+        with pytest.raises(apcg.ApcgError):
+            run_batch(apcg, ctx, systems, 1e-10, 100, batch_schedule=2, batch_tail_tile_rows=bad)
 
 
 def test_batch_autotune_and_table(apcg, ctx):

@@ -290,6 +290,35 @@ def test_sliced_diagonal_systems_bitwise(apcg, ctx, mode):
     check_against_oracle(apcg, cases, r_sd, x_sd, 1e-10, 20000)
 
 
+@pytest.mark.parametrize("sdia", [False, True])
+def test_tail_plan_bitwise(apcg, ctx, sdia):
+    """Once the rows still running fill fewer than two large tiles per
+    compute unit, the iteration continues on a plan of smaller tiles (the
+    tiles only group slices, so the sums do not change).  These batches are
+    below that size from the start, so the switch comes at the first poll:
+    4096-row tiles with the tail plan at 256 or 512 rows are bit for bit the
+    run that keeps its tiles, and the oracle's bar holds."""
+    cases = mixed_cases()
+    rng = np.random.default_rng(65)
+    s = P._lognormal_system(rng, 2, 120, 1.0, 1.0)
+    lm = oracle.gershgorin(s.A)[1]
+    cases.append((s.A, s.b, cheb_coeffs(lm, lm / 30).astype(np.float32), lm, "long2d_120"))
+    print(f"case batched fcg tail plan sdia={sdia}", flush=True)
+    runs = [run_batch(apcg, ctx, cases, 1e-10, 20000, sdia=sdia, batch_tile_rows=4096, batch_tail_tile_rows=tt)
+            for tt in (-1, 256, 0)]
+    for res, xs in runs[1:]:
+        assert res == runs[0][0]
+        assert all(np.array_equal(a, b) for a, b in zip(xs, runs[0][1]))
+    check_against_oracle(apcg, cases, *runs[0], 1e-10, 20000)
+
+
+def test_tail_rows_rejected(apcg, ctx):
+    cases = mixed_cases()[:2]
+    for bad in (-2, 100, 9000):
+        with pytest.raises(apcg.ApcgError):
+            run_batch(apcg, ctx, cases, 1e-10, 100, batch_tail_tile_rows=bad)
+
+
 def unsymmetric_twin(A, frac=0.3):
     """A copy of A with the same (symmetric) pattern whose values are no
     longer symmetric: one entry left of the diagonal changed in its last
