@@ -334,6 +334,35 @@ def batch_roofline(apcg, systems, As, res, seconds, opts):
                     "systems are still running"}
 
 
+def learned_batch_roofline(apcg, As, res, seconds):
+    """Algorithmic HBM bytes of the batched learned solve over its wall time.
+    V = one pass over a matrix (sliced-diagonal copy: 512 U + 96 per 64-row
+    slice; CSR: 12 nnz + 4 (n + 1)).  Per flexible iteration: 9 V (product
+    and eight Clenshaw steps) + 392 n (product 32: z, p_old read, p, w
+    written; update 48: x, p, w, r read, x, r written; Clenshaw 24 + 6 x 40 +
+    48: D^-1, r and the recurrence's vectors read, each b_j or z written);
+    per Jacobi-mode iteration V + 112 n; the feature run's 12 Jacobi-PCG
+    steps alike, and its two row passes 2 x (12 nnz + 4 (n + 1)).  The
+    per-system kernels and the network are not counted."""
+    total = 0
+    for a, r in zip(As, res):
+        n = a.n
+        nnz = a.nnz
+        csr = 12 * nnz + 4 * (n + 1)
+        cfg = apcg.apcg_mat_get_spmv_config(a.h)
+        info = apcg.apcg_mat_get_sdia_info(a.h) if cfg["schedule"] == apcg.APCG_SPMV_SDIA else None
+        V = (((n + 63) // 64) * (512 * info["value_slots"] + 96)
+             if info and info["state"] == 1 and info["offset_slots"] == 8 else csr)
+        flex = r["fcg_iterations"]
+        jac = max(0, r["iterations"] - flex) + 12
+        total += flex * (9 * V + 392 * n) + jac * (V + 112 * n) + 2 * csr
+    achieved = total / seconds / 1e9
+    return {"bound": "hbm", "algorithmic_bytes": total, "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+            "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+            "note": "whole batched learned solve (features, network, FCG): wall time includes the per-system "
+                    "kernels, the network and the iterations where few systems are still running"}
+
+
 def device_system(fields, device=0):
     """Uploads host-drawn coefficients and right-hand side and assembles the
     matrix on the GPU (problems.diffusion_csr_torch; the same bits as the
@@ -602,6 +631,7 @@ def bench_mixed(apcg, torch, count, n_train, train_nhi, epochs, reps, workers, b
     apcg.apcg_batch_autotune(ctx, hA, hb, hx, 1, 4)
     dt = timed(lambda: learned(50000), lambda: learned(0))
     res = summary("batched_learned", dt)
+    out["batched_learned_roofline"] = learned_batch_roofline(apcg, As, res, dt)
     out["batched_learned_fallbacks"] = sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_FALLBACK)
     out["batched_learned_fallback_reasons"] = {
         k: sum(1 for r in res if r["status"] & apcg.APCG_SOLVE_FALLBACK and r["status"] & bit)

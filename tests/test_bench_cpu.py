@@ -118,3 +118,27 @@ def test_batch_roofline_byte_model():
     assert r["row_iterations"] == 30 * 100 + 11 * 49
     assert abs(r["achieved"] - (b1 + b2) / 0.5 / 1e9) < 0.06
     assert bench.batch_roofline(apcg, systems, [_H(0), _H(1)], res, 0.5, _Opts(1)) is None
+
+
+class _M:
+    def __init__(self, h, A):
+        self.h, self.n, self.nnz = h, A.n, A.nnz
+
+
+def test_learned_batch_roofline_byte_model():
+    """A system on a 7-slot sliced-diagonal copy (30 flexible iterations, no
+    fallback) and one on CSR (5 flexible and 20 Jacobi-mode iterations):
+    9 V + 392 n per flexible iteration, V + 112 n per Jacobi-mode iteration
+    (the feature run's 12 steps included) and two CSR row passes, by hand."""
+    A1 = P.stencil_laplacian((6, 6, 6), 7)  # n = 216, 4 slices
+    A2 = P.laplace_2d(7)
+    apcg = _StubApcg({0: (3, 7), 1: (0, 0)})
+    res = [{"iterations": 30, "fcg_iterations": 30}, {"iterations": 25, "fcg_iterations": 5}]
+    r = bench.learned_batch_roofline(apcg, [_M(0, A1), _M(1, A2)], res, 0.25)
+    csr1 = 12 * A1.nnz + 4 * (A1.n + 1)
+    V1 = 4 * (512 * 7 + 96)
+    csr2 = 12 * A2.nnz + 4 * (A2.n + 1)
+    b1 = 30 * (9 * V1 + 392 * 216) + 12 * (V1 + 112 * 216) + 2 * csr1
+    b2 = 5 * (9 * csr2 + 392 * 49) + 32 * (csr2 + 112 * 49) + 2 * csr2
+    assert r["algorithmic_bytes"] == b1 + b2
+    assert abs(r["achieved"] - (b1 + b2) / 0.25 / 1e9) < 0.06
