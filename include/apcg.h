@@ -721,8 +721,9 @@ apcg_status apcg_ksp_solve_tfqmr(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec 
  *     that cover every such system of the batch.
  *   APCG_BATCH_AUTO: persistent when no system costs more than 1/CUs of the
  *     batch, else segmented.
- * A, b, x: arrays of nsys handles on ctx's device (the x[i] distinct and not
- * aliasing any b[i]); x[i] holds x0 (ignored with x0_is_zero) and receives
+ * A, b, x: arrays of nsys handles on ctx's device; the memory of each x[i]
+ * may overlap no other x[j] and no b[j] (checked on the host over the
+ * vectors' address ranges: APCG_ERR_INVALID_ARG); x[i] holds x0 (ignored with x0_is_zero) and receives
  * the solution; info must hold >= nsys records, record i for system i.
  * opts->mode APCG_MODE_GRAPH (default) replays captured graphs (cached while
  * the batch is unchanged).  The context keeps 6 sum(n_i) doubles of
@@ -833,8 +834,9 @@ apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_v
  * switch to Jacobi-PCG from its current x, taken on the device for that
  * system alone (its status then carries APCG_SOLVE_FALLBACK and the reason).
  * info[i] receives system i's record.  opts: mode (graph/stream),
- * iters_per_graph, lookahead, x0_is_zero.  x vectors must be distinct.  A
- * system whose matrix is on APCG_SPMV_SDIA with 8 offset slots per slice
+ * iters_per_graph, lookahead, x0_is_zero.  The memory of each x[i] may
+ * overlap no other x[j] and no b[j] (checked on the host:
+ * APCG_ERR_INVALID_ARG).  A system whose matrix is on APCG_SPMV_SDIA with 8 offset slots per slice
  * has its products and Clenshaw steps read the sliced-diagonal copy (same
  * row sums, bit for bit; refilled at the start of every call). */
 apcg_status apcg_ksp_solve_batched_fcg_poly(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,

@@ -350,6 +350,32 @@ void batch_cache_release(uint64_t ctx_id, int device) {
 
 using namespace apcg;
 
+// The ranges [d, d + n) of the solution vectors must not overlap each other,
+// any right-hand side or the system's own b (the kernels write x while other
+// systems read b): one sweep over all ranges in address order.
+static apcg_status check_batch_ranges(int32_t nsys, const apcg_vec *b, const apcg_vec *x) {
+    struct Range {
+        uintptr_t lo, hi;
+        bool written;
+    };
+    std::vector<Range> rs;
+    rs.reserve(2 * (size_t)nsys);
+    for (int32_t i = 0; i < nsys; ++i) {
+        if (x[i]->n > 0) rs.push_back({(uintptr_t)x[i]->d, (uintptr_t)(x[i]->d + x[i]->n), true});
+        if (b[i]->n > 0) rs.push_back({(uintptr_t)b[i]->d, (uintptr_t)(b[i]->d + b[i]->n), false});
+    }
+    std::sort(rs.begin(), rs.end(), [](const Range &p, const Range &q) { return p.lo < q.lo; });
+    uintptr_t end_written = 0, end_any = 0;
+    for (const Range &r : rs) {
+        if (r.lo < end_written || (r.written && r.lo < end_any))
+            return set_error(APCG_ERR_INVALID_ARG,
+                             "a solution vector overlaps another solution vector or a right-hand side");
+        if (r.written) end_written = std::max(end_written, r.hi);
+        end_any = std::max(end_any, r.hi);
+    }
+    return APCG_SUCCESS;
+}
+
 extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b,
                                               const apcg_vec *x, double rtol, int32_t maxit,
                                               const apcg_solve_opts *opts_in, apcg_info info) {
@@ -400,10 +426,7 @@ extern "C" apcg_status apcg_ksp_solve_batched(apcg_ctx ctx, int32_t nsys, const 
             // estimated cost = nnz * sqrt(n)
             cost[i] = (double)(A[i]->nnz + n) * std::sqrt((double)std::max<int64_t>(n, 1));
         }
-        for (int32_t i = 0; i < nsys; ++i)
-            for (int32_t j = i + 1; j < nsys; ++j)
-                if (x[i] == x[j] || (x[i]->d == x[j]->d && x[i]->n > 0))
-                    return set_error(APCG_ERR_INVALID_ARG, "two systems share one solution vector");
+        if (apcg_status s = check_batch_ranges(nsys, b, x)) return s;
         std::vector<int32_t> order(nsys);
         std::iota(order.begin(), order.end(), 0);
         std::stable_sort(order.begin(), order.end(), [&](int32_t a, int32_t c) { return cost[a] > cost[c]; });

@@ -1144,6 +1144,32 @@ static apcg_status bf_core(apcg_ctx ctx, BfCache *bc, int32_t nsys, std::vector<
 }
 
 // Checks the systems and builds their descriptors (workspace offsets in ws).
+// The ranges [d, d + n) of the solution vectors must not overlap each other,
+// any right-hand side or the system's own b (the kernels write x while other
+// systems read b): one sweep over all ranges in address order.
+static apcg_status check_batch_ranges(int32_t nsys, const apcg_vec *b, const apcg_vec *x) {
+    struct Range {
+        uintptr_t lo, hi;
+        bool written;
+    };
+    std::vector<Range> rs;
+    rs.reserve(2 * (size_t)nsys);
+    for (int32_t i = 0; i < nsys; ++i) {
+        if (x[i]->n > 0) rs.push_back({(uintptr_t)x[i]->d, (uintptr_t)(x[i]->d + x[i]->n), true});
+        if (b[i]->n > 0) rs.push_back({(uintptr_t)b[i]->d, (uintptr_t)(b[i]->d + b[i]->n), false});
+    }
+    std::sort(rs.begin(), rs.end(), [](const Range &p, const Range &q) { return p.lo < q.lo; });
+    uintptr_t end_written = 0, end_any = 0;
+    for (const Range &r : rs) {
+        if (r.lo < end_written || (r.written && r.lo < end_any))
+            return set_error(APCG_ERR_INVALID_ARG,
+                             "a solution vector overlaps another solution vector or a right-hand side");
+        if (r.written) end_written = std::max(end_written, r.hi);
+        end_any = std::max(end_any, r.hi);
+    }
+    return APCG_SUCCESS;
+}
+
 static apcg_status bf_systems(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, const apcg_vec *b, const apcg_vec *x,
                               std::vector<FSys> &hs, int64_t *ws_total, std::vector<apcg_mat_s *> &refill) {
     const int dev = ctx->device;
@@ -1169,14 +1195,8 @@ static apcg_status bf_systems(apcg_ctx ctx, int32_t nsys, const apcg_mat *A, con
         }
         tot += ((9 * n + 63) / 64) * 64;
     }
-    if (x) {
-        std::vector<std::pair<const double *, int32_t>> xs(nsys);
-        for (int32_t i = 0; i < nsys; ++i) xs[i] = {x[i]->d, i};
-        std::sort(xs.begin(), xs.end());
-        for (int32_t i = 1; i < nsys; ++i)
-            if (xs[i].first == xs[i - 1].first && x[xs[i].second]->n > 0)
-                return set_error(APCG_ERR_INVALID_ARG, "two systems share one solution vector");
-    }
+    if (x)
+        if (apcg_status s = check_batch_ranges(nsys, b, x)) return s;
     *ws_total = tot;
     return APCG_SUCCESS;
 }

@@ -338,3 +338,47 @@ def test_batch_autotune_and_table(apcg, ctx):
             assert abs(r["iterations"] - ref.its) <= 1 and rel(xs[i].numpy(), ref.x) <= 1e-9, i
     apcg.apcg_info_destroy(info)
     apcg.apcg_tune_cache_clear()
+
+
+def test_batched_vector_overlaps_rejected(apcg, ctx):
+    """A solution vector may share no memory with another system's solution
+    or with any right-hand side: the batched PCG and the batched FCG reject
+    such a batch on the host (the same handle twice, two overlapping views of
+    one buffer, one system's x on another's b) and solve the systems once
+    the views are disjoint (adjacent views of one buffer)."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    A = P.laplace_2d(6)
+    n = A.n
+    rng = np.random.default_rng(90)
+    rhs = [rng.uniform(-1, 1, n) for _ in range(2)]
+    As = [DeviceCSR(A), DeviceCSR(A)]
+    bs = [DeviceVec(r) for r in rhs]
+    big = torch.zeros(2 * n, dtype=torch.float64, device="cuda:0")
+    x0 = DeviceVec.zeros(n)
+    overlapping = [DeviceVec(big[0:n]), DeviceVec(big[n // 2:n // 2 + n])]
+    on_b0 = DeviceVec(bs[0].t)
+    hA, hb = [a.h for a in As], [b.h for b in bs]
+    info = apcg.apcg_info_create(0, 2)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    coef = torch.zeros(18, dtype=torch.float32, device="cuda:0")
+    lmax = torch.full((2,), 8.0, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    bad = {"same handle": [x0.h, x0.h], "overlapping views": [v.h for v in overlapping],
+           "x on another system's b": [x0.h, on_b0.h]}
+    for name, hx in bad.items():
+        print(f"case overlap rejected: {name}", flush=True)
+        with pytest.raises(apcg.ApcgError):
+            apcg.apcg_ksp_solve_batched(ctx, hA, hb, hx, 1e-10, 100, opts, info)
+        with pytest.raises(apcg.ApcgError):
+            apcg.apcg_ksp_solve_batched_fcg_poly(ctx, hA, hb, hx, 1e-10, 100, coef, lmax, opts,
+                                                 apcg.apcg_fcg_opts_default(), info)
+    adjacent = [DeviceVec(big[0:n]), DeviceVec(big[n:2 * n])]
+    apcg.apcg_ksp_solve_batched(ctx, hA, hb, [v.h for v in adjacent], 1e-10, 1000, opts, info)
+    for i in range(2):
+        r = apcg.apcg_info_get(info, i)
+        ref = oracle.pcg(A, rhs[i], rtol=1e-10, maxit=1000)
+        assert r["status"] == apcg.APCG_SOLVE_CONVERGED and abs(r["iterations"] - ref.its) <= 1
+        assert rel(adjacent[i].numpy(), ref.x) <= 1e-9
+    apcg.apcg_info_destroy(info)
