@@ -27,6 +27,9 @@
  *     was accepted (for asynchronous calls: enqueued).  On any other value
  *     nothing was enqueued and apcg_last_error() returns a message
  *     (thread-local, valid until the next failing call on the thread).
+ *   - A vector that a call writes (a solve's x, MatMult's y) may share no
+ *     memory with the vectors it reads: the same handle twice or two
+ *     overlapping address ranges [d, d + n) return APCG_ERR_INVALID_ARG.
  *   - Numerical failures of asynchronous work (breakdown, NaN, iteration
  *     limit) are not return codes: they are written to device-resident
  *     solve-info words and read with apcg_info_get().

@@ -452,7 +452,7 @@ extern "C" apcg_status apcg_ksp_solve_fcg_poly(apcg_ctx ctx, apcg_mat A, apcg_ve
         if (!ctx || !A || !b || !x || !info || !dev_coeffs || !dev_lmax)
             return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
         if (b->n != A->n || x->n != A->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
-        if (b == x || (b->d == x->d && A->n > 0)) return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
+        if (vec_overlap(b, x)) return set_error(APCG_ERR_INVALID_ARG, "b and x must not share memory");
         if (ctx->device != A->device || b->device != A->device || x->device != A->device ||
             info->device != A->device)
             return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");

@@ -236,6 +236,13 @@ apcg_status resolve_ctx(apcg_ctx in, int device, apcg_ctx *out);  // NULL -> glo
 apcg_status op_begin(apcg_ctx c, const Acc *acc, int n);
 apcg_status op_end(apcg_ctx c, const Acc *acc, int n);
 apcg_status ensure_workspace(apcg_ctx c, int64_t n);
+// Whether two vectors share memory: the same handle, or address ranges
+// [d, d + n) that overlap (an empty range overlaps nothing).
+inline bool vec_overlap(const apcg_vec_s *a, const apcg_vec_s *b) {
+    const uintptr_t a0 = (uintptr_t)a->d, a1 = (uintptr_t)(a->d + a->n);
+    const uintptr_t b0 = (uintptr_t)b->d, b1 = (uintptr_t)(b->d + b->n);
+    return a == b || (a->n > 0 && b->n > 0 && a0 < b1 && b0 < a1);
+}
 // rows per tile of the segmented batched schedules (apcg_solve_opts.batch_tile_rows)
 constexpr int32_t kDefaultBatchTileRows = 1024;
 inline bool valid_batch_tile_rows(int32_t tr) { return tr == 0 || (tr >= 256 && tr <= 8192 && tr % 256 == 0); }

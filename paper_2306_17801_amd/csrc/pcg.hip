@@ -1765,7 +1765,7 @@ apcg_status pcg_solve_marked(apcg_ctx ctx, apcg_mat A, apcg_vec b, apcg_vec x, d
     try {
         if (!A || !b || !x || !info) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
         if (b->n != A->n || x->n != A->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
-        if (b == x || (b->d == x->d && A->n > 0)) return set_error(APCG_ERR_INVALID_ARG, "b and x must not alias");
+        if (vec_overlap(b, x)) return set_error(APCG_ERR_INVALID_ARG, "b and x must not share memory");
         if (b->device != A->device || x->device != A->device || info->device != A->device)
             return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
         if (info_index < 0 || info_index >= info->count)

@@ -375,6 +375,8 @@ extern "C" apcg_status apcg_ksp_solve_small_noalloc(apcg_ctx ctx, int32_t n, con
         return set_error(APCG_ERR_INVALID_ARG, "n exceeds APCG_NOALLOC_MAX_N (4096 rows), the no-allocation "
                                                "solve's fixed direction buffer");
     if (!rowptr || !col || !val || !b || !x || !info) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
+    if (n > 0 && (uintptr_t)b < (uintptr_t)(x + n) && (uintptr_t)x < (uintptr_t)(b + n))
+        return set_error(APCG_ERR_INVALID_ARG, "b and x must not share memory");
     if (maxit < 0 || !(rtol >= 0.0)) return set_error(APCG_ERR_INVALID_ARG, "maxit must be >= 0 and rtol >= 0");
     int pc = APCG_PC_JACOBI, norm_pre = 0, x0_zero = 0;
     if (opts) {

@@ -998,7 +998,7 @@ apcg_status apcg_mat_mult_async(apcg_mat A, apcg_vec x, apcg_vec y, apcg_ctx ctx
     API_BEGIN();
     if (!A || !x || !y) return set_error(APCG_ERR_INVALID_ARG, "NULL argument");
     if (x->n != A->n || y->n != A->n) return set_error(APCG_ERR_INVALID_ARG, "dimension mismatch");
-    if (x == y || (x->d == y->d && A->n > 0)) return set_error(APCG_ERR_INVALID_ARG, "x and y must not alias");
+    if (vec_overlap(x, y)) return set_error(APCG_ERR_INVALID_ARG, "x and y must not share memory");
     if (x->device != A->device || y->device != A->device)
         return set_error(APCG_ERR_INVALID_ARG, "operands on different devices");
     apcg_ctx c = nullptr;

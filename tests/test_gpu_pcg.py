@@ -568,3 +568,45 @@ def test_sliced_diagonal_info(apcg, ctx):
     with pytest.raises(apcg.ApcgError):
         apcg.apcg_mat_set_spmv_config(dB.h, 1, 256, 0, apcg.APCG_SPMV_SDIA)
     assert apcg.apcg_mat_get_sdia_info(dB.h)["state"] == -1
+
+
+def test_overlapping_vectors_rejected(apcg, ctx):
+    """A vector a call writes may share no memory with one it reads: the
+    PCG, FCG and TFQMR solves (x against b) and MatMult (y against x) reject
+    a view that overlaps the other in part, and the PCG solve runs to the
+    oracle's bar once the two views of the buffer are adjacent."""
+    import torch
+    from paper_2306_17801_amd.device import DeviceCSR, DeviceVec
+
+    A = P.laplace_2d(6)
+    n = A.n
+    rhs = np.random.default_rng(91).uniform(-1, 1, n)
+    dA = DeviceCSR(A)
+    big = torch.zeros(2 * n, dtype=torch.float64, device="cuda:0")
+    big[:n] = torch.from_numpy(rhs).to("cuda:0")
+    b = DeviceVec(big[0:n])
+    half = DeviceVec(big[n // 2:n // 2 + n])
+    info = apcg.apcg_info_create(0, 1)
+    opts = apcg.apcg_solve_opts_default(x0_is_zero=1)
+    coef = torch.zeros(9, dtype=torch.float32, device="cuda:0")
+    lmax = torch.full((1,), 8.0, dtype=torch.float64, device="cuda:0")
+    torch.cuda.synchronize()
+    calls = {
+        "pcg": lambda: apcg.apcg_ksp_solve(ctx, dA.h, b.h, half.h, 1e-10, 100, opts, info, 0),
+        "fcg": lambda: apcg.apcg_ksp_solve_fcg_poly(ctx, dA.h, b.h, half.h, 1e-10, 100, coef, lmax, opts,
+                                                    apcg.apcg_fcg_opts_default(), info, 0),
+        "tfqmr": lambda: apcg.apcg_ksp_solve_tfqmr(ctx, dA.h, b.h, half.h, 1e-10, 100, opts, info, 0),
+        "matmult": lambda: apcg.apcg_mat_mult_async(dA.h, b.h, half.h, ctx),
+    }
+    for name, call in calls.items():
+        print(f"case overlapping views rejected: {name}", flush=True)
+        with pytest.raises(apcg.ApcgError):
+            call()
+    x = DeviceVec(big[n:2 * n])
+    apcg.apcg_ksp_solve(ctx, dA.h, b.h, x.h, 1e-10, 1000, opts, info, 0)
+    r = apcg.apcg_info_get(info, 0)
+    ref = oracle.pcg(A, rhs, rtol=1e-10, maxit=1000)
+    assert r["status"] == apcg.APCG_SOLVE_CONVERGED and abs(r["iterations"] - ref.its) <= 1
+    assert rel(x.numpy(), ref.x) <= 1e-9
+    assert np.array_equal(b.numpy(), rhs)
+    apcg.apcg_info_destroy(info)
