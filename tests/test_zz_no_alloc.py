@@ -110,5 +110,9 @@ def test_noalloc_rejects_bad_arguments(apcg):
         apcg.apcg_ksp_solve_small_noalloc(ctx, 16, p, p, p, p, p, RTOL, 10, None, 0)
     with pytest.raises(apcg.ApcgError):
         apcg.apcg_ksp_solve_small_noalloc(None, 16, p, p, p, p, p, RTOL, 10, None, dinfo.data_ptr())
+    # x overlapping b in part (b = buf[0:16], x = buf[8:24])
+    with pytest.raises(apcg.ApcgError):
+        apcg.apcg_ksp_solve_small_noalloc(ctx, 16, p, p, p, p, p + 8 * 8, RTOL, 10, None, dinfo.data_ptr())
+    assert "share memory" in apcg.apcg_last_error()
     apcg.apcg_ctx_synchronize(ctx)
     apcg.apcg_ctx_destroy(ctx)
